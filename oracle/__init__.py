@@ -1,0 +1,362 @@
+"""FP64 CPU oracle for concurrent stochastic propagation (arXiv:2510.17432).
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent checker for the
+GPU library: only tests/, __graft_entry__.smoke() and the cpu_baseline leg of
+bench.py may import it.  It shares no code with the GPU library and never
+imports it.
+
+Contents, each following the passage cited beside it:
+  * SplitMix64 counter generator (Steele, Lea & Flood 2014) -- inputs;
+  * chain / square / honeycomb lattices with Anderson disorder -- Sec. II.B
+    (matrix density) and the lattice conventions stated in ``Lattice``;
+  * spectral half-width |H| by a Gershgorin bound times a margin -- Sec. II.A
+    names the rescaling H~ = (H - H0)/|H|, not how |H| is found;
+  * Bessel / Chebyshev coefficients and truncation order -- App. B, Sec. II.A;
+  * sequential and state-based concurrent propagation -- Sec. II.A Eq. (TE),
+    Sec. II.B time blocks (C code in csp_oracle.c);
+  * DOS from the correlation function -- Sec. III.
+
+Pins: see tests/test_oracle_*.py.  Every routine here is pinned by at least
+one test against a closed form, a library routine, a printed value of the
+paper or brute force; none is "parity unpinned".
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+KIND_CHAIN, KIND_SQUARE, KIND_HONEYCOMB = 0, 1, 2
+KINDS = {"chain": KIND_CHAIN, "square": KIND_SQUARE, "honeycomb": KIND_HONEYCOMB}
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load (building first if absent) the C part of the oracle."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    L = ctypes.CDLL(_build.LIB)
+    L.orc_splitmix64.restype = ctypes.c_uint64
+    L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.orc_splitmix64_stream.restype = None
+    L.orc_splitmix64_stream.argtypes = [ctypes.c_uint64, ctypes.c_int64, _u64p]
+    L.orc_draw.restype = ctypes.c_uint64
+    L.orc_draw.argtypes = [ctypes.c_uint64] * 3
+    L.orc_u01.restype = ctypes.c_double
+    L.orc_u01.argtypes = [ctypes.c_uint64]
+    L.orc_below.restype = ctypes.c_int64
+    L.orc_below.argtypes = [ctypes.c_uint64, ctypes.c_int64]
+    L.orc_lattice_sites.restype = ctypes.c_int64
+    L.orc_lattice_sites.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
+    L.orc_lattice_bonds.restype = ctypes.c_int64
+    L.orc_lattice_bonds.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int, ctypes.c_int, _i64p, _i64p]
+    L.orc_onsite.restype = None
+    L.orc_onsite.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _dp]
+    L.orc_build_csr.restype = None
+    L.orc_build_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i64p,
+                                ctypes.c_double, _dp, _i64p, _i64p, _dp]
+    L.orc_bessel_j.restype = ctypes.c_int
+    L.orc_bessel_j.argtypes = [ctypes.c_double, ctypes.c_int64, _dp]
+    L.orc_cheb_coeffs.restype = ctypes.c_int
+    L.orc_cheb_coeffs.argtypes = [ctypes.c_double, ctypes.c_int64, _dp]
+    L.orc_truncation.restype = ctypes.c_int64
+    L.orc_truncation.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.orc_propagate.restype = ctypes.c_int
+    L.orc_propagate.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int64, _dp,
+                                ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int64, _dp, _dp, _i64p]
+    L.orc_chebyshev_vectors.restype = ctypes.c_int
+    L.orc_chebyshev_vectors.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
+                                        ctypes.c_double, ctypes.c_double, _dp,
+                                        ctypes.c_int64, _dp]
+    _LIB = L
+    return L
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+# ---------------------------------------------------------------- generator
+def splitmix64(seed: int, k: int) -> int:
+    """Output number k (0-based) of SplitMix64 seeded with `seed`."""
+    return int(lib().orc_splitmix64(seed & (2**64 - 1), k))
+
+
+def splitmix64_stream(seed: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.uint64)
+    lib().orc_splitmix64_stream(seed & (2**64 - 1), n, _p(out, _u64p))
+    return out
+
+
+def draw(seed: int, stream: int, index: int) -> int:
+    return int(lib().orc_draw(seed & (2**64 - 1), stream, index))
+
+
+def u01(bits: int) -> float:
+    return float(lib().orc_u01(bits))
+
+
+def below(bits: int, n: int) -> int:
+    return int(lib().orc_below(bits, n))
+
+
+# ---------------------------------------------------------------- lattices
+class Lattice:
+    """Tight-binding lattice with uniform hopping t and Anderson disorder.
+
+    Orbital order: chain s = ix; square s = iy*Lx + ix; honeycomb
+    s = 2*(iy*Lx + ix) + sigma (sigma 0 = A, 1 = B) with bonds A(ix,iy)-B(ix,iy),
+    A(ix,iy)-B(ix-1,iy), A(ix,iy)-B(ix,iy-1).  H_ab = t on every bond (repeated
+    bonds add), H_ss = eps_s = W*(u_s - 1/2) with u_s drawn from stream 0 of
+    `disorder_seed`.
+    """
+
+    def __init__(self, kind, Lx, Ly=1, t=1.0, W=0.0, disorder_seed=0,
+                 periodic_x=True, periodic_y=True):
+        self.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
+        self.Lx, self.Ly = int(Lx), int(Ly) if self.kind != KIND_CHAIN else 1
+        self.t, self.W = float(t), float(W)
+        self.seed = int(disorder_seed)
+        self.px, self.py = int(bool(periodic_x)), int(bool(periodic_y))
+        L = lib()
+        self.N = int(L.orc_lattice_sites(self.kind, self.Lx, self.Ly))
+        nb = L.orc_lattice_bonds(self.kind, self.Lx, self.Ly, self.px, self.py, None, None)
+        self.bond_a = np.zeros(nb, dtype=np.int64)
+        self.bond_b = np.zeros(nb, dtype=np.int64)
+        L.orc_lattice_bonds(self.kind, self.Lx, self.Ly, self.px, self.py,
+                            _p(self.bond_a, _i64p), _p(self.bond_b, _i64p))
+        self.eps = np.zeros(self.N, dtype=np.float64)
+        L.orc_onsite(self.N, self.W, self.seed & (2**64 - 1), _p(self.eps, _dp))
+        nnz = 2 * nb + self.N
+        self.rowptr = np.zeros(self.N + 1, dtype=np.int64)
+        self.col = np.zeros(nnz, dtype=np.int64)
+        self.val = np.zeros(nnz, dtype=np.float64)
+        L.orc_build_csr(self.N, nb, _p(self.bond_a, _i64p), _p(self.bond_b, _i64p),
+                        self.t, _p(self.eps, _dp), _p(self.rowptr, _i64p),
+                        _p(self.col, _i64p), _p(self.val, _dp))
+
+    @property
+    def nbonds(self):
+        return len(self.bond_a)
+
+    def degree(self):
+        """Number of bond ends at each orbital (repeated bonds counted)."""
+        d = np.zeros(self.N, dtype=np.int64)
+        np.add.at(d, self.bond_a, 1)
+        np.add.at(d, self.bond_b, 1)
+        return d
+
+    def halfwidth(self, margin=1.025):
+        """|H| = margin * max_s (|eps_s| + deg(s)|t|): Gershgorin's row bound,
+        which encloses every eigenvalue, so H~ has its spectrum in [-1, 1]."""
+        return margin * float(np.max(np.abs(self.eps) + self.degree() * abs(self.t)))
+
+    def scipy_csr(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.N, self.N))
+
+    def dense(self):
+        return self.scipy_csr().toarray()
+
+
+# ---------------------------------------------------------------- states
+def random_phase_states(N: int, R: int, seed: int) -> np.ndarray:
+    """psi_r(s) = exp(2 pi i u_{r,s}) / sqrt(N), u from stream r of `seed`.
+    Returned as [N][R] (state r is column r)."""
+    L = lib()
+    u = np.empty((N, R), dtype=np.float64)
+    sd = seed & (2**64 - 1)
+    for r in range(R):
+        for s in range(N):
+            u[s, r] = L.orc_u01(L.orc_draw(sd, r, s))
+    return np.exp(2j * np.pi * u) / math.sqrt(N)
+
+
+def random_phase_states_fast(N: int, R: int, seed: int) -> np.ndarray:
+    """Vectorised copy of random_phase_states (same draws, numpy uint64
+    arithmetic); pinned to the loop version in the tests."""
+    G = np.uint64(0x9E3779B97F4A7C15)
+    s_idx = np.arange(N, dtype=np.uint64)
+    out = np.empty((N, R), dtype=np.complex128)
+    with np.errstate(over="ignore"):
+        for r in range(R):
+            k = (np.uint64(r) << np.uint64(40)) + s_idx
+            z = np.uint64(seed & (2**64 - 1)) + (k + np.uint64(1)) * G
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+            z = z ^ (z >> np.uint64(31))
+            u = (z >> np.uint64(11)).astype(np.float64) * 2.0**-53
+            out[:, r] = np.exp(2j * np.pi * u) / math.sqrt(N)
+    return out
+
+
+def ldos_sites(N: int, n_sites: int, seed: int) -> np.ndarray:
+    """The first n_sites distinct values floor(bits_i * N / 2^64), i = 0, 1, ...
+    of stream 0 of `seed` (the localized states |r> of Sec. III)."""
+    if n_sites > N:
+        raise ValueError("more sites than orbitals")
+    L = lib()
+    out, seen, i = [], set(), 0
+    sd = seed & (2**64 - 1)
+    while len(out) < n_sites:
+        s = int(L.orc_below(L.orc_draw(sd, 0, i), N))
+        i += 1
+        if s not in seen:
+            seen.add(s)
+            out.append(s)
+    return np.array(out, dtype=np.int64)
+
+
+def site_states(N: int, sites) -> np.ndarray:
+    """Unit vectors e_r as columns of an [N][len(sites)] array."""
+    out = np.zeros((N, len(sites)), dtype=np.complex128)
+    for k, s in enumerate(sites):
+        out[s, k] = 1.0
+    return out
+
+
+# ---------------------------------------------------------------- coefficients
+def bessel_j(x: float, nmax: int) -> np.ndarray:
+    J = np.zeros(nmax + 1, dtype=np.float64)
+    rc = lib().orc_bessel_j(float(x), int(nmax), _p(J, _dp))
+    if rc:
+        raise ValueError("bessel_j failed (%d)" % rc)
+    return J
+
+
+def cheb_coeffs(x: float, nmax: int) -> np.ndarray:
+    """c_0 = J_0(x), c_n = 2(-i)^n J_n(x): exp(-i x y) = sum_n c_n T_n(y)."""
+    c = np.zeros(nmax + 1, dtype=np.complex128)
+    rc = lib().orc_cheb_coeffs(float(x), int(nmax), _p(c.view(np.float64), _dp))
+    if rc:
+        raise ValueError("cheb_coeffs failed (%d)" % rc)
+    return c
+
+
+def truncation(x: float, eta: float = 1e-14) -> int:
+    """N(x): first order above x whose coefficient magnitude is <= eta."""
+    n = int(lib().orc_truncation(float(x), float(eta)))
+    if n < 0:
+        raise ValueError("bad truncation arguments")
+    return n
+
+
+# ---------------------------------------------------------------- propagation
+def propagate(lat, psi0, Nt, b=0, Hn=None, H0=0.0, tau=math.pi, eta=1e-14,
+              margin=1.025, return_final=False):
+    """Correlations <psi0_r|psi_r(t_j)>, j = 0..Nt, as an array [(Nt+1)][R].
+
+    b = 0: sequential form psi(t_j) = exp(-iH tau) psi(t_{j-1}) (Sec. II.A);
+    b >= 1: state-based concurrent form in time blocks of b steps (Eq. TE,
+    Sec. II.B).  psi0 is [N][R].  Returns (corr, counters) with counters a
+    dict of amxsy / axpy / dot counts (Sec. II.B definitions; the t = 0
+    correlation is counted under 'dot0').  With return_final=True a third
+    item, the final states psi(t_Nt) as [N][R], is returned."""
+    psi0 = np.asarray(psi0, dtype=np.complex128)
+    if psi0.ndim == 1:
+        psi0 = psi0[:, None]
+    N, R = psi0.shape
+    if N != lat.N:
+        raise ValueError("state length does not match the lattice")
+    if Hn is None:
+        Hn = lat.halfwidth(margin)
+    cols = np.ascontiguousarray(psi0.T)
+    corr = np.zeros((R, Nt + 1), dtype=np.complex128)
+    cnt = np.zeros(4, dtype=np.int64)
+    fin = np.zeros((R, N), dtype=np.complex128)
+    rc = lib().orc_propagate(N, _p(lat.rowptr, _i64p), _p(lat.col, _i64p), _p(lat.val, _dp),
+                             float(H0), float(Hn), R, _p(cols.view(np.float64), _dp),
+                             int(Nt), float(tau), float(eta), int(b),
+                             _p(corr.view(np.float64), _dp), _p(fin.view(np.float64), _dp),
+                             _p(cnt, _i64p))
+    if rc:
+        raise RuntimeError("orc_propagate failed (%d)" % rc)
+    counters = {"amxsy": int(cnt[0]), "axpy": int(cnt[1]),
+                "dot": int(cnt[2]), "dot0": int(cnt[3])}
+    if return_final:
+        return corr.T.copy(), counters, fin.T.copy()
+    return corr.T.copy(), counters
+
+
+def chebyshev_vectors(lat, x, nmax, Hn, H0=0.0):
+    """[T_0(H~)x, ..., T_nmax(H~)x] as an array [nmax+1][N]."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    out = np.zeros((nmax + 1, lat.N), dtype=np.complex128)
+    rc = lib().orc_chebyshev_vectors(lat.N, _p(lat.rowptr, _i64p), _p(lat.col, _i64p),
+                                     _p(lat.val, _dp), float(H0), float(Hn),
+                                     _p(x.view(np.float64), _dp), int(nmax),
+                                     _p(out.view(np.float64), _dp))
+    if rc:
+        raise RuntimeError("orc_chebyshev_vectors failed")
+    return out
+
+
+# ---------------------------------------------------------------- DOS
+def hann(Nt):
+    j = np.arange(-Nt, Nt)
+    return 0.5 * (1.0 + np.cos(np.pi * j / Nt))
+
+
+def dos(corr, Hn, window="hann"):
+    """Density of states from correlations (Sec. III).
+
+    D(E) = (1/2pi) int exp(iEt) C(t) dt with C(-t) = conj C(t), sampled at
+    t_j = j tau, tau = pi/|H|, j = -Nt..Nt-1, windowed by w_j, at energies
+    E_k = |H| k / Nt, k = -Nt..Nt-1:
+        D(E_k) = (tau/2pi) sum_j w_j C_j exp(i pi k j / Nt),
+    evaluated as a 2Nt-point inverse FFT.  corr is [(Nt+1)][R]; returns
+    (E [2Nt], D [2Nt][R] real, max |Im D| as a check)."""
+    corr = np.asarray(corr, dtype=np.complex128)
+    if corr.ndim == 1:
+        corr = corr[:, None]
+    Nt = corr.shape[0] - 1
+    R = corr.shape[1]
+    j = np.arange(-Nt, Nt)
+    C = np.where(j[:, None] >= 0, corr[np.abs(j)], np.conj(corr[np.abs(j)]))
+    if window == "hann":
+        w = hann(Nt)
+    elif window == "none":
+        w = np.ones(2 * Nt)
+    else:
+        raise ValueError(window)
+    x = w[:, None] * C
+    # position m = j mod 2Nt
+    xm = np.zeros((2 * Nt, R), dtype=np.complex128)
+    xm[j % (2 * Nt)] = x
+    S = np.fft.ifft(xm, axis=0) * (2 * Nt)        # S[k] = sum_m xm[m] e^{+2pi i k m / 2Nt}
+    k = np.arange(-Nt, Nt)
+    tau = math.pi / Hn
+    D = (tau / (2 * math.pi)) * S[k % (2 * Nt)]
+    E = Hn * k / Nt
+    return E, D.real.copy(), float(np.max(np.abs(D.imag)))
+
+
+def dos_direct(corr, Hn, window="hann"):
+    """The same sum as dos(), written out term by term (small Nt only)."""
+    corr = np.asarray(corr, dtype=np.complex128)
+    if corr.ndim == 1:
+        corr = corr[:, None]
+    Nt = corr.shape[0] - 1
+    tau = math.pi / Hn
+    w = hann(Nt) if window == "hann" else np.ones(2 * Nt)
+    E = np.zeros(2 * Nt)
+    D = np.zeros((2 * Nt, corr.shape[1]), dtype=np.complex128)
+    for ik, k in enumerate(range(-Nt, Nt)):
+        E[ik] = Hn * k / Nt
+        for ij, jj in enumerate(range(-Nt, Nt)):
+            Cj = corr[jj] if jj >= 0 else np.conj(corr[-jj])
+            D[ik] += w[ij] * Cj * np.exp(1j * math.pi * k * jj / Nt)
+    return E, (tau / (2 * math.pi)) * D

@@ -1,0 +1,449 @@
+/*
+ * csp_oracle.c -- plain FP64 CPU oracle for concurrent stochastic propagation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  It shares no code,
+ * header or generated table with the GPU library; it is written directly
+ * from the paper (arXiv:2510.17432) and from the published definitions of
+ * the generator and of Miller's recurrence named below.
+ *
+ * What it computes, all in double precision complex:
+ *   - a counter-based SplitMix64 generator (Steele, Lea & Flood, OOPSLA 2014);
+ *   - chain / square / honeycomb tight-binding lattices with Anderson
+ *     on-site disorder, as an explicit bond list and a CSR matrix;
+ *   - Bessel functions J_n(x) by Miller's backward recurrence normalised with
+ *     the Neumann sum J_0 + 2 sum_k J_2k = 1, the Chebyshev coefficients
+ *     c_n(x) of exp(-i H x) (App. B) and the truncation order N(x) (Sec. II.A);
+ *   - sequential propagation psi(t_j) = exp(-i H tau) psi(t_{j-1}) with the
+ *     correlation <psi0|psi(t_j)> (Sec. II.A, Sec. III);
+ *   - state-based concurrent propagation in time blocks, Eq. (TE) with the
+ *     blocks of Sec. II.B, with the same correlations.
+ * Operation counters (amxsy / axpy / dot) follow the definitions of Sec. II.B
+ * so that tests can compare them with Tab. (cost).
+ *
+ * Layout of every state array handed in or out: column-major per state,
+ * i.e. a state is N contiguous complex values and R states follow each other.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------ */
+/* SplitMix64.  The generator keeps a 64-bit state that advances by the  */
+/* odd constant GAMMA; output k (k = 0, 1, ...) of the generator seeded  */
+/* with s is therefore mix(s + (k + 1) * GAMMA), which makes it a        */
+/* counter-based generator.                                              */
+/* ------------------------------------------------------------------ */
+static const uint64_t GAMMA = 0x9e3779b97f4a7c15ULL;
+
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Output number k of SplitMix64 seeded with `seed`. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
+{
+    return mix64(seed + (k + 1) * GAMMA);
+}
+
+/* The same generator run statefully, for the equivalence test. */
+void orc_splitmix64_stream(uint64_t seed, int64_t n, uint64_t *out)
+{
+    uint64_t x = seed;
+    for (int64_t i = 0; i < n; ++i) {
+        x += GAMMA;
+        out[i] = mix64(x);
+    }
+}
+
+/* Draw `index` of stream `stream`: counter = stream * 2^40 + index. */
+uint64_t orc_draw(uint64_t seed, uint64_t stream, uint64_t index)
+{
+    return orc_splitmix64(seed, (stream << 40) + index);
+}
+
+/* Uniform double in [0, 1) from the top 53 bits. */
+double orc_u01(uint64_t bits)
+{
+    return (double)(bits >> 11) * 0x1.0p-53;
+}
+
+/* Uniform integer in [0, n) by the multiply-high map floor(bits * n / 2^64). */
+int64_t orc_below(uint64_t bits, int64_t n)
+{
+    return (int64_t)(((unsigned __int128)bits * (unsigned __int128)(uint64_t)n) >> 64);
+}
+
+/* ------------------------------------------------------------------ */
+/* Lattices.  kind 0 = chain (s = ix), 1 = square (s = iy*Lx + ix),     */
+/* 2 = honeycomb (s = 2*(iy*Lx + ix) + sigma, sigma 0 = A, 1 = B).      */
+/* Honeycomb bonds: A(ix,iy)-B(ix,iy), A(ix,iy)-B(ix-1,iy),             */
+/* A(ix,iy)-B(ix,iy-1).  Periodic directions wrap modulo L.             */
+/* ------------------------------------------------------------------ */
+int64_t orc_lattice_sites(int kind, int64_t Lx, int64_t Ly)
+{
+    switch (kind) {
+    case 0: return Lx;
+    case 1: return Lx * Ly;
+    case 2: return 2 * Lx * Ly;
+    default: return -1;
+    }
+}
+
+/* Writes the bond list (a[i], b[i]); returns the number of bonds.  With
+ * a == NULL only counts. */
+int64_t orc_lattice_bonds(int kind, int64_t Lx, int64_t Ly, int px, int py,
+                          int64_t *a, int64_t *b)
+{
+    int64_t nb = 0;
+#define BOND(u, v) do { if (a) { a[nb] = (u); b[nb] = (v); } ++nb; } while (0)
+    if (kind == 0) {
+        for (int64_t ix = 0; ix < Lx; ++ix) {
+            if (ix + 1 < Lx) BOND(ix, ix + 1);
+            else if (px) BOND(ix, 0);
+        }
+    } else if (kind == 1) {
+        for (int64_t iy = 0; iy < Ly; ++iy)
+            for (int64_t ix = 0; ix < Lx; ++ix) {
+                int64_t s = iy * Lx + ix;
+                if (ix + 1 < Lx) BOND(s, s + 1);
+                else if (px) BOND(s, iy * Lx);
+                if (iy + 1 < Ly) BOND(s, s + Lx);
+                else if (py) BOND(s, ix);
+            }
+    } else if (kind == 2) {
+        for (int64_t iy = 0; iy < Ly; ++iy)
+            for (int64_t ix = 0; ix < Lx; ++ix) {
+                int64_t A = 2 * (iy * Lx + ix);
+                BOND(A, A + 1);
+                if (ix >= 1) BOND(A, 2 * (iy * Lx + ix - 1) + 1);
+                else if (px) BOND(A, 2 * (iy * Lx + Lx - 1) + 1);
+                if (iy >= 1) BOND(A, 2 * ((iy - 1) * Lx + ix) + 1);
+                else if (py) BOND(A, 2 * ((Ly - 1) * Lx + ix) + 1);
+            }
+    } else {
+        return -1;
+    }
+#undef BOND
+    return nb;
+}
+
+/* Anderson disorder: eps_s = W * (u_s - 1/2), u_s from stream 0 of `seed`. */
+void orc_onsite(int64_t N, double W, uint64_t seed, double *eps)
+{
+    for (int64_t s = 0; s < N; ++s)
+        eps[s] = W * (orc_u01(orc_draw(seed, 0, (uint64_t)s)) - 0.5);
+}
+
+/* CSR of H: H_ab = H_ba = t for every bond (repeated bonds add up),
+ * H_ss = eps_s.  rowptr has N+1 entries, col/val 2*nbonds + N entries.
+ * Within a row the diagonal comes first, then bond entries in bond order. */
+void orc_build_csr(int64_t N, int64_t nbonds, const int64_t *a, const int64_t *b,
+                   double t, const double *eps,
+                   int64_t *rowptr, int64_t *col, double *val)
+{
+    int64_t *fill = (int64_t *)calloc((size_t)N, sizeof(int64_t));
+    for (int64_t s = 0; s <= N; ++s) rowptr[s] = 0;
+    for (int64_t s = 0; s < N; ++s) rowptr[s + 1] += 1;
+    for (int64_t i = 0; i < nbonds; ++i) {
+        rowptr[a[i] + 1] += 1;
+        rowptr[b[i] + 1] += 1;
+    }
+    for (int64_t s = 0; s < N; ++s) rowptr[s + 1] += rowptr[s];
+    for (int64_t s = 0; s < N; ++s) {
+        col[rowptr[s]] = s;
+        val[rowptr[s]] = eps ? eps[s] : 0.0;
+        fill[s] = 1;
+    }
+    for (int64_t i = 0; i < nbonds; ++i) {
+        int64_t u = a[i], v = b[i];
+        col[rowptr[u] + fill[u]] = v; val[rowptr[u] + fill[u]] = t; fill[u]++;
+        col[rowptr[v] + fill[v]] = u; val[rowptr[v] + fill[v]] = t; fill[v]++;
+    }
+    free(fill);
+}
+
+/* ------------------------------------------------------------------ */
+/* Bessel functions by Miller's backward recurrence.                    */
+/* J_{k-1}(x) = (2k/x) J_k(x) - J_{k+1}(x), started at an order M far   */
+/* beyond both n_max and x with (J_{M+1}, J_M) = (0, 1), then scaled so */
+/* that J_0 + 2 (J_2 + J_4 + ...) = 1.  Values above 1e250 trigger a    */
+/* rescale of everything computed so far (the smallest ones underflow   */
+/* harmlessly to zero).  Valid for x >= 0.                              */
+/* ------------------------------------------------------------------ */
+static int64_t miller_start(double x, int64_t nmax)
+{
+    double hi = (double)nmax > x ? (double)nmax : x;
+    int64_t M = (int64_t)ceil(hi + 30.0 + 20.0 * cbrt(x > 1.0 ? x : 1.0));
+    if (M & 1) M += 1;
+    return M;
+}
+
+int orc_bessel_j(double x, int64_t nmax, double *J)
+{
+    if (nmax < 0 || !(x >= 0.0)) return -1;
+    if (x == 0.0) {
+        J[0] = 1.0;
+        for (int64_t n = 1; n <= nmax; ++n) J[n] = 0.0;
+        return 0;
+    }
+    int64_t M = miller_start(x, nmax);
+    double *w = (double *)malloc((size_t)(M + 2) * sizeof(double));
+    if (!w) return -2;
+    w[M + 1] = 0.0;
+    w[M] = 1.0;
+    for (int64_t k = M; k >= 1; --k) {
+        w[k - 1] = (2.0 * (double)k / x) * w[k] - w[k + 1];
+        if (fabs(w[k - 1]) > 1e250) {
+            for (int64_t i = k - 1; i <= M + 1; ++i) w[i] *= 1e-250;
+        }
+    }
+    double norm = w[0];
+    for (int64_t k = 2; k <= M; k += 2) norm += 2.0 * w[k];
+    for (int64_t n = 0; n <= nmax; ++n) J[n] = w[n] / norm;
+    free(w);
+    return 0;
+}
+
+/* Chebyshev coefficients of exp(-i x y) on y in [-1, 1] (App. B):
+ * c_0 = J_0(x), c_n = 2 (-i)^n J_n(x). */
+int orc_cheb_coeffs(double x, int64_t nmax, cplx *c)
+{
+    double *J = (double *)malloc((size_t)(nmax + 1) * sizeof(double));
+    if (!J) return -2;
+    int rc = orc_bessel_j(x, nmax, J);
+    if (rc) { free(J); return rc; }
+    const cplx mi_pow[4] = {1.0, -I, -1.0, I};   /* (-i)^n for n mod 4 */
+    c[0] = J[0];
+    for (int64_t n = 1; n <= nmax; ++n) c[n] = 2.0 * mi_pow[n & 3] * J[n];
+    free(J);
+    return 0;
+}
+
+/* Truncation order (Sec. II.A): the coefficients must exceed eta for every
+ * order below N.  Orders below x can pass through a zero of J_n by accident,
+ * so N is the first order above x whose coefficient is at most eta.  The
+ * expansion then runs over n = 0..N inclusive. */
+int64_t orc_truncation(double x, double eta)
+{
+    if (!(x >= 0.0) || !(eta > 0.0)) return -1;
+    int64_t nmax = (int64_t)ceil(x + 40.0 + 25.0 * cbrt(x > 1.0 ? x : 1.0));
+    double *J = (double *)malloc((size_t)(nmax + 1) * sizeof(double));
+    if (!J) return -2;
+    orc_bessel_j(x, nmax, J);
+    int64_t N = -1;
+    for (int64_t n = (int64_t)floor(x) + 1; n <= nmax; ++n) {
+        double cn = (n == 0) ? fabs(J[0]) : 2.0 * fabs(J[n]);
+        if (cn <= eta) { N = n; break; }
+    }
+    free(J);
+    return N;
+}
+
+/* ------------------------------------------------------------------ */
+/* Propagation.                                                         */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const int64_t *rowptr, *col;
+    const double *val;
+    double H0, Hn;          /* rescaled H = (H - H0) / Hn */
+} orc_ham;
+
+/* y <- a * Ht x - y   (amxsy of Sec. II.B with M = Ht) */
+static void amxsy(const orc_ham *H, double a, const cplx *x, cplx *y)
+{
+    const double inv = 1.0 / H->Hn;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < H->n; ++s) {
+        cplx acc = -H->H0 * x[s];
+        for (int64_t p = H->rowptr[s]; p < H->rowptr[s + 1]; ++p)
+            acc += H->val[p] * x[H->col[p]];
+        y[s] = a * (acc * inv) - y[s];
+    }
+}
+
+/* y <- a x + y */
+static void axpy(int64_t n, cplx a, const cplx *x, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) y[s] += a * x[s];
+}
+
+/* <x|y> = sum conj(x) y, summed in index order per thread then in thread
+ * order (OpenMP reduction on real and imaginary parts). */
+static cplx dot(int64_t n, const cplx *x, const cplx *y)
+{
+    double re = 0.0, im = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : re, im)
+    for (int64_t s = 0; s < n; ++s) {
+        cplx v = conj(x[s]) * y[s];
+        re += creal(v);
+        im += cimag(v);
+    }
+    return re + I * im;
+}
+
+static void copy_scaled(int64_t n, cplx a, const cplx *x, cplx *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) y[s] = a * x[s];
+}
+
+/* counters: [0] amxsy, [1] axpy, [2] dot (the correlation at t = 0 is
+ * counted separately in [3]). */
+
+/* Sequential form: psi(t_j) = sum_{n=0}^{N(tau)} c_n(tau) T_n(Ht) psi(t_{j-1}),
+ * corr[j] = <psi0|psi(t_j)>, j = 0..Nt, for one state. */
+static int propagate_one_sequential(const orc_ham *H, const cplx *psi0, int64_t Nt,
+                                    double tau, double eta, cplx *corr, cplx *final_out,
+                                    int64_t *cnt)
+{
+    const int64_t n = H->n;
+    int64_t Ntr = orc_truncation(tau, eta);
+    if (Ntr < 1) return -1;
+    cplx *c = (cplx *)malloc((size_t)(Ntr + 1) * sizeof(cplx));
+    cplx *psi = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p0 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p1 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *acc = (cplx *)malloc((size_t)n * sizeof(cplx));
+    if (!c || !psi || !p0 || !p1 || !acc) return -2;
+    orc_cheb_coeffs(tau, Ntr, c);
+
+    memcpy(psi, psi0, (size_t)n * sizeof(cplx));
+    corr[0] = dot(n, psi0, psi);
+    cnt[3] += 1;
+    for (int64_t j = 1; j <= Nt; ++j) {
+        /* phi_0 = psi, phi_1 = Ht psi */
+        memcpy(p0, psi, (size_t)n * sizeof(cplx));
+        memset(p1, 0, (size_t)n * sizeof(cplx));
+        amxsy(H, 1.0, p0, p1); cnt[0]++;
+        copy_scaled(n, c[0], p0, acc);
+        axpy(n, c[1], p1, acc); cnt[1]++;
+        for (int64_t k = 2; k <= Ntr; ++k) {
+            /* phi_k = 2 Ht phi_{k-1} - phi_{k-2}, written over phi_{k-2} */
+            amxsy(H, 2.0, p1, p0); cnt[0]++;
+            cplx *tmp = p0; p0 = p1; p1 = tmp;
+            axpy(n, c[k], p1, acc); cnt[1]++;
+        }
+        cplx *tmp = psi; psi = acc; acc = tmp;
+        corr[j] = dot(n, psi0, psi); cnt[2]++;
+    }
+    if (final_out) memcpy(final_out, psi, (size_t)n * sizeof(cplx));
+    free(c); free(psi); free(p0); free(p1); free(acc);
+    return 0;
+}
+
+/* State-based concurrent form in time blocks of b steps (Eq. TE and the
+ * blocks of Sec. II.B): within block k starting from s_k = psi(t_{kb}),
+ * psi(t_{kb+j}) = sum_{n=0}^{N(j tau)} c_n(j tau) T_n(Ht) s_k, j = 1..b_k,
+ * with b_k = min(b, Nt - kb); the next block starts from psi(t_{kb+b_k}).
+ * The Chebyshev vectors are generated once per block and each is added to
+ * every state whose expansion still includes its order. */
+static int propagate_one_concurrent(const orc_ham *H, const cplx *psi0, int64_t Nt,
+                                    double tau, double eta, int64_t b,
+                                    cplx *corr, cplx *final_out, int64_t *cnt)
+{
+    const int64_t n = H->n;
+    if (b < 1) return -1;
+    int64_t *Nj = (int64_t *)malloc((size_t)(b + 1) * sizeof(int64_t));
+    for (int64_t j = 1; j <= b; ++j) {
+        Nj[j] = orc_truncation((double)j * tau, eta);
+        if (Nj[j] < 1) return -1;
+    }
+    int64_t Nmax = Nj[b];
+    cplx *c = (cplx *)malloc((size_t)(b + 1) * (size_t)(Nmax + 1) * sizeof(cplx));
+    for (int64_t j = 1; j <= b; ++j)
+        orc_cheb_coeffs((double)j * tau, Nj[j], c + (size_t)j * (size_t)(Nmax + 1));
+#define COEF(jj, nn) c[(size_t)(jj) * (size_t)(Nmax + 1) + (size_t)(nn)]
+    cplx *s = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p0 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p1 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *acc = (cplx *)malloc((size_t)b * (size_t)n * sizeof(cplx));
+    if (!s || !p0 || !p1 || !acc) return -2;
+
+    memcpy(s, psi0, (size_t)n * sizeof(cplx));
+    corr[0] = dot(n, psi0, s);
+    cnt[3] += 1;
+    for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+        int64_t bk = (Nt - t0 < b) ? (Nt - t0) : b;
+        int64_t Nk = Nj[bk];
+        memcpy(p0, s, (size_t)n * sizeof(cplx));
+        memset(p1, 0, (size_t)n * sizeof(cplx));
+        amxsy(H, 1.0, p0, p1); cnt[0]++;
+        for (int64_t j = 1; j <= bk; ++j) {
+            cplx *aj = acc + (size_t)(j - 1) * (size_t)n;
+            copy_scaled(n, COEF(j, 0), p0, aj);
+            axpy(n, COEF(j, 1), p1, aj); cnt[1]++;
+        }
+        for (int64_t k = 2; k <= Nk; ++k) {
+            amxsy(H, 2.0, p1, p0); cnt[0]++;
+            cplx *tmp = p0; p0 = p1; p1 = tmp;
+            for (int64_t j = 1; j <= bk; ++j) {
+                if (k > Nj[j]) continue;
+                axpy(n, COEF(j, k), p1, acc + (size_t)(j - 1) * (size_t)n); cnt[1]++;
+            }
+        }
+        for (int64_t j = 1; j <= bk; ++j) {
+            corr[t0 + j] = dot(n, psi0, acc + (size_t)(j - 1) * (size_t)n);
+            cnt[2]++;
+        }
+        memcpy(s, acc + (size_t)(bk - 1) * (size_t)n, (size_t)n * sizeof(cplx));
+    }
+    if (final_out) memcpy(final_out, s, (size_t)n * sizeof(cplx));
+#undef COEF
+    free(Nj); free(c); free(s); free(p0); free(p1); free(acc);
+    return 0;
+}
+
+/* Propagate R states (each N contiguous complex values, states back to
+ * back) and write corr[r * (Nt + 1) + j] = <psi0_r|psi_r(t_j)>.
+ * b = 0 selects the sequential form; b >= 1 the concurrent form with blocks
+ * of b steps.  tau is the rescaled time step (pi for DOS).  final_states
+ * (may be NULL) receives psi_r(t_Nt) laid out like psi0.  counters[0..3]
+ * are accumulated. */
+int orc_propagate(int64_t n, const int64_t *rowptr, const int64_t *col, const double *val,
+                  double H0, double Hn, int64_t R, const cplx *psi0, int64_t Nt,
+                  double tau, double eta, int64_t b, cplx *corr, cplx *final_states,
+                  int64_t *counters)
+{
+    orc_ham H = {n, rowptr, col, val, H0, Hn};
+    if (n < 1 || R < 1 || Nt < 0 || !(Hn > 0.0)) return -1;
+    for (int64_t r = 0; r < R; ++r) {
+        const cplx *p = psi0 + (size_t)r * (size_t)n;
+        cplx *cr = corr + (size_t)r * (size_t)(Nt + 1);
+        cplx *fr = final_states ? final_states + (size_t)r * (size_t)n : NULL;
+        int rc = (b == 0) ? propagate_one_sequential(&H, p, Nt, tau, eta, cr, fr, counters)
+                          : propagate_one_concurrent(&H, p, Nt, tau, eta, b, cr, fr, counters);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* Apply T_n(Ht) to one state for n = 0..nmax (for eigenvector tests):
+ * out[k * n_sites + s] = (T_k(Ht) x)_s. */
+int orc_chebyshev_vectors(int64_t n, const int64_t *rowptr, const int64_t *col,
+                          const double *val, double H0, double Hn,
+                          const cplx *x, int64_t nmax, cplx *out)
+{
+    orc_ham H = {n, rowptr, col, val, H0, Hn};
+    if (nmax < 0) return -1;
+    memcpy(out, x, (size_t)n * sizeof(cplx));
+    if (nmax == 0) return 0;
+    cplx *o1 = out + (size_t)n;
+    memset(o1, 0, (size_t)n * sizeof(cplx));
+    amxsy(&H, 1.0, out, o1);
+    for (int64_t k = 2; k <= nmax; ++k) {
+        cplx *dst = out + (size_t)k * (size_t)n;
+        memcpy(dst, out + (size_t)(k - 2) * (size_t)n, (size_t)n * sizeof(cplx));
+        amxsy(&H, 2.0, out + (size_t)(k - 1) * (size_t)n, dst);
+    }
+    return 0;
+}
