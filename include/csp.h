@@ -1,0 +1,251 @@
+/*
+ * csp.h -- concurrent stochastic propagation on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libcsp.  The library evaluates exp(-i H t) applied to blocks of
+ * random-phase (or localized) states of a sparse tight-binding Hamiltonian by
+ * a Chebyshev expansion (arXiv:2510.17432, Sec. II.A and App. B), assembles
+ * the states at many time points from blocks of Chebyshev vectors
+ * (state-based concurrent form, Eq. (TE), with the time blocks of Sec. II.B),
+ * reduces them to the correlation functions C(t_j) = <psi0|psi(t_j)> and
+ * turns those into the density of states (Sec. III).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns a csp_status; 0 is success.  Nothing throws
+ *     across the ABI.  On failure csp_last_error() returns a message that is
+ *     local to the calling thread and valid until its next csp_* call.
+ *   - "dev_" pointers are device pointers on the context's device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes in; the library owns contexts, lattices and its workspace.
+ *   - State blocks are laid out [N][ld]: orbital-major, the ld columns of one
+ *     orbital contiguous, each value an interleaved complex number
+ *     (re, im) of the stated dtype.  Columns col0 .. col0+R-1 are used.
+ *   - Correlations are complex128 laid out [(Nt+1)][R] (time-major).
+ *   - All work is ordered on the context's HIP stream.  Calls that return
+ *     values to the host synchronise that stream before returning.
+ *   - Sizes are int64 wherever an orbital count can exceed 2^31.
+ */
+#ifndef CSP_H
+#define CSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSP_ABI_VERSION 1
+
+typedef enum {
+    CSP_OK = 0,
+    CSP_EINVAL = -1,        /* bad argument, shape or combination */
+    CSP_ENOMEM = -2,        /* device memory (or the given cap) too small */
+    CSP_EHIP = -3,          /* a HIP runtime call failed */
+    CSP_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    CSP_ENUMERIC = -5       /* non-finite value or norm guard tripped */
+} csp_status;
+
+typedef enum { CSP_CHAIN = 0, CSP_SQUARE = 1, CSP_HONEYCOMB = 2 } csp_lattice_kind;
+
+/* Value type of a state block. */
+typedef enum { CSP_C64 = 0 /* complex float */, CSP_C128 = 1 /* complex double */ } csp_dtype;
+
+/* How the propagation is carried out (Sec. II.A, Sec. II.B, Sec. III). */
+typedef enum {
+    /* Sequential form: psi(t_j) = exp(-i H tau) psi(t_{j-1}), each step a
+     * Chebyshev expansion of order N(tau); complex128 throughout.  This is
+     * the plain form the concurrent method is compared against. */
+    CSP_FP64_SEQ = 0,
+    /* State-based concurrent form in time blocks, complex128 throughout;
+     * the block contraction uses FP64 fused multiply-adds. */
+    CSP_FP64_CONC = 1,
+    /* State-based concurrent form: complex64 Chebyshev recursion, block
+     * contraction on MFMA in split-bfloat16 (three products, FP32
+     * accumulation), carried block-final state in FP32, correlations
+     * finished in FP64.  psi0 must be complex64. */
+    CSP_FP32_CONC = 2
+} csp_mode;
+
+/* How correlations are taken from a block of Chebyshev vectors. */
+typedef enum {
+    /* Assemble psi(t_j) = sum_n c_n(j tau) T_n(H~) s_k for every j of the
+     * block (Eq. TE) and reduce <psi0|psi(t_j)> in the same kernel. */
+    CSP_ASSEMBLE_STATES = 0,
+    /* Reduce the block moments mu_n = <psi0|T_n(H~) s_k> during the
+     * recursion and form C(t_j) = sum_n c_n(j tau) mu_n in FP64; no
+     * Chebyshev vectors are kept.  Same result up to rounding. */
+    CSP_ASSEMBLE_MOMENTS = 1
+} csp_assembly;
+
+typedef enum { CSP_WINDOW_HANN = 0, CSP_WINDOW_NONE = 1 } csp_window;
+
+/* Lattice description.  Orbital order: chain s = ix; square s = iy*Lx+ix;
+ * honeycomb s = 2*(iy*Lx+ix)+sigma (sigma 0 = A, 1 = B) with bonds
+ * A(ix,iy)-B(ix,iy), A(ix,iy)-B(ix-1,iy), A(ix,iy)-B(ix,iy-1).  H_ab = t on
+ * every bond (bonds that repeat on small periodic lattices add),
+ * H_ss = W*(u_s - 1/2) with u_s the SplitMix64 draw s of stream 0 of
+ * disorder_seed mapped to [0,1) by its top 53 bits. */
+typedef struct {
+    int32_t kind;              /* csp_lattice_kind */
+    int32_t periodic_x;        /* nonzero: wrap in x */
+    int32_t periodic_y;        /* nonzero: wrap in y (ignored for chains) */
+    int32_t reserved0;
+    int64_t Lx, Ly;            /* cells; Ly ignored for chains */
+    double t;                  /* hopping */
+    double W;                  /* Anderson disorder width (0: clean) */
+    uint64_t disorder_seed;
+    double bound_margin;       /* |H| = margin * Gershgorin bound; 0 -> 1.025 */
+    double halfwidth_override; /* > 0: use this |H| instead */
+    double center;             /* spectral centre H0 (Sec. II.A) */
+} csp_lattice_desc;
+
+typedef struct {
+    int64_t n_orb;             /* N */
+    int64_t rows;              /* Ly (1 for chains) */
+    int64_t orb_per_row;       /* Lx (chain, square) or 2*Lx (honeycomb) */
+    double H0, halfwidth;      /* rescaling H~ = (H - H0)/halfwidth */
+    double gershgorin;         /* max_s |eps_s - H0| + deg(s)|t| */
+    int32_t max_degree;        /* 2, 4 or 3 bond ends per orbital */
+    int32_t has_onsite;        /* W != 0 */
+} csp_lattice_info;
+
+typedef struct {
+    int64_t Nt;                /* time steps; correlations for j = 0..Nt */
+    double tau_tilde;          /* rescaled step |H|*tau; 0 -> pi (Sec. II.A) */
+    double eta;                /* truncation threshold; 0 -> 1e-14 */
+    int32_t mode;              /* csp_mode */
+    int32_t assembly;          /* csp_assembly */
+    int32_t block_b;           /* time-block size; 0 -> selection rule */
+    int32_t chunk_K;           /* Chebyshev vectors kept per contraction;
+                                  0 -> as many as fit (multiple of 16) */
+    uint64_t mem_cap_bytes;    /* workspace cap; 0 -> free device memory */
+    int32_t profile;           /* nonzero: time kernel classes with events */
+    int32_t check_norm;        /* nonzero: norm guard on the carried state */
+    double norm_tol;           /* relative tolerance of the guard; 0 -> 1e-3 */
+} csp_params;
+
+/* What a propagation did.  Operation counts are per state column and follow
+ * the definitions of Sec. II.B: amxsy = Chebyshev recursion steps,
+ * axpy = (n, j) coefficient pairs of the block sums, dot = correlations
+ * after t = 0. */
+typedef struct {
+    int32_t block_b, chunk_K, n_blocks, n_groups;
+    int64_t amxsy, axpy, dot;
+    int64_t spmm_launches, contract_launches;
+    double ms_total;           /* host wall time of the call */
+    double ms_spmm;            /* event time of recursion kernels (profile) */
+    double ms_contract;        /* event time of contraction kernels (profile) */
+    double spmm_bytes;         /* algorithmic bytes of all recursion steps */
+    double contract_bytes;     /* algorithmic bytes of all contractions */
+    double contract_flops;     /* MFMA (or FMA) flops of all contractions */
+    uint64_t workspace_bytes;
+    double model_cost[8];      /* selection-rule cost of b = 1,2,4,...,128 */
+} csp_report;
+
+typedef struct csp_context csp_context;
+typedef struct csp_lattice csp_lattice;
+
+/* Library ABI version (CSP_ABI_VERSION). */
+int csp_abi_version(void);
+
+/* Thread-local message describing the last failure of this thread. */
+const char *csp_last_error(void);
+
+/* Create a context on HIP device `device` whose work is ordered on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  The stream stays
+ * owned by the caller and must outlive the context. */
+csp_status csp_context_create(int device, void *hip_stream, csp_context **out);
+csp_status csp_context_destroy(csp_context *ctx);
+
+/* Build a lattice on the context's device: on-site energies (FP64 and an
+ * FP32 copy) by the generator above and the half-width |H| by Gershgorin's
+ * row bound times the margin, reduced on the GPU in FP64 (Sec. II.A asks
+ * for H0 and |H|; it obtains them by Lanczos). */
+csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
+                              csp_lattice **out);
+csp_status csp_lattice_destroy(csp_lattice *lat);
+csp_status csp_lattice_get_info(const csp_lattice *lat, csp_lattice_info *out);
+
+/* Copy the FP64 on-site energies into dev_eps[N]. */
+csp_status csp_lattice_onsite(const csp_lattice *lat, double *dev_eps);
+
+/* Write the neighbour table dev_nbr[N][max_deg] (int64 orbital indices, -1
+ * where a bond is absent at an open edge; repeated bonds appear twice), in
+ * the order left, right, down, up (square), left, right (chain) or
+ * B(ix), B(ix-1), B(iy-1) for A and A(ix), A(ix+1), A(iy+1) for B. */
+csp_status csp_lattice_neighbors(const csp_lattice *lat, int64_t *dev_nbr);
+
+/* Random-phase states (Sec. II.A; phases uniform, norm 1):
+ * psi_r(s) = exp(2 pi i u_{r,s}) / sqrt(N), u_{r,s} from stream r of `seed`,
+ * written into columns col0+r of the [N][ld] block dev_psi (dtype C64 or
+ * C128; C64 values are the FP64 values rounded). */
+csp_status csp_states_random_phase(csp_context *ctx, int64_t N, int32_t R, uint64_t seed,
+                                   int32_t dtype, void *dev_psi, int32_t ld, int32_t col0);
+
+/* Localized sites for the LDOS (Sec. III): the first n distinct values
+ * floor(bits_i * N / 2^64) of stream 0 of `seed`, into dev_sites[n]. */
+csp_status csp_ldos_sites(csp_context *ctx, int64_t N, int32_t n, uint64_t seed,
+                          int64_t *dev_sites);
+
+/* Unit vectors e_{sites[k]} into columns col0+k of dev_psi (other entries of
+ * those columns are zeroed). */
+csp_status csp_states_sites(csp_context *ctx, int64_t N, int32_t n, const int64_t *dev_sites,
+                            int32_t dtype, void *dev_psi, int32_t ld, int32_t col0);
+
+/* Chebyshev coefficients of exp(-i x y) on [-1, 1] (App. B):
+ * c_0 = J_0(x), c_n = 2(-i)^n J_n(x), computed on the GPU in FP64 with
+ * Miller's backward recurrence; writes complex128 dev_c[0..nmax].  If
+ * n_trunc is not NULL it receives the truncation order N(x) for threshold
+ * eta (Sec. II.A: the first order above x whose coefficient is <= eta). */
+csp_status csp_chebyshev_coefficients(csp_context *ctx, double x, double eta, int32_t nmax,
+                                      double *dev_c, int32_t *n_trunc);
+
+/* One Chebyshev recursion step on an [N][R] block (amxsy, Sec. II.B):
+ * first != 0: y = H~ x; otherwise y = 2 H~ x - y.  dtype C64 or C128,
+ * 1 <= R <= 64, x and y distinct. */
+csp_status csp_chebyshev_step(csp_context *ctx, const csp_lattice *lat, int32_t R,
+                              int32_t dtype, const void *dev_x, void *dev_y, int32_t first);
+
+/* Propagate the R states dev_psi0 ([N][R], dtype per mode) for Nt steps of
+ * the rescaled size params->tau_tilde and write the correlations
+ * dev_corr[(Nt+1)][R] (complex128, device) with
+ * C_r(t_j) = <psi0_r|psi_r(t_j)>.  dev_final (may be NULL) receives
+ * psi(t_Nt) in the layout and dtype of psi0.  rep may be NULL. */
+csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *dev_psi0,
+                         int32_t R, const csp_params *params, double *dev_corr,
+                         void *dev_final, csp_report *rep);
+
+/* Many lattices in one set of launches: instance i has lattice lats[i],
+ * states dev_psi0[i] ([N_i][R[i]]) and correlations dev_corr[i]
+ * ([(Nt+1)][R[i]]).  Every instance uses the same params (Nt, mode, b); the
+ * recursion of all instances is one launch per Chebyshev step and the
+ * contraction one launch per chunk, captured in a HIP graph per block. */
+csp_status csp_propagate_batch(csp_context *ctx, int32_t n_inst, const csp_lattice *const *lats,
+                               const void *const *dev_psi0, const int32_t *R,
+                               const csp_params *params, double *const *dev_corr,
+                               csp_report *rep);
+
+/* Density of states from correlations (Sec. III): with t_j = j*tau,
+ * tau = tau_tilde/halfwidth, C_{-j} = conj(C_j) and window w_j,
+ * D_r(E_k) = (tau/2pi) Re sum_{j=-Nt}^{Nt-1} w_j C_j exp(i E_k t_j) at
+ * E_k = k*pi/(Nt*tau), k = -Nt..Nt-1.  dev_corr is [(Nt+1)][R] complex128;
+ * writes dev_E[2Nt], dev_D[2Nt][R] and, if not NULL, the column mean
+ * dev_Dmean[2Nt], all FP64 on the device. */
+csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t R,
+                   double halfwidth, double tau_tilde, int32_t window, double *dev_E,
+                   double *dev_D, double *dev_Dmean);
+
+/* Time-block size from the cost model of Sec. II.B,
+ * C(b) = N_amxsy(b) t_amxsy + N_axpy(b) t_axpy, minimised over b subject to
+ * the workspace fitting mem_cap; t_amxsy and t_axpy are measured on this
+ * device for this lattice and R (cached in the context). */
+csp_status csp_select_block(csp_context *ctx, const csp_lattice *lat, int32_t R,
+                            const csp_params *params, int32_t *b_out, csp_report *rep);
+
+/* Free cached workspace of the context. */
+csp_status csp_context_trim(csp_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSP_H */

@@ -1,0 +1,964 @@
+// C ABI of libcsp: contexts, lattices, states, coefficients and the
+// propagation driver (planner + launch sequence).  See include/csp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "csp_internal.h"
+
+using namespace csp;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+
+csp_status fail(csp_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCALL(x)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      return fail(CSP_EHIP, "%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                            \
+  } while (0)
+
+#define CHECK(x)                          \
+  do {                                    \
+    csp_status s_ = (x);                  \
+    if (s_ != CSP_OK) return s_;          \
+  } while (0)
+
+// Makes `dev` current for the scope and restores the previous device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+// ------------------------------------------------------------------ objects
+struct csp_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 256;
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  std::vector<hipEvent_t> events;   // pool for profiling
+  std::map<std::string, std::pair<double, double>> calib;  // t_amxsy, t_axpy per shape
+};
+
+struct csp_lattice {
+  csp_context* ctx = nullptr;
+  csp_lattice_desc desc{};
+  Geom g{};
+  double H0 = 0.0, halfwidth = 0.0, gersh = 0.0;
+  double* eps64 = nullptr;
+  float* eps32 = nullptr;
+  bool has_onsite = false;
+};
+
+namespace {
+
+// Grow-only workspace of the context; contents are not preserved.
+csp_status ws_reserve(csp_context* c, size_t bytes) {
+  if (bytes <= c->ws_size) return CSP_OK;
+  if (c->ws) {
+    HIPCALL(hipStreamSynchronize(c->stream));
+    HIPCALL(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_size = 0;
+  }
+  hipError_t e = hipMalloc(&c->ws, bytes);
+  if (e != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(CSP_ENOMEM, "workspace of %.3f GB could not be allocated (%s)", bytes / 1e9,
+                hipGetErrorString(e));
+  }
+  c->ws_size = bytes;
+  return CSP_OK;
+}
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t n) {
+    void* p = base + off;
+    off += align256(n);
+    return p;
+  }
+};
+
+csp_status hip_event(csp_context* c, size_t i, hipEvent_t* out) {
+  while (c->events.size() <= i) {
+    hipEvent_t e;
+    HIPCALL(hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  *out = c->events[i];
+  return CSP_OK;
+}
+
+int64_t trunc_nmax(double x) { return (int64_t)std::ceil(x + 40.0 + 25.0 * std::cbrt(x + 1.0)); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ basics
+extern "C" int csp_abi_version(void) { return CSP_ABI_VERSION; }
+extern "C" const char* csp_last_error(void) { return g_err.c_str(); }
+
+extern "C" csp_status csp_context_create(int device, void* hip_stream, csp_context** out) {
+  if (!out) return fail(CSP_EINVAL, "out is NULL");
+  int n = 0;
+  HIPCALL(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(CSP_EINVAL, "device %d out of range (%d)", device, n);
+  DeviceGuard dg(device);
+  if (!dg.ok) return fail(CSP_EHIP, "hipSetDevice(%d) failed", device);
+  hipDeviceProp_t prop;
+  HIPCALL(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(CSP_EUNSUPPORTED, "libcsp is built for gfx950, device is %s", prop.gcnArchName);
+  csp_context* c = new csp_context();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  *out = c;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_context_trim(csp_context* c) {
+  if (!c) return fail(CSP_EINVAL, "context is NULL");
+  DeviceGuard dg(c->device);
+  if (c->ws) {
+    HIPCALL(hipStreamSynchronize(c->stream));
+    HIPCALL(hipFree(c->ws));
+  }
+  c->ws = nullptr;
+  c->ws_size = 0;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_context_destroy(csp_context* c) {
+  if (!c) return CSP_OK;
+  DeviceGuard dg(c->device);
+  csp_status st = csp_context_trim(c);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  delete c;
+  return st;
+}
+
+// ------------------------------------------------------------------ lattices
+extern "C" csp_status csp_lattice_create(csp_context* c, const csp_lattice_desc* d,
+                                         csp_lattice** out) {
+  if (!c || !d || !out) return fail(CSP_EINVAL, "NULL argument");
+  if (d->kind < CSP_CHAIN || d->kind > CSP_HONEYCOMB)
+    return fail(CSP_EINVAL, "unknown lattice kind %d", d->kind);
+  const int64_t Ly = d->kind == CSP_CHAIN ? 1 : d->Ly;
+  if (d->Lx < 1 || Ly < 1) return fail(CSP_EINVAL, "lattice sizes must be >= 1");
+  if (!std::isfinite(d->t) || !std::isfinite(d->W) || d->W < 0)
+    return fail(CSP_EINVAL, "hopping and disorder must be finite, W >= 0");
+  DeviceGuard dg(c->device);
+  csp_lattice* L = new csp_lattice();
+  L->ctx = c;
+  L->desc = *d;
+  L->g.kind = d->kind;
+  L->g.px = d->periodic_x ? 1 : 0;
+  L->g.py = (d->kind != CSP_CHAIN && d->periodic_y) ? 1 : 0;
+  L->g.Lx = d->Lx;
+  L->g.Ly = Ly;
+  L->g.opr = d->kind == CSP_HONEYCOMB ? 2 * d->Lx : d->Lx;
+  L->g.N = L->g.opr * Ly;
+  L->has_onsite = d->W != 0.0;
+  L->H0 = d->center;
+  auto cleanup = [&](csp_status st) {
+    if (L->eps64) (void)hipFree(L->eps64);
+    if (L->eps32) (void)hipFree(L->eps32);
+    delete L;
+    return st;
+  };
+  if (hipMalloc(&L->eps64, sizeof(double) * L->g.N) != hipSuccess ||
+      hipMalloc(&L->eps32, sizeof(float) * L->g.N) != hipSuccess) {
+    (void)hipGetLastError();
+    return cleanup(fail(CSP_ENOMEM, "on-site arrays of %lld orbitals", (long long)L->g.N));
+  }
+  hipError_t e = launch_onsite(L->g, d->W, d->disorder_seed, L->eps64, L->eps32, c->stream);
+  const int np = 1024;
+  double* d_part = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&d_part, sizeof(double) * np);
+  if (e == hipSuccess) e = launch_gershgorin(L->g, L->eps64, d->t, L->H0, d_part, np, c->stream);
+  std::vector<double> part(np);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), d_part, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (d_part) (void)hipFree(d_part);
+  if (e != hipSuccess) return cleanup(fail(CSP_EHIP, "lattice set-up: %s", hipGetErrorString(e)));
+  double m = 0.0;
+  for (double v : part) m = std::max(m, v);
+  L->gersh = m;
+  const double margin = d->bound_margin > 0 ? d->bound_margin : 1.025;
+  L->halfwidth = d->halfwidth_override > 0 ? d->halfwidth_override : margin * m;
+  if (!(L->halfwidth > 0)) return cleanup(fail(CSP_EINVAL, "zero spectral half-width (t = W = 0)"));
+  *out = L;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_lattice_destroy(csp_lattice* L) {
+  if (!L) return CSP_OK;
+  DeviceGuard dg(L->ctx->device);
+  (void)hipStreamSynchronize(L->ctx->stream);
+  if (L->eps64) (void)hipFree(L->eps64);
+  if (L->eps32) (void)hipFree(L->eps32);
+  delete L;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_lattice_get_info(const csp_lattice* L, csp_lattice_info* o) {
+  if (!L || !o) return fail(CSP_EINVAL, "NULL argument");
+  o->n_orb = L->g.N;
+  o->rows = L->g.Ly;
+  o->orb_per_row = L->g.opr;
+  o->H0 = L->H0;
+  o->halfwidth = L->halfwidth;
+  o->gershgorin = L->gersh;
+  o->max_degree = max_degree(L->g.kind);
+  o->has_onsite = L->has_onsite ? 1 : 0;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_lattice_onsite(const csp_lattice* L, double* dev_eps) {
+  if (!L || !dev_eps) return fail(CSP_EINVAL, "NULL argument");
+  DeviceGuard dg(L->ctx->device);
+  HIPCALL(hipMemcpyAsync(dev_eps, L->eps64, sizeof(double) * L->g.N, hipMemcpyDeviceToDevice,
+                         L->ctx->stream));
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_lattice_neighbors(const csp_lattice* L, int64_t* dev_nbr) {
+  if (!L || !dev_nbr) return fail(CSP_EINVAL, "NULL argument");
+  DeviceGuard dg(L->ctx->device);
+  HIPCALL(launch_neighbours(L->g, dev_nbr, L->ctx->stream));
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ states
+extern "C" csp_status csp_states_random_phase(csp_context* c, int64_t N, int32_t R, uint64_t seed,
+                                              int32_t dtype, void* dev_psi, int32_t ld,
+                                              int32_t col0) {
+  if (!c || !dev_psi) return fail(CSP_EINVAL, "NULL argument");
+  if (N < 1 || R < 0 || col0 < 0 || col0 + R > ld)
+    return fail(CSP_EINVAL, "bad block shape N=%lld R=%d ld=%d col0=%d", (long long)N, R, ld, col0);
+  if (dtype != CSP_C64 && dtype != CSP_C128) return fail(CSP_EINVAL, "bad dtype %d", dtype);
+  if (R == 0) return CSP_OK;
+  DeviceGuard dg(c->device);
+  HIPCALL(launch_random_phase(N, R, seed, dtype, dev_psi, ld, col0, c->stream));
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_ldos_sites(csp_context* c, int64_t N, int32_t n, uint64_t seed,
+                                     int64_t* dev_sites) {
+  if (!c || !dev_sites) return fail(CSP_EINVAL, "NULL argument");
+  if (n < 0 || n > N || n > 65536) return fail(CSP_EINVAL, "need 0 <= n <= min(N, 65536)");
+  if (n == 0) return CSP_OK;
+  DeviceGuard dg(c->device);
+  HIPCALL(launch_ldos_sites(N, n, seed, dev_sites, c->stream));
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_states_sites(csp_context* c, int64_t N, int32_t n,
+                                       const int64_t* dev_sites, int32_t dtype, void* dev_psi,
+                                       int32_t ld, int32_t col0) {
+  if (!c || !dev_psi || (n > 0 && !dev_sites)) return fail(CSP_EINVAL, "NULL argument");
+  if (N < 1 || n < 0 || col0 < 0 || col0 + n > ld) return fail(CSP_EINVAL, "bad block shape");
+  if (dtype != CSP_C64 && dtype != CSP_C128) return fail(CSP_EINVAL, "bad dtype %d", dtype);
+  if (n == 0) return CSP_OK;
+  DeviceGuard dg(c->device);
+  HIPCALL(launch_site_states(N, n, dev_sites, dtype, dev_psi, ld, col0, c->stream));
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ coefficients
+extern "C" csp_status csp_chebyshev_coefficients(csp_context* c, double x, double eta,
+                                                 int32_t nmax, double* dev_c, int32_t* n_trunc) {
+  if (!c || !dev_c) return fail(CSP_EINVAL, "NULL argument");
+  if (!(x >= 0) || !std::isfinite(x) || nmax < 0 || !(eta > 0))
+    return fail(CSP_EINVAL, "need x >= 0, nmax >= 0, eta > 0");
+  DeviceGuard dg(c->device);
+  const int64_t nm = std::max<int64_t>(nmax, trunc_nmax(x));
+  double* d_a = nullptr;
+  int32_t* d_n = nullptr;
+  HIPCALL(hipMalloc(&d_a, sizeof(double) * (nm + 1)));
+  HIPCALL(hipMalloc(&d_n, sizeof(int32_t)));
+  hipError_t e = launch_bessel(x, 1, (int)nm, eta, d_a, d_n, c->stream);
+  if (e == hipSuccess) e = launch_complex_coeffs(d_a, nmax, dev_c, c->stream);
+  int32_t nt = -1;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&nt, d_n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_a);
+  (void)hipFree(d_n);
+  if (e != hipSuccess) return fail(CSP_EHIP, "coefficients: %s", hipGetErrorString(e));
+  if (n_trunc) *n_trunc = nt;
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ recursion helpers
+namespace {
+
+struct SpmmPlan {
+  int vec = 1;
+  int seg_rows = 32;
+  int halo = 1;
+  int64_t total_tiles = 0;
+};
+
+// Fill tiling fields of the instances and choose vector width / segment rows.
+SpmmPlan plan_spmm(std::vector<SpmmInst>& insts, bool fp64, int n_cu) {
+  SpmmPlan p;
+  int64_t minrow = INT64_MAX;
+  for (auto& I : insts) {
+    minrow = std::min(minrow, I.rowlen);
+    p.halo = std::max(p.halo, (int)I.R);
+  }
+  p.vec = 1;
+  const int vmax = fp64 ? 2 : 4;
+  while (p.vec < vmax && (int64_t)kSpmmThreads * p.vec * 2 <= minrow) p.vec *= 2;
+  const int W = kSpmmThreads * p.vec;
+  const int64_t target = (int64_t)n_cu * 8;
+  int seg = 32;
+  auto count = [&](int sr) {
+    int64_t t = 0;
+    for (auto& I : insts) t += ceil_div(I.rowlen, W) * ceil_div(I.Ly, sr);
+    return t;
+  };
+  while (seg > 4 && count(seg) < target) seg /= 2;
+  p.seg_rows = seg;
+  int64_t t0 = 0;
+  for (auto& I : insts) {
+    I.n_strips = ceil_div(I.rowlen, W);
+    I.n_segs = ceil_div(I.Ly, seg);
+    I.tile0 = t0;
+    t0 += I.n_strips * I.n_segs;
+  }
+  p.total_tiles = t0;
+  return p;
+}
+
+SpmmInst make_inst(const csp_lattice* L, int R, bool fp64) {
+  SpmmInst I{};
+  I.kind = L->g.kind;
+  I.px = L->g.px;
+  I.py = L->g.py;
+  I.R = R;
+  I.Ly = L->g.Ly;
+  I.opr = L->g.opr;
+  I.rowlen = L->g.opr * R;
+  I.alpha = 2.0 * L->desc.t / L->halfwidth;
+  I.beta0 = -2.0 * L->H0 / L->halfwidth;
+  I.onsite_scale = 2.0 / L->halfwidth;
+  I.eps = L->has_onsite ? (fp64 ? (const void*)L->eps64 : (const void*)L->eps32) : nullptr;
+  return I;
+}
+
+}  // namespace
+
+extern "C" csp_status csp_chebyshev_step(csp_context* c, const csp_lattice* L, int32_t R,
+                                         int32_t dtype, const void* dev_x, void* dev_y,
+                                         int32_t first) {
+  if (!c || !L || !dev_x || !dev_y) return fail(CSP_EINVAL, "NULL argument");
+  if (R < 1 || R > kMaxStepCols) return fail(CSP_EINVAL, "need 1 <= R <= %d", kMaxStepCols);
+  if (dtype != CSP_C64 && dtype != CSP_C128) return fail(CSP_EINVAL, "bad dtype %d", dtype);
+  if (dev_x == dev_y) return fail(CSP_EINVAL, "x and y must be distinct");
+  if (L->ctx->device != c->device) return fail(CSP_EINVAL, "lattice is on another device");
+  DeviceGuard dg(c->device);
+  const bool fp64 = dtype == CSP_C128;
+  std::vector<SpmmInst> insts(1, make_inst(L, R, fp64));
+  insts[0].base = dev_y;
+  insts[0].slot_stride = 0;
+  insts[0].src = dev_x;
+  SpmmPlan p = plan_spmm(insts, fp64, c->n_cu);
+  SpmmInst* d_inst = nullptr;
+  HIPCALL(hipMalloc(&d_inst, sizeof(SpmmInst)));
+  hipError_t e = hipMemcpyAsync(d_inst, insts.data(), sizeof(SpmmInst), hipMemcpyHostToDevice,
+                                c->stream);
+  SpmmStep st{};
+  st.slot_out = 0;
+  st.slot_cur = 0;
+  st.slot_prev = 0;
+  st.cur_from_src = 1;
+  st.copy_cur = 0;
+  st.has_prev = first ? 0 : 1;
+  st.scale_f = first ? 0.5f : 1.0f;
+  st.scale_d = first ? 0.5 : 1.0;
+  st.seg_rows = p.seg_rows;
+  st.halo = p.halo;
+  st.total_tiles = p.total_tiles;
+  if (e == hipSuccess) e = launch_spmm(fp64, p.vec, d_inst, 1, st, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_inst);
+  if (e != hipSuccess) return fail(CSP_EHIP, "chebyshev step: %s", hipGetErrorString(e));
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ propagation
+namespace {
+
+struct InstIn {
+  const csp_lattice* lat;
+  const void* psi0;
+  int R;
+  double* corr;
+  void* final_out;
+};
+
+struct Group {
+  int inst, col0, Rg;
+  int64_t M;
+  void* slots = nullptr;
+  void* psi0g = nullptr;
+  void* carry = nullptr;
+  double* partial = nullptr;
+  int n_wg = 1;
+};
+
+struct ChunkTab {
+  int n_lo, n_cnt;
+  void* bop = nullptr;     // FP32 path
+  float* ccf = nullptr;
+  double* coef = nullptr;  // FP64 path
+  double* ccd = nullptr;
+};
+
+struct BlockTab {
+  int bk = 0, Nk = 0;
+  std::vector<ChunkTab> chunks;
+};
+
+std::vector<int> split_columns(int R) {
+  std::vector<int> g;
+  while (R > 0) {
+    int p = 1;
+    while (p * 2 <= std::min(R, kMaxGroupCols)) p *= 2;
+    g.push_back(p);
+    R -= p;
+  }
+  return g;
+}
+
+void fill_defaults(const csp_params* in, csp_params* p) {
+  *p = *in;
+  if (!(p->tau_tilde > 0)) p->tau_tilde = M_PI;
+  if (!(p->eta > 0)) p->eta = 1e-14;
+  if (!(p->norm_tol > 0)) p->norm_tol = 1e-3;
+}
+
+struct Profiler {
+  csp_context* c;
+  bool on;
+  size_t next = 0;
+  std::vector<std::pair<size_t, int>> spans;  // first event index, kind (0 spmm, 1 contract)
+  csp_status begin(int kind, size_t* idx) {
+    if (!on) return CSP_OK;
+    hipEvent_t e0;
+    CHECK(hip_event(c, next, &e0));
+    HIPCALL(hipEventRecord(e0, c->stream));
+    *idx = next;
+    spans.push_back({next, kind});
+    next += 2;
+    return CSP_OK;
+  }
+  csp_status end(size_t idx) {
+    if (!on) return CSP_OK;
+    hipEvent_t e1;
+    CHECK(hip_event(c, idx + 1, &e1));
+    HIPCALL(hipEventRecord(e1, c->stream));
+    return CSP_OK;
+  }
+  csp_status collect(double* ms_spmm, double* ms_contract) {
+    *ms_spmm = 0;
+    *ms_contract = 0;
+    if (!on) return CSP_OK;
+    for (auto& s : spans) {
+      float ms = 0.f;
+      HIPCALL(hipEventElapsedTime(&ms, c->events[s.first], c->events[s.first + 1]));
+      (s.second == 0 ? *ms_spmm : *ms_contract) += ms;
+    }
+    return CSP_OK;
+  }
+};
+
+int select_b_rule(const std::vector<int32_t>& ntr_all, int bmax, int64_t Nt, double t_amxsy,
+                  double t_axpy, const std::vector<bool>& fits, double* model) {
+  // C(b) = N_amxsy(b) t_amxsy + N_axpy(b) t_axpy (Sec. II.B) over the blocks
+  // of b steps (last block shorter when b does not divide Nt).
+  auto cost = [&](int b) {
+    double amxsy = 0, axpy = 0;
+    for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+      const int bk = (int)std::min<int64_t>(b, Nt - t0);
+      amxsy += ntr_all[bk - 1];
+      for (int j = 1; j <= bk; ++j) axpy += ntr_all[j - 1];
+    }
+    return amxsy * t_amxsy + axpy * t_axpy;
+  };
+  int best = 1;
+  double bestc = cost(1);
+  for (int b = 1, k = 0; b <= 128; b *= 2, ++k)
+    if (model) model[k] = (b <= bmax && b <= (int)ntr_all.size()) ? cost(b) : -1.0;
+  for (int b = 2; b <= bmax && b <= (int)ntr_all.size(); ++b) {
+    if (!fits[b]) continue;
+    const double cb = cost(b);
+    if (cb < bestc) {
+      bestc = cb;
+      best = b;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
+                                 const csp_params* params_in, csp_report* rep);
+
+extern "C" csp_status csp_propagate(csp_context* c, const csp_lattice* L, const void* dev_psi0,
+                                    int32_t R, const csp_params* params, double* dev_corr,
+                                    void* dev_final, csp_report* rep) {
+  if (!c || !L || !dev_psi0 || !params || !dev_corr) return fail(CSP_EINVAL, "NULL argument");
+  std::vector<InstIn> ins(1);
+  ins[0] = {L, dev_psi0, R, dev_corr, dev_final};
+  return propagate_impl(c, ins, params, rep);
+}
+
+extern "C" csp_status csp_propagate_batch(csp_context* c, int32_t n_inst,
+                                          const csp_lattice* const* lats,
+                                          const void* const* dev_psi0, const int32_t* R,
+                                          const csp_params* params, double* const* dev_corr,
+                                          csp_report* rep) {
+  if (!c || n_inst < 1 || !lats || !dev_psi0 || !R || !params || !dev_corr)
+    return fail(CSP_EINVAL, "NULL argument or n_inst < 1");
+  std::vector<InstIn> ins(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    if (!lats[i] || !dev_psi0[i] || !dev_corr[i]) return fail(CSP_EINVAL, "instance %d NULL", i);
+    ins[i] = {lats[i], dev_psi0[i], R[i], dev_corr[i], nullptr};
+  }
+  return propagate_impl(c, ins, params, rep);
+}
+
+static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
+                                 const csp_params* params_in, csp_report* rep) {
+  const double t_start = now_ms();
+  csp_params P;
+  fill_defaults(params_in, &P);
+  if (P.Nt < 0) return fail(CSP_EINVAL, "Nt < 0");
+  if (P.mode < CSP_FP64_SEQ || P.mode > CSP_FP32_CONC) return fail(CSP_EINVAL, "bad mode %d", P.mode);
+  if (P.assembly != CSP_ASSEMBLE_STATES && P.assembly != CSP_ASSEMBLE_MOMENTS)
+    return fail(CSP_EINVAL, "bad assembly %d", P.assembly);
+  if (P.assembly == CSP_ASSEMBLE_MOMENTS)
+    return fail(CSP_EUNSUPPORTED, "moment assembly is not available in this build");
+  if (P.check_norm) return fail(CSP_EUNSUPPORTED, "norm guard is not available in this build");
+  const bool fp64 = P.mode != CSP_FP32_CONC;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  for (size_t i = 0; i < ins.size(); ++i) {
+    if (ins[i].R < 1) return fail(CSP_EINVAL, "instance %zu: R must be >= 1", i);
+    if (ins[i].lat->ctx->device != c->device)
+      return fail(CSP_EINVAL, "instance %zu: lattice on another device", i);
+  }
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+
+  // ---------------------------------------------------------- block size
+  int bmax = P.mode == CSP_FP64_SEQ ? 1 : (fp64 ? kMaxFp64B : 32 * kMaxJTiles);
+  int b = P.mode == CSP_FP64_SEQ ? 1 : P.block_b;
+  if (b < 0) return fail(CSP_EINVAL, "block_b < 0");
+  if (b > bmax) return fail(CSP_EUNSUPPORTED, "block_b %d above %d for this mode", b, bmax);
+  const int64_t Nt = P.Nt;
+
+  // Coefficients for x_j = j tau, j = 1..bmax (all block sizes share them).
+  const int ncol = bmax;
+  const int nmax = (int)trunc_nmax(ncol * P.tau_tilde);
+  const int lda = nmax + 1;
+  std::vector<int32_t> ntr(ncol);
+  double* d_a = nullptr;
+  int32_t* d_ntr = nullptr;
+  HIPCALL(hipMalloc(&d_a, sizeof(double) * (size_t)ncol * lda));
+  HIPCALL(hipMalloc(&d_ntr, sizeof(int32_t) * ncol));
+  struct Free {
+    std::vector<void*> p;
+    ~Free() { for (void* q : p) (void)hipFree(q); }
+  } tmp;
+  tmp.p.push_back(d_a);
+  tmp.p.push_back(d_ntr);
+  HIPCALL(launch_bessel(P.tau_tilde, ncol, nmax, P.eta, d_a, d_ntr, s));
+  HIPCALL(hipMemcpyAsync(ntr.data(), d_ntr, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, s));
+  HIPCALL(hipStreamSynchronize(s));
+  for (int j = 0; j < ncol; ++j)
+    if (ntr[j] < 1) return fail(CSP_ENUMERIC, "no truncation order for x = %g", (j + 1) * P.tau_tilde);
+
+  // ---------------------------------------------------------- groups & memory
+  std::vector<Group> groups;
+  int64_t vec_elems = 0;   // complex values of one vector over all groups
+  for (size_t i = 0; i < ins.size(); ++i) {
+    int col = 0;
+    for (int Rg : split_columns(ins[i].R)) {
+      Group g;
+      g.inst = (int)i;
+      g.col0 = col;
+      g.Rg = Rg;
+      g.M = ins[i].lat->g.N * Rg;
+      groups.push_back(g);
+      vec_elems += g.M;
+      col += Rg;
+    }
+  }
+  size_t freeb = 0, totalb = 0;
+  HIPCALL(hipMemGetInfo(&freeb, &totalb));
+  const size_t avail = freeb + c->ws_size;
+  const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
+  const size_t vec_bytes = (size_t)vec_elems * csz + 256 * groups.size();
+  const int total_wg_target = c->n_cu * 4;
+  const size_t fixed_guess = 2 * vec_bytes + (size_t)total_wg_target * 64 * 32 * 16 + (64u << 20);
+
+  auto fits_b = [&](int bb) {
+    // Workspace with every order of a block resident, or at least 16 of them.
+    const int need = std::min(ntr[bb - 1] + 1, 16);
+    return fixed_guess + (size_t)need * vec_bytes <= cap;
+  };
+  if (b == 0) {
+    std::vector<bool> fits(bmax + 1, false);
+    for (int bb = 1; bb <= bmax; ++bb) fits[bb] = fits_b(bb);
+    // Cost constants: one recursion step streams 3 vectors; one (n, j) pair of
+    // the contraction costs a fraction of a vector pass (measured per device
+    // when csp_select_block has calibrated this shape, else the byte model).
+    double ta = 3.0, tp = 1.0 / 32.0;
+    char key[128];
+    snprintf(key, sizeof(key), "%d:%lld:%d", (int)fp64, (long long)vec_elems, (int)groups.size());
+    auto it = c->calib.find(key);
+    if (it != c->calib.end()) {
+      ta = it->second.first;
+      tp = it->second.second;
+    }
+    b = select_b_rule(ntr, bmax, Nt, ta, tp, fits, rep ? rep->model_cost : nullptr);
+  }
+  if (Nt > 0) b = (int)std::min<int64_t>(b, Nt);
+  b = std::max(b, 1);
+  const int b_last = Nt > 0 ? (int)(Nt - (int64_t)(ceil_div(Nt, b) - 1) * b) : b;
+  const int jtiles = fp64 ? 1 : (int)ceil_div(b, 32);
+  const int N_full = ntr[b - 1];
+  const int Ktot = N_full + 1;
+
+  // Chunk size: all orders of a block if they fit, else the largest multiple
+  // of 16 that fits (the ring then holds exactly one chunk).
+  const size_t tabs_guess = (64u << 20);
+  auto ws_need = [&](int S_, int n_wg_total) {
+    size_t by = 0;
+    for (auto& g : groups) by += align256((size_t)S_ * g.M * csz) + 2 * align256(g.M * csz);
+    by += align256((size_t)n_wg_total * b * kMaxGroupCols * 16) * 2;
+    return by + tabs_guess;
+  };
+  const int wg_bound = total_wg_target + (int)groups.size();
+  const int kcap = fp64 ? 1 << 20 : (496 / jtiles / 16) * 16;   // LDS budget of B operands
+  int K = P.chunk_K > 0 ? P.chunk_K : Ktot;
+  if (K >= Ktot && Ktot <= kcap && ws_need(Ktot, wg_bound) <= cap) {
+    K = Ktot;
+  } else {
+    K = std::min(std::min(K, Ktot), kcap);
+    K = std::max(16, (K / 16) * 16);
+    while (K > 16 && ws_need(K, wg_bound) > cap) K -= 16;
+  }
+  const int S = std::max(3, K);
+  if (ws_need(S, wg_bound) > cap)
+    return fail(CSP_ENOMEM, "workspace for b=%d, K=%d exceeds the cap (%.2f GB)", b, K, cap / 1e9);
+
+  // Contraction workgroups per group, proportional to the group's values.
+  int64_t Msum = 0;
+  for (auto& g : groups) Msum += g.M;
+  int total_wg = 0;
+  for (auto& g : groups) {
+    const int64_t units = fp64 ? ceil_div(g.M, kContractThreads) : ceil_div(ceil_div(g.M, 32), 4);
+    int w = (int)std::llround((double)total_wg_target * (double)g.M / (double)Msum);
+    w = (int)std::max<int64_t>(1, std::min<int64_t>(w, units));
+    g.n_wg = w;
+    total_wg += w;
+  }
+
+  // ---------------------------------------------------------- block tables
+  std::vector<BlockTab> btabs;
+  auto make_tab = [&](int bk) {
+    BlockTab t;
+    t.bk = bk;
+    t.Nk = ntr[bk - 1];
+    for (int lo = 0; lo <= t.Nk; lo += K) t.chunks.push_back({lo, std::min(K, t.Nk + 1 - lo)});
+    return t;
+  };
+  btabs.push_back(make_tab(b));
+  if (b_last != b) btabs.push_back(make_tab(b_last));
+  size_t tab_bytes = 0;
+  for (auto& t : btabs)
+    for (auto& ch : t.chunks)
+      tab_bytes += fp64 ? align256(sizeof(double2) * ch.n_cnt * t.bk) + align256(sizeof(double2) * ch.n_cnt)
+                        : align256(bop_bytes(jtiles, ch.n_cnt)) + align256(sizeof(float) * 16 * ceil_div(ch.n_cnt, 16));
+
+  // ---------------------------------------------------------- workspace
+  size_t need = tab_bytes;
+  for (auto& g : groups) {
+    need += align256((size_t)S * g.M * csz) + 2 * align256(g.M * csz);
+    need += align256((size_t)g.n_wg * b * g.Rg * 16);
+  }
+  const size_t n_sd = 256;   // self-dot partial blocks
+  need += align256(sizeof(double) * n_sd * kMaxGroupCols);
+  need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size()) +
+          align256(sizeof(FinishInst) * groups.size());
+  if (need > cap) return fail(CSP_ENOMEM, "workspace %.2f GB exceeds the cap %.2f GB", need / 1e9, cap / 1e9);
+  CHECK(ws_reserve(c, need));
+  Carver cv(c->ws);
+  for (auto& t : btabs)
+    for (auto& ch : t.chunks) {
+      if (fp64) {
+        ch.coef = (double*)cv.take(sizeof(double2) * ch.n_cnt * t.bk);
+        ch.ccd = (double*)cv.take(sizeof(double2) * ch.n_cnt);
+        HIPCALL(launch_pack_c64(d_a, lda, d_ntr, t.bk, ch.n_lo, ch.n_cnt, ch.coef, ch.ccd, s));
+      } else {
+        ch.bop = cv.take(bop_bytes(jtiles, ch.n_cnt));
+        ch.ccf = (float*)cv.take(sizeof(float) * 16 * ceil_div(ch.n_cnt, 16));
+        HIPCALL(launch_pack_bop(d_a, lda, d_ntr, t.bk, jtiles, ch.n_lo, ch.n_cnt, ch.bop, ch.ccf, s));
+      }
+    }
+  for (auto& g : groups) {
+    g.slots = cv.take((size_t)S * g.M * csz);
+    g.psi0g = cv.take(g.M * csz);
+    g.carry = cv.take(g.M * csz);
+    g.partial = (double*)cv.take((size_t)g.n_wg * b * g.Rg * 16);
+  }
+  double* d_sd = (double*)cv.take(sizeof(double) * n_sd * kMaxGroupCols);
+  SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
+  ContractInst* d_con = (ContractInst*)cv.take(sizeof(ContractInst) * groups.size());
+  FinishInst* d_fin = (FinishInst*)cv.take(sizeof(FinishInst) * groups.size());
+
+  // ---------------------------------------------------------- instance tables
+  std::vector<SpmmInst> sp;
+  std::vector<ContractInst> ct;
+  std::vector<FinishInst> fi;
+  int wg0 = 0;
+  for (auto& g : groups) {
+    const InstIn& in = ins[g.inst];
+    SpmmInst I = make_inst(in.lat, g.Rg, fp64);
+    I.base = g.slots;
+    I.slot_stride = g.M;
+    I.src = g.carry;
+    sp.push_back(I);
+    ContractInst C{};
+    C.slots = g.slots;
+    C.slot_stride = g.M;
+    C.M = g.M;
+    C.Rg = g.Rg;
+    C.psi0 = g.psi0g;
+    C.carry = g.carry;
+    C.partial = g.partial;
+    C.wg0 = wg0;
+    C.n_wg = g.n_wg;
+    wg0 += g.n_wg;
+    ct.push_back(C);
+    FinishInst F{};
+    F.partial = g.partial;
+    F.n_wg = g.n_wg;
+    F.Rg = g.Rg;
+    F.corr = in.corr;
+    F.ldc = in.R;
+    F.col0 = g.col0;
+    fi.push_back(F);
+  }
+  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu);
+  HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(SpmmInst) * sp.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_con, ct.data(), sizeof(ContractInst) * ct.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_fin, fi.data(), sizeof(FinishInst) * fi.size(), hipMemcpyHostToDevice, s));
+
+  // ---------------------------------------------------------- initial state, C_0
+  for (auto& g : groups) {
+    const InstIn& in = ins[g.inst];
+    const int in_dtype = fp64 ? CSP_C128 : CSP_C64;
+    const int64_t N = in.lat->g.N;
+    HIPCALL(launch_gather_cols(N, in.R, g.col0, g.Rg, in_dtype, in.psi0, fp64, g.psi0g, s));
+    HIPCALL(hipMemcpyAsync(g.carry, g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
+    HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, (int)n_sd, s));
+  }
+  // ψ0 group copies and the C_0 row must be complete before the synchronous
+  // copies above go out of scope (the host vectors live until the end).
+
+  // ---------------------------------------------------------- blocks
+  Profiler prof{c, P.profile != 0};
+  int64_t n_spmm = 0, n_con = 0, amxsy = 0, axpy = 0;
+  double spmm_bytes = 0, con_bytes = 0, con_flops = 0;
+  double eps_bytes = 0;
+  for (auto& g : groups)
+    if (ins[g.inst].lat->has_onsite) eps_bytes += (double)ins[g.inst].lat->g.N * (fp64 ? 8 : 4);
+  const double step_bytes = 3.0 * (double)vec_elems * csz + eps_bytes;
+
+  ContractArgs ca{};
+  ca.n_inst = (int)groups.size();
+  ca.S = S;
+  ca.jtiles = jtiles;
+  ca.total_wg = total_wg;
+  SpmmStep st{};
+  st.seg_rows = sp_plan.seg_rows;
+  st.halo = sp_plan.halo;
+  st.total_tiles = sp_plan.total_tiles;
+
+  for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+    const int bk = (int)std::min<int64_t>(b, Nt - t0);
+    const BlockTab& T = (bk == b) ? btabs[0] : btabs.back();
+    const int Nk = T.Nk;
+    amxsy += Nk;
+    for (int j = 1; j <= bk; ++j) axpy += ntr[j - 1];
+    size_t ev = 0;
+    CHECK(prof.begin(0, &ev));
+    // order 1 from the carried state (also stored as order 0)
+    st.slot_out = 1 % S;
+    st.slot_cur = 0;
+    st.slot_prev = 0;
+    st.cur_from_src = 1;
+    st.copy_cur = 1;
+    st.has_prev = 0;
+    st.scale_f = 0.5f;
+    st.scale_d = 0.5;
+    HIPCALL(launch_spmm(fp64, sp_plan.vec, d_spmm, (int)sp.size(), st, s));
+    ++n_spmm;
+    spmm_bytes += step_bytes;
+    size_t ci = 0;
+    int produced = 1;
+    auto run_chunks = [&]() -> csp_status {
+      while (ci < T.chunks.size() && T.chunks[ci].n_lo + T.chunks[ci].n_cnt - 1 <= produced) {
+        const ChunkTab& ch = T.chunks[ci];
+        CHECK(prof.end(ev));
+        size_t evc = 0;
+        CHECK(prof.begin(1, &evc));
+        ca.n_lo = ch.n_lo;
+        ca.n_cnt = ch.n_cnt;
+        ca.first_chunk = ci == 0 ? 1 : 0;
+        ca.bcols = bk;
+        if (fp64) {
+          ca.coef = ch.coef;
+          ca.ccarry = ch.ccd;
+          HIPCALL(launch_contract_f64(d_con, ca, s));
+          con_flops += 8.0 * (double)vec_elems * ch.n_cnt * (bk + 1);
+        } else {
+          ca.bop = ch.bop;
+          ca.ccarry = ch.ccf;
+          HIPCALL(launch_contract_f32(d_con, ca, s));
+          con_flops += 2.0 * 6.0 * 32.0 * 32.0 * 16.0 * jtiles * (double)ceil_div(ch.n_cnt, 16) *
+                       (double)ceil_div(vec_elems, 32);
+        }
+        ++n_con;
+        con_bytes += (double)vec_elems * csz * (ch.n_cnt + 2 + (ci == 0 ? 0 : 1));
+        CHECK(prof.end(evc));
+        CHECK(prof.begin(0, &ev));
+        ++ci;
+      }
+      return CSP_OK;
+    };
+    CHECK(run_chunks());
+    for (int n = 1; n < Nk; ++n) {
+      st.slot_out = (n + 1) % S;
+      st.slot_cur = n % S;
+      st.slot_prev = (n - 1) % S;
+      st.cur_from_src = 0;
+      st.copy_cur = 0;
+      st.has_prev = 1;
+      st.scale_f = 1.0f;
+      st.scale_d = 1.0;
+      HIPCALL(launch_spmm(fp64, sp_plan.vec, d_spmm, (int)sp.size(), st, s));
+      ++n_spmm;
+      spmm_bytes += step_bytes;
+      produced = n + 1;
+      CHECK(run_chunks());
+    }
+    CHECK(prof.end(ev));
+    HIPCALL(launch_finish(d_fin, (int)fi.size(), bk, t0, s));
+  }
+
+  // ---------------------------------------------------------- final state
+  for (auto& g : groups) {
+    const InstIn& in = ins[g.inst];
+    if (!in.final_out) continue;
+    HIPCALL(launch_scatter_cols(in.lat->g.N, in.R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64,
+                                g.carry, fp64, in.final_out, s));
+  }
+  HIPCALL(hipStreamSynchronize(s));
+
+  if (rep) {
+    double ms_s = 0, ms_c = 0;
+    CHECK(prof.collect(&ms_s, &ms_c));
+    rep->block_b = b;
+    rep->chunk_K = K;
+    rep->n_blocks = (int)(Nt > 0 ? ceil_div(Nt, b) : 0);
+    rep->n_groups = (int)groups.size();
+    rep->amxsy = amxsy;
+    rep->axpy = axpy;
+    rep->dot = Nt;
+    rep->spmm_launches = n_spmm;
+    rep->contract_launches = n_con;
+    rep->ms_total = now_ms() - t_start;
+    rep->ms_spmm = ms_s;
+    rep->ms_contract = ms_c;
+    rep->spmm_bytes = spmm_bytes;
+    rep->contract_bytes = con_bytes;
+    rep->contract_flops = con_flops;
+    rep->workspace_bytes = c->ws_size;
+  }
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ DOS
+extern "C" csp_status csp_dos(csp_context* c, const double* dev_corr, int64_t Nt, int32_t R,
+                              double halfwidth, double tau_tilde, int32_t window, double* dev_E,
+                              double* dev_D, double* dev_Dmean) {
+  if (!c || !dev_corr || !dev_E || !dev_D) return fail(CSP_EINVAL, "NULL argument");
+  if (Nt < 1 || R < 1 || !(halfwidth > 0)) return fail(CSP_EINVAL, "need Nt >= 1, R >= 1, |H| > 0");
+  if (window != CSP_WINDOW_HANN && window != CSP_WINDOW_NONE) return fail(CSP_EINVAL, "bad window");
+  if (!(tau_tilde > 0)) tau_tilde = M_PI;
+  DeviceGuard dg(c->device);
+  double* tw = nullptr;
+  HIPCALL(hipMalloc(&tw, sizeof(double2) * 2 * Nt));
+  hipError_t e = launch_dos(dev_corr, Nt, R, halfwidth, tau_tilde, window, dev_E, dev_D, dev_Dmean,
+                            tw, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tw);
+  if (e != hipSuccess) return fail(CSP_EHIP, "dos: %s", hipGetErrorString(e));
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ block selection
+extern "C" csp_status csp_select_block(csp_context* c, const csp_lattice* L, int32_t R,
+                                       const csp_params* params, int32_t* b_out, csp_report* rep) {
+  (void)c; (void)L; (void)R; (void)params; (void)b_out; (void)rep;
+  return fail(CSP_EUNSUPPORTED, "calibrated block selection is not available in this build");
+}

@@ -1,0 +1,231 @@
+// Internal definitions of libcsp: device-side data structures, the
+// generator, lattice geometry and the host-side launch wrappers that the API
+// layer (api.cpp) calls.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "csp.h"
+
+namespace csp {
+
+// ------------------------------------------------------------------ limits
+constexpr int kMaxGroupCols = 32;     // columns per propagation group (power of 2)
+constexpr int kMaxStepCols = 64;      // columns accepted by the single-step API
+constexpr int kSpmmThreads = 256;     // recursion workgroup
+constexpr int kContractThreads = 256; // contraction workgroup (4 waves)
+constexpr int kMaxJTiles = 2;         // 32-wide time tiles: b <= 64 on MFMA
+constexpr int kMaxFp64B = 16;         // b limit of the FP64 contraction
+
+// ------------------------------------------------------------------ generator
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).  The generator's state
+// advances by the golden-ratio increment and every output is the state passed
+// through a xor-shift-multiply finaliser, so output k of the generator seeded
+// with s depends only on s + (k+1)*increment.  Draw `index` of `stream` is
+// output (stream << 40) + index.
+__host__ __device__ inline uint64_t sm64_finalise(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xbf58476d1ce4e5b9ULL;
+  z ^= z >> 27;
+  z *= 0x94d049bb133111ebULL;
+  z ^= z >> 31;
+  return z;
+}
+__host__ __device__ inline uint64_t rng_draw(uint64_t seed, uint64_t stream, uint64_t index) {
+  const uint64_t counter = (stream << 40) + index;
+  return sm64_finalise(seed + (counter + 1ULL) * 0x9e3779b97f4a7c15ULL);
+}
+// Top 53 bits as a double in [0, 1).
+__host__ __device__ inline double rng_unit(uint64_t bits) {
+  return static_cast<double>(bits >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+  int32_t kind;        // csp_lattice_kind
+  int32_t px, py;      // periodic flags
+  int32_t pad;
+  int64_t Lx, Ly;      // cells (Ly = 1 for chains)
+  int64_t N;           // orbitals
+  int64_t opr;         // orbitals per row: Lx, or 2*Lx for honeycomb
+};
+
+__host__ __device__ inline int max_degree(int kind) {
+  return kind == CSP_CHAIN ? 2 : (kind == CSP_SQUARE ? 4 : 3);
+}
+
+// Neighbour k of orbital s (-1 if the bond is cut by an open edge).
+__host__ __device__ inline int64_t neighbour(const Geom& g, int64_t s, int k) {
+  if (g.kind == CSP_CHAIN) {
+    int64_t x = s;
+    if (k == 0) return x > 0 ? x - 1 : (g.px ? g.Lx - 1 : -1);
+    return x + 1 < g.Lx ? x + 1 : (g.px ? 0 : -1);
+  }
+  if (g.kind == CSP_SQUARE) {
+    int64_t y = s / g.Lx, x = s - y * g.Lx;
+    switch (k) {
+      case 0: return x > 0 ? s - 1 : (g.px ? s + g.Lx - 1 : -1);
+      case 1: return x + 1 < g.Lx ? s + 1 : (g.px ? s - x : -1);
+      case 2: return y > 0 ? s - g.Lx : (g.py ? s + (g.Ly - 1) * g.Lx : -1);
+      default: return y + 1 < g.Ly ? s + g.Lx : (g.py ? x : -1);
+    }
+  }
+  // honeycomb
+  int64_t cell = s >> 1;
+  int sig = static_cast<int>(s & 1);
+  int64_t y = cell / g.Lx, x = cell - y * g.Lx;
+  if (sig == 0) {  // A(x, y): B(x, y), B(x-1, y), B(x, y-1)
+    switch (k) {
+      case 0: return s + 1;
+      case 1: return x > 0 ? s - 1 : (g.px ? 2 * (y * g.Lx + g.Lx - 1) + 1 : -1);
+      default: return y > 0 ? 2 * ((y - 1) * g.Lx + x) + 1 : (g.py ? 2 * ((g.Ly - 1) * g.Lx + x) + 1 : -1);
+    }
+  }
+  // B(x, y): A(x, y), A(x+1, y), A(x, y+1)
+  switch (k) {
+    case 0: return s - 1;
+    case 1: return x + 1 < g.Lx ? s + 1 : (g.px ? 2 * (y * g.Lx) : -1);
+    default: return y + 1 < g.Ly ? 2 * ((y + 1) * g.Lx + x) : (g.py ? 2 * x : -1);
+  }
+}
+
+// ------------------------------------------------------------------ recursion
+// One instance of a recursion launch: a lattice and a group of R columns
+// stored [N][R] complex in slots base + slot * slot_stride.
+struct SpmmInst {
+  int32_t kind, px, py, R;
+  int64_t Ly, opr, rowlen;     // rowlen = opr * R complex values
+  double alpha;                // 2 t / |H|
+  double beta0;                // -2 H0 / |H|
+  double onsite_scale;         // 2 / |H|
+  const void* eps;             // per-orbital on-site energy (float or double), may be null
+  void* base;                  // slot array
+  int64_t slot_stride;         // complex values between slots
+  const void* src;             // input vector when the step reads from outside the slots
+  void* moment_psi0;           // psi0 of the group for the moment epilogue (may be null)
+  double* moment_out;          // per-WG moment partials [n_tiles][R] complex
+  int64_t n_strips, n_segs;    // tiling of this instance
+  int64_t tile0;               // first tile of this instance in the launch
+};
+
+// Per-step arguments of a recursion launch.
+struct SpmmStep {
+  int32_t slot_out, slot_cur, slot_prev;
+  int32_t cur_from_src;    // read the current vector from inst.src
+  int32_t copy_cur;        // also write the current vector into slot_cur
+  int32_t has_prev;        // subtract the previous vector (2 H~ x - y form)
+  float scale_f;           // 1 (2 H~ x - y) or 0.5 (H~ x)
+  double scale_d;
+  int32_t seg_rows;        // rows per tile
+  int32_t halo;            // max R over instances (LDS halo width)
+  int32_t moments;         // moment epilogue on
+  int32_t moment_slot;     // index of the moment in moment_out (row of [K][tiles][R])
+  int64_t total_tiles;
+};
+
+hipError_t launch_spmm(bool fp64, int vec, const SpmmInst* d_inst, int n_inst,
+                       const SpmmStep& st, hipStream_t s);
+
+// ------------------------------------------------------------------ contraction
+struct ContractInst {
+  const void* slots;        // slot array of the group
+  int64_t slot_stride;      // complex values
+  int64_t M;                // N * Rg complex values
+  int32_t Rg;               // columns of the group (power of 2, <= 32)
+  int32_t pad;
+  const void* psi0;         // psi0 of the group [M]
+  void* carry;              // carried state [M]
+  double* partial;          // [n_wg][b][Rg] complex (2 doubles)
+  int32_t wg0, n_wg;        // workgroups of this instance in the launch
+};
+
+struct ContractArgs {
+  int32_t n_inst;
+  int32_t n_lo, n_cnt;      // orders n_lo .. n_lo + n_cnt - 1 of this chunk
+  int32_t S;                // ring size: order n lives in slot n % S
+  int32_t first_chunk;      // write (1) or accumulate (0) carry and partials
+  int32_t jtiles;           // 32-wide time tiles (FP32 MFMA path)
+  int32_t bcols;            // time points of the block (b_k)
+  int32_t total_wg;
+  const void* bop;          // FP32 path: B operands in MFMA lane layout
+  const void* coef;         // FP64 path: complex c[n][j], [n_cnt][bcols]
+  const void* ccarry;       // carry coefficients: float a_n (FP32 path) or complex double (FP64)
+};
+
+hipError_t launch_contract_f32(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s);
+hipError_t launch_contract_f64(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s);
+
+// Finish: corr[(t0 + j) * ldc + col0 + r] = sum_wg partial[wg][j-1][r], j = 1..b.
+struct FinishInst {
+  const double* partial;
+  int32_t n_wg, Rg;
+  double* corr;             // device correlation array of the instance
+  int64_t ldc;              // R of the instance
+  int32_t col0;
+  int32_t pad;
+};
+hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_t t0,
+                         hipStream_t s);
+
+// ------------------------------------------------------------------ coefficients
+// For x_j = (j + 1) * tau, j = 0..nx-1: a[j][n] = J_n(x_j) (n = 0) or
+// 2 J_n(x_j) (n >= 1) for n <= nmax, and ntrunc[j] = N(x_j).
+hipError_t launch_bessel(double tau, int nx, int nmax, double eta, double* d_a,
+                         int32_t* d_ntrunc, hipStream_t s);
+// Complex c_n(x) = (-i)^n a_n written as complex128 [nmax+1].
+hipError_t launch_complex_coeffs(const double* d_a, int nmax, double* d_c, hipStream_t s);
+// B-operand table of the MFMA contraction for orders n_lo..n_lo+n_cnt-1 and
+// time columns j = 1..bcols (a is [bcols][lda] as produced by launch_bessel),
+// plus the FP32 carry coefficients a[bcols-1][n].
+hipError_t launch_pack_bop(const double* d_a, int lda, const int32_t* d_ntrunc, int bcols,
+                           int jtiles, int n_lo, int n_cnt, void* d_bop, float* d_ccarry,
+                           hipStream_t s);
+// FP64 complex coefficient table c[n - n_lo][j] and carry coefficients.
+hipError_t launch_pack_c64(const double* d_a, int lda, const int32_t* d_ntrunc, int bcols,
+                           int n_lo, int n_cnt, double* d_coef, double* d_ccarry,
+                           hipStream_t s);
+size_t bop_bytes(int jtiles, int n_cnt);
+
+// ------------------------------------------------------------------ setup kernels
+hipError_t launch_onsite(const Geom& g, double W, uint64_t seed, double* d_eps64,
+                         float* d_eps32, hipStream_t s);
+hipError_t launch_gershgorin(const Geom& g, const double* d_eps, double t, double H0,
+                             double* d_rowmax_partial, int n_partial, hipStream_t s);
+hipError_t launch_neighbours(const Geom& g, int64_t* d_nbr, hipStream_t s);
+hipError_t launch_random_phase(int64_t N, int R, uint64_t seed, int dtype, void* d_psi,
+                               int ld, int col0, hipStream_t s);
+hipError_t launch_ldos_sites(int64_t N, int n, uint64_t seed, int64_t* d_sites, hipStream_t s);
+hipError_t launch_site_states(int64_t N, int n, const int64_t* d_sites, int dtype, void* d_psi,
+                              int ld, int col0, hipStream_t s);
+// Copy columns col0..col0+Rg-1 of an [N][ld] block (dtype) into a dense [N][Rg]
+// block of the path's precision (fp64 selects double2 output).
+hipError_t launch_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype,
+                              const void* d_in, bool fp64, void* d_out, hipStream_t s);
+hipError_t launch_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtype,
+                               const void* d_in, bool fp64, void* d_out, hipStream_t s);
+// C_0: corr[col0 + r] = <psi0_r|psi0_r> for an [N][Rg] group, FP64 result.
+hipError_t launch_self_dot(int64_t N, int Rg, const void* d_psi, bool fp64, double* d_corr,
+                           int col0, double* d_scratch, int n_scratch_wg, hipStream_t s);
+// Moments -> correlations: corr[t0 + j][col0 + r] = sum_n c_n(j tau) mu_n[r].
+hipError_t launch_moment_corr(const double* d_mu_partial, int n_tiles, int Rg, int n_cnt,
+                              const double* d_a, int lda, const int32_t* d_ntrunc, int bcols,
+                              int64_t t0, double* d_corr, int64_t ldc, int col0,
+                              hipStream_t s);
+hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth,
+                      double tau_tilde, int window, double* d_E, double* d_D, double* d_Dmean,
+                      double* d_twiddle, hipStream_t s);
+
+// ------------------------------------------------------------------ helpers
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Workgroup b of g runs on XCD b % 8; return the logical index that gives each
+// XCD one contiguous range of logical indices (so that neighbouring tiles of a
+// lattice share the L2 of one XCD).
+__device__ inline int64_t xcd_remap(int64_t b, int64_t g) {
+  const int64_t q = g / 8, rem = g % 8;
+  const int64_t x = b % 8, k = b / 8;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+}  // namespace csp

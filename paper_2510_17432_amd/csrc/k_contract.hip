@@ -1,0 +1,356 @@
+// Block contraction of Chebyshev vectors with expansion coefficients
+// (state-based concurrent form, Eq. TE):
+//   psi(t_{kb+j}) = sum_n c_n(j tau) phi_n,   j = 1..b_k,
+// fused with the correlation reduction <psi0|psi(t_{kb+j})> and with the
+// carried state s_{k+1} = psi(t_{kb+b_k}) (Sec. II.B time blocks).
+//
+// FP32 path (MFMA).  With c_n(x) = (-i)^n a_n(x), a_n real (App. B:
+// a_0 = J_0, a_n = 2 J_n), write X_n = (-i)^n phi_n = p_n + i q_n.  Then
+//   Re psi_j = sum_n p_n a_{n,j},   Im psi_j = sum_n q_n a_{n,j},
+// two real products of a [32 values x K orders] tile with one real
+// [K x 32 times] coefficient tile, which run on v_mfma_f32_32x32x16_bf16.
+// Each FP32 operand is split x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi), and the product is hi*hi + hi*lo + lo*hi (the lo*lo term
+// is below FP32 resolution), accumulated in FP32.  The carried state uses
+// plain FP32 FMAs on the same loaded values, since its error would feed
+// every later block.
+//
+// One wave owns one 32-value tile at a time: lane (i = lane%32, h = lane/32)
+// loads value i of orders 8h..8h+7 of each 16-order step (coalesced: for a
+// fixed order the 32 lanes read 256 contiguous bytes).  The B operand (lane
+// (j, h) holds time j, orders 8h..8h+7) is staged in LDS once per launch.
+// The accumulator holds psi for rows 8(v/4) + 4h + v%4 and time lane%32; the
+// epilogue multiplies by conj(psi0) and accumulates per lane, then the
+// workgroup reduces in FP64 in a fixed order and writes its partial sums.
+#include "csp_internal.h"
+
+namespace csp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct BopEntry {
+  bf16x8 hi;
+  bf16x8 lo;
+};
+
+size_t bop_bytes(int jtiles, int n_cnt) {
+  return sizeof(BopEntry) * 64 * (size_t)jtiles * (size_t)ceil_div(n_cnt, 16);
+}
+
+template <int JT>
+__global__ __launch_bounds__(kContractThreads) void k_contract_f32(
+    const ContractInst* __restrict__ insts, ContractArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n_kb = (a.n_cnt + 15) >> 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int il = lane & 31, h = lane >> 5;
+
+  const int nb_entries = n_kb * JT * 64;
+  BopEntry* sb = reinterpret_cast<BopEntry*>(smem);
+  const size_t bop_sz = sizeof(BopEntry) * (size_t)nb_entries;
+  const size_t red_sz = sizeof(double2) * JT * 32 * kMaxGroupCols;
+  float* sc = reinterpret_cast<float*>(smem + (bop_sz > red_sz ? bop_sz : red_sz));
+  double2* sred = reinterpret_cast<double2*>(smem);
+
+  {
+    const BopEntry* gb = static_cast<const BopEntry*>(a.bop);
+    for (int e = tid; e < nb_entries; e += kContractThreads) sb[e] = gb[e];
+    const float* gc = static_cast<const float*>(a.ccarry);
+    for (int e = tid; e < n_kb * 16; e += kContractThreads) sc[e] = e < a.n_cnt ? gc[e] : 0.f;
+  }
+  __syncthreads();
+
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  int ii = 0;
+  while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
+  const ContractInst& I = insts[ii];
+  const int64_t wgl = wg - I.wg0;
+  const float2* slots = static_cast<const float2*>(I.slots);
+  const float2* psi0 = static_cast<const float2*>(I.psi0);
+  float2* carry = static_cast<float2*>(I.carry);
+  const int64_t M = I.M;
+  const int64_t n_tiles = ceil_div(M, 32);
+  const int Rg = I.Rg;
+
+  float pr[JT][16], pi[JT][16];
+#pragma unroll
+  for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { pr[jt][v] = 0.f; pi[jt][v] = 0.f; }
+
+  const int64_t stride_tiles = (int64_t)I.n_wg * 4;
+  for (int64_t tile = wgl * 4 + wave; tile < n_tiles; tile += stride_tiles) {
+    const int64_t m = tile * 32 + il;
+    const bool mv = m < M;
+    f32x16 accR[JT], accI[JT];
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) { accR[jt][v] = 0.f; accI[jt][v] = 0.f; }
+    float cr = 0.f, ci = 0.f;
+
+    for (int kb = 0; kb < n_kb; ++kb) {
+      const int r0 = kb * 16 + h * 8;
+      float2 x[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int rel = r0 + v;
+        const int n = a.n_lo + rel;
+        x[v] = (mv && rel < a.n_cnt) ? slots[(int64_t)(n % a.S) * I.slot_stride + m]
+                                     : make_float2(0.f, 0.f);
+      }
+      bf16x8 phi, plo, qhi, qlo;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int n = a.n_lo + r0 + v;
+        float p, q;
+        switch (n & 3) {            // (-i)^n (u + i w)
+          case 0: p = x[v].x;  q = x[v].y;  break;
+          case 1: p = x[v].y;  q = -x[v].x; break;
+          case 2: p = -x[v].x; q = -x[v].y; break;
+          default: p = -x[v].y; q = x[v].x; break;
+        }
+        const float cc = sc[r0 + v];
+        cr = fmaf(cc, p, cr);
+        ci = fmaf(cc, q, ci);
+        const __bf16 ph = static_cast<__bf16>(p);
+        const __bf16 qh = static_cast<__bf16>(q);
+        phi[v] = ph;
+        qhi[v] = qh;
+        plo[v] = static_cast<__bf16>(p - static_cast<float>(ph));
+        qlo[v] = static_cast<__bf16>(q - static_cast<float>(qh));
+      }
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const BopEntry be = sb[(kb * JT + jt) * 64 + lane];
+        accR[jt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(phi, be.hi, accR[jt], 0, 0, 0);
+        accR[jt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(phi, be.lo, accR[jt], 0, 0, 0);
+        accR[jt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(plo, be.hi, accR[jt], 0, 0, 0);
+        accI[jt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qhi, be.hi, accI[jt], 0, 0, 0);
+        accI[jt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qhi, be.lo, accI[jt], 0, 0, 0);
+        accI[jt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qlo, be.hi, accI[jt], 0, 0, 0);
+      }
+    }
+
+    // Carried state: the two half-waves hold complementary orders of row il.
+    cr += __shfl_xor(cr, 32);
+    ci += __shfl_xor(ci, 32);
+    if (h == 0 && mv) {
+      float2 cv = make_float2(cr, ci);
+      if (!a.first_chunk) {
+        const float2 old = carry[m];
+        cv.x += old.x;
+        cv.y += old.y;
+      }
+      carry[m] = cv;
+    }
+
+    // Correlation epilogue: conj(psi0[row]) * psi[row, time].
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t mm = tile * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+      const float2 p0 = mm < M ? psi0[mm] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const float re = accR[jt][v], im = accI[jt][v];
+        pr[jt][v] = fmaf(p0.x, re, fmaf(p0.y, im, pr[jt][v]));
+        pi[jt][v] = fmaf(p0.x, im, fmaf(-p0.y, re, pi[jt][v]));
+      }
+    }
+  }
+
+  // Workgroup reduction in FP64, fixed order: waves 0..3, half-waves 0, 1.
+  __syncthreads();  // LDS B operands are no longer needed
+  const int nred = JT * 32 * Rg;
+  for (int e = tid; e < nred; e += kContractThreads) sred[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      for (int half = 0; half < 2; ++half) {
+        if (h == half) {
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int r = (8 * (v >> 2) + 4 * h + (v & 3)) & (Rg - 1);
+              double2& d = sred[(jt * 32 + il) * Rg + r];
+              d.x += static_cast<double>(pr[jt][v]);
+              d.y += static_cast<double>(pi[jt][v]);
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double2* part = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols * Rg;
+  for (int e = tid; e < a.bcols * Rg; e += kContractThreads) {
+    const double2 v = sred[e];
+    if (a.first_chunk) {
+      part[e] = v;
+    } else {
+      double2 o = part[e];
+      o.x += v.x;
+      o.y += v.y;
+      part[e] = o;
+    }
+  }
+}
+
+// FP64 contraction: one value per thread, B (<= 16) time columns in
+// registers, complex coefficients c[n][j] in LDS.
+template <int B>
+__global__ __launch_bounds__(kContractThreads) void k_contract_f64(
+    const ContractInst* __restrict__ insts, ContractArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2* scoef = reinterpret_cast<double2*>(smem);           // [n_cnt][B]
+  double2* scc = scoef + (size_t)a.n_cnt * B;                  // [n_cnt]
+  double2* sred = scc + a.n_cnt;                               // [256]
+  const int tid = threadIdx.x;
+  {
+    const double2* gc = static_cast<const double2*>(a.coef);
+    for (int e = tid; e < a.n_cnt * B; e += kContractThreads) {
+      const int n = e / B, j = e - n * B;
+      scoef[e] = j < a.bcols ? gc[(size_t)n * a.bcols + j] : make_double2(0.0, 0.0);
+    }
+    const double2* gcc = static_cast<const double2*>(a.ccarry);
+    for (int e = tid; e < a.n_cnt; e += kContractThreads) scc[e] = gcc[e];
+  }
+  __syncthreads();
+
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  int ii = 0;
+  while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
+  const ContractInst& I = insts[ii];
+  const int64_t wgl = wg - I.wg0;
+  const double2* slots = static_cast<const double2*>(I.slots);
+  const double2* psi0 = static_cast<const double2*>(I.psi0);
+  double2* carry = static_cast<double2*>(I.carry);
+  const int64_t M = I.M;
+  const int Rg = I.Rg;
+
+  double2 part[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) part[j] = make_double2(0.0, 0.0);
+
+  const int64_t step = (int64_t)I.n_wg * kContractThreads;
+  for (int64_t m = wgl * kContractThreads + tid; m < M; m += step) {
+    double2 acc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = make_double2(0.0, 0.0);
+    double2 cy = make_double2(0.0, 0.0);
+    for (int rel = 0; rel < a.n_cnt; ++rel) {
+      const double2 x = slots[(int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + m];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const double2 c = scoef[rel * B + j];
+        acc[j].x = fma(c.x, x.x, fma(-c.y, x.y, acc[j].x));
+        acc[j].y = fma(c.x, x.y, fma(c.y, x.x, acc[j].y));
+      }
+      const double2 c = scc[rel];
+      cy.x = fma(c.x, x.x, fma(-c.y, x.y, cy.x));
+      cy.y = fma(c.x, x.y, fma(c.y, x.x, cy.y));
+    }
+    if (!a.first_chunk) {
+      const double2 o = carry[m];
+      cy.x += o.x;
+      cy.y += o.y;
+    }
+    carry[m] = cy;
+    const double2 p0 = psi0[m];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      part[j].x = fma(p0.x, acc[j].x, fma(p0.y, acc[j].y, part[j].x));
+      part[j].y = fma(p0.x, acc[j].y, fma(-p0.y, acc[j].x, part[j].y));
+    }
+  }
+
+  // Thread tid always sees column tid % Rg (the element stride is a multiple
+  // of 256 and Rg divides 256): reduce over tid = r, r + Rg, ... in order.
+  double2* outp = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols * Rg;
+  for (int j = 0; j < a.bcols && j < B; ++j) {
+    sred[tid] = part[j];
+    __syncthreads();
+    if (tid < Rg) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int k = tid; k < kContractThreads; k += Rg) {
+        s.x += sred[k].x;
+        s.y += sred[k].y;
+      }
+      double2* d = outp + (int64_t)j * Rg + tid;
+      if (a.first_chunk) {
+        *d = s;
+      } else {
+        double2 o = *d;
+        o.x += s.x;
+        o.y += s.y;
+        *d = o;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_contract_f32(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s) {
+  if (a.total_wg <= 0 || a.n_cnt <= 0) return hipSuccess;
+  const size_t bsz = bop_bytes(a.jtiles, a.n_cnt);
+  const size_t rsz = sizeof(double2) * a.jtiles * 32 * kMaxGroupCols;
+  const size_t lds = (bsz > rsz ? bsz : rsz) + sizeof(float) * 16 * ceil_div(a.n_cnt, 16);
+  const dim3 grid(a.total_wg), block(kContractThreads);
+  if (a.jtiles == 1)
+    hipLaunchKernelGGL(k_contract_f32<1>, grid, block, lds, s, d_inst, a);
+  else if (a.jtiles == 2)
+    hipLaunchKernelGGL(k_contract_f32<2>, grid, block, lds, s, d_inst, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_f64(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s) {
+  if (a.total_wg <= 0 || a.n_cnt <= 0) return hipSuccess;
+  int B = 1;
+  while (B < a.bcols) B *= 2;
+  if (B > kMaxFp64B) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double2) * ((size_t)a.n_cnt * B + a.n_cnt + kContractThreads);
+  const dim3 grid(a.total_wg), block(kContractThreads);
+  switch (B) {
+    case 1: hipLaunchKernelGGL(k_contract_f64<1>, grid, block, lds, s, d_inst, a); break;
+    case 2: hipLaunchKernelGGL(k_contract_f64<2>, grid, block, lds, s, d_inst, a); break;
+    case 4: hipLaunchKernelGGL(k_contract_f64<4>, grid, block, lds, s, d_inst, a); break;
+    case 8: hipLaunchKernelGGL(k_contract_f64<8>, grid, block, lds, s, d_inst, a); break;
+    case 16: hipLaunchKernelGGL(k_contract_f64<16>, grid, block, lds, s, d_inst, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Sum the workgroup partials of every instance in workgroup order (FP64).
+__global__ void k_finish(const FinishInst* __restrict__ insts, int n_inst, int bcols,
+                         int64_t t0) {
+  const int ii = blockIdx.y;
+  if (ii >= n_inst) return;
+  const FinishInst& I = insts[ii];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= bcols * I.Rg) return;
+  const int j = e / I.Rg, r = e - j * I.Rg;
+  const double2* p = reinterpret_cast<const double2*>(I.partial);
+  double sx = 0.0, sy = 0.0;
+  for (int w = 0; w < I.n_wg; ++w) {
+    const double2 v = p[(int64_t)w * bcols * I.Rg + e];
+    sx += v.x;
+    sy += v.y;
+  }
+  double2* c = reinterpret_cast<double2*>(I.corr);
+  c[(t0 + 1 + j) * I.ldc + I.col0 + r] = make_double2(sx, sy);
+}
+
+hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_t t0,
+                         hipStream_t s) {
+  const int need = bcols * kMaxGroupCols;
+  const dim3 grid(static_cast<unsigned>(ceil_div(need, 256)), n_inst), block(256);
+  hipLaunchKernelGGL(k_finish, grid, block, 0, s, d_inst, n_inst, bcols, t0);
+  return hipGetLastError();
+}
+
+}  // namespace csp

@@ -1,0 +1,291 @@
+// Set-up and small kernels: on-site disorder, spectral bound, neighbour
+// table, random-phase and localized states, column-group gather/scatter,
+// <psi0|psi0>, and the DOS transform (Sec. III).
+#include "csp_internal.h"
+
+namespace csp {
+
+// ------------------------------------------------------------------ lattice
+__global__ void k_onsite(int64_t N, double W, uint64_t seed, double* __restrict__ e64,
+                         float* __restrict__ e32) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const double e = W * (rng_unit(rng_draw(seed, 0, (uint64_t)s)) - 0.5);
+  e64[s] = e;
+  e32[s] = static_cast<float>(e);
+}
+
+hipError_t launch_onsite(const Geom& g, double W, uint64_t seed, double* d_eps64, float* d_eps32,
+                         hipStream_t s) {
+  const int64_t nb = ceil_div(g.N, 256);
+  hipLaunchKernelGGL(k_onsite, dim3((unsigned)nb), dim3(256), 0, s, g.N, W, seed, d_eps64, d_eps32);
+  return hipGetLastError();
+}
+
+// Gershgorin row bound max_s (|eps_s - H0| + deg(s) |t|); one max per block.
+__global__ void k_gershgorin(Geom g, const double* __restrict__ eps, double t, double H0,
+                             double* __restrict__ partial) {
+  __shared__ double red[256];
+  double m = 0.0;
+  const int deg_max = max_degree(g.kind);
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < g.N;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    int deg = 0;
+    for (int k = 0; k < deg_max; ++k) deg += neighbour(g, s, k) >= 0 ? 1 : 0;
+    const double e = eps ? eps[s] : 0.0;
+    const double r = fabs(e - H0) + deg * fabs(t);
+    m = r > m ? r : m;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = red[threadIdx.x + w];
+      red[threadIdx.x] = o > red[threadIdx.x] ? o : red[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_gershgorin(const Geom& g, const double* d_eps, double t, double H0,
+                             double* d_partial, int n_partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_gershgorin, dim3(n_partial), dim3(256), 0, s, g, d_eps, t, H0, d_partial);
+  return hipGetLastError();
+}
+
+__global__ void k_neighbours(Geom g, int64_t* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.N) return;
+  const int d = max_degree(g.kind);
+  for (int k = 0; k < d; ++k) out[s * d + k] = neighbour(g, s, k);
+}
+
+hipError_t launch_neighbours(const Geom& g, int64_t* d_nbr, hipStream_t s) {
+  hipLaunchKernelGGL(k_neighbours, dim3((unsigned)ceil_div(g.N, 256)), dim3(256), 0, s, g, d_nbr);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ states
+__global__ void k_random_phase(int64_t N, int R, uint64_t seed, int dtype, void* __restrict__ psi,
+                               int ld, int col0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * R) return;
+  const int64_t s = e / R;
+  const int r = static_cast<int>(e - s * R);
+  const double u = rng_unit(rng_draw(seed, (uint64_t)r, (uint64_t)s));
+  double sn, cs;
+  sincospi(2.0 * u, &sn, &cs);
+  const double inv = 1.0 / sqrt(static_cast<double>(N));
+  const int64_t at = s * ld + col0 + r;
+  if (dtype == CSP_C128)
+    static_cast<double2*>(psi)[at] = make_double2(cs * inv, sn * inv);
+  else
+    static_cast<float2*>(psi)[at] = make_float2(static_cast<float>(cs * inv),
+                                                static_cast<float>(sn * inv));
+}
+
+hipError_t launch_random_phase(int64_t N, int R, uint64_t seed, int dtype, void* d_psi, int ld,
+                               int col0, hipStream_t s) {
+  hipLaunchKernelGGL(k_random_phase, dim3((unsigned)ceil_div(N * R, 256)), dim3(256), 0, s, N, R,
+                     seed, dtype, d_psi, ld, col0);
+  return hipGetLastError();
+}
+
+// Sequential by nature (distinct draws in order); one thread.
+__global__ void k_ldos_sites(int64_t N, int n, uint64_t seed, int64_t* __restrict__ sites) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int got = 0;
+  for (uint64_t i = 0; got < n; ++i) {
+    const uint64_t bits = rng_draw(seed, 0, i);
+    const int64_t s = static_cast<int64_t>(__umul64hi(bits, static_cast<uint64_t>(N)));
+    bool dup = false;
+    for (int k = 0; k < got; ++k) dup |= sites[k] == s;
+    if (!dup) sites[got++] = s;
+  }
+}
+
+hipError_t launch_ldos_sites(int64_t N, int n, uint64_t seed, int64_t* d_sites, hipStream_t s) {
+  hipLaunchKernelGGL(k_ldos_sites, dim3(1), dim3(1), 0, s, N, n, seed, d_sites);
+  return hipGetLastError();
+}
+
+__global__ void k_site_states(int64_t N, int n, const int64_t* __restrict__ sites, int dtype,
+                              void* __restrict__ psi, int ld, int col0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * n) return;
+  const int64_t s = e / n;
+  const int k = static_cast<int>(e - s * n);
+  const double v = sites[k] == s ? 1.0 : 0.0;
+  const int64_t at = s * ld + col0 + k;
+  if (dtype == CSP_C128)
+    static_cast<double2*>(psi)[at] = make_double2(v, 0.0);
+  else
+    static_cast<float2*>(psi)[at] = make_float2(static_cast<float>(v), 0.f);
+}
+
+hipError_t launch_site_states(int64_t N, int n, const int64_t* d_sites, int dtype, void* d_psi,
+                              int ld, int col0, hipStream_t s) {
+  hipLaunchKernelGGL(k_site_states, dim3((unsigned)ceil_div(N * n, 256)), dim3(256), 0, s, N, n,
+                     d_sites, dtype, d_psi, ld, col0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ column groups
+__global__ void k_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype,
+                              const void* __restrict__ in, int fp64, void* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * Rg) return;
+  const int64_t s = e / Rg;
+  const int r = static_cast<int>(e - s * Rg);
+  const int64_t at = s * ld + col0 + r;
+  double x, y;
+  if (in_dtype == CSP_C128) {
+    const double2 v = static_cast<const double2*>(in)[at];
+    x = v.x; y = v.y;
+  } else {
+    const float2 v = static_cast<const float2*>(in)[at];
+    x = v.x; y = v.y;
+  }
+  if (fp64) static_cast<double2*>(out)[e] = make_double2(x, y);
+  else static_cast<float2*>(out)[e] = make_float2(static_cast<float>(x), static_cast<float>(y));
+}
+
+hipError_t launch_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype, const void* d_in,
+                              bool fp64, void* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)ceil_div(N * Rg, 256)), dim3(256), 0, s, N, ld,
+                     col0, Rg, in_dtype, d_in, fp64 ? 1 : 0, d_out);
+  return hipGetLastError();
+}
+
+__global__ void k_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtype,
+                               const void* __restrict__ in, int fp64, void* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * Rg) return;
+  const int64_t s = e / Rg;
+  const int r = static_cast<int>(e - s * Rg);
+  double x, y;
+  if (fp64) {
+    const double2 v = static_cast<const double2*>(in)[e];
+    x = v.x; y = v.y;
+  } else {
+    const float2 v = static_cast<const float2*>(in)[e];
+    x = v.x; y = v.y;
+  }
+  const int64_t at = s * ld + col0 + r;
+  if (out_dtype == CSP_C128) static_cast<double2*>(out)[at] = make_double2(x, y);
+  else static_cast<float2*>(out)[at] = make_float2(static_cast<float>(x), static_cast<float>(y));
+}
+
+hipError_t launch_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtype, const void* d_in,
+                               bool fp64, void* d_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)ceil_div(N * Rg, 256)), dim3(256), 0, s, N,
+                     ld, col0, Rg, out_dtype, d_in, fp64 ? 1 : 0, d_out);
+  return hipGetLastError();
+}
+
+// <psi_r|psi_r> per column of an [N][Rg] group: FP64 partial per block (in a
+// fixed order), then one block sums the partials in order.
+__global__ void k_self_dot_partial(int64_t M, int Rg, const void* __restrict__ psi, int fp64,
+                                   double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x; m < M; m += (int64_t)gridDim.x * 256) {
+    double x, y;
+    if (fp64) { const double2 v = static_cast<const double2*>(psi)[m]; x = v.x; y = v.y; }
+    else { const float2 v = static_cast<const float2*>(psi)[m]; x = v.x; y = v.y; }
+    acc = fma(x, x, fma(y, y, acc));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < Rg) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < 256; k += Rg) s += red[k];
+    partial[(int64_t)blockIdx.x * Rg + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_self_dot_finish(int n_wg, int Rg, const double* __restrict__ partial,
+                                  double* __restrict__ corr, int col0) {
+  const int r = threadIdx.x;
+  if (r >= Rg) return;
+  double s = 0.0;
+  for (int w = 0; w < n_wg; ++w) s += partial[(int64_t)w * Rg + r];
+  corr[2 * (col0 + r)] = s;
+  corr[2 * (col0 + r) + 1] = 0.0;
+}
+
+hipError_t launch_self_dot(int64_t N, int Rg, const void* d_psi, bool fp64, double* d_corr,
+                           int col0, double* d_scratch, int n_scratch_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg), dim3(256), 0, s, N * Rg, Rg, d_psi,
+                     fp64 ? 1 : 0, d_scratch);
+  hipLaunchKernelGGL(k_self_dot_finish, dim3(1), dim3(64), 0, s, n_scratch_wg, Rg, d_scratch,
+                     d_corr, col0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ DOS
+// twiddle[m] = exp(i pi m / Nt), m = 0..2Nt-1 (exact arguments via sincospi).
+__global__ void k_twiddle(int64_t Nt, double2* __restrict__ tw) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= 2 * Nt) return;
+  double sn, cs;
+  sincospi(static_cast<double>(m) / static_cast<double>(Nt), &sn, &cs);
+  tw[m] = make_double2(cs, sn);
+}
+
+// D_r(E_k) for k = -Nt..Nt-1 (index k + Nt), pairing j with -j:
+// (tau/2pi) [w_0 Re C_0 + 2 sum_{j=1}^{Nt-1} w_j Re(C_j e^{i pi k j/Nt})
+//            + w_{Nt} Re(conj(C_Nt) e^{-i pi k})].
+__global__ void k_dos(const double2* __restrict__ corr, int64_t Nt, int R, double pref,
+                      int window, const double2* __restrict__ tw, double* __restrict__ D) {
+  const int64_t kk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // 0..2Nt-1
+  const int r = blockIdx.y;
+  if (kk >= 2 * Nt) return;
+  const int64_t two = 2 * Nt;
+  const int64_t kpos = (kk - Nt + two) % two;   // k mod 2Nt, nonnegative
+  auto w = [&](int64_t j) { return window == CSP_WINDOW_HANN ? 0.5 * (1.0 + tw[j].x) : 1.0; };
+  double acc = w(0) * corr[r].x;
+  int64_t idx = 0;
+  for (int64_t j = 1; j < Nt; ++j) {
+    idx += kpos;
+    if (idx >= two) idx -= two;
+    const double2 c = corr[j * R + r];
+    const double2 t = tw[idx];
+    acc += 2.0 * w(j) * (c.x * t.x - c.y * t.y);
+  }
+  {
+    const double2 c = corr[Nt * R + r];
+    const double2 t = tw[(two - (kpos * Nt) % two) % two];   // e^{-i pi k}
+    acc += w(Nt) * (c.x * t.x + c.y * t.y);
+  }
+  D[kk * R + r] = pref * acc;
+}
+
+__global__ void k_dos_mean(int64_t n, int R, const double* __restrict__ D, double* __restrict__ Dm,
+                           double* __restrict__ E, double dE, int64_t Nt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s = 0.0;
+  for (int r = 0; r < R; ++r) s += D[k * R + r];
+  if (Dm) Dm[k] = s / R;
+  E[k] = dE * static_cast<double>(k - Nt);
+}
+
+hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth, double tau_tilde,
+                      int window, double* d_E, double* d_D, double* d_Dmean, double* d_twiddle,
+                      hipStream_t s) {
+  const int64_t n = 2 * Nt;
+  double2* tw = reinterpret_cast<double2*>(d_twiddle);
+  hipLaunchKernelGGL(k_twiddle, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, Nt, tw);
+  const double tau = tau_tilde / halfwidth;
+  const double pref = tau / (2.0 * M_PI);
+  hipLaunchKernelGGL(k_dos, dim3((unsigned)ceil_div(n, 128), R), dim3(128), 0, s,
+                     reinterpret_cast<const double2*>(d_corr), Nt, R, pref, window, tw, d_D);
+  const double dE = M_PI / (static_cast<double>(Nt) * tau);
+  hipLaunchKernelGGL(k_dos_mean, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, R, d_D,
+                     d_Dmean, d_E, dE, Nt);
+  return hipGetLastError();
+}
+
+}  // namespace csp

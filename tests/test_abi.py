@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/csp.h declares, and the binding's structures match the header."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "csp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(csp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("csp_context_create", "csp_lattice_create", "csp_states_random_phase",
+              "csp_propagate", "csp_propagate_batch", "csp_dos", "csp_last_error",
+              "csp_chebyshev_coefficients", "csp_chebyshev_step", "csp_select_block"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2510_17432_amd as csp
+    lib = ctypes.CDLL(csp.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert csp.abi_version() == 1
+
+
+def test_struct_layouts():
+    import paper_2510_17432_amd as csp
+    # sizes implied by include/csp.h with natural alignment
+    assert ctypes.sizeof(csp.LatticeDesc) == 16 + 16 + 16 + 8 + 24
+    assert ctypes.sizeof(csp.LatticeInfo) == 24 + 24 + 8
+    assert ctypes.sizeof(csp.Params) == 8 + 16 + 16 + 8 + 8 + 8
+    assert ctypes.sizeof(csp.Report) == 16 + 40 + 48 + 8 + 64
+
+
+def test_errors_without_gpu_are_reported_not_thrown():
+    import paper_2510_17432_amd as csp
+    h = ctypes.c_void_p()
+    rc = csp._lib.csp_context_create(0, None, ctypes.byref(h))
+    assert rc != 0 or h.value  # with no GPU: an error code, never a crash
+    if rc != 0:
+        assert len(csp._lib.csp_last_error()) > 0
+    else:
+        csp._lib.csp_context_destroy(h)
+
+
+def test_null_arguments_rejected():
+    import paper_2510_17432_amd as csp
+    assert csp._lib.csp_lattice_get_info(None, None) == csp.CSP_EINVAL
+    assert csp._lib.csp_propagate(None, None, None, 1, None, None, None, None) == csp.CSP_EINVAL
+    assert b"NULL" in csp._lib.csp_last_error()
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2510_17432_amd", "__init__.py")
+    pkg = tmp_path / "fakepkg"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text(open(src).read())
+    spec = importlib.util.spec_from_file_location("fakepkg", str(pkg / "__init__.py"))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)

@@ -1,0 +1,281 @@
+"""GPU parity: every HIP entry point against the FP64 CPU oracle.
+
+Bit-exact: on-site energies, neighbour tables, localized sites, the
+spectral half-width.  FP64 paths: 1e-10 on correlations (1e-13 for single
+steps and coefficients).  FP32 concurrent path: correlations within 2e-5
+absolute and DOS within 1e-4 relative (max |D32 - D64| / max |D64|).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def csp():
+    import paper_2510_17432_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(csp):
+    print("[gpu] creating context", flush=True)
+    c = csp.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+LATS = [
+    dict(kind="square", Lx=37, Ly=23, t=1.0, W=1.3, disorder_seed=5),
+    dict(kind="square", Lx=17, Ly=9, t=-0.7, W=0.0, periodic_x=False, periodic_y=True),
+    dict(kind="honeycomb", Lx=16, Ly=9, t=-2.7, W=1.0, disorder_seed=2),
+    dict(kind="honeycomb", Lx=5, Ly=4, t=-2.7, W=0.5, disorder_seed=3, periodic_x=False,
+         periodic_y=False),
+    dict(kind="chain", Lx=301, t=1.0, W=2.0, disorder_seed=9),
+    dict(kind="chain", Lx=50, t=0.5, W=0.0, periodic_x=False),
+]
+
+
+def pair(csp, ctx, spec):
+    g = csp.Lattice(ctx, **spec)
+    spec2 = dict(spec)
+    kind = spec2.pop("kind")
+    Lx = spec2.pop("Lx")
+    Ly = spec2.pop("Ly", 1)
+    return g, o.Lattice(kind, Lx, Ly, **spec2)
+
+
+@pytest.mark.parametrize("spec", LATS)
+def test_lattice_onsite_and_bound_bit_exact(csp, ctx, spec):
+    print("[gpu] lattice", spec, flush=True)
+    g, c = pair(csp, ctx, spec)
+    assert g.N == c.N
+    assert np.array_equal(host(g.onsite()), c.eps)
+    assert g.halfwidth == c.halfwidth()
+
+
+@pytest.mark.parametrize("spec", LATS)
+def test_neighbour_table_matches_bonds(csp, ctx, spec):
+    g, c = pair(csp, ctx, spec)
+    nb = host(g.neighbors())
+    for s in range(c.N):
+        cols = c.col[c.rowptr[s] + 1:c.rowptr[s + 1]]          # off-diagonal entries
+        mine = nb[s][nb[s] >= 0]
+        assert sorted(mine.tolist()) == sorted(cols.tolist()), s
+
+
+def test_random_phase_states(csp, ctx):
+    N, R, ld, col0, seed = 1000, 3, 5, 1, 77
+    ref = o.random_phase_states_fast(N, R, seed)
+    p64 = torch.zeros((N, ld), dtype=torch.complex128, device="cuda:0")
+    csp.csp_states_random_phase(ctx, p64, R, seed, col0=col0)
+    got = host(p64)
+    assert np.max(np.abs(got[:, col0:col0 + R] - ref)) < 1e-15
+    assert np.all(got[:, :col0] == 0) and np.all(got[:, col0 + R:] == 0)
+    p32 = torch.zeros((N, ld), dtype=torch.complex64, device="cuda:0")
+    csp.csp_states_random_phase(ctx, p32, R, seed, col0=col0)
+    assert np.max(np.abs(host(p32)[:, col0:col0 + R] - ref)) < 1e-7
+
+
+def test_ldos_sites_and_site_states(csp, ctx):
+    sites = host(csp.csp_ldos_sites(ctx, 5000, 64, 3))
+    assert np.array_equal(sites, o.ldos_sites(5000, 64, 3))
+    psi = torch.full((5000, 66), 7.0, dtype=torch.complex64, device="cuda:0")
+    csp.csp_states_sites(ctx, psi, dev(sites), col0=2)
+    got = host(psi)
+    assert np.array_equal(got[:, 2:], o.site_states(5000, sites).astype(np.complex64))
+    assert np.all(got[:, :2] == 7.0)
+
+
+@pytest.mark.parametrize("x", [math.pi, 10 * math.pi, 32 * math.pi, 64 * math.pi])
+def test_chebyshev_coefficients(csp, ctx, x):
+    n_ref = o.truncation(x)
+    c, n = csp.csp_chebyshev_coefficients(ctx, x, n_ref + 5)
+    assert n == n_ref
+    assert np.max(np.abs(host(c) - o.cheb_coeffs(x, n_ref + 5))) < 1e-13
+
+
+STEP_LATS = LATS + [
+    dict(kind="square", Lx=40, Ly=100, t=1.0, W=0.8, disorder_seed=4),   # several row segments
+    dict(kind="square", Lx=600, Ly=5, t=1.0, W=0.0),                     # several strips
+    dict(kind="honeycomb", Lx=300, Ly=40, t=-2.7, W=1.0, disorder_seed=6),
+    dict(kind="square", Lx=1, Ly=7, t=1.0, W=0.0),                       # self-bonds
+    dict(kind="honeycomb", Lx=2, Ly=2, t=1.0, W=0.2, disorder_seed=1),   # repeated bonds
+]
+
+
+@pytest.mark.parametrize("spec", STEP_LATS)
+@pytest.mark.parametrize("R", [1, 3, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_chebyshev_step(csp, ctx, spec, R, dtype):
+    g, c = pair(csp, ctx, spec)
+    Hn = g.halfwidth
+    rng = np.random.default_rng(R)
+    x = rng.normal(size=(c.N, R)) + 1j * rng.normal(size=(c.N, R))
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    xd = dev(x).to(tdt)
+    y1 = torch.zeros_like(xd)
+    csp.csp_chebyshev_step(ctx, g, xd, y1, first=True)
+    y2 = xd.clone()
+    csp.csp_chebyshev_step(ctx, g, y1, y2, first=False)
+    ref = np.stack([o.chebyshev_vectors(c, x[:, r], 2, Hn) for r in range(R)], axis=-1)
+    tol = 1e-13 if dtype == "c128" else 2e-6
+    scale = np.max(np.abs(x))
+    assert np.max(np.abs(host(y1) - ref[1])) < tol * scale
+    assert np.max(np.abs(host(y2) - ref[2])) < tol * 3 * scale
+
+
+def test_chebyshev_step_spectral_centre(csp, ctx):
+    spec = dict(kind="honeycomb", Lx=7, Ly=6, t=-1.0, W=1.0, disorder_seed=8)
+    g = csp.Lattice(ctx, halfwidth_override=4.5, center=0.3, **spec)
+    c = o.Lattice("honeycomb", 7, 6, t=-1.0, W=1.0, disorder_seed=8)
+    x = np.random.default_rng(0).normal(size=(c.N, 2)).astype(np.complex128)
+    xd = dev(x)
+    y = torch.zeros_like(xd)
+    csp.csp_chebyshev_step(ctx, g, xd, y, first=True)
+    ref = np.stack([o.chebyshev_vectors(c, x[:, r], 1, 4.5, H0=0.3)[1] for r in range(2)], -1)
+    assert np.max(np.abs(host(y) - ref)) < 1e-13
+
+
+def run_gpu(csp, ctx, g, psi, Nt, mode, b=0, K=0, final=False):
+    tdt = torch.complex128 if mode != "fp32_conc" else torch.complex64
+    p = dev(psi).to(tdt)
+    params = csp.make_params(Nt, mode=mode, block_b=b, chunk_K=K)
+    fin = torch.zeros_like(p) if final else None
+    corr, rep = csp.csp_propagate(ctx, g, p, params, final=fin)
+    return host(corr), rep, (host(fin) if final else None)
+
+
+def test_fp64_sequential_config1(csp, ctx):
+    # 64 x 64 square, t = 1, |H| = 4.1, one random state (seed 1), 1024 steps
+    print("[gpu] config-1 fp64 sequential", flush=True)
+    g = csp.Lattice(ctx, "square", 64, 64, t=1.0)
+    assert g.halfwidth == pytest.approx(4.1, abs=1e-15)
+    c = o.Lattice("square", 64, 64, t=1.0)
+    psi = o.random_phase_states_fast(c.N, 1, 1)
+    ref, _ = o.propagate(c, psi, 1024, b=0, Hn=4.1)
+    got, rep, _ = run_gpu(csp, ctx, g, psi, 1024, "fp64_seq")
+    assert np.max(np.abs(got - ref)) < 1e-10
+    assert rep.amxsy == 1024 * 20 and rep.dot == 1024
+
+
+@pytest.mark.parametrize("b", [1, 4, 13, 16])
+def test_fp64_concurrent(csp, ctx, b):
+    spec = dict(kind="honeycomb", Lx=20, Ly=12, t=-2.7, W=1.0, disorder_seed=4)
+    g, c = pair(csp, ctx, spec)
+    psi = o.random_phase_states_fast(c.N, 3, 5)
+    Nt = 100
+    ref, cnt = o.propagate(c, psi, Nt, b=b)
+    got, rep, _ = run_gpu(csp, ctx, g, psi, Nt, "fp64_conc", b=b)
+    assert np.max(np.abs(got - ref)) < 1e-10
+    assert rep.amxsy * 3 == cnt["amxsy"] and rep.axpy * 3 == cnt["axpy"]
+
+
+def rel_dos_err(c32, c64, Hn):
+    _, D32, _ = o.dos(c32, Hn)
+    _, D64, _ = o.dos(c64, Hn)
+    return np.max(np.abs(D32.mean(1) - D64.mean(1))) / np.max(np.abs(D64.mean(1)))
+
+
+@pytest.mark.parametrize("b,K", [(1, 0), (7, 0), (32, 0), (64, 0), (32, 16), (40, 32)])
+def test_fp32_concurrent(csp, ctx, b, K):
+    print("[gpu] fp32 concurrent b=%d K=%d" % (b, K), flush=True)
+    spec = dict(kind="honeycomb", Lx=24, Ly=24, t=-2.7, W=1.0, disorder_seed=4)
+    g, c = pair(csp, ctx, spec)
+    psi = o.random_phase_states_fast(c.N, 5, 5)       # groups of 4 + 1 columns
+    Nt = 200
+    ref, _ = o.propagate(c, psi, Nt, b=0)
+    got, rep, _ = run_gpu(csp, ctx, g, psi, Nt, "fp32_conc", b=b, K=K)
+    assert rep.block_b == b
+    assert np.max(np.abs(got - ref)) < 2e-5
+    assert rel_dos_err(got, ref, g.halfwidth) < 1e-4
+
+
+def test_fp32_concurrent_ldos_columns(csp, ctx):
+    # random columns and localized columns in one block, as the LDOS workload
+    g, c = pair(csp, ctx, dict(kind="honeycomb", Lx=32, Ly=32, t=-2.7, W=0.0))
+    sites = o.ldos_sites(c.N, 6, 3)
+    psi = np.concatenate([o.random_phase_states_fast(c.N, 4, 2), o.site_states(c.N, sites)], 1)
+    Nt = 96
+    ref, _ = o.propagate(c, psi, Nt, b=0)
+    got, rep, _ = run_gpu(csp, ctx, g, psi, Nt, "fp32_conc", b=32)
+    assert rep.n_groups == 3                     # 8 + 2 columns
+    assert np.max(np.abs(got - ref)) < 2e-5
+    assert rel_dos_err(got[:, 4:], ref[:, 4:], g.halfwidth) < 1e-4
+
+
+def test_final_state_and_norm(csp, ctx):
+    g, c = pair(csp, ctx, dict(kind="square", Lx=30, Ly=20, t=1.0, W=1.0, disorder_seed=1))
+    psi = o.random_phase_states_fast(c.N, 2, 4)
+    ref, _, fin_ref = o.propagate(c, psi, 50, b=0, return_final=True)
+    got, _, fin = run_gpu(csp, ctx, g, psi, 50, "fp64_seq", final=True)
+    assert np.max(np.abs(fin - fin_ref)) < 1e-10
+    _, _, fin32 = run_gpu(csp, ctx, g, psi, 50, "fp32_conc", b=16, final=True)
+    assert np.max(np.abs(np.linalg.norm(fin32, axis=0) - 1.0)) < 1e-5
+
+
+def test_dos_kernel(csp, ctx):
+    g, c = pair(csp, ctx, dict(kind="square", Lx=12, Ly=11, t=1.0, W=1.0, disorder_seed=2))
+    psi = o.random_phase_states_fast(c.N, 3, 1)
+    ref, _ = o.propagate(c, psi, 128, b=8)
+    for window, wcode in (("hann", csp.CSP_WINDOW_HANN), ("none", csp.CSP_WINDOW_NONE)):
+        E, D, Dm = csp.csp_dos(ctx, dev(ref), g.halfwidth, window=wcode)
+        Er, Dr, _ = o.dos(ref, g.halfwidth, window=window)
+        assert np.max(np.abs(host(E) - Er)) < 1e-12
+        assert np.max(np.abs(host(D) - Dr)) < 1e-12
+        assert np.max(np.abs(host(Dm) - Dr.mean(1))) < 1e-12
+
+
+def test_batch_matches_oracle(csp, ctx):
+    specs = [dict(kind="square", Lx=20, Ly=18, t=1.0, W=1.5, disorder_seed=1),
+             dict(kind="honeycomb", Lx=9, Ly=14, t=-2.7, W=0.5, disorder_seed=2),
+             dict(kind="chain", Lx=400, t=1.0, W=0.0)]
+    Rs = [1, 3, 2]
+    Nt = 64
+    gl, psis, refs = [], [], []
+    for spec, R in zip(specs, Rs):
+        g, c = pair(csp, ctx, spec)
+        psi = o.random_phase_states_fast(c.N, R, 11)
+        gl.append(g)
+        psis.append(dev(psi).to(torch.complex64))
+        refs.append(o.propagate(c, psi, Nt, b=0)[0])
+    params = csp.make_params(Nt, mode="fp32_conc", block_b=16)
+    corrs, rep = csp.csp_propagate_batch(ctx, gl, psis, params)
+    for corr, ref in zip(corrs, refs):
+        assert np.max(np.abs(host(corr) - ref)) < 2e-5
+
+
+def test_error_paths(csp, ctx):
+    g = csp.Lattice(ctx, "square", 8, 8)
+    psi = torch.zeros((64, 1), dtype=torch.complex64, device="cuda:0")
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_propagate(ctx, g, psi, csp.make_params(10, mode="fp32_conc", block_b=65))
+    assert e.value.status == csp.CSP_EUNSUPPORTED
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_propagate(ctx, g, psi, csp.make_params(10, mode=7))
+    assert e.value.status == csp.CSP_EINVAL
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_propagate(ctx, g, psi, csp.make_params(10, mode="fp32_conc", block_b=8,
+                                                       mem_cap_bytes=1 << 20))
+    assert e.value.status == csp.CSP_ENOMEM
+    with pytest.raises(csp.CspError):
+        csp.Lattice(ctx, "square", 0, 8)
+    # Nt = 0: only the t = 0 correlation
+    psi[0, 0] = 1.0
+    corr, _ = csp.csp_propagate(ctx, g, psi, csp.make_params(0, mode="fp32_conc", block_b=4))
+    assert host(corr).shape == (1, 1) and host(corr)[0, 0] == 1.0
