@@ -1,0 +1,239 @@
+"""Throughput of the concurrent stochastic propagation hot path on one GPU.
+
+One step = one pass of the whole path over one batch of synthetic input on
+graphene (honeycomb 1024 x 1024 cells, 2 097 152 orbitals, periodic,
+t = -2.7 eV, no disorder): random-phase states for 4 columns and localized
+states on 64 sampled sites (generated on the GPU), the Chebyshev
+coefficients (FP64, on the GPU), the complex64 Chebyshev recursion, the
+split-bf16 MFMA block contraction fused with <psi0|psi(t_j)>, the FP32
+carried state, 2048 time points, and the DOS / LDOS transform.
+
+The reported value is orbital-state Chebyshev steps per second:
+N * R * (recursion steps executed) / wall time of a step.  Beside it:
+  roofline      the recursion kernel's algorithmic HBM bytes per launch over
+                its average launch time (HIP events on the library stream);
+  time_to_accuracy
+                the DOS of the 4 random columns by the complex64 concurrent
+                form and by the plain complex128 sequential form on the same
+                GPU, with the relative DOS difference between them;
+  cpu_baseline  the FP64 CPU oracle (sequential form) on a bounded sample of
+                the same lattice, timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Graphene, 1024 x 1024 cells, 4 random-phase states + 64 LDOS sites, 2048
+# time points (Sec. III DOS / LDOS on a lattice of the paper's size range).
+WORKLOAD = dict(kind="honeycomb", Lx=1024, Ly=1024, t=-2.7, W=0.0, R_rand=4, n_sites=64,
+                Nt=2048, seed_states=2, seed_sites=3, block_b=32)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--block-b", type=int, default=WORKLOAD["block_b"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-seq", action="store_true",
+                    help="skip the complex128 sequential comparison run")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target length of the CPU oracle sample")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel_prefix):
+    """HBM bytes per launch of the recursion kernel from the committed
+    rocprofv3 counter summary, if present (null otherwise)."""
+    path = os.path.join(ROOT, "profiles", "spmm_honeycomb1024_r68_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        if d.get("kernel_prefix") != kernel_prefix:
+            return None
+        return float(d["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(W, seconds):
+    """FP64 sequential oracle on the same lattice, one random column, for as
+    many time steps as fit in about `seconds`."""
+    import numpy as np
+    import oracle as o
+    t0 = time.perf_counter()
+    lat = o.Lattice(W["kind"], W["Lx"], W["Ly"], t=W["t"], W=W["W"])
+    psi = o.random_phase_states_fast(lat.N, 1, W["seed_states"])
+    t_setup = time.perf_counter() - t0
+    # one probe step to size the sample
+    t0 = time.perf_counter()
+    _, cnt = o.propagate(lat, psi, 1, b=0)
+    t1 = time.perf_counter() - t0
+    nt = max(1, int(seconds / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    _, cnt = o.propagate(lat, psi, nt, b=0)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    rate = lat.N * 1 * cnt["amxsy"] / el
+    return {"value": rate, "unit": "orbital*steps/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 sequential form, graphene 1024x1024 cells (N=%d), 1 random column, "
+                      "%d time steps (%d Chebyshev steps) in %.1f s; lattice set-up %.1f s "
+                      "excluded" % (lat.N, nt, cnt["amxsy"], el, t_setup)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2510_17432_amd as csp
+
+    W = dict(WORKLOAD)
+    W["block_b"] = a.block_b
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = csp.Context(0)
+    stream = ctx.stream
+    lat = csp.Lattice(ctx, W["kind"], W["Lx"], W["Ly"], t=W["t"], W=W["W"])
+    N = lat.N
+    R = W["R_rand"] + W["n_sites"]
+    Nt = W["Nt"]
+    psi = torch.empty((N, R), dtype=torch.complex64, device=dev)
+    corr = torch.empty((Nt + 1, R), dtype=torch.complex128, device=dev)
+    params = csp.make_params(Nt, mode="fp32_conc", block_b=W["block_b"], profile=True)
+    log("lattice N=%d |H|=%.6f R=%d Nt=%d b=%d" % (N, lat.halfwidth, R, Nt, W["block_b"]))
+
+    def step():
+        csp.csp_states_random_phase(ctx, psi, W["R_rand"], W["seed_states"], col0=0)
+        sites = csp.csp_ldos_sites(ctx, N, W["n_sites"], W["seed_sites"])
+        csp.csp_states_sites(ctx, psi, sites, col0=W["R_rand"])
+        _, rep = csp.csp_propagate(ctx, lat, psi, params, corr=corr)
+        E, D, Dm = csp.csp_dos(ctx, corr[:, :W["R_rand"]].contiguous(), lat.halfwidth)
+        E2, D2, _ = csp.csp_dos(ctx, corr[:, W["R_rand"]:].contiguous(), lat.halfwidth)
+        return rep, Dm
+
+    for i in range(a.warmup):
+        rep, _ = step()
+        log("warmup %d done: %.1f ms, spmm %.1f ms over %d launches" %
+            (i, rep.ms_total, rep.ms_spmm, rep.spmm_launches))
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        rep, Dm = step()
+        reps.append(rep)
+        log("step %d done: %.1f ms" % (i, rep.ms_total))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = 1000.0 * el / a.steps
+    steps_exec = reps[-1].amxsy
+    value = N * R * steps_exec / (el / a.steps)
+
+    ms_spmm = sum(r.ms_spmm for r in reps)
+    n_spmm = sum(r.spmm_launches for r in reps)
+    bytes_spmm = sum(r.spmm_bytes for r in reps)
+    avg_launch_s = ms_spmm / 1000.0 / n_spmm
+    bytes_per_launch = bytes_spmm / n_spmm
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    ms_con = sum(r.ms_contract for r in reps)
+    n_con = sum(r.contract_launches for r in reps)
+    con_flops = sum(r.contract_flops for r in reps)
+    con_bytes = sum(r.contract_bytes for r in reps)
+    traffic = traffic_from_profiles("k_spmm")
+    out = {
+        "metric": "orbital·Chebyshev-steps/s + DOS time-to-accuracy, FP32 concurrent vs FP64 seq",
+        "value": value,
+        "unit": "orbital*steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "graphene honeycomb 1024x1024 cells (N=%d), t=-2.7 eV, periodic, "
+                               "4 random-phase + 64 LDOS columns, Nt=2048, complex64 concurrent "
+                               "b=%d, split-bf16 MFMA contraction" % (N, rep.block_b),
+                   "orbitals": N, "columns": R, "Nt": Nt, "block_b": rep.block_b,
+                   "chunk_K": rep.chunk_K, "recursion_steps": steps_exec,
+                   "sequential_equivalent_steps": Nt * 20},
+        "roofline": {"bound": "hbm", "kernel": "k_spmm (Chebyshev recursion step)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "contraction": {"kernel": "k_contract_f32 (split-bf16 MFMA)",
+                        "avg_launch_us": 1000.0 * ms_con / max(n_con, 1),
+                        "achieved_GBs": con_bytes / max(ms_con, 1e-9) / 1e6,
+                        "mfma_TFLOPs": con_flops / max(ms_con, 1e-9) / 1e9,
+                        "share_of_step": ms_con / max(ms_con + ms_spmm, 1e-9)},
+        "effective_rate": N * R * Nt * 20 / (el / a.steps),
+    }
+
+    # time-to-accuracy: DOS of the random columns, complex64 concurrent vs
+    # complex128 sequential, both on this GPU
+    if not a.no_seq:
+        p4 = psi[:, :W["R_rand"]].contiguous()
+        c32 = torch.empty((Nt + 1, W["R_rand"]), dtype=torch.complex128, device=dev)
+        pr32 = csp.make_params(Nt, mode="fp32_conc", block_b=W["block_b"])
+        csp.csp_propagate(ctx, lat, p4, pr32, corr=c32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        csp.csp_propagate(ctx, lat, p4, pr32, corr=c32)
+        _, _, D32 = csp.csp_dos(ctx, c32, lat.halfwidth)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        log("fp32 concurrent DOS (4 columns): %.3f s" % t32)
+        p64 = p4.to(torch.complex128)
+        c64 = torch.empty((Nt + 1, W["R_rand"]), dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        csp.csp_propagate(ctx, lat, p64, csp.make_params(Nt, mode="fp64_seq"), corr=c64)
+        _, _, D64 = csp.csp_dos(ctx, c64, lat.halfwidth)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        log("fp64 sequential DOS (4 columns): %.3f s" % t64)
+        d32, d64 = D32.cpu().numpy(), D64.cpu().numpy()
+        rel = float(np.max(np.abs(d32 - d64)) / np.max(np.abs(d64)))
+        eps_c = float((c32 - c64).abs().max().item())
+        out["time_to_accuracy"] = {"fp32_concurrent_s": t32, "fp64_sequential_s": t64,
+                                   "speedup": t64 / t32, "dos_rel_err": rel,
+                                   "corr_eps_inf": eps_c, "target_rel_err": 1e-4,
+                                   "columns": W["R_rand"]}
+    del psi, corr
+    lat.close()
+    ctx.close()
+    torch.cuda.synchronize()
+
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(W, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -8,9 +8,11 @@ this package fails loudly if the library has not been built.
 The function names follow ``include/csp.h``; see that header for the meaning
 of every argument.
 """
+import atexit
 import ctypes
 import math
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsp.so")
@@ -142,8 +144,25 @@ def _dtype_code(t):
 
 
 # ------------------------------------------------------------------ objects
+_LIVE_CONTEXTS = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # Lattices before their context, everything before the HIP runtime and
+    # torch's allocator are torn down at interpreter exit.
+    for c in list(_LIVE_CONTEXTS):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
-    """csp_context on a device, ordered on a torch stream (default: current)."""
+    """csp_context on a device, ordered on a torch stream (default: current).
+
+    A lattice must not outlive the context it was built on: closing the
+    context closes its lattices first."""
 
     def __init__(self, device=0, stream=None):
         import torch
@@ -151,13 +170,17 @@ class Context:
             stream = torch.cuda.current_stream(device)
         self.device = device
         self.stream = stream
+        self._lattices = weakref.WeakSet()
         h = ctypes.c_void_p()
         _check(_lib.csp_context_create(device, ctypes.c_void_p(stream.cuda_stream),
                                        ctypes.byref(h)))
         self.handle = h
+        _LIVE_CONTEXTS.add(self)
 
     def close(self):
         if self.handle:
+            for lat in list(self._lattices):
+                lat.close()
             _check(_lib.csp_context_destroy(self.handle))
             self.handle = None
 
@@ -195,6 +218,7 @@ class Lattice:
         h = ctypes.c_void_p()
         _check(_lib.csp_lattice_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
+        ctx._lattices.add(self)
         info = LatticeInfo()
         _check(_lib.csp_lattice_get_info(h, ctypes.byref(info)))
         self.info = info
@@ -218,6 +242,8 @@ class Lattice:
 
     def close(self):
         if getattr(self, "handle", None):
+            if not self.ctx.handle:
+                raise CspError(CSP_EINVAL, "lattice outlived its context")
             _check(_lib.csp_lattice_destroy(self.handle))
             self.handle = None
 

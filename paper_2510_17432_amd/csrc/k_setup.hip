@@ -33,7 +33,13 @@ __global__ void k_gershgorin(Geom g, const double* __restrict__ eps, double t, d
     int deg = 0;
     for (int k = 0; k < deg_max; ++k) deg += neighbour(g, s, k) >= 0 ? 1 : 0;
     const double e = eps ? eps[s] : 0.0;
-    const double r = fabs(e - H0) + deg * fabs(t);
+    double r;
+    {
+      // No fused multiply-add here: the bound must be reproducible bit for
+      // bit by any IEEE implementation of the same expression.
+#pragma clang fp contract(off)
+      r = fabs(e - H0) + (double)deg * fabs(t);
+    }
     m = r > m ? r : m;
   }
   red[threadIdx.x] = m;

@@ -110,7 +110,10 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const SpmmInst* __restric
   auto stash = [&](int slot) {
     C* d = lds + slot * ldsw;
 #pragma unroll
-    for (int v = 0; v < V; ++v) d[R + v * kSpmmThreads + tid] = cen[v];
+    for (int v = 0; v < V; ++v)
+      if (valid[v]) d[R + v * kSpmmThreads + tid] = cen[v];
+    // The right halo sits just past the valid part of a short strip, where
+    // the slots of invalid threads would be: those threads store nothing.
     if (tid < 2 * R) d[hslot] = hal;
   };
 

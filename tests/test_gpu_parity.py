@@ -214,7 +214,7 @@ def test_fp32_concurrent_ldos_columns(csp, ctx):
     Nt = 96
     ref, _ = o.propagate(c, psi, Nt, b=0)
     got, rep, _ = run_gpu(csp, ctx, g, psi, Nt, "fp32_conc", b=32)
-    assert rep.n_groups == 3                     # 8 + 2 columns
+    assert rep.n_groups == 2                     # 8 + 2 columns
     assert np.max(np.abs(got - ref)) < 2e-5
     assert rel_dos_err(got[:, 4:], ref[:, 4:], g.halfwidth) < 1e-4
 
