@@ -38,6 +38,7 @@ WORKLOAD = dict(kind="honeycomb", Lx=1024, Ly=1024, t=-2.7, W=0.0, R_rand=4, n_s
                 Nt=2048, seed_states=2, seed_sites=3, block_b=32)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+COPY_PROBE_BYTES = 2 << 30
 
 
 def parse():
@@ -51,6 +52,9 @@ def parse():
                     help="skip the complex128 sequential comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 2 GiB device to device (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -58,18 +62,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profiles(kernel_prefix):
-    """HBM bytes per launch of the recursion kernel from the committed
-    rocprofv3 counter summary, if present (null otherwise)."""
-    path = os.path.join(ROOT, "profiles", "spmm_honeycomb1024_r68_counters.json")
+def traffic_from_profiles():
+    """HBM bytes per launch of the recursion kernel: the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, each scaled by what the same counter
+    read for a device copy of known size.  None when there is no summary or
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_spmm_graphene1024_r68_counters.json")
+    src = os.path.join(ROOT, "paper_2510_17432_amd", "csrc", "k_spmm.hip")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        if d.get("kernel_prefix") != kernel_prefix:
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        if d.get("source_sha256") != h:
             return None
-        return float(d["bytes_per_launch"])
+        return float(d["hbm_bytes_per_launch"])
     except Exception:
         return None
 
@@ -83,11 +93,12 @@ def cpu_baseline(W, seconds):
     lat = o.Lattice(W["kind"], W["Lx"], W["Ly"], t=W["t"], W=W["W"])
     psi = o.random_phase_states_fast(lat.N, 1, W["seed_states"])
     t_setup = time.perf_counter() - t0
-    # one probe step to size the sample
+    # size the sample from a short probe after one warm-up step
+    o.propagate(lat, psi, 1, b=0)
     t0 = time.perf_counter()
-    _, cnt = o.propagate(lat, psi, 1, b=0)
-    t1 = time.perf_counter() - t0
-    nt = max(1, int(seconds / max(t1, 1e-3)))
+    o.propagate(lat, psi, 8, b=0)
+    t8 = (time.perf_counter() - t0) / 8
+    nt = max(1, int(seconds / max(t8, 1e-4)))
     t0 = time.perf_counter()
     _, cnt = o.propagate(lat, psi, nt, b=0)
     el = time.perf_counter() - t0
@@ -113,6 +124,14 @@ def main():
     W["block_b"] = a.block_b
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d written" % (COPY_PROBE_BYTES, COPY_PROBE_BYTES))
+        del src, dst
     ctx = csp.Context(0)
     stream = ctx.stream
     lat = csp.Lattice(ctx, W["kind"], W["Lx"], W["Ly"], t=W["t"], W=W["W"])
@@ -160,7 +179,7 @@ def main():
     n_con = sum(r.contract_launches for r in reps)
     con_flops = sum(r.contract_flops for r in reps)
     con_bytes = sum(r.contract_bytes for r in reps)
-    traffic = traffic_from_profiles("k_spmm")
+    traffic = traffic_from_profiles()
     out = {
         "metric": "orbital·Chebyshev-steps/s + DOS time-to-accuracy, FP32 concurrent vs FP64 seq",
         "value": value,

@@ -360,3 +360,110 @@ def dos_direct(corr, Hn, window="hann"):
             Cj = corr[jj] if jj >= 0 else np.conj(corr[-jj])
             D[ik] += w[ij] * Cj * np.exp(1j * math.pi * k * jj / Nt)
     return E, (tau / (2 * math.pi)) * D
+
+
+# ---------------------------------------------------------------- closed forms
+def _bloch_modes(kind, Lx, Ly, t, psi):
+    """Band energies w_q and weights of a clean periodic lattice such that
+    <psi_r|exp(-iHt)|psi_r> = sum_q [P_qr cos(w_q t) - i Q_qr sin(w_q t)].
+
+    square: E(k) = 2t (cos kx + cos ky), P = |psi_k|^2, Q = P E/|E| (so that
+    the sum is sum_k |psi_k|^2 exp(-i E_k t)); chain likewise with
+    E = 2t cos k.  honeycomb (orbital 2(y Lx + x) + sigma, bonds
+    A(x,y)-B(x,y), A(x,y)-B(x-1,y), A(x,y)-B(x,y-1)): the 2x2 Bloch matrix
+    [[0, g], [g*, 0]] with g(k) = t (1 + e^{-i k1} + e^{-i k2}) has the
+    propagator cos(|g|t) I - i sin(|g|t)/|g| H(k), so w = |g|,
+    P = |a_k|^2 + |b_k|^2 and Q = 2 Re(conj(a_k) g b_k)/|g| (0 where g = 0,
+    where that term vanishes for every t)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    if psi.ndim == 1:
+        psi = psi[:, None]
+    R = psi.shape[1]
+    if kind == "chain":
+        E = 2 * t * np.cos(2 * np.pi * np.arange(Lx) / Lx)
+        P = np.abs(np.fft.fft(psi, axis=0)) ** 2 / Lx
+        w = np.abs(E)
+        Q = P * np.sign(E)[:, None]
+        return w, P, Q
+    if kind == "square":
+        kx = 2 * np.pi * np.arange(Lx) / Lx
+        ky = 2 * np.pi * np.arange(Ly) / Ly
+        E = (2 * t * (np.cos(kx)[None, :] + np.cos(ky)[:, None])).ravel()
+        P = np.empty((Lx * Ly, R))
+        for r in range(R):
+            P[:, r] = (np.abs(np.fft.fft2(psi[:, r].reshape(Ly, Lx))) ** 2).ravel() / (Lx * Ly)
+        return np.abs(E), P, P * np.sign(E)[:, None]
+    if kind == "honeycomb":
+        k1 = 2 * np.pi * np.arange(Lx) / Lx
+        k2 = 2 * np.pi * np.arange(Ly) / Ly
+        g = (t * (1 + np.exp(-1j * k1)[None, :] + np.exp(-1j * k2)[:, None])).ravel()
+        mag = np.abs(g)
+        nz = mag > 0
+        inv = np.where(nz, 1.0 / np.where(nz, mag, 1.0), 0.0)
+        P = np.empty((Lx * Ly, R))
+        Q = np.empty((Lx * Ly, R))
+        for r in range(R):
+            a = psi[:, r].reshape(Ly, Lx, 2)
+            ha = (np.fft.fft2(a[:, :, 0]) / math.sqrt(Lx * Ly)).ravel()
+            hb = (np.fft.fft2(a[:, :, 1]) / math.sqrt(Lx * Ly)).ravel()
+            P[:, r] = np.abs(ha) ** 2 + np.abs(hb) ** 2
+            # conj(a) g b + conj(b) conj(g) a = 2 Re(conj(a) g b)
+            Q[:, r] = 2.0 * np.real(np.conj(ha) * g * hb) * inv
+        return mag, P, Q
+    raise ValueError(kind)
+
+
+def bloch_corr(kind, Lx, Ly, t, psi, times):
+    """<psi_r|exp(-iHt)|psi_r> of a clean periodic lattice (chain, square,
+    honeycomb) from its band structure, at arbitrary times: H is diagonal in
+    crystal momentum (see _bloch_modes).  psi is [N][R]; returns
+    [len(times)][R] complex128.  Cost O(N len(times) + N R log N)."""
+    w, P, Q = _bloch_modes(kind, Lx, Ly, t, psi)
+    times = np.asarray(times, dtype=np.float64)
+    out = np.zeros((len(times), P.shape[1]), dtype=np.complex128)
+    for i0 in range(0, len(times), 16):
+        ph = np.outer(times[i0:i0 + 16], w)
+        out[i0:i0 + ph.shape[0]] = np.cos(ph) @ P - 1j * (np.sin(ph) @ Q)
+    return out
+
+
+def bloch_corr_uniform(kind, Lx, Ly, t, psi, tau, n, threads=None):
+    """bloch_corr at the n uniform times t_j = j tau, j = 0..n-1.  Blocks of
+    16 consecutive times share one table exp(-i w m tau), m < 16, so a block
+    costs one exp per mode plus a complex product:
+    exp(-i w (j0 + m) tau) = exp(-i w j0 tau) exp(-i w m tau).  With
+    C = sum_q [(P+Q)/2 e^{-iwt} + (P-Q)/2 e^{+iwt}] each block is one complex
+    matrix product.  Blocks are independent and run on a thread pool."""
+    import concurrent.futures as cf
+    w, P, Q = _bloch_modes(kind, Lx, Ly, t, psi)
+    R = P.shape[1]
+    B = 16
+    Wm = np.concatenate([(P + Q) / 2, (P - Q) / 2], axis=1).astype(np.complex128)
+    step_m = np.exp(-1j * np.outer(np.arange(B) * tau, w))     # [B][q]
+    out = np.zeros((n, R), dtype=np.complex128)
+
+    def block(j0):
+        m = min(B, n - j0)
+        z = step_m[:m] * np.exp(-1j * (j0 * tau) * w)[None, :]
+        y = z @ Wm                     # [m][2R]: sum W+ e^{-iwt}, sum W- e^{-iwt}
+        out[j0:j0 + m] = y[:, :R] + np.conj(y[:, R:])
+
+    nthr = threads or min(16, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(nthr) as ex:
+        list(ex.map(block, range(0, n, B)))
+    return out
+
+
+def bloch_return_amplitude(kind, Lx, Ly, t, tau, n):
+    """<r|exp(-iHt_j)|r>, t_j = j tau, j = 0..n-1, of a clean periodic
+    lattice.  It is the same for every orbital r (translation symmetry, and
+    on the honeycomb the A-B symmetry of the propagator's diagonal
+    cos(|g| t)), so the local density of states is site independent."""
+    N = orc_sites(kind, Lx, Ly)
+    unit = np.zeros((N, 1), dtype=np.complex128)
+    unit[0, 0] = 1.0
+    return bloch_corr_uniform(kind, Lx, Ly, t, unit, tau, n)[:, 0]
+
+
+def orc_sites(kind, Lx, Ly):
+    return int(lib().orc_lattice_sites(KINDS[kind], Lx, Ly))

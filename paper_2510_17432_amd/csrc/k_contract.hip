@@ -91,16 +91,25 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
       for (int v = 0; v < 16; ++v) { accR[jt][v] = 0.f; accI[jt][v] = 0.f; }
     float cr = 0.f, ci = 0.f;
 
+    // Orders of the next 16-order step are loaded while the current one is
+    // converted and multiplied (two register sets of 8 values).
+    float2 xn[8];
+    auto load_step = [&](int kb) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int rel = kb * 16 + h * 8 + v;
+        const int n = a.n_lo + rel;
+        xn[v] = (mv && rel < a.n_cnt) ? slots[(int64_t)(n % a.S) * I.slot_stride + m]
+                                      : make_float2(0.f, 0.f);
+      }
+    };
+    load_step(0);
     for (int kb = 0; kb < n_kb; ++kb) {
       const int r0 = kb * 16 + h * 8;
       float2 x[8];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const int rel = r0 + v;
-        const int n = a.n_lo + rel;
-        x[v] = (mv && rel < a.n_cnt) ? slots[(int64_t)(n % a.S) * I.slot_stride + m]
-                                     : make_float2(0.f, 0.f);
-      }
+      for (int v = 0; v < 8; ++v) x[v] = xn[v];
+      if (kb + 1 < n_kb) load_step(kb + 1);
       bf16x8 phi, plo, qhi, qlo;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {

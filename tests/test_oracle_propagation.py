@@ -70,25 +70,6 @@ def test_square_bloch_closed_form():
     assert np.max(np.abs(corr[:, 0] - ref)) < 1e-10
 
 
-def honeycomb_bloch_corr(psi, Lx, Ly, tt, times):
-    a = psi.reshape(Ly, Lx, 2)
-    ha = np.fft.fft2(a[:, :, 0]) / math.sqrt(Lx * Ly)
-    hb = np.fft.fft2(a[:, :, 1]) / math.sqrt(Lx * Ly)
-    k1 = 2 * np.pi * np.arange(Lx) / Lx
-    k2 = 2 * np.pi * np.arange(Ly) / Ly
-    g = tt * (1 + np.exp(-1j * k1)[None, :] + np.exp(-1j * k2)[:, None])
-    mag = np.abs(g)
-    out = np.zeros(len(times), dtype=np.complex128)
-    for i, tm in enumerate(times):
-        c = np.cos(mag * tm)
-        s_over = np.where(mag > 1e-300, np.sin(mag * tm) / np.where(mag > 0, mag, 1.0), tm)
-        # exp(-i H(k) t) = cos(|g|t) I - i sin(|g|t)/|g| H(k), H(k) = [[0, g], [g*, 0]]
-        ya = c * ha - 1j * s_over * g * hb
-        yb = c * hb - 1j * s_over * np.conj(g) * ha
-        out[i] = np.sum(np.conj(ha) * ya + np.conj(hb) * yb)
-    return out
-
-
 def test_honeycomb_bloch_closed_form():
     Lx, Ly = 24, 21          # 21 divisible by 3: Dirac points are on the grid
     lat = o.Lattice("honeycomb", Lx, Ly, t=-2.7)
@@ -96,8 +77,52 @@ def test_honeycomb_bloch_closed_form():
     Hn = lat.halfwidth()
     Nt = 150
     corr, _ = o.propagate(lat, psi, Nt, b=8, Hn=Hn)
-    ref = honeycomb_bloch_corr(psi, Lx, Ly, -2.7, np.arange(Nt + 1) * math.pi / Hn)
-    assert np.max(np.abs(corr[:, 0] - ref)) < 1e-10
+    ref = o.bloch_corr("honeycomb", Lx, Ly, -2.7, psi, np.arange(Nt + 1) * math.pi / Hn)
+    assert np.max(np.abs(corr[:, 0] - ref[:, 0])) < 1e-10
+
+
+@pytest.mark.parametrize("kind,Lx,Ly,t", [("square", 7, 5, 1.0), ("square", 6, 6, -0.8),
+                                          ("honeycomb", 5, 4, -2.7), ("honeycomb", 6, 3, 1.0),
+                                          ("chain", 13, 1, 0.7)])
+def test_bloch_closed_form_equals_exact_diagonalisation(kind, Lx, Ly, t):
+    # the k-space closed form against eigh of the real-space matrix, also
+    # with localized columns (the LDOS states)
+    lat = o.Lattice(kind, Lx, Ly, t=t)
+    psi = np.concatenate([o.random_phase_states_fast(lat.N, 2, 8),
+                          o.site_states(lat.N, [0, lat.N - 1])], axis=1)
+    Hn = lat.halfwidth()
+    Nt = 40
+    ref = exact_corr(lat, psi, Nt, Hn)
+    got = o.bloch_corr(kind, Lx, Ly, t, psi, np.arange(Nt + 1) * math.pi / Hn)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("kind,Lx,Ly,t", [("square", 6, 5, 1.0), ("honeycomb", 5, 4, -2.7),
+                                          ("chain", 11, 1, 0.9)])
+def test_bloch_uniform_and_return_amplitude_equal_exact_diagonalisation(kind, Lx, Ly, t):
+    lat = o.Lattice(kind, Lx, Ly, t=t)
+    Hn = lat.halfwidth()
+    Nt = 50
+    tau = math.pi / Hn
+    psi = np.concatenate([o.random_phase_states_fast(lat.N, 2, 4),
+                          o.site_states(lat.N, [1])], axis=1)
+    got = o.bloch_corr_uniform(kind, Lx, Ly, t, psi, tau, Nt + 1)
+    assert np.max(np.abs(got - exact_corr(lat, psi, Nt, Hn))) < 1e-12
+    ret = o.bloch_return_amplitude(kind, Lx, Ly, t, tau, Nt + 1)
+    for site in (0, 1, lat.N // 2, lat.N - 1):
+        ref = exact_corr(lat, o.site_states(lat.N, [site]), Nt, Hn)[:, 0]
+        assert np.max(np.abs(ret - ref)) < 1e-12
+
+
+def test_bloch_uniform_long_times_match_direct():
+    # block products against direct cos/sin over thousands of steps
+    lat = o.Lattice("honeycomb", 30, 24, t=-2.7)
+    psi = o.random_phase_states_fast(lat.N, 2, 6)
+    tau = math.pi / lat.halfwidth()
+    u = o.bloch_corr_uniform("honeycomb", 30, 24, -2.7, psi, tau, 4097)
+    sel = np.array([0, 1, 17, 1000, 2047, 4096])
+    d = o.bloch_corr("honeycomb", 30, 24, -2.7, psi, sel * tau)
+    assert np.max(np.abs(u[sel] - d)) < 1e-12
 
 
 def test_chain_return_amplitude_is_bessel_j0():
