@@ -14,6 +14,9 @@ Contents, each following the passage cited beside it:
   * Bessel / Chebyshev coefficients and truncation order -- App. B, Sec. II.A;
   * sequential and state-based concurrent propagation -- Sec. II.A Eq. (TE),
     Sec. II.B time blocks (C code in csp_oracle.c);
+  * moment-based propagation, in time blocks or in one block with the
+    halving of Eq. (cheby_prod) -- Sec. II.A, Sec. III DOS-Concurrent-M;
+  * band-structure closed forms of clean periodic lattices (any size);
   * DOS from the correlation function -- Sec. III.
 
 Pins: see tests/test_oracle_*.py.  Every routine here is pinned by at least
@@ -77,6 +80,11 @@ def lib():
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int64, _dp,
                                 ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int64, _dp, _dp, _i64p]
+    L.orc_propagate_moments.restype = ctypes.c_int
+    L.orc_propagate_moments.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int64, _dp,
+                                        ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int64, ctypes.c_int, _dp, _dp, _i64p]
     L.orc_chebyshev_vectors.restype = ctypes.c_int
     L.orc_chebyshev_vectors.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
                                         ctypes.c_double, ctypes.c_double, _dp,
@@ -284,6 +292,43 @@ def propagate(lat, psi0, Nt, b=0, Hn=None, H0=0.0, tau=math.pi, eta=1e-14,
                              _p(cnt, _i64p))
     if rc:
         raise RuntimeError("orc_propagate failed (%d)" % rc)
+    counters = {"amxsy": int(cnt[0]), "axpy": int(cnt[1]),
+                "dot": int(cnt[2]), "dot0": int(cnt[3])}
+    if return_final:
+        return corr.T.copy(), counters, fin.T.copy()
+    return corr.T.copy(), counters
+
+
+def propagate_moments(lat, psi0, Nt, b=None, halving=True, Hn=None, H0=0.0, tau=math.pi,
+                      eta=1e-14, margin=1.025, return_final=False):
+    """Correlations [(Nt+1)][R] by the moment-based form (Sec. II.A) in
+    blocks of b steps (b = None: one block, the DOS-Concurrent-M form of
+    Sec. III), optionally with the halving of Eq. (cheby_prod) (one block
+    only).  Returns (corr, counters) with counters amxsy (recursion steps),
+    axpy (carry updates), dot (moments from inner products) and dot0."""
+    psi0 = np.asarray(psi0, dtype=np.complex128)
+    if psi0.ndim == 1:
+        psi0 = psi0[:, None]
+    N, R = psi0.shape
+    if N != lat.N:
+        raise ValueError("state length does not match the lattice")
+    if Hn is None:
+        Hn = lat.halfwidth(margin)
+    if b is None:
+        b = Nt
+    cols = np.ascontiguousarray(psi0.T)
+    corr = np.zeros((R, Nt + 1), dtype=np.complex128)
+    cnt = np.zeros(4, dtype=np.int64)
+    fin = np.zeros((R, N), dtype=np.complex128)
+    rc = lib().orc_propagate_moments(N, _p(lat.rowptr, _i64p), _p(lat.col, _i64p),
+                                     _p(lat.val, _dp), float(H0), float(Hn), R,
+                                     _p(cols.view(np.float64), _dp), int(Nt), float(tau),
+                                     float(eta), int(b), int(bool(halving)),
+                                     _p(corr.view(np.float64), _dp),
+                                     _p(fin.view(np.float64), _dp) if return_final else None,
+                                     _p(cnt, _i64p))
+    if rc:
+        raise RuntimeError("orc_propagate_moments failed (%d)" % rc)
     counters = {"amxsy": int(cnt[0]), "axpy": int(cnt[1]),
                 "dot": int(cnt[2]), "dot0": int(cnt[3])}
     if return_final:

@@ -17,7 +17,9 @@
  *   - sequential propagation psi(t_j) = exp(-i H tau) psi(t_{j-1}) with the
  *     correlation <psi0|psi(t_j)> (Sec. II.A, Sec. III);
  *   - state-based concurrent propagation in time blocks, Eq. (TE) with the
- *     blocks of Sec. II.B, with the same correlations.
+ *     blocks of Sec. II.B, with the same correlations;
+ *   - moment-based propagation (Sec. II.A) in blocks, and in one block with
+ *     the halving of Eq. (cheby_prod) (DOS-Concurrent-M of Sec. III).
  * Operation counters (amxsy / axpy / dot) follow the definitions of Sec. II.B
  * so that tests can compare them with Tab. (cost).
  *
@@ -444,6 +446,128 @@ int orc_chebyshev_vectors(int64_t n, const int64_t *rowptr, const int64_t *col,
         cplx *dst = out + (size_t)k * (size_t)n;
         memcpy(dst, out + (size_t)(k - 2) * (size_t)n, (size_t)n * sizeof(cplx));
         amxsy(&H, 2.0, out + (size_t)(k - 1) * (size_t)n, dst);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Moment-based form (Sec. II.A, moment-based implementation; Sec. III  */
+/* DOS-Concurrent-M).  Within a block starting from s_k the Chebyshev   */
+/* moments mu_n = <psi0|T_n(Ht) s_k> give                               */
+/*   C(t_{kb+j}) = sum_{n=0}^{N(j tau)} c_n(j tau) mu_n,  j = 1..b_k,   */
+/* the order of the time and polynomial sums of the sequential form     */
+/* interchanged.  With more than one block the next block starts from   */
+/* s_{k+1} = sum_n c_n(b_k tau) T_n(Ht) s_k.                            */
+/*                                                                      */
+/* halving (only for one block, where s_0 = psi0, and no final state):  */
+/* with 2 T_m T_n = T_{m+n} + T_{|m-n|} (Eq. cheby_prod) and T_n        */
+/* Hermitian, the moments above h = floor(N/2) follow from inner        */
+/* products of vectors already generated:                               */
+/*   mu_{2k}   = 2 <phi_k|phi_k>     - mu_0,                            */
+/*   mu_{2k+1} = 2 <phi_{k+1}|phi_k> - mu_1,                            */
+/* so the recursion stops at order ceil(N/2).  (Eq. cheby-moment as     */
+/* printed omits the factor 2 on the inner products; with T_0 = 1 the   */
+/* identity at m = n gives 2 T_n^2 = T_{2n} + 1, which fixes it.)       */
+/* Counters: [0] recursion steps, [1] carry axpys, [2] moments taken    */
+/* from inner products (n >= 1), [3] t = 0 correlations.               */
+/* ------------------------------------------------------------------ */
+static int propagate_one_moments(const orc_ham *H, const cplx *psi0, int64_t Nt, double tau,
+                                 double eta, int64_t b, int halving, cplx *corr,
+                                 cplx *final_out, int64_t *cnt)
+{
+    const int64_t n = H->n;
+    if (b < 1) return -1;
+    if (b > Nt && Nt > 0) b = Nt;
+    const int single = (b >= Nt);
+    if (halving && (!single || final_out)) return -1;
+    int64_t *Nj = (int64_t *)malloc((size_t)(b + 1) * sizeof(int64_t));
+    for (int64_t j = 1; j <= b; ++j) {
+        Nj[j] = orc_truncation((double)j * tau, eta);
+        if (Nj[j] < 1) return -1;
+    }
+    const int64_t Nmax = Nj[b];
+    cplx *c = (cplx *)malloc((size_t)(b + 1) * (size_t)(Nmax + 1) * sizeof(cplx));
+    for (int64_t j = 1; j <= b; ++j)
+        orc_cheb_coeffs((double)j * tau, Nj[j], c + (size_t)j * (size_t)(Nmax + 1));
+#define COEF(jj, nn) c[(size_t)(jj) * (size_t)(Nmax + 1) + (size_t)(nn)]
+    cplx *mu = (cplx *)malloc((size_t)(Nmax + 1) * sizeof(cplx));
+    cplx *s = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *s_next = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p0 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p1 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *self = (cplx *)malloc((size_t)(Nmax + 2) * sizeof(cplx));   /* <phi_k|phi_k> */
+    cplx *cross = (cplx *)malloc((size_t)(Nmax + 2) * sizeof(cplx));  /* <phi_k|phi_{k-1}> */
+    if (!mu || !s || !s_next || !p0 || !p1 || !self || !cross) return -2;
+
+    memcpy(s, psi0, (size_t)n * sizeof(cplx));
+    corr[0] = dot(n, psi0, s);
+    cnt[3] += 1;
+    for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+        const int64_t bk = (Nt - t0 < b) ? (Nt - t0) : b;
+        const int64_t Nk = Nj[bk];
+        const int carry = !single || final_out != NULL;
+        const int64_t top = halving ? (Nk + 1) / 2 : Nk;      /* highest order generated */
+        const int64_t h = Nk / 2;
+        /* phi_0 = s, phi_1 = Ht s */
+        memcpy(p0, s, (size_t)n * sizeof(cplx));
+        memset(p1, 0, (size_t)n * sizeof(cplx));
+        amxsy(H, 1.0, p0, p1); cnt[0]++;
+        mu[0] = dot(n, psi0, p0);
+        mu[1] = dot(n, psi0, p1); cnt[2]++;
+        if (halving) {
+            self[1] = dot(n, p1, p1);
+            cross[1] = dot(n, p1, p0);
+        }
+        if (carry) {
+            copy_scaled(n, COEF(bk, 0), p0, s_next);
+            axpy(n, COEF(bk, 1), p1, s_next); cnt[1]++;
+        }
+        for (int64_t k = 2; k <= top; ++k) {
+            amxsy(H, 2.0, p1, p0); cnt[0]++;       /* p0 <- phi_k */
+            cplx *tmp = p0; p0 = p1; p1 = tmp;     /* p1 = phi_k, p0 = phi_{k-1} */
+            if (!halving || k <= h) { mu[k] = dot(n, psi0, p1); cnt[2]++; }
+            if (halving) {
+                self[k] = dot(n, p1, p1);
+                cross[k] = dot(n, p1, p0);
+            }
+            if (carry) { axpy(n, COEF(bk, k), p1, s_next); cnt[1]++; }
+        }
+        if (halving) {
+            for (int64_t m = h + 1; m <= Nk; ++m) {
+                if (m % 2 == 0) mu[m] = 2.0 * self[m / 2] - mu[0];
+                else mu[m] = 2.0 * cross[(m + 1) / 2] - mu[1];
+                cnt[2]++;
+            }
+        }
+        for (int64_t j = 1; j <= bk; ++j) {
+            cplx acc = 0.0;
+            for (int64_t m = 0; m <= Nj[j]; ++m) acc += COEF(j, m) * mu[m];
+            corr[t0 + j] = acc;
+        }
+        if (carry) { cplx *tmp = s; s = s_next; s_next = tmp; }
+    }
+    if (final_out) memcpy(final_out, s, (size_t)n * sizeof(cplx));
+#undef COEF
+    free(Nj); free(c); free(mu); free(s); free(s_next); free(p0); free(p1); free(self); free(cross);
+    return 0;
+}
+
+/* Moment-based propagation of R states (layout as orc_propagate).  b >= 1
+ * is the block size (b >= Nt: one block), halving selects the doubling
+ * identity for the upper half of the moments (one block only). */
+int orc_propagate_moments(int64_t n, const int64_t *rowptr, const int64_t *col,
+                          const double *val, double H0, double Hn, int64_t R, const cplx *psi0,
+                          int64_t Nt, double tau, double eta, int64_t b, int halving,
+                          cplx *corr, cplx *final_states, int64_t *counters)
+{
+    orc_ham H = {n, rowptr, col, val, H0, Hn};
+    if (n < 1 || R < 1 || Nt < 1 || !(Hn > 0.0)) return -1;
+    for (int64_t r = 0; r < R; ++r) {
+        const cplx *p = psi0 + (size_t)r * (size_t)n;
+        cplx *cr = corr + (size_t)r * (size_t)(Nt + 1);
+        cplx *fr = final_states ? final_states + (size_t)r * (size_t)n : NULL;
+        int rc = propagate_one_moments(&H, p, Nt, tau, eta, b, halving, cr, fr, counters);
+        if (rc) return rc;
     }
     return 0;
 }

@@ -15,12 +15,15 @@ import oracle as o
 
 
 @pytest.mark.parametrize("x", [1e-3, 0.5, 1.0, math.pi, 10.0, 32 * math.pi,
-                               100.5, 256 * math.pi])
+                               100.5, 256 * math.pi, 1024 * math.pi, 2048 * math.pi,
+                               4096 * math.pi])
 def test_bessel_matches_scipy(x):
+    # single-block moment propagation over 2048 or 4096 steps needs
+    # J_n(j pi) up to x = 4096 pi; both methods lose a few ulp per 1e3 orders
     nmax = o.truncation(x) + 10
     J = o.bessel_j(x, nmax)
     ref = jv(np.arange(nmax + 1), x)
-    assert np.max(np.abs(J - ref)) < 1e-13
+    assert np.max(np.abs(J - ref)) < (1e-13 if x < 1000 else 2e-13)
 
 
 def test_bessel_zero_argument():
