@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-seq", action="store_true",
                     help="skip the complex128 sequential comparison run")
+    ap.add_argument("--no-moments", action="store_true",
+                    help="skip the moment-based form runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
@@ -213,6 +215,31 @@ def main():
         "effective_rate": N * R * Nt * 20 / (el / a.steps),
     }
 
+    # the moment-based form (DOS-Concurrent-M of Sec. III: one block, halving)
+    # on the same step, outside the timed region
+    if not a.no_moments:
+        pm = csp.make_params(Nt, mode="fp32_conc", block_b=0, assembly=csp.CSP_ASSEMBLE_MOMENTS,
+                             profile=True)
+        csp.csp_propagate(ctx, lat, psi, pm, corr=corr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, mrep = csp.csp_propagate(ctx, lat, psi, pm, corr=corr)
+        csp.csp_dos(ctx, corr[:, :W["R_rand"]].contiguous(), lat.halfwidth)
+        csp.csp_dos(ctx, corr[:, W["R_rand"]:].contiguous(), lat.halfwidth)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        mb = mrep.spmm_bytes / mrep.spmm_launches
+        mt = mrep.ms_spmm / 1000.0 / mrep.spmm_launches
+        out["moments"] = {"form": "moment-based, one block of %d steps, halving (DOS-Concurrent-M)"
+                                  % Nt,
+                          "ms_per_step": 1000.0 * tm, "recursion_steps": mrep.amxsy,
+                          "value": N * R * mrep.amxsy / tm,
+                          "sequential_equivalent_rate": N * R * Nt * 20 / tm,
+                          "kernel": "k_spmm<float, 4, moments>", "bytes_per_launch": mb,
+                          "avg_launch_us": mt * 1e6, "achieved_GBs": mb / mt / 1e9,
+                          "frac": mb / mt / 1e9 / HBM_PEAK_GBS}
+        log("moments: %.3f s per step, %d recursion steps" % (tm, mrep.amxsy))
+
     # time-to-accuracy: DOS of the random columns, complex64 concurrent vs
     # complex128 sequential, both on this GPU
     if not a.no_seq:
@@ -243,6 +270,21 @@ def main():
                                    "speedup": t64 / t32, "dos_rel_err": rel,
                                    "corr_eps_inf": eps_c, "target_rel_err": 1e-4,
                                    "columns": W["R_rand"]}
+        if not a.no_moments:
+            cm = torch.empty_like(c32)
+            pm4 = csp.make_params(Nt, mode="fp32_conc", block_b=0,
+                                  assembly=csp.CSP_ASSEMBLE_MOMENTS)
+            csp.csp_propagate(ctx, lat, p4, pm4, corr=cm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            csp.csp_propagate(ctx, lat, p4, pm4, corr=cm)
+            _, _, Dm4 = csp.csp_dos(ctx, cm, lat.halfwidth)
+            torch.cuda.synchronize()
+            tmo = time.perf_counter() - t0
+            relm = float(np.max(np.abs(Dm4.cpu().numpy() - d64)) / np.max(np.abs(d64)))
+            out["time_to_accuracy"].update({"fp32_moments_s": tmo, "speedup_moments": t64 / tmo,
+                                            "dos_rel_err_moments": relm})
+            log("fp32 moments DOS (4 columns): %.3f s" % tmo)
     del psi, corr
     lat.close()
     ctx.close()

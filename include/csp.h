@@ -70,9 +70,16 @@ typedef enum {
     /* Assemble psi(t_j) = sum_n c_n(j tau) T_n(H~) s_k for every j of the
      * block (Eq. TE) and reduce <psi0|psi(t_j)> in the same kernel. */
     CSP_ASSEMBLE_STATES = 0,
-    /* Reduce the block moments mu_n = <psi0|T_n(H~) s_k> during the
-     * recursion and form C(t_j) = sum_n c_n(j tau) mu_n in FP64; no
-     * Chebyshev vectors are kept.  Same result up to rounding. */
+    /* Moment-based form (Sec. II.A): reduce the block moments
+     * mu_n = <psi0|T_n(H~) s_k> in the recursion kernel's epilogue and form
+     * C(t_j) = sum_n c_n(j tau) mu_n in FP64; three Chebyshev vectors per
+     * column are kept.  With one block (block_b = 0 or >= Nt) and no final
+     * state requested this is DOS-Concurrent-M of Sec. III: the moments
+     * above N/2 come from the halving identity of Eq. (cheby_prod),
+     * mu_2k = 2<phi_k|phi_k> - mu_0 and mu_2k+1 = 2<phi_k+1|phi_k> - mu_1,
+     * so only N/2 recursion steps run.  With several blocks the recursion
+     * epilogue also accumulates the carried state.  Same correlations as
+     * CSP_ASSEMBLE_STATES up to rounding. */
     CSP_ASSEMBLE_MOMENTS = 1
 } csp_assembly;
 
@@ -114,19 +121,28 @@ typedef struct {
     double eta;                /* truncation threshold; 0 -> 1e-14 */
     int32_t mode;              /* csp_mode */
     int32_t assembly;          /* csp_assembly */
-    int32_t block_b;           /* time-block size; 0 -> selection rule */
+    int32_t block_b;           /* time-block size; 0 -> the selection rule
+                                  (state assembly) or one block (moment
+                                  assembly); the sequential mode uses 1 */
     int32_t chunk_K;           /* Chebyshev vectors kept per contraction;
                                   0 -> as many as fit (multiple of 16) */
     uint64_t mem_cap_bytes;    /* workspace cap; 0 -> free device memory */
     int32_t profile;           /* nonzero: time kernel classes with events */
-    int32_t check_norm;        /* nonzero: norm guard on the carried state */
+    int32_t check_norm;        /* nonzero: after every time block check on the
+                                  GPU that the carried state kept the norm of
+                                  psi0 (the propagator is unitary) and that
+                                  every new correlation is finite with
+                                  |C_j| <= (1 + norm_tol) <psi0|psi0>;
+                                  a violation makes the call return
+                                  CSP_ENUMERIC naming the first failing block */
     double norm_tol;           /* relative tolerance of the guard; 0 -> 1e-3 */
 } csp_params;
 
 /* What a propagation did.  Operation counts are per state column and follow
- * the definitions of Sec. II.B: amxsy = Chebyshev recursion steps,
- * axpy = (n, j) coefficient pairs of the block sums, dot = correlations
- * after t = 0. */
+ * the definitions of Sec. II.B and Tab. (cost): amxsy = Chebyshev recursion
+ * steps; axpy = (n, j) coefficient pairs of the block sums (state assembly)
+ * or carry updates (moment assembly); dot = correlations after t = 0 (state
+ * assembly) or moments taken from inner products (moment assembly). */
 typedef struct {
     int32_t block_b, chunk_K, n_blocks, n_groups;
     int64_t amxsy, axpy, dot;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -131,6 +132,25 @@ csp_status hip_event(csp_context* c, size_t i, hipEvent_t* out) {
 }
 
 int64_t trunc_nmax(double x) { return (int64_t)std::ceil(x + 40.0 + 25.0 * std::cbrt(x + 1.0)); }
+
+// Norm-guard flag: [0] first failing block (INT32_MAX = none), [1] column.
+csp_status guard_reset(int* d_flag, hipStream_t s) {
+  static const int init[2] = {INT32_MAX, -1};
+  HIPCALL(hipMemcpyAsync(d_flag, init, sizeof(init), hipMemcpyHostToDevice, s));
+  return CSP_OK;
+}
+
+csp_status guard_check(const int* d_flag, hipStream_t s) {
+  int h[2] = {0, 0};
+  HIPCALL(hipMemcpyAsync(h, d_flag, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCALL(hipStreamSynchronize(s));
+  if (h[0] != INT32_MAX)
+    return fail(CSP_ENUMERIC,
+                "norm guard tripped after time block %d (column %d): the carried state lost "
+                "its norm or a correlation is not finite or exceeds <psi0|psi0>",
+                h[0], h[1]);
+  return CSP_OK;
+}
 
 }  // namespace
 
@@ -319,7 +339,7 @@ extern "C" csp_status csp_chebyshev_coefficients(csp_context* c, double x, doubl
   int32_t* d_n = nullptr;
   HIPCALL(hipMalloc(&d_a, sizeof(double) * (nm + 1)));
   HIPCALL(hipMalloc(&d_n, sizeof(int32_t)));
-  hipError_t e = launch_bessel(x, 1, (int)nm, eta, d_a, d_n, c->stream);
+  hipError_t e = launch_bessel(x, 1, (int)nm, eta, false, d_a, d_n, c->stream);
   if (e == hipSuccess) e = launch_complex_coeffs(d_a, nmax, dev_c, c->stream);
   int32_t nt = -1;
   if (e == hipSuccess)
@@ -423,7 +443,7 @@ extern "C" csp_status csp_chebyshev_step(csp_context* c, const csp_lattice* L, i
   st.seg_rows = p.seg_rows;
   st.halo = p.halo;
   st.total_tiles = p.total_tiles;
-  if (e == hipSuccess) e = launch_spmm(fp64, p.vec, d_inst, 1, st, c->stream);
+  if (e == hipSuccess) e = launch_spmm(fp64, p.vec, false, d_inst, 1, st, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(d_inst);
   if (e != hipSuccess) return fail(CSP_EHIP, "chebyshev step: %s", hipGetErrorString(e));
@@ -574,6 +594,9 @@ extern "C" csp_status csp_propagate_batch(csp_context* c, int32_t n_inst,
   return propagate_impl(c, ins, params, rep);
 }
 
+static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstIn>& ins,
+                                         const csp_params& P, double t_start, csp_report* rep);
+
 static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
                                  const csp_params* params_in, csp_report* rep) {
   const double t_start = now_ms();
@@ -583,9 +606,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   if (P.mode < CSP_FP64_SEQ || P.mode > CSP_FP32_CONC) return fail(CSP_EINVAL, "bad mode %d", P.mode);
   if (P.assembly != CSP_ASSEMBLE_STATES && P.assembly != CSP_ASSEMBLE_MOMENTS)
     return fail(CSP_EINVAL, "bad assembly %d", P.assembly);
-  if (P.assembly == CSP_ASSEMBLE_MOMENTS)
-    return fail(CSP_EUNSUPPORTED, "moment assembly is not available in this build");
-  if (P.check_norm) return fail(CSP_EUNSUPPORTED, "norm guard is not available in this build");
+  if (P.assembly == CSP_ASSEMBLE_MOMENTS) return propagate_moments_impl(c, ins, P, t_start, rep);
   const bool fp64 = P.mode != CSP_FP32_CONC;
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   for (size_t i = 0; i < ins.size(); ++i) {
@@ -618,7 +639,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   } tmp;
   tmp.p.push_back(d_a);
   tmp.p.push_back(d_ntr);
-  HIPCALL(launch_bessel(P.tau_tilde, ncol, nmax, P.eta, d_a, d_ntr, s));
+  HIPCALL(launch_bessel(P.tau_tilde, ncol, nmax, P.eta, true, d_a, d_ntr, s));
   HIPCALL(hipMemcpyAsync(ntr.data(), d_ntr, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, s));
   HIPCALL(hipStreamSynchronize(s));
   for (int j = 0; j < ncol; ++j)
@@ -736,6 +757,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   }
   const size_t n_sd = 256;   // self-dot partial blocks
   need += align256(sizeof(double) * n_sd * kMaxGroupCols);
+  need += align256(2 * sizeof(int));
   need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size()) +
           align256(sizeof(FinishInst) * groups.size());
   if (need > cap) return fail(CSP_ENOMEM, "workspace %.2f GB exceeds the cap %.2f GB", need / 1e9, cap / 1e9);
@@ -760,6 +782,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     g.partial = (double*)cv.take((size_t)g.n_wg * b * g.Rg * 16);
   }
   double* d_sd = (double*)cv.take(sizeof(double) * n_sd * kMaxGroupCols);
+  int* d_flag = (int*)cv.take(2 * sizeof(int));
   SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
   ContractInst* d_con = (ContractInst*)cv.take(sizeof(ContractInst) * groups.size());
   FinishInst* d_fin = (FinishInst*)cv.take(sizeof(FinishInst) * groups.size());
@@ -815,6 +838,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   // copies above go out of scope (the host vectors live until the end).
 
   // ---------------------------------------------------------- blocks
+  if (P.check_norm) CHECK(guard_reset(d_flag, s));
   Profiler prof{c, P.profile != 0};
   int64_t n_spmm = 0, n_con = 0, amxsy = 0, axpy = 0;
   double spmm_bytes = 0, con_bytes = 0, con_flops = 0;
@@ -850,7 +874,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     st.has_prev = 0;
     st.scale_f = 0.5f;
     st.scale_d = 0.5;
-    HIPCALL(launch_spmm(fp64, sp_plan.vec, d_spmm, (int)sp.size(), st, s));
+    HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), st, s));
     ++n_spmm;
     spmm_bytes += step_bytes;
     size_t ci = 0;
@@ -895,7 +919,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       st.has_prev = 1;
       st.scale_f = 1.0f;
       st.scale_d = 1.0;
-      HIPCALL(launch_spmm(fp64, sp_plan.vec, d_spmm, (int)sp.size(), st, s));
+      HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), st, s));
       ++n_spmm;
       spmm_bytes += step_bytes;
       produced = n + 1;
@@ -903,6 +927,13 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     }
     CHECK(prof.end(ev));
     HIPCALL(launch_finish(d_fin, (int)fi.size(), bk, t0, s));
+    if (P.check_norm) {
+      for (auto& g : groups) {
+        const InstIn& in = ins[g.inst];
+        HIPCALL(launch_guard(in.lat->g.N, g.Rg, g.carry, fp64, in.corr, in.R, g.col0, t0, bk,
+                             P.norm_tol, (int)(t0 / b), d_flag, d_sd, (int)n_sd, s));
+      }
+    }
   }
 
   // ---------------------------------------------------------- final state
@@ -913,6 +944,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
                                 g.carry, fp64, in.final_out, s));
   }
   HIPCALL(hipStreamSynchronize(s));
+  if (P.check_norm) CHECK(guard_check(d_flag, s));
 
   if (rep) {
     double ms_s = 0, ms_c = 0;
@@ -932,6 +964,297 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     rep->spmm_bytes = spmm_bytes;
     rep->contract_bytes = con_bytes;
     rep->contract_flops = con_flops;
+    rep->workspace_bytes = c->ws_size;
+  }
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ moment form
+// Moment-based propagation (Sec. II.A moment-based implementation): per time
+// block the recursion runs with the moment epilogue (inner products with
+// psi0, and with halving the self products of Eq. cheby_prod), the block
+// moments are contracted with the coefficients in FP64, and with more than
+// one block the epilogue also accumulates the carried state.  Three
+// Chebyshev vectors per column group are kept (Tab. cost: 3 states).
+static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstIn>& ins,
+                                         const csp_params& P, double t_start, csp_report* rep) {
+  const bool fp64 = P.mode != CSP_FP32_CONC;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  const int64_t Nt = P.Nt;
+  for (size_t i = 0; i < ins.size(); ++i) {
+    if (ins[i].R < 1) return fail(CSP_EINVAL, "instance %zu: R must be >= 1", i);
+    if (ins[i].lat->ctx->device != c->device)
+      return fail(CSP_EINVAL, "instance %zu: lattice on another device", i);
+  }
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+  bool want_final = false;
+  for (auto& in : ins) want_final |= in.final_out != nullptr;
+
+  // Block size: sequential mode is b = 1; otherwise block_b, 0 = one block.
+  int64_t b = P.mode == CSP_FP64_SEQ ? 1 : (P.block_b > 0 ? P.block_b : std::max<int64_t>(Nt, 1));
+  if (Nt > 0) b = std::min<int64_t>(b, Nt);
+  if (b > (1 << 20)) return fail(CSP_EUNSUPPORTED, "block of %lld steps", (long long)b);
+  const bool single = b >= Nt;
+  const bool halving = single && !want_final && Nt > 0;
+  const bool carry = !single || want_final;
+  const int64_t b_last = Nt > 0 ? Nt - (ceil_div(Nt, b) - 1) * b : b;
+
+  // Coefficient table a[j][n], x = (j + 1) tau, j < b.
+  const int ncol = (int)b;
+  const int nmax = (int)trunc_nmax((double)ncol * P.tau_tilde);
+  const int lda = nmax + 1;
+  struct Free {
+    std::vector<void*> p;
+    ~Free() { for (void* q : p) (void)hipFree(q); }
+  } tmp;
+  double* d_a = nullptr;
+  int32_t* d_ntr = nullptr;
+  HIPCALL(hipMalloc(&d_a, sizeof(double) * (size_t)ncol * lda));
+  tmp.p.push_back(d_a);
+  HIPCALL(hipMalloc(&d_ntr, sizeof(int32_t) * ncol));
+  tmp.p.push_back(d_ntr);
+  HIPCALL(launch_bessel(P.tau_tilde, ncol, nmax, P.eta, true, d_a, d_ntr, s));
+  std::vector<int32_t> ntr(ncol);
+  HIPCALL(hipMemcpyAsync(ntr.data(), d_ntr, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, s));
+  // carry coefficients: rows of the block lengths b and b_last
+  std::vector<double> arow_b, arow_last;
+  if (carry) {
+    arow_b.resize(lda);
+    arow_last.resize(lda);
+    HIPCALL(hipMemcpyAsync(arow_b.data(), d_a + (size_t)(b - 1) * lda, sizeof(double) * lda,
+                           hipMemcpyDeviceToHost, s));
+    HIPCALL(hipMemcpyAsync(arow_last.data(), d_a + (size_t)(b_last - 1) * lda,
+                           sizeof(double) * lda, hipMemcpyDeviceToHost, s));
+  }
+  HIPCALL(hipStreamSynchronize(s));
+  for (int j = 0; j < ncol; ++j)
+    if (ntr[j] < 1) return fail(CSP_ENUMERIC, "no truncation order for x = %g", (j + 1) * P.tau_tilde);
+  const int Nk_max = ntr[b - 1];
+  const int steps_max = halving ? (Nk_max + 1) / 2 : Nk_max;
+
+  // Column groups (powers of two, <= 32 columns).
+  std::vector<Group> groups;
+  int64_t vec_elems = 0;
+  int rmax = 1;
+  for (size_t i = 0; i < ins.size(); ++i) {
+    int col = 0;
+    for (int Rg : split_columns(ins[i].R)) {
+      Group g;
+      g.inst = (int)i;
+      g.col0 = col;
+      g.Rg = Rg;
+      g.M = ins[i].lat->g.N * Rg;
+      groups.push_back(g);
+      vec_elems += g.M;
+      rmax = std::max(rmax, Rg);
+      col += Rg;
+    }
+  }
+  std::vector<SpmmInst> sp;
+  for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu);
+  const int P_batch = 16;
+
+  // Workspace.
+  size_t need = 0;
+  const size_t part_bytes = (size_t)P_batch * sp_plan.total_tiles * 4 * rmax * 16;
+  need += align256(part_bytes);
+  for (auto& g : groups) {
+    need += 3 * align256(g.M * csz) + align256(g.M * csz);          // ring + psi0
+    if (carry) need += 2 * align256(g.M * csz);                      // carry in / out
+    need += align256((size_t)(steps_max + 1) * 4 * g.Rg * 16);       // dots
+    need += align256((size_t)(Nk_max + 1) * g.Rg * 16);              // mu
+  }
+  need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(MomInst) * groups.size()) +
+          align256(sizeof(MomCorrInst) * groups.size()) +
+          align256(sizeof(double) * 256 * kMaxGroupCols) + align256(2 * sizeof(int));
+  size_t freeb = 0, totalb = 0;
+  HIPCALL(hipMemGetInfo(&freeb, &totalb));
+  const size_t avail = freeb + c->ws_size;
+  const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
+  if (need > cap)
+    return fail(CSP_ENOMEM, "workspace %.2f GB exceeds the cap %.2f GB", need / 1e9, cap / 1e9);
+  CHECK(ws_reserve(c, need));
+  Carver cv(c->ws);
+  double* d_part = (double*)cv.take(part_bytes);
+  std::vector<void*> carry_a(groups.size()), carry_b(groups.size());
+  std::vector<double*> dots(groups.size()), mus(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    g.slots = cv.take(3 * g.M * csz);
+    g.psi0g = cv.take(g.M * csz);
+    if (carry) {
+      carry_a[gi] = cv.take(g.M * csz);
+      carry_b[gi] = cv.take(g.M * csz);
+    }
+    dots[gi] = (double*)cv.take((size_t)(steps_max + 1) * 4 * g.Rg * 16);
+    mus[gi] = (double*)cv.take((size_t)(Nk_max + 1) * g.Rg * 16);
+  }
+  SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
+  MomInst* d_mi = (MomInst*)cv.take(sizeof(MomInst) * groups.size());
+  MomCorrInst* d_mc = (MomCorrInst*)cv.take(sizeof(MomCorrInst) * groups.size());
+  double* d_sd = (double*)cv.take(sizeof(double) * 256 * kMaxGroupCols);
+  int* d_flag = (int*)cv.take(2 * sizeof(int));
+  if (P.check_norm) CHECK(guard_reset(d_flag, s));
+
+  // Initial state, C_0, instance tables.
+  std::vector<MomInst> mi;
+  std::vector<MomCorrInst> mc;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    const InstIn& in = ins[g.inst];
+    const int64_t N = in.lat->g.N;
+    HIPCALL(launch_gather_cols(N, in.R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, in.psi0, fp64,
+                               g.psi0g, s));
+    HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, 256, s));
+    if (carry)
+      HIPCALL(hipMemcpyAsync(carry_a[gi], g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
+    SpmmInst& I = sp[gi];
+    I.base = g.slots;
+    I.slot_stride = g.M;
+    I.psi0 = g.psi0g;
+    MomInst m{};
+    m.tile0 = I.tile0;
+    m.n_tiles = I.n_strips * I.n_segs;
+    m.Rg = g.Rg;
+    m.dots = dots[gi];
+    mi.push_back(m);
+    MomCorrInst q{};
+    q.dots = dots[gi];
+    q.mu = mus[gi];
+    q.corr = in.corr;
+    q.ldc = in.R;
+    q.Rg = g.Rg;
+    q.col0 = g.col0;
+    mc.push_back(q);
+  }
+  HIPCALL(hipMemcpyAsync(d_mi, mi.data(), sizeof(MomInst) * mi.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_mc, mc.data(), sizeof(MomCorrInst) * mc.size(), hipMemcpyHostToDevice, s));
+
+  Profiler prof{c, P.profile != 0};
+  int64_t n_spmm = 0, amxsy = 0, axpy = 0, ndot = 0;
+  double spmm_bytes = 0;
+  double eps_bytes = 0;
+  for (auto& g : groups)
+    if (ins[g.inst].lat->has_onsite) eps_bytes += (double)ins[g.inst].lat->g.N * (fp64 ? 8 : 4);
+
+  SpmmStep st{};
+  st.seg_rows = sp_plan.seg_rows;
+  st.halo = sp_plan.halo;
+  st.total_tiles = sp_plan.total_tiles;
+  st.rmax = rmax;
+  st.partial = d_part;
+  int cur_carry = 0;   // carry_a holds s_k when 0
+  for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+    const int bk = (int)std::min<int64_t>(b, Nt - t0);
+    const int Nk = ntr[bk - 1];
+    const int steps = halving ? (Nk + 1) / 2 : Nk;
+    const int h = Nk / 2;
+    const std::vector<double>& arow = (bk == b) ? arow_b : arow_last;
+    // per-block instance table: source and carry destination
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      SpmmInst& I = sp[gi];
+      if (carry) {
+        I.src = cur_carry == 0 ? carry_a[gi] : carry_b[gi];
+        I.carry_out = cur_carry == 0 ? carry_b[gi] : carry_a[gi];
+      } else {
+        I.src = groups[gi].psi0g;
+        I.carry_out = nullptr;
+      }
+    }
+    HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(SpmmInst) * sp.size(), hipMemcpyHostToDevice, s));
+    size_t ev = 0;
+    CHECK(prof.begin(0, &ev));
+    int batch0 = 1;   // order produced by the first step of the pending batch
+    for (int i = 0; i < steps; ++i) {
+      const int n_out = i + 1;   // order produced by this step
+      st.slot_out = n_out % 3;
+      st.slot_cur = i % 3;
+      st.slot_prev = (i + 2) % 3;
+      st.cur_from_src = i == 0 ? 1 : 0;
+      st.copy_cur = i == 0 ? 1 : 0;
+      st.has_prev = i == 0 ? 0 : 1;
+      st.scale_f = i == 0 ? 0.5f : 1.0f;
+      st.scale_d = i == 0 ? 0.5 : 1.0;
+      st.dot_psi0 = (!halving || n_out <= h || i == 0) ? 1 : 0;
+      st.dot_self = halving ? 1 : 0;
+      st.mom_slot = i % P_batch;
+      if (carry) {
+        auto coef = [&](int n, double* out2) {
+          const double v = arow[n];
+          switch (n & 3) {   // (-i)^n v
+            case 0: out2[0] = v; out2[1] = 0.0; break;
+            case 1: out2[0] = 0.0; out2[1] = -v; break;
+            case 2: out2[0] = -v; out2[1] = 0.0; break;
+            default: out2[0] = 0.0; out2[1] = v; break;
+          }
+        };
+        st.carry_mode = i == 0 ? 1 : 2;
+        coef(0, st.cc0);
+        coef(n_out, st.cc);
+        axpy += i == 0 ? 2 : 1;
+      } else {
+        st.carry_mode = 0;
+      }
+      HIPCALL(launch_spmm(fp64, sp_plan.vec, true, d_spmm, (int)sp.size(), st, s));
+      ++n_spmm;
+      ++amxsy;
+      spmm_bytes += 3.0 * (double)vec_elems * csz + eps_bytes +
+                    (st.dot_psi0 ? (double)vec_elems * csz : 0.0) +
+                    (carry ? (i == 0 ? 1.0 : 2.0) * (double)vec_elems * csz : 0.0);
+      const bool flush = ((i + 1) % P_batch == 0) || (i + 1 == steps);
+      if (flush) {
+        const int cnt = i + 1 - (batch0 - 1);
+        HIPCALL(launch_mom_finish(d_mi, (int)mi.size(), d_part, sp_plan.total_tiles, rmax, cnt,
+                                  batch0, s));
+        batch0 = i + 2;
+      }
+    }
+    CHECK(prof.end(ev));
+    ndot += Nk;
+    HIPCALL(launch_mom_corr(d_mc, (int)mc.size(), Nk, halving ? 1 : 0, d_a, lda, d_ntr, bk, t0,
+                            rmax, s));
+    if (P.check_norm) {
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group& g = groups[gi];
+        const InstIn& in = ins[g.inst];
+        const void* cy = carry ? (cur_carry == 0 ? carry_b[gi] : carry_a[gi]) : nullptr;
+        HIPCALL(launch_guard(in.lat->g.N, g.Rg, cy, fp64, in.corr, in.R, g.col0, t0, bk,
+                             P.norm_tol, (int)(t0 / b), d_flag, d_sd, 256, s));
+      }
+    }
+    if (carry) cur_carry ^= 1;
+  }
+  // final state
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    const InstIn& in = ins[g.inst];
+    if (!in.final_out) continue;
+    void* fin = cur_carry == 0 ? carry_a[gi] : carry_b[gi];
+    HIPCALL(launch_scatter_cols(in.lat->g.N, in.R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, fin,
+                                fp64, in.final_out, s));
+  }
+  HIPCALL(hipStreamSynchronize(s));
+  if (P.check_norm) CHECK(guard_check(d_flag, s));
+  if (rep) {
+    double ms_s = 0, ms_c = 0;
+    CHECK(prof.collect(&ms_s, &ms_c));
+    rep->block_b = (int)b;
+    rep->chunk_K = 3;
+    rep->n_blocks = (int)(Nt > 0 ? ceil_div(Nt, b) : 0);
+    rep->n_groups = (int)groups.size();
+    rep->amxsy = amxsy;
+    rep->axpy = axpy;
+    rep->dot = ndot;
+    rep->spmm_launches = n_spmm;
+    rep->contract_launches = 0;
+    rep->ms_total = now_ms() - t_start;
+    rep->ms_spmm = ms_s;
+    rep->ms_contract = ms_c;
+    rep->spmm_bytes = spmm_bytes;
+    rep->contract_bytes = 0;
+    rep->contract_flops = 0;
     rep->workspace_bytes = c->ws_size;
   }
   return CSP_OK;

@@ -103,8 +103,8 @@ struct SpmmInst {
   void* base;                  // slot array
   int64_t slot_stride;         // complex values between slots
   const void* src;             // input vector when the step reads from outside the slots
-  void* moment_psi0;           // psi0 of the group for the moment epilogue (may be null)
-  double* moment_out;          // per-WG moment partials [n_tiles][R] complex
+  const void* psi0;            // psi0 of the group (moment epilogue), [N][R]
+  void* carry_out;             // carried state accumulated by the epilogue, [N][R]
   int64_t n_strips, n_segs;    // tiling of this instance
   int64_t tile0;               // first tile of this instance in the launch
 };
@@ -119,13 +119,46 @@ struct SpmmStep {
   double scale_d;
   int32_t seg_rows;        // rows per tile
   int32_t halo;            // max R over instances (LDS halo width)
-  int32_t moments;         // moment epilogue on
-  int32_t moment_slot;     // index of the moment in moment_out (row of [K][tiles][R])
   int64_t total_tiles;
+  // Moment epilogue (moment-based form), used by the MOM kernel variant only.
+  // Per tile and column the workgroup writes four complex FP64 sums:
+  //   0: <psi0|out>   1: <psi0|cur>   2: <out|out>   3: <out|cur>
+  // to partial[((slot * total_tiles + tile) * 4 + kind) * rmax + r].
+  int32_t dot_psi0;        // sums 0 and 1 (reads psi0)
+  int32_t dot_self;        // sums 2 and 3
+  int32_t carry_mode;      // 0 none, 1 carry = cc0 cur + cc out, 2 carry += cc out
+  int32_t mom_slot;
+  int32_t rmax;            // column stride of the partial records
+  int32_t pad1;
+  double cc0[2], cc[2];    // carry coefficients (complex)
+  double* partial;
 };
 
-hipError_t launch_spmm(bool fp64, int vec, const SpmmInst* d_inst, int n_inst,
+hipError_t launch_spmm(bool fp64, int vec, bool mom, const SpmmInst* d_inst, int n_inst,
                        const SpmmStep& st, hipStream_t s);
+
+// Sum the workgroup partials of `n_slots` steps into dots[(n0 + slot)][4][Rg]
+// (complex FP64) per instance, tiles in order.
+struct MomInst {
+  int64_t tile0, n_tiles;
+  int32_t Rg, pad;
+  double* dots;            // [n_rows][4][Rg] complex
+};
+hipError_t launch_mom_finish(const MomInst* d_mi, int n_inst, const double* partial,
+                             int64_t total_tiles, int rmax, int n_slots, int n0, hipStream_t s);
+// Moments of a block from the step sums (halving: doubling identity above h)
+// and correlations corr[(t0 + j) * ldc + col0 + r] = sum_n c_n(j tau) mu_n[r]
+// for j = 1..bk (table a as produced by launch_bessel, row j-1 for x = j tau).
+struct MomCorrInst {
+  const double* dots;      // [steps + 1][4][Rg] complex, row n = step producing order n
+  double* mu;              // [Nk + 1][Rg] complex (output of the assemble pass)
+  double* corr;
+  int64_t ldc;
+  int32_t Rg, col0;
+};
+hipError_t launch_mom_corr(const MomCorrInst* d_mc, int n_inst, int Nk, int halving,
+                           const double* d_a, int lda, const int32_t* d_ntrunc, int bk,
+                           int64_t t0, int rg_max, hipStream_t s);
 
 // ------------------------------------------------------------------ contraction
 struct ContractInst {
@@ -170,8 +203,9 @@ hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_
 
 // ------------------------------------------------------------------ coefficients
 // For x_j = (j + 1) * tau, j = 0..nx-1: a[j][n] = J_n(x_j) (n = 0) or
-// 2 J_n(x_j) (n >= 1) for n <= nmax, and ntrunc[j] = N(x_j).
-hipError_t launch_bessel(double tau, int nx, int nmax, double eta, double* d_a,
+// 2 J_n(x_j) (n >= 1) for n <= nmax, and ntrunc[j] = N(x_j).  clip: orders
+// beyond x_j + 40 + 25 x_j^(1/3) (past the truncation) are stored as 0.
+hipError_t launch_bessel(double tau, int nx, int nmax, double eta, bool clip, double* d_a,
                          int32_t* d_ntrunc, hipStream_t s);
 // Complex c_n(x) = (-i)^n a_n written as complex128 [nmax+1].
 hipError_t launch_complex_coeffs(const double* d_a, int nmax, double* d_c, hipStream_t s);
@@ -212,6 +246,10 @@ hipError_t launch_moment_corr(const double* d_mu_partial, int n_tiles, int Rg, i
                               const double* d_a, int lda, const int32_t* d_ntrunc, int bcols,
                               int64_t t0, double* d_corr, int64_t ldc, int col0,
                               hipStream_t s);
+// Norm guard after a block (see k_guard); d_carry may be null.
+hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const double* d_corr,
+                        int64_t ldc, int col0, int64_t t0, int bk, double tol, int block,
+                        int* d_flag, double* d_scratch, int n_scratch_wg, hipStream_t s);
 hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth,
                       double tau_tilde, int window, double* d_E, double* d_D, double* d_Dmean,
                       double* d_twiddle, hipStream_t s);

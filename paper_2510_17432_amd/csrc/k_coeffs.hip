@@ -13,56 +13,64 @@
 
 namespace csp {
 
-__global__ void k_bessel(double tau, int nx, int nmax, double eta, double* __restrict__ out,
-                         int32_t* __restrict__ ntrunc) {
+__global__ void k_bessel(double tau, int nx, int nmax, double eta, int clip,
+                         double* __restrict__ out, int32_t* __restrict__ ntrunc) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nx) return;
   const double x = tau * (double)(j + 1);
   double* a = out + (size_t)j * (nmax + 1);
-  for (int n = 0; n <= nmax; ++n) a[n] = 0.0;
   if (!(x > 0.0)) {
     a[0] = 1.0;
+    for (int n = 1; n <= nmax; ++n) a[n] = 0.0;
     ntrunc[j] = 0;
     return;
   }
-  // Start order: beyond the turning point x by a margin that grows like
-  // x^(1/3) (the width of the transition region of J_n near n = x), and
-  // beyond nmax; even so the sum below ends on an even order.
-  int M = (int)ceil((x > (double)nmax ? x : (double)nmax) + 24.0 + 18.0 * cbrt(x + 1.0));
+  // With clip, only the orders this argument needs are computed: past its
+  // truncation order (bounded by x + 40 + 25 x^(1/3)) the coefficients are
+  // below 1e-14 and stored as 0.  Arguments far below the table's largest
+  // then avoid a long, repeatedly rescaled recurrence.
+  const int need = (int)ceil(x + 40.0 + 25.0 * cbrt(x + 1.0));
+  const int top = (clip && need < nmax) ? need : nmax;   // highest order stored
+  for (int n = top + 1; n <= nmax; ++n) a[n] = 0.0;
+  // Start order: beyond the stored orders and the turning point x by a
+  // margin that grows like x^(1/3) (the width of the transition region of
+  // J_n near n = x); even, so that the Neumann sum ends on an even order.
+  int M = (int)ceil((x > (double)top ? x : (double)top) + 24.0 + 18.0 * cbrt(x + 1.0));
   M += M & 1;
   const double big = 0x1p600, small = 0x1p-600;
-  double up = 0.0;       // J_{k+1}
+  const double inv_x = 1.0 / x;
+  double up = 0.0;        // J_{k+1}
   double cur = 0x1p-300;  // J_k, arbitrary seed at k = M
   double even_sum = 0.0;  // sum of J_k over even k >= 2 seen so far
   for (int k = M; k >= 1; --k) {
-    if (k <= nmax) a[k] = cur;
+    if (k <= top) a[k] = cur;
     if ((k & 1) == 0) even_sum += cur;
-    const double down = (2.0 * (double)k / x) * cur - up;
+    const double down = (2.0 * (double)k * inv_x) * cur - up;
     up = cur;
     cur = down;
     if (fabs(cur) > big) {
       cur *= small;
       up *= small;
       even_sum *= small;
-      for (int n = k; n <= nmax; ++n) a[n] *= small;  // orders stored so far
+      for (int n = k; n <= top; ++n) a[n] *= small;  // orders stored so far
     }
   }
   // cur now holds J_0 (unnormalised).
   a[0] = cur;
   const double norm = cur + 2.0 * even_sum;
   const double inv = 1.0 / norm;
-  for (int n = 0; n <= nmax; ++n) a[n] *= (n == 0 ? inv : 2.0 * inv);
+  for (int n = 0; n <= top; ++n) a[n] *= (n == 0 ? inv : 2.0 * inv);
   // Truncation: first order above x with |c_n| = a_n <= eta.
   int N = -1;
-  for (int n = (int)floor(x) + 1; n <= nmax; ++n)
+  for (int n = (int)floor(x) + 1; n <= top; ++n)
     if (fabs(a[n]) <= eta) { N = n; break; }
   ntrunc[j] = N;
 }
 
-hipError_t launch_bessel(double tau, int nx, int nmax, double eta, double* d_a,
+hipError_t launch_bessel(double tau, int nx, int nmax, double eta, bool clip, double* d_a,
                          int32_t* d_ntrunc, hipStream_t s) {
-  hipLaunchKernelGGL(k_bessel, dim3((nx + 63) / 64), dim3(64), 0, s, tau, nx, nmax, eta, d_a,
-                     d_ntrunc);
+  hipLaunchKernelGGL(k_bessel, dim3((nx + 63) / 64), dim3(64), 0, s, tau, nx, nmax, eta,
+                     clip ? 1 : 0, d_a, d_ntrunc);
   return hipGetLastError();
 }
 

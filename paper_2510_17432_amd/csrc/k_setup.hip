@@ -230,6 +230,47 @@ hipError_t launch_self_dot(int64_t N, int Rg, const void* d_psi, bool fp64, doub
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ norm guard
+// After a time block: the carried state must keep the norm of psi0 (the
+// propagator is unitary) and every new correlation must be finite with
+// |C_j| <= |psi0|^2 (Cauchy-Schwarz).  Thread r checks column r of the group:
+// the carry norm from the self-dot partials (when carry_partial is set) and
+// the correlation rows t0+1..t0+bk.  A violation stores the block index into
+// flag[0] (smallest index wins) and the column into flag[1].
+__global__ void k_guard(int n_wg, int Rg, const double* __restrict__ carry_partial,
+                        const double* __restrict__ corr, int64_t ldc, int col0, int64_t t0,
+                        int bk, double tol, int block, int* __restrict__ flag) {
+  const int r = threadIdx.x;
+  if (r >= Rg) return;
+  const double2* C = reinterpret_cast<const double2*>(corr);
+  const double c0 = C[col0 + r].x;
+  bool bad = !(c0 >= 0.0) || !isfinite(c0);
+  if (carry_partial) {
+    double s = 0.0;
+    for (int w = 0; w < n_wg; ++w) s += carry_partial[(int64_t)w * Rg + r];
+    bad |= !isfinite(s) || fabs(s - c0) > tol * c0;
+  }
+  const double lim = (1.0 + tol) * c0;
+  for (int j = 1; j <= bk; ++j) {
+    const double2 v = C[(t0 + j) * ldc + col0 + r];
+    bad |= !isfinite(v.x) || !isfinite(v.y) || sqrt(v.x * v.x + v.y * v.y) > lim;
+  }
+  if (bad) {
+    if (atomicMin(&flag[0], block) > block) flag[1] = col0 + r;
+  }
+}
+
+hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const double* d_corr,
+                        int64_t ldc, int col0, int64_t t0, int bk, double tol, int block,
+                        int* d_flag, double* d_scratch, int n_scratch_wg, hipStream_t s) {
+  if (d_carry)
+    hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg), dim3(256), 0, s, N * Rg, Rg,
+                       d_carry, fp64 ? 1 : 0, d_scratch);
+  hipLaunchKernelGGL(k_guard, dim3(1), dim3(64), 0, s, n_scratch_wg, Rg,
+                     d_carry ? d_scratch : nullptr, d_corr, ldc, col0, t0, bk, tol, block, d_flag);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ DOS
 // twiddle[m] = exp(i pi m / Nt), m = 0..2Nt-1 (exact arguments via sincospi).
 __global__ void k_twiddle(int64_t Nt, double2* __restrict__ tw) {

@@ -21,6 +21,19 @@
 // Honeycomb (orbital 2x+sigma): A reaches B(x), B(x-1) in its row and
 // B(x, y-1); B reaches A(x), A(x+1) and A(x, y+1).  Chain: left, right.
 // Open edges read zeros from the halo; periodic edges wrap.
+//
+// Moment variant (MOM = true, moment-based form of Sec. II.A): the same
+// step, plus per-column inner products of the new vector with psi0, of psi0
+// with the current vector, and of the new vector with itself and with the
+// current vector (the halving identity of Eq. cheby_prod needs the last
+// two), and optionally the carried state s_{k+1} = sum_n c_n phi_n of a time
+// block.  Every column's products are accumulated by a fixed set of
+// threads in FP64 (column = thread % R, since the strip width is a multiple
+// of 256 and R a power of two dividing it), reduced per workgroup in a fixed
+// order and written as one record per tile; no atomics, so the result is the
+// same on every run.
+#include <algorithm>
+
 #include "csp_internal.h"
 
 namespace csp {
@@ -31,7 +44,7 @@ template <> struct cplx_of<double> { using type = double2; };
 
 template <typename C> __device__ inline C czero() { C z; z.x = 0; z.y = 0; return z; }
 
-template <typename T, int V>
+template <typename T, int V, bool MOM>
 __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const SpmmInst* __restrict__ insts,
                                                        int n_inst, SpmmStep st) {
   using C = typename cplx_of<T>::type;
@@ -132,6 +145,26 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const SpmmInst* __restric
     ep[v] = (eps && valid[v]) ? eps[y0 * I.opr + xv[v]] : T(0);
   }
 
+  // Moment epilogue state (compiled out of the plain variant).
+  const C* psi0 = static_cast<const C*>(I.psi0);
+  C* carry = static_cast<C*>(I.carry_out);
+  const bool dpsi = MOM && st.dot_psi0;
+  const bool dself = MOM && st.dot_self;
+  const int cmode = MOM ? st.carry_mode : 0;
+  const T cc0r = static_cast<T>(st.cc0[0]), cc0i = static_cast<T>(st.cc0[1]);
+  const T ccr = static_cast<T>(st.cc[0]), cci = static_cast<T>(st.cc[1]);
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  C p0v[MOM ? V : 1], p0n[MOM ? V : 1], cyv[MOM ? V : 1], cyn[MOM ? V : 1];
+  if constexpr (MOM) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      p0v[v] = (dpsi && valid[v]) ? psi0[y0 * rowlen + ev[v]] : czero<C>();
+      cyv[v] = (cmode == 2 && valid[v]) ? carry[y0 * rowlen + ev[v]] : czero<C>();
+    }
+  }
+
   int sm = 0, sc = 1, sp = 2;
   for (int64_t y = y0; y < y1; ++y) {
     const bool more = y + 1 < y1;
@@ -139,6 +172,13 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const SpmmInst* __restric
     for (int v = 0; v < V; ++v) {
       prvn[v] = (more && st.has_prev && valid[v]) ? prev[(y + 1) * rowlen + ev[v]] : czero<C>();
       epn[v] = (more && eps && valid[v]) ? eps[(y + 1) * I.opr + xv[v]] : T(0);
+    }
+    if constexpr (MOM) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        p0n[v] = (more && dpsi && valid[v]) ? psi0[(y + 1) * rowlen + ev[v]] : czero<C>();
+        cyn[v] = (more && cmode == 2 && valid[v]) ? carry[(y + 1) * rowlen + ev[v]] : czero<C>();
+      }
     }
     const C* Lm = lds + sm * ldsw + R;
     const C* Lc = lds + sc * ldsw + R;
@@ -166,6 +206,33 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const SpmmInst* __restric
       o.y = scale * (alpha * ny + beta * c.y) - prv[v].y;
       out[y * rowlen + ev[v]] = o;
       if (copy) copy[y * rowlen + ev[v]] = c;
+      if constexpr (MOM) {
+        const double ox = o.x, oy = o.y, cx = c.x, cy = c.y;
+        if (dpsi) {
+          const double px = p0v[v].x, py = p0v[v].y;
+          acc[0] = fma(px, ox, fma(py, oy, acc[0]));      // conj(psi0) out
+          acc[1] = fma(px, oy, fma(-py, ox, acc[1]));
+          acc[2] = fma(px, cx, fma(py, cy, acc[2]));      // conj(psi0) cur
+          acc[3] = fma(px, cy, fma(-py, cx, acc[3]));
+        }
+        if (dself) {
+          acc[4] = fma(ox, ox, fma(oy, oy, acc[4]));      // |out|^2
+          acc[6] = fma(ox, cx, fma(oy, cy, acc[6]));      // conj(out) cur
+          acc[7] = fma(ox, cy, fma(-oy, cx, acc[7]));
+        }
+        if (cmode) {
+          C b;
+          if (cmode == 1) {
+            b.x = cc0r * c.x - cc0i * c.y;
+            b.y = cc0r * c.y + cc0i * c.x;
+          } else {
+            b = cyv[v];
+          }
+          b.x += ccr * o.x - cci * o.y;
+          b.y += ccr * o.y + cci * o.x;
+          carry[y * rowlen + ev[v]] = b;
+        }
+      }
     }
     if (more) {
       __syncthreads();          // every thread is done with row y-1's slot
@@ -176,29 +243,62 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const SpmmInst* __restric
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) { prv[v] = prvn[v]; ep[v] = epn[v]; }
+    if constexpr (MOM) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) { p0v[v] = p0n[v]; cyv[v] = cyn[v]; }
+    }
+  }
+
+  if constexpr (MOM) {
+    if (dpsi || dself) {
+      // Workgroup sum per column in a fixed order: thread r, r + R, ...
+      __syncthreads();                 // the LDS ring is no longer read
+      double* red = reinterpret_cast<double*>(smem);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) red[k * kSpmmThreads + tid] = acc[k];
+      __syncthreads();
+      double* part = st.partial + (((int64_t)st.mom_slot * st.total_tiles + tile) * 4) *
+                                      (int64_t)st.rmax * 2;
+      for (int q = tid; q < 8 * R; q += kSpmmThreads) {
+        const int k = q / R, r = q - k * R;
+        double sum = 0.0;
+        for (int t = r; t < kSpmmThreads; t += R) sum += red[k * kSpmmThreads + t];
+        // record layout [kind][rmax][re, im]
+        part[((k >> 1) * st.rmax + r) * 2 + (k & 1)] = sum;
+      }
+    }
   }
 }
 
-hipError_t launch_spmm(bool fp64, int vec, const SpmmInst* d_inst, int n_inst,
+hipError_t launch_spmm(bool fp64, int vec, bool mom, const SpmmInst* d_inst, int n_inst,
                        const SpmmStep& st, hipStream_t s) {
   if (st.total_tiles <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(st.total_tiles)), block(kSpmmThreads);
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
-  const size_t lds = 3 * (size_t)(kSpmmThreads * vec + 2 * st.halo) * csz;
+  size_t lds = 3 * (size_t)(kSpmmThreads * vec + 2 * st.halo) * csz;
+  if (mom) lds = std::max(lds, sizeof(double) * 8 * kSpmmThreads);
+#define CSP_SPMM_CASE(T, V, M)                                                              \
+  hipLaunchKernelGGL((k_spmm<T, V, M>), grid, block, lds, s, d_inst, n_inst, st)
   if (fp64) {
-    switch (vec) {
-      case 1: hipLaunchKernelGGL((k_spmm<double, 1>), grid, block, lds, s, d_inst, n_inst, st); break;
-      case 2: hipLaunchKernelGGL((k_spmm<double, 2>), grid, block, lds, s, d_inst, n_inst, st); break;
+    switch (vec * 2 + (mom ? 1 : 0)) {
+      case 2: CSP_SPMM_CASE(double, 1, false); break;
+      case 3: CSP_SPMM_CASE(double, 1, true); break;
+      case 4: CSP_SPMM_CASE(double, 2, false); break;
+      case 5: CSP_SPMM_CASE(double, 2, true); break;
       default: return hipErrorInvalidValue;
     }
   } else {
-    switch (vec) {
-      case 1: hipLaunchKernelGGL((k_spmm<float, 1>), grid, block, lds, s, d_inst, n_inst, st); break;
-      case 2: hipLaunchKernelGGL((k_spmm<float, 2>), grid, block, lds, s, d_inst, n_inst, st); break;
-      case 4: hipLaunchKernelGGL((k_spmm<float, 4>), grid, block, lds, s, d_inst, n_inst, st); break;
+    switch (vec * 2 + (mom ? 1 : 0)) {
+      case 2: CSP_SPMM_CASE(float, 1, false); break;
+      case 3: CSP_SPMM_CASE(float, 1, true); break;
+      case 4: CSP_SPMM_CASE(float, 2, false); break;
+      case 5: CSP_SPMM_CASE(float, 2, true); break;
+      case 8: CSP_SPMM_CASE(float, 4, false); break;
+      case 9: CSP_SPMM_CASE(float, 4, true); break;
       default: return hipErrorInvalidValue;
     }
   }
+#undef CSP_SPMM_CASE
   return hipGetLastError();
 }
 

@@ -109,3 +109,24 @@ def test_fp64_sequential_full_size(csp, setup):
     err = np.max(np.abs(corr.cpu().numpy() - setup["ref_rand"]))
     print("[gpu-full] eps_inf %.3e" % err, flush=True)
     assert err < 1e-10
+
+
+def test_fp32_moments_single_block_full_size(csp, setup):
+    # DOS-Concurrent-M of Sec. III: one block of 2048 steps, halving
+    print("[gpu-full] complex64 moments, one block, halving, R = 68", flush=True)
+    ctx, lat, psi = setup["ctx"], setup["lat"], setup["psi"]
+    params = csp.make_params(NT, mode="fp32_conc", block_b=0, assembly=csp.CSP_ASSEMBLE_MOMENTS)
+    corr, rep = csp.csp_propagate(ctx, lat, psi, params)
+    torch.cuda.synchronize()
+    Nfull = o.truncation(NT * math.pi)
+    assert rep.amxsy == (Nfull + 1) // 2 and rep.dot == Nfull
+    c = corr.cpu().numpy()
+    err_rand = np.max(np.abs(c[:, :R_RAND] - setup["ref_rand"]))
+    err_ldos = np.max(np.abs(c[:, R_RAND:] - setup["ref_ldos"][:, None]))
+    print("[gpu-full] moments eps_inf random %.3e, ldos %.3e" % (err_rand, err_ldos), flush=True)
+    assert err_rand < 2e-5 and err_ldos < 2e-5
+    e_dos = rel_dos_err(c[:, :R_RAND], setup["ref_rand"], lat.halfwidth)
+    e_ldos = rel_dos_err(c[:, R_RAND:], np.repeat(setup["ref_ldos"][:, None], N_SITES, 1),
+                         lat.halfwidth)
+    print("[gpu-full] moments relative DOS error %.3e, LDOS %.3e" % (e_dos, e_ldos), flush=True)
+    assert e_dos < 1e-4 and e_ldos < 1e-4

@@ -279,3 +279,93 @@ def test_error_paths(csp, ctx):
     psi[0, 0] = 1.0
     corr, _ = csp.csp_propagate(ctx, g, psi, csp.make_params(0, mode="fp32_conc", block_b=4))
     assert host(corr).shape == (1, 1) and host(corr)[0, 0] == 1.0
+
+
+# ---------------------------------------------------------------- moment form
+def run_gpu_moments(csp, ctx, g, psi, Nt, mode, b=0, final=False):
+    tdt = torch.complex128 if mode != "fp32_conc" else torch.complex64
+    p = dev(psi).to(tdt)
+    params = csp.make_params(Nt, mode=mode, block_b=b, assembly=csp.CSP_ASSEMBLE_MOMENTS)
+    fin = torch.zeros_like(p) if final else None
+    corr, rep = csp.csp_propagate(ctx, g, p, params, final=fin)
+    return host(corr), rep, (host(fin) if final else None)
+
+
+@pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
+@pytest.mark.parametrize("b", [0, 16, 7, 200])
+def test_moments_match_oracle(csp, ctx, mode, b):
+    print("[gpu] moments %s b=%d" % (mode, b), flush=True)
+    spec = dict(kind="honeycomb", Lx=24, Ly=20, t=-2.7, W=1.0, disorder_seed=4)
+    g, c = pair(csp, ctx, spec)
+    psi = np.concatenate([o.random_phase_states_fast(c.N, 3, 5),
+                          o.site_states(c.N, o.ldos_sites(c.N, 2, 3))], axis=1)   # groups 4 + 1
+    Nt = 200
+    ref, cnt = o.propagate_moments(c, psi, Nt, b=(None if b in (0, 200) else b),
+                                   halving=b in (0, 200))
+    seq, _ = o.propagate(c, psi, Nt, b=0)
+    assert np.max(np.abs(ref - seq)) < 1e-12
+    got, rep, _ = run_gpu_moments(csp, ctx, g, psi, Nt, mode, b=b)
+    R = psi.shape[1]
+    assert rep.amxsy * R == cnt["amxsy"] and rep.dot * R == cnt["dot"]
+    if mode == "fp64_conc":
+        assert np.max(np.abs(got - ref)) < 1e-10
+    else:
+        assert np.max(np.abs(got - ref)) < 2e-5
+        assert rel_dos_err(got, ref, g.halfwidth) < 1e-4
+
+
+def test_moments_sequential_mode_and_final_state(csp, ctx):
+    g, c = pair(csp, ctx, dict(kind="square", Lx=30, Ly=20, t=1.0, W=1.0, disorder_seed=1))
+    psi = o.random_phase_states_fast(c.N, 2, 4)
+    ref, _, fin_ref = o.propagate(c, psi, 50, b=0, return_final=True)
+    got, rep, fin = run_gpu_moments(csp, ctx, g, psi, 50, "fp64_seq", final=True)
+    assert rep.block_b == 1 and rep.amxsy == 50 * 20
+    assert np.max(np.abs(got - ref)) < 1e-10
+    assert np.max(np.abs(fin - fin_ref)) < 1e-10
+    # one block with a final state: no halving, carry over all orders
+    got, rep, fin = run_gpu_moments(csp, ctx, g, psi, 50, "fp64_conc", final=True)
+    assert rep.amxsy == o.truncation(50 * math.pi)
+    assert np.max(np.abs(got - ref)) < 1e-10
+    assert np.max(np.abs(fin - fin_ref)) < 1e-10
+
+
+@pytest.mark.parametrize("mode,tol", [("fp64_conc", 1e-12), ("fp32_conc", 2e-5)])
+def test_state_and_moment_assembly_agree(csp, ctx, mode, tol):
+    # the reduction <psi0|.> commutes with the block contraction: assembling
+    # the states on MFMA and contracting the block moments give the same
+    # correlations up to rounding
+    g, c = pair(csp, ctx, dict(kind="square", Lx=41, Ly=33, t=1.0, W=0.5, disorder_seed=7))
+    psi = o.random_phase_states_fast(c.N, 4, 9)
+    Nt = 160
+    b = 16
+    s_corr, _, _ = run_gpu(csp, ctx, g, psi, Nt, mode, b=b)
+    m_corr, _, _ = run_gpu_moments(csp, ctx, g, psi, Nt, mode, b=b)
+    assert np.max(np.abs(s_corr - m_corr)) < tol
+
+
+# ---------------------------------------------------------------- norm guard
+@pytest.mark.parametrize("mode,assembly,b", [("fp32_conc", 0, 16), ("fp32_conc", 1, 16),
+                                             ("fp32_conc", 1, 0), ("fp64_seq", 0, 1)])
+def test_norm_guard(csp, ctx, mode, assembly, b):
+    g, c = pair(csp, ctx, dict(kind="honeycomb", Lx=16, Ly=12, t=-2.7, W=1.0, disorder_seed=2))
+    psi = o.random_phase_states_fast(c.N, 3, 1)
+    tdt = torch.complex128 if mode != "fp32_conc" else torch.complex64
+    Nt = 64
+    ok = csp.make_params(Nt, mode=mode, block_b=b, assembly=assembly, check_norm=True)
+    corr, _ = csp.csp_propagate(ctx, g, dev(psi).to(tdt), ok)
+    ref, _ = o.propagate(c, psi, Nt, b=0)
+    assert np.max(np.abs(host(corr) - ref)) < 2e-5
+    # a non-finite input value is caught after the first block
+    bad = psi.copy()
+    bad[7, 1] = np.nan
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_propagate(ctx, g, dev(bad).to(tdt), ok)
+    assert e.value.status == csp.CSP_ENUMERIC and "block 0" in str(e.value)
+    # a tolerance below the rounding of the path trips the guard too (forced
+    # from the host; the kernels run normally)
+    if mode == "fp32_conc" and b > 0:
+        tight = csp.make_params(Nt, mode=mode, block_b=b, assembly=assembly, check_norm=True,
+                                norm_tol=1e-14)
+        with pytest.raises(csp.CspError) as e:
+            csp.csp_propagate(ctx, g, dev(psi).to(tdt), tight)
+        assert e.value.status == csp.CSP_ENUMERIC
