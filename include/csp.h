@@ -136,6 +136,14 @@ typedef struct {
                                   a violation makes the call return
                                   CSP_ENUMERIC naming the first failing block */
     double norm_tol;           /* relative tolerance of the guard; 0 -> 1e-3 */
+    int32_t graph;             /* state assembly: capture one time block's
+                                  launches in a HIP graph and replay it for
+                                  every full block; 0 = on for
+                                  csp_propagate_batch, off for csp_propagate;
+                                  1 = on; -1 = off.  Ignored when profile is
+                                  set.  If capture fails the launches are
+                                  issued directly (same results). */
+    int32_t reserved1;
 } csp_params;
 
 /* What a propagation did.  Operation counts are per state column and follow
@@ -155,7 +163,29 @@ typedef struct {
     double contract_flops;     /* MFMA (or FMA) flops of all contractions */
     uint64_t workspace_bytes;
     double model_cost[8];      /* selection-rule cost of b = 1,2,4,...,128 */
+    int32_t graph_blocks;      /* time blocks replayed from a HIP graph */
+    int32_t reserved;
 } csp_report;
+
+/* Launch shapes and time-block size measured by csp_autotune. */
+typedef struct {
+    int32_t spmm_vec;          /* complex values per thread and row in a
+                                  recursion strip (strip = 256 * vec) */
+    int32_t spmm_seg_rows;     /* lattice rows per recursion workgroup */
+    int32_t contract_wg_per_cu;/* contraction workgroups per compute unit */
+    int32_t block_b;           /* time-block size from the cost model (state
+                                  assembly; 0 for the moment assembly, which
+                                  always runs one block) */
+    double t_amxsy_us;         /* one recursion step over all columns, best
+                                  shape */
+    double t_order_us[2];      /* contraction time per Chebyshev order for
+                                  b <= 32 and b <= 64 (state assembly) */
+    double model_cost_ms[8];   /* modelled propagation time at
+                                  b = 1, 2, 4, ..., 128; -1 where b is not
+                                  allowed or does not fit */
+    int32_t n_candidates;      /* recursion shapes timed */
+    int32_t reserved;
+} csp_tuning;
 
 typedef struct csp_context csp_context;
 typedef struct csp_lattice csp_lattice;
@@ -234,7 +264,9 @@ csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *d
  * states dev_psi0[i] ([N_i][R[i]]) and correlations dev_corr[i]
  * ([(Nt+1)][R[i]]).  Every instance uses the same params (Nt, mode, b); the
  * recursion of all instances is one launch per Chebyshev step and the
- * contraction one launch per chunk, captured in a HIP graph per block. */
+ * contraction one launch per chunk; with the state assembly one time
+ * block's launches are captured in a HIP graph and replayed per block
+ * (params->graph). */
 csp_status csp_propagate_batch(csp_context *ctx, int32_t n_inst, const csp_lattice *const *lats,
                                const void *const *dev_psi0, const int32_t *R,
                                const csp_params *params, double *const *dev_corr,
@@ -250,10 +282,29 @@ csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t
                    double halfwidth, double tau_tilde, int32_t window, double *dev_E,
                    double *dev_D, double *dev_Dmean);
 
-/* Time-block size from the cost model of Sec. II.B,
- * C(b) = N_amxsy(b) t_amxsy + N_axpy(b) t_axpy, minimised over b subject to
- * the workspace fitting mem_cap; t_amxsy and t_axpy are measured on this
- * device for this lattice and R (cached in the context). */
+/* Autotuner.  For the instances (lats[i], R[i]) with params->mode and
+ * params->assembly, times on this device every recursion launch shape
+ * (vec in {1, 2, 4}, rows per workgroup in {2, ..., 128}) and, for the state
+ * assembly, the contraction at 2, 4 and 8 workgroups per compute unit for
+ * time tiles of 32 and 64, then picks the time-block size b by the cost
+ * model of Sec. II.B with measured operation costs:
+ *   C(b) = sum over blocks k [ N_k t_amxsy + (N_k + 1) t_order(b) ],
+ * N_k = N(b_k tau) (the last block is shorter when b does not divide Nt).
+ * This is the paper's C = N_amxsy t_amxsy + N_axpy t_axpy with the axpy term
+ * replaced by what it costs here: one MFMA pass over a Chebyshev vector
+ * performs the axpys of that order for every time point of the block.
+ * Only b whose workspace fits params->mem_cap_bytes are allowed.  The
+ * result is cached in the context under the instances' shape (lattice
+ * kinds and sizes, column groups, precision, assembly); csp_propagate and
+ * csp_propagate_batch use a cached entry for their shape: its launch shapes
+ * always, its b when params->block_b is 0.  The states and correlation
+ * buffers of the caller are not touched (the timing uses workspace). */
+csp_status csp_autotune(csp_context *ctx, int32_t n_inst, const csp_lattice *const *lats,
+                        const int32_t *R, const csp_params *params, csp_tuning *out);
+
+/* Time-block size of csp_autotune for one lattice with R columns: runs the
+ * autotuner (or takes its cached entry) and returns its block_b; rep (may be
+ * NULL) receives the model costs in model_cost. */
 csp_status csp_select_block(csp_context *ctx, const csp_lattice *lat, int32_t R,
                             const csp_params *params, int32_t *b_out, csp_report *rep);
 

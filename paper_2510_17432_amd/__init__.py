@@ -65,7 +65,8 @@ class Params(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("assembly", ctypes.c_int32),
                 ("block_b", ctypes.c_int32), ("chunk_K", ctypes.c_int32),
                 ("mem_cap_bytes", ctypes.c_uint64), ("profile", ctypes.c_int32),
-                ("check_norm", ctypes.c_int32), ("norm_tol", ctypes.c_double)]
+                ("check_norm", ctypes.c_int32), ("norm_tol", ctypes.c_double),
+                ("graph", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -76,11 +77,27 @@ class Report(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_spmm", ctypes.c_double),
                 ("ms_contract", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
                 ("contract_bytes", ctypes.c_double), ("contract_flops", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_uint64), ("model_cost", ctypes.c_double * 8)]
+                ("workspace_bytes", ctypes.c_uint64), ("model_cost", ctypes.c_double * 8),
+                ("graph_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "model_cost"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("model_cost", "reserved")}
         d["model_cost"] = list(self.model_cost)
+        return d
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("spmm_vec", ctypes.c_int32), ("spmm_seg_rows", ctypes.c_int32),
+                ("contract_wg_per_cu", ctypes.c_int32), ("block_b", ctypes.c_int32),
+                ("t_amxsy_us", ctypes.c_double), ("t_order_us", ctypes.c_double * 2),
+                ("model_cost_ms", ctypes.c_double * 8), ("n_candidates", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("t_order_us", "model_cost_ms", "reserved")}
+        d["t_order_us"] = list(self.t_order_us)
+        d["model_cost_ms"] = list(self.model_cost_ms)
         return d
 
 
@@ -119,6 +136,7 @@ _sig("csp_propagate_batch", [_vp, ctypes.c_int32, _P(_vp), _P(_vp), _P(ctypes.c_
 _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                  ctypes.c_int32, _vp, _vp, _vp])
 _sig("csp_select_block", [_vp, _vp, ctypes.c_int32, _P(Params), _P(ctypes.c_int32), _P(Report)])
+_sig("csp_autotune", [_vp, ctypes.c_int32, _P(_vp), _P(ctypes.c_int32), _P(Params), _P(Tuning)])
 
 
 def _check(rc):
@@ -294,7 +312,7 @@ def csp_chebyshev_step(ctx, lat, x, y, first=False):
 
 def make_params(Nt, mode="fp32_conc", block_b=0, chunk_K=0, tau_tilde=math.pi, eta=1e-14,
                 assembly=CSP_ASSEMBLE_STATES, mem_cap_bytes=0, profile=False, check_norm=False,
-                norm_tol=0.0):
+                norm_tol=0.0, graph=0):
     p = Params()
     p.Nt = int(Nt)
     p.tau_tilde = float(tau_tilde)
@@ -307,6 +325,7 @@ def make_params(Nt, mode="fp32_conc", block_b=0, chunk_K=0, tau_tilde=math.pi, e
     p.profile = int(bool(profile))
     p.check_norm = int(bool(check_norm))
     p.norm_tol = float(norm_tol)
+    p.graph = int(graph)
     return p
 
 
@@ -358,3 +377,14 @@ def csp_select_block(ctx, lat, R, params):
     _check(_lib.csp_select_block(ctx.handle, lat.handle, R, ctypes.byref(params),
                                  ctypes.byref(b), ctypes.byref(rep)))
     return b.value, rep
+
+
+def csp_autotune(ctx, lats, Rs, params):
+    """Measure launch shapes and the block size for these instances (cached in
+    the context for later propagations of the same shape)."""
+    n = len(lats)
+    L = (ctypes.c_void_p * n)(*[l.handle.value for l in lats])
+    Rv = (ctypes.c_int32 * n)(*[int(r) for r in Rs])
+    t = Tuning()
+    _check(_lib.csp_autotune(ctx.handle, n, L, Rv, ctypes.byref(params), ctypes.byref(t)))
+    return t

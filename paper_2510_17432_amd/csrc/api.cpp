@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -75,7 +76,8 @@ struct csp_context {
   void* ws = nullptr;
   size_t ws_size = 0;
   std::vector<hipEvent_t> events;   // pool for profiling
-  std::map<std::string, std::pair<double, double>> calib;  // t_amxsy, t_axpy per shape
+  std::map<std::string, csp_tuning> tuned;  // autotuner results per shape
+  hipStream_t cap = nullptr;                 // library stream for HIP graph capture
 };
 
 struct csp_lattice {
@@ -128,6 +130,14 @@ csp_status hip_event(csp_context* c, size_t i, hipEvent_t* out) {
     c->events.push_back(e);
   }
   *out = c->events[i];
+  return CSP_OK;
+}
+
+// The library's own stream, used only to capture HIP graphs (capture is not
+// allowed on the legacy null stream a caller may have given).  Default
+// priority, non-blocking.
+csp_status capture_stream(csp_context* c) {
+  if (!c->cap) HIPCALL(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   return CSP_OK;
 }
 
@@ -194,6 +204,7 @@ extern "C" csp_status csp_context_destroy(csp_context* c) {
   DeviceGuard dg(c->device);
   csp_status st = csp_context_trim(c);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
   return st;
 }
@@ -362,8 +373,10 @@ struct SpmmPlan {
   int64_t total_tiles = 0;
 };
 
-// Fill tiling fields of the instances and choose vector width / segment rows.
-SpmmPlan plan_spmm(std::vector<SpmmInst>& insts, bool fp64, int n_cu) {
+// Fill tiling fields of the instances and choose vector width / segment rows
+// (vec_force / seg_force > 0: use those, as measured by the autotuner).
+SpmmPlan plan_spmm(std::vector<SpmmInst>& insts, bool fp64, int n_cu, int vec_force = 0,
+                   int seg_force = 0) {
   SpmmPlan p;
   int64_t minrow = INT64_MAX;
   for (auto& I : insts) {
@@ -373,6 +386,7 @@ SpmmPlan plan_spmm(std::vector<SpmmInst>& insts, bool fp64, int n_cu) {
   p.vec = 1;
   const int vmax = fp64 ? 2 : 4;
   while (p.vec < vmax && (int64_t)kSpmmThreads * p.vec * 2 <= minrow) p.vec *= 2;
+  if (vec_force > 0) p.vec = std::min(vec_force, vmax);
   const int W = kSpmmThreads * p.vec;
   const int64_t target = (int64_t)n_cu * 8;
   int seg = 32;
@@ -382,6 +396,7 @@ SpmmPlan plan_spmm(std::vector<SpmmInst>& insts, bool fp64, int n_cu) {
     return t;
   };
   while (seg > 4 && count(seg) < target) seg /= 2;
+  if (seg_force > 0) seg = seg_force;
   p.seg_rows = seg;
   int64_t t0 = 0;
   for (auto& I : insts) {
@@ -495,6 +510,27 @@ std::vector<int> split_columns(int R) {
   return g;
 }
 
+// Key of the autotuner cache: precision, assembly and, per instance, the
+// lattice shape and column count (which fixes the column groups).
+std::string shape_key(const std::vector<InstIn>& ins, bool fp64, int assembly) {
+  std::string k = fp64 ? "d" : "f";
+  k += assembly == CSP_ASSEMBLE_MOMENTS ? "m" : "s";
+  char buf[160];
+  for (auto& in : ins) {
+    const Geom& g = in.lat->g;
+    snprintf(buf, sizeof(buf), "|%d:%lld:%lld:%d%d:%d:%d", g.kind, (long long)g.Lx,
+             (long long)g.Ly, g.px, g.py, in.lat->has_onsite ? 1 : 0, in.R);
+    k += buf;
+  }
+  return k;
+}
+
+const csp_tuning* find_tuning(const csp_context* c, const std::vector<InstIn>& ins, bool fp64,
+                              int assembly) {
+  auto it = c->tuned.find(shape_key(ins, fp64, assembly));
+  return it == c->tuned.end() ? nullptr : &it->second;
+}
+
 void fill_defaults(const csp_params* in, csp_params* p) {
   *p = *in;
   if (!(p->tau_tilde > 0)) p->tau_tilde = M_PI;
@@ -568,7 +604,7 @@ int select_b_rule(const std::vector<int32_t>& ntr_all, int bmax, int64_t Nt, dou
 }  // namespace
 
 static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
-                                 const csp_params* params_in, csp_report* rep);
+                                 const csp_params* params_in, csp_report* rep, bool batch_call);
 
 extern "C" csp_status csp_propagate(csp_context* c, const csp_lattice* L, const void* dev_psi0,
                                     int32_t R, const csp_params* params, double* dev_corr,
@@ -576,7 +612,7 @@ extern "C" csp_status csp_propagate(csp_context* c, const csp_lattice* L, const 
   if (!c || !L || !dev_psi0 || !params || !dev_corr) return fail(CSP_EINVAL, "NULL argument");
   std::vector<InstIn> ins(1);
   ins[0] = {L, dev_psi0, R, dev_corr, dev_final};
-  return propagate_impl(c, ins, params, rep);
+  return propagate_impl(c, ins, params, rep, false);
 }
 
 extern "C" csp_status csp_propagate_batch(csp_context* c, int32_t n_inst,
@@ -591,14 +627,14 @@ extern "C" csp_status csp_propagate_batch(csp_context* c, int32_t n_inst,
     if (!lats[i] || !dev_psi0[i] || !dev_corr[i]) return fail(CSP_EINVAL, "instance %d NULL", i);
     ins[i] = {lats[i], dev_psi0[i], R[i], dev_corr[i], nullptr};
   }
-  return propagate_impl(c, ins, params, rep);
+  return propagate_impl(c, ins, params, rep, true);
 }
 
 static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstIn>& ins,
                                          const csp_params& P, double t_start, csp_report* rep);
 
 static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
-                                 const csp_params* params_in, csp_report* rep) {
+                                 const csp_params* params_in, csp_report* rep, bool batch_call) {
   const double t_start = now_ms();
   csp_params P;
   fill_defaults(params_in, &P);
@@ -666,7 +702,8 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   const size_t avail = freeb + c->ws_size;
   const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
   const size_t vec_bytes = (size_t)vec_elems * csz + 256 * groups.size();
-  const int total_wg_target = c->n_cu * 4;
+  const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_STATES);
+  const int total_wg_target = c->n_cu * (tune ? tune->contract_wg_per_cu : 4);
   const size_t fixed_guess = 2 * vec_bytes + (size_t)total_wg_target * 64 * 32 * 16 + (64u << 20);
 
   auto fits_b = [&](int bb) {
@@ -674,21 +711,16 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     const int need = std::min(ntr[bb - 1] + 1, 16);
     return fixed_guess + (size_t)need * vec_bytes <= cap;
   };
-  if (b == 0) {
+  if (b == 0 && tune && tune->block_b > 0 && tune->block_b <= bmax && fits_b(tune->block_b)) {
+    b = tune->block_b;   // measured by csp_autotune for this shape
+    if (rep)
+      for (int k = 0; k < 8; ++k) rep->model_cost[k] = tune->model_cost_ms[k];
+  } else if (b == 0) {
     std::vector<bool> fits(bmax + 1, false);
     for (int bb = 1; bb <= bmax; ++bb) fits[bb] = fits_b(bb);
-    // Cost constants: one recursion step streams 3 vectors; one (n, j) pair of
-    // the contraction costs a fraction of a vector pass (measured per device
-    // when csp_select_block has calibrated this shape, else the byte model).
-    double ta = 3.0, tp = 1.0 / 32.0;
-    char key[128];
-    snprintf(key, sizeof(key), "%d:%lld:%d", (int)fp64, (long long)vec_elems, (int)groups.size());
-    auto it = c->calib.find(key);
-    if (it != c->calib.end()) {
-      ta = it->second.first;
-      tp = it->second.second;
-    }
-    b = select_b_rule(ntr, bmax, Nt, ta, tp, fits, rep ? rep->model_cost : nullptr);
+    // Without a measurement: the byte model (a recursion step streams 3
+    // vectors, one (n, j) pair of the contraction about 1/32 of a vector).
+    b = select_b_rule(ntr, bmax, Nt, 3.0, 1.0 / 32.0, fits, rep ? rep->model_cost : nullptr);
   }
   if (Nt > 0) b = (int)std::min<int64_t>(b, Nt);
   b = std::max(b, 1);
@@ -757,7 +789,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   }
   const size_t n_sd = 256;   // self-dot partial blocks
   need += align256(sizeof(double) * n_sd * kMaxGroupCols);
-  need += align256(2 * sizeof(int));
+  need += align256(2 * sizeof(int)) + align256(2 * sizeof(int64_t));
   need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size()) +
           align256(sizeof(FinishInst) * groups.size());
   if (need > cap) return fail(CSP_ENOMEM, "workspace %.2f GB exceeds the cap %.2f GB", need / 1e9, cap / 1e9);
@@ -783,6 +815,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   }
   double* d_sd = (double*)cv.take(sizeof(double) * n_sd * kMaxGroupCols);
   int* d_flag = (int*)cv.take(2 * sizeof(int));
+  int64_t* d_blk = (int64_t*)cv.take(2 * sizeof(int64_t));
   SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
   ContractInst* d_con = (ContractInst*)cv.take(sizeof(ContractInst) * groups.size());
   FinishInst* d_fin = (FinishInst*)cv.take(sizeof(FinishInst) * groups.size());
@@ -820,7 +853,8 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     F.col0 = g.col0;
     fi.push_back(F);
   }
-  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu);
+  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu, tune ? tune->spmm_vec : 0,
+                               tune ? tune->spmm_seg_rows : 0);
   HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(SpmmInst) * sp.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_con, ct.data(), sizeof(ContractInst) * ct.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_fin, fi.data(), sizeof(FinishInst) * fi.size(), hipMemcpyHostToDevice, s));
@@ -857,82 +891,146 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   st.halo = sp_plan.halo;
   st.total_tiles = sp_plan.total_tiles;
 
-  for (int64_t t0 = 0; t0 < Nt; t0 += b) {
-    const int bk = (int)std::min<int64_t>(b, Nt - t0);
-    const BlockTab& T = (bk == b) ? btabs[0] : btabs.back();
+  // One time block: recursion steps with the contractions of each chunk of
+  // orders as soon as its last order exists, the workgroup-partial sum and
+  // the norm guard.  t0_dev: the block's time index and number come from the
+  // device counter (graph replays), which the block then advances.
+  auto enqueue_block = [&](const BlockTab& T, int bk, int64_t t0, hipStream_t strm,
+                           bool from_dev) -> csp_status {
     const int Nk = T.Nk;
-    amxsy += Nk;
-    for (int j = 1; j <= bk; ++j) axpy += ntr[j - 1];
     size_t ev = 0;
-    CHECK(prof.begin(0, &ev));
+    if (!from_dev) CHECK(prof.begin(0, &ev));
     // order 1 from the carried state (also stored as order 0)
-    st.slot_out = 1 % S;
-    st.slot_cur = 0;
-    st.slot_prev = 0;
-    st.cur_from_src = 1;
-    st.copy_cur = 1;
-    st.has_prev = 0;
-    st.scale_f = 0.5f;
-    st.scale_d = 0.5;
-    HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), st, s));
-    ++n_spmm;
-    spmm_bytes += step_bytes;
+    SpmmStep stb = st;
+    stb.slot_out = 1 % S;
+    stb.slot_cur = 0;
+    stb.slot_prev = 0;
+    stb.cur_from_src = 1;
+    stb.copy_cur = 1;
+    stb.has_prev = 0;
+    stb.scale_f = 0.5f;
+    stb.scale_d = 0.5;
+    HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), stb, strm));
     size_t ci = 0;
     int produced = 1;
+    ContractArgs cab = ca;
     auto run_chunks = [&]() -> csp_status {
       while (ci < T.chunks.size() && T.chunks[ci].n_lo + T.chunks[ci].n_cnt - 1 <= produced) {
         const ChunkTab& ch = T.chunks[ci];
-        CHECK(prof.end(ev));
         size_t evc = 0;
-        CHECK(prof.begin(1, &evc));
-        ca.n_lo = ch.n_lo;
-        ca.n_cnt = ch.n_cnt;
-        ca.first_chunk = ci == 0 ? 1 : 0;
-        ca.bcols = bk;
-        if (fp64) {
-          ca.coef = ch.coef;
-          ca.ccarry = ch.ccd;
-          HIPCALL(launch_contract_f64(d_con, ca, s));
-          con_flops += 8.0 * (double)vec_elems * ch.n_cnt * (bk + 1);
-        } else {
-          ca.bop = ch.bop;
-          ca.ccarry = ch.ccf;
-          HIPCALL(launch_contract_f32(d_con, ca, s));
-          con_flops += 2.0 * 6.0 * 32.0 * 32.0 * 16.0 * jtiles * (double)ceil_div(ch.n_cnt, 16) *
-                       (double)ceil_div(vec_elems, 32);
+        if (!from_dev) {
+          CHECK(prof.end(ev));
+          CHECK(prof.begin(1, &evc));
         }
-        ++n_con;
-        con_bytes += (double)vec_elems * csz * (ch.n_cnt + 2 + (ci == 0 ? 0 : 1));
-        CHECK(prof.end(evc));
-        CHECK(prof.begin(0, &ev));
+        cab.n_lo = ch.n_lo;
+        cab.n_cnt = ch.n_cnt;
+        cab.first_chunk = ci == 0 ? 1 : 0;
+        cab.bcols = bk;
+        if (fp64) {
+          cab.coef = ch.coef;
+          cab.ccarry = ch.ccd;
+          HIPCALL(launch_contract_f64(d_con, cab, strm));
+        } else {
+          cab.bop = ch.bop;
+          cab.ccarry = ch.ccf;
+          HIPCALL(launch_contract_f32(d_con, cab, strm));
+        }
+        if (!from_dev) {
+          CHECK(prof.end(evc));
+          CHECK(prof.begin(0, &ev));
+        }
         ++ci;
       }
       return CSP_OK;
     };
     CHECK(run_chunks());
     for (int n = 1; n < Nk; ++n) {
-      st.slot_out = (n + 1) % S;
-      st.slot_cur = n % S;
-      st.slot_prev = (n - 1) % S;
-      st.cur_from_src = 0;
-      st.copy_cur = 0;
-      st.has_prev = 1;
-      st.scale_f = 1.0f;
-      st.scale_d = 1.0;
-      HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), st, s));
-      ++n_spmm;
-      spmm_bytes += step_bytes;
+      stb.slot_out = (n + 1) % S;
+      stb.slot_cur = n % S;
+      stb.slot_prev = (n - 1) % S;
+      stb.cur_from_src = 0;
+      stb.copy_cur = 0;
+      stb.has_prev = 1;
+      stb.scale_f = 1.0f;
+      stb.scale_d = 1.0;
+      HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), stb, strm));
       produced = n + 1;
       CHECK(run_chunks());
     }
-    CHECK(prof.end(ev));
-    HIPCALL(launch_finish(d_fin, (int)fi.size(), bk, t0, s));
+    if (!from_dev) CHECK(prof.end(ev));
+    HIPCALL(launch_finish(d_fin, (int)fi.size(), bk, t0, from_dev ? d_blk : nullptr, strm));
     if (P.check_norm) {
       for (auto& g : groups) {
         const InstIn& in = ins[g.inst];
         HIPCALL(launch_guard(in.lat->g.N, g.Rg, g.carry, fp64, in.corr, in.R, g.col0, t0, bk,
-                             P.norm_tol, (int)(t0 / b), d_flag, d_sd, (int)n_sd, s));
+                             P.norm_tol, (int)(t0 / b), from_dev ? d_blk : nullptr, d_flag, d_sd,
+                             (int)n_sd, strm));
       }
+    }
+    if (from_dev) HIPCALL(launch_advance(d_blk, b, strm));
+    return CSP_OK;
+  };
+  auto count_block = [&](const BlockTab& T, int bk) {
+    const int Nk = T.Nk;
+    amxsy += Nk;
+    for (int j = 1; j <= bk; ++j) axpy += ntr[j - 1];
+    n_spmm += Nk;
+    spmm_bytes += step_bytes * Nk;
+    for (size_t ci = 0; ci < T.chunks.size(); ++ci) {
+      const ChunkTab& ch = T.chunks[ci];
+      ++n_con;
+      con_bytes += (double)vec_elems * csz * (ch.n_cnt + 2 + (ci == 0 ? 0 : 1));
+      con_flops += fp64 ? 8.0 * (double)vec_elems * ch.n_cnt * (bk + 1)
+                        : 2.0 * 6.0 * 32.0 * 32.0 * 16.0 * jtiles *
+                              (double)ceil_div(ch.n_cnt, 16) * (double)ceil_div(vec_elems, 32);
+    }
+  };
+
+  // Graph replay of the full blocks (state assembly), unless profiling.
+  const int64_t n_full = Nt / b;
+  bool use_graph = !prof.on && n_full >= 2 &&
+                   (P.graph > 0 || (P.graph == 0 && ins.size() > 1 && batch_call));
+  hipGraphExec_t gexec = nullptr;
+  if (use_graph) {
+    const char* force = std::getenv("CSP_FORCE_GRAPH_FAILURE");
+    hipGraph_t graph = nullptr;
+    bool ok = !(force && force[0] == '1');
+    if (ok) ok = capture_stream(c) == CSP_OK;
+    if (ok) {
+      static const int64_t blk0[2] = {0, 0};
+      ok = hipMemcpyAsync(d_blk, blk0, sizeof(blk0), hipMemcpyHostToDevice, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+    }
+    if (ok) ok = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      const csp_status st_cap = enqueue_block(btabs[0], (int)b, 0, c->cap, true);
+      const bool end_ok = hipStreamEndCapture(c->cap, &graph) == hipSuccess;
+      ok = st_cap == CSP_OK && end_ok && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      (void)hipGetLastError();
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+      use_graph = false;   // issue the launches directly
+    }
+  }
+  struct ExecGuard {
+    hipGraphExec_t e;
+    ~ExecGuard() { if (e) (void)hipGraphExecDestroy(e); }
+  } exec_guard{gexec};
+
+  int graph_blocks = 0;
+  for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+    const int bk = (int)std::min<int64_t>(b, Nt - t0);
+    const BlockTab& T = (bk == b) ? btabs[0] : btabs.back();
+    count_block(T, bk);
+    if (use_graph && bk == b) {
+      HIPCALL(hipGraphLaunch(gexec, s));
+      ++graph_blocks;
+    } else {
+      CHECK(enqueue_block(T, bk, t0, s, false));
     }
   }
 
@@ -965,6 +1063,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     rep->contract_bytes = con_bytes;
     rep->contract_flops = con_flops;
     rep->workspace_bytes = c->ws_size;
+    rep->graph_blocks = graph_blocks;
   }
   return CSP_OK;
 }
@@ -1053,7 +1152,9 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   }
   std::vector<SpmmInst> sp;
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
-  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu);
+  const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_MOMENTS);
+  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu, tune ? tune->spmm_vec : 0,
+                               tune ? tune->spmm_seg_rows : 0);
   const int P_batch = 16;
 
   // Workspace.
@@ -1221,7 +1322,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         const InstIn& in = ins[g.inst];
         const void* cy = carry ? (cur_carry == 0 ? carry_b[gi] : carry_a[gi]) : nullptr;
         HIPCALL(launch_guard(in.lat->g.N, g.Rg, cy, fp64, in.corr, in.R, g.col0, t0, bk,
-                             P.norm_tol, (int)(t0 / b), d_flag, d_sd, 256, s));
+                             P.norm_tol, (int)(t0 / b), nullptr, d_flag, d_sd, 256, s));
       }
     }
     if (carry) cur_carry ^= 1;
@@ -1279,9 +1380,349 @@ extern "C" csp_status csp_dos(csp_context* c, const double* dev_corr, int64_t Nt
   return CSP_OK;
 }
 
-// ------------------------------------------------------------------ block selection
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+// Median of three launch times (ms) of `launch`, after one untimed launch.
+template <typename F>
+csp_status time_launch(csp_context* c, F launch, double* ms_out) {
+  hipStream_t s = c->stream;
+  CHECK(launch());
+  double v[3];
+  for (int i = 0; i < 3; ++i) {
+    hipEvent_t e0, e1;
+    CHECK(hip_event(c, 2 * i, &e0));
+    CHECK(hip_event(c, 2 * i + 1, &e1));
+    HIPCALL(hipEventRecord(e0, s));
+    CHECK(launch());
+    HIPCALL(hipEventRecord(e1, s));
+    HIPCALL(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCALL(hipEventElapsedTime(&ms, e0, e1));
+    v[i] = ms;
+  }
+  std::sort(v, v + 3);
+  *ms_out = v[1];
+  return CSP_OK;
+}
+
+}  // namespace
+
+extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lattice* const* lats,
+                                   const int32_t* R, const csp_params* params_in,
+                                   csp_tuning* out) {
+  if (!c || n_inst < 1 || !lats || !R || !params_in) return fail(CSP_EINVAL, "NULL argument");
+  csp_params P;
+  fill_defaults(params_in, &P);
+  if (P.mode < CSP_FP64_SEQ || P.mode > CSP_FP32_CONC) return fail(CSP_EINVAL, "bad mode %d", P.mode);
+  if (P.assembly != CSP_ASSEMBLE_STATES && P.assembly != CSP_ASSEMBLE_MOMENTS)
+    return fail(CSP_EINVAL, "bad assembly %d", P.assembly);
+  const bool fp64 = P.mode != CSP_FP32_CONC;
+  const bool mom = P.assembly == CSP_ASSEMBLE_MOMENTS;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  std::vector<InstIn> ins(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    if (!lats[i] || R[i] < 1) return fail(CSP_EINVAL, "instance %d: NULL lattice or R < 1", i);
+    if (lats[i]->ctx->device != c->device) return fail(CSP_EINVAL, "instance %d on another device", i);
+    ins[i] = {lats[i], nullptr, R[i], nullptr, nullptr};
+  }
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+
+  // column groups, as csp_propagate forms them
+  std::vector<Group> groups;
+  int64_t vec_elems = 0;
+  int rmax = 1;
+  for (size_t i = 0; i < ins.size(); ++i) {
+    int col = 0;
+    for (int Rg : split_columns(ins[i].R)) {
+      Group g;
+      g.inst = (int)i;
+      g.col0 = col;
+      g.Rg = Rg;
+      g.M = ins[i].lat->g.N * Rg;
+      groups.push_back(g);
+      vec_elems += g.M;
+      rmax = std::max(rmax, Rg);
+      col += Rg;
+    }
+  }
+  std::vector<SpmmInst> sp;
+  for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+
+  // recursion candidates and the largest tile count among them
+  std::vector<std::pair<int, int>> cands;
+  const int vmax = fp64 ? 2 : 4;
+  int64_t max_tiles = 0;
+  for (int v = 1; v <= vmax; v *= 2)
+    for (int seg = 2; seg <= 128; seg *= 2) {
+      std::vector<SpmmInst> tmp_sp = sp;
+      SpmmPlan p = plan_spmm(tmp_sp, fp64, c->n_cu, v, seg);
+      if (p.total_tiles < 1 || p.total_tiles > INT32_MAX) continue;
+      cands.push_back({v, seg});
+      max_tiles = std::max(max_tiles, p.total_tiles);
+    }
+
+  // coefficient table for the cost model and the contraction operands
+  const int bmax = P.mode == CSP_FP64_SEQ ? 1 : (fp64 ? kMaxFp64B : 32 * kMaxJTiles);
+  const int ncol = bmax;
+  const int nmax = (int)trunc_nmax(ncol * P.tau_tilde);
+  const int lda = nmax + 1;
+  struct Free {
+    std::vector<void*> p;
+    ~Free() { for (void* q : p) (void)hipFree(q); }
+  } tmp;
+  double* d_a = nullptr;
+  int32_t* d_ntr = nullptr;
+  HIPCALL(hipMalloc(&d_a, sizeof(double) * (size_t)ncol * lda));
+  tmp.p.push_back(d_a);
+  HIPCALL(hipMalloc(&d_ntr, sizeof(int32_t) * ncol));
+  tmp.p.push_back(d_ntr);
+  HIPCALL(launch_bessel(P.tau_tilde, ncol, nmax, P.eta, true, d_a, d_ntr, s));
+  std::vector<int32_t> ntr(ncol);
+  HIPCALL(hipMemcpyAsync(ntr.data(), d_ntr, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, s));
+  HIPCALL(hipStreamSynchronize(s));
+  for (int j = 0; j < ncol; ++j)
+    if (ntr[j] < 1) return fail(CSP_ENUMERIC, "no truncation order for x = %g", (j + 1) * P.tau_tilde);
+
+  // timing workspace: K_t Chebyshev slots per group (3 for the recursion
+  // alone), psi0, carry, partial sums, operand tables
+  size_t freeb = 0, totalb = 0;
+  HIPCALL(hipMemGetInfo(&freeb, &totalb));
+  const size_t avail = freeb + c->ws_size;
+  const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
+  const int wg_max = 8 * c->n_cu + (int)groups.size();
+  auto tune_ws = [&](int S_) {
+    size_t by = 0;
+    for (auto& g : groups) by += align256((size_t)S_ * g.M * csz) + 2 * align256(g.M * csz);
+    by += align256((size_t)max_tiles * 4 * rmax * 16);                       // moment partials
+    by += align256((size_t)wg_max * 64 * kMaxGroupCols * 16);                // contraction partials
+    by += 2 * align256(bop_bytes(kMaxJTiles, 32)) + 2 * align256(sizeof(double2) * 32 * 17);
+    by += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size());
+    return by;
+  };
+  int K_t = (mom || P.mode == CSP_FP64_SEQ) ? 3 : 32;
+  while (K_t > 16 && tune_ws(K_t) > cap) K_t -= 16;
+  if (K_t > 3 && tune_ws(K_t) > cap) K_t = 3;
+  if (tune_ws(K_t) > cap)
+    return fail(CSP_ENOMEM, "autotuner workspace %.2f GB exceeds the cap %.2f GB", tune_ws(K_t) / 1e9,
+                cap / 1e9);
+  CHECK(ws_reserve(c, tune_ws(K_t)));
+  Carver cv(c->ws);
+  for (auto& g : groups) {
+    g.slots = cv.take((size_t)K_t * g.M * csz);
+    g.psi0g = cv.take(g.M * csz);
+    g.carry = cv.take(g.M * csz);
+  }
+  double* d_part = (double*)cv.take((size_t)max_tiles * 4 * rmax * 16);
+  double* d_cpart = (double*)cv.take((size_t)wg_max * 64 * kMaxGroupCols * 16);
+  void* d_bop1 = cv.take(bop_bytes(kMaxJTiles, 32));
+  void* d_bop2 = cv.take(bop_bytes(kMaxJTiles, 32));
+  float* d_cc1 = (float*)cv.take(sizeof(double2) * 32 * 17);
+  float* d_cc2 = (float*)cv.take(sizeof(double2) * 32 * 17);
+  SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
+  ContractInst* d_con = (ContractInst*)cv.take(sizeof(ContractInst) * groups.size());
+  // state values: random phases in every slot, psi0 and carry
+  for (auto& g : groups) {
+    const int64_t N = ins[g.inst].lat->g.N;
+    for (int k = 0; k < K_t; ++k)
+      HIPCALL(launch_random_phase(N, g.Rg, 0x5eed + k, fp64 ? CSP_C128 : CSP_C64,
+                                  static_cast<char*>(g.slots) + (size_t)k * g.M * csz, g.Rg, 0, s));
+    HIPCALL(launch_random_phase(N, g.Rg, 0x1234, fp64 ? CSP_C128 : CSP_C64, g.psi0g, g.Rg, 0, s));
+    HIPCALL(launch_random_phase(N, g.Rg, 0x4321, fp64 ? CSP_C128 : CSP_C64, g.carry, g.Rg, 0, s));
+  }
+
+  csp_tuning T{};
+  // ---- recursion shapes
+  double best_ms = 1e30;
+  for (auto& cd : cands) {
+    std::vector<SpmmInst> tsp = sp;
+    SpmmPlan p = plan_spmm(tsp, fp64, c->n_cu, cd.first, cd.second);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      tsp[gi].base = groups[gi].slots;
+      tsp[gi].slot_stride = groups[gi].M;
+      tsp[gi].psi0 = groups[gi].psi0g;
+    }
+    HIPCALL(hipMemcpyAsync(d_spmm, tsp.data(), sizeof(SpmmInst) * tsp.size(),
+                           hipMemcpyHostToDevice, s));
+    SpmmStep st{};
+    st.slot_out = 2;
+    st.slot_cur = 1;
+    st.slot_prev = 0;
+    st.has_prev = 1;
+    st.scale_f = 1.0f;
+    st.scale_d = 1.0;
+    st.seg_rows = p.seg_rows;
+    st.halo = p.halo;
+    st.total_tiles = p.total_tiles;
+    st.dot_psi0 = mom ? 1 : 0;
+    st.dot_self = mom ? 1 : 0;
+    st.rmax = rmax;
+    st.partial = d_part;
+    double ms = 0;
+    CHECK(time_launch(c, [&]() -> csp_status {
+      HIPCALL(launch_spmm(fp64, p.vec, mom, d_spmm, (int)tsp.size(), st, s));
+      return CSP_OK;
+    }, &ms));
+    ++T.n_candidates;
+    if (ms < best_ms) {
+      best_ms = ms;
+      T.spmm_vec = p.vec;
+      T.spmm_seg_rows = p.seg_rows;
+    }
+  }
+  T.t_amxsy_us = best_ms * 1000.0;
+
+  // ---- contraction (state assembly)
+  T.contract_wg_per_cu = 4;
+  T.t_order_us[0] = T.t_order_us[1] = -1.0;
+  if (!mom && K_t >= 16) {
+    const int jt_max = fp64 ? 1 : kMaxJTiles;
+    auto setup = [&](int wpc, int* total) -> csp_status {
+      std::vector<ContractInst> ct;
+      int64_t Msum = 0;
+      for (auto& g : groups) Msum += g.M;
+      int wg0 = 0;
+      for (auto& g : groups) {
+        const int64_t units = fp64 ? ceil_div(g.M, kContractThreads) : ceil_div(ceil_div(g.M, 32), 4);
+        int w = (int)std::llround((double)c->n_cu * wpc * (double)g.M / (double)Msum);
+        w = (int)std::max<int64_t>(1, std::min<int64_t>(w, units));
+        ContractInst C{};
+        C.slots = g.slots;
+        C.slot_stride = g.M;
+        C.M = g.M;
+        C.Rg = g.Rg;
+        C.psi0 = g.psi0g;
+        C.carry = g.carry;
+        C.partial = d_cpart;   // timing only: instances may share it
+        C.wg0 = wg0;
+        C.n_wg = w;
+        wg0 += w;
+        ct.push_back(C);
+      }
+      HIPCALL(hipMemcpyAsync(d_con, ct.data(), sizeof(ContractInst) * ct.size(),
+                             hipMemcpyHostToDevice, s));
+      *total = wg0;
+      return CSP_OK;
+    };
+    const int K = std::min(K_t, 32);
+    if (fp64) {
+      HIPCALL(launch_pack_c64(d_a, lda, d_ntr, kMaxFp64B, 0, K, (double*)d_bop1, (double*)d_cc1, s));
+    } else {
+      HIPCALL(launch_pack_bop(d_a, lda, d_ntr, 32, 1, 0, K, d_bop1, d_cc1, s));
+      HIPCALL(launch_pack_bop(d_a, lda, d_ntr, 64, 2, 0, K, d_bop2, d_cc2, s));
+    }
+    auto run = [&](int jt, int total) -> csp_status {
+      ContractArgs ca{};
+      ca.n_inst = (int)groups.size();
+      ca.n_lo = 0;
+      ca.n_cnt = K;
+      ca.S = K_t;
+      ca.first_chunk = 0;
+      ca.jtiles = jt;
+      ca.bcols = fp64 ? kMaxFp64B : 32 * jt;
+      ca.total_wg = total;
+      if (fp64) {
+        ca.coef = d_bop1;
+        ca.ccarry = d_cc1;
+        HIPCALL(launch_contract_f64(d_con, ca, s));
+      } else {
+        ca.bop = jt == 1 ? d_bop1 : d_bop2;
+        ca.ccarry = jt == 1 ? d_cc1 : d_cc2;
+        HIPCALL(launch_contract_f32(d_con, ca, s));
+      }
+      return CSP_OK;
+    };
+    double best = 1e30;
+    for (int wpc = 2; wpc <= 8; wpc *= 2) {
+      int total = 0;
+      CHECK(setup(wpc, &total));
+      double ms = 0;
+      CHECK(time_launch(c, [&]() { return run(1, total); }, &ms));
+      if (ms < best) {
+        best = ms;
+        T.contract_wg_per_cu = wpc;
+      }
+    }
+    T.t_order_us[0] = best * 1000.0 / K;
+    if (jt_max > 1) {
+      int total = 0;
+      CHECK(setup(T.contract_wg_per_cu, &total));
+      double ms = 0;
+      CHECK(time_launch(c, [&]() { return run(2, total); }, &ms));
+      T.t_order_us[1] = ms * 1000.0 / K;
+    }
+  }
+
+  // ---- time-block size by the cost model
+  for (int k = 0; k < 8; ++k) T.model_cost_ms[k] = -1.0;
+  T.block_b = 0;
+  if (!mom) {
+    const int64_t Nt = std::max<int64_t>(P.Nt, 1);
+    const int wg_total = c->n_cu * T.contract_wg_per_cu + (int)groups.size();
+    auto state_ws = [&](int S_, int b) {
+      size_t by = 0;
+      for (auto& g : groups) by += align256((size_t)S_ * g.M * csz) + 2 * align256(g.M * csz);
+      by += align256((size_t)wg_total * b * kMaxGroupCols * 16) * 2;
+      return by + (64u << 20);
+    };
+    auto cost = [&](int b) -> double {
+      const int jt = fp64 ? 1 : (int)ceil_div(b, 32);
+      const double t_ord = T.t_order_us[jt - 1];
+      if (t_ord < 0 && b > 1 && P.mode != CSP_FP64_SEQ) return -1.0;
+      const int Ktot = ntr[b - 1] + 1;
+      const int kcap = fp64 ? (1 << 20) : (496 / jt / 16) * 16;
+      int K = std::min(Ktot, kcap);
+      if (K < Ktot) K = (K / 16) * 16;
+      while (K > 16 && state_ws(std::max(3, K), b) > cap) K = ((K - 1) / 16) * 16;
+      if (state_ws(std::max(3, K), b) > cap) return -1.0;
+      double us = 0;
+      for (int64_t t0 = 0; t0 < Nt; t0 += b) {
+        const int bk = (int)std::min<int64_t>(b, Nt - t0);
+        const int Nk = ntr[bk - 1];
+        const int chunks = (int)ceil_div(Nk + 1, K);
+        // the carry is read back and rewritten once per extra chunk
+        us += Nk * T.t_amxsy_us + (Nk + 1 + 2 * (chunks - 1)) * std::max(t_ord, 0.0);
+      }
+      return us / 1000.0;
+    };
+    double best = 1e300;
+    for (int b = 1; b <= bmax; ++b) {
+      const double cb = cost(b);
+      if (cb >= 0 && cb < best) {
+        best = cb;
+        T.block_b = b;
+      }
+    }
+    for (int b = 1, k = 0; b <= 128; b *= 2, ++k) T.model_cost_ms[k] = b <= bmax ? cost(b) : -1.0;
+  }
+  c->tuned[shape_key(ins, fp64, P.assembly)] = T;
+  if (out) *out = T;
+  return CSP_OK;
+}
+
 extern "C" csp_status csp_select_block(csp_context* c, const csp_lattice* L, int32_t R,
                                        const csp_params* params, int32_t* b_out, csp_report* rep) {
-  (void)c; (void)L; (void)R; (void)params; (void)b_out; (void)rep;
-  return fail(CSP_EUNSUPPORTED, "calibrated block selection is not available in this build");
+  if (!c || !L || !params || !b_out) return fail(CSP_EINVAL, "NULL argument");
+  csp_params P;
+  fill_defaults(params, &P);
+  P.assembly = CSP_ASSEMBLE_STATES;
+  const bool fp64 = P.mode != CSP_FP32_CONC;
+  std::vector<InstIn> ins(1);
+  ins[0] = {L, nullptr, R, nullptr, nullptr};
+  csp_tuning T{};
+  const csp_tuning* have = find_tuning(c, ins, fp64, CSP_ASSEMBLE_STATES);
+  if (have) {
+    T = *have;
+  } else {
+    const csp_lattice* lats[1] = {L};
+    CHECK(csp_autotune(c, 1, lats, &R, &P, &T));
+  }
+  *b_out = T.block_b;
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->block_b = T.block_b;
+    for (int k = 0; k < 8; ++k) rep->model_cost[k] = T.model_cost_ms[k];
+  }
+  return CSP_OK;
 }

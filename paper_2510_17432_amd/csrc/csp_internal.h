@@ -198,8 +198,11 @@ struct FinishInst {
   int32_t col0;
   int32_t pad;
 };
+// t0_dev (may be null): device copy of t0, read at run time (graph replays).
 hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_t t0,
-                         hipStream_t s);
+                         const int64_t* t0_dev, hipStream_t s);
+// d_blk[0] += b, d_blk[1] += 1 (the block counter of graph replays).
+hipError_t launch_advance(int64_t* d_blk, int64_t b, hipStream_t s);
 
 // ------------------------------------------------------------------ coefficients
 // For x_j = (j + 1) * tau, j = 0..nx-1: a[j][n] = J_n(x_j) (n = 0) or
@@ -247,9 +250,11 @@ hipError_t launch_moment_corr(const double* d_mu_partial, int n_tiles, int Rg, i
                               int64_t t0, double* d_corr, int64_t ldc, int col0,
                               hipStream_t s);
 // Norm guard after a block (see k_guard); d_carry may be null.
+// blk_dev (may be null): device (t0, block) read at run time (graph replays).
 hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const double* d_corr,
                         int64_t ldc, int col0, int64_t t0, int bk, double tol, int block,
-                        int* d_flag, double* d_scratch, int n_scratch_wg, hipStream_t s);
+                        const int64_t* blk_dev, int* d_flag, double* d_scratch,
+                        int n_scratch_wg, hipStream_t s);
 hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth,
                       double tau_tilde, int window, double* d_E, double* d_D, double* d_Dmean,
                       double* d_twiddle, hipStream_t s);

@@ -335,13 +335,16 @@ hipError_t launch_contract_f64(const ContractInst* d_inst, const ContractArgs& a
 }
 
 // Sum the workgroup partials of every instance in workgroup order (FP64).
+// The block's first time index comes from t0_dev[0] when it is given (a
+// block replayed from a HIP graph), else from t0.
 __global__ void k_finish(const FinishInst* __restrict__ insts, int n_inst, int bcols,
-                         int64_t t0) {
+                         int64_t t0, const int64_t* __restrict__ t0_dev) {
   const int ii = blockIdx.y;
   if (ii >= n_inst) return;
   const FinishInst& I = insts[ii];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= bcols * I.Rg) return;
+  if (t0_dev) t0 = t0_dev[0];
   const int j = e / I.Rg, r = e - j * I.Rg;
   const double2* p = reinterpret_cast<const double2*>(I.partial);
   double sx = 0.0, sy = 0.0;
@@ -355,10 +358,24 @@ __global__ void k_finish(const FinishInst* __restrict__ insts, int n_inst, int b
 }
 
 hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_t t0,
-                         hipStream_t s) {
+                         const int64_t* t0_dev, hipStream_t s) {
   const int need = bcols * kMaxGroupCols;
   const dim3 grid(static_cast<unsigned>(ceil_div(need, 256)), n_inst), block(256);
-  hipLaunchKernelGGL(k_finish, grid, block, 0, s, d_inst, n_inst, bcols, t0);
+  hipLaunchKernelGGL(k_finish, grid, block, 0, s, d_inst, n_inst, bcols, t0, t0_dev);
+  return hipGetLastError();
+}
+
+// Block counter of graph replays: [0] first time index of the next block,
+// [1] its block number.
+__global__ void k_advance(int64_t* __restrict__ blk, int64_t b) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    blk[0] += b;
+    blk[1] += 1;
+  }
+}
+
+hipError_t launch_advance(int64_t* d_blk, int64_t b, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d_blk, b);
   return hipGetLastError();
 }
 

@@ -239,9 +239,14 @@ hipError_t launch_self_dot(int64_t N, int Rg, const void* d_psi, bool fp64, doub
 // flag[0] (smallest index wins) and the column into flag[1].
 __global__ void k_guard(int n_wg, int Rg, const double* __restrict__ carry_partial,
                         const double* __restrict__ corr, int64_t ldc, int col0, int64_t t0,
-                        int bk, double tol, int block, int* __restrict__ flag) {
+                        int bk, double tol, int block, const int64_t* __restrict__ blk_dev,
+                        int* __restrict__ flag) {
   const int r = threadIdx.x;
   if (r >= Rg) return;
+  if (blk_dev) {
+    t0 = blk_dev[0];
+    block = static_cast<int>(blk_dev[1]);
+  }
   const double2* C = reinterpret_cast<const double2*>(corr);
   const double c0 = C[col0 + r].x;
   bool bad = !(c0 >= 0.0) || !isfinite(c0);
@@ -262,12 +267,14 @@ __global__ void k_guard(int n_wg, int Rg, const double* __restrict__ carry_parti
 
 hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const double* d_corr,
                         int64_t ldc, int col0, int64_t t0, int bk, double tol, int block,
-                        int* d_flag, double* d_scratch, int n_scratch_wg, hipStream_t s) {
+                        const int64_t* blk_dev, int* d_flag, double* d_scratch,
+                        int n_scratch_wg, hipStream_t s) {
   if (d_carry)
     hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg), dim3(256), 0, s, N * Rg, Rg,
                        d_carry, fp64 ? 1 : 0, d_scratch);
   hipLaunchKernelGGL(k_guard, dim3(1), dim3(64), 0, s, n_scratch_wg, Rg,
-                     d_carry ? d_scratch : nullptr, d_corr, ldc, col0, t0, bk, tol, block, d_flag);
+                     d_carry ? d_scratch : nullptr, d_corr, ldc, col0, t0, bk, tol, block,
+                     blk_dev, d_flag);
   return hipGetLastError();
 }
 

@@ -369,3 +369,108 @@ def test_norm_guard(csp, ctx, mode, assembly, b):
         with pytest.raises(csp.CspError) as e:
             csp.csp_propagate(ctx, g, dev(psi).to(tdt), tight)
         assert e.value.status == csp.CSP_ENUMERIC
+
+
+# ---------------------------------------------------------------- autotuner
+def test_autotune_and_block_selection(csp, ctx):
+    print("[gpu] autotune", flush=True)
+    spec = dict(kind="honeycomb", Lx=96, Ly=64, t=-2.7, W=1.0, disorder_seed=4)
+    g, c = pair(csp, ctx, spec)
+    R, Nt = 5, 256
+    params = csp.make_params(Nt, mode="fp32_conc", block_b=0)
+    T = csp.csp_autotune(ctx, [g], [R], params)
+    assert T.n_candidates >= 10 and T.spmm_vec in (1, 2, 4) and T.spmm_seg_rows >= 2
+    assert T.contract_wg_per_cu in (2, 4, 8) and T.t_amxsy_us > 0 and T.t_order_us[0] > 0
+    assert 1 <= T.block_b <= 64
+    costs = list(T.model_cost_ms)
+    assert costs[0] > 0 and all(x > 0 for x in costs[:7])      # b = 1..64 allowed
+    assert costs[7] == -1.0                                     # b = 128 above the MFMA limit
+    b_sel, rep_sel = csp.csp_select_block(ctx, g, R, params)
+    assert b_sel == T.block_b
+    # a propagation of the same shape uses the tuned launch shapes and b
+    psi = o.random_phase_states_fast(c.N, R, 3)
+    got, rep, _ = run_gpu(csp, ctx, g, psi, Nt, "fp32_conc", b=0)
+    assert rep.block_b == T.block_b
+    ref, _ = o.propagate(c, psi, Nt, b=0)
+    assert np.max(np.abs(got - ref)) < 2e-5
+    # moment assembly: recursion shapes only, one block
+    pm = csp.make_params(Nt, mode="fp32_conc", assembly=csp.CSP_ASSEMBLE_MOMENTS)
+    Tm = csp.csp_autotune(ctx, [g], [R], pm)
+    assert Tm.block_b == 0 and Tm.t_amxsy_us > 0
+    gotm, _, _ = run_gpu_moments(csp, ctx, g, psi, Nt, "fp32_conc")
+    assert np.max(np.abs(gotm - ref)) < 2e-5
+
+
+def test_autotune_fp64_and_memory_cap(csp, ctx):
+    g, c = pair(csp, ctx, dict(kind="square", Lx=80, Ly=70, t=1.0, W=0.5, disorder_seed=2))
+    T = csp.csp_autotune(ctx, [g], [3], csp.make_params(64, mode="fp64_conc"))
+    assert 1 <= T.block_b <= 16 and T.t_order_us[1] == -1.0
+    psi = o.random_phase_states_fast(c.N, 3, 8)
+    got, rep, _ = run_gpu(csp, ctx, g, psi, 64, "fp64_conc", b=0)
+    assert rep.block_b == T.block_b
+    ref, _ = o.propagate(c, psi, 64, b=0)
+    assert np.max(np.abs(got - ref)) < 1e-10
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_autotune(ctx, [g], [3], csp.make_params(64, mode="fp64_conc", mem_cap_bytes=4096))
+    assert e.value.status == csp.CSP_ENOMEM
+
+
+# ---------------------------------------------------------------- HIP graphs
+def _batch_inputs(csp, ctx, Nt):
+    specs = [dict(kind="square", Lx=33, Ly=21, t=1.0, W=1.5, disorder_seed=1),
+             dict(kind="honeycomb", Lx=17, Ly=14, t=-2.7, W=0.5, disorder_seed=2),
+             dict(kind="chain", Lx=900, t=1.0, W=0.3, disorder_seed=3)]
+    Rs = [1, 6, 3]
+    gl, psis, refs = [], [], []
+    for spec, R in zip(specs, Rs):
+        g, c = pair(csp, ctx, spec)
+        psi = o.random_phase_states_fast(c.N, R, 13)
+        gl.append(g)
+        psis.append(dev(psi).to(torch.complex64))
+        refs.append(o.propagate(c, psi, Nt, b=0)[0])
+    return gl, psis, refs
+
+
+def test_graph_replay_equals_direct_launches(csp, ctx):
+    print("[gpu] graph replay", flush=True)
+    Nt, b = 100, 16                                     # 6 full blocks + 1 of 4 steps
+    gl, psis, refs = _batch_inputs(csp, ctx, Nt)
+    direct, rep_d = csp.csp_propagate_batch(ctx, gl, psis, csp.make_params(Nt, block_b=b, graph=-1))
+    assert rep_d.graph_blocks == 0
+    direct = [host(x) for x in direct]
+    for ref, d in zip(refs, direct):
+        assert np.max(np.abs(d - ref)) < 2e-5
+    # several graph-mode calls with eager work in between: every replay is
+    # bit-identical to the direct launches
+    for rep_i in range(3):
+        got, rep_g = csp.csp_propagate_batch(ctx, gl, psis, csp.make_params(Nt, block_b=b))
+        assert rep_g.graph_blocks == 6
+        for d, x in zip(direct, got):
+            assert np.array_equal(host(x), d)
+        _ = (psis[0] * 2).sum().item()
+    # single-lattice call with the graph switched on
+    single, rep_s = csp.csp_propagate(ctx, gl[1], psis[1], csp.make_params(Nt, block_b=b, graph=1))
+    assert rep_s.graph_blocks == 6 and np.array_equal(host(single), direct[1])
+
+
+def test_graph_capture_failure_falls_back(csp, ctx, monkeypatch):
+    Nt, b = 64, 16
+    gl, psis, refs = _batch_inputs(csp, ctx, Nt)
+    monkeypatch.setenv("CSP_FORCE_GRAPH_FAILURE", "1")
+    got, rep = csp.csp_propagate_batch(ctx, gl, psis, csp.make_params(Nt, block_b=b, graph=1))
+    assert rep.graph_blocks == 0
+    for ref, x in zip(refs, got):
+        assert np.max(np.abs(host(x) - ref)) < 2e-5
+
+
+def test_graph_replay_with_norm_guard(csp, ctx):
+    Nt, b = 64, 8
+    gl, psis, refs = _batch_inputs(csp, ctx, Nt)
+    params = csp.make_params(Nt, block_b=b, graph=1, check_norm=True)
+    got, rep = csp.csp_propagate_batch(ctx, gl, psis, params)
+    assert rep.graph_blocks == 8
+    bad = [p.clone() for p in psis]
+    bad[2][5, 1] = float("nan")
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_propagate_batch(ctx, gl, bad, params)
+    assert e.value.status == csp.CSP_ENUMERIC and "block 0" in str(e.value)
