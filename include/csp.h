@@ -164,7 +164,9 @@ typedef struct {
     uint64_t workspace_bytes;
     double model_cost[8];      /* selection-rule cost of b = 1,2,4,...,128 */
     int32_t graph_blocks;      /* time blocks replayed from a HIP graph */
-    int32_t reserved;
+    int32_t n_passes;          /* column windows run one after another
+                                  because all columns at once exceed the
+                                  memory cap (1 = all columns together) */
 } csp_report;
 
 /* Launch shapes and time-block size measured by csp_autotune. */

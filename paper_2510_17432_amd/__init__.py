@@ -78,10 +78,10 @@ class Report(ctypes.Structure):
                 ("ms_contract", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
                 ("contract_bytes", ctypes.c_double), ("contract_flops", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_uint64), ("model_cost", ctypes.c_double * 8),
-                ("graph_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("graph_blocks", ctypes.c_int32), ("n_passes", ctypes.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("model_cost", "reserved")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "model_cost"}
         d["model_cost"] = list(self.model_cost)
         return d
 

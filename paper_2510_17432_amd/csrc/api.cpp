@@ -468,12 +468,16 @@ extern "C" csp_status csp_chebyshev_step(csp_context* c, const csp_lattice* L, i
 // ------------------------------------------------------------------ propagation
 namespace {
 
+// One instance of a propagation: columns col_base .. col_base+R-1 of the
+// caller's [N][ld] state block and [(Nt+1)][ld] correlation block.
 struct InstIn {
   const csp_lattice* lat;
   const void* psi0;
   int R;
   double* corr;
   void* final_out;
+  int ld;
+  int col_base;
 };
 
 struct Group {
@@ -604,14 +608,15 @@ int select_b_rule(const std::vector<int32_t>& ntr_all, int bmax, int64_t Nt, dou
 }  // namespace
 
 static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
-                                 const csp_params* params_in, csp_report* rep, bool batch_call);
+                                 const csp_params* params_in, csp_report* rep, bool batch_call,
+                                 bool allow_split = true);
 
 extern "C" csp_status csp_propagate(csp_context* c, const csp_lattice* L, const void* dev_psi0,
                                     int32_t R, const csp_params* params, double* dev_corr,
                                     void* dev_final, csp_report* rep) {
   if (!c || !L || !dev_psi0 || !params || !dev_corr) return fail(CSP_EINVAL, "NULL argument");
   std::vector<InstIn> ins(1);
-  ins[0] = {L, dev_psi0, R, dev_corr, dev_final};
+  ins[0] = {L, dev_psi0, R, dev_corr, dev_final, R, 0};
   return propagate_impl(c, ins, params, rep, false);
 }
 
@@ -625,7 +630,7 @@ extern "C" csp_status csp_propagate_batch(csp_context* c, int32_t n_inst,
   std::vector<InstIn> ins(n_inst);
   for (int i = 0; i < n_inst; ++i) {
     if (!lats[i] || !dev_psi0[i] || !dev_corr[i]) return fail(CSP_EINVAL, "instance %d NULL", i);
-    ins[i] = {lats[i], dev_psi0[i], R[i], dev_corr[i], nullptr};
+    ins[i] = {lats[i], dev_psi0[i], R[i], dev_corr[i], nullptr, R[i], 0};
   }
   return propagate_impl(c, ins, params, rep, true);
 }
@@ -633,8 +638,58 @@ extern "C" csp_status csp_propagate_batch(csp_context* c, int32_t n_inst,
 static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstIn>& ins,
                                          const csp_params& P, double t_start, csp_report* rep);
 
+// Column windows.  Every column is propagated independently, so when even
+// the smallest workspace (a 16-order chunk plus psi0 and carry for the
+// state assembly, 3 vectors plus psi0 and two carries for the moment
+// assembly) of all columns exceeds the memory cap, the columns are run in
+// passes over windows of at most w columns (w a power of two) per instance.
+static csp_status plan_passes(csp_context* c, const std::vector<InstIn>& ins, const csp_params& P,
+                              std::vector<std::vector<InstIn>>* passes) {
+  const size_t csz = P.mode == CSP_FP32_CONC ? sizeof(float2) : sizeof(double2);
+  const double slots = P.assembly == CSP_ASSEMBLE_MOMENTS ? 6.0 : 18.0;
+  size_t freeb = 0, totalb = 0;
+  HIPCALL(hipMemGetInfo(&freeb, &totalb));
+  const size_t avail = freeb + c->ws_size;
+  const double cap = (double)(P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail);
+  auto need = [&](const std::vector<InstIn>& v) {
+    double vb = 0;
+    for (auto& in : v) vb += (double)in.lat->g.N * in.R * csz;
+    return vb * slots + (double)(96u << 20);
+  };
+  passes->clear();
+  if (need(ins) <= cap) {
+    passes->push_back(ins);
+    return CSP_OK;
+  }
+  std::vector<InstIn> cur;
+  for (auto& in : ins) {
+    int w = 32;
+    while (w > 1) {
+      InstIn x = in;
+      x.R = std::min(w, in.R);
+      if (need({x}) <= cap) break;
+      w /= 2;
+    }
+    for (int c0 = 0; c0 < in.R; c0 += w) {
+      InstIn x = in;
+      x.col_base = in.col_base + c0;
+      x.R = std::min(w, in.R - c0);
+      std::vector<InstIn> trial = cur;
+      trial.push_back(x);
+      if (!cur.empty() && need(trial) > cap) {
+        passes->push_back(cur);
+        cur.clear();
+      }
+      cur.push_back(x);
+    }
+  }
+  if (!cur.empty()) passes->push_back(cur);
+  return CSP_OK;
+}
+
 static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
-                                 const csp_params* params_in, csp_report* rep, bool batch_call) {
+                                 const csp_params* params_in, csp_report* rep, bool batch_call,
+                                 bool allow_split) {
   const double t_start = now_ms();
   csp_params P;
   fill_defaults(params_in, &P);
@@ -642,6 +697,43 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   if (P.mode < CSP_FP64_SEQ || P.mode > CSP_FP32_CONC) return fail(CSP_EINVAL, "bad mode %d", P.mode);
   if (P.assembly != CSP_ASSEMBLE_STATES && P.assembly != CSP_ASSEMBLE_MOMENTS)
     return fail(CSP_EINVAL, "bad assembly %d", P.assembly);
+  for (size_t i = 0; i < ins.size(); ++i)
+    if (ins[i].R < 1) return fail(CSP_EINVAL, "instance %zu: R must be >= 1", i);
+  if (allow_split) {
+    std::vector<std::vector<InstIn>> passes;
+    {
+      DeviceGuard dg0(c->device);
+      CHECK(plan_passes(c, ins, P, &passes));
+    }
+    if (passes.size() > 1) {
+      csp_report tot{};
+      for (size_t p = 0; p < passes.size(); ++p) {
+        csp_report r{};
+        CHECK(propagate_impl(c, passes[p], params_in, &r, batch_call, false));
+        tot.block_b = r.block_b;
+        tot.chunk_K = r.chunk_K;
+        tot.n_blocks = r.n_blocks;
+        tot.n_groups += r.n_groups;
+        tot.amxsy = std::max(tot.amxsy, r.amxsy);
+        tot.axpy = std::max(tot.axpy, r.axpy);
+        tot.dot = std::max(tot.dot, r.dot);
+        tot.spmm_launches += r.spmm_launches;
+        tot.contract_launches += r.contract_launches;
+        tot.ms_spmm += r.ms_spmm;
+        tot.ms_contract += r.ms_contract;
+        tot.spmm_bytes += r.spmm_bytes;
+        tot.contract_bytes += r.contract_bytes;
+        tot.contract_flops += r.contract_flops;
+        tot.workspace_bytes = std::max(tot.workspace_bytes, r.workspace_bytes);
+        for (int k = 0; k < 8; ++k) tot.model_cost[k] = r.model_cost[k];
+        tot.graph_blocks += r.graph_blocks;
+      }
+      tot.n_passes = (int)passes.size();
+      tot.ms_total = now_ms() - t_start;
+      if (rep) *rep = tot;
+      return CSP_OK;
+    }
+  }
   if (P.assembly == CSP_ASSEMBLE_MOMENTS) return propagate_moments_impl(c, ins, P, t_start, rep);
   const bool fp64 = P.mode != CSP_FP32_CONC;
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
@@ -685,7 +777,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   std::vector<Group> groups;
   int64_t vec_elems = 0;   // complex values of one vector over all groups
   for (size_t i = 0; i < ins.size(); ++i) {
-    int col = 0;
+    int col = ins[i].col_base;
     for (int Rg : split_columns(ins[i].R)) {
       Group g;
       g.inst = (int)i;
@@ -849,7 +941,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     F.n_wg = g.n_wg;
     F.Rg = g.Rg;
     F.corr = in.corr;
-    F.ldc = in.R;
+    F.ldc = in.ld;
     F.col0 = g.col0;
     fi.push_back(F);
   }
@@ -864,7 +956,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     const InstIn& in = ins[g.inst];
     const int in_dtype = fp64 ? CSP_C128 : CSP_C64;
     const int64_t N = in.lat->g.N;
-    HIPCALL(launch_gather_cols(N, in.R, g.col0, g.Rg, in_dtype, in.psi0, fp64, g.psi0g, s));
+    HIPCALL(launch_gather_cols(N, in.ld, g.col0, g.Rg, in_dtype, in.psi0, fp64, g.psi0g, s));
     HIPCALL(hipMemcpyAsync(g.carry, g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
     HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, (int)n_sd, s));
   }
@@ -962,7 +1054,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     if (P.check_norm) {
       for (auto& g : groups) {
         const InstIn& in = ins[g.inst];
-        HIPCALL(launch_guard(in.lat->g.N, g.Rg, g.carry, fp64, in.corr, in.R, g.col0, t0, bk,
+        HIPCALL(launch_guard(in.lat->g.N, g.Rg, g.carry, fp64, in.corr, in.ld, g.col0, t0, bk,
                              P.norm_tol, (int)(t0 / b), from_dev ? d_blk : nullptr, d_flag, d_sd,
                              (int)n_sd, strm));
       }
@@ -1038,7 +1130,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   for (auto& g : groups) {
     const InstIn& in = ins[g.inst];
     if (!in.final_out) continue;
-    HIPCALL(launch_scatter_cols(in.lat->g.N, in.R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64,
+    HIPCALL(launch_scatter_cols(in.lat->g.N, in.ld, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64,
                                 g.carry, fp64, in.final_out, s));
   }
   HIPCALL(hipStreamSynchronize(s));
@@ -1064,6 +1156,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     rep->contract_flops = con_flops;
     rep->workspace_bytes = c->ws_size;
     rep->graph_blocks = graph_blocks;
+    rep->n_passes = 1;
   }
   return CSP_OK;
 }
@@ -1137,7 +1230,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   int64_t vec_elems = 0;
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
-    int col = 0;
+    int col = ins[i].col_base;
     for (int Rg : split_columns(ins[i].R)) {
       Group g;
       g.inst = (int)i;
@@ -1206,7 +1299,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     Group& g = groups[gi];
     const InstIn& in = ins[g.inst];
     const int64_t N = in.lat->g.N;
-    HIPCALL(launch_gather_cols(N, in.R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, in.psi0, fp64,
+    HIPCALL(launch_gather_cols(N, in.ld, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, in.psi0, fp64,
                                g.psi0g, s));
     HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, 256, s));
     if (carry)
@@ -1225,7 +1318,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     q.dots = dots[gi];
     q.mu = mus[gi];
     q.corr = in.corr;
-    q.ldc = in.R;
+    q.ldc = in.ld;
     q.Rg = g.Rg;
     q.col0 = g.col0;
     mc.push_back(q);
@@ -1321,7 +1414,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         const Group& g = groups[gi];
         const InstIn& in = ins[g.inst];
         const void* cy = carry ? (cur_carry == 0 ? carry_b[gi] : carry_a[gi]) : nullptr;
-        HIPCALL(launch_guard(in.lat->g.N, g.Rg, cy, fp64, in.corr, in.R, g.col0, t0, bk,
+        HIPCALL(launch_guard(in.lat->g.N, g.Rg, cy, fp64, in.corr, in.ld, g.col0, t0, bk,
                              P.norm_tol, (int)(t0 / b), nullptr, d_flag, d_sd, 256, s));
       }
     }
@@ -1333,7 +1426,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     const InstIn& in = ins[g.inst];
     if (!in.final_out) continue;
     void* fin = cur_carry == 0 ? carry_a[gi] : carry_b[gi];
-    HIPCALL(launch_scatter_cols(in.lat->g.N, in.R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, fin,
+    HIPCALL(launch_scatter_cols(in.lat->g.N, in.ld, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, fin,
                                 fp64, in.final_out, s));
   }
   HIPCALL(hipStreamSynchronize(s));
@@ -1357,6 +1450,8 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     rep->contract_bytes = 0;
     rep->contract_flops = 0;
     rep->workspace_bytes = c->ws_size;
+    rep->graph_blocks = 0;
+    rep->n_passes = 1;
   }
   return CSP_OK;
 }
@@ -1424,7 +1519,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   for (int i = 0; i < n_inst; ++i) {
     if (!lats[i] || R[i] < 1) return fail(CSP_EINVAL, "instance %d: NULL lattice or R < 1", i);
     if (lats[i]->ctx->device != c->device) return fail(CSP_EINVAL, "instance %d on another device", i);
-    ins[i] = {lats[i], nullptr, R[i], nullptr, nullptr};
+    ins[i] = {lats[i], nullptr, R[i], nullptr, nullptr, R[i], 0};
   }
   DeviceGuard dg(c->device);
   hipStream_t s = c->stream;
@@ -1434,7 +1529,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   int64_t vec_elems = 0;
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
-    int col = 0;
+    int col = ins[i].col_base;
     for (int Rg : split_columns(ins[i].R)) {
       Group g;
       g.inst = (int)i;
@@ -1709,7 +1804,7 @@ extern "C" csp_status csp_select_block(csp_context* c, const csp_lattice* L, int
   P.assembly = CSP_ASSEMBLE_STATES;
   const bool fp64 = P.mode != CSP_FP32_CONC;
   std::vector<InstIn> ins(1);
-  ins[0] = {L, nullptr, R, nullptr, nullptr};
+  ins[0] = {L, nullptr, R, nullptr, nullptr, R, 0};
   csp_tuning T{};
   const csp_tuning* have = find_tuning(c, ins, fp64, CSP_ASSEMBLE_STATES);
   if (have) {

@@ -474,3 +474,28 @@ def test_graph_replay_with_norm_guard(csp, ctx):
     with pytest.raises(csp.CspError) as e:
         csp.csp_propagate_batch(ctx, gl, bad, params)
     assert e.value.status == csp.CSP_ENUMERIC and "block 0" in str(e.value)
+
+
+# ---------------------------------------------------------------- memory cap
+@pytest.mark.parametrize("assembly", [0, 1])
+def test_column_windows_under_memory_cap(csp, ctx, assembly):
+    # all 8 columns at once exceed the cap: the library runs windows of
+    # fewer columns one after another, with the same results
+    print("[gpu] column windows assembly=%d" % assembly, flush=True)
+    g, c = pair(csp, ctx, dict(kind="honeycomb", Lx=128, Ly=128, t=-2.7, W=1.0, disorder_seed=3))
+    R, Nt = 8, 48
+    psi = o.random_phase_states_fast(c.N, R, 21)
+    ref, _ = o.propagate(c, psi, Nt, b=0)
+    cap = 96 * 2**20 + 18 * c.N * 4 * 8 + 2**20     # room for 4 columns, not 8
+    if assembly == 1:
+        cap = 96 * 2**20 + 6 * c.N * 4 * 8 + 2**20
+    params = csp.make_params(Nt, mode="fp32_conc", block_b=16, assembly=assembly,
+                             mem_cap_bytes=cap)
+    corr, rep = csp.csp_propagate(ctx, g, dev(psi).to(torch.complex64), params)
+    assert rep.n_passes == 2
+    assert np.max(np.abs(host(corr) - ref)) < 2e-5
+    full, rep1 = csp.csp_propagate(ctx, g, dev(psi).to(torch.complex64),
+                                   csp.make_params(Nt, mode="fp32_conc", block_b=16,
+                                                   assembly=assembly))
+    assert rep1.n_passes == 1
+    assert np.max(np.abs(host(full) - host(corr))) < 1e-6
