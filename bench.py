@@ -32,10 +32,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import csp_inputs  # noqa: E402  (seeded workload recipes)
+
 # Graphene, 1024 x 1024 cells, 4 random-phase states + 64 LDOS sites, 2048
 # time points (Sec. III DOS / LDOS on a lattice of the paper's size range).
-WORKLOAD = dict(kind="honeycomb", Lx=1024, Ly=1024, t=-2.7, W=0.0, R_rand=4, n_sites=64,
-                Nt=2048, seed_states=2, seed_sites=3, block_b=32)
+_G = csp_inputs.GRAPHENE1024
+WORKLOAD = dict(kind=_G["kind"], Lx=_G["Lx"], Ly=_G["Ly"], t=_G["t"], W=_G["W"], R_rand=_G["R"],
+                n_sites=_G["n_sites"], Nt=_G["Nt"], seed_states=_G["seed_states"],
+                seed_sites=_G["seed_sites"], block_b=32)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 COPY_PROBE_BYTES = 2 << 30

@@ -1,0 +1,56 @@
+"""Seeded synthetic workloads (input recipes only).
+
+The lattices, column counts, seeds and time-step counts of the workloads the
+tests and the benchmark run.  Nothing here computes any part of the method:
+states and disorder are drawn by the library (on the GPU) and by the oracle
+(on the CPU) from the seeds given here, each with its own implementation of
+the counter-based generator.
+
+The paper's test system (twisted bilayer graphene, Sec. III) cannot be
+rebuilt from its text; these lattices stand in for its size range
+(5e7 to 1e9 orbitals in Fig. 1).
+"""
+import numpy as np
+
+# Plain method, CPU-sized: 64 x 64 square lattice, |H| = 4.1.
+SQUARE64 = dict(kind="square", Lx=64, Ly=64, t=1.0, W=0.0, disorder_seed=0, R=1,
+                seed_states=1, Nt=1024)
+
+# Graphene, 1024 x 1024 cells (2 097 152 orbitals), 4 random-phase columns
+# and 64 LDOS sites.
+GRAPHENE1024 = dict(kind="honeycomb", Lx=1024, Ly=1024, t=-2.7, W=0.0, disorder_seed=0, R=4,
+                    n_sites=64, seed_states=2, seed_sites=3, Nt=2048)
+
+# Disordered graphene, 4096 x 4096 cells (33 554 432 orbitals), Anderson
+# disorder W = 1 eV, 16 random-phase columns, block size from the cost model.
+DISORDERED_GRAPHENE4096 = dict(kind="honeycomb", Lx=4096, Ly=4096, t=-2.7, W=1.0,
+                               disorder_seed=4, R=16, seed_states=5, Nt=2048)
+
+# Large square lattice, 31623 x 31623 (1 000 014 129 orbitals), W = 0.5,
+# 4 random-phase columns.
+SQUARE31623 = dict(kind="square", Lx=31623, Ly=31623, t=1.0, W=0.5, disorder_seed=6, R=4,
+                   seed_states=7, Nt=4096)
+
+
+def batch32(seed=8, n=32):
+    """Uneven batch: n lattices alternating square (t = 1 eV) and honeycomb
+    (t = -2.7 eV), sides drawn from 128..2048 cells, W uniform in [0, 2] eV,
+    1..8 random-phase columns each; 1024 time steps."""
+    rng = np.random.default_rng(seed)
+    sides = [128, 256, 512, 1024, 2048]
+    out = []
+    for i in range(n):
+        kind = "square" if i % 2 == 0 else "honeycomb"
+        L = int(sides[rng.integers(len(sides))])
+        out.append(dict(kind=kind, Lx=L, Ly=L, t=1.0 if kind == "square" else -2.7,
+                        W=float(rng.uniform(0.0, 2.0)), disorder_seed=100 + i,
+                        R=int(rng.integers(1, 9)), seed_states=200 + i))
+    return out, 1024
+
+
+def scaled(cfg, **over):
+    """A copy of a workload with some fields replaced (scaled-down parity
+    cases keep the kind, hopping, disorder and seeds)."""
+    d = dict(cfg)
+    d.update(over)
+    return d

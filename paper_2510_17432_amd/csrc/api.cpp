@@ -141,6 +141,18 @@ csp_status capture_stream(csp_context* c) {
   return CSP_OK;
 }
 
+// Device memory the planner may use for the workspace: the cap of the
+// parameters, else what is free (plus the workspace already held) less a
+// small reserve for the caller's own allocations.
+csp_status memory_cap(csp_context* c, uint64_t mem_cap_bytes, size_t* cap) {
+  size_t freeb = 0, totalb = 0;
+  HIPCALL(hipMemGetInfo(&freeb, &totalb));
+  const size_t avail = freeb + c->ws_size;
+  const size_t reserve = std::min<size_t>(avail / 32, size_t(4) << 30);
+  *cap = mem_cap_bytes ? std::min<size_t>(mem_cap_bytes, avail) : avail - reserve;
+  return CSP_OK;
+}
+
 int64_t trunc_nmax(double x) { return (int64_t)std::ceil(x + 40.0 + 25.0 * std::cbrt(x + 1.0)); }
 
 // Norm-guard flag: [0] first failing block (INT32_MAX = none), [1] column.
@@ -647,10 +659,9 @@ static csp_status plan_passes(csp_context* c, const std::vector<InstIn>& ins, co
                               std::vector<std::vector<InstIn>>* passes) {
   const size_t csz = P.mode == CSP_FP32_CONC ? sizeof(float2) : sizeof(double2);
   const double slots = P.assembly == CSP_ASSEMBLE_MOMENTS ? 6.0 : 18.0;
-  size_t freeb = 0, totalb = 0;
-  HIPCALL(hipMemGetInfo(&freeb, &totalb));
-  const size_t avail = freeb + c->ws_size;
-  const double cap = (double)(P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail);
+  size_t cap_b = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap_b));
+  const double cap = (double)cap_b;
   auto need = [&](const std::vector<InstIn>& v) {
     double vb = 0;
     for (auto& in : v) vb += (double)in.lat->g.N * in.R * csz;
@@ -789,10 +800,8 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       col += Rg;
     }
   }
-  size_t freeb = 0, totalb = 0;
-  HIPCALL(hipMemGetInfo(&freeb, &totalb));
-  const size_t avail = freeb + c->ws_size;
-  const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
+  size_t cap = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
   const size_t vec_bytes = (size_t)vec_elems * csz + 256 * groups.size();
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_STATES);
   const int total_wg_target = c->n_cu * (tune ? tune->contract_wg_per_cu : 4);
@@ -1263,10 +1272,8 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(MomInst) * groups.size()) +
           align256(sizeof(MomCorrInst) * groups.size()) +
           align256(sizeof(double) * 256 * kMaxGroupCols) + align256(2 * sizeof(int));
-  size_t freeb = 0, totalb = 0;
-  HIPCALL(hipMemGetInfo(&freeb, &totalb));
-  const size_t avail = freeb + c->ws_size;
-  const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
+  size_t cap = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
   if (need > cap)
     return fail(CSP_ENOMEM, "workspace %.2f GB exceeds the cap %.2f GB", need / 1e9, cap / 1e9);
   CHECK(ws_reserve(c, need));
@@ -1582,10 +1589,8 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
 
   // timing workspace: K_t Chebyshev slots per group (3 for the recursion
   // alone), psi0, carry, partial sums, operand tables
-  size_t freeb = 0, totalb = 0;
-  HIPCALL(hipMemGetInfo(&freeb, &totalb));
-  const size_t avail = freeb + c->ws_size;
-  const size_t cap = P.mem_cap_bytes ? std::min<size_t>(P.mem_cap_bytes, avail) : avail;
+  size_t cap = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
   const int wg_max = 8 * c->n_cu + (int)groups.size();
   auto tune_ws = [&](int S_) {
     size_t by = 0;
