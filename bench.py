@@ -74,8 +74,8 @@ def traffic_from_profiles():
     read for a device copy of known size.  None when there is no summary or
     when the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_spmm_graphene1024_r68_counters.json")
-    src = os.path.join(ROOT, "paper_2510_17432_amd", "csrc", "k_spmm.hip")
+    path = os.path.join(ROOT, "profiles", "k_cheb_graphene1024_cols68_counters.json")
+    src = os.path.join(ROOT, "paper_2510_17432_amd", "csrc", "k_cheb.hip")
     if not os.path.exists(path):
         return None
     try:
@@ -186,6 +186,9 @@ def main():
     con_flops = sum(r.contract_flops for r in reps)
     con_bytes = sum(r.contract_bytes for r in reps)
     traffic = traffic_from_profiles()
+    # practical streaming ceilings of this device (context for the roofline)
+    bw_read, bw_write, bw_r2w1 = csp.csp_bandwidth_probe(ctx, 1 << 30)
+    ctx.trim()
     out = {
         "metric": "orbital·Chebyshev-steps/s + DOS time-to-accuracy, FP32 concurrent vs FP64 seq",
         "value": value,
@@ -205,12 +208,15 @@ def main():
                    "orbitals": N, "columns": R, "Nt": Nt, "block_b": rep.block_b,
                    "chunk_K": rep.chunk_K, "recursion_steps": steps_exec,
                    "sequential_equivalent_steps": Nt * 20},
-        "roofline": {"bound": "hbm", "kernel": "k_spmm (Chebyshev recursion step)",
+        "roofline": {"bound": "hbm", "kernel": "k_cheb<float> (Chebyshev recursion, %d steps per launch)" % rep.spmm_steps,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6},
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "streaming_ceiling_GBs": {"read": bw_read, "write": bw_write,
+                                               "two_reads_one_write": bw_r2w1},
+                     "frac_of_streaming_ceiling": achieved / bw_r2w1},
         "contraction": {"kernel": "k_contract_f32 (split-bf16 MFMA)",
                         "avg_launch_us": 1000.0 * ms_con / max(n_con, 1),
                         "achieved_GBs": con_bytes / max(ms_con, 1e-9) / 1e6,
@@ -239,7 +245,7 @@ def main():
                           "ms_per_step": 1000.0 * tm, "recursion_steps": mrep.amxsy,
                           "value": N * R * mrep.amxsy / tm,
                           "sequential_equivalent_rate": N * R * Nt * 20 / tm,
-                          "kernel": "k_spmm<float, 4, moments>", "bytes_per_launch": mb,
+                          "kernel": "k_cheb<float, moments>", "bytes_per_launch": mb,
                           "avg_launch_us": mt * 1e6, "achieved_GBs": mb / mt / 1e9,
                           "frac": mb / mt / 1e9 / HBM_PEAK_GBS}
         log("moments: %.3f s per step, %d recursion steps" % (tm, mrep.amxsy))

@@ -167,26 +167,31 @@ typedef struct {
     int32_t n_passes;          /* column windows run one after another
                                   because all columns at once exceed the
                                   memory cap (1 = all columns together) */
+    int32_t spmm_steps;        /* Chebyshev steps per recursion launch (the
+                                  last launch of a block may do fewer) */
+    int32_t reserved;
 } csp_report;
 
 /* Launch shapes and time-block size measured by csp_autotune. */
 typedef struct {
-    int32_t spmm_vec;          /* complex values per thread and row in a
-                                  recursion strip (strip = 256 * vec) */
-    int32_t spmm_seg_rows;     /* lattice rows per recursion workgroup */
+    int32_t spmm_vec;          /* complex values per lane in a recursion
+                                  strip (one wavefront covers 64 * vec
+                                  consecutive values of a lattice row) */
+    int32_t spmm_seg_rows;     /* lattice rows per recursion work item */
     int32_t contract_wg_per_cu;/* contraction workgroups per compute unit */
     int32_t block_b;           /* time-block size from the cost model (state
                                   assembly; 0 for the moment assembly, which
                                   always runs one block) */
     double t_amxsy_us;         /* one recursion step over all columns, best
-                                  shape */
+                                  shape (launch time / spmm_steps) */
     double t_order_us[2];      /* contraction time per Chebyshev order for
                                   b <= 32 and b <= 64 (state assembly) */
     double model_cost_ms[8];   /* modelled propagation time at
                                   b = 1, 2, 4, ..., 128; -1 where b is not
                                   allowed or does not fit */
     int32_t n_candidates;      /* recursion shapes timed */
-    int32_t reserved;
+    int32_t spmm_steps;        /* Chebyshev steps per recursion launch
+                                  (orders kept in registers between steps) */
 } csp_tuning;
 
 typedef struct csp_context csp_context;
@@ -287,8 +292,9 @@ csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t
 /* Autotuner.  For the instances (lats[i], R[i]) with params->mode and
  * params->assembly, times on this device every recursion launch shape
  * (vec in {1, 2, 4}, rows per workgroup in {2, ..., 128}) and, for the state
- * assembly, the contraction at 2, 4 and 8 workgroups per compute unit for
- * time tiles of 32 and 64, then picks the time-block size b by the cost
+ * assembly, the contraction in both of its load schemes at 2, 4 and 8
+ * workgroups per compute unit for time tiles of 32 and 64, then picks the
+ * time-block size b by the cost
  * model of Sec. II.B with measured operation costs:
  *   C(b) = sum over blocks k [ N_k t_amxsy + (N_k + 1) t_order(b) ],
  * N_k = N(b_k tau) (the last block is shorter when b does not divide Nt).
@@ -309,6 +315,13 @@ csp_status csp_autotune(csp_context *ctx, int32_t n_inst, const csp_lattice *con
  * NULL) receives the model costs in model_cost. */
 csp_status csp_select_block(csp_context *ctx, const csp_lattice *lat, int32_t R,
                             const csp_params *params, int32_t *b_out, csp_report *rep);
+
+/* Streaming bandwidth of this device: plain grid-stride streams of 16-byte
+ * accesses over `bytes` per array (workspace), best of several launch
+ * widths, in GB/s: gbs_out[0] read only, [1] write only, [2] two reads and
+ * one write (the access mix of a recursion step, counted as 3 x bytes).
+ * These are the practical ceilings beside the published HBM peak. */
+csp_status csp_bandwidth_probe(csp_context *ctx, uint64_t bytes, double *gbs_out);
 
 /* Free cached workspace of the context. */
 csp_status csp_context_trim(csp_context *ctx);

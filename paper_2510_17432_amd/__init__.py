@@ -78,7 +78,8 @@ class Report(ctypes.Structure):
                 ("ms_contract", ctypes.c_double), ("spmm_bytes", ctypes.c_double),
                 ("contract_bytes", ctypes.c_double), ("contract_flops", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_uint64), ("model_cost", ctypes.c_double * 8),
-                ("graph_blocks", ctypes.c_int32), ("n_passes", ctypes.c_int32)]
+                ("graph_blocks", ctypes.c_int32), ("n_passes", ctypes.c_int32),
+                ("spmm_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "model_cost"}
@@ -91,11 +92,11 @@ class Tuning(ctypes.Structure):
                 ("contract_wg_per_cu", ctypes.c_int32), ("block_b", ctypes.c_int32),
                 ("t_amxsy_us", ctypes.c_double), ("t_order_us", ctypes.c_double * 2),
                 ("model_cost_ms", ctypes.c_double * 8), ("n_candidates", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("spmm_steps", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_
-             if k not in ("t_order_us", "model_cost_ms", "reserved")}
+             if k not in ("t_order_us", "model_cost_ms")}
         d["t_order_us"] = list(self.t_order_us)
         d["model_cost_ms"] = list(self.model_cost_ms)
         return d
@@ -137,6 +138,7 @@ _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctyp
                  ctypes.c_int32, _vp, _vp, _vp])
 _sig("csp_select_block", [_vp, _vp, ctypes.c_int32, _P(Params), _P(ctypes.c_int32), _P(Report)])
 _sig("csp_autotune", [_vp, ctypes.c_int32, _P(_vp), _P(ctypes.c_int32), _P(Params), _P(Tuning)])
+_sig("csp_bandwidth_probe", [_vp, ctypes.c_uint64, _P(ctypes.c_double)])
 
 
 def _check(rc):
@@ -388,3 +390,10 @@ def csp_autotune(ctx, lats, Rs, params):
     t = Tuning()
     _check(_lib.csp_autotune(ctx.handle, n, L, Rv, ctypes.byref(params), ctypes.byref(t)))
     return t
+
+
+def csp_bandwidth_probe(ctx, nbytes=1 << 30):
+    """Streaming GB/s of this device: (read only, write only, 2 reads + 1 write)."""
+    out = (ctypes.c_double * 3)()
+    _check(_lib.csp_bandwidth_probe(ctx.handle, int(nbytes), out))
+    return tuple(out)

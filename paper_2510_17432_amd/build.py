@@ -11,8 +11,9 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsp.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["k_setup.hip", "k_coeffs.hip", "k_spmm.hip", "k_contract.hip", "k_moments.hip",
-           "api.cpp"]
+SOURCES = ["k_cheb_f32.hip", "k_cheb_f32m.hip", "k_cheb_f64.hip", "k_setup.hip", "k_coeffs.hip",
+           "k_cheb.hip", "k_contract.hip", "k_moments.hip",
+           "k_probe.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I" + INCLUDE, "-I" + SRC,

@@ -378,63 +378,79 @@ extern "C" csp_status csp_chebyshev_coefficients(csp_context* c, double x, doubl
 // ------------------------------------------------------------------ recursion helpers
 namespace {
 
-struct SpmmPlan {
-  int vec = 1;
-  int seg_rows = 32;
-  int halo = 1;
-  int64_t total_tiles = 0;
+struct ChebPlan {
+  int vec = 4;          // values per lane and row (strip = 64 vec)
+  int kt = 1;           // steps per launch (temporal blocking)
+  int seg_rows = 32;    // rows per work item
+  int ow = 0;           // owned values per strip
+  int64_t total_items = 0;
+  std::vector<ChebRun> runs;   // one launch per run of same-class instances
 };
 
-// Fill tiling fields of the instances and choose vector width / segment rows
-// (vec_force / seg_force > 0: use those, as measured by the autotuner).
-SpmmPlan plan_spmm(std::vector<SpmmInst>& insts, bool fp64, int n_cu, int vec_force = 0,
-                   int seg_force = 0) {
-  SpmmPlan p;
-  int64_t minrow = INT64_MAX;
-  for (auto& I : insts) {
-    minrow = std::min(minrow, I.rowlen);
-    p.halo = std::max(p.halo, (int)I.R);
+// Work items (waves) of the instances for strips of 64 vec values carrying
+// kt levels, and segments of seg_rows rows; 0 arguments choose defaults
+// (the autotuner passes what it measured).
+ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, int vec = 0,
+                   int kt = 0, int seg = 0) {
+  ChebPlan p;
+  p.vec = vec > 0 ? vec : (fp64 ? 2 : 4);
+  p.kt = kt > 0 ? kt : 1;
+  if (!cheb_shape_supported(fp64, p.vec, p.kt, mom)) {
+    p.vec = fp64 ? 2 : 4;
+    p.kt = 1;
   }
-  p.vec = 1;
-  const int vmax = fp64 ? 2 : 4;
-  while (p.vec < vmax && (int64_t)kSpmmThreads * p.vec * 2 <= minrow) p.vec *= 2;
-  if (vec_force > 0) p.vec = std::min(vec_force, vmax);
-  const int W = kSpmmThreads * p.vec;
-  const int64_t target = (int64_t)n_cu * 8;
-  int seg = 32;
-  auto count = [&](int sr) {
-    int64_t t = 0;
-    for (auto& I : insts) t += ceil_div(I.rowlen, W) * ceil_div(I.Ly, sr);
-    return t;
-  };
-  while (seg > 4 && count(seg) < target) seg /= 2;
-  if (seg_force > 0) seg = seg_force;
-  p.seg_rows = seg;
+  p.ow = 64 * p.vec - 2 * cheb_margin(p.vec, p.kt);
+  int64_t items_rows1 = 0;   // items with one row per segment
+  for (auto& I : insts) items_rows1 += I.Rg * ceil_div(I.opr, p.ow) * I.Ly;
+  if (seg > 0) {
+    p.seg_rows = seg;
+  } else {
+    // long segments amortise the 2 kt margin rows; keep >= 8 waves per CU
+    p.seg_rows = 64;
+    while (p.seg_rows > 4 && items_rows1 / p.seg_rows < (int64_t)n_cu * 8) p.seg_rows /= 2;
+  }
   int64_t t0 = 0;
-  for (auto& I : insts) {
-    I.n_strips = ceil_div(I.rowlen, W);
-    I.n_segs = ceil_div(I.Ly, seg);
-    I.tile0 = t0;
-    t0 += I.n_strips * I.n_segs;
+  for (size_t k = 0; k < insts.size(); ++k) {
+    ChebInst& I = insts[k];
+    I.n_strips = ceil_div(I.opr, p.ow);
+    I.n_segs = ceil_div(I.Ly, p.seg_rows);
+    I.item0 = t0;
+    const int64_t n = (int64_t)I.Rg * I.n_strips * I.n_segs;
+    const bool honey = I.kind == CSP_HONEYCOMB, eps = I.eps != nullptr;
+    if (p.runs.empty() || p.runs.back().honey != honey || p.runs.back().eps != eps)
+      p.runs.push_back({(int)k, 0, t0, 0, honey, eps});
+    p.runs.back().n_inst += 1;
+    p.runs.back().n_items += n;
+    t0 += n;
   }
-  p.total_tiles = t0;
+  p.total_items = t0;
   return p;
 }
 
-SpmmInst make_inst(const csp_lattice* L, int R, bool fp64) {
-  SpmmInst I{};
+ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
+  ChebInst I{};
   I.kind = L->g.kind;
   I.px = L->g.px;
   I.py = L->g.py;
-  I.R = R;
+  I.Rg = Rg;
   I.Ly = L->g.Ly;
   I.opr = L->g.opr;
-  I.rowlen = L->g.opr * R;
+  I.N = L->g.N;
   I.alpha = 2.0 * L->desc.t / L->halfwidth;
   I.beta0 = -2.0 * L->H0 / L->halfwidth;
   I.onsite_scale = 2.0 / L->halfwidth;
   I.eps = L->has_onsite ? (fp64 ? (const void*)L->eps64 : (const void*)L->eps32) : nullptr;
   return I;
+}
+
+ChebStep step_args(const ChebPlan& p) {
+  ChebStep st{};
+  st.seg_rows = p.seg_rows;
+  st.ow = p.ow;
+  st.total_items = p.total_items;
+  st.copy_slot = -1;
+  for (int l = 0; l < 8; ++l) st.slot_out[l] = -1;
+  return st;
 }
 
 }  // namespace
@@ -449,31 +465,31 @@ extern "C" csp_status csp_chebyshev_step(csp_context* c, const csp_lattice* L, i
   if (L->ctx->device != c->device) return fail(CSP_EINVAL, "lattice is on another device");
   DeviceGuard dg(c->device);
   const bool fp64 = dtype == CSP_C128;
-  std::vector<SpmmInst> insts(1, make_inst(L, R, fp64));
-  insts[0].base = dev_y;
-  insts[0].slot_stride = 0;
-  insts[0].src = dev_x;
-  SpmmPlan p = plan_spmm(insts, fp64, c->n_cu);
-  SpmmInst* d_inst = nullptr;
-  HIPCALL(hipMalloc(&d_inst, sizeof(SpmmInst)));
-  hipError_t e = hipMemcpyAsync(d_inst, insts.data(), sizeof(SpmmInst), hipMemcpyHostToDevice,
-                                c->stream);
-  SpmmStep st{};
-  st.slot_out = 0;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  const int64_t N = L->g.N;
+  // the step runs on column-major copies: slot 0 = x, slot 1 = y in, slot 2 = y out
+  const int64_t stride = (N * R + 63) / 64 * 64;
+  std::vector<ChebInst> insts(1, make_inst(L, R, fp64));
+  ChebPlan p = plan_cheb(insts, fp64, false, c->n_cu);
+  CHECK(ws_reserve(c, 3 * align256(stride * csz) + align256(sizeof(ChebInst))));
+  Carver cv(c->ws);
+  char* slots = static_cast<char*>(cv.take(3 * stride * csz));
+  ChebInst* d_inst = (ChebInst*)cv.take(sizeof(ChebInst));
+  insts[0].base = slots;
+  insts[0].slot_stride = stride;
+  hipStream_t s = c->stream;
+  HIPCALL(launch_gather_cols(N, R, 0, R, dtype, dev_x, fp64, slots, s));
+  if (!first) HIPCALL(launch_gather_cols(N, R, 0, R, dtype, dev_y, fp64, slots + stride * csz, s));
+  HIPCALL(hipMemcpyAsync(d_inst, insts.data(), sizeof(ChebInst), hipMemcpyHostToDevice, s));
+  ChebStep st = step_args(p);
+  st.nlev = 1;
+  st.first = first ? 1 : 0;
   st.slot_cur = 0;
-  st.slot_prev = 0;
-  st.cur_from_src = 1;
-  st.copy_cur = 0;
-  st.has_prev = first ? 0 : 1;
-  st.scale_f = first ? 0.5f : 1.0f;
-  st.scale_d = first ? 0.5 : 1.0;
-  st.seg_rows = p.seg_rows;
-  st.halo = p.halo;
-  st.total_tiles = p.total_tiles;
-  if (e == hipSuccess) e = launch_spmm(fp64, p.vec, false, d_inst, 1, st, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(d_inst);
-  if (e != hipSuccess) return fail(CSP_EHIP, "chebyshev step: %s", hipGetErrorString(e));
+  st.slot_prev = 1;
+  st.slot_out[0] = 2;
+  HIPCALL(launch_cheb(fp64, p.vec, p.kt, false, d_inst, p.runs, st, s));
+  HIPCALL(launch_scatter_cols(N, R, 0, R, dtype, slots + 2 * stride * csz, fp64, dev_y, s));
+  HIPCALL(hipStreamSynchronize(s));
   return CSP_OK;
 }
 
@@ -495,6 +511,9 @@ struct InstIn {
 struct Group {
   int inst, col0, Rg;
   int64_t M;
+  // distance between Chebyshev slots: M rounded up to 64 values, so every
+  // slot starts 512-byte aligned (16-byte vector loads in the contraction)
+  int64_t stride() const { return (M + 63) / 64 * 64; }
   void* slots = nullptr;
   void* psi0g = nullptr;
   void* carry = nullptr;
@@ -738,6 +757,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
         tot.workspace_bytes = std::max(tot.workspace_bytes, r.workspace_bytes);
         for (int k = 0; k < 8; ++k) tot.model_cost[k] = r.model_cost[k];
         tot.graph_blocks += r.graph_blocks;
+        tot.spmm_steps = r.spmm_steps;
       }
       tot.n_passes = (int)passes.size();
       tot.ms_total = now_ms() - t_start;
@@ -805,11 +825,19 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   const size_t vec_bytes = (size_t)vec_elems * csz + 256 * groups.size();
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_STATES);
   const int total_wg_target = c->n_cu * (tune ? tune->contract_wg_per_cu : 4);
-  const size_t fixed_guess = 2 * vec_bytes + (size_t)total_wg_target * 64 * 32 * 16 + (64u << 20);
+  const size_t fixed_guess = 2 * vec_bytes + (size_t)total_wg_target * 64 * 16 + (64u << 20);
+
+  // recursion launch shape (steps per launch kt)
+  std::vector<ChebInst> sp;
+  for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+  const ChebPlan sp_plan = plan_cheb(sp, fp64, false, c->n_cu, tune ? tune->spmm_vec : 0,
+                                     tune ? tune->spmm_steps : (fp64 ? 2 : 4),
+                                     tune ? tune->spmm_seg_rows : 0);
+  const int kt = sp_plan.kt;
 
   auto fits_b = [&](int bb) {
     // Workspace with every order of a block resident, or at least 16 of them.
-    const int need = std::min(ntr[bb - 1] + 1, 16);
+    const int need = std::min(ntr[bb - 1] + 1, 16) + kt;
     return fixed_guess + (size_t)need * vec_bytes <= cap;
   };
   if (b == 0 && tune && tune->block_b > 0 && tune->block_b <= bmax && fits_b(tune->block_b)) {
@@ -831,15 +859,18 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   const int Ktot = N_full + 1;
 
   // Chunk size: all orders of a block if they fit, else the largest multiple
-  // of 16 that fits (the ring then holds exactly one chunk).
+  // of 16 that fits.  The ring holds K + kt slots: a launch writes kt orders
+  // past the newest one while the chunk in progress must stay intact.
   const size_t tabs_guess = (64u << 20);
-  auto ws_need = [&](int S_, int n_wg_total) {
+  auto ring_slots = [&](int K_) { return std::max(K_ + kt, kt + 2); };
+  auto ws_need = [&](int K_, int n_wg_total) {
     size_t by = 0;
-    for (auto& g : groups) by += align256((size_t)S_ * g.M * csz) + 2 * align256(g.M * csz);
-    by += align256((size_t)n_wg_total * b * kMaxGroupCols * 16) * 2;
+    for (auto& g : groups)
+      by += align256((size_t)ring_slots(K_) * g.stride() * csz) + 2 * align256(g.M * csz);
+    by += align256((size_t)n_wg_total * b * 16) * 2;
     return by + tabs_guess;
   };
-  const int wg_bound = total_wg_target + (int)groups.size();
+  const int wg_bound = total_wg_target + kMaxGroupCols * (int)groups.size();
   const int kcap = fp64 ? 1 << 20 : (496 / jtiles / 16) * 16;   // LDS budget of B operands
   int K = P.chunk_K > 0 ? P.chunk_K : Ktot;
   if (K >= Ktot && Ktot <= kcap && ws_need(Ktot, wg_bound) <= cap) {
@@ -849,20 +880,24 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     K = std::max(16, (K / 16) * 16);
     while (K > 16 && ws_need(K, wg_bound) > cap) K -= 16;
   }
-  const int S = std::max(3, K);
-  if (ws_need(S, wg_bound) > cap)
+  const int S = ring_slots(K);
+  if (ws_need(K, wg_bound) > cap)
     return fail(CSP_ENOMEM, "workspace for b=%d, K=%d exceeds the cap (%.2f GB)", b, K, cap / 1e9);
 
-  // Contraction workgroups per group, proportional to the group's values.
+  // Contraction workgroups: per group proportional to its values, an equal
+  // number on each of its columns.
   int64_t Msum = 0;
   for (auto& g : groups) Msum += g.M;
   int total_wg = 0;
-  for (auto& g : groups) {
-    const int64_t units = fp64 ? ceil_div(g.M, kContractThreads) : ceil_div(ceil_div(g.M, 32), 4);
-    int w = (int)std::llround((double)total_wg_target * (double)g.M / (double)Msum);
-    w = (int)std::max<int64_t>(1, std::min<int64_t>(w, units));
-    g.n_wg = w;
-    total_wg += w;
+  std::vector<int> wpc(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    const int64_t N = g.M / g.Rg;
+    const int64_t units = fp64 ? ceil_div(N, kContractThreads) : ceil_div(ceil_div(N, 32), 4);
+    const double share = (double)total_wg_target * (double)g.M / (double)Msum / g.Rg;
+    wpc[gi] = (int)std::max<int64_t>(1, std::min<int64_t>(std::llround(share), units));
+    g.n_wg = g.Rg * wpc[gi];
+    total_wg += g.n_wg;
   }
 
   // ---------------------------------------------------------- block tables
@@ -885,13 +920,13 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   // ---------------------------------------------------------- workspace
   size_t need = tab_bytes;
   for (auto& g : groups) {
-    need += align256((size_t)S * g.M * csz) + 2 * align256(g.M * csz);
-    need += align256((size_t)g.n_wg * b * g.Rg * 16);
+    need += align256((size_t)S * g.stride() * csz) + 2 * align256(g.M * csz);
+    need += align256((size_t)g.n_wg * b * 16);
   }
   const size_t n_sd = 256;   // self-dot partial blocks
   need += align256(sizeof(double) * n_sd * kMaxGroupCols);
   need += align256(2 * sizeof(int)) + align256(2 * sizeof(int64_t));
-  need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size()) +
+  need += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size()) +
           align256(sizeof(FinishInst) * groups.size());
   if (need > cap) return fail(CSP_ENOMEM, "workspace %.2f GB exceeds the cap %.2f GB", need / 1e9, cap / 1e9);
   CHECK(ws_reserve(c, need));
@@ -909,35 +944,35 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       }
     }
   for (auto& g : groups) {
-    g.slots = cv.take((size_t)S * g.M * csz);
+    g.slots = cv.take((size_t)S * g.stride() * csz);
     g.psi0g = cv.take(g.M * csz);
     g.carry = cv.take(g.M * csz);
-    g.partial = (double*)cv.take((size_t)g.n_wg * b * g.Rg * 16);
+    g.partial = (double*)cv.take((size_t)g.n_wg * b * 16);
   }
   double* d_sd = (double*)cv.take(sizeof(double) * n_sd * kMaxGroupCols);
   int* d_flag = (int*)cv.take(2 * sizeof(int));
   int64_t* d_blk = (int64_t*)cv.take(2 * sizeof(int64_t));
-  SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
+  ChebInst* d_spmm = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
   ContractInst* d_con = (ContractInst*)cv.take(sizeof(ContractInst) * groups.size());
   FinishInst* d_fin = (FinishInst*)cv.take(sizeof(FinishInst) * groups.size());
 
   // ---------------------------------------------------------- instance tables
-  std::vector<SpmmInst> sp;
   std::vector<ContractInst> ct;
   std::vector<FinishInst> fi;
   int wg0 = 0;
-  for (auto& g : groups) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
     const InstIn& in = ins[g.inst];
-    SpmmInst I = make_inst(in.lat, g.Rg, fp64);
+    ChebInst& I = sp[gi];
     I.base = g.slots;
-    I.slot_stride = g.M;
+    I.slot_stride = g.stride();
     I.src = g.carry;
-    sp.push_back(I);
     ContractInst C{};
     C.slots = g.slots;
-    C.slot_stride = g.M;
-    C.M = g.M;
+    C.slot_stride = g.stride();
+    C.N = g.M / g.Rg;
     C.Rg = g.Rg;
+    C.wpc = wpc[gi];
     C.psi0 = g.psi0g;
     C.carry = g.carry;
     C.partial = g.partial;
@@ -947,16 +982,14 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     ct.push_back(C);
     FinishInst F{};
     F.partial = g.partial;
-    F.n_wg = g.n_wg;
+    F.wpc = wpc[gi];
     F.Rg = g.Rg;
     F.corr = in.corr;
     F.ldc = in.ld;
     F.col0 = g.col0;
     fi.push_back(F);
   }
-  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu, tune ? tune->spmm_vec : 0,
-                               tune ? tune->spmm_seg_rows : 0);
-  HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(SpmmInst) * sp.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_con, ct.data(), sizeof(ContractInst) * ct.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_fin, fi.data(), sizeof(FinishInst) * fi.size(), hipMemcpyHostToDevice, s));
 
@@ -969,8 +1002,6 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     HIPCALL(hipMemcpyAsync(g.carry, g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
     HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, (int)n_sd, s));
   }
-  // ψ0 group copies and the C_0 row must be complete before the synchronous
-  // copies above go out of scope (the host vectors live until the end).
 
   // ---------------------------------------------------------- blocks
   if (P.check_norm) CHECK(guard_reset(d_flag, s));
@@ -980,40 +1011,27 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   double eps_bytes = 0;
   for (auto& g : groups)
     if (ins[g.inst].lat->has_onsite) eps_bytes += (double)ins[g.inst].lat->g.N * (fp64 ? 8 : 4);
-  const double step_bytes = 3.0 * (double)vec_elems * csz + eps_bytes;
+  const double vbytes = (double)vec_elems * csz;
 
   ContractArgs ca{};
   ca.n_inst = (int)groups.size();
   ca.S = S;
   ca.jtiles = jtiles;
   ca.total_wg = total_wg;
-  SpmmStep st{};
-  st.seg_rows = sp_plan.seg_rows;
-  st.halo = sp_plan.halo;
-  st.total_tiles = sp_plan.total_tiles;
+  const ChebStep st0 = step_args(sp_plan);
 
-  // One time block: recursion steps with the contractions of each chunk of
-  // orders as soon as its last order exists, the workgroup-partial sum and
-  // the norm guard.  t0_dev: the block's time index and number come from the
-  // device counter (graph replays), which the block then advances.
+  // One time block: recursion launches of up to kt steps each, with the
+  // contraction of every chunk of orders as soon as its last order exists,
+  // then the per-column partial sums and the norm guard.  from_dev: the
+  // block's time index and number come from the device counter (graph
+  // replays), which the block then advances.
   auto enqueue_block = [&](const BlockTab& T, int bk, int64_t t0, hipStream_t strm,
                            bool from_dev) -> csp_status {
     const int Nk = T.Nk;
     size_t ev = 0;
     if (!from_dev) CHECK(prof.begin(0, &ev));
-    // order 1 from the carried state (also stored as order 0)
-    SpmmStep stb = st;
-    stb.slot_out = 1 % S;
-    stb.slot_cur = 0;
-    stb.slot_prev = 0;
-    stb.cur_from_src = 1;
-    stb.copy_cur = 1;
-    stb.has_prev = 0;
-    stb.scale_f = 0.5f;
-    stb.scale_d = 0.5;
-    HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), stb, strm));
     size_t ci = 0;
-    int produced = 1;
+    int produced = 0;
     ContractArgs cab = ca;
     auto run_chunks = [&]() -> csp_status {
       while (ci < T.chunks.size() && T.chunks[ci].n_lo + T.chunks[ci].n_cnt - 1 <= produced) {
@@ -1044,18 +1062,21 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       }
       return CSP_OK;
     };
-    CHECK(run_chunks());
-    for (int n = 1; n < Nk; ++n) {
-      stb.slot_out = (n + 1) % S;
-      stb.slot_cur = n % S;
-      stb.slot_prev = (n - 1) % S;
-      stb.cur_from_src = 0;
-      stb.copy_cur = 0;
-      stb.has_prev = 1;
-      stb.scale_f = 1.0f;
-      stb.scale_d = 1.0;
-      HIPCALL(launch_spmm(fp64, sp_plan.vec, false, d_spmm, (int)sp.size(), stb, strm));
-      produced = n + 1;
+    while (produced < Nk) {
+      ChebStep stb = st0;
+      stb.nlev = std::min(kt, Nk - produced);
+      if (produced == 0) {
+        // block start: phi_0 = carried state (copied to slot 0), phi_1 = H~ phi_0
+        stb.first = 1;
+        stb.slot_cur = -1;
+        stb.copy_slot = 0;
+      } else {
+        stb.slot_cur = produced % S;
+        stb.slot_prev = (produced - 1) % S;
+      }
+      for (int l = 1; l <= stb.nlev; ++l) stb.slot_out[l - 1] = (produced + l) % S;
+      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, d_spmm, sp_plan.runs, stb, strm));
+      produced += stb.nlev;
       CHECK(run_chunks());
     }
     if (!from_dev) CHECK(prof.end(ev));
@@ -1075,12 +1096,17 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     const int Nk = T.Nk;
     amxsy += Nk;
     for (int j = 1; j <= bk; ++j) axpy += ntr[j - 1];
-    n_spmm += Nk;
-    spmm_bytes += step_bytes * Nk;
+    // algorithmic bytes of a launch of l steps: read phi_n, phi_{n-1} (the
+    // first launch reads phi_0 only and writes it once), write l vectors
+    for (int done = 0; done < Nk; done += kt) {
+      const int l = std::min(kt, Nk - done);
+      ++n_spmm;
+      spmm_bytes += vbytes * (done == 0 ? 2.0 + l : 2.0 + l) + eps_bytes;
+    }
     for (size_t ci = 0; ci < T.chunks.size(); ++ci) {
       const ChunkTab& ch = T.chunks[ci];
       ++n_con;
-      con_bytes += (double)vec_elems * csz * (ch.n_cnt + 2 + (ci == 0 ? 0 : 1));
+      con_bytes += vbytes * (ch.n_cnt + 2 + (ci == 0 ? 0 : 1));
       con_flops += fp64 ? 8.0 * (double)vec_elems * ch.n_cnt * (bk + 1)
                         : 2.0 * 6.0 * 32.0 * 32.0 * 16.0 * jtiles *
                               (double)ceil_div(ch.n_cnt, 16) * (double)ceil_div(vec_elems, 32);
@@ -1166,6 +1192,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     rep->workspace_bytes = c->ws_size;
     rep->graph_blocks = graph_blocks;
     rep->n_passes = 1;
+    rep->spmm_steps = kt;
   }
   return CSP_OK;
 }
@@ -1252,24 +1279,27 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
       col += Rg;
     }
   }
-  std::vector<SpmmInst> sp;
+  std::vector<ChebInst> sp;
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_MOMENTS);
-  SpmmPlan sp_plan = plan_spmm(sp, fp64, c->n_cu, tune ? tune->spmm_vec : 0,
-                               tune ? tune->spmm_seg_rows : 0);
+  // the carried state is accumulated one step per launch
+  const int kt_want = carry ? 1 : (tune ? tune->spmm_steps : (fp64 ? 2 : 4));
+  const ChebPlan sp_plan = plan_cheb(sp, fp64, true, c->n_cu, tune ? tune->spmm_vec : 0, kt_want,
+                                     tune ? tune->spmm_seg_rows : 0);
+  const int kt = sp_plan.kt;
   const int P_batch = 16;
 
   // Workspace.
   size_t need = 0;
-  const size_t part_bytes = (size_t)P_batch * sp_plan.total_tiles * 4 * rmax * 16;
+  const size_t part_bytes = (size_t)P_batch * kt * sp_plan.total_items * 8 * sizeof(double);
   need += align256(part_bytes);
   for (auto& g : groups) {
-    need += 3 * align256(g.M * csz) + align256(g.M * csz);          // ring + psi0
+    need += align256(4 * g.stride() * csz) + align256(g.M * csz);   // ring + psi0
     if (carry) need += 2 * align256(g.M * csz);                      // carry in / out
     need += align256((size_t)(steps_max + 1) * 4 * g.Rg * 16);       // dots
     need += align256((size_t)(Nk_max + 1) * g.Rg * 16);              // mu
   }
-  need += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(MomInst) * groups.size()) +
+  need += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(MomInst) * groups.size()) +
           align256(sizeof(MomCorrInst) * groups.size()) +
           align256(sizeof(double) * 256 * kMaxGroupCols) + align256(2 * sizeof(int));
   size_t cap = 0;
@@ -1283,7 +1313,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   std::vector<double*> dots(groups.size()), mus(groups.size());
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     Group& g = groups[gi];
-    g.slots = cv.take(3 * g.M * csz);
+    g.slots = cv.take(4 * g.stride() * csz);
     g.psi0g = cv.take(g.M * csz);
     if (carry) {
       carry_a[gi] = cv.take(g.M * csz);
@@ -1292,7 +1322,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     dots[gi] = (double*)cv.take((size_t)(steps_max + 1) * 4 * g.Rg * 16);
     mus[gi] = (double*)cv.take((size_t)(Nk_max + 1) * g.Rg * 16);
   }
-  SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
+  ChebInst* d_spmm = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
   MomInst* d_mi = (MomInst*)cv.take(sizeof(MomInst) * groups.size());
   MomCorrInst* d_mc = (MomCorrInst*)cv.take(sizeof(MomCorrInst) * groups.size());
   double* d_sd = (double*)cv.take(sizeof(double) * 256 * kMaxGroupCols);
@@ -1311,13 +1341,13 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, 256, s));
     if (carry)
       HIPCALL(hipMemcpyAsync(carry_a[gi], g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
-    SpmmInst& I = sp[gi];
+    ChebInst& I = sp[gi];
     I.base = g.slots;
-    I.slot_stride = g.M;
+    I.slot_stride = g.stride();
     I.psi0 = g.psi0g;
     MomInst m{};
-    m.tile0 = I.tile0;
-    m.n_tiles = I.n_strips * I.n_segs;
+    m.tile0 = I.item0;
+    m.n_tiles = (int64_t)g.Rg * I.n_strips * I.n_segs;
     m.Rg = g.Rg;
     m.dots = dots[gi];
     mi.push_back(m);
@@ -1339,13 +1369,9 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   double eps_bytes = 0;
   for (auto& g : groups)
     if (ins[g.inst].lat->has_onsite) eps_bytes += (double)ins[g.inst].lat->g.N * (fp64 ? 8 : 4);
+  const double vbytes = (double)vec_elems * csz;
 
-  SpmmStep st{};
-  st.seg_rows = sp_plan.seg_rows;
-  st.halo = sp_plan.halo;
-  st.total_tiles = sp_plan.total_tiles;
-  st.rmax = rmax;
-  st.partial = d_part;
+  const ChebStep st0 = step_args(sp_plan);
   int cur_carry = 0;   // carry_a holds s_k when 0
   for (int64_t t0 = 0; t0 < Nt; t0 += b) {
     const int bk = (int)std::min<int64_t>(b, Nt - t0);
@@ -1355,32 +1381,50 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     const std::vector<double>& arow = (bk == b) ? arow_b : arow_last;
     // per-block instance table: source and carry destination
     for (size_t gi = 0; gi < groups.size(); ++gi) {
-      SpmmInst& I = sp[gi];
+      ChebInst& I = sp[gi];
       if (carry) {
         I.src = cur_carry == 0 ? carry_a[gi] : carry_b[gi];
-        I.carry_out = cur_carry == 0 ? carry_b[gi] : carry_a[gi];
+        I.carry = cur_carry == 0 ? carry_b[gi] : carry_a[gi];
       } else {
         I.src = groups[gi].psi0g;
-        I.carry_out = nullptr;
+        I.carry = nullptr;
       }
     }
-    HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(SpmmInst) * sp.size(), hipMemcpyHostToDevice, s));
+    HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
     size_t ev = 0;
     CHECK(prof.begin(0, &ev));
-    int batch0 = 1;   // order produced by the first step of the pending batch
-    for (int i = 0; i < steps; ++i) {
-      const int n_out = i + 1;   // order produced by this step
-      st.slot_out = n_out % 3;
-      st.slot_cur = i % 3;
-      st.slot_prev = (i + 2) % 3;
-      st.cur_from_src = i == 0 ? 1 : 0;
-      st.copy_cur = i == 0 ? 1 : 0;
-      st.has_prev = i == 0 ? 0 : 1;
-      st.scale_f = i == 0 ? 0.5f : 1.0f;
-      st.scale_d = i == 0 ? 0.5 : 1.0;
-      st.dot_psi0 = (!halving || n_out <= h || i == 0) ? 1 : 0;
+    // four slots: phi_n, phi_{n-1} and the two newest levels of a launch
+    int cur_slot = -1, prev_slot = -1;
+    int produced = 0;
+    int launches = 0;          // launches in the pending batch of records
+    int batch0 = 1;            // order produced by the first level of that batch
+    while (produced < steps) {
+      ChebStep st = st0;
+      st.nlev = std::min(kt, steps - produced);
+      int freeb[4], nf = 0;
+      for (int q = 0; q < 4; ++q)
+        if (q != cur_slot && q != prev_slot) freeb[nf++] = q;
+      int new_cur = freeb[0], new_prev;
+      if (produced == 0) {
+        st.first = 1;
+        st.slot_cur = -1;
+        if (st.nlev == 1) {
+          st.copy_slot = freeb[1];     // phi_0 is the next launch's phi_{n-1}
+          new_prev = freeb[1];
+        } else {
+          new_prev = freeb[1];
+        }
+      } else {
+        st.slot_cur = cur_slot;
+        st.slot_prev = prev_slot;
+        new_prev = st.nlev == 1 ? cur_slot : freeb[1];
+      }
+      st.slot_out[st.nlev - 1] = new_cur;
+      if (st.nlev >= 2) st.slot_out[st.nlev - 2] = new_prev;
+      st.dot_psi0 = (!halving || produced + 1 <= h || produced == 0) ? 1 : 0;
       st.dot_self = halving ? 1 : 0;
-      st.mom_slot = i % P_batch;
+      st.mom_slot = launches;
+      st.partial = d_part;
       if (carry) {
         auto coef = [&](int n, double* out2) {
           const double v = arow[n];
@@ -1391,25 +1435,27 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
             default: out2[0] = 0.0; out2[1] = v; break;
           }
         };
-        st.carry_mode = i == 0 ? 1 : 2;
+        st.carry_mode = produced == 0 ? 1 : 2;
         coef(0, st.cc0);
-        coef(n_out, st.cc);
-        axpy += i == 0 ? 2 : 1;
-      } else {
-        st.carry_mode = 0;
+        coef(produced + 1, st.cc1);
+        axpy += produced == 0 ? 2 : 1;
       }
-      HIPCALL(launch_spmm(fp64, sp_plan.vec, true, d_spmm, (int)sp.size(), st, s));
+      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, true, d_spmm, sp_plan.runs, st, s));
       ++n_spmm;
-      ++amxsy;
-      spmm_bytes += 3.0 * (double)vec_elems * csz + eps_bytes +
-                    (st.dot_psi0 ? (double)vec_elems * csz : 0.0) +
-                    (carry ? (i == 0 ? 1.0 : 2.0) * (double)vec_elems * csz : 0.0);
-      const bool flush = ((i + 1) % P_batch == 0) || (i + 1 == steps);
-      if (flush) {
-        const int cnt = i + 1 - (batch0 - 1);
-        HIPCALL(launch_mom_finish(d_mi, (int)mi.size(), d_part, sp_plan.total_tiles, rmax, cnt,
-                                  batch0, s));
-        batch0 = i + 2;
+      amxsy += st.nlev;
+      spmm_bytes += vbytes * ((produced == 0 ? 1.0 : 2.0) + std::min(st.nlev, 2) +
+                              (st.copy_slot >= 0 ? 1.0 : 0.0) + (st.dot_psi0 ? 1.0 : 0.0) +
+                              (carry ? (produced == 0 ? 1.0 : 2.0) : 0.0)) +
+                    eps_bytes;
+      produced += st.nlev;
+      cur_slot = new_cur;
+      prev_slot = new_prev;
+      ++launches;
+      if (launches == P_batch || produced >= steps) {
+        HIPCALL(launch_cheb_mom_finish(d_mi, (int)mi.size(), d_part, sp_plan.total_items, kt,
+                                       launches, batch0, produced, s));
+        batch0 = produced + 1;
+        launches = 0;
       }
     }
     CHECK(prof.end(ev));
@@ -1459,6 +1505,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     rep->workspace_bytes = c->ws_size;
     rep->graph_blocks = 0;
     rep->n_passes = 1;
+    rep->spmm_steps = kt;
   }
   return CSP_OK;
 }
@@ -1549,20 +1596,24 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
       col += Rg;
     }
   }
-  std::vector<SpmmInst> sp;
+  std::vector<ChebInst> sp;
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
 
-  // recursion candidates and the largest tile count among them
-  std::vector<std::pair<int, int>> cands;
-  const int vmax = fp64 ? 2 : 4;
-  int64_t max_tiles = 0;
-  for (int v = 1; v <= vmax; v *= 2)
-    for (int seg = 2; seg <= 128; seg *= 2) {
-      std::vector<SpmmInst> tmp_sp = sp;
-      SpmmPlan p = plan_spmm(tmp_sp, fp64, c->n_cu, v, seg);
-      if (p.total_tiles < 1 || p.total_tiles > INT32_MAX) continue;
-      cands.push_back({v, seg});
-      max_tiles = std::max(max_tiles, p.total_tiles);
+  // recursion candidates (values per lane, steps per launch, rows per work
+  // item) and the largest record buffer among them
+  struct Cand { int vec, kt, seg; };
+  std::vector<Cand> cands;
+  int64_t max_rec = 0;
+  for (int v = 2; v <= 4; v *= 2)
+    for (int kt = 1; kt <= 8; kt *= 2) {
+      if (!cheb_shape_supported(fp64, v, kt, mom)) continue;
+      for (int seg = 8; seg <= 128; seg *= 2) {
+        std::vector<ChebInst> tmp_sp = sp;
+        ChebPlan p = plan_cheb(tmp_sp, fp64, mom, c->n_cu, v, kt, seg);
+        if (p.total_items < 1 || ceil_div(p.total_items, 4) > INT32_MAX) continue;
+        cands.push_back({v, kt, seg});
+        max_rec = std::max(max_rec, p.total_items * kt);
+      }
     }
 
   // coefficient table for the cost model and the contraction operands
@@ -1591,83 +1642,86 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   // alone), psi0, carry, partial sums, operand tables
   size_t cap = 0;
   CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
-  const int wg_max = 8 * c->n_cu + (int)groups.size();
+  const int wg_max = 8 * c->n_cu + kMaxGroupCols * (int)groups.size();
   auto tune_ws = [&](int S_) {
     size_t by = 0;
-    for (auto& g : groups) by += align256((size_t)S_ * g.M * csz) + 2 * align256(g.M * csz);
-    by += align256((size_t)max_tiles * 4 * rmax * 16);                       // moment partials
-    by += align256((size_t)wg_max * 64 * kMaxGroupCols * 16);                // contraction partials
+    for (auto& g : groups) by += align256((size_t)S_ * g.stride() * csz) + 2 * align256(g.M * csz);
+    by += align256((size_t)max_rec * 8 * sizeof(double));                    // moment records
+    by += align256((size_t)wg_max * 64 * 16);                                // contraction partials
     by += 2 * align256(bop_bytes(kMaxJTiles, 32)) + 2 * align256(sizeof(double2) * 32 * 17);
-    by += align256(sizeof(SpmmInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size());
+    by += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(ContractInst) * groups.size());
     return by;
   };
-  int K_t = (mom || P.mode == CSP_FP64_SEQ) ? 3 : 32;
+  // slots: the recursion writes up to 8 levels after phi_{n-1}, phi_n
+  int K_t = (mom || P.mode == CSP_FP64_SEQ) ? 10 : 32;
   while (K_t > 16 && tune_ws(K_t) > cap) K_t -= 16;
-  if (K_t > 3 && tune_ws(K_t) > cap) K_t = 3;
+  if (K_t > 10 && tune_ws(K_t) > cap) K_t = 10;
   if (tune_ws(K_t) > cap)
     return fail(CSP_ENOMEM, "autotuner workspace %.2f GB exceeds the cap %.2f GB", tune_ws(K_t) / 1e9,
                 cap / 1e9);
   CHECK(ws_reserve(c, tune_ws(K_t)));
   Carver cv(c->ws);
   for (auto& g : groups) {
-    g.slots = cv.take((size_t)K_t * g.M * csz);
+    g.slots = cv.take((size_t)K_t * g.stride() * csz);
     g.psi0g = cv.take(g.M * csz);
     g.carry = cv.take(g.M * csz);
   }
-  double* d_part = (double*)cv.take((size_t)max_tiles * 4 * rmax * 16);
-  double* d_cpart = (double*)cv.take((size_t)wg_max * 64 * kMaxGroupCols * 16);
+  double* d_part = (double*)cv.take((size_t)max_rec * 8 * sizeof(double));
+  double* d_cpart = (double*)cv.take((size_t)wg_max * 64 * 16);
   void* d_bop1 = cv.take(bop_bytes(kMaxJTiles, 32));
   void* d_bop2 = cv.take(bop_bytes(kMaxJTiles, 32));
   float* d_cc1 = (float*)cv.take(sizeof(double2) * 32 * 17);
   float* d_cc2 = (float*)cv.take(sizeof(double2) * 32 * 17);
-  SpmmInst* d_spmm = (SpmmInst*)cv.take(sizeof(SpmmInst) * groups.size());
+  ChebInst* d_spmm = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
   ContractInst* d_con = (ContractInst*)cv.take(sizeof(ContractInst) * groups.size());
   // state values: random phases in every slot, psi0 and carry
   for (auto& g : groups) {
     const int64_t N = ins[g.inst].lat->g.N;
     for (int k = 0; k < K_t; ++k)
       HIPCALL(launch_random_phase(N, g.Rg, 0x5eed + k, fp64 ? CSP_C128 : CSP_C64,
-                                  static_cast<char*>(g.slots) + (size_t)k * g.M * csz, g.Rg, 0, s));
+                                  static_cast<char*>(g.slots) + (size_t)k * g.stride() * csz, g.Rg, 0, s));
     HIPCALL(launch_random_phase(N, g.Rg, 0x1234, fp64 ? CSP_C128 : CSP_C64, g.psi0g, g.Rg, 0, s));
     HIPCALL(launch_random_phase(N, g.Rg, 0x4321, fp64 ? CSP_C128 : CSP_C64, g.carry, g.Rg, 0, s));
   }
 
   csp_tuning T{};
-  // ---- recursion shapes
+  // ---- recursion shapes: time per Chebyshev step of a launch of kt steps
   double best_ms = 1e30;
   for (auto& cd : cands) {
-    std::vector<SpmmInst> tsp = sp;
-    SpmmPlan p = plan_spmm(tsp, fp64, c->n_cu, cd.first, cd.second);
+    std::vector<ChebInst> tsp = sp;
+    ChebPlan p = plan_cheb(tsp, fp64, mom, c->n_cu, cd.vec, cd.kt, cd.seg);
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       tsp[gi].base = groups[gi].slots;
-      tsp[gi].slot_stride = groups[gi].M;
+      tsp[gi].slot_stride = groups[gi].stride();
       tsp[gi].psi0 = groups[gi].psi0g;
     }
-    HIPCALL(hipMemcpyAsync(d_spmm, tsp.data(), sizeof(SpmmInst) * tsp.size(),
+    HIPCALL(hipMemcpyAsync(d_spmm, tsp.data(), sizeof(ChebInst) * tsp.size(),
                            hipMemcpyHostToDevice, s));
-    SpmmStep st{};
-    st.slot_out = 2;
+    ChebStep st = step_args(p);
+    st.nlev = p.kt;
     st.slot_cur = 1;
     st.slot_prev = 0;
-    st.has_prev = 1;
-    st.scale_f = 1.0f;
-    st.scale_d = 1.0;
-    st.seg_rows = p.seg_rows;
-    st.halo = p.halo;
-    st.total_tiles = p.total_tiles;
-    st.dot_psi0 = mom ? 1 : 0;
-    st.dot_self = mom ? 1 : 0;
-    st.rmax = rmax;
+    if (mom) {
+      // moment form: the two newest levels are kept
+      st.slot_out[p.kt - 1] = 2;
+      if (p.kt >= 2) st.slot_out[p.kt - 2] = 3;
+      st.dot_psi0 = 1;
+      st.dot_self = 1;
+    } else {
+      for (int l = 1; l <= p.kt; ++l) st.slot_out[l - 1] = 1 + l;
+    }
     st.partial = d_part;
     double ms = 0;
     CHECK(time_launch(c, [&]() -> csp_status {
-      HIPCALL(launch_spmm(fp64, p.vec, mom, d_spmm, (int)tsp.size(), st, s));
+      HIPCALL(launch_cheb(fp64, p.vec, p.kt, mom, d_spmm, p.runs, st, s));
       return CSP_OK;
     }, &ms));
+    ms /= p.kt;
     ++T.n_candidates;
     if (ms < best_ms) {
       best_ms = ms;
       T.spmm_vec = p.vec;
+      T.spmm_steps = p.kt;
       T.spmm_seg_rows = p.seg_rows;
     }
   }
@@ -1684,20 +1738,22 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
       for (auto& g : groups) Msum += g.M;
       int wg0 = 0;
       for (auto& g : groups) {
-        const int64_t units = fp64 ? ceil_div(g.M, kContractThreads) : ceil_div(ceil_div(g.M, 32), 4);
-        int w = (int)std::llround((double)c->n_cu * wpc * (double)g.M / (double)Msum);
-        w = (int)std::max<int64_t>(1, std::min<int64_t>(w, units));
+        const int64_t N = g.M / g.Rg;
+        const int64_t units = fp64 ? ceil_div(N, kContractThreads) : ceil_div(ceil_div(N, 32), 4);
+        const double share = (double)c->n_cu * wpc * (double)g.M / (double)Msum / g.Rg;
+        const int w = (int)std::max<int64_t>(1, std::min<int64_t>(std::llround(share), units));
         ContractInst C{};
         C.slots = g.slots;
-        C.slot_stride = g.M;
-        C.M = g.M;
+        C.slot_stride = g.stride();
+        C.N = N;
         C.Rg = g.Rg;
+        C.wpc = w;
         C.psi0 = g.psi0g;
         C.carry = g.carry;
         C.partial = d_cpart;   // timing only: instances may share it
         C.wg0 = wg0;
-        C.n_wg = w;
-        wg0 += w;
+        C.n_wg = g.Rg * w;
+        wg0 += C.n_wg;
         ct.push_back(C);
       }
       HIPCALL(hipMemcpyAsync(d_con, ct.data(), sizeof(ContractInst) * ct.size(),
@@ -1759,11 +1815,13 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   T.block_b = 0;
   if (!mom) {
     const int64_t Nt = std::max<int64_t>(P.Nt, 1);
-    const int wg_total = c->n_cu * T.contract_wg_per_cu + (int)groups.size();
-    auto state_ws = [&](int S_, int b) {
+    const int wg_total = c->n_cu * T.contract_wg_per_cu + kMaxGroupCols * (int)groups.size();
+    const int kt_best = std::max(1, T.spmm_steps);
+    auto state_ws = [&](int K_, int b) {
+      const int S_ = std::max(K_ + kt_best, kt_best + 2);
       size_t by = 0;
-      for (auto& g : groups) by += align256((size_t)S_ * g.M * csz) + 2 * align256(g.M * csz);
-      by += align256((size_t)wg_total * b * kMaxGroupCols * 16) * 2;
+      for (auto& g : groups) by += align256((size_t)S_ * g.stride() * csz) + 2 * align256(g.M * csz);
+      by += align256((size_t)wg_total * b * 16) * 2;
       return by + (64u << 20);
     };
     auto cost = [&](int b) -> double {
@@ -1774,8 +1832,8 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
       const int kcap = fp64 ? (1 << 20) : (496 / jt / 16) * 16;
       int K = std::min(Ktot, kcap);
       if (K < Ktot) K = (K / 16) * 16;
-      while (K > 16 && state_ws(std::max(3, K), b) > cap) K = ((K - 1) / 16) * 16;
-      if (state_ws(std::max(3, K), b) > cap) return -1.0;
+      while (K > 16 && state_ws(K, b) > cap) K = ((K - 1) / 16) * 16;
+      if (state_ws(K, b) > cap) return -1.0;
       double us = 0;
       for (int64_t t0 = 0; t0 < Nt; t0 += b) {
         const int bk = (int)std::min<int64_t>(b, Nt - t0);
@@ -1823,6 +1881,40 @@ extern "C" csp_status csp_select_block(csp_context* c, const csp_lattice* L, int
     std::memset(rep, 0, sizeof(*rep));
     rep->block_b = T.block_b;
     for (int k = 0; k < 8; ++k) rep->model_cost[k] = T.model_cost_ms[k];
+  }
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ bandwidth probe
+extern "C" csp_status csp_bandwidth_probe(csp_context* c, uint64_t bytes, double* gbs_out) {
+  if (!c || !gbs_out) return fail(CSP_EINVAL, "NULL argument");
+  bytes = (bytes / 4096) * 4096;
+  if (bytes < (1u << 20)) return fail(CSP_EINVAL, "need at least 1 MiB per array");
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+  CHECK(ws_reserve(c, 3 * bytes + 4096));
+  Carver cv(c->ws);
+  void* a = cv.take(bytes);
+  void* b = cv.take(bytes);
+  void* d = cv.take(bytes);
+  float* sink = (float*)cv.take(4096);
+  const int64_t n16 = (int64_t)(bytes / 16);
+  // defined contents for the reads
+  HIPCALL(launch_probe(1, nullptr, nullptr, a, sink, n16, 4 * c->n_cu, s));
+  HIPCALL(launch_probe(1, nullptr, nullptr, b, sink, n16, 4 * c->n_cu, s));
+  for (int kind = 0; kind < 3; ++kind) {
+    double best = 0.0;
+    for (int wpc = 4; wpc <= 64; wpc *= 2) {
+      const int grid = wpc * c->n_cu;
+      double ms = 0;
+      CHECK(time_launch(c, [&]() -> csp_status {
+        HIPCALL(launch_probe(kind, a, b, d, sink, n16, grid, s));
+        return CSP_OK;
+      }, &ms));
+      const double moved = (kind == 2 ? 3.0 : 1.0) * (double)bytes;
+      best = std::max(best, moved / (ms * 1e-3) / 1e9);
+    }
+    gbs_out[kind] = best;
   }
   return CSP_OK;
 }

@@ -4,6 +4,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 
 #include "csp.h"
@@ -13,7 +15,6 @@ namespace csp {
 // ------------------------------------------------------------------ limits
 constexpr int kMaxGroupCols = 32;     // columns per propagation group (power of 2)
 constexpr int kMaxStepCols = 64;      // columns accepted by the single-step API
-constexpr int kSpmmThreads = 256;     // recursion workgroup
 constexpr int kContractThreads = 256; // contraction workgroup (4 waves)
 constexpr int kMaxJTiles = 2;         // 32-wide time tiles: b <= 64 on MFMA
 constexpr int kMaxFp64B = 16;         // b limit of the FP64 contraction
@@ -91,61 +92,70 @@ __host__ __device__ inline int64_t neighbour(const Geom& g, int64_t s, int k) {
 }
 
 // ------------------------------------------------------------------ recursion
-// One instance of a recursion launch: a lattice and a group of R columns
-// stored [N][R] complex in slots base + slot * slot_stride.
-struct SpmmInst {
-  int32_t kind, px, py, R;
-  int64_t Ly, opr, rowlen;     // rowlen = opr * R complex values
+// Vectors of a column group are column-major, [Rg][N]: column c is values
+// c*N .. c*N + N - 1, a lattice vector in the lattice's orbital order.
+//
+// One instance of a recursion launch: a lattice and a column group, its
+// Chebyshev slots base + slot * slot_stride.
+struct ChebInst {
+  int32_t kind, px, py, Rg;
+  int64_t Ly, opr, N;          // rows, values per row (Lx or 2 Lx), orbitals
+  int64_t n_strips, n_segs;    // work items of one column: strips x row segments
+  int64_t item0;               // first work item (wave) of this instance
   double alpha;                // 2 t / |H|
   double beta0;                // -2 H0 / |H|
   double onsite_scale;         // 2 / |H|
   const void* eps;             // per-orbital on-site energy (float or double), may be null
   void* base;                  // slot array
   int64_t slot_stride;         // complex values between slots
-  const void* src;             // input vector when the step reads from outside the slots
-  const void* psi0;            // psi0 of the group (moment epilogue), [N][R]
-  void* carry_out;             // carried state accumulated by the epilogue, [N][R]
-  int64_t n_strips, n_segs;    // tiling of this instance
-  int64_t tile0;               // first tile of this instance in the launch
+  const void* src;             // phi_n of a block's first launch (slot_cur < 0)
+  const void* psi0;            // psi0 of the group (moment epilogue)
+  void* carry;                 // carried state (moment epilogue, nlev = 1)
 };
 
-// Per-step arguments of a recursion launch.
-struct SpmmStep {
-  int32_t slot_out, slot_cur, slot_prev;
-  int32_t cur_from_src;    // read the current vector from inst.src
-  int32_t copy_cur;        // also write the current vector into slot_cur
-  int32_t has_prev;        // subtract the previous vector (2 H~ x - y form)
-  float scale_f;           // 1 (2 H~ x - y) or 0.5 (H~ x)
-  double scale_d;
-  int32_t seg_rows;        // rows per tile
-  int32_t halo;            // max R over instances (LDS halo width)
-  int64_t total_tiles;
-  // Moment epilogue (moment-based form), used by the MOM kernel variant only.
-  // Per tile and column the workgroup writes four complex FP64 sums:
-  //   0: <psi0|out>   1: <psi0|cur>   2: <out|out>   3: <out|cur>
-  // to partial[((slot * total_tiles + tile) * 4 + kind) * rmax + r].
-  int32_t dot_psi0;        // sums 0 and 1 (reads psi0)
-  int32_t dot_self;        // sums 2 and 3
-  int32_t carry_mode;      // 0 none, 1 carry = cc0 cur + cc out, 2 carry += cc out
-  int32_t mom_slot;
-  int32_t rmax;            // column stride of the partial records
-  int32_t pad1;
-  double cc0[2], cc[2];    // carry coefficients (complex)
-  double* partial;
+// Per-launch arguments: levels l = 1..nlev produce phi_{n+l} from
+// phi_n (slot_cur, or src when slot_cur < 0) and phi_{n-1} (slot_prev).
+struct ChebStep {
+  int32_t nlev;
+  int32_t first;               // block start: phi_1 = H~ phi_0, no phi_{n-1}
+  int32_t slot_cur, slot_prev;
+  int32_t slot_out[8];         // slot receiving level l+1 (-1: not stored)
+  int32_t copy_slot;           // slot receiving phi_n itself (-1: none)
+  int32_t seg_rows;            // rows per work item
+  int32_t ow;                  // owned values per strip (64 V - 2 margin)
+  int32_t dot_psi0, dot_self;  // moment epilogue sums (see k_cheb)
+  int32_t carry_mode;          // 0 none, 1 carry = cc0 phi_n + cc1 phi_{n+1}, 2 carry += cc1 phi_{n+1}
+  int32_t mom_slot;            // launch index inside the partial-sum buffer
+  int32_t pad;
+  double cc0[2], cc1[2];
+  double* partial;             // [slot][KT][items][4] complex records
+  int64_t total_items;
 };
 
-hipError_t launch_spmm(bool fp64, int vec, bool mom, const SpmmInst* d_inst, int n_inst,
-                       const SpmmStep& st, hipStream_t s);
+// Consecutive instances of one lattice class (honeycomb or not, with or
+// without on-site energies) and their work items; one launch per run.
+struct ChebRun {
+  int inst0, n_inst;
+  int64_t item0, n_items;
+  bool honey, eps;
+};
+hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, const ChebInst* d_inst,
+                       const std::vector<ChebRun>& runs, const ChebStep& st, hipStream_t s);
+// (values per lane, steps per launch) pairs with a compiled kernel
+bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom);
+// margin positions per strip side: kt rounded up to a multiple of vec
+int cheb_margin(int vec, int kt);
 
-// Sum the workgroup partials of `n_slots` steps into dots[(n0 + slot)][4][Rg]
-// (complex FP64) per instance, tiles in order.
+// Moment records -> per-step sums dots[row][4][Rg] (complex FP64), rows
+// n0 + slot*kt + level for every record slot and level up to max_row.
 struct MomInst {
-  int64_t tile0, n_tiles;
+  int64_t tile0, n_tiles;      // first work item and work items of the instance
   int32_t Rg, pad;
-  double* dots;            // [n_rows][4][Rg] complex
+  double* dots;                // [n_rows][4][Rg] complex
 };
-hipError_t launch_mom_finish(const MomInst* d_mi, int n_inst, const double* partial,
-                             int64_t total_tiles, int rmax, int n_slots, int n0, hipStream_t s);
+hipError_t launch_cheb_mom_finish(const MomInst* d_mi, int n_inst, const double* partial,
+                                  int64_t total_items, int kt, int n_slots, int n0, int max_row,
+                                  hipStream_t s);
 // Moments of a block from the step sums (halving: doubling identity above h)
 // and correlations corr[(t0 + j) * ldc + col0 + r] = sum_n c_n(j tau) mu_n[r]
 // for j = 1..bk (table a as produced by launch_bessel, row j-1 for x = j tau).
@@ -161,15 +171,18 @@ hipError_t launch_mom_corr(const MomCorrInst* d_mc, int n_inst, int Nk, int halv
                            int64_t t0, int rg_max, hipStream_t s);
 
 // ------------------------------------------------------------------ contraction
+// Every workgroup of an instance works on one column of the group: column
+// c = (workgroup / wpc) with wpc workgroups per column, so its correlation
+// sums belong to that column alone.
 struct ContractInst {
   const void* slots;        // slot array of the group
   int64_t slot_stride;      // complex values
-  int64_t M;                // N * Rg complex values
+  int64_t N;                // values per column
   int32_t Rg;               // columns of the group (power of 2, <= 32)
-  int32_t pad;
-  const void* psi0;         // psi0 of the group [M]
-  void* carry;              // carried state [M]
-  double* partial;          // [n_wg][b][Rg] complex (2 doubles)
+  int32_t wpc;              // workgroups per column
+  const void* psi0;         // psi0 of the group [Rg][N]
+  void* carry;              // carried state [Rg][N]
+  double* partial;          // [n_wg][b] complex (2 doubles), n_wg = Rg * wpc
   int32_t wg0, n_wg;        // workgroups of this instance in the launch
 };
 
@@ -189,12 +202,13 @@ struct ContractArgs {
 hipError_t launch_contract_f32(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s);
 hipError_t launch_contract_f64(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s);
 
-// Finish: corr[(t0 + j) * ldc + col0 + r] = sum_wg partial[wg][j-1][r], j = 1..b.
+// Finish: corr[(t0 + j) * ldc + col0 + c] = sum_{sub < wpc} partial[c * wpc + sub][j-1],
+// j = 1..b, for every column c of the group.
 struct FinishInst {
   const double* partial;
-  int32_t n_wg, Rg;
+  int32_t wpc, Rg;
   double* corr;             // device correlation array of the instance
-  int64_t ldc;              // R of the instance
+  int64_t ldc;              // columns of the caller's correlation array
   int32_t col0;
   int32_t pad;
 };
@@ -258,6 +272,11 @@ hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const
 hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth,
                       double tau_tilde, int window, double* d_E, double* d_D, double* d_Dmean,
                       double* d_twiddle, hipStream_t s);
+
+// ------------------------------------------------------------------ probe
+// kind 0: read a, 1: write c, 2: c = 2a - b; n16 = 16-byte elements.
+hipError_t launch_probe(int kind, const void* a, const void* b, void* c, float* sink, int64_t n16,
+                        int grid, hipStream_t s);
 
 // ------------------------------------------------------------------ helpers
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

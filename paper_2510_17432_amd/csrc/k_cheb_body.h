@@ -1,0 +1,543 @@
+// Chebyshev recursion (amxsy of Sec. II.B), several steps per pass over
+// memory:  phi_{n+l} = 2 H~ phi_{n+l-1} - phi_{n+l-2},  l = 1..nlev (nlev <=
+// KT), with H~ = (H - H0)/|H| the rescaled lattice Hamiltonian of Sec. II.A
+// applied as a stencil (no matrix in memory).  The first step of a time
+// block is phi_1 = H~ phi_0.
+//
+// Layout.  A column group is stored column-major, [Rg][N]: column c of the
+// group is one lattice vector of N values, rows of `opr` values in the
+// orbital order of the lattice, so the in-row stencil neighbours are at +-1
+// and the vertical ones one row up or down.
+//
+// Work decomposition.  One wave (64 lanes) owns a strip of a row segment of
+// one column and is independent of every other wave: no LDS, no barriers.
+// Lane l holds the V consecutive positions p0 + V l .. p0 + V l + V - 1 of
+// the strip, so a lane loads and stores V values with wide accesses and the
+// whole wave touches 64 V consecutive values.  In-row neighbours are in the
+// lane's own registers except at its two ends, which come from the adjacent
+// lane by a DPP wavefront shift.  On the honeycomb lattice the vertical
+// partner of an orbital is the other orbital of its (even, odd) pair one row
+// up or down, which is in the same lane (V is even, p0 is even).
+//
+// The strip covers [os - MG, os - MG + 64 V); each level is valid one
+// position further inside on each side than the one before, so after up to
+// KT <= MG levels the owned positions [os, os + 64 V - 2 MG) are exact and
+// neighbouring strips overlap by 2 MG positions that both compute (the
+// redundant-margin form of temporal blocking).  MG is KT rounded up to a
+// multiple of V, so every lane is either wholly owned or wholly margin.
+// The wave marches down the rows y0 - nlev .. y1 + nlev - 1 of its segment
+// keeping, for every level, the last three rows in registers; level l
+// computes row r0 - l while level 0 loads row r0, so all levels advance
+// together and only the owned rows [y0, y1) of every level are written.
+// Per pass the memory traffic is one read of phi_n and phi_{n-1} (plus the
+// 2 nlev-row segment margins) and one write per level kept, instead of two
+// reads and one write per step.
+//
+// Moment variant (MOM, moment-based form of Sec. II.A): for every level and
+// owned value the epilogue accumulates <psi0|phi_{n+l}>, <psi0|phi_n> (first
+// level only), <phi_{n+l}|phi_{n+l}> and <phi_{n+l}|phi_{n+l-1}> (the halving
+// identity of Eq. cheby_prod): products over the V values of a lane in the
+// working precision, then FP64 sums over rows; each wave reduces with a
+// fixed butterfly and writes one record per level, so the sums do not depend
+// on the run.  With nlev = 1 it can also accumulate the carried state
+// s_{k+1} = sum_n c_n phi_n of a time block.
+#pragma once
+
+#include "csp_internal.h"
+
+#define CSP_GLOBAL __attribute__((address_space(1)))
+
+namespace csp {
+namespace cheb {
+
+template <typename T> struct cx {
+  T x, y;
+};
+
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(8)));
+typedef float f32x2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef float f32x4w __attribute__((ext_vector_type(4), aligned(4)));
+typedef double f64x2u __attribute__((ext_vector_type(2), aligned(8)));
+
+// ---- V consecutive complex values of one lane (T units: 2 per value)
+template <int V>
+__device__ __forceinline__ void ldv(const CSP_GLOBAL float* p, cx<float> (&d)[V]) {
+  const CSP_GLOBAL f32x4u* q = reinterpret_cast<const CSP_GLOBAL f32x4u*>(p);
+#pragma unroll
+  for (int k = 0; k < V / 2; ++k) {
+    const f32x4u t = q[k];
+    d[2 * k] = {t.x, t.y};
+    d[2 * k + 1] = {t.z, t.w};
+  }
+}
+template <int V>
+__device__ __forceinline__ void stv(CSP_GLOBAL float* p, const cx<float> (&d)[V]) {
+  CSP_GLOBAL f32x4u* q = reinterpret_cast<CSP_GLOBAL f32x4u*>(p);
+#pragma unroll
+  for (int k = 0; k < V / 2; ++k) {
+    f32x4u t;
+    t.x = d[2 * k].x;
+    t.y = d[2 * k].y;
+    t.z = d[2 * k + 1].x;
+    t.w = d[2 * k + 1].y;
+    q[k] = t;
+  }
+}
+template <int V>
+__device__ __forceinline__ void ldv(const CSP_GLOBAL double* p, cx<double> (&d)[V]) {
+  const CSP_GLOBAL f64x2u* q = reinterpret_cast<const CSP_GLOBAL f64x2u*>(p);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const f64x2u t = q[v];
+    d[v] = {t.x, t.y};
+  }
+}
+template <int V>
+__device__ __forceinline__ void stv(CSP_GLOBAL double* p, const cx<double> (&d)[V]) {
+  CSP_GLOBAL f64x2u* q = reinterpret_cast<CSP_GLOBAL f64x2u*>(p);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    f64x2u t;
+    t.x = d[v].x;
+    t.y = d[v].y;
+    q[v] = t;
+  }
+}
+__device__ __forceinline__ cx<float> ld1(const CSP_GLOBAL float* p) {
+  const f32x2u t = *reinterpret_cast<const CSP_GLOBAL f32x2u*>(p);
+  return {t.x, t.y};
+}
+__device__ __forceinline__ void st1(CSP_GLOBAL float* p, cx<float> v) {
+  f32x2u t;
+  t.x = v.x;
+  t.y = v.y;
+  *reinterpret_cast<CSP_GLOBAL f32x2u*>(p) = t;
+}
+__device__ __forceinline__ cx<double> ld1(const CSP_GLOBAL double* p) {
+  const f64x2u t = *reinterpret_cast<const CSP_GLOBAL f64x2u*>(p);
+  return {t.x, t.y};
+}
+__device__ __forceinline__ void st1(CSP_GLOBAL double* p, cx<double> v) {
+  f64x2u t;
+  t.x = v.x;
+  t.y = v.y;
+  *reinterpret_cast<CSP_GLOBAL f64x2u*>(p) = t;
+}
+// V consecutive on-site energies
+template <int V>
+__device__ __forceinline__ void ldr(const CSP_GLOBAL float* p, float (&d)[V]) {
+  if constexpr (V == 4) {
+    const f32x4w t = *reinterpret_cast<const CSP_GLOBAL f32x4w*>(p);
+    d[0] = t.x;
+    d[1] = t.y;
+    d[2] = t.z;
+    d[3] = t.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < V / 2; ++k) {
+      const f32x2u t = reinterpret_cast<const CSP_GLOBAL f32x2u*>(p)[k];
+      d[2 * k] = t.x;
+      d[2 * k + 1] = t.y;
+    }
+  }
+}
+template <int V>
+__device__ __forceinline__ void ldr(const CSP_GLOBAL double* p, double (&d)[V]) {
+#pragma unroll
+  for (int k = 0; k < V / 2; ++k) {
+    const f64x2u t = reinterpret_cast<const CSP_GLOBAL f64x2u*>(p)[k];
+    d[2 * k] = t.x;
+    d[2 * k + 1] = t.y;
+  }
+}
+
+// ---- wavefront shifts by one lane (DPP): lane l receives lane l - 1 (shr)
+// or lane l + 1 (shl); the lane without a source receives 0.
+__device__ __forceinline__ int dpp_shr1_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int dpp_shl1_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float shr1(float x) {
+  return __builtin_bit_cast(float, dpp_shr1_i(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ float shl1(float x) {
+  return __builtin_bit_cast(float, dpp_shl1_i(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double shr1(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)dpp_shr1_i((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_shr1_i((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double shl1(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)dpp_shl1_i((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_shl1_i((int)(unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int V, int KT> struct Shape {
+  static constexpr int MG = ((KT + V - 1) / V) * V;   // margin positions per side
+  static constexpr int OW = 64 * V - 2 * MG;          // owned positions per strip
+};
+
+// insts: the instances of this launch (consecutive items item_lo..item_hi-1).
+template <typename T, int V, int KT, bool HONEY, bool EPS, bool MOM>
+__global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts, int n_inst,
+                                              int64_t item_lo, int64_t item_hi, ChebStep st) {
+  static_assert(V % 2 == 0, "lanes hold whole (even, odd) orbital pairs");
+  using C = cx<T>;
+  using gT = CSP_GLOBAL T;
+  constexpr int MG = Shape<V, KT>::MG;
+  constexpr int OW = Shape<V, KT>::OW;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int64_t item = item_lo + xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (item >= item_hi) return;                     // a whole wave; no barriers below
+  int ii = 0;
+  while (ii + 1 < n_inst && item >= insts[ii + 1].item0) ++ii;
+  const ChebInst& I = insts[ii];
+
+  // ---- geometry of this work item (wave-uniform)
+  const int64_t per_col = I.n_strips * I.n_segs;
+  const int64_t local = item - I.item0;
+  const int64_t col = local / per_col;
+  const int64_t rem = local - col * per_col;
+  const int64_t seg = rem / I.n_strips;
+  const int64_t strip = rem - seg * I.n_strips;
+  const int64_t opr = I.opr, Ly = I.Ly;
+  const int64_t os = strip * OW;                     // first owned position
+  const int64_t p0 = os - MG;                        // first position of the strip
+  const bool fast = p0 >= 0 && p0 + 64 * V <= opr;   // no wrap, every position a site
+  const int64_t y0 = seg * st.seg_rows;
+  const int64_t y1 = (y0 + st.seg_rows < Ly) ? y0 + st.seg_rows : Ly;
+  const int nlev = st.nlev;
+  const int py = I.py;
+  const int64_t coff = 2 * col * I.N;                // column offset in T units
+
+  // ---- per-lane positions
+  const int lq = V * lane;
+  const bool lane_own = lq >= MG && lq < MG + OW;
+  int wpos[V];          // position inside the row (wrapped), valid when present
+  bool pres[V];         // position is a site of the lattice
+  bool own[V];          // position owned by this strip
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int64_t p = p0 + lq + v;
+    if (I.px) {
+      int64_t w = p % opr;
+      if (w < 0) w += opr;
+      wpos[v] = static_cast<int>(w);
+      pres[v] = true;
+    } else {
+      pres[v] = p >= 0 && p < opr;
+      wpos[v] = pres[v] ? static_cast<int>(p) : 0;
+    }
+    own[v] = lane_own && p >= 0 && p < opr;
+  }
+  auto row_of = [&](int64_t r, bool& present) -> int64_t {
+    if (py) {
+      while (r < 0) r += Ly;
+      while (r >= Ly) r -= Ly;
+      present = true;
+      return r;
+    }
+    present = r >= 0 && r < Ly;
+    return r;
+  };
+
+  gT* base = (gT*)(I.base);
+  const gT* curv = (st.slot_cur < 0 ? (const gT*)(I.src)
+                                    : base + 2 * (int64_t)st.slot_cur * I.slot_stride) + coff;
+  const gT* prevv = st.first ? nullptr : base + 2 * (int64_t)st.slot_prev * I.slot_stride + coff;
+  gT* copyv = st.copy_slot >= 0 ? base + 2 * (int64_t)st.copy_slot * I.slot_stride + coff
+                                : nullptr;
+  const gT* eps = (const gT*)(I.eps);
+  const gT* psi0 = (const gT*)(I.psi0) + coff;
+  gT* carry = MOM && I.carry ? (gT*)(I.carry) + coff : nullptr;
+
+  auto load_row = [&](const gT* vec, int64_t r, C (&d)[V]) {
+    bool rp;
+    const int64_t rw = row_of(r, rp);
+    if (!rp) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) d[v] = {T(0), T(0)};
+      return;
+    }
+    const gT* rowp = vec + 2 * rw * opr;
+    if (fast) {
+      ldv<V>(rowp + 2 * p0 + 2 * lq, d);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) d[v] = pres[v] ? ld1(rowp + 2 * wpos[v]) : C{T(0), T(0)};
+    }
+  };
+  auto load_eps = [&](int64_t r, T (&d)[V]) {
+    bool rp;
+    const int64_t rw = row_of(r, rp);
+    if (!rp) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) d[v] = T(0);
+      return;
+    }
+    const gT* rowp = eps + rw * opr;
+    if (fast) {
+      ldr<V>(rowp + p0 + lq, d);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) d[v] = pres[v] ? rowp[wpos[v]] : T(0);
+    }
+  };
+  // row rw must be inside [0, Ly)
+  auto store_row = [&](gT* vec, int64_t rw, const C (&o)[V]) {
+    gT* rowp = vec + 2 * rw * opr;
+    if (fast) {
+      if (lane_own) stv<V>(rowp + 2 * p0 + 2 * lq, o);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (own[v]) st1(rowp + 2 * wpos[v], o[v]);
+    }
+  };
+
+  // ---- register rows: lo/mid/hi = the last three rows of levels 0..KT-1
+  C lo[KT][V], mid[KT][V], hi[KT][V];
+#pragma unroll
+  for (int l = 0; l < KT; ++l)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      lo[l][v] = {T(0), T(0)};
+      mid[l][v] = {T(0), T(0)};
+      hi[l][v] = {T(0), T(0)};
+    }
+  T er[EPS ? KT + 1 : 1][V];                         // on-site energies of rows r0 - k
+#pragma unroll
+  for (int k = 0; k < (EPS ? KT + 1 : 1); ++k)
+#pragma unroll
+    for (int v = 0; v < V; ++v) er[k][v] = T(0);
+
+  // moment sums: [0,1] <psi0|out>, [2] |out|^2, [3,4] <out|cur>; and
+  // <psi0|cur> of the first level
+  double acc[MOM ? KT : 1][5];
+  double acc_c[2] = {0.0, 0.0};
+#pragma unroll
+  for (int l = 0; l < (MOM ? KT : 1); ++l)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[l][k] = 0.0;
+
+  const T alpha = static_cast<T>(I.alpha);
+  const T beta0 = static_cast<T>(I.beta0);
+  const T oscale = static_cast<T>(I.onsite_scale);
+  const bool vert = I.kind != CSP_CHAIN;
+
+  const int64_t n_iter = (y1 - y0) + 2 * nlev;
+  const int64_t rbase = y0 - nlev;                   // level-0 row of iteration 0
+  C ncur[V], nprev[V], pv[V];
+  T neps[V];
+  load_row(curv, rbase, ncur);
+  if (prevv) {
+    load_row(prevv, rbase - 1, nprev);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) nprev[v] = {T(0), T(0)};
+  }
+  if constexpr (EPS) load_eps(rbase, neps);
+
+#pragma unroll 1
+  for (int64_t i = 0; i < n_iter; ++i) {
+    const int64_t r0 = rbase + i;
+    // level 0 takes row r0
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      lo[0][v] = mid[0][v];
+      mid[0][v] = hi[0][v];
+      hi[0][v] = ncur[v];
+      pv[v] = nprev[v];
+    }
+    if constexpr (EPS) {
+#pragma unroll
+      for (int k = KT; k >= 1; --k)
+#pragma unroll
+        for (int v = 0; v < V; ++v) er[k][v] = er[k - 1][v];
+#pragma unroll
+      for (int v = 0; v < V; ++v) er[0][v] = neps[v];
+    }
+    if (i + 1 < n_iter) {
+      load_row(curv, r0 + 1, ncur);
+      if (prevv) load_row(prevv, r0, nprev);
+      if constexpr (EPS) load_eps(r0 + 1, neps);
+    }
+    // phi_n itself for the contraction (order 0 of a block)
+    if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0]);
+
+#pragma unroll
+    for (int l = 1; l <= KT; ++l) {
+      if (l > nlev || i < 2 * l) break;
+      const int64_t r = r0 - l;
+      bool rp;
+      const int64_t rw = row_of(r, rp);
+      const T scale = (l == 1 && st.first) ? T(0.5) : T(1);
+      const T as = scale * alpha, bs = scale * beta0, os_ = scale * oscale;
+      // level l-1 rows r - 1, r, r + 1 and level l-2 row r (phi_{n+l-2})
+      const C(&up)[V] = lo[l - 1];
+      const C(&c)[V] = mid[l - 1];
+      const C(&dn)[V] = hi[l - 1];
+      C o[V];
+      if (rp) {
+        const T lx = shr1(c[V - 1].x), ly = shr1(c[V - 1].y);
+        const T rx = shl1(c[0].x), ry = shl1(c[0].y);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T nx = (v > 0 ? c[v - 1].x : lx) + (v < V - 1 ? c[v + 1].x : rx);
+          T ny = (v > 0 ? c[v - 1].y : ly) + (v < V - 1 ? c[v + 1].y : ry);
+          if constexpr (HONEY) {
+            // even orbital: partner one row up (pos + 1); odd: one row down (pos - 1)
+            if (v % 2 == 0) {
+              nx += up[v + 1].x;
+              ny += up[v + 1].y;
+            } else {
+              nx += dn[v - 1].x;
+              ny += dn[v - 1].y;
+            }
+          } else {
+            if (vert) {
+              nx += up[v].x + dn[v].x;
+              ny += up[v].y + dn[v].y;
+            }
+          }
+          const C p = l == 1 ? pv[v] : lo[l - 2 >= 0 ? l - 2 : 0][v];
+          T beta = bs;
+          if constexpr (EPS) beta = bs + os_ * er[l][v];
+          o[v].x = as * nx + (beta * c[v].x - p.x);
+          o[v].y = as * ny + (beta * c[v].y - p.y);
+        }
+        if (!fast) {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (!pres[v]) o[v] = {T(0), T(0)};
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = {T(0), T(0)};
+      }
+      if (l < KT) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          lo[l][v] = mid[l][v];
+          mid[l][v] = hi[l][v];
+          hi[l][v] = o[v];
+        }
+      }
+      if (r >= y0 && r < y1) {
+        const int so = st.slot_out[l - 1];
+        if (so >= 0) store_row(base + 2 * (int64_t)so * I.slot_stride + coff, rw, o);
+        if constexpr (MOM) {
+          if (st.dot_psi0 || st.dot_self) {
+            C q[V];
+            if (st.dot_psi0) load_row(psi0, r, q);
+            T s[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              if (!own[v]) continue;
+              s[0] += q[v].x * o[v].x + q[v].y * o[v].y;
+              s[1] += q[v].x * o[v].y - q[v].y * o[v].x;
+              s[2] += o[v].x * o[v].x + o[v].y * o[v].y;
+              s[3] += o[v].x * c[v].x + o[v].y * c[v].y;
+              s[4] += o[v].x * c[v].y - o[v].y * c[v].x;
+              if (l == 1) {
+                s[5] += q[v].x * c[v].x + q[v].y * c[v].y;
+                s[6] += q[v].x * c[v].y - q[v].y * c[v].x;
+              }
+            }
+            if (st.dot_psi0) {
+              acc[l - 1][0] += static_cast<double>(s[0]);
+              acc[l - 1][1] += static_cast<double>(s[1]);
+              if (l == 1) {
+                acc_c[0] += static_cast<double>(s[5]);
+                acc_c[1] += static_cast<double>(s[6]);
+              }
+            }
+            if (st.dot_self) {
+              acc[l - 1][2] += static_cast<double>(s[2]);
+              acc[l - 1][3] += static_cast<double>(s[3]);
+              acc[l - 1][4] += static_cast<double>(s[4]);
+            }
+          }
+          if (l == 1 && st.carry_mode && carry) {
+            const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
+            const T c1r = static_cast<T>(st.cc1[0]), c1i = static_cast<T>(st.cc1[1]);
+            C b[V];
+            if (st.carry_mode == 1) {
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                b[v].x = c0r * c[v].x - c0i * c[v].y;
+                b[v].y = c0r * c[v].y + c0i * c[v].x;
+              }
+            } else {
+              load_row(carry, r, b);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              b[v].x += c1r * o[v].x - c1i * o[v].y;
+              b[v].y += c1r * o[v].y + c1i * o[v].x;
+            }
+            store_row(carry, rw, b);
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (MOM) {
+    if (st.dot_psi0 || st.dot_self) {
+      // fixed butterfly over the 64 lanes, then lane 0 writes one record per
+      // level: [kind][re, im], kinds <psi0|out>, <psi0|cur>, <out|out>, <out|cur>
+      auto wsum = [&](double x) {
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+        return x;
+      };
+      const double c0 = wsum(acc_c[0]), c1 = wsum(acc_c[1]);
+#pragma unroll
+      for (int l = 0; l < KT; ++l) {
+        if (l >= nlev) break;
+        double rec[8];
+        rec[0] = wsum(acc[l][0]);
+        rec[1] = wsum(acc[l][1]);
+        rec[2] = l == 0 ? c0 : 0.0;
+        rec[3] = l == 0 ? c1 : 0.0;
+        rec[4] = wsum(acc[l][2]);
+        rec[5] = 0.0;
+        rec[6] = wsum(acc[l][3]);
+        rec[7] = wsum(acc[l][4]);
+        if (lane == 0) {
+          double* out = st.partial + (((int64_t)st.mom_slot * KT + l) * st.total_items + item) * 8;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) out[k] = rec[k];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace cheb
+}  // namespace csp
+
+// Launch helper for one instantiation file: (V, KT) pairs are listed by the
+// including file.
+#define CSP_CHEB_LAUNCH(T, V, KT, MOM)                                                         \
+  do {                                                                                         \
+    if (honey) {                                                                               \
+      if (eps) hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, true, true, MOM>), grid, block, 0, s, \
+                                  d_inst, n_inst, item_lo, item_hi, st);                       \
+      else hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, true, false, MOM>), grid, block, 0, s,    \
+                              d_inst, n_inst, item_lo, item_hi, st);                           \
+    } else {                                                                                   \
+      if (eps) hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, false, true, MOM>), grid, block, 0,   \
+                                  s, d_inst, n_inst, item_lo, item_hi, st);                    \
+      else hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, false, false, MOM>), grid, block, 0, s,   \
+                              d_inst, n_inst, item_lo, item_hi, st);                           \
+    }                                                                                          \
+  } while (0)

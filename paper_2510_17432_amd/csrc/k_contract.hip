@@ -15,13 +15,19 @@
 // plain FP32 FMAs on the same loaded values, since its error would feed
 // every later block.
 //
-// One wave owns one 32-value tile at a time: lane (i = lane%32, h = lane/32)
-// loads value i of orders 8h..8h+7 of each 16-order step (coalesced: for a
-// fixed order the 32 lanes read 256 contiguous bytes).  The B operand (lane
-// (j, h) holds time j, orders 8h..8h+7) is staged in LDS once per launch.
-// The accumulator holds psi for rows 8(v/4) + 4h + v%4 and time lane%32; the
-// epilogue multiplies by conj(psi0) and accumulates per lane, then the
-// workgroup reduces in FP64 in a fixed order and writes its partial sums.
+// Every workgroup works on one column of the group (groups are stored
+// column-major, [Rg][N]), so all of its correlation sums belong to that
+// column.  One wave owns one 32-value tile of the column at a time: lane
+// (i = lane%32, h = lane/32) loads value i of orders 8h..8h+7 of each
+// 16-order step (coalesced: for a fixed order the 32 lanes read 256
+// contiguous bytes), with the next step's values already in flight.  The B
+// operand (lane (j, h) holds time j, orders 8h..8h+7) is staged in LDS once
+// per launch.  The accumulator holds psi for rows 8(v/4) + 4h + v%4 and time
+// lane%32; the epilogue multiplies by conj(psi0) and accumulates per lane,
+// then the workgroup reduces in FP64 in a fixed order and writes its partial
+// sums, one per time point.
+#include <algorithm>
+
 #include "csp_internal.h"
 
 namespace csp {
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
   const int nb_entries = n_kb * JT * 64;
   BopEntry* sb = reinterpret_cast<BopEntry*>(smem);
   const size_t bop_sz = sizeof(BopEntry) * (size_t)nb_entries;
-  const size_t red_sz = sizeof(double2) * JT * 32 * kMaxGroupCols;
+  const size_t red_sz = sizeof(double2) * JT * 32;
   float* sc = reinterpret_cast<float*>(smem + (bop_sz > red_sz ? bop_sz : red_sz));
   double2* sred = reinterpret_cast<double2*>(smem);
 
@@ -67,12 +73,13 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const ContractInst& I = insts[ii];
   const int64_t wgl = wg - I.wg0;
-  const float2* slots = static_cast<const float2*>(I.slots);
-  const float2* psi0 = static_cast<const float2*>(I.psi0);
-  float2* carry = static_cast<float2*>(I.carry);
-  const int64_t M = I.M;
-  const int64_t n_tiles = ceil_div(M, 32);
-  const int Rg = I.Rg;
+  const int64_t col = wgl / I.wpc, sub = wgl - col * I.wpc;
+  const int64_t N = I.N;
+  const int64_t coff = col * N;
+  const float2* slots = static_cast<const float2*>(I.slots) + coff;
+  const float2* psi0 = static_cast<const float2*>(I.psi0) + coff;
+  float2* carry = static_cast<float2*>(I.carry) + coff;
+  const int64_t n_tiles = ceil_div(N, 32);
 
   float pr[JT][16], pi[JT][16];
 #pragma unroll
@@ -80,10 +87,10 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
 #pragma unroll
     for (int v = 0; v < 16; ++v) { pr[jt][v] = 0.f; pi[jt][v] = 0.f; }
 
-  const int64_t stride_tiles = (int64_t)I.n_wg * 4;
-  for (int64_t tile = wgl * 4 + wave; tile < n_tiles; tile += stride_tiles) {
+  const int64_t stride_tiles = (int64_t)I.wpc * 4;
+  for (int64_t tile = sub * 4 + wave; tile < n_tiles; tile += stride_tiles) {
     const int64_t m = tile * 32 + il;
-    const bool mv = m < M;
+    const bool mv = m < N;
     f32x16 accR[JT], accI[JT];
 #pragma unroll
     for (int jt = 0; jt < JT; ++jt)
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t mm = tile * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-      const float2 p0 = mm < M ? psi0[mm] : make_float2(0.f, 0.f);
+      const float2 p0 = mm < N ? psi0[mm] : make_float2(0.f, 0.f);
 #pragma unroll
       for (int jt = 0; jt < JT; ++jt) {
         const float re = accR[jt][v], im = accI[jt][v];
@@ -170,31 +177,37 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
     }
   }
 
-  // Workgroup reduction in FP64, fixed order: waves 0..3, half-waves 0, 1.
+  // Workgroup reduction in FP64, fixed order: per lane over its 16 rows,
+  // then waves 0..3 and half-waves 0, 1 into sred[time].
   __syncthreads();  // LDS B operands are no longer needed
-  const int nred = JT * 32 * Rg;
-  for (int e = tid; e < nred; e += kContractThreads) sred[e] = make_double2(0.0, 0.0);
+  for (int e = tid; e < JT * 32; e += kContractThreads) sred[e] = make_double2(0.0, 0.0);
   __syncthreads();
+  double sx[JT], sy[JT];
+#pragma unroll
+  for (int jt = 0; jt < JT; ++jt) {
+    sx[jt] = 0.0;
+    sy[jt] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      sx[jt] += static_cast<double>(pr[jt][v]);
+      sy[jt] += static_cast<double>(pi[jt][v]);
+    }
+  }
   for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-      for (int half = 0; half < 2; ++half) {
-        if (h == half) {
+    for (int half = 0; half < 2; ++half) {
+      if (wave == w && h == half) {
 #pragma unroll
-          for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const int r = (8 * (v >> 2) + 4 * h + (v & 3)) & (Rg - 1);
-              double2& d = sred[(jt * 32 + il) * Rg + r];
-              d.x += static_cast<double>(pr[jt][v]);
-              d.y += static_cast<double>(pi[jt][v]);
-            }
+        for (int jt = 0; jt < JT; ++jt) {
+          double2& d = sred[jt * 32 + il];
+          d.x += sx[jt];
+          d.y += sy[jt];
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  double2* part = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols * Rg;
-  for (int e = tid; e < a.bcols * Rg; e += kContractThreads) {
+  double2* part = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols;
+  for (int e = tid; e < a.bcols; e += kContractThreads) {
     const double2 v = sred[e];
     if (a.first_chunk) {
       part[e] = v;
@@ -208,7 +221,8 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
 }
 
 // FP64 contraction: one value per thread, B (<= 16) time columns in
-// registers, complex coefficients c[n][j] in LDS.
+// registers, complex coefficients c[n][j] in LDS; each workgroup works on
+// one column.
 template <int B>
 __global__ __launch_bounds__(kContractThreads) void k_contract_f64(
     const ContractInst* __restrict__ insts, ContractArgs a) {
@@ -233,18 +247,19 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f64(
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const ContractInst& I = insts[ii];
   const int64_t wgl = wg - I.wg0;
-  const double2* slots = static_cast<const double2*>(I.slots);
-  const double2* psi0 = static_cast<const double2*>(I.psi0);
-  double2* carry = static_cast<double2*>(I.carry);
-  const int64_t M = I.M;
-  const int Rg = I.Rg;
+  const int64_t col = wgl / I.wpc, sub = wgl - col * I.wpc;
+  const int64_t N = I.N;
+  const int64_t coff = col * N;
+  const double2* slots = static_cast<const double2*>(I.slots) + coff;
+  const double2* psi0 = static_cast<const double2*>(I.psi0) + coff;
+  double2* carry = static_cast<double2*>(I.carry) + coff;
 
   double2 part[B];
 #pragma unroll
   for (int j = 0; j < B; ++j) part[j] = make_double2(0.0, 0.0);
 
-  const int64_t step = (int64_t)I.n_wg * kContractThreads;
-  for (int64_t m = wgl * kContractThreads + tid; m < M; m += step) {
+  const int64_t step = (int64_t)I.wpc * kContractThreads;
+  for (int64_t m = sub * kContractThreads + tid; m < N; m += step) {
     double2 acc[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[j] = make_double2(0.0, 0.0);
@@ -275,19 +290,18 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f64(
     }
   }
 
-  // Thread tid always sees column tid % Rg (the element stride is a multiple
-  // of 256 and Rg divides 256): reduce over tid = r, r + Rg, ... in order.
-  double2* outp = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols * Rg;
+  // Sum over the 256 threads in order (FP64).
+  double2* outp = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols;
   for (int j = 0; j < a.bcols && j < B; ++j) {
     sred[tid] = part[j];
     __syncthreads();
-    if (tid < Rg) {
+    if (tid == 0) {
       double2 s = make_double2(0.0, 0.0);
-      for (int k = tid; k < kContractThreads; k += Rg) {
+      for (int k = 0; k < kContractThreads; ++k) {
         s.x += sred[k].x;
         s.y += sred[k].y;
       }
-      double2* d = outp + (int64_t)j * Rg + tid;
+      double2* d = outp + j;
       if (a.first_chunk) {
         *d = s;
       } else {
@@ -304,7 +318,7 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f64(
 hipError_t launch_contract_f32(const ContractInst* d_inst, const ContractArgs& a, hipStream_t s) {
   if (a.total_wg <= 0 || a.n_cnt <= 0) return hipSuccess;
   const size_t bsz = bop_bytes(a.jtiles, a.n_cnt);
-  const size_t rsz = sizeof(double2) * a.jtiles * 32 * kMaxGroupCols;
+  const size_t rsz = sizeof(double2) * a.jtiles * 32;
   const size_t lds = (bsz > rsz ? bsz : rsz) + sizeof(float) * 16 * ceil_div(a.n_cnt, 16);
   const dim3 grid(a.total_wg), block(kContractThreads);
   if (a.jtiles == 1)
@@ -334,7 +348,7 @@ hipError_t launch_contract_f64(const ContractInst* d_inst, const ContractArgs& a
   return hipGetLastError();
 }
 
-// Sum the workgroup partials of every instance in workgroup order (FP64).
+// Sum the workgroup partials of every column in workgroup order (FP64).
 // The block's first time index comes from t0_dev[0] when it is given (a
 // block replayed from a HIP graph), else from t0.
 __global__ void k_finish(const FinishInst* __restrict__ insts, int n_inst, int bcols,
@@ -345,16 +359,16 @@ __global__ void k_finish(const FinishInst* __restrict__ insts, int n_inst, int b
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= bcols * I.Rg) return;
   if (t0_dev) t0 = t0_dev[0];
-  const int j = e / I.Rg, r = e - j * I.Rg;
+  const int j = e / I.Rg, c = e - j * I.Rg;
   const double2* p = reinterpret_cast<const double2*>(I.partial);
   double sx = 0.0, sy = 0.0;
-  for (int w = 0; w < I.n_wg; ++w) {
-    const double2 v = p[(int64_t)w * bcols * I.Rg + e];
+  for (int w = 0; w < I.wpc; ++w) {
+    const double2 v = p[((int64_t)c * I.wpc + w) * bcols + j];
     sx += v.x;
     sy += v.y;
   }
-  double2* c = reinterpret_cast<double2*>(I.corr);
-  c[(t0 + 1 + j) * I.ldc + I.col0 + r] = make_double2(sx, sy);
+  double2* cr = reinterpret_cast<double2*>(I.corr);
+  cr[(t0 + 1 + j) * I.ldc + I.col0 + c] = make_double2(sx, sy);
 }
 
 hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_t t0,

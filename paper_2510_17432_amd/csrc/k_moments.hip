@@ -10,56 +10,6 @@
 
 namespace csp {
 
-// One workgroup per (step slot, instance).  Thread t handles value
-// t % (8 Rg) of the record (kind, column, re/im) for the tiles
-// lane, lane + lanes, ... with lane = t / (8 Rg); the lanes are then added in
-// order.
-__global__ __launch_bounds__(256) void k_mom_finish(const MomInst* __restrict__ mi,
-                                                    const double* __restrict__ partial,
-                                                    int64_t total_tiles, int rmax, int n0) {
-  __shared__ double red[256];
-  const int slot = blockIdx.x;
-  const MomInst& M = mi[blockIdx.y];
-  const int nval = 8 * M.Rg;              // doubles per record used
-  const int lanes = 256 / nval;           // Rg <= 32 -> at least one lane
-  const int t = threadIdx.x;
-  const int lane = t / nval, vi = t - lane * nval;
-  double s = 0.0;
-  if (lane < lanes) {
-    const int kind = vi / (2 * M.Rg);
-    const int rem = vi - kind * 2 * M.Rg;
-    const int off = (kind * rmax + (rem >> 1)) * 2 + (rem & 1);
-    const double* base = partial + ((int64_t)slot * total_tiles + M.tile0) * 4 * rmax * 2 + off;
-    const int64_t rec = 4 * rmax * 2;
-    // eight interleaved sums keep eight loads in flight; they are added in
-    // a fixed order, so the result does not depend on the run
-    double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t tl = lane;
-    for (; tl + 7 * lanes < M.n_tiles; tl += 8 * lanes) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] += base[(tl + u * lanes) * rec];
-    }
-    for (int u = 0; tl < M.n_tiles; tl += lanes, ++u) q[u & 7] += base[tl * rec];
-    s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
-  }
-  red[t] = s;
-  __syncthreads();
-  if (t < nval) {
-    double sum = 0.0;
-    for (int l = 0; l < lanes; ++l) sum += red[l * nval + t];
-    // dots row n0 + slot, layout [kind][Rg][re, im] == the record order
-    M.dots[((int64_t)(n0 + slot)) * nval + t] = sum;
-  }
-}
-
-hipError_t launch_mom_finish(const MomInst* d_mi, int n_inst, const double* partial,
-                             int64_t total_tiles, int rmax, int n_slots, int n0, hipStream_t s) {
-  if (n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mom_finish, dim3(n_slots, n_inst), dim3(256), 0, s, d_mi, partial,
-                     total_tiles, rmax, n0);
-  return hipGetLastError();
-}
-
 // mu_n for n = 0..Nk of one instance.  dots row n holds the sums of the step
 // that produced order n: [0] <psi0|phi_n>, [1] <psi0|phi_{n-1}>,
 // [2] <phi_n|phi_n>, [3] <phi_n|phi_{n-1}>.

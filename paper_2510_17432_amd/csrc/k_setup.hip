@@ -138,13 +138,16 @@ hipError_t launch_site_states(int64_t N, int n, const int64_t* d_sites, int dtyp
 }
 
 // ------------------------------------------------------------------ column groups
+// A column group is stored column-major, [Rg][N]: column c of the group is
+// values c*N .. c*N + N - 1 (one lattice vector).  Gather/scatter convert
+// from/to the caller's orbital-major [N][ld] blocks.
 __global__ void k_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype,
                               const void* __restrict__ in, int fp64, void* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * Rg) return;
-  const int64_t s = e / Rg;
-  const int r = static_cast<int>(e - s * Rg);
-  const int64_t at = s * ld + col0 + r;
+  const int64_t c = e / N;
+  const int64_t s = e - c * N;
+  const int64_t at = s * ld + col0 + c;
   double x, y;
   if (in_dtype == CSP_C128) {
     const double2 v = static_cast<const double2*>(in)[at];
@@ -168,8 +171,8 @@ __global__ void k_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtyp
                                const void* __restrict__ in, int fp64, void* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N * Rg) return;
-  const int64_t s = e / Rg;
-  const int r = static_cast<int>(e - s * Rg);
+  const int64_t c = e / N;
+  const int64_t s = e - c * N;
   double x, y;
   if (fp64) {
     const double2 v = static_cast<const double2*>(in)[e];
@@ -178,7 +181,7 @@ __global__ void k_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtyp
     const float2 v = static_cast<const float2*>(in)[e];
     x = v.x; y = v.y;
   }
-  const int64_t at = s * ld + col0 + r;
+  const int64_t at = s * ld + col0 + c;
   if (out_dtype == CSP_C128) static_cast<double2*>(out)[at] = make_double2(x, y);
   else static_cast<float2*>(out)[at] = make_float2(static_cast<float>(x), static_cast<float>(y));
 }
@@ -190,25 +193,28 @@ hipError_t launch_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtyp
   return hipGetLastError();
 }
 
-// <psi_r|psi_r> per column of an [N][Rg] group: FP64 partial per block (in a
-// fixed order), then one block sums the partials in order.
-__global__ void k_self_dot_partial(int64_t M, int Rg, const void* __restrict__ psi, int fp64,
+// <psi_c|psi_c> per column of an [Rg][N] group: workgroup (x, c) sums column
+// c with stride gridDim.x * 256 and reduces in a fixed order into
+// partial[c * gridDim.x + x] (FP64); one thread per column then adds the
+// partials in order.
+__global__ void k_self_dot_partial(int64_t N, int Rg, const void* __restrict__ psi, int fp64,
                                    double* __restrict__ partial) {
   __shared__ double red[256];
+  const int64_t c = blockIdx.y;
   double acc = 0.0;
-  for (int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x; m < M; m += (int64_t)gridDim.x * 256) {
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < N; s += (int64_t)gridDim.x * 256) {
     double x, y;
-    if (fp64) { const double2 v = static_cast<const double2*>(psi)[m]; x = v.x; y = v.y; }
-    else { const float2 v = static_cast<const float2*>(psi)[m]; x = v.x; y = v.y; }
+    if (fp64) { const double2 v = static_cast<const double2*>(psi)[c * N + s]; x = v.x; y = v.y; }
+    else { const float2 v = static_cast<const float2*>(psi)[c * N + s]; x = v.x; y = v.y; }
     acc = fma(x, x, fma(y, y, acc));
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  if ((int)threadIdx.x < Rg) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < 256; k += Rg) s += red[k];
-    partial[(int64_t)blockIdx.x * Rg + threadIdx.x] = s;
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) partial[c * gridDim.x + blockIdx.x] = red[0];
 }
 
 __global__ void k_self_dot_finish(int n_wg, int Rg, const double* __restrict__ partial,
@@ -216,14 +222,14 @@ __global__ void k_self_dot_finish(int n_wg, int Rg, const double* __restrict__ p
   const int r = threadIdx.x;
   if (r >= Rg) return;
   double s = 0.0;
-  for (int w = 0; w < n_wg; ++w) s += partial[(int64_t)w * Rg + r];
+  for (int w = 0; w < n_wg; ++w) s += partial[(int64_t)r * n_wg + w];
   corr[2 * (col0 + r)] = s;
   corr[2 * (col0 + r) + 1] = 0.0;
 }
 
 hipError_t launch_self_dot(int64_t N, int Rg, const void* d_psi, bool fp64, double* d_corr,
                            int col0, double* d_scratch, int n_scratch_wg, hipStream_t s) {
-  hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg), dim3(256), 0, s, N * Rg, Rg, d_psi,
+  hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg, Rg), dim3(256), 0, s, N, Rg, d_psi,
                      fp64 ? 1 : 0, d_scratch);
   hipLaunchKernelGGL(k_self_dot_finish, dim3(1), dim3(64), 0, s, n_scratch_wg, Rg, d_scratch,
                      d_corr, col0);
@@ -252,7 +258,7 @@ __global__ void k_guard(int n_wg, int Rg, const double* __restrict__ carry_parti
   bool bad = !(c0 >= 0.0) || !isfinite(c0);
   if (carry_partial) {
     double s = 0.0;
-    for (int w = 0; w < n_wg; ++w) s += carry_partial[(int64_t)w * Rg + r];
+    for (int w = 0; w < n_wg; ++w) s += carry_partial[(int64_t)r * n_wg + w];
     bad |= !isfinite(s) || fabs(s - c0) > tol * c0;
   }
   const double lim = (1.0 + tol) * c0;
@@ -270,7 +276,7 @@ hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const
                         const int64_t* blk_dev, int* d_flag, double* d_scratch,
                         int n_scratch_wg, hipStream_t s) {
   if (d_carry)
-    hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg), dim3(256), 0, s, N * Rg, Rg,
+    hipLaunchKernelGGL(k_self_dot_partial, dim3(n_scratch_wg, Rg), dim3(256), 0, s, N, Rg,
                        d_carry, fp64 ? 1 : 0, d_scratch);
   hipLaunchKernelGGL(k_guard, dim3(1), dim3(64), 0, s, n_scratch_wg, Rg,
                      d_carry ? d_scratch : nullptr, d_corr, ldc, col0, t0, bk, tol, block,

@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
     for n in ("csp_context_create", "csp_lattice_create", "csp_states_random_phase",
               "csp_propagate", "csp_propagate_batch", "csp_dos", "csp_last_error",
               "csp_chebyshev_coefficients", "csp_chebyshev_step", "csp_select_block",
-              "csp_autotune"):
+              "csp_autotune", "csp_bandwidth_probe"):
         assert n in names
 
 
@@ -39,7 +39,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(csp.LatticeDesc) == 16 + 16 + 16 + 8 + 24
     assert ctypes.sizeof(csp.LatticeInfo) == 24 + 24 + 8
     assert ctypes.sizeof(csp.Params) == 8 + 16 + 16 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(csp.Report) == 16 + 40 + 48 + 8 + 64 + 8
+    assert ctypes.sizeof(csp.Report) == 16 + 40 + 48 + 8 + 64 + 16
     assert ctypes.sizeof(csp.Tuning) == 16 + 8 + 16 + 64 + 8
 
 

@@ -499,3 +499,12 @@ def test_column_windows_under_memory_cap(csp, ctx, assembly):
                                                    assembly=assembly))
     assert rep1.n_passes == 1
     assert np.max(np.abs(host(full) - host(corr))) < 1e-6
+
+
+def test_bandwidth_probe(csp, ctx):
+    r, w, rw = csp.csp_bandwidth_probe(ctx, 256 << 20)
+    print("[gpu] streaming GB/s read %.0f write %.0f 2r1w %.0f" % (r, w, rw), flush=True)
+    for x in (r, w, rw):
+        assert 500.0 < x < 8000.0 * 1.05      # below the published HBM peak
+    with pytest.raises(csp.CspError):
+        csp.csp_bandwidth_probe(ctx, 1000)
