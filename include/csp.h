@@ -291,8 +291,9 @@ csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t
 
 /* Autotuner.  For the instances (lats[i], R[i]) with params->mode and
  * params->assembly, times on this device every recursion launch shape
- * (vec in {1, 2, 4}, rows per workgroup in {2, ..., 128}) and, for the state
- * assembly, the contraction in both of its load schemes at 2, 4 and 8
+ * (values per lane in {2, 4}, Chebyshev steps per launch in {1, 2, 4, 8} as
+ * compiled for the precision and assembly, rows per work item in
+ * {8, ..., 128}) and, for the state assembly, the contraction at 2, 4 and 8
  * workgroups per compute unit for time tiles of 32 and 64, then picks the
  * time-block size b by the cost
  * model of Sec. II.B with measured operation costs:
@@ -309,6 +310,15 @@ csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t
  * buffers of the caller are not touched (the timing uses workspace). */
 csp_status csp_autotune(csp_context *ctx, int32_t n_inst, const csp_lattice *const *lats,
                         const int32_t *R, const csp_params *params, csp_tuning *out);
+
+/* Installs a tuning record (for instance one saved from csp_autotune on an
+ * earlier run) for the shape of these instances, as csp_autotune would
+ * cache it; later propagations of that shape use it.  Fails with
+ * CSP_EINVAL when a launch shape in *tuning is not compiled for
+ * params->mode and params->assembly. */
+csp_status csp_set_tuning(csp_context *ctx, int32_t n_inst, const csp_lattice *const *lats,
+                          const int32_t *R, const csp_params *params,
+                          const csp_tuning *tuning);
 
 /* Time-block size of csp_autotune for one lattice with R columns: runs the
  * autotuner (or takes its cached entry) and returns its block_b; rep (may be

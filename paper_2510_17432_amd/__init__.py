@@ -138,6 +138,7 @@ _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctyp
                  ctypes.c_int32, _vp, _vp, _vp])
 _sig("csp_select_block", [_vp, _vp, ctypes.c_int32, _P(Params), _P(ctypes.c_int32), _P(Report)])
 _sig("csp_autotune", [_vp, ctypes.c_int32, _P(_vp), _P(ctypes.c_int32), _P(Params), _P(Tuning)])
+_sig("csp_set_tuning", [_vp, ctypes.c_int32, _P(_vp), _P(ctypes.c_int32), _P(Params), _P(Tuning)])
 _sig("csp_bandwidth_probe", [_vp, ctypes.c_uint64, _P(ctypes.c_double)])
 
 
@@ -390,6 +391,14 @@ def csp_autotune(ctx, lats, Rs, params):
     t = Tuning()
     _check(_lib.csp_autotune(ctx.handle, n, L, Rv, ctypes.byref(params), ctypes.byref(t)))
     return t
+
+
+def csp_set_tuning(ctx, lats, Rs, params, tuning):
+    """Install a tuning record for the shape of these instances."""
+    n = len(lats)
+    L = (ctypes.c_void_p * n)(*[l.handle.value for l in lats])
+    Rv = (ctypes.c_int32 * n)(*[int(r) for r in Rs])
+    _check(_lib.csp_set_tuning(ctx.handle, n, L, Rv, ctypes.byref(params), ctypes.byref(tuning)))
 
 
 def csp_bandwidth_probe(ctx, nbytes=1 << 30):

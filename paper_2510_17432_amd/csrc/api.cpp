@@ -393,10 +393,10 @@ struct ChebPlan {
 ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, int vec = 0,
                    int kt = 0, int seg = 0) {
   ChebPlan p;
-  p.vec = vec > 0 ? vec : (fp64 ? 2 : 4);
+  p.vec = vec > 0 ? vec : 2;
   p.kt = kt > 0 ? kt : 1;
   if (!cheb_shape_supported(fp64, p.vec, p.kt, mom)) {
-    p.vec = fp64 ? 2 : 4;
+    p.vec = 2;
     p.kt = 1;
   }
   p.ow = 64 * p.vec - 2 * cheb_margin(p.vec, p.kt);
@@ -831,7 +831,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   std::vector<ChebInst> sp;
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
   const ChebPlan sp_plan = plan_cheb(sp, fp64, false, c->n_cu, tune ? tune->spmm_vec : 0,
-                                     tune ? tune->spmm_steps : (fp64 ? 2 : 4),
+                                     tune ? tune->spmm_steps : (fp64 ? 4 : 8),
                                      tune ? tune->spmm_seg_rows : 0);
   const int kt = sp_plan.kt;
 
@@ -1283,7 +1283,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_MOMENTS);
   // the carried state is accumulated one step per launch
-  const int kt_want = carry ? 1 : (tune ? tune->spmm_steps : (fp64 ? 2 : 4));
+  const int kt_want = carry ? 1 : (tune ? tune->spmm_steps : 4);
   const ChebPlan sp_plan = plan_cheb(sp, fp64, true, c->n_cu, tune ? tune->spmm_vec : 0, kt_want,
                                      tune ? tune->spmm_seg_rows : 0);
   const int kt = sp_plan.kt;
@@ -1856,6 +1856,31 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   }
   c->tuned[shape_key(ins, fp64, P.assembly)] = T;
   if (out) *out = T;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_set_tuning(csp_context* c, int32_t n_inst,
+                                      const csp_lattice* const* lats, const int32_t* R,
+                                      const csp_params* params_in, const csp_tuning* T) {
+  if (!c || n_inst < 1 || !lats || !R || !params_in || !T) return fail(CSP_EINVAL, "NULL argument");
+  csp_params P;
+  fill_defaults(params_in, &P);
+  if (P.mode < CSP_FP64_SEQ || P.mode > CSP_FP32_CONC) return fail(CSP_EINVAL, "bad mode %d", P.mode);
+  if (P.assembly != CSP_ASSEMBLE_STATES && P.assembly != CSP_ASSEMBLE_MOMENTS)
+    return fail(CSP_EINVAL, "bad assembly %d", P.assembly);
+  const bool fp64 = P.mode != CSP_FP32_CONC;
+  const bool mom = P.assembly == CSP_ASSEMBLE_MOMENTS;
+  if (!cheb_shape_supported(fp64, T->spmm_vec, T->spmm_steps, mom))
+    return fail(CSP_EINVAL, "no recursion kernel for %d values per lane, %d steps per launch",
+                T->spmm_vec, T->spmm_steps);
+  if (T->spmm_seg_rows < 1 || T->contract_wg_per_cu < 1 || T->block_b < 0)
+    return fail(CSP_EINVAL, "rows per work item and workgroups per CU must be >= 1, b >= 0");
+  std::vector<InstIn> ins(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    if (!lats[i] || R[i] < 1) return fail(CSP_EINVAL, "instance %d: NULL lattice or R < 1", i);
+    ins[i] = {lats[i], nullptr, R[i], nullptr, nullptr, R[i], 0};
+  }
+  c->tuned[shape_key(ins, fp64, P.assembly)] = *T;
   return CSP_OK;
 }
 

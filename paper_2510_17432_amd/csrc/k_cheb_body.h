@@ -83,6 +83,28 @@ __device__ __forceinline__ void stv(CSP_GLOBAL float* p, const cx<float> (&d)[V]
     q[k] = t;
   }
 }
+// Chebyshev vectors are written once and read back only after many other
+// vectors have streamed through the caches: non-temporal stores.
+#ifndef CSP_CHEB_NT
+#define CSP_CHEB_NT 1
+#endif
+template <int V>
+__device__ __forceinline__ void stv_nt(CSP_GLOBAL float* p, const cx<float> (&d)[V]) {
+  CSP_GLOBAL f32x4u* q = reinterpret_cast<CSP_GLOBAL f32x4u*>(p);
+#pragma unroll
+  for (int k = 0; k < V / 2; ++k) {
+    f32x4u t;
+    t.x = d[2 * k].x;
+    t.y = d[2 * k].y;
+    t.z = d[2 * k + 1].x;
+    t.w = d[2 * k + 1].y;
+#if CSP_CHEB_NT
+    __builtin_nontemporal_store(t, q + k);
+#else
+    q[k] = t;
+#endif
+  }
+}
 template <int V>
 __device__ __forceinline__ void ldv(const CSP_GLOBAL double* p, cx<double> (&d)[V]) {
   const CSP_GLOBAL f64x2u* q = reinterpret_cast<const CSP_GLOBAL f64x2u*>(p);
@@ -101,6 +123,21 @@ __device__ __forceinline__ void stv(CSP_GLOBAL double* p, const cx<double> (&d)[
     t.x = d[v].x;
     t.y = d[v].y;
     q[v] = t;
+  }
+}
+template <int V>
+__device__ __forceinline__ void stv_nt(CSP_GLOBAL double* p, const cx<double> (&d)[V]) {
+  CSP_GLOBAL f64x2u* q = reinterpret_cast<CSP_GLOBAL f64x2u*>(p);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    f64x2u t;
+    t.x = d[v].x;
+    t.y = d[v].y;
+#if CSP_CHEB_NT
+    __builtin_nontemporal_store(t, q + v);
+#else
+    q[v] = t;
+#endif
   }
 }
 __device__ __forceinline__ cx<float> ld1(const CSP_GLOBAL float* p) {
@@ -290,11 +327,14 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
       for (int v = 0; v < V; ++v) d[v] = pres[v] ? rowp[wpos[v]] : T(0);
     }
   };
-  // row rw must be inside [0, Ly)
-  auto store_row = [&](gT* vec, int64_t rw, const C (&o)[V]) {
+  // row rw must be inside [0, Ly); nt: non-temporal (Chebyshev slots)
+  auto store_row = [&](gT* vec, int64_t rw, const C (&o)[V], bool nt) {
     gT* rowp = vec + 2 * rw * opr;
     if (fast) {
-      if (lane_own) stv<V>(rowp + 2 * p0 + 2 * lq, o);
+      if (lane_own) {
+        if (nt) stv_nt<V>(rowp + 2 * p0 + 2 * lq, o);
+        else stv<V>(rowp + 2 * p0 + 2 * lq, o);
+      }
     } else {
 #pragma unroll
       for (int v = 0; v < V; ++v)
@@ -318,14 +358,31 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
     for (int v = 0; v < V; ++v) er[k][v] = T(0);
 
-  // moment sums: [0,1] <psi0|out>, [2] |out|^2, [3,4] <out|cur>; and
-  // <psi0|cur> of the first level
-  double acc[MOM ? KT : 1][5];
-  double acc_c[2] = {0.0, 0.0};
+  // Moment sums, quantity q = 5 (l - 1) + j for level l: j = 0, 1
+  // <psi0|out>, 2 |out|^2, 3, 4 <out|cur>; q = 5 KT + 0, 1: <psi0|cur> of
+  // the first level.  sq holds this lane's working-precision sums of the
+  // last rows; every kFlush rows each is summed over the wave and added in
+  // FP64 into accq of lane q.
+  constexpr int kFlush = 16;
+  constexpr int NQ = MOM ? 5 * KT + 2 : 1;
+  T sq[NQ];
 #pragma unroll
-  for (int l = 0; l < (MOM ? KT : 1); ++l)
+  for (int k = 0; k < NQ; ++k) sq[k] = T(0);
+  double accq = 0.0;
+  // psi0 rows r0 - k (moment epilogue), carried-state row r0 - 1
+  C pq[MOM ? KT + 1 : 1][V], npq[V], ncar[V];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) acc[l][k] = 0.0;
+  for (int k = 0; k < (MOM ? KT + 1 : 1); ++k)
+#pragma unroll
+    for (int v = 0; v < V; ++v) pq[k][v] = {T(0), T(0)};
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    npq[v] = {T(0), T(0)};
+    ncar[v] = {T(0), T(0)};
+  }
+  const bool dots = MOM && (st.dot_psi0 || st.dot_self);
+  const bool want_psi0 = MOM && st.dot_psi0;
+  const bool carry_in = MOM && carry && st.carry_mode == 2;
 
   const T alpha = static_cast<T>(I.alpha);
   const T beta0 = static_cast<T>(I.beta0);
@@ -344,6 +401,8 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     for (int v = 0; v < V; ++v) nprev[v] = {T(0), T(0)};
   }
   if constexpr (EPS) load_eps(rbase, neps);
+  if (want_psi0) load_row(psi0, rbase, npq);
+  if (carry_in) load_row(carry, rbase - 1, ncar);
 
 #pragma unroll 1
   for (int64_t i = 0; i < n_iter; ++i) {
@@ -364,13 +423,27 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
       for (int v = 0; v < V; ++v) er[0][v] = neps[v];
     }
+    C car[V];
+    if constexpr (MOM) {
+#pragma unroll
+      for (int k = KT; k >= 1; --k)
+#pragma unroll
+        for (int v = 0; v < V; ++v) pq[k][v] = pq[k - 1][v];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        pq[0][v] = npq[v];
+        car[v] = ncar[v];
+      }
+    }
     if (i + 1 < n_iter) {
       load_row(curv, r0 + 1, ncur);
       if (prevv) load_row(prevv, r0, nprev);
       if constexpr (EPS) load_eps(r0 + 1, neps);
+      if (want_psi0) load_row(psi0, r0 + 1, npq);
+      if (carry_in) load_row(carry, r0, ncar);
     }
     // phi_n itself for the contraction (order 0 of a block)
-    if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0]);
+    if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0], true);
 
 #pragma unroll
     for (int l = 1; l <= KT; ++l) {
@@ -432,91 +505,79 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
       }
       if (r >= y0 && r < y1) {
         const int so = st.slot_out[l - 1];
-        if (so >= 0) store_row(base + 2 * (int64_t)so * I.slot_stride + coff, rw, o);
+        if (so >= 0) store_row(base + 2 * (int64_t)so * I.slot_stride + coff, rw, o, true);
         if constexpr (MOM) {
-          if (st.dot_psi0 || st.dot_self) {
-            C q[V];
-            if (st.dot_psi0) load_row(psi0, r, q);
-            T s[7] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+          if (dots) {
+            const C(&q)[V] = pq[l];
+            T* s = sq + 5 * (l - 1);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
               if (!own[v]) continue;
-              s[0] += q[v].x * o[v].x + q[v].y * o[v].y;
-              s[1] += q[v].x * o[v].y - q[v].y * o[v].x;
-              s[2] += o[v].x * o[v].x + o[v].y * o[v].y;
-              s[3] += o[v].x * c[v].x + o[v].y * c[v].y;
-              s[4] += o[v].x * c[v].y - o[v].y * c[v].x;
-              if (l == 1) {
-                s[5] += q[v].x * c[v].x + q[v].y * c[v].y;
-                s[6] += q[v].x * c[v].y - q[v].y * c[v].x;
+              if (want_psi0) {
+                s[0] += q[v].x * o[v].x + q[v].y * o[v].y;
+                s[1] += q[v].x * o[v].y - q[v].y * o[v].x;
+                if (l == 1) {
+                  sq[5 * KT] += q[v].x * c[v].x + q[v].y * c[v].y;
+                  sq[5 * KT + 1] += q[v].x * c[v].y - q[v].y * c[v].x;
+                }
               }
-            }
-            if (st.dot_psi0) {
-              acc[l - 1][0] += static_cast<double>(s[0]);
-              acc[l - 1][1] += static_cast<double>(s[1]);
-              if (l == 1) {
-                acc_c[0] += static_cast<double>(s[5]);
-                acc_c[1] += static_cast<double>(s[6]);
+              if (st.dot_self) {
+                s[2] += o[v].x * o[v].x + o[v].y * o[v].y;
+                s[3] += o[v].x * c[v].x + o[v].y * c[v].y;
+                s[4] += o[v].x * c[v].y - o[v].y * c[v].x;
               }
-            }
-            if (st.dot_self) {
-              acc[l - 1][2] += static_cast<double>(s[2]);
-              acc[l - 1][3] += static_cast<double>(s[3]);
-              acc[l - 1][4] += static_cast<double>(s[4]);
             }
           }
           if (l == 1 && st.carry_mode && carry) {
             const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
             const T c1r = static_cast<T>(st.cc1[0]), c1i = static_cast<T>(st.cc1[1]);
             C b[V];
-            if (st.carry_mode == 1) {
-#pragma unroll
-              for (int v = 0; v < V; ++v) {
-                b[v].x = c0r * c[v].x - c0i * c[v].y;
-                b[v].y = c0r * c[v].y + c0i * c[v].x;
-              }
-            } else {
-              load_row(carry, r, b);
-            }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
+              if (st.carry_mode == 1) {
+                b[v].x = c0r * c[v].x - c0i * c[v].y;
+                b[v].y = c0r * c[v].y + c0i * c[v].x;
+              } else {
+                b[v] = car[v];
+              }
               b[v].x += c1r * o[v].x - c1i * o[v].y;
               b[v].y += c1r * o[v].y + c1i * o[v].x;
             }
-            store_row(carry, rw, b);
+            store_row(carry, rw, b, false);
           }
+        }
+      }
+    }
+    if constexpr (MOM) {
+      if (dots && (((i + 1) % kFlush) == 0 || i + 1 == n_iter)) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+          T x = sq[k];
+#pragma unroll
+          for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+          if (lane == k) accq += static_cast<double>(x);
+          sq[k] = T(0);
         }
       }
     }
   }
 
   if constexpr (MOM) {
-    if (st.dot_psi0 || st.dot_self) {
-      // fixed butterfly over the 64 lanes, then lane 0 writes one record per
-      // level: [kind][re, im], kinds <psi0|out>, <psi0|cur>, <out|out>, <out|cur>
-      auto wsum = [&](double x) {
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
-        return x;
-      };
-      const double c0 = wsum(acc_c[0]), c1 = wsum(acc_c[1]);
-#pragma unroll
-      for (int l = 0; l < KT; ++l) {
-        if (l >= nlev) break;
-        double rec[8];
-        rec[0] = wsum(acc[l][0]);
-        rec[1] = wsum(acc[l][1]);
-        rec[2] = l == 0 ? c0 : 0.0;
-        rec[3] = l == 0 ? c1 : 0.0;
-        rec[4] = wsum(acc[l][2]);
-        rec[5] = 0.0;
-        rec[6] = wsum(acc[l][3]);
-        rec[7] = wsum(acc[l][4]);
-        if (lane == 0) {
-          double* out = st.partial + (((int64_t)st.mom_slot * KT + l) * st.total_items + item) * 8;
-#pragma unroll
-          for (int k = 0; k < 8; ++k) out[k] = rec[k];
-        }
+    if (dots) {
+      // one record of 8 doubles per level, [kind][re, im] with kinds
+      // <psi0|out>, <psi0|cur> (first level only), <out|out>, <out|cur>;
+      // lane m writes element m % 8 of level m / 8
+      const int m = lane;
+      const int l = m >> 3, slot = m & 7;
+      int q = -1;
+      if (slot == 0 || slot == 1) q = 5 * l + slot;
+      else if (slot == 4) q = 5 * l + 2;
+      else if (slot == 6 || slot == 7) q = 5 * l + slot - 3;
+      else if ((slot == 2 || slot == 3) && l == 0) q = 5 * KT + slot - 2;
+      const double val = __shfl(accq, q < 0 ? 0 : q);
+      if (l < nlev && l < KT) {
+        double* out = st.partial + (((int64_t)st.mom_slot * KT + l) * st.total_items + item) * 8;
+        out[slot] = q < 0 ? 0.0 : val;
       }
     }
   }
