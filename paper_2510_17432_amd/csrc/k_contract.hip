@@ -23,9 +23,10 @@
 // contiguous bytes), with the next step's values already in flight.  The B
 // operand (lane (j, h) holds time j, orders 8h..8h+7) is staged in LDS once
 // per launch.  The accumulator holds psi for rows 8(v/4) + 4h + v%4 and time
-// lane%32; the epilogue multiplies by conj(psi0) and accumulates per lane,
-// then the workgroup reduces in FP64 in a fixed order and writes its partial
-// sums, one per time point.
+// lane%32; the epilogue multiplies by conj(psi0) (loaded with the tile's
+// first orders, one value per lane, and passed between lanes) and adds the
+// tile's rows into one FP32 sum per lane and time, then the workgroup reduces
+// in FP64 in a fixed order and writes its partial sums, one per time point.
 #include <algorithm>
 
 #include "csp_internal.h"
@@ -40,12 +41,26 @@ struct BopEntry {
   bf16x8 lo;
 };
 
+// complex64 values through global-address-space pointers
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) f32x2 gf2;
+__device__ __forceinline__ float2 ldg2(const gf2* p) {
+  const f32x2 t = *p;
+  return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ void stg2(gf2* p, float2 v) {
+  f32x2 t;
+  t.x = v.x;
+  t.y = v.y;
+  *p = t;
+}
+
 size_t bop_bytes(int jtiles, int n_cnt) {
   return sizeof(BopEntry) * 64 * (size_t)jtiles * (size_t)ceil_div(n_cnt, 16);
 }
 
 template <int JT>
-__global__ __launch_bounds__(kContractThreads) void k_contract_f32(
+__global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_eu(JT == 1 ? 4 : 2))) void k_contract_f32(
     const ContractInst* __restrict__ insts, ContractArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n_kb = (a.n_cnt + 15) >> 4;
@@ -76,16 +91,17 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
   const int64_t col = wgl / I.wpc, sub = wgl - col * I.wpc;
   const int64_t N = I.N;
   const int64_t coff = col * N;
-  const float2* slots = static_cast<const float2*>(I.slots) + coff;
-  const float2* psi0 = static_cast<const float2*>(I.psi0) + coff;
-  float2* carry = static_cast<float2*>(I.carry) + coff;
+  const gf2* slots = (const gf2*)(I.slots) + coff;
+  const gf2* psi0 = (const gf2*)(I.psi0) + coff;
+  gf2* carry = (gf2*)(I.carry) + coff;
   const int64_t n_tiles = ceil_div(N, 32);
+  const int64_t sstr = I.slot_stride;
+  const int64_t wrap = (int64_t)a.S * sstr;
 
-  float pr[JT][16], pi[JT][16];
+  // per-lane correlation sums of time lane%32 (+ 32 jt) over the rows seen
+  float pr[JT], pi[JT];
 #pragma unroll
-  for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) { pr[jt][v] = 0.f; pi[jt][v] = 0.f; }
+  for (int jt = 0; jt < JT; ++jt) { pr[jt] = 0.f; pi[jt] = 0.f; }
 
   const int64_t stride_tiles = (int64_t)I.wpc * 4;
   for (int64_t tile = sub * 4 + wave; tile < n_tiles; tile += stride_tiles) {
@@ -97,17 +113,22 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
 #pragma unroll
       for (int v = 0; v < 16; ++v) { accR[jt][v] = 0.f; accI[jt][v] = 0.f; }
     float cr = 0.f, ci = 0.f;
+    // psi0 of the tile, value il in both half-waves (used after the orders)
+    const float2 p0l = mv ? ldg2(psi0 + m) : make_float2(0.f, 0.f);
 
-    // Orders of the next 16-order step are loaded while the current one is
-    // converted and multiplied (two register sets of 8 values).
+    // Orders of the next 16-order step are in flight while the current one
+    // is multiplied (its values are converted to bf16 first, so the loads
+    // can reuse their registers).
     float2 xn[8];
+    // order n lives in slot n % S; consecutive orders in consecutive slots
     auto load_step = [&](int kb) {
+      const int rel0 = kb * 16 + h * 8;
+      int64_t off = (int64_t)((a.n_lo + rel0) % a.S) * sstr;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const int rel = kb * 16 + h * 8 + v;
-        const int n = a.n_lo + rel;
-        xn[v] = (mv && rel < a.n_cnt) ? slots[(int64_t)(n % a.S) * I.slot_stride + m]
-                                      : make_float2(0.f, 0.f);
+        xn[v] = (mv && rel0 + v < a.n_cnt) ? ldg2(slots + off + m) : make_float2(0.f, 0.f);
+        off += sstr;
+        if (off >= wrap) off -= wrap;
       }
     };
     load_step(0);
@@ -116,7 +137,6 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
       float2 x[8];
 #pragma unroll
       for (int v = 0; v < 8; ++v) x[v] = xn[v];
-      if (kb + 1 < n_kb) load_step(kb + 1);
       bf16x8 phi, plo, qhi, qlo;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
@@ -138,6 +158,7 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
         plo[v] = static_cast<__bf16>(p - static_cast<float>(ph));
         qlo[v] = static_cast<__bf16>(q - static_cast<float>(qh));
       }
+      if (kb + 1 < n_kb) load_step(kb + 1);
 #pragma unroll
       for (int jt = 0; jt < JT; ++jt) {
         const BopEntry be = sb[(kb * JT + jt) * 64 + lane];
@@ -156,24 +177,34 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
     if (h == 0 && mv) {
       float2 cv = make_float2(cr, ci);
       if (!a.first_chunk) {
-        const float2 old = carry[m];
+        const float2 old = ldg2(carry + m);
         cv.x += old.x;
         cv.y += old.y;
       }
-      carry[m] = cv;
+      stg2(carry + m, cv);
     }
 
-    // Correlation epilogue: conj(psi0[row]) * psi[row, time].
+    // Correlation epilogue: conj(psi0[row]) * psi[row, time] summed over
+    // the 16 rows 8(v/4) + 4h + v%4 of this lane; psi0 of row rho comes from
+    // lane rho (rows past N hold 0).
+    float tr[JT], ti[JT];
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) { tr[jt] = 0.f; ti[jt] = 0.f; }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int64_t mm = tile * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-      const float2 p0 = mm < N ? psi0[mm] : make_float2(0.f, 0.f);
+      const int rho = 8 * (v >> 2) + 4 * h + (v & 3);
+      const float p0x = __shfl(p0l.x, rho), p0y = __shfl(p0l.y, rho);
 #pragma unroll
       for (int jt = 0; jt < JT; ++jt) {
         const float re = accR[jt][v], im = accI[jt][v];
-        pr[jt][v] = fmaf(p0.x, re, fmaf(p0.y, im, pr[jt][v]));
-        pi[jt][v] = fmaf(p0.x, im, fmaf(-p0.y, re, pi[jt][v]));
+        tr[jt] = fmaf(p0x, re, fmaf(p0y, im, tr[jt]));
+        ti[jt] = fmaf(p0x, im, fmaf(-p0y, re, ti[jt]));
       }
+    }
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) {
+      pr[jt] += tr[jt];
+      pi[jt] += ti[jt];
     }
   }
 
@@ -185,13 +216,8 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f32(
   double sx[JT], sy[JT];
 #pragma unroll
   for (int jt = 0; jt < JT; ++jt) {
-    sx[jt] = 0.0;
-    sy[jt] = 0.0;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      sx[jt] += static_cast<double>(pr[jt][v]);
-      sy[jt] += static_cast<double>(pi[jt][v]);
-    }
+    sx[jt] = static_cast<double>(pr[jt]);
+    sy[jt] = static_cast<double>(pi[jt]);
   }
   for (int w = 0; w < 4; ++w) {
     for (int half = 0; half < 2; ++half) {
@@ -290,17 +316,24 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f64(
     }
   }
 
-  // Sum over the 256 threads in order (FP64).
+  // Sum over the 256 threads in a fixed tree (FP64).
   double2* outp = reinterpret_cast<double2*>(I.partial) + wgl * (int64_t)a.bcols;
   for (int j = 0; j < a.bcols && j < B; ++j) {
-    sred[tid] = part[j];
+    double2 pj = part[0];
+#pragma unroll
+    for (int k = 1; k < B; ++k)
+      if (k == j) pj = part[k];   // static register indices
+    sred[tid] = pj;
     __syncthreads();
-    if (tid == 0) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int k = 0; k < kContractThreads; ++k) {
-        s.x += sred[k].x;
-        s.y += sred[k].y;
+    for (int w = kContractThreads / 2; w > 0; w >>= 1) {   // fixed tree
+      if (tid < w) {
+        sred[tid].x += sred[tid + w].x;
+        sred[tid].y += sred[tid + w].y;
       }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double2 s = sred[0];
       double2* d = outp + j;
       if (a.first_chunk) {
         *d = s;
