@@ -68,6 +68,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# sources of the recursion kernel whose counters profiles/ holds
+KERNEL_SOURCES = ("k_cheb_body.h", "k_cheb_f32.hip")
+
+
 def traffic_from_profiles():
     """HBM bytes per launch of the recursion kernel: the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, each scaled by what the same counter
@@ -75,14 +79,17 @@ def traffic_from_profiles():
     when the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_cheb_graphene1024_cols68_counters.json")
-    src = os.path.join(ROOT, "paper_2510_17432_amd", "csrc", "k_cheb.hip")
+    csrc = os.path.join(ROOT, "paper_2510_17432_amd", "csrc")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for name in KERNEL_SOURCES:
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+        h = h.hexdigest()
         if d.get("source_sha256") != h:
             return None
         return float(d["hbm_bytes_per_launch"])

@@ -1028,8 +1028,6 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   auto enqueue_block = [&](const BlockTab& T, int bk, int64_t t0, hipStream_t strm,
                            bool from_dev) -> csp_status {
     const int Nk = T.Nk;
-    size_t ev = 0;
-    if (!from_dev) CHECK(prof.begin(0, &ev));
     size_t ci = 0;
     int produced = 0;
     ContractArgs cab = ca;
@@ -1037,10 +1035,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       while (ci < T.chunks.size() && T.chunks[ci].n_lo + T.chunks[ci].n_cnt - 1 <= produced) {
         const ChunkTab& ch = T.chunks[ci];
         size_t evc = 0;
-        if (!from_dev) {
-          CHECK(prof.end(ev));
-          CHECK(prof.begin(1, &evc));
-        }
+        if (!from_dev) CHECK(prof.begin(1, &evc));
         cab.n_lo = ch.n_lo;
         cab.n_cnt = ch.n_cnt;
         cab.first_chunk = ci == 0 ? 1 : 0;
@@ -1054,10 +1049,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
           cab.ccarry = ch.ccf;
           HIPCALL(launch_contract_f32(d_con, cab, strm));
         }
-        if (!from_dev) {
-          CHECK(prof.end(evc));
-          CHECK(prof.begin(0, &ev));
-        }
+        if (!from_dev) CHECK(prof.end(evc));
         ++ci;
       }
       return CSP_OK;
@@ -1075,11 +1067,13 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
         stb.slot_prev = (produced - 1) % S;
       }
       for (int l = 1; l <= stb.nlev; ++l) stb.slot_out[l - 1] = (produced + l) % S;
+      size_t ev = 0;
+      if (!from_dev) CHECK(prof.begin(0, &ev));
       HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, d_spmm, sp_plan.runs, stb, strm));
+      if (!from_dev) CHECK(prof.end(ev));
       produced += stb.nlev;
       CHECK(run_chunks());
     }
-    if (!from_dev) CHECK(prof.end(ev));
     HIPCALL(launch_finish(d_fin, (int)fi.size(), bk, t0, from_dev ? d_blk : nullptr, strm));
     if (P.check_norm) {
       for (auto& g : groups) {
@@ -1391,8 +1385,6 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
       }
     }
     HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
-    size_t ev = 0;
-    CHECK(prof.begin(0, &ev));
     // four slots: phi_n, phi_{n-1} and the two newest levels of a launch
     int cur_slot = -1, prev_slot = -1;
     int produced = 0;
@@ -1440,7 +1432,10 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         coef(produced + 1, st.cc1);
         axpy += produced == 0 ? 2 : 1;
       }
+      size_t ev = 0;
+      CHECK(prof.begin(0, &ev));
       HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, true, d_spmm, sp_plan.runs, st, s));
+      CHECK(prof.end(ev));
       ++n_spmm;
       amxsy += st.nlev;
       spmm_bytes += vbytes * ((produced == 0 ? 1.0 : 2.0) + std::min(st.nlev, 2) +
@@ -1458,7 +1453,6 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         launches = 0;
       }
     }
-    CHECK(prof.end(ev));
     ndot += Nk;
     HIPCALL(launch_mom_corr(d_mc, (int)mc.size(), Nk, halving ? 1 : 0, d_a, lda, d_ntr, bk, t0,
                             rmax, s));
