@@ -508,3 +508,62 @@ def test_bandwidth_probe(csp, ctx):
         assert 500.0 < x < 8000.0 * 1.05      # below the published HBM peak
     with pytest.raises(csp.CspError):
         csp.csp_bandwidth_probe(ctx, 1000)
+
+
+# ---------------------------------------------------------------- launch shapes
+SHAPE_LATS = [
+    dict(kind="honeycomb", Lx=80, Ly=20, t=-2.7, W=1.0, disorder_seed=6),
+    dict(kind="honeycomb", Lx=70, Ly=11, t=-2.7, W=0.0, periodic_x=False, periodic_y=False),
+    dict(kind="square", Lx=150, Ly=13, t=1.0, W=0.7, disorder_seed=2, periodic_x=False),
+    dict(kind="square", Lx=45, Ly=17, t=-1.0, W=0.0, periodic_y=False),
+    dict(kind="chain", Lx=301, t=1.0, W=1.0, disorder_seed=3),
+]
+SHAPES = {("fp32_conc", 0): [(v, k) for v in (2, 4) for k in (1, 2, 4, 8)],
+          ("fp32_conc", 1): [(v, k) for v in (2, 4) for k in (1, 2, 4)],
+          ("fp64_conc", 0): [(2, 1), (2, 2), (2, 4)],
+          ("fp64_conc", 1): [(2, 1), (2, 2), (2, 4)]}
+
+
+@pytest.mark.parametrize("spec", SHAPE_LATS)
+def test_every_recursion_shape_matches_oracle(csp, ctx, spec):
+    # every compiled recursion kernel (values per lane, steps per launch),
+    # with short row segments so strips, segments and their ragged ends all
+    # occur, in both assemblies and both precisions
+    print("[gpu] launch shapes %s %dx%d" % (spec["kind"], spec["Lx"], spec.get("Ly", 1)),
+          flush=True)
+    g, c = pair(csp, ctx, spec)
+    psi = o.random_phase_states_fast(c.N, 3, 21)
+    Nt = 40
+    ref, _ = o.propagate(c, psi, Nt, b=0)
+    for (mode, assembly), shapes in SHAPES.items():
+        tdt = torch.complex128 if mode == "fp64_conc" else torch.complex64
+        tol = 1e-10 if mode == "fp64_conc" else 2e-5
+        for b in ((8,) if assembly == 0 else (0, 8)):
+            params = csp.make_params(Nt, mode=mode, block_b=b, assembly=assembly)
+            for (v, k) in shapes:
+                T = csp.Tuning()
+                T.spmm_vec, T.spmm_steps, T.spmm_seg_rows = v, k, 8
+                T.contract_wg_per_cu, T.block_b = 4, 8
+                csp.csp_set_tuning(ctx, [g], [psi.shape[1]], params, T)
+                corr, rep = csp.csp_propagate(ctx, g, dev(psi).to(tdt), params)
+                got = host(corr)
+                want_k = 1 if (assembly == 1 and b == 8) else k
+                assert rep.spmm_steps == want_k, (mode, assembly, b, v, k)
+                err = np.max(np.abs(got - ref))
+                assert err < tol, (mode, assembly, b, v, k, err)
+
+
+def test_set_tuning_rejects_missing_shapes(csp, ctx):
+    g = csp.Lattice(ctx, "square", 16, 16)
+    T = csp.Tuning()
+    T.spmm_vec, T.spmm_steps, T.spmm_seg_rows, T.contract_wg_per_cu = 3, 4, 8, 4
+    params = csp.make_params(10, mode="fp32_conc", block_b=4)
+    with pytest.raises(csp.CspError) as e:
+        csp.csp_set_tuning(ctx, [g], [1], params, T)
+    assert e.value.status == csp.CSP_EINVAL
+    T.spmm_vec, T.spmm_steps = 2, 8
+    pm = csp.make_params(10, mode="fp32_conc", assembly=csp.CSP_ASSEMBLE_MOMENTS)
+    with pytest.raises(csp.CspError) as e:          # no moment kernel with 8 steps
+        csp.csp_set_tuning(ctx, [g], [1], pm, T)
+    assert e.value.status == csp.CSP_EINVAL
+    csp.csp_set_tuning(ctx, [g], [1], params, T)
