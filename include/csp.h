@@ -212,7 +212,8 @@ csp_status csp_context_destroy(csp_context *ctx);
 /* Build a lattice on the context's device: on-site energies (FP64 and an
  * FP32 copy) by the generator above and the half-width |H| by Gershgorin's
  * row bound times the margin, reduced on the GPU in FP64 (Sec. II.A asks
- * for H0 and |H|; it obtains them by Lanczos). */
+ * for H0 and |H|; it obtains them by Lanczos).  A lattice has at most
+ * 2^31 - 1 orbitals (CSP_EUNSUPPORTED beyond). */
 csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
                               csp_lattice **out);
 csp_status csp_lattice_destroy(csp_lattice *lat);

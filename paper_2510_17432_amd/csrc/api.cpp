@@ -229,6 +229,11 @@ extern "C" csp_status csp_lattice_create(csp_context* c, const csp_lattice_desc*
     return fail(CSP_EINVAL, "unknown lattice kind %d", d->kind);
   const int64_t Ly = d->kind == CSP_CHAIN ? 1 : d->Ly;
   if (d->Lx < 1 || Ly < 1) return fail(CSP_EINVAL, "lattice sizes must be >= 1");
+  {
+    const int64_t opr = d->kind == CSP_HONEYCOMB ? 2 * d->Lx : d->Lx;
+    if (opr > INT32_MAX || Ly > INT32_MAX || opr * Ly >= ((int64_t)1 << 31))
+      return fail(CSP_EUNSUPPORTED, "at most 2^31 - 1 orbitals per lattice");
+  }
   if (!std::isfinite(d->t) || !std::isfinite(d->W) || d->W < 0)
     return fail(CSP_EINVAL, "hopping and disorder must be finite, W >= 0");
   DeviceGuard dg(c->device);

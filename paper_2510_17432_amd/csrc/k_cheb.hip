@@ -18,7 +18,7 @@ CSP_CHEB_LAUNCHER(launch_cheb_f64m)
 bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom) {
   if (fp64) return vec == 2 && (kt == 1 || kt == 2 || kt == 4);
   if (vec != 2 && vec != 4) return false;
-  return kt == 1 || kt == 2 || kt == 4 || (kt == 8 && !mom);
+  return kt == 1 || kt == 2 || kt == 4 || (kt == 8 && (!mom || vec == 2));
 }
 
 int cheb_margin(int vec, int kt) { return (kt + vec - 1) / vec * vec; }

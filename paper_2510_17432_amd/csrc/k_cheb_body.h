@@ -43,6 +43,8 @@
 // s_{k+1} = sum_n c_n phi_n of a time block.
 #pragma once
 
+#include <type_traits>
+
 #include "csp_internal.h"
 
 #define CSP_GLOBAL __attribute__((address_space(1)))
@@ -244,12 +246,14 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   const int64_t rem = local - col * per_col;
   const int64_t seg = rem / I.n_strips;
   const int64_t strip = rem - seg * I.n_strips;
-  const int64_t opr = I.opr, Ly = I.Ly;
-  const int64_t os = strip * OW;                     // first owned position
-  const int64_t p0 = os - MG;                        // first position of the strip
+  // positions, rows and offsets inside one lattice vector fit in 32 bits
+  // (the host checks N < 2^31)
+  const int opr = static_cast<int>(I.opr), Ly = static_cast<int>(I.Ly);
+  const int os = static_cast<int>(strip) * OW;       // first owned position
+  const int p0 = os - MG;                            // first position of the strip
   const bool fast = p0 >= 0 && p0 + 64 * V <= opr;   // no wrap, every position a site
-  const int64_t y0 = seg * st.seg_rows;
-  const int64_t y1 = (y0 + st.seg_rows < Ly) ? y0 + st.seg_rows : Ly;
+  const int y0 = static_cast<int>(seg) * st.seg_rows;
+  const int y1 = (y0 + st.seg_rows < Ly) ? y0 + st.seg_rows : Ly;
   const int nlev = st.nlev;
   const int py = I.py;
   const int64_t coff = 2 * col * I.N;                // column offset in T units
@@ -262,9 +266,9 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   bool own[V];          // position owned by this strip
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    const int64_t p = p0 + lq + v;
+    const int p = p0 + lq + v;
     if (I.px) {
-      int64_t w = p % opr;
+      int w = p % opr;
       if (w < 0) w += opr;
       wpos[v] = static_cast<int>(w);
       pres[v] = true;
@@ -274,16 +278,18 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     }
     own[v] = lane_own && p >= 0 && p < opr;
   }
-  auto row_of = [&](int64_t r, bool& present) -> int64_t {
+  auto row_of = [&](int r, bool& present) -> int {
     if (py) {
       while (r < 0) r += Ly;
       while (r >= Ly) r -= Ly;
       present = true;
       return r;
     }
-    present = r >= 0 && r < Ly;
+    present = static_cast<unsigned>(r) < static_cast<unsigned>(Ly);
     return r;
   };
+  // T offset of row rw (inside the lattice) in a column
+  auto row_off = [&](int rw) -> int64_t { return 2 * static_cast<int64_t>(rw * opr); };
 
   gT* base = (gT*)(I.base);
   const gT* curv = (st.slot_cur < 0 ? (const gT*)(I.src)
@@ -295,52 +301,12 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   const gT* psi0 = (const gT*)(I.psi0) + coff;
   gT* carry = MOM && I.carry ? (gT*)(I.carry) + coff : nullptr;
 
-  auto load_row = [&](const gT* vec, int64_t r, C (&d)[V]) {
-    bool rp;
-    const int64_t rw = row_of(r, rp);
-    if (!rp) {
+  // output slot of each level (nullptr: not stored)
+  gT* outv[KT];
 #pragma unroll
-      for (int v = 0; v < V; ++v) d[v] = {T(0), T(0)};
-      return;
-    }
-    const gT* rowp = vec + 2 * rw * opr;
-    if (fast) {
-      ldv<V>(rowp + 2 * p0 + 2 * lq, d);
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v) d[v] = pres[v] ? ld1(rowp + 2 * wpos[v]) : C{T(0), T(0)};
-    }
-  };
-  auto load_eps = [&](int64_t r, T (&d)[V]) {
-    bool rp;
-    const int64_t rw = row_of(r, rp);
-    if (!rp) {
-#pragma unroll
-      for (int v = 0; v < V; ++v) d[v] = T(0);
-      return;
-    }
-    const gT* rowp = eps + rw * opr;
-    if (fast) {
-      ldr<V>(rowp + p0 + lq, d);
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v) d[v] = pres[v] ? rowp[wpos[v]] : T(0);
-    }
-  };
-  // row rw must be inside [0, Ly); nt: non-temporal (Chebyshev slots)
-  auto store_row = [&](gT* vec, int64_t rw, const C (&o)[V], bool nt) {
-    gT* rowp = vec + 2 * rw * opr;
-    if (fast) {
-      if (lane_own) {
-        if (nt) stv_nt<V>(rowp + 2 * p0 + 2 * lq, o);
-        else stv<V>(rowp + 2 * p0 + 2 * lq, o);
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (own[v]) st1(rowp + 2 * wpos[v], o[v]);
-    }
-  };
+  for (int l = 0; l < KT; ++l)
+    outv[l] = st.slot_out[l] >= 0 ? base + 2 * (int64_t)st.slot_out[l] * I.slot_stride + coff
+                                  : nullptr;
 
   // ---- register rows: lo/mid/hi = the last three rows of levels 0..KT-1
   C lo[KT][V], mid[KT][V], hi[KT][V];
@@ -369,17 +335,12 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
   for (int k = 0; k < NQ; ++k) sq[k] = T(0);
   double accq = 0.0;
-  // psi0 rows r0 - k (moment epilogue), carried-state row r0 - 1
-  C pq[MOM ? KT + 1 : 1][V], npq[V], ncar[V];
+  // psi0 rows r0 - k (moment epilogue)
+  C pq[MOM ? KT + 1 : 1][V];
 #pragma unroll
   for (int k = 0; k < (MOM ? KT + 1 : 1); ++k)
 #pragma unroll
     for (int v = 0; v < V; ++v) pq[k][v] = {T(0), T(0)};
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    npq[v] = {T(0), T(0)};
-    ncar[v] = {T(0), T(0)};
-  }
   const bool dots = MOM && (st.dot_psi0 || st.dot_self);
   const bool want_psi0 = MOM && st.dot_psi0;
   const bool carry_in = MOM && carry && st.carry_mode == 2;
@@ -388,179 +349,244 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   const T beta0 = static_cast<T>(I.beta0);
   const T oscale = static_cast<T>(I.onsite_scale);
   const bool vert = I.kind != CSP_CHAIN;
+  const int n_iter = (y1 - y0) + 2 * nlev;
+  const int rbase = y0 - nlev;                       // level-0 row of iteration 0
 
-  const int64_t n_iter = (y1 - y0) + 2 * nlev;
-  const int64_t rbase = y0 - nlev;                   // level-0 row of iteration 0
-  C ncur[V], nprev[V], pv[V];
-  T neps[V];
-  load_row(curv, rbase, ncur);
-  if (prevv) {
-    load_row(prevv, rbase - 1, nprev);
-  } else {
-#pragma unroll
-    for (int v = 0; v < V; ++v) nprev[v] = {T(0), T(0)};
-  }
-  if constexpr (EPS) load_eps(rbase, neps);
-  if (want_psi0) load_row(psi0, rbase, npq);
-  if (carry_in) load_row(carry, rbase - 1, ncar);
-
-#pragma unroll 1
-  for (int64_t i = 0; i < n_iter; ++i) {
-    const int64_t r0 = rbase + i;
-    // level 0 takes row r0
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      lo[0][v] = mid[0][v];
-      mid[0][v] = hi[0][v];
-      hi[0][v] = ncur[v];
-      pv[v] = nprev[v];
-    }
-    if constexpr (EPS) {
-#pragma unroll
-      for (int k = KT; k >= 1; --k)
-#pragma unroll
-        for (int v = 0; v < V; ++v) er[k][v] = er[k - 1][v];
-#pragma unroll
-      for (int v = 0; v < V; ++v) er[0][v] = neps[v];
-    }
-    C car[V];
-    if constexpr (MOM) {
-#pragma unroll
-      for (int k = KT; k >= 1; --k)
-#pragma unroll
-        for (int v = 0; v < V; ++v) pq[k][v] = pq[k - 1][v];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        pq[0][v] = npq[v];
-        car[v] = ncar[v];
-      }
-    }
-    if (i + 1 < n_iter) {
-      load_row(curv, r0 + 1, ncur);
-      if (prevv) load_row(prevv, r0, nprev);
-      if constexpr (EPS) load_eps(r0 + 1, neps);
-      if (want_psi0) load_row(psi0, r0 + 1, npq);
-      if (carry_in) load_row(carry, r0, ncar);
-    }
-    // phi_n itself for the contraction (order 0 of a block)
-    if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0], true);
-
-#pragma unroll
-    for (int l = 1; l <= KT; ++l) {
-      if (l > nlev || i < 2 * l) break;
-      const int64_t r = r0 - l;
+  // The row loop, compiled twice: FAST for strips inside the row (no wrap,
+  // every position a site: wide loads and stores, whole lanes owned), and
+  // the general form with per-position wrap, presence and ownership.
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    auto load_row = [&](const gT* vec, int r, C (&d)[V]) {
       bool rp;
-      const int64_t rw = row_of(r, rp);
-      const T scale = (l == 1 && st.first) ? T(0.5) : T(1);
-      const T as = scale * alpha, bs = scale * beta0, os_ = scale * oscale;
-      // level l-1 rows r - 1, r, r + 1 and level l-2 row r (phi_{n+l-2})
-      const C(&up)[V] = lo[l - 1];
-      const C(&c)[V] = mid[l - 1];
-      const C(&dn)[V] = hi[l - 1];
-      C o[V];
-      if (rp) {
-        const T lx = shr1(c[V - 1].x), ly = shr1(c[V - 1].y);
-        const T rx = shl1(c[0].x), ry = shl1(c[0].y);
+      const int rw = row_of(r, rp);
+      if (!rp) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          T nx = (v > 0 ? c[v - 1].x : lx) + (v < V - 1 ? c[v + 1].x : rx);
-          T ny = (v > 0 ? c[v - 1].y : ly) + (v < V - 1 ? c[v + 1].y : ry);
-          if constexpr (HONEY) {
-            // even orbital: partner one row up (pos + 1); odd: one row down (pos - 1)
-            if (v % 2 == 0) {
-              nx += up[v + 1].x;
-              ny += up[v + 1].y;
-            } else {
-              nx += dn[v - 1].x;
-              ny += dn[v - 1].y;
-            }
-          } else {
-            if (vert) {
-              nx += up[v].x + dn[v].x;
-              ny += up[v].y + dn[v].y;
-            }
-          }
-          const C p = l == 1 ? pv[v] : lo[l - 2 >= 0 ? l - 2 : 0][v];
-          T beta = bs;
-          if constexpr (EPS) beta = bs + os_ * er[l][v];
-          o[v].x = as * nx + (beta * c[v].x - p.x);
-          o[v].y = as * ny + (beta * c[v].y - p.y);
-        }
-        if (!fast) {
+        for (int v = 0; v < V; ++v) d[v] = {T(0), T(0)};
+        return;
+      }
+      const gT* rowp = vec + row_off(rw);
+      if constexpr (FAST) {
+        ldv<V>(rowp + 2 * p0 + 2 * lq, d);
+      } else {
 #pragma unroll
-          for (int v = 0; v < V; ++v)
-            if (!pres[v]) o[v] = {T(0), T(0)};
+        for (int v = 0; v < V; ++v) d[v] = pres[v] ? ld1(rowp + 2 * wpos[v]) : C{T(0), T(0)};
+      }
+    };
+    auto load_eps = [&](int r, T (&d)[V]) {
+      bool rp;
+      const int rw = row_of(r, rp);
+      if (!rp) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = T(0);
+        return;
+      }
+      const gT* rowp = eps + row_off(rw) / 2;
+      if constexpr (FAST) {
+        ldr<V>(rowp + p0 + lq, d);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = pres[v] ? rowp[wpos[v]] : T(0);
+      }
+    };
+    // row rw must be inside [0, Ly); nt: non-temporal (Chebyshev slots)
+    auto store_row = [&](gT* vec, int rw, const C (&o)[V], bool nt) {
+      gT* rowp = vec + row_off(rw);
+      if constexpr (FAST) {
+        if (lane_own) {
+          if (nt) stv_nt<V>(rowp + 2 * p0 + 2 * lq, o);
+          else stv<V>(rowp + 2 * p0 + 2 * lq, o);
         }
       } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = {T(0), T(0)};
+        for (int v = 0; v < V; ++v)
+          if (own[v]) st1(rowp + 2 * wpos[v], o[v]);
       }
-      if (l < KT) {
+    };
+
+    C ncur[V], nprev[V], pv[V], npq[V], ncar[V], car[V];
+    T neps[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      nprev[v] = {T(0), T(0)};
+      npq[v] = {T(0), T(0)};
+      ncar[v] = {T(0), T(0)};
+    }
+    load_row(curv, rbase, ncur);
+    if (prevv) load_row(prevv, rbase - 1, nprev);
+    if constexpr (EPS) load_eps(rbase, neps);
+    if (want_psi0) load_row(psi0, rbase, npq);
+    if (carry_in) load_row(carry, rbase - 1, ncar);
+
+    int flush_in = kFlush;                           // rows left before the next flush
+#pragma unroll 1
+    for (int i = 0; i < n_iter; ++i) {
+      const int r0 = rbase + i;
+      // level 0 takes row r0
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        lo[0][v] = mid[0][v];
+        mid[0][v] = hi[0][v];
+        hi[0][v] = ncur[v];
+        pv[v] = nprev[v];
+      }
+      if constexpr (EPS) {
+#pragma unroll
+        for (int k = KT; k >= 1; --k)
+#pragma unroll
+          for (int v = 0; v < V; ++v) er[k][v] = er[k - 1][v];
+#pragma unroll
+        for (int v = 0; v < V; ++v) er[0][v] = neps[v];
+      }
+      if constexpr (MOM) {
+#pragma unroll
+        for (int k = KT; k >= 1; --k)
+#pragma unroll
+          for (int v = 0; v < V; ++v) pq[k][v] = pq[k - 1][v];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          lo[l][v] = mid[l][v];
-          mid[l][v] = hi[l][v];
-          hi[l][v] = o[v];
+          pq[0][v] = npq[v];
+          car[v] = ncar[v];
         }
       }
-      if (r >= y0 && r < y1) {
-        const int so = st.slot_out[l - 1];
-        if (so >= 0) store_row(base + 2 * (int64_t)so * I.slot_stride + coff, rw, o, true);
-        if constexpr (MOM) {
-          if (dots) {
-            const C(&q)[V] = pq[l];
-            T* s = sq + 5 * (l - 1);
+      if (i + 1 < n_iter) {
+        load_row(curv, r0 + 1, ncur);
+        if (prevv) load_row(prevv, r0, nprev);
+        if constexpr (EPS) load_eps(r0 + 1, neps);
+        if (want_psi0) load_row(psi0, r0 + 1, npq);
+        if (carry_in) load_row(carry, r0, ncar);
+      }
+      // phi_n itself for the contraction (order 0 of a block)
+      if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0], true);
+
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-              if (!own[v]) continue;
-              if (want_psi0) {
-                s[0] += q[v].x * o[v].x + q[v].y * o[v].y;
-                s[1] += q[v].x * o[v].y - q[v].y * o[v].x;
-                if (l == 1) {
-                  sq[5 * KT] += q[v].x * c[v].x + q[v].y * c[v].y;
-                  sq[5 * KT + 1] += q[v].x * c[v].y - q[v].y * c[v].x;
+      for (int l = 1; l <= KT; ++l) {
+        if (l > nlev || i < 2 * l) break;
+        const int r = r0 - l;
+        bool rp;
+        const int rw = row_of(r, rp);
+        const T scale = (l == 1 && st.first) ? T(0.5) : T(1);
+        const T as = scale * alpha, bs = scale * beta0, os_ = scale * oscale;
+        // level l-1 rows r - 1, r, r + 1 and level l-2 row r (phi_{n+l-2})
+        const C(&up)[V] = lo[l - 1];
+        const C(&c)[V] = mid[l - 1];
+        const C(&dn)[V] = hi[l - 1];
+        C o[V];
+        if (rp) {
+          const T lx = shr1(c[V - 1].x), ly = shr1(c[V - 1].y);
+          const T rx = shl1(c[0].x), ry = shl1(c[0].y);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T nx = (v > 0 ? c[v - 1].x : lx) + (v < V - 1 ? c[v + 1].x : rx);
+            T ny = (v > 0 ? c[v - 1].y : ly) + (v < V - 1 ? c[v + 1].y : ry);
+            if constexpr (HONEY) {
+              // even orbital: partner one row up (pos + 1); odd: one row down (pos - 1)
+              if (v % 2 == 0) {
+                nx += up[v + 1].x;
+                ny += up[v + 1].y;
+              } else {
+                nx += dn[v - 1].x;
+                ny += dn[v - 1].y;
+              }
+            } else {
+              if (vert) {
+                nx += up[v].x + dn[v].x;
+                ny += up[v].y + dn[v].y;
+              }
+            }
+            const C p = l == 1 ? pv[v] : lo[l - 2 >= 0 ? l - 2 : 0][v];
+            T beta = bs;
+            if constexpr (EPS) beta = bs + os_ * er[l][v];
+            o[v].x = as * nx + (beta * c[v].x - p.x);
+            o[v].y = as * ny + (beta * c[v].y - p.y);
+          }
+          if constexpr (!FAST) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+              if (!pres[v]) o[v] = {T(0), T(0)};
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) o[v] = {T(0), T(0)};
+        }
+        if (l < KT) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            lo[l][v] = mid[l][v];
+            mid[l][v] = hi[l][v];
+            hi[l][v] = o[v];
+          }
+        }
+        if (r >= y0 && r < y1) {
+          if (outv[l - 1]) store_row(outv[l - 1], rw, o, true);
+          if constexpr (MOM) {
+            if (dots) {
+              // values outside the owned positions take no part in the sums
+              // (interior strips: whole lanes, masked when the sums are
+              // flushed)
+              C oo[V], cc[V];
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                const bool w = FAST ? true : own[v];
+                oo[v] = w ? o[v] : C{T(0), T(0)};
+                cc[v] = w ? c[v] : C{T(0), T(0)};
+              }
+              const C(&q)[V] = pq[l];
+              const int q0 = 5 * (l - 1);
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                if (want_psi0) {
+                  sq[q0] += q[v].x * oo[v].x + q[v].y * oo[v].y;
+                  sq[q0 + 1] += q[v].x * oo[v].y - q[v].y * oo[v].x;
+                  if (l == 1) {
+                    sq[5 * KT] += q[v].x * cc[v].x + q[v].y * cc[v].y;
+                    sq[5 * KT + 1] += q[v].x * cc[v].y - q[v].y * cc[v].x;
+                  }
+                }
+                if (st.dot_self) {
+                  sq[q0 + 2] += oo[v].x * oo[v].x + oo[v].y * oo[v].y;
+                  sq[q0 + 3] += oo[v].x * c[v].x + oo[v].y * c[v].y;
+                  sq[q0 + 4] += oo[v].x * c[v].y - oo[v].y * c[v].x;
                 }
               }
-              if (st.dot_self) {
-                s[2] += o[v].x * o[v].x + o[v].y * o[v].y;
-                s[3] += o[v].x * c[v].x + o[v].y * c[v].y;
-                s[4] += o[v].x * c[v].y - o[v].y * c[v].x;
+            }
+            if (l == 1 && st.carry_mode && carry) {
+              const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
+              const T c1r = static_cast<T>(st.cc1[0]), c1i = static_cast<T>(st.cc1[1]);
+              C b[V];
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                if (st.carry_mode == 1) {
+                  b[v].x = c0r * c[v].x - c0i * c[v].y;
+                  b[v].y = c0r * c[v].y + c0i * c[v].x;
+                } else {
+                  b[v] = car[v];
+                }
+                b[v].x += c1r * o[v].x - c1i * o[v].y;
+                b[v].y += c1r * o[v].y + c1i * o[v].x;
               }
+              store_row(carry, rw, b, false);
             }
           }
-          if (l == 1 && st.carry_mode && carry) {
-            const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
-            const T c1r = static_cast<T>(st.cc1[0]), c1i = static_cast<T>(st.cc1[1]);
-            C b[V];
+        }
+      }
+      if constexpr (MOM) {
+        if (dots && (--flush_in == 0 || i + 1 == n_iter)) {
+          flush_in = kFlush;
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-              if (st.carry_mode == 1) {
-                b[v].x = c0r * c[v].x - c0i * c[v].y;
-                b[v].y = c0r * c[v].y + c0i * c[v].x;
-              } else {
-                b[v] = car[v];
-              }
-              b[v].x += c1r * o[v].x - c1i * o[v].y;
-              b[v].y += c1r * o[v].y + c1i * o[v].x;
-            }
-            store_row(carry, rw, b, false);
+          for (int k = 0; k < NQ; ++k) {
+            T x = (FAST && !lane_own) ? T(0) : sq[k];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+            if (lane == k) accq += static_cast<double>(x);
+            sq[k] = T(0);
           }
         }
       }
     }
-    if constexpr (MOM) {
-      if (dots && (((i + 1) % kFlush) == 0 || i + 1 == n_iter)) {
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-          T x = sq[k];
-#pragma unroll
-          for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
-          if (lane == k) accq += static_cast<double>(x);
-          sq[k] = T(0);
-        }
-      }
-    }
-  }
+  };
+  if (fast) run(std::true_type{});
+  else run(std::false_type{});
 
   if constexpr (MOM) {
     if (dots) {

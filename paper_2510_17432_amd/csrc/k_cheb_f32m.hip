@@ -12,6 +12,7 @@ hipError_t launch_cheb_f32m(int vec, int kt, bool honey, bool eps, const ChebIns
     case 201: CSP_CHEB_LAUNCH(float, 2, 1, true); break;
     case 202: CSP_CHEB_LAUNCH(float, 2, 2, true); break;
     case 204: CSP_CHEB_LAUNCH(float, 2, 4, true); break;
+    case 208: CSP_CHEB_LAUNCH(float, 2, 8, true); break;
     case 401: CSP_CHEB_LAUNCH(float, 4, 1, true); break;
     case 402: CSP_CHEB_LAUNCH(float, 4, 2, true); break;
     case 404: CSP_CHEB_LAUNCH(float, 4, 4, true); break;

@@ -519,7 +519,7 @@ SHAPE_LATS = [
     dict(kind="chain", Lx=301, t=1.0, W=1.0, disorder_seed=3),
 ]
 SHAPES = {("fp32_conc", 0): [(v, k) for v in (2, 4) for k in (1, 2, 4, 8)],
-          ("fp32_conc", 1): [(v, k) for v in (2, 4) for k in (1, 2, 4)],
+          ("fp32_conc", 1): [(v, k) for v in (2, 4) for k in (1, 2, 4)] + [(2, 8)],
           ("fp64_conc", 0): [(2, 1), (2, 2), (2, 4)],
           ("fp64_conc", 1): [(2, 1), (2, 2), (2, 4)]}
 
@@ -561,9 +561,11 @@ def test_set_tuning_rejects_missing_shapes(csp, ctx):
     with pytest.raises(csp.CspError) as e:
         csp.csp_set_tuning(ctx, [g], [1], params, T)
     assert e.value.status == csp.CSP_EINVAL
-    T.spmm_vec, T.spmm_steps = 2, 8
+    T.spmm_vec, T.spmm_steps = 4, 8
     pm = csp.make_params(10, mode="fp32_conc", assembly=csp.CSP_ASSEMBLE_MOMENTS)
-    with pytest.raises(csp.CspError) as e:          # no moment kernel with 8 steps
+    with pytest.raises(csp.CspError) as e:          # no moment kernel with 4 values x 8 steps
         csp.csp_set_tuning(ctx, [g], [1], pm, T)
     assert e.value.status == csp.CSP_EINVAL
+    T.spmm_vec = 2
+    csp.csp_set_tuning(ctx, [g], [1], pm, T)
     csp.csp_set_tuning(ctx, [g], [1], params, T)
