@@ -58,6 +58,13 @@ def parse():
                     help="skip the moment-based form runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample")
+    ap.add_argument("--dos-1e9", action="store_true",
+                    help="instead of the step benchmark: the DOS of the 1e9-orbital square "
+                         "lattice (31623^2, W = 0.5, 4 random columns, Nt = 4096) in the "
+                         "complex64 moment and state forms against the complex128 moment form, "
+                         "and the complex128 sequential form timed on a truncated run")
+    ap.add_argument("--seq-steps", type=int, default=8,
+                    help="time steps of the truncated complex128 sequential run (--dos-1e9)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 2 GiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -123,12 +130,102 @@ def cpu_baseline(W, seconds):
                       "excluded" % (lat.N, nt, cnt["amxsy"], el, t_setup)}
 
 
+def dos_1e9(a):
+    """DOS of the 1e9-orbital square lattice: complex64 concurrent forms against
+    the complex128 moment form (checked against the oracle on small lattices by
+    the parity tests), with the time of each, and the complex128 sequential
+    form timed on a truncated run and scaled to all Nt steps (its cost is
+    linear in the steps, Tab. cost)."""
+    import numpy as np
+    import torch
+    import paper_2510_17432_amd as csp
+    w = csp_inputs.SQUARE31623
+    Nt = w["Nt"]
+    ctx = csp.Context(0)
+    t0 = time.perf_counter()
+    lat = csp.Lattice(ctx, w["kind"], w["Lx"], w["Ly"], t=w["t"], W=w["W"],
+                      disorder_seed=w["disorder_seed"])
+    N, R = lat.N, w["R"]
+    log("lattice N=%d |H|=%.6f R=%d Nt=%d (%.1f s)" % (N, lat.halfwidth, R, Nt,
+                                                       time.perf_counter() - t0))
+    dev = "cuda:0"
+    psi64 = torch.empty((N, R), dtype=torch.complex128, device=dev)
+    csp.csp_states_random_phase(ctx, psi64, R, w["seed_states"])
+    out = {"workload": "square 31623x31623 (N=%d), t=1, W=0.5 (seed %d), periodic, %d random "
+                       "columns (seed %d), Nt=%d" % (N, w["disorder_seed"], R, w["seed_states"], Nt),
+           "halfwidth": lat.halfwidth}
+
+    def run(psi, mode, assembly, b=0, steps=Nt, per_column=False):
+        # per_column: one call per column (each finishes in about a minute)
+        corr = torch.empty((steps + 1, R), dtype=torch.complex128, device=dev)
+        params = csp.make_params(steps, mode=mode, block_b=b, assembly=assembly)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cols = [(k, k + 1) for k in range(R)] if per_column else [(0, R)]
+        passes = 0
+        for (c0, c1) in cols:
+            p = psi[:, c0:c1].contiguous() if per_column else psi
+            cc = torch.empty((steps + 1, c1 - c0), dtype=torch.complex128, device=dev)
+            _, rep = csp.csp_propagate(ctx, lat, p, params, corr=cc)
+            corr[:, c0:c1] = cc
+            passes += rep.n_passes
+            del p
+            torch.cuda.synchronize()
+            log("  %s assembly %d columns %d..%d: %.1f s" % (mode, assembly, c0, c1 - 1,
+                                                          time.perf_counter() - t))
+        _, _, Dm = csp.csp_dos(ctx, corr, lat.halfwidth)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ctx.trim()
+        return corr, Dm, el, rep, passes
+
+    c64, D64, t64m, r64, p64 = run(psi64, "fp64_conc", csp.CSP_ASSEMBLE_MOMENTS, per_column=True)
+    log("complex128 moments: %.1f s" % t64m)
+    # complex128 sequential (b = 1, psi(t_j) accumulated in the recursion, one
+    # dot per step): a truncated run, scaled linearly to Nt steps
+    _, _, ts, _, _ = run(psi64, "fp64_seq", csp.CSP_ASSEMBLE_MOMENTS, 1, a.seq_steps,
+                         per_column=True)
+    t_seq = ts * Nt / a.seq_steps
+    log("complex128 sequential: %d steps in %.1f s -> %.0f s for %d" % (a.seq_steps, ts, t_seq, Nt))
+    psi32 = psi64.to(torch.complex64)
+    del psi64
+    ctx.trim()
+    torch.cuda.empty_cache()
+    ref_c, ref_d = c64.cpu().numpy(), D64.cpu().numpy()
+    del c64, D64
+    res = {}
+    for name, assembly, b, pc in (("fp32_moments", csp.CSP_ASSEMBLE_MOMENTS, 0, False),
+                                  ("fp32_states", csp.CSP_ASSEMBLE_STATES, 16, True)):
+        c32, D32, el, rep, npass = run(psi32, "fp32_conc", assembly, b, per_column=pc)
+        rel = float(np.max(np.abs(D32.cpu().numpy() - ref_d)) / np.max(np.abs(ref_d)))
+        eps = float(np.max(np.abs(c32.cpu().numpy() - ref_c)))
+        res[name] = {"s": el, "dos_rel_err": rel, "corr_eps_inf": eps, "block_b": rep.block_b,
+                     "chunk_K": rep.chunk_K, "calls_x_passes": npass,
+                     "recursion_steps_per_column": rep.amxsy}
+        log("%s: %.1f s, DOS rel err %.2e, eps_inf %.2e" % (name, el, rel, eps))
+        del c32, D32
+    del psi32
+    out.update({"fp64_moments_s": t64m, "fp64_moments_calls_x_passes": p64,
+                "fp64_sequential_s_extrapolated": t_seq,
+                "fp64_sequential_sample": "%d of %d steps in %.2f s" % (a.seq_steps, Nt, ts),
+                "target_rel_err": 1e-4})
+    for k, v in res.items():
+        out[k] = v
+        out[k]["speedup_vs_fp64_sequential"] = t_seq / v["s"]
+    lat.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.dos_1e9:
+        dos_1e9(a)
+        return
     import numpy as np
     import torch
     import paper_2510_17432_amd as csp

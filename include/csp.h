@@ -72,8 +72,9 @@ typedef enum {
     CSP_ASSEMBLE_STATES = 0,
     /* Moment-based form (Sec. II.A): reduce the block moments
      * mu_n = <psi0|T_n(H~) s_k> in the recursion kernel's epilogue and form
-     * C(t_j) = sum_n c_n(j tau) mu_n in FP64; three Chebyshev vectors per
-     * column are kept.  With one block (block_b = 0 or >= Nt) and no final
+     * C(t_j) = sum_n c_n(j tau) mu_n in FP64; four Chebyshev vectors per
+     * column are kept (phi_n, phi_{n-1} and the two newest orders of a
+     * recursion launch) besides psi0.  With one block (block_b = 0 or >= Nt) and no final
      * state requested this is DOS-Concurrent-M of Sec. III: the moments
      * above N/2 come from the halving identity of Eq. (cheby_prod),
      * mu_2k = 2<phi_k|phi_k> - mu_0 and mu_2k+1 = 2<phi_k+1|phi_k> - mu_1,

@@ -492,7 +492,7 @@ extern "C" csp_status csp_chebyshev_step(csp_context* c, const csp_lattice* L, i
   st.slot_cur = 0;
   st.slot_prev = 1;
   st.slot_out[0] = 2;
-  HIPCALL(launch_cheb(fp64, p.vec, p.kt, false, d_inst, p.runs, st, s));
+  HIPCALL(launch_cheb(fp64, p.vec, p.kt, false, false, d_inst, p.runs, st, s));
   HIPCALL(launch_scatter_cols(N, R, 0, R, dtype, slots + 2 * stride * csz, fp64, dev_y, s));
   HIPCALL(hipStreamSynchronize(s));
   return CSP_OK;
@@ -1074,7 +1074,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       for (int l = 1; l <= stb.nlev; ++l) stb.slot_out[l - 1] = (produced + l) % S;
       size_t ev = 0;
       if (!from_dev) CHECK(prof.begin(0, &ev));
-      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, d_spmm, sp_plan.runs, stb, strm));
+      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_spmm, sp_plan.runs, stb, strm));
       if (!from_dev) CHECK(prof.end(ev));
       produced += stb.nlev;
       CHECK(run_chunks());
@@ -1281,9 +1281,11 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   std::vector<ChebInst> sp;
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_MOMENTS);
-  // the carried state is accumulated one step per launch
-  const int kt_want = carry ? 1 : (tune ? tune->spmm_steps : 4);
-  const ChebPlan sp_plan = plan_cheb(sp, fp64, true, c->n_cu, tune ? tune->spmm_vec : 0, kt_want,
+  int vec_want = tune ? tune->spmm_vec : 0;
+  int kt_want = tune ? tune->spmm_steps : 4;
+  if (carry && !cheb_carry_supported(fp64, 2, kt_want)) kt_want = 4;
+  if (carry) vec_want = 2;   // the carried-state kernels hold 2 values per lane
+  const ChebPlan sp_plan = plan_cheb(sp, fp64, true, c->n_cu, vec_want, kt_want,
                                      tune ? tune->spmm_seg_rows : 0);
   const int kt = sp_plan.kt;
   const int P_batch = 16;
@@ -1434,12 +1436,12 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         };
         st.carry_mode = produced == 0 ? 1 : 2;
         coef(0, st.cc0);
-        coef(produced + 1, st.cc1);
-        axpy += produced == 0 ? 2 : 1;
+        for (int l = 1; l <= st.nlev; ++l) coef(produced + l, st.ccl[l - 1]);
+        axpy += st.nlev + (produced == 0 ? 1 : 0);
       }
       size_t ev = 0;
       CHECK(prof.begin(0, &ev));
-      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, true, d_spmm, sp_plan.runs, st, s));
+      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, true, carry, d_spmm, sp_plan.runs, st, s));
       CHECK(prof.end(ev));
       ++n_spmm;
       amxsy += st.nlev;
@@ -1712,7 +1714,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
     st.partial = d_part;
     double ms = 0;
     CHECK(time_launch(c, [&]() -> csp_status {
-      HIPCALL(launch_cheb(fp64, p.vec, p.kt, mom, d_spmm, p.runs, st, s));
+      HIPCALL(launch_cheb(fp64, p.vec, p.kt, mom, false, d_spmm, p.runs, st, s));
       return CSP_OK;
     }, &ms));
     ms /= p.kt;

@@ -124,10 +124,12 @@ struct ChebStep {
   int32_t seg_rows;            // rows per work item
   int32_t ow;                  // owned values per strip (64 V - 2 margin)
   int32_t dot_psi0, dot_self;  // moment epilogue sums (see k_cheb)
-  int32_t carry_mode;          // 0 none, 1 carry = cc0 phi_n + cc1 phi_{n+1}, 2 carry += cc1 phi_{n+1}
+  int32_t carry_mode;          // 0 none; 1 carry = cc0 phi_n + sum_l ccl[l-1] phi_{n+l};
+                               // 2 carry += sum_l ccl[l-1] phi_{n+l}
   int32_t mom_slot;            // launch index inside the partial-sum buffer
   int32_t pad;
-  double cc0[2], cc1[2];
+  double cc0[2];               // complex coefficient of phi_n (carry_mode 1)
+  double ccl[8][2];            // complex coefficient of level l (phi_{n+l})
   double* partial;             // [slot][KT][items][4] complex records
   int64_t total_items;
 };
@@ -139,10 +141,12 @@ struct ChebRun {
   int64_t item0, n_items;
   bool honey, eps;
 };
-hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, const ChebInst* d_inst,
+// mom: moment epilogue; carry: also the carried state (moment epilogue only)
+hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const ChebInst* d_inst,
                        const std::vector<ChebRun>& runs, const ChebStep& st, hipStream_t s);
 // (values per lane, steps per launch) pairs with a compiled kernel
 bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom);
+bool cheb_carry_supported(bool fp64, int vec, int kt);
 // margin positions per strip side: kt rounded up to a multiple of vec
 int cheb_margin(int vec, int kt);
 

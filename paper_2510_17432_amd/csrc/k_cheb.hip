@@ -1,6 +1,6 @@
 // Chebyshev recursion launches: the kernel itself (k_cheb_body.h) is
-// instantiated per precision in k_cheb_f32.hip, k_cheb_f32m.hip and
-// k_cheb_f64.hip; this file picks the instantiation for each run of
+// instantiated per precision and epilogue in k_cheb_f32*.hip and
+// k_cheb_f64*.hip; this file picks the instantiation for each run of
 // instances with the same lattice class, and sums the moment records.
 #include "csp_internal.h"
 
@@ -13,6 +13,8 @@ CSP_CHEB_LAUNCHER(launch_cheb_f32)
 CSP_CHEB_LAUNCHER(launch_cheb_f32m)
 CSP_CHEB_LAUNCHER(launch_cheb_f64)
 CSP_CHEB_LAUNCHER(launch_cheb_f64m)
+CSP_CHEB_LAUNCHER(launch_cheb_f32mc)
+CSP_CHEB_LAUNCHER(launch_cheb_f64mc)
 #undef CSP_CHEB_LAUNCHER
 
 bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom) {
@@ -21,23 +23,30 @@ bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom) {
   return kt == 1 || kt == 2 || kt == 4 || (kt == 8 && (!mom || vec == 2));
 }
 
+bool cheb_carry_supported(bool fp64, int vec, int kt) {
+  return vec == 2 && (kt == 1 || kt == 2 || kt == 4 || (kt == 8 && !fp64));
+}
+
 int cheb_margin(int vec, int kt) { return (kt + vec - 1) / vec * vec; }
 
-hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, const ChebInst* d_inst,
+hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const ChebInst* d_inst,
                        const std::vector<ChebRun>& runs, const ChebStep& st, hipStream_t s) {
   if (st.nlev < 1 || st.nlev > kt) return hipErrorInvalidValue;
   if (!cheb_shape_supported(fp64, vec, kt, mom)) return hipErrorInvalidValue;
+  if (carry && (!mom || !cheb_carry_supported(fp64, vec, kt))) return hipErrorInvalidValue;
   if (st.ow != 64 * vec - 2 * cheb_margin(vec, kt)) return hipErrorInvalidValue;
   for (const ChebRun& r : runs) {
     const ChebInst* di = d_inst + r.inst0;
     const int64_t lo = r.item0, hi = r.item0 + r.n_items;
     hipError_t e;
     if (fp64)
-      e = mom ? launch_cheb_f64m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
-              : launch_cheb_f64(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
+      e = carry ? launch_cheb_f64mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+          : mom ? launch_cheb_f64m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+                : launch_cheb_f64(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
     else
-      e = mom ? launch_cheb_f32m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
-              : launch_cheb_f32(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
+      e = carry ? launch_cheb_f32mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+          : mom ? launch_cheb_f32m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+                : launch_cheb_f32(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

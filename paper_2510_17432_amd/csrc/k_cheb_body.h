@@ -223,7 +223,7 @@ template <int V, int KT> struct Shape {
 };
 
 // insts: the instances of this launch (consecutive items item_lo..item_hi-1).
-template <typename T, int V, int KT, bool HONEY, bool EPS, bool MOM>
+template <typename T, int V, int KT, bool HONEY, bool EPS, bool MOM, bool CARRY>
 __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts, int n_inst,
                                               int64_t item_lo, int64_t item_hi, ChebStep st) {
   static_assert(V % 2 == 0, "lanes hold whole (even, odd) orbital pairs");
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                                 : nullptr;
   const gT* eps = (const gT*)(I.eps);
   const gT* psi0 = (const gT*)(I.psi0) + coff;
-  gT* carry = MOM && I.carry ? (gT*)(I.carry) + coff : nullptr;
+  gT* carry = CARRY && I.carry ? (gT*)(I.carry) + coff : nullptr;
 
   // output slot of each level (nullptr: not stored)
   gT* outv[KT];
@@ -343,7 +343,15 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     for (int v = 0; v < V; ++v) pq[k][v] = {T(0), T(0)};
   const bool dots = MOM && (st.dot_psi0 || st.dot_self);
   const bool want_psi0 = MOM && st.dot_psi0;
-  const bool carry_in = MOM && carry && st.carry_mode == 2;
+  // carried state: partial sums of rows r0 - 1 - j (j < KT) in registers;
+  // a row is read (carry_mode 2), completed and written once per launch
+  const bool carry_on = CARRY && carry && st.carry_mode != 0;
+  const bool carry_in = CARRY && carry && st.carry_mode == 2;
+  C cpr[CARRY ? KT : 1][V];
+#pragma unroll
+  for (int k = 0; k < (CARRY ? KT : 1); ++k)
+#pragma unroll
+    for (int v = 0; v < V; ++v) cpr[k][v] = {T(0), T(0)};
 
   const T alpha = static_cast<T>(I.alpha);
   const T beta0 = static_cast<T>(I.beta0);
@@ -416,7 +424,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     if (prevv) load_row(prevv, rbase - 1, nprev);
     if constexpr (EPS) load_eps(rbase, neps);
     if (want_psi0) load_row(psi0, rbase, npq);
-    if (carry_in) load_row(carry, rbase - 1, ncar);
+    if (carry_in) load_row(carry, rbase - nlev, ncar);
 
     int flush_in = kFlush;                           // rows left before the next flush
 #pragma unroll 1
@@ -449,12 +457,20 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
           car[v] = ncar[v];
         }
       }
+      if constexpr (CARRY) {
+#pragma unroll
+        for (int k = KT - 1; k >= 1; --k)
+#pragma unroll
+          for (int v = 0; v < V; ++v) cpr[k][v] = cpr[k - 1][v];
+#pragma unroll
+        for (int v = 0; v < V; ++v) cpr[0][v] = {T(0), T(0)};
+      }
       if (i + 1 < n_iter) {
         load_row(curv, r0 + 1, ncur);
         if (prevv) load_row(prevv, r0, nprev);
         if constexpr (EPS) load_eps(r0 + 1, neps);
         if (want_psi0) load_row(psi0, r0 + 1, npq);
-        if (carry_in) load_row(carry, r0, ncar);
+        if (carry_in) load_row(carry, r0 + 1 - nlev, ncar);
       }
       // phi_n itself for the contraction (order 0 of a block)
       if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0], true);
@@ -550,22 +566,35 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                 }
               }
             }
-            if (l == 1 && st.carry_mode && carry) {
+          }
+          if constexpr (CARRY) {
+            // level l adds c_{n+l} phi_{n+l} (and the first launch of a
+            // block c_n phi_n) to the partial carried row r = r0 - l
+            if (carry_on) {
+              const T clr = static_cast<T>(st.ccl[l - 1][0]), cli = static_cast<T>(st.ccl[l - 1][1]);
               const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
-              const T c1r = static_cast<T>(st.cc1[0]), c1i = static_cast<T>(st.cc1[1]);
-              C b[V];
 #pragma unroll
               for (int v = 0; v < V; ++v) {
-                if (st.carry_mode == 1) {
-                  b[v].x = c0r * c[v].x - c0i * c[v].y;
-                  b[v].y = c0r * c[v].y + c0i * c[v].x;
-                } else {
-                  b[v] = car[v];
+                C& b = cpr[l - 1][v];
+                b.x += clr * o[v].x - cli * o[v].y;
+                b.y += clr * o[v].y + cli * o[v].x;
+                if (l == 1 && st.carry_mode == 1) {
+                  b.x += c0r * c[v].x - c0i * c[v].y;
+                  b.y += c0r * c[v].y + c0i * c[v].x;
                 }
-                b[v].x += c1r * o[v].x - c1i * o[v].y;
-                b[v].y += c1r * o[v].y + c1i * o[v].x;
               }
-              store_row(carry, rw, b, false);
+              if (l == nlev) {                       // row r is complete
+                C b[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                  b[v] = cpr[l - 1][v];
+                  if (st.carry_mode == 2) {
+                    b[v].x += car[v].x;
+                    b[v].y += car[v].y;
+                  }
+                }
+                store_row(carry, rw, b, false);
+              }
             }
           }
         }
@@ -614,17 +643,17 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 
 // Launch helper for one instantiation file: (V, KT) pairs are listed by the
 // including file.
-#define CSP_CHEB_LAUNCH(T, V, KT, MOM)                                                         \
+#define CSP_CHEB_LAUNCH(T, V, KT, MOM, CARRY)                                                  \
   do {                                                                                         \
     if (honey) {                                                                               \
-      if (eps) hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, true, true, MOM>), grid, block, 0, s, \
-                                  d_inst, n_inst, item_lo, item_hi, st);                       \
-      else hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, true, false, MOM>), grid, block, 0, s,    \
-                              d_inst, n_inst, item_lo, item_hi, st);                           \
+      if (eps) hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, true, true, MOM, CARRY>), grid,      \
+                                  block, 0, s, d_inst, n_inst, item_lo, item_hi, st);          \
+      else hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, true, false, MOM, CARRY>), grid, block,  \
+                              0, s, d_inst, n_inst, item_lo, item_hi, st);                     \
     } else {                                                                                   \
-      if (eps) hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, false, true, MOM>), grid, block, 0,   \
-                                  s, d_inst, n_inst, item_lo, item_hi, st);                    \
-      else hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, false, false, MOM>), grid, block, 0, s,   \
-                              d_inst, n_inst, item_lo, item_hi, st);                           \
+      if (eps) hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, false, true, MOM, CARRY>), grid,     \
+                                  block, 0, s, d_inst, n_inst, item_lo, item_hi, st);          \
+      else hipLaunchKernelGGL((cheb::k_cheb<T, V, KT, false, false, MOM, CARRY>), grid, block, \
+                              0, s, d_inst, n_inst, item_lo, item_hi, st);                     \
     }                                                                                          \
   } while (0)

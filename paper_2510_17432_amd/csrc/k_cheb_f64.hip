@@ -4,28 +4,28 @@
 namespace csp {
 
 hipError_t launch_cheb_f64(int vec, int kt, bool honey, bool eps, const ChebInst* d_inst, int n_inst,
-                      int64_t item_lo, int64_t item_hi, const ChebStep& st, hipStream_t s) {
+                           int64_t item_lo, int64_t item_hi, const ChebStep& st, hipStream_t s) {
   const int64_t n = item_hi - item_lo;
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(double, 2, 1, false); break;
-    case 202: CSP_CHEB_LAUNCH(double, 2, 2, false); break;
-    case 204: CSP_CHEB_LAUNCH(double, 2, 4, false); break;
+    case 201: CSP_CHEB_LAUNCH(double, 2, 1, false, false); break;
+    case 202: CSP_CHEB_LAUNCH(double, 2, 2, false, false); break;
+    case 204: CSP_CHEB_LAUNCH(double, 2, 4, false, false); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_cheb_f64m(int vec, int kt, bool honey, bool eps, const ChebInst* d_inst, int n_inst,
-                      int64_t item_lo, int64_t item_hi, const ChebStep& st, hipStream_t s) {
+                            int64_t item_lo, int64_t item_hi, const ChebStep& st, hipStream_t s) {
   const int64_t n = item_hi - item_lo;
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(double, 2, 1, true); break;
-    case 202: CSP_CHEB_LAUNCH(double, 2, 2, true); break;
-    case 204: CSP_CHEB_LAUNCH(double, 2, 4, true); break;
+    case 201: CSP_CHEB_LAUNCH(double, 2, 1, true, false); break;
+    case 202: CSP_CHEB_LAUNCH(double, 2, 2, true, false); break;
+    case 204: CSP_CHEB_LAUNCH(double, 2, 4, true, false); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
