@@ -16,6 +16,8 @@ Contents, each following the passage cited beside it:
     Sec. II.B time blocks (C code in csp_oracle.c);
   * moment-based propagation, in time blocks or in one block with the
     halving of Eq. (cheby_prod) -- Sec. II.A, Sec. III DOS-Concurrent-M;
+  * quasi-eigenstates by forward and backward sequential propagation and
+    the sum of Eq. QE_coeff (QE section, QE-Sequential);
   * band-structure closed forms of clean periodic lattices (any size);
   * DOS from the correlation function -- Sec. III.
 
@@ -85,6 +87,11 @@ def lib():
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int64, _dp,
                                         ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int64, ctypes.c_int, _dp, _dp, _i64p]
+    L.orc_quasi_eigenstates.restype = ctypes.c_int
+    L.orc_quasi_eigenstates.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int64, _dp,
+                                        ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int64, _dp, _dp, _i64p]
     L.orc_chebyshev_vectors.restype = ctypes.c_int
     L.orc_chebyshev_vectors.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
                                         ctypes.c_double, ctypes.c_double, _dp,
@@ -334,6 +341,38 @@ def propagate_moments(lat, psi0, Nt, b=None, halving=True, Hn=None, H0=0.0, tau=
     if return_final:
         return corr.T.copy(), counters, fin.T.copy()
     return corr.T.copy(), counters
+
+
+def quasi_eigenstates(lat, psi0, Nt, energies, Hn=None, H0=0.0, tau=math.pi, eta=1e-14,
+                      margin=1.025):
+    """Quasi-eigenstates Psi_r(E) (QE section, Eq. QE) by the sequential form:
+    forward and backward propagation by exp(-+iH tau_p) step by step and the
+    sum of Eq. QE_coeff over the propagated states,
+      Psi(E) = tau_p sum_{j=0}^{Nt} (2 - delta_j0)/2 [e^{iE't_j} psi(t_j) + e^{-iE't_j} psi(-t_j)],
+    tau_p = tau / Hn, t_j = j tau_p, E' = E - H0.  psi0 is [N][R]; returns
+    ([n_E][N][R] complex, counters)."""
+    psi0 = np.asarray(psi0, dtype=np.complex128)
+    if psi0.ndim == 1:
+        psi0 = psi0[:, None]
+    N, R = psi0.shape
+    if N != lat.N:
+        raise ValueError("state length does not match the lattice")
+    if Hn is None:
+        Hn = lat.halfwidth(margin)
+    E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
+    nE = len(E)
+    cols = np.ascontiguousarray(psi0.T)
+    out = np.zeros((R, nE, N), dtype=np.complex128)
+    cnt = np.zeros(4, dtype=np.int64)
+    rc = lib().orc_quasi_eigenstates(N, _p(lat.rowptr, _i64p), _p(lat.col, _i64p),
+                                     _p(lat.val, _dp), float(H0), float(Hn), R,
+                                     _p(cols.view(np.float64), _dp), int(Nt), float(tau),
+                                     float(eta), nE, _p(E, _dp), _p(out.view(np.float64), _dp),
+                                     _p(cnt, _i64p))
+    if rc:
+        raise RuntimeError("orc_quasi_eigenstates failed (%d)" % rc)
+    counters = {"amxsy": int(cnt[0]), "axpy": int(cnt[1])}
+    return np.ascontiguousarray(out.transpose(1, 2, 0)), counters
 
 
 def chebyshev_vectors(lat, x, nmax, Hn, H0=0.0):

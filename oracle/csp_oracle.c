@@ -19,7 +19,9 @@
  *   - state-based concurrent propagation in time blocks, Eq. (TE) with the
  *     blocks of Sec. II.B, with the same correlations;
  *   - moment-based propagation (Sec. II.A) in blocks, and in one block with
- *     the halving of Eq. (cheby_prod) (DOS-Concurrent-M of Sec. III).
+ *     the halving of Eq. (cheby_prod) (DOS-Concurrent-M of Sec. III);
+ *   - quasi-eigenstates by sequential forward and backward propagation
+ *     (QE section, Eq. QE summed as in Eq. QE_coeff).
  * Operation counters (amxsy / axpy / dot) follow the definitions of Sec. II.B
  * so that tests can compare them with Tab. (cost).
  *
@@ -569,5 +571,80 @@ int orc_propagate_moments(int64_t n, const int64_t *rowptr, const int64_t *col,
         int rc = propagate_one_moments(&H, p, Nt, tau, eta, b, halving, cr, fr, counters);
         if (rc) return rc;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Quasi-eigenstates (QE section, Eq. QE), sequential form (QE-Sequential): */
+/* the state is propagated forward and backward in time step by step,      */
+/*   psi(+-t_j) = sum_{n=0}^{N(tau)} c_n(+-tau) T_n(Ht) psi(+-t_{j-1}),     */
+/* with c_n(-x) = conj(c_n(x)) (J_n real), and the time integral of Eq. QE   */
+/* is the sum of Eq. QE_coeff taken over the propagated states:              */
+/*   Psi(E) = tau_p sum_{j=0}^{Nt} (2 - delta_{j0})/2                        */
+/*            [ e^{i E' t_j} psi(t_j) + e^{-i E' t_j} psi(-t_j) ],            */
+/* t_j = j tau_p, tau_p = tau / Hn (physical time step), E' = E - H0.        */
+/* ------------------------------------------------------------------ */
+
+/* out <- sum_{k=0}^{Ntr} c[k] T_k(Ht) in, with p0, p1 scratch (amxsy and
+ * axpy counted as in the sequential propagation). */
+static void cheb_apply(const orc_ham *H, const cplx *c, int64_t Ntr, const cplx *in,
+                       cplx *out, cplx *p0, cplx *p1, int64_t *cnt)
+{
+    const int64_t n = H->n;
+    memcpy(p0, in, (size_t)n * sizeof(cplx));
+    memset(p1, 0, (size_t)n * sizeof(cplx));
+    amxsy(H, 1.0, p0, p1); cnt[0]++;
+    copy_scaled(n, c[0], p0, out);
+    axpy(n, c[1], p1, out); cnt[1]++;
+    for (int64_t k = 2; k <= Ntr; ++k) {
+        amxsy(H, 2.0, p1, p0); cnt[0]++;
+        cplx *tmp = p0; p0 = p1; p1 = tmp;
+        axpy(n, c[k], p1, out); cnt[1]++;
+    }
+}
+
+/* R states psi0 (column-major, N values each), nE energies E[e]; writes
+ * out[(r * nE + e) * n + s] = Psi_r(E_e)_s. */
+int orc_quasi_eigenstates(int64_t n, const int64_t *rowptr, const int64_t *col,
+                          const double *val, double H0, double Hn, int64_t R,
+                          const cplx *psi0, int64_t Nt, double tau, double eta, int64_t nE,
+                          const double *E, cplx *out, int64_t *counters)
+{
+    orc_ham H = {n, rowptr, col, val, H0, Hn};
+    if (n < 1 || R < 1 || Nt < 0 || nE < 1 || !(Hn > 0.0)) return -1;
+    const int64_t Ntr = orc_truncation(tau, eta);
+    if (Ntr < 1) return -1;
+    cplx *cf = (cplx *)malloc((size_t)(Ntr + 1) * sizeof(cplx));
+    cplx *cb = (cplx *)malloc((size_t)(Ntr + 1) * sizeof(cplx));
+    cplx *fw = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *bw = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *nx = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p0 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p1 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    if (!cf || !cb || !fw || !bw || !nx || !p0 || !p1) return -2;
+    orc_cheb_coeffs(tau, Ntr, cf);
+    for (int64_t k = 0; k <= Ntr; ++k) cb[k] = conj(cf[k]);
+    const double tp = tau / Hn;
+    for (int64_t r = 0; r < R; ++r) {
+        const cplx *ps = psi0 + (size_t)r * (size_t)n;
+        cplx *o = out + (size_t)r * (size_t)nE * (size_t)n;
+        /* j = 0: (1/2)(psi0 + psi0) */
+        for (int64_t e = 0; e < nE; ++e) copy_scaled(n, tp, ps, o + (size_t)e * (size_t)n);
+        memcpy(fw, ps, (size_t)n * sizeof(cplx));
+        memcpy(bw, ps, (size_t)n * sizeof(cplx));
+        for (int64_t j = 1; j <= Nt; ++j) {
+            cheb_apply(&H, cf, Ntr, fw, nx, p0, p1, counters);
+            cplx *t = fw; fw = nx; nx = t;
+            cheb_apply(&H, cb, Ntr, bw, nx, p0, p1, counters);
+            t = bw; bw = nx; nx = t;
+            for (int64_t e = 0; e < nE; ++e) {
+                const double th = (E[e] - H0) * (double)j * tp;
+                cplx *oe = o + (size_t)e * (size_t)n;
+                axpy(n, tp * cexp(I * th), fw, oe);
+                axpy(n, tp * cexp(-I * th), bw, oe);
+            }
+        }
+    }
+    free(cf); free(cb); free(fw); free(bw); free(nx); free(p0); free(p1);
     return 0;
 }
