@@ -269,6 +269,27 @@ csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *d
                          int32_t R, const csp_params *params, double *dev_corr,
                          void *dev_final, csp_report *rep);
 
+/* Quasi-eigenstates (QE section), the energy-based concurrent form
+ * QE-Concurrent-E: for each of the R states psi0_r (dev_psi0, [N][R], dtype
+ * per mode) and each of the n_E energies (host array, units of t), with
+ * tau = params->tau_tilde / |H|, t_j = j tau, E' = E - H0,
+ *   Psi_r(E) = sum_{n=0}^{N(Nt tau~)} C_n(E) T_n(H~) psi0_r,
+ *   C_n(E) = tau [ delta_n0 + sum_{j=1..Nt, n <= N(j tau~)}
+ *                  2 a_n(j tau~) Re((-i)^n e^{i E' t_j}) ]
+ * (a_0 = J_0, a_n = 2 J_n): the forward and backward time sums of Eq. QE
+ * merged as in Eq. QE_coeff, no window.  This equals
+ * tau sum_{j=0}^{Nt} (2 - delta_j0)/2 [e^{iE't_j} psi(t_j) + e^{-iE't_j} psi(-t_j)]
+ * of the sequentially propagated states up to rounding.  Writes dev_qe
+ * [n_E][N][R] in the dtype of psi0.  params->mode CSP_FP32_CONC (complex64
+ * recursion, split-bf16 MFMA accumulation, 1 <= n_E <= 32) or CSP_FP64_CONC
+ * (complex128, 1 <= n_E <= 16); 1 <= Nt <= 2^20.  Coefficients are FP64 on
+ * the GPU.  CSP_ENOMEM when a 16-order ring of all columns with the n_E
+ * accumulated states does not fit (call per column then).  rep may be NULL. */
+csp_status csp_quasi_eigenstates(csp_context *ctx, const csp_lattice *lat,
+                                 const void *dev_psi0, int32_t R, const csp_params *params,
+                                 int32_t n_E, const double *energies, void *dev_qe,
+                                 csp_report *rep);
+
 /* Many lattices in one set of launches: instance i has lattice lats[i],
  * states dev_psi0[i] ([N_i][R[i]]) and correlations dev_corr[i]
  * ([(Nt+1)][R[i]]).  Every instance uses the same params (Nt, mode, b); the

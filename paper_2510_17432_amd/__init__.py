@@ -137,6 +137,8 @@ _sig("csp_propagate_batch", [_vp, ctypes.c_int32, _P(_vp), _P(_vp), _P(ctypes.c_
 _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                  ctypes.c_int32, _vp, _vp, _vp])
 _sig("csp_select_block", [_vp, _vp, ctypes.c_int32, _P(Params), _P(ctypes.c_int32), _P(Report)])
+_sig("csp_quasi_eigenstates", [_vp, _vp, _vp, ctypes.c_int32, _P(Params), ctypes.c_int32,
+                               _P(ctypes.c_double), _vp, _P(Report)])
 _sig("csp_autotune", [_vp, ctypes.c_int32, _P(_vp), _P(ctypes.c_int32), _P(Params), _P(Tuning)])
 _sig("csp_set_tuning", [_vp, ctypes.c_int32, _P(_vp), _P(ctypes.c_int32), _P(Params), _P(Tuning)])
 _sig("csp_bandwidth_probe", [_vp, ctypes.c_uint64, _P(ctypes.c_double)])
@@ -342,6 +344,22 @@ def csp_propagate(ctx, lat, psi0, params, corr=None, final=None):
     _check(_lib.csp_propagate(ctx.handle, lat.handle, _ptr(psi0), R, ctypes.byref(params),
                               _ptr(corr), _ptr(final), ctypes.byref(rep)))
     return corr, rep
+
+
+def csp_quasi_eigenstates(ctx, lat, psi0, params, energies, out=None):
+    """Quasi-eigenstates [n_E][N][R] (device tensor, dtype of psi0) and the
+    report, by the energy-based concurrent form."""
+    import torch
+    N, R = psi0.shape
+    E = [float(e) for e in energies]
+    if out is None:
+        out = torch.empty((len(E), N, R), dtype=psi0.dtype, device=psi0.device)
+    Ev = (ctypes.c_double * len(E))(*E)
+    rep = Report()
+    _check(_lib.csp_quasi_eigenstates(ctx.handle, lat.handle, _ptr(psi0), R,
+                                      ctypes.byref(params), len(E), Ev, _ptr(out),
+                                      ctypes.byref(rep)))
+    return out, rep
 
 
 def csp_propagate_batch(ctx, lats, psi0s, params, corrs=None):

@@ -1511,6 +1511,243 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   return CSP_OK;
 }
 
+// ------------------------------------------------------------------ quasi-eigenstates
+// QE-Concurrent-E (QE section): the Chebyshev vectors of psi0 up to
+// N(Nt tau~) are produced by the recursion into a ring of K + kt slots and
+// contracted chunk by chunk with the real coefficients C_n(E) of Eq.
+// QE_coeff into one accumulated state per energy and column.
+extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L,
+                                            const void* dev_psi0, int32_t R,
+                                            const csp_params* params_in, int32_t n_E,
+                                            const double* energies, void* dev_qe,
+                                            csp_report* rep) {
+  const double t_start = now_ms();
+  if (!c || !L || !dev_psi0 || !params_in || !energies || !dev_qe)
+    return fail(CSP_EINVAL, "NULL argument");
+  csp_params P;
+  fill_defaults(params_in, &P);
+  if (P.mode != CSP_FP32_CONC && P.mode != CSP_FP64_CONC)
+    return fail(CSP_EINVAL, "quasi-eigenstates need CSP_FP32_CONC or CSP_FP64_CONC");
+  const bool fp64 = P.mode == CSP_FP64_CONC;
+  const int nE = n_E;
+  if (nE < 1 || nE > (fp64 ? kMaxFp64B : 32))
+    return fail(CSP_EINVAL, "need 1 <= n_E <= %d", fp64 ? kMaxFp64B : 32);
+  if (R < 1) return fail(CSP_EINVAL, "R must be >= 1");
+  if (P.Nt < 1 || P.Nt > (1 << 20)) return fail(CSP_EINVAL, "need 1 <= Nt <= 2^20");
+  if (L->ctx->device != c->device) return fail(CSP_EINVAL, "lattice is on another device");
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(energies[e])) return fail(CSP_EINVAL, "energy %d is not finite", e);
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  const int Nt = (int)P.Nt;
+  const int64_t N = L->g.N;
+
+  // Bessel table for x = j tau~, j = 1..Nt, and the coefficients C_n(E).
+  const int nmax_tab = (int)trunc_nmax((double)Nt * P.tau_tilde);
+  const int lda = nmax_tab + 1;
+  struct Free {
+    std::vector<void*> p;
+    ~Free() { for (void* q : p) (void)hipFree(q); }
+  } tmp;
+  auto alloc = [&](void** ptr, size_t bytes) -> csp_status {
+    HIPCALL(hipMalloc(ptr, bytes));
+    tmp.p.push_back(*ptr);
+    return CSP_OK;
+  };
+  double *d_a = nullptr, *d_E = nullptr, *d_cs = nullptr, *d_C = nullptr;
+  int32_t *d_ntr = nullptr, *d_ntrq = nullptr;
+  CHECK(alloc((void**)&d_a, sizeof(double) * (size_t)Nt * lda));
+  CHECK(alloc((void**)&d_ntr, sizeof(int32_t) * Nt));
+  HIPCALL(launch_bessel(P.tau_tilde, Nt, nmax_tab, P.eta, true, d_a, d_ntr, s));
+  int32_t Nmax = 0;
+  HIPCALL(hipMemcpyAsync(&Nmax, d_ntr + (Nt - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCALL(hipStreamSynchronize(s));
+  if (Nmax < 1) return fail(CSP_ENUMERIC, "no truncation order for x = %g", Nt * P.tau_tilde);
+  const int ldc = Nmax + 1;
+  CHECK(alloc((void**)&d_E, sizeof(double) * nE));
+  CHECK(alloc((void**)&d_cs, sizeof(double2) * (size_t)nE * Nt));
+  CHECK(alloc((void**)&d_C, sizeof(double) * (size_t)nE * ldc));
+  CHECK(alloc((void**)&d_ntrq, sizeof(int32_t) * 32));
+  HIPCALL(hipMemcpyAsync(d_E, energies, sizeof(double) * nE, hipMemcpyHostToDevice, s));
+  {
+    std::vector<int32_t> nq(32, Nmax);
+    HIPCALL(hipMemcpyAsync(d_ntrq, nq.data(), sizeof(int32_t) * 32, hipMemcpyHostToDevice, s));
+    HIPCALL(launch_qe_coeffs(d_a, lda, d_ntr, Nt, nE, d_E, L->H0, P.tau_tilde / L->halfwidth,
+                             Nmax, d_cs, d_C, s));
+    HIPCALL(hipStreamSynchronize(s));   // nq leaves scope
+  }
+
+  // Column groups and the recursion's launch shape.
+  std::vector<Group> groups;
+  {
+    int col = 0;
+    for (int Rg : split_columns(R)) {
+      Group g;
+      g.inst = 0;
+      g.col0 = col;
+      g.Rg = Rg;
+      g.M = N * Rg;
+      groups.push_back(g);
+      col += Rg;
+    }
+  }
+  std::vector<ChebInst> sp;
+  for (auto& g : groups) sp.push_back(make_inst(L, g.Rg, fp64));
+  const ChebPlan sp_plan = plan_cheb(sp, fp64, false, c->n_cu, 2, fp64 ? 4 : 8, 0);
+  const int kt = sp_plan.kt;
+
+  // Orders per contraction chunk: all of them when they fit, else a multiple
+  // of 16 (LDS holds the chunk's coefficients; the ring K + kt slots).
+  int B64 = 1;
+  while (B64 < nE) B64 *= 2;
+  const int kcap = fp64 ? (int)((60 * 1024) / (sizeof(double2) * B64)) / 16 * 16 : 496;
+  size_t cap = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
+  auto ws_need = [&](int K_) {
+    size_t by = 0;
+    for (auto& g : groups)
+      by += align256((size_t)(K_ + kt) * g.stride() * csz) + align256(g.M * csz) +
+            align256((size_t)nE * g.M * csz);
+    by += fp64 ? align256(sizeof(double2) * (size_t)K_ * B64)
+               : align256(bop_bytes(1, K_)) + align256(sizeof(float) * 16 * ceil_div(K_, 16));
+    by += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(QeInst) * groups.size());
+    return by;
+  };
+  int K = std::min(Nmax + 1, kcap);
+  if (K < Nmax + 1) K = std::max(16, K / 16 * 16);
+  while (K > 16 && ws_need(K) > cap) K = (K > 32 ? (K - 1) / 16 * 16 : 16);
+  if (ws_need(K) > cap)
+    return fail(CSP_ENOMEM, "quasi-eigenstate workspace %.2f GB exceeds the cap %.2f GB",
+                ws_need(K) / 1e9, cap / 1e9);
+  const int S = K + kt;
+  CHECK(ws_reserve(c, ws_need(K)));
+  Carver cv(c->ws);
+  std::vector<void*> outs(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    g.slots = cv.take((size_t)S * g.stride() * csz);
+    g.psi0g = cv.take(g.M * csz);
+    outs[gi] = cv.take((size_t)nE * g.M * csz);
+  }
+  void* d_bop = nullptr;
+  float* d_ccd = nullptr;
+  double* d_coef = nullptr;
+  if (fp64) {
+    d_coef = (double*)cv.take(sizeof(double2) * (size_t)K * B64);
+  } else {
+    d_bop = cv.take(bop_bytes(1, K));
+    d_ccd = (float*)cv.take(sizeof(float) * 16 * ceil_div(K, 16));
+  }
+  ChebInst* d_inst = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
+  QeInst* d_qi = (QeInst*)cv.take(sizeof(QeInst) * groups.size());
+
+  // Instance tables (workgroups per column as in the state assembly).
+  int64_t Msum = 0;
+  for (auto& g : groups) Msum += g.M;
+  std::vector<QeInst> qi;
+  int wg0 = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    HIPCALL(launch_gather_cols(N, R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, dev_psi0, fp64,
+                               g.psi0g, s));
+    ChebInst& I = sp[gi];
+    I.base = g.slots;
+    I.slot_stride = g.stride();
+    I.src = g.psi0g;
+    const int64_t units = fp64 ? ceil_div(N, kContractThreads) : ceil_div(ceil_div(N, 32), 4);
+    const double share = (double)c->n_cu * 4.0 * (double)g.M / (double)Msum / g.Rg;
+    const int wpc = (int)std::max<int64_t>(1, std::min<int64_t>(std::llround(share), units));
+    QeInst q{};
+    q.slots = g.slots;
+    q.slot_stride = g.stride();
+    q.N = N;
+    q.Rg = g.Rg;
+    q.wpc = wpc;
+    q.out = outs[gi];
+    q.wg0 = wg0;
+    q.n_wg = g.Rg * wpc;
+    wg0 += q.n_wg;
+    qi.push_back(q);
+  }
+  HIPCALL(hipMemcpyAsync(d_inst, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_qi, qi.data(), sizeof(QeInst) * qi.size(), hipMemcpyHostToDevice, s));
+
+  // Recursion launches with a contraction after every completed chunk.
+  Profiler prof{c, P.profile != 0};
+  int64_t n_spmm = 0, n_con = 0;
+  const ChebStep st0 = step_args(sp_plan);
+  int produced = 0, n_lo = 0;
+  while (produced < Nmax) {
+    ChebStep st = st0;
+    st.nlev = std::min(kt, Nmax - produced);
+    if (produced == 0) {
+      st.first = 1;
+      st.slot_cur = -1;
+      st.copy_slot = 0;
+    } else {
+      st.slot_cur = produced % S;
+      st.slot_prev = (produced - 1) % S;
+    }
+    for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
+    size_t ev = 0;
+    CHECK(prof.begin(0, &ev));
+    HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_inst, sp_plan.runs, st, s));
+    CHECK(prof.end(ev));
+    ++n_spmm;
+    produced += st.nlev;
+    while (n_lo <= Nmax && (n_lo + K - 1 <= produced || produced == Nmax)) {
+      const int n_cnt = std::min(K, Nmax + 1 - n_lo);
+      if (fp64) HIPCALL(launch_pack_qe64(d_C, ldc, nE, B64, n_lo, n_cnt, d_coef, s));
+      else HIPCALL(launch_pack_bop(d_C, ldc, d_ntrq, nE, 1, n_lo, n_cnt, d_bop, d_ccd, s));
+      QeArgs qa{};
+      qa.n_inst = (int)groups.size();
+      qa.n_lo = n_lo;
+      qa.n_cnt = n_cnt;
+      qa.S = S;
+      qa.first_chunk = n_lo == 0 ? 1 : 0;
+      qa.nE = nE;
+      qa.total_wg = wg0;
+      qa.bop = d_bop;
+      qa.coef = d_coef;
+      size_t evc = 0;
+      CHECK(prof.begin(1, &evc));
+      HIPCALL(launch_contract_qe(fp64, d_qi, qa, s));
+      CHECK(prof.end(evc));
+      ++n_con;
+      n_lo += n_cnt;
+    }
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi)
+    HIPCALL(launch_qe_scatter(N, groups[gi].Rg, nE, R, groups[gi].col0, fp64, outs[gi],
+                              fp64 ? CSP_C128 : CSP_C64, dev_qe, s));
+  HIPCALL(hipStreamSynchronize(s));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    double ms_s = 0, ms_c = 0;
+    CHECK(prof.collect(&ms_s, &ms_c));
+    rep->block_b = Nt;
+    rep->chunk_K = K;
+    rep->n_blocks = 1;
+    rep->n_groups = (int)groups.size();
+    rep->amxsy = Nmax;
+    rep->axpy = (int64_t)(Nmax + 1) * nE;
+    rep->dot = 0;
+    rep->spmm_launches = n_spmm;
+    rep->contract_launches = n_con;
+    rep->ms_total = now_ms() - t_start;
+    rep->ms_spmm = ms_s;
+    rep->ms_contract = ms_c;
+    rep->spmm_bytes = (double)N * R * csz * ((double)Nmax + 2.0 * n_spmm);
+    rep->contract_bytes = (double)N * R * csz * ((double)Nmax + 1.0 + 2.0 * nE * n_con);
+    rep->contract_flops = 2.0 * 2.0 * (double)N * R * (Nmax + 1) * nE * (fp64 ? 1.0 : 3.0);
+    rep->workspace_bytes = c->ws_size;
+    rep->n_passes = 1;
+    rep->spmm_steps = kt;
+  }
+  return CSP_OK;
+}
+
 // ------------------------------------------------------------------ DOS
 extern "C" csp_status csp_dos(csp_context* c, const double* dev_corr, int64_t Nt, int32_t R,
                               double halfwidth, double tau_tilde, int32_t window, double* dev_E,

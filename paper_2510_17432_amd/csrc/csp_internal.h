@@ -222,6 +222,39 @@ hipError_t launch_finish(const FinishInst* d_inst, int n_inst, int bcols, int64_
 // d_blk[0] += b, d_blk[1] += 1 (the block counter of graph replays).
 hipError_t launch_advance(int64_t* d_blk, int64_t b, hipStream_t s);
 
+// ------------------------------------------------------------------ quasi-eigenstates
+// One column group of a quasi-eigenstate contraction: Chebyshev ring as in
+// the state assembly, accumulators out [Rg][nE][N] (complex, working precision).
+struct QeInst {
+  const void* slots;
+  int64_t slot_stride;      // complex values between slots
+  int64_t N;
+  int32_t Rg, wpc;          // columns, workgroups per column
+  void* out;
+  int32_t wg0, n_wg;
+};
+struct QeArgs {
+  int32_t n_inst;
+  int32_t n_lo, n_cnt;      // orders n_lo .. n_lo + n_cnt - 1 of this chunk
+  int32_t S;                // ring size: order n lives in slot n % S
+  int32_t first_chunk;      // write (1) or accumulate (0) the states
+  int32_t nE;               // energies
+  int32_t total_wg;
+  int32_t pad;
+  const void* bop;          // FP32: A operands C_n(E) in the MFMA lane layout
+  const void* coef;         // FP64: [n_cnt][B] complex (imaginary part 0)
+};
+// C[e][n] = tau (delta_n0 + sum_j 2 a_n(j tau~) Re((-i)^n e^{i (E_e - H0) j tau})), n <= nmax;
+// d_cs: scratch [nE][Nt] double2.
+hipError_t launch_qe_coeffs(const double* d_a, int lda, const int32_t* d_ntr, int Nt, int nE,
+                            const double* d_E, double H0, double tau, int nmax, double* d_cs,
+                            double* d_C, hipStream_t s);
+hipError_t launch_pack_qe64(const double* d_C, int ldc, int nE, int B, int n_lo, int n_cnt,
+                            double* d_coef, hipStream_t s);
+hipError_t launch_contract_qe(bool fp64, const QeInst* d_inst, const QeArgs& a, hipStream_t s);
+hipError_t launch_qe_scatter(int64_t N, int Rg, int nE, int ld, int col0, bool fp64_in,
+                             const void* d_in, int out_dtype, void* d_out, hipStream_t s);
+
 // ------------------------------------------------------------------ coefficients
 // For x_j = (j + 1) * tau, j = 0..nx-1: a[j][n] = J_n(x_j) (n = 0) or
 // 2 J_n(x_j) (n >= 1) for n <= nmax, and ntrunc[j] = N(x_j).  clip: orders

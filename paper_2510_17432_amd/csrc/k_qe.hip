@@ -1,0 +1,312 @@
+// Quasi-eigenstates by the energy-based concurrent form (QE section,
+// QE-Concurrent-E): the forward and backward time integrals of Eq. QE are
+// merged into real, energy-dependent expansion coefficients (Eq. QE_coeff),
+//   C_n(E) = tau [ delta_n0 + sum_{j >= 1, n <= N(j tau~)} 2 a_n(j tau~) Re((-i)^n e^{i E' t_j}) ],
+// (c_n(-x) = conj(c_n(x)) turns the pair e^{iE't} c_n(t~) + e^{-iE't} c_n(-t~)
+// into twice a real part), t_j = j tau, E' = E - H0, and the states are one
+// contraction of the Chebyshev vectors of psi0,
+//   Psi(E) = sum_{n=0}^{N(Nt tau~)} C_n(E) T_n(H~) psi0,
+// over chunks of orders as the recursion produces them.
+//
+// FP32 path: the contraction runs on v_mfma_f32_32x32x16_bf16 with the
+// split hi + lo bf16 operands of the state assembly, here with the
+// coefficients as the A operand (32 energies x 16 orders) and the Chebyshev
+// values as the B operand (16 orders x 32 values), so that the accumulator
+// holds, per lane, one value and 16 energies and the states are stored with
+// 256-byte coalesced writes.  The FP64 path multiplies complex128 values by
+// the real coefficients with FMAs.  Coefficients are FP64 on the GPU, summed
+// over j in a fixed order.
+#include "csp_internal.h"
+
+namespace csp {
+
+typedef __bf16 qbf16x8 __attribute__((ext_vector_type(8)));
+typedef float qf32x16 __attribute__((ext_vector_type(16)));
+typedef float qf32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) qf32x2 gq2;
+
+struct QeBop {
+  qbf16x8 hi;
+  qbf16x8 lo;
+};
+
+// cs[e][j-1] = (cos, sin) of (E_e - H0) j tau, j = 1..Nt
+__global__ void k_qe_phase(int nE, int Nt, const double* __restrict__ E, double H0, double tau,
+                           double2* __restrict__ cs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nE * Nt) return;
+  const int e = (int)(i / Nt), j = (int)(i - (int64_t)e * Nt) + 1;
+  const double th = (E[e] - H0) * ((double)j * tau);
+  double sn, cn;
+  sincos(th, &sn, &cn);
+  cs[i] = make_double2(cn, sn);
+}
+
+// C[e][n], n = 0..nmax: thread per (n, e); a is the Bessel table of
+// launch_bessel (row j-1 for x = j tau~), ntr its truncation orders.
+__global__ void k_qe_coeffs(const double* __restrict__ a, int lda, const int32_t* __restrict__ ntr,
+                            int Nt, int nE, const double2* __restrict__ cs, double tau, int nmax,
+                            double* __restrict__ C) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (n > nmax || e >= nE) return;
+  double s = 0.0;
+  const double2* ce = cs + (int64_t)e * Nt;
+  for (int j = 1; j <= Nt; ++j) {
+    if (n > ntr[j - 1]) continue;                 // order n not yet in the expansion
+    const double an = a[(int64_t)(j - 1) * lda + n];
+    const double2 t = ce[j - 1];
+    double r;
+    switch (n & 3) {                              // Re((-i)^n e^{i th})
+      case 0: r = t.x; break;
+      case 1: r = t.y; break;
+      case 2: r = -t.x; break;
+      default: r = -t.y; break;
+    }
+    s = fma(2.0 * an, r, s);
+  }
+  C[(int64_t)e * (nmax + 1) + n] = tau * ((n == 0 ? 1.0 : 0.0) + s);
+}
+
+hipError_t launch_qe_coeffs(const double* d_a, int lda, const int32_t* d_ntr, int Nt, int nE,
+                            const double* d_E, double H0, double tau, int nmax, double* d_cs,
+                            double* d_C, hipStream_t s) {
+  const int64_t np = (int64_t)nE * Nt;
+  hipLaunchKernelGGL(k_qe_phase, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s, nE, Nt, d_E,
+                     H0, tau, reinterpret_cast<double2*>(d_cs));
+  hipLaunchKernelGGL(k_qe_coeffs, dim3((unsigned)ceil_div(nmax + 1, 128), nE), dim3(128), 0, s,
+                     d_a, lda, d_ntr, Nt, nE, reinterpret_cast<const double2*>(d_cs), tau, nmax,
+                     d_C);
+  return hipGetLastError();
+}
+
+// FP64 table coef[rel][e] = C[e][n_lo + rel] (imaginary part 0), e < B.
+__global__ void k_pack_qe64(const double* __restrict__ C, int ldc, int nE, int B, int n_lo,
+                            int n_cnt, double2* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cnt * B) return;
+  const int rel = i / B, e = i - rel * B;
+  coef[i] = make_double2(e < nE ? C[(int64_t)e * ldc + n_lo + rel] : 0.0, 0.0);
+}
+
+hipError_t launch_pack_qe64(const double* d_C, int ldc, int nE, int B, int n_lo, int n_cnt,
+                            double* d_coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_qe64, dim3((unsigned)ceil_div(n_cnt * B, 256)), dim3(256), 0, s, d_C,
+                     ldc, nE, B, n_lo, n_cnt, reinterpret_cast<double2*>(d_coef));
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ FP32 contraction
+// Workgroup -> (instance, column, sub) as in the state assembly; each wave
+// owns one 32-value tile of its column at a time.  Lane (i, h): B operand =
+// value i of orders 8h..8h+7 of a 16-order step; A operand (LDS) =
+// C_n(E_i) for the same orders; accumulator = Psi(E_e) at value i for
+// e = 8(v/4) + 4h + v%4.
+__global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
+    const QeInst* __restrict__ insts, QeArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n_kb = (a.n_cnt + 15) >> 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int il = lane & 31, h = lane >> 5;
+  QeBop* sb = reinterpret_cast<QeBop*>(smem);
+  {
+    const QeBop* gb = static_cast<const QeBop*>(a.bop);
+    for (int e = tid; e < n_kb * 64; e += kContractThreads) sb[e] = gb[e];
+  }
+  __syncthreads();
+
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  int ii = 0;
+  while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
+  const QeInst& I = insts[ii];
+  const int64_t wgl = wg - I.wg0;
+  const int64_t col = wgl / I.wpc, sub = wgl - col * I.wpc;
+  const int64_t N = I.N;
+  const gq2* slots = (const gq2*)(I.slots) + col * N;
+  gq2* out = (gq2*)(I.out) + col * (int64_t)a.nE * N;
+  const int64_t n_tiles = ceil_div(N, 32);
+  const int64_t sstr = I.slot_stride;
+  const int64_t wrap = (int64_t)a.S * sstr;
+
+  const int64_t stride_tiles = (int64_t)I.wpc * 4;
+  for (int64_t tile = sub * 4 + wave; tile < n_tiles; tile += stride_tiles) {
+    const int64_t m = tile * 32 + il;
+    const bool mv = m < N;
+    qf32x16 accR, accI;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      accR[v] = 0.f;
+      accI[v] = 0.f;
+    }
+    qf32x2 xn[8];
+    auto load_step = [&](int kb) {
+      const int rel0 = kb * 16 + h * 8;
+      int64_t off = (int64_t)((a.n_lo + rel0) % a.S) * sstr;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        qf32x2 z;
+        z.x = 0.f;
+        z.y = 0.f;
+        xn[v] = (mv && rel0 + v < a.n_cnt) ? slots[off + m] : z;
+        off += sstr;
+        if (off >= wrap) off -= wrap;
+      }
+    };
+    load_step(0);
+    for (int kb = 0; kb < n_kb; ++kb) {
+      qbf16x8 phi, plo, qhi, qlo;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const float p = xn[v].x, q = xn[v].y;
+        const __bf16 ph = static_cast<__bf16>(p);
+        const __bf16 qh = static_cast<__bf16>(q);
+        phi[v] = ph;
+        qhi[v] = qh;
+        plo[v] = static_cast<__bf16>(p - static_cast<float>(ph));
+        qlo[v] = static_cast<__bf16>(q - static_cast<float>(qh));
+      }
+      if (kb + 1 < n_kb) load_step(kb + 1);
+      const QeBop be = sb[kb * 64 + lane];
+      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, phi, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.lo, phi, accR, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, plo, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, qhi, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.lo, qhi, accI, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, qlo, accI, 0, 0, 0);
+    }
+    if (mv) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int e = 8 * (v >> 2) + 4 * h + (v & 3);
+        if (e < a.nE) {
+          gq2* p = out + (int64_t)e * N + m;
+          qf32x2 o;
+          o.x = accR[v];
+          o.y = accI[v];
+          if (!a.first_chunk) {
+            const qf32x2 old = *p;
+            o.x += old.x;
+            o.y += old.y;
+          }
+          *p = o;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP64 contraction
+// One value per thread, B (>= nE) energy columns in registers, complex
+// coefficients (imaginary part 0) in LDS.
+template <int B>
+__global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
+    const QeInst* __restrict__ insts, QeArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2* scoef = reinterpret_cast<double2*>(smem);   // [n_cnt][B]
+  const int tid = threadIdx.x;
+  {
+    const double2* gc = static_cast<const double2*>(a.coef);
+    for (int e = tid; e < a.n_cnt * B; e += kContractThreads) scoef[e] = gc[e];
+  }
+  __syncthreads();
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  int ii = 0;
+  while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
+  const QeInst& I = insts[ii];
+  const int64_t wgl = wg - I.wg0;
+  const int64_t col = wgl / I.wpc, sub = wgl - col * I.wpc;
+  const int64_t N = I.N;
+  const double2* slots = static_cast<const double2*>(I.slots) + col * N;
+  double2* out = static_cast<double2*>(I.out) + col * (int64_t)a.nE * N;
+  const int64_t step = (int64_t)I.wpc * kContractThreads;
+  for (int64_t m = sub * kContractThreads + tid; m < N; m += step) {
+    double2 acc[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) acc[e] = make_double2(0.0, 0.0);
+    for (int rel = 0; rel < a.n_cnt; ++rel) {
+      const double2 x = slots[(int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + m];
+#pragma unroll
+      for (int e = 0; e < B; ++e) {
+        const double c = scoef[rel * B + e].x;
+        acc[e].x = fma(c, x.x, acc[e].x);
+        acc[e].y = fma(c, x.y, acc[e].y);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      if (e < a.nE) {
+        double2* p = out + (int64_t)e * N + m;
+        double2 o = acc[e];
+        if (!a.first_chunk) {
+          const double2 old = *p;
+          o.x += old.x;
+          o.y += old.y;
+        }
+        *p = o;
+      }
+    }
+  }
+}
+
+hipError_t launch_contract_qe(bool fp64, const QeInst* d_inst, const QeArgs& a, hipStream_t s) {
+  if (a.total_wg <= 0 || a.n_cnt <= 0) return hipSuccess;
+  const dim3 grid(a.total_wg), block(kContractThreads);
+  if (!fp64) {
+    if (a.nE < 1 || a.nE > 32) return hipErrorInvalidValue;
+    const size_t lds = sizeof(QeBop) * 64 * (size_t)ceil_div(a.n_cnt, 16);
+    hipLaunchKernelGGL(k_contract_qe_f32, grid, block, lds, s, d_inst, a);
+    return hipGetLastError();
+  }
+  int B = 1;
+  while (B < a.nE) B *= 2;
+  const size_t lds = sizeof(double2) * (size_t)a.n_cnt * B;
+  switch (B) {
+    case 1: hipLaunchKernelGGL(k_contract_qe_f64<1>, grid, block, lds, s, d_inst, a); break;
+    case 2: hipLaunchKernelGGL(k_contract_qe_f64<2>, grid, block, lds, s, d_inst, a); break;
+    case 4: hipLaunchKernelGGL(k_contract_qe_f64<4>, grid, block, lds, s, d_inst, a); break;
+    case 8: hipLaunchKernelGGL(k_contract_qe_f64<8>, grid, block, lds, s, d_inst, a); break;
+    case 16: hipLaunchKernelGGL(k_contract_qe_f64<16>, grid, block, lds, s, d_inst, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ output layout
+// in: [Rg][nE][N] (the group's accumulators); out: [nE][N][ld], columns
+// col0 .. col0 + Rg - 1, complex64 or complex128.
+__global__ void k_qe_scatter(int64_t N, int Rg, int nE, int ld, int col0, int fp64_in,
+                             const void* __restrict__ in, int out_dtype, void* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = N * Rg * nE;
+  if (i >= total) return;
+  // i runs over (e, s, c) with c fastest, so the writes of a row are contiguous
+  const int64_t c = i % Rg;
+  const int64_t rest = i / Rg;
+  const int64_t s = rest % N;
+  const int64_t e = rest / N;
+  const int64_t src = (c * nE + e) * N + s;
+  double x, y;
+  if (fp64_in) {
+    const double2 v = static_cast<const double2*>(in)[src];
+    x = v.x;
+    y = v.y;
+  } else {
+    const float2 v = static_cast<const float2*>(in)[src];
+    x = v.x;
+    y = v.y;
+  }
+  const int64_t dst = (e * N + s) * ld + col0 + c;
+  if (out_dtype == CSP_C128) static_cast<double2*>(out)[dst] = make_double2(x, y);
+  else static_cast<float2*>(out)[dst] = make_float2(static_cast<float>(x), static_cast<float>(y));
+}
+
+hipError_t launch_qe_scatter(int64_t N, int Rg, int nE, int ld, int col0, bool fp64_in,
+                             const void* d_in, int out_dtype, void* d_out, hipStream_t s) {
+  const int64_t total = N * Rg * nE;
+  hipLaunchKernelGGL(k_qe_scatter, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, N, Rg,
+                     nE, ld, col0, fp64_in ? 1 : 0, d_in, out_dtype, d_out);
+  return hipGetLastError();
+}
+
+}  // namespace csp

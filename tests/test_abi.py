@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
     for n in ("csp_context_create", "csp_lattice_create", "csp_states_random_phase",
               "csp_propagate", "csp_propagate_batch", "csp_dos", "csp_last_error",
               "csp_chebyshev_coefficients", "csp_chebyshev_step", "csp_select_block",
-              "csp_autotune", "csp_set_tuning", "csp_bandwidth_probe"):
+              "csp_autotune", "csp_set_tuning", "csp_bandwidth_probe",
+              "csp_quasi_eigenstates"):
         assert n in names
 
 
