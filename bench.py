@@ -58,6 +58,8 @@ def parse():
                     help="skip the moment-based form runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample")
+    ap.add_argument("--no-qe", action="store_true",
+                    help="skip the quasi-eigenstate runs")
     ap.add_argument("--dos-1e9", action="store_true",
                     help="instead of the step benchmark: the DOS of the 1e9-orbital square "
                          "lattice (31623^2, W = 0.5, 4 random columns, Nt = 4096) in the "
@@ -359,6 +361,39 @@ def main():
                           "avg_launch_us": mt * 1e6, "achieved_GBs": mb / mt / 1e9,
                           "frac": mb / mt / 1e9 / HBM_PEAK_GBS}
         log("moments: %.3f s per step, %d recursion steps" % (tm, mrep.amxsy))
+
+    # quasi-eigenstates (QE-Concurrent-E) of the random columns at 5
+    # energies, Nt = 1024 (the paper's QE benchmark sizes), complex64 against
+    # complex128, outside the timed region
+    if not a.no_qe:
+        Rr = W["R_rand"]
+        Ntq = 1024
+        Eq = [-6.0, -2.7, 0.5, 2.7, 5.0]
+        pq32 = psi[:, :Rr].contiguous()
+        pq64 = pq32.to(torch.complex128)
+        res_q = {}
+        for name, pin, mode in (("fp32", pq32, "fp32_conc"), ("fp64", pq64, "fp64_conc")):
+            prm = csp.make_params(Ntq, mode=mode)
+            csp.csp_quasi_eigenstates(ctx, lat, pin, prm, Eq)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            q, qrep = csp.csp_quasi_eigenstates(ctx, lat, pin, prm, Eq)
+            torch.cuda.synchronize()
+            res_q[name] = (q, time.perf_counter() - t0, qrep)
+            log("quasi-eigenstates %s: %.3f s, %d orders, %d chunks" %
+                (name, res_q[name][1], qrep.amxsy, qrep.contract_launches))
+        q32, q64 = res_q["fp32"][0], res_q["fp64"][0]
+        qerr = float((q32.to(torch.complex128) - q64).abs().max().item() / q64.abs().max().item())
+        seq_steps = 2 * Ntq * 20
+        out["quasi_eigenstates"] = {
+            "form": "QE-Concurrent-E (energy-based, forward and backward merged)",
+            "Nt": Ntq, "energies_eV": Eq, "columns": Rr,
+            "fp32_s": res_q["fp32"][1], "fp64_s": res_q["fp64"][1],
+            "fp32_max_rel_err_vs_fp64": qerr,
+            "chebyshev_orders": res_q["fp32"][2].amxsy,
+            "sequential_chebyshev_steps": seq_steps,
+            "step_ratio_vs_sequential": seq_steps / res_q["fp32"][2].amxsy}
+        del q32, q64, res_q, pq32, pq64
 
     # time-to-accuracy: DOS of the random columns on this GPU, complex64
     # concurrent forms vs the plain complex128 sequential form; each run is
