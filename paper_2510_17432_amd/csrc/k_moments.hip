@@ -1,9 +1,9 @@
 // Moment-based form (Sec. II.A, moment-based implementation; Sec. III
-// DOS-Concurrent-M): the per-tile inner products written by the recursion
-// kernel's moment epilogue are summed into per-step dots, turned into the
-// block moments mu_n = <psi0|T_n(H~) s_k> (directly, or above h = floor(N/2)
-// by the halving identity of Eq. cheby_prod), and contracted with the
-// expansion coefficients into correlations
+// DOS-Concurrent-M): the per-order inner products (the recursion kernel's
+// moment records, summed per column by k_cheb_mom_finish) are turned into
+// the block moments mu_n = <psi0|T_n(H~) s_k> (directly, or above
+// h = floor(N/2) by the halving identity of Eq. cheby_prod), and contracted
+// with the expansion coefficients into correlations
 //   C(t_{kb+j}) = sum_{n=0}^{N(j tau)} c_n(j tau) mu_n,   c_n = (-i)^n a_n.
 // Everything here is FP64 and summed in a fixed order.
 #include "csp_internal.h"
