@@ -54,3 +54,30 @@ def scaled(cfg, **over):
     d = dict(cfg)
     d.update(over)
     return d
+
+
+def long_range_square(L, r_cut, t0=1.0, decay=1.0, W=0.0, seed=0):
+    """Stand-in for the paper's dense twisted-bilayer Hamiltonians (matrix
+    density D_H = 60..230): an L x L periodic square lattice (orbital
+    s = y*L + x) with hopping t0 * exp(-(d - 1)/decay) to every site at
+    distance 0 < d <= r_cut, and on-site energies W*(u - 1/2) from numpy's
+    generator seeded with `seed`.  Returns (col, val) in ELL form, [N][D]
+    each, with the on-site entry first; D_H = D = 1 + #{lattice vectors
+    0 < |v| <= r_cut}.  L must exceed 2 r_cut (no duplicate neighbours)."""
+    if L <= 2 * r_cut:
+        raise ValueError("L must exceed 2 r_cut")
+    R = int(np.floor(r_cut))
+    offs = [(dx, dy) for dy in range(-R, R + 1) for dx in range(-R, R + 1)
+            if 0 < dx * dx + dy * dy <= r_cut * r_cut]
+    N = L * L
+    D = 1 + len(offs)
+    col = np.empty((N, D), dtype=np.int32)
+    val = np.empty((N, D), dtype=np.float64)
+    s = np.arange(N, dtype=np.int64)
+    y, x = s // L, s % L
+    col[:, 0] = s
+    val[:, 0] = W * (np.random.default_rng(seed).random(N) - 0.5) if W else 0.0
+    for k, (dx, dy) in enumerate(offs, start=1):
+        col[:, k] = ((y + dy) % L) * L + (x + dx) % L
+        val[:, k] = t0 * np.exp(-(np.sqrt(dx * dx + dy * dy) - 1.0) / decay)
+    return col, val

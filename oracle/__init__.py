@@ -16,6 +16,7 @@ Contents, each following the passage cited beside it:
     Sec. II.B time blocks (C code in csp_oracle.c);
   * moment-based propagation, in time blocks or in one block with the
     halving of Eq. (cheby_prod) -- Sec. II.A, Sec. III DOS-Concurrent-M;
+  * Hamiltonians given explicitly in ELL form (any matrix density D_H);
   * quasi-eigenstates by forward and backward sequential propagation and
     the sum of Eq. QE_coeff (QE section, QE-Sequential);
   * band-structure closed forms of clean periodic lattices (any size);
@@ -341,6 +342,43 @@ def propagate_moments(lat, psi0, Nt, b=None, halving=True, Hn=None, H0=0.0, tau=
     if return_final:
         return corr.T.copy(), counters, fin.T.copy()
     return corr.T.copy(), counters
+
+
+class SparseLattice:
+    """A Hamiltonian given explicitly in ELL form: row s holds the entries
+    (col[s][k], val[s][k]), k < D; col < 0 marks padding.  It is used by
+    every propagation routine here exactly as a lattice (CSR rowptr / col /
+    val, N), so that general matrices of any density D_H (Sec. II.B) run
+    through the same oracle."""
+
+    def __init__(self, col, val):
+        col = np.asarray(col, dtype=np.int64)
+        val = np.asarray(val, dtype=np.float64)
+        if col.shape != val.shape or col.ndim != 2:
+            raise ValueError("col and val must both be [N][D]")
+        self.N, self.D = col.shape
+        self.ell_col, self.ell_val = col, val
+        keep = col >= 0
+        counts = keep.sum(1)
+        self.rowptr = np.zeros(self.N + 1, dtype=np.int64)
+        self.rowptr[1:] = np.cumsum(counts)
+        self.col = np.ascontiguousarray(col[keep])
+        self.val = np.ascontiguousarray(val[keep])
+
+    def halfwidth(self, margin=1.025):
+        """margin * max_s sum_k |H_sk| (Gershgorin, H0 = 0), the row sum taken
+        in k order with plain additions."""
+        acc = np.zeros(self.N)
+        for k in range(self.D):
+            acc = acc + np.where(self.ell_col[:, k] >= 0, np.abs(self.ell_val[:, k]), 0.0)
+        return margin * float(acc.max())
+
+    def dense(self):
+        H = np.zeros((self.N, self.N))
+        for s in range(self.N):
+            for p in range(self.rowptr[s], self.rowptr[s + 1]):
+                H[s, self.col[p]] += self.val[p]
+        return H
 
 
 def quasi_eigenstates(lat, psi0, Nt, energies, Hn=None, H0=0.0, tau=math.pi, eta=1e-14,
