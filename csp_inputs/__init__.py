@@ -81,3 +81,34 @@ def long_range_square(L, r_cut, t0=1.0, decay=1.0, W=0.0, seed=0):
         col[:, k] = ((y + dy) % L) * L + (x + dx) % L
         val[:, k] = t0 * np.exp(-(np.sqrt(dx * dx + dy * dy) - 1.0) / decay)
     return col, val
+
+
+def random_symmetric_ell(N, n_pairs, seed=0, diag=True):
+    """A random real symmetric matrix of irregular row lengths in ELL form:
+    n_pairs off-diagonal pairs (i, j), i != j, drawn uniformly (duplicates
+    dropped), each with one normal value placed at (i, j) and (j, i), plus a
+    normal diagonal when diag.  Rows are padded to the longest with col = -1
+    (val = 0).  Returns (col int32 [N][D], val float64 [N][D])."""
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, N, size=n_pairs)
+    j = rng.integers(0, N, size=n_pairs)
+    keep = i != j
+    a, b = np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
+    pairs = np.unique(np.stack([a, b], 1), axis=0)
+    v = rng.normal(size=len(pairs))
+    rows = [[] for _ in range(N)]
+    if diag:
+        d = rng.normal(size=N)
+        for s in range(N):
+            rows[s].append((s, d[s]))
+    for (p, q), x in zip(pairs, v):
+        rows[p].append((q, x))
+        rows[q].append((p, x))
+    D = max(1, max(len(r) for r in rows))
+    col = np.full((N, D), -1, dtype=np.int32)
+    val = np.zeros((N, D), dtype=np.float64)
+    for s, r in enumerate(rows):
+        for k, (c, x) in enumerate(r):
+            col[s, k] = c
+            val[s, k] = x
+    return col, val

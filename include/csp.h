@@ -44,7 +44,10 @@ typedef enum {
     CSP_ENUMERIC = -5       /* non-finite value or norm guard tripped */
 } csp_status;
 
-typedef enum { CSP_CHAIN = 0, CSP_SQUARE = 1, CSP_HONEYCOMB = 2 } csp_lattice_kind;
+typedef enum {
+    CSP_CHAIN = 0, CSP_SQUARE = 1, CSP_HONEYCOMB = 2,
+    CSP_SPARSE = 3       /* matrix given explicitly (csp_lattice_create_sparse) */
+} csp_lattice_kind;
 
 /* Value type of a state block. */
 typedef enum { CSP_C64 = 0 /* complex float */, CSP_C128 = 1 /* complex double */ } csp_dtype;
@@ -217,6 +220,21 @@ csp_status csp_context_destroy(csp_context *ctx);
  * 2^31 - 1 orbitals (CSP_EUNSUPPORTED beyond). */
 csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
                               csp_lattice **out);
+/* A Hamiltonian given explicitly, for matrices of any density D_H (Sec. II.B;
+ * the paper's speedups are measured at D_H = 60..230): N orbitals, D entries
+ * per row in ELL form, row s holding (col[s*D+k], val[s*D+k]) for k < D;
+ * col < 0 marks padding (its val is ignored).  The matrix must be real
+ * symmetric (not checked).  Host arrays, copied to the device (as [D][N],
+ * values in FP64 and FP32).  H0 = 0 and |H| = margin * max_s sum_k |val_sk|
+ * (Gershgorin, reduced on the GPU in FP64; margin <= 0 selects 1.025).
+ * Such a lattice runs through every propagation entry point; its recursion
+ * applies one Chebyshev step per launch (a gathered sparse product).
+ * csp_lattice_onsite and csp_lattice_neighbors return CSP_EUNSUPPORTED for
+ * it.  Errors: CSP_EINVAL for N outside [1, 2^31), D outside [1, 4096], a
+ * column index >= N, a non-finite value or an all-zero matrix; CSP_ENOMEM
+ * when the device cannot hold the 16 D N bytes of the matrix. */
+csp_status csp_lattice_create_sparse(csp_context *ctx, int64_t N, int32_t D, const int32_t *col,
+                                     const double *val, double margin, csp_lattice **out);
 csp_status csp_lattice_destroy(csp_lattice *lat);
 csp_status csp_lattice_get_info(const csp_lattice *lat, csp_lattice_info *out);
 

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ------------------------------------------------------------------ constants
 CSP_OK, CSP_EINVAL, CSP_ENOMEM, CSP_EHIP, CSP_EUNSUPPORTED, CSP_ENUMERIC = 0, -1, -2, -3, -4, -5
-CSP_CHAIN, CSP_SQUARE, CSP_HONEYCOMB = 0, 1, 2
+CSP_CHAIN, CSP_SQUARE, CSP_HONEYCOMB, CSP_SPARSE = 0, 1, 2, 3
 KINDS = {"chain": CSP_CHAIN, "square": CSP_SQUARE, "honeycomb": CSP_HONEYCOMB}
 CSP_C64, CSP_C128 = 0, 1
 CSP_FP64_SEQ, CSP_FP64_CONC, CSP_FP32_CONC = 0, 1, 2
@@ -119,6 +119,8 @@ _sig("csp_context_create", [ctypes.c_int, _vp, _P(_vp)])
 _sig("csp_context_destroy", [_vp])
 _sig("csp_context_trim", [_vp])
 _sig("csp_lattice_create", [_vp, _P(LatticeDesc), _P(_vp)])
+_sig("csp_lattice_create_sparse", [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, ctypes.c_double,
+                                   _P(_vp)])
 _sig("csp_lattice_destroy", [_vp])
 _sig("csp_lattice_get_info", [_vp, _P(LatticeInfo)])
 _sig("csp_lattice_onsite", [_vp, _vp])
@@ -240,6 +242,9 @@ class Lattice:
         self.desc = d
         h = ctypes.c_void_p()
         _check(_lib.csp_lattice_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
+        self._finish(ctx, h)
+
+    def _finish(self, ctx, h):
         self.handle = h
         ctx._lattices.add(self)
         info = LatticeInfo()
@@ -247,6 +252,26 @@ class Lattice:
         self.info = info
         self.N = info.n_orb
         self.halfwidth = info.halfwidth
+
+    @classmethod
+    def sparse(cls, ctx, col, val, margin=0.0):
+        """Explicit Hamiltonian in ELL form: host arrays col (int32, [N][D],
+        negative = padding) and val (float64, [N][D]); see
+        csp_lattice_create_sparse."""
+        import numpy as np
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        if col.ndim != 2 or col.shape != val.shape:
+            raise ValueError("col and val must both be [N][D]")
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.desc = None
+        h = ctypes.c_void_p()
+        _check(_lib.csp_lattice_create_sparse(
+            ctx.handle, col.shape[0], col.shape[1], col.ctypes.data_as(_vp),
+            val.ctypes.data_as(_vp), float(margin), ctypes.byref(h)))
+        self._finish(ctx, h)
+        return self
 
     def onsite(self):
         import torch

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 
 SOURCES = ["k_cheb_f32.hip", "k_cheb_f32m.hip", "k_cheb_f32mc.hip", "k_cheb_f64.hip",
            "k_cheb_f64mc.hip", "k_setup.hip", "k_coeffs.hip",
-           "k_cheb.hip", "k_contract.hip", "k_moments.hip",
+           "k_cheb.hip", "k_cheb_ell.hip", "k_contract.hip", "k_moments.hip",
            "k_probe.hip", "k_qe.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -88,6 +88,11 @@ struct csp_lattice {
   double* eps64 = nullptr;
   float* eps32 = nullptr;
   bool has_onsite = false;
+  // explicit matrix (kind CSP_SPARSE), [D][N]
+  int32_t* ell_col = nullptr;
+  double* ell_v64 = nullptr;
+  float* ell_v32 = nullptr;
+  int ell_D = 0;
 };
 
 namespace {
@@ -281,12 +286,84 @@ extern "C" csp_status csp_lattice_create(csp_context* c, const csp_lattice_desc*
   return CSP_OK;
 }
 
+extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32_t D,
+                                                const int32_t* col, const double* val,
+                                                double margin, csp_lattice** out) {
+  if (!c || !col || !val || !out) return fail(CSP_EINVAL, "NULL argument");
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(CSP_EINVAL, "need 1 <= N < 2^31");
+  if (D < 1 || D > 4096) return fail(CSP_EINVAL, "need 1 <= D <= 4096");
+  // transpose to [D][N] on the host, checking the indices
+  std::vector<int32_t> ct((size_t)D * N);
+  std::vector<double> vt((size_t)D * N);
+  std::vector<float> vf((size_t)D * N);
+  for (int64_t s = 0; s < N; ++s)
+    for (int k = 0; k < D; ++k) {
+      const int32_t j = col[s * D + k];
+      if (j >= N) return fail(CSP_EINVAL, "row %lld: column %d out of range", (long long)s, j);
+      const double v = j >= 0 ? val[s * D + k] : 0.0;
+      if (!std::isfinite(v)) return fail(CSP_EINVAL, "row %lld: non-finite value", (long long)s);
+      ct[(size_t)k * N + s] = j < 0 ? static_cast<int32_t>(s) : j;   // padding: 0 x own value
+      vt[(size_t)k * N + s] = v;
+      vf[(size_t)k * N + s] = static_cast<float>(v);
+    }
+  DeviceGuard dg(c->device);
+  csp_lattice* L = new csp_lattice();
+  L->ctx = c;
+  L->g.kind = CSP_SPARSE;
+  L->g.Lx = N;
+  L->g.Ly = 1;
+  L->g.opr = N;
+  L->g.N = N;
+  L->desc.kind = CSP_SPARSE;
+  L->desc.Lx = N;
+  L->desc.Ly = 1;
+  L->ell_D = D;
+  auto cleanup = [&](csp_status st) {
+    if (L->ell_col) (void)hipFree(L->ell_col);
+    if (L->ell_v64) (void)hipFree(L->ell_v64);
+    if (L->ell_v32) (void)hipFree(L->ell_v32);
+    delete L;
+    return st;
+  };
+  const size_t n = (size_t)D * N;
+  if (hipMalloc(&L->ell_col, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&L->ell_v64, sizeof(double) * n) != hipSuccess ||
+      hipMalloc(&L->ell_v32, sizeof(float) * n) != hipSuccess) {
+    (void)hipGetLastError();
+    return cleanup(fail(CSP_ENOMEM, "explicit matrix of %lld entries", (long long)n));
+  }
+  hipError_t e = hipMemcpy(L->ell_col, ct.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(L->ell_v64, vt.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(L->ell_v32, vf.data(), sizeof(float) * n, hipMemcpyHostToDevice);
+  const int np = 1024;
+  double* d_part = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&d_part, sizeof(double) * np);
+  if (e == hipSuccess) e = launch_ell_gershgorin(N, D, L->ell_col, L->ell_v64, d_part, np, c->stream);
+  std::vector<double> part(np);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), d_part, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (d_part) (void)hipFree(d_part);
+  if (e != hipSuccess) return cleanup(fail(CSP_EHIP, "matrix set-up: %s", hipGetErrorString(e)));
+  double m = 0.0;
+  for (double v : part) m = std::max(m, v);
+  L->gersh = m;
+  L->H0 = 0.0;
+  L->halfwidth = (margin > 0 ? margin : 1.025) * m;
+  if (!(L->halfwidth > 0)) return cleanup(fail(CSP_EINVAL, "zero matrix"));
+  *out = L;
+  return CSP_OK;
+}
+
 extern "C" csp_status csp_lattice_destroy(csp_lattice* L) {
   if (!L) return CSP_OK;
   DeviceGuard dg(L->ctx->device);
   (void)hipStreamSynchronize(L->ctx->stream);
   if (L->eps64) (void)hipFree(L->eps64);
   if (L->eps32) (void)hipFree(L->eps32);
+  if (L->ell_col) (void)hipFree(L->ell_col);
+  if (L->ell_v64) (void)hipFree(L->ell_v64);
+  if (L->ell_v32) (void)hipFree(L->ell_v32);
   delete L;
   return CSP_OK;
 }
@@ -299,13 +376,14 @@ extern "C" csp_status csp_lattice_get_info(const csp_lattice* L, csp_lattice_inf
   o->H0 = L->H0;
   o->halfwidth = L->halfwidth;
   o->gershgorin = L->gersh;
-  o->max_degree = max_degree(L->g.kind);
+  o->max_degree = L->g.kind == CSP_SPARSE ? L->ell_D : max_degree(L->g.kind);
   o->has_onsite = L->has_onsite ? 1 : 0;
   return CSP_OK;
 }
 
 extern "C" csp_status csp_lattice_onsite(const csp_lattice* L, double* dev_eps) {
   if (!L || !dev_eps) return fail(CSP_EINVAL, "NULL argument");
+  if (L->g.kind == CSP_SPARSE) return fail(CSP_EUNSUPPORTED, "explicit matrix: no on-site array");
   DeviceGuard dg(L->ctx->device);
   HIPCALL(hipMemcpyAsync(dev_eps, L->eps64, sizeof(double) * L->g.N, hipMemcpyDeviceToDevice,
                          L->ctx->stream));
@@ -314,6 +392,7 @@ extern "C" csp_status csp_lattice_onsite(const csp_lattice* L, double* dev_eps) 
 
 extern "C" csp_status csp_lattice_neighbors(const csp_lattice* L, int64_t* dev_nbr) {
   if (!L || !dev_nbr) return fail(CSP_EINVAL, "NULL argument");
+  if (L->g.kind == CSP_SPARSE) return fail(CSP_EUNSUPPORTED, "explicit matrix: no stencil");
   DeviceGuard dg(L->ctx->device);
   HIPCALL(launch_neighbours(L->g, dev_nbr, L->ctx->stream));
   return CSP_OK;
@@ -400,13 +479,16 @@ ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, 
   ChebPlan p;
   p.vec = vec > 0 ? vec : 2;
   p.kt = kt > 0 ? kt : 1;
+  for (auto& I : insts)
+    if (I.kind == CSP_SPARSE) p.kt = 1;   // explicit matrices: one step per launch
   if (!cheb_shape_supported(fp64, p.vec, p.kt, mom)) {
     p.vec = 2;
     p.kt = 1;
   }
   p.ow = 64 * p.vec - 2 * cheb_margin(p.vec, p.kt);
   int64_t items_rows1 = 0;   // items with one row per segment
-  for (auto& I : insts) items_rows1 += I.Rg * ceil_div(I.opr, p.ow) * I.Ly;
+  for (auto& I : insts)
+    if (I.kind != CSP_SPARSE) items_rows1 += I.Rg * ceil_div(I.opr, p.ow) * I.Ly;
   if (seg > 0) {
     p.seg_rows = seg;
   } else {
@@ -417,19 +499,30 @@ ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, 
   int64_t t0 = 0;
   for (size_t k = 0; k < insts.size(); ++k) {
     ChebInst& I = insts[k];
-    I.n_strips = ceil_div(I.opr, p.ow);
-    I.n_segs = ceil_div(I.Ly, p.seg_rows);
+    const bool sparse = I.kind == CSP_SPARSE;
+    I.n_strips = sparse ? 1 : ceil_div(I.opr, p.ow);
+    I.n_segs = sparse ? ceil_div(I.N, 64) : ceil_div(I.Ly, p.seg_rows);
     I.item0 = t0;
     const int64_t n = (int64_t)I.Rg * I.n_strips * I.n_segs;
     const bool honey = I.kind == CSP_HONEYCOMB, eps = I.eps != nullptr;
-    if (p.runs.empty() || p.runs.back().honey != honey || p.runs.back().eps != eps)
-      p.runs.push_back({(int)k, 0, t0, 0, honey, eps});
+    if (p.runs.empty() || p.runs.back().honey != honey || p.runs.back().eps != eps ||
+        p.runs.back().sparse != sparse)
+      p.runs.push_back({(int)k, 0, t0, 0, honey, eps, sparse});
     p.runs.back().n_inst += 1;
     p.runs.back().n_items += n;
     t0 += n;
   }
   p.total_items = t0;
   return p;
+}
+
+// Bytes of the per-orbital operands that every recursion launch reads once
+// per column group: on-site energies, or the explicit matrix (indices and
+// values).
+double static_bytes(const csp_lattice* L, bool fp64) {
+  const double w = fp64 ? 8 : 4;
+  if (L->g.kind == CSP_SPARSE) return (double)L->g.N * L->ell_D * (4 + w);
+  return L->has_onsite ? (double)L->g.N * w : 0.0;
 }
 
 ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
@@ -441,10 +534,15 @@ ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
   I.Ly = L->g.Ly;
   I.opr = L->g.opr;
   I.N = L->g.N;
-  I.alpha = 2.0 * L->desc.t / L->halfwidth;
+  I.alpha = 2.0 * (L->g.kind == CSP_SPARSE ? 1.0 : L->desc.t) / L->halfwidth;
   I.beta0 = -2.0 * L->H0 / L->halfwidth;
   I.onsite_scale = 2.0 / L->halfwidth;
   I.eps = L->has_onsite ? (fp64 ? (const void*)L->eps64 : (const void*)L->eps32) : nullptr;
+  if (L->g.kind == CSP_SPARSE) {
+    I.ell_col = L->ell_col;
+    I.ell_val = fp64 ? (const void*)L->ell_v64 : (const void*)L->ell_v32;
+    I.ell_D = L->ell_D;
+  }
   return I;
 }
 
@@ -558,8 +656,8 @@ std::string shape_key(const std::vector<InstIn>& ins, bool fp64, int assembly) {
   char buf[160];
   for (auto& in : ins) {
     const Geom& g = in.lat->g;
-    snprintf(buf, sizeof(buf), "|%d:%lld:%lld:%d%d:%d:%d", g.kind, (long long)g.Lx,
-             (long long)g.Ly, g.px, g.py, in.lat->has_onsite ? 1 : 0, in.R);
+    snprintf(buf, sizeof(buf), "|%d:%lld:%lld:%d%d:%d:%d:%d", g.kind, (long long)g.Lx,
+             (long long)g.Ly, g.px, g.py, in.lat->has_onsite ? 1 : 0, in.lat->ell_D, in.R);
     k += buf;
   }
   return k;
@@ -1015,7 +1113,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   double spmm_bytes = 0, con_bytes = 0, con_flops = 0;
   double eps_bytes = 0;
   for (auto& g : groups)
-    if (ins[g.inst].lat->has_onsite) eps_bytes += (double)ins[g.inst].lat->g.N * (fp64 ? 8 : 4);
+    eps_bytes += static_bytes(ins[g.inst].lat, fp64);
   const double vbytes = (double)vec_elems * csz;
 
   ContractArgs ca{};
@@ -1369,7 +1467,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   double spmm_bytes = 0;
   double eps_bytes = 0;
   for (auto& g : groups)
-    if (ins[g.inst].lat->has_onsite) eps_bytes += (double)ins[g.inst].lat->g.N * (fp64 ? 8 : 4);
+    eps_bytes += static_bytes(ins[g.inst].lat, fp64);
   const double vbytes = (double)vec_elems * csz;
 
   const ChebStep st0 = step_args(sp_plan);
@@ -1738,7 +1836,8 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     rep->ms_total = now_ms() - t_start;
     rep->ms_spmm = ms_s;
     rep->ms_contract = ms_c;
-    rep->spmm_bytes = (double)N * R * csz * ((double)Nmax + 2.0 * n_spmm);
+    rep->spmm_bytes = (double)N * R * csz * ((double)Nmax + 2.0 * n_spmm) +
+                      (double)groups.size() * static_bytes(L, fp64) * n_spmm;
     rep->contract_bytes = (double)N * R * csz * ((double)Nmax + 1.0 + 2.0 * nE * n_con);
     rep->contract_flops = 2.0 * 2.0 * (double)N * R * (Nmax + 1) * nE * (fp64 ? 1.0 : 3.0);
     rep->workspace_bytes = c->ws_size;
@@ -1842,10 +1941,12 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   struct Cand { int vec, kt, seg; };
   std::vector<Cand> cands;
   int64_t max_rec = 0;
-  for (int v = 2; v <= 4; v *= 2)
-    for (int kt = 1; kt <= 8; kt *= 2) {
+  bool any_sparse = false;
+  for (auto& I : sp) any_sparse = any_sparse || I.kind == CSP_SPARSE;
+  for (int v = 2; v <= (any_sparse ? 2 : 4); v *= 2)
+    for (int kt = 1; kt <= (any_sparse ? 1 : 8); kt *= 2) {
       if (!cheb_shape_supported(fp64, v, kt, mom)) continue;
-      for (int seg = 8; seg <= 128; seg *= 2) {
+      for (int seg = 8; seg <= (any_sparse ? 8 : 128); seg *= 2) {
         std::vector<ChebInst> tmp_sp = sp;
         ChebPlan p = plan_cheb(tmp_sp, fp64, mom, c->n_cu, v, kt, seg);
         if (p.total_items < 1 || ceil_div(p.total_items, 4) > INT32_MAX) continue;

@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
               "csp_propagate", "csp_propagate_batch", "csp_dos", "csp_last_error",
               "csp_chebyshev_coefficients", "csp_chebyshev_step", "csp_select_block",
               "csp_autotune", "csp_set_tuning", "csp_bandwidth_probe",
-              "csp_quasi_eigenstates"):
+              "csp_quasi_eigenstates", "csp_lattice_create_sparse"):
         assert n in names
 
 
