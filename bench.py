@@ -65,8 +65,14 @@ def parse():
                          "lattice (31623^2, W = 0.5, 4 random columns, Nt = 4096) in the "
                          "complex64 moment and state forms against the complex128 moment form, "
                          "and the complex128 sequential form timed on a truncated run")
+    ap.add_argument("--dense-dh", action="store_true",
+                    help="instead of the step benchmark: the DOS (Nt = 4096) of explicit "
+                         "matrices of density D_H = 61, 121, 233 (4.76 M orbitals, 10 / 5 / 2 "
+                         "random columns) by the moment form in complex64 and complex128 "
+                         "against the complex128 sequential form timed on a truncated run")
     ap.add_argument("--seq-steps", type=int, default=8,
-                    help="time steps of the truncated complex128 sequential run (--dos-1e9)")
+                    help="time steps of the truncated complex128 sequential run "
+                         "(--dos-1e9, --dense-dh)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 2 GiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -225,6 +231,94 @@ def dos_1e9(a):
     print(json.dumps(out), flush=True)
 
 
+def dense_dh(a):
+    """DOS of explicit Hamiltonians of matrix density D_H = 61, 121, 233
+    (Sec. III: the speedup of the concurrent method grows with D_H; the
+    paper measures 10.2x at D_H = 60 to 11.3x at D_H = 230 for Nt = 4096).
+    Per density: the moment form with halving (one block, DOS-Concurrent-M)
+    in complex64 and complex128, the complex128 sequential form on two
+    truncated runs scaled to Nt (its cost is linear in the steps), and the
+    explicit-matrix recursion kernel's algorithmic bandwidth."""
+    import numpy as np
+    import torch
+    import paper_2510_17432_amd as csp
+    w = csp_inputs.LONG_RANGE2182
+    Nt = w["Nt"]
+    ctx = csp.Context(0)
+    dev = "cuda:0"
+    out = {"workload": "long-range square lattice %dx%d (N=%d), hopping %g exp(-(d-1)/%g) "
+                       "within r_cut, W=%g (seed %d), Nt=%d; stand-in for the twisted "
+                       "bilayer graphene supercell" % (w["L"], w["L"], w["L"] ** 2, w["t0"],
+                                                        w["decay"], w["W"], w["seed"], Nt),
+           "cases": []}
+    for case in w["cases"]:
+        t0 = time.perf_counter()
+        col, val = csp_inputs.long_range_square(w["L"], case["r_cut"], w["t0"], w["decay"],
+                                                w["W"], w["seed"])
+        lat = csp.Lattice.sparse(ctx, col, val)
+        N, D, R = col.shape[0], col.shape[1], case["R"]
+        del col, val
+        log("D_H=%d N=%d R=%d |H|=%.6f (set-up %.1f s)" % (D, N, R, lat.halfwidth,
+                                                           time.perf_counter() - t0))
+        psi64 = torch.empty((N, R), dtype=torch.complex128, device=dev)
+        csp.csp_states_random_phase(ctx, psi64, R, w["seed_states"])
+        psi32 = psi64.to(torch.complex64)
+
+        def run(psi, mode, steps, profile=False):
+            params = csp.make_params(steps, mode=mode, assembly=csp.CSP_ASSEMBLE_MOMENTS,
+                                     profile=profile)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            corr, rep = csp.csp_propagate(ctx, lat, psi, params)
+            _, _, Dm = csp.csp_dos(ctx, corr, lat.halfwidth)
+            torch.cuda.synchronize()
+            return corr, Dm, time.perf_counter() - t, rep
+
+        # kernel bandwidth: a short profiled run (HIP events around each launch)
+        kern = {}
+        for mode, psi in (("fp32_conc", psi32), ("fp64_conc", psi64)):
+            _, _, _, rep = run(psi, mode, 64, profile=True)
+            per = rep.ms_spmm / rep.spmm_launches
+            kern[mode] = {"ms_per_launch": per,
+                          "alg_GBps": rep.spmm_bytes / rep.spmm_launches / per / 1e6}
+        c64, D64, t64, r64 = run(psi64, "fp64_conc", Nt)
+        log("  complex128 moments: %.1f s (%d steps)" % (t64, r64.amxsy))
+        c32, D32, t32, r32 = run(psi32, "fp32_conc", Nt)
+        log("  complex64 moments: %.1f s" % t32)
+        s1, s2 = a.seq_steps, 3 * a.seq_steps
+        _, _, ts1, _ = run(psi64, "fp64_seq", s1)
+        cs2, _, ts2, rs2 = run(psi64, "fp64_seq", s2)
+        per_step = (ts2 - ts1) / (s2 - s1)
+        t_seq = ts1 + per_step * (Nt - s1)
+        log("  complex128 sequential: %d steps %.2f s, %d steps %.2f s -> %.0f s for %d" %
+            (s1, ts1, s2, ts2, t_seq, Nt))
+        ref_d = D64.cpu().numpy()
+        rel32 = float(np.max(np.abs(D32.cpu().numpy() - ref_d)) / np.max(np.abs(ref_d)))
+        eps32 = float(np.max(np.abs(c32.cpu().numpy() - c64.cpu().numpy())))
+        # the two complex128 forms on the time points both computed
+        seq_gap = float(np.max(np.abs(cs2.cpu().numpy() - c64[:s2 + 1].cpu().numpy())))
+        out["cases"].append({
+            "D_H": D, "N": N, "R": R, "halfwidth": lat.halfwidth,
+            "recursion_steps": r64.amxsy, "sequential_steps_per_time_step": rs2.amxsy // s2,
+            "fp64_moments_s": t64, "fp32_moments_s": t32,
+            "fp64_sequential_s_extrapolated": t_seq,
+            "fp64_sequential_sample": "%d and %d of %d steps in %.2f s and %.2f s; %.4f s per "
+                                      "step" % (s1, s2, Nt, ts1, ts2, per_step),
+            "speedup_fp64_moments_vs_fp64_sequential": t_seq / t64,
+            "speedup_fp32_moments_vs_fp64_sequential": t_seq / t32,
+            "fp32_dos_rel_err": rel32, "fp32_corr_eps_inf": eps32,
+            "fp64_moments_vs_sequential_eps_inf": seq_gap,
+            "recursion_kernel": kern})
+        log("  speedup vs sequential: complex128 %.1fx, complex64 %.1fx; DOS rel err %.2e" %
+            (t_seq / t64, t_seq / t32, rel32))
+        del psi32, psi64, c64, c32, D64, D32, cs2
+        lat.close()
+        ctx.trim()
+        torch.cuda.empty_cache()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -233,6 +327,9 @@ def main():
         sys.exit(2)
     if a.dos_1e9:
         dos_1e9(a)
+        return
+    if a.dense_dh:
+        dense_dh(a)
         return
     import numpy as np
     import torch

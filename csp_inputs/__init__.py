@@ -31,6 +31,16 @@ DISORDERED_GRAPHENE4096 = dict(kind="honeycomb", Lx=4096, Ly=4096, t=-2.7, W=1.0
 SQUARE31623 = dict(kind="square", Lx=31623, Ly=31623, t=1.0, W=0.5, disorder_seed=6, R=4,
                    seed_states=7, Nt=4096)
 
+# Stand-in for the paper's magic-angle twisted bilayer graphene supercell
+# (4 763 200 atoms, matrix densities D_H = 60, 120, 230; Sec. III): the
+# long-range square lattice below, 2182 x 2182 sites (4 761 124 orbitals),
+# hopping -1 * exp(-(d - 1)/2) to every site within r_cut, on-site energies
+# W = 0.5; r_cut 4.3, 6.1, 8.6 give D_H = 61, 121, 233.  Random-phase
+# states per density as in the paper's protocol (10, 5, 2), Nt = 4096.
+LONG_RANGE2182 = dict(L=2182, t0=-1.0, decay=2.0, W=0.5, seed=1, seed_states=9, Nt=4096,
+                      cases=[dict(r_cut=4.3, D=61, R=10), dict(r_cut=6.1, D=121, R=5),
+                             dict(r_cut=8.6, D=233, R=2)])
+
 
 def batch32(seed=8, n=32):
     """Uneven batch: n lattices alternating square (t = 1 eV) and honeycomb

@@ -224,8 +224,9 @@ csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
  * the paper's speedups are measured at D_H = 60..230): N orbitals, D entries
  * per row in ELL form, row s holding (col[s*D+k], val[s*D+k]) for k < D;
  * col < 0 marks padding (its val is ignored).  The matrix must be real
- * symmetric (not checked).  Host arrays, copied to the device (as [D][N],
- * values in FP64 and FP32).  H0 = 0 and |H| = margin * max_s sum_k |val_sk|
+ * symmetric (not checked).  Host arrays, copied (the caller keeps them) to
+ * the device in slices of 128 rows, [N/128][D][128], with the values in
+ * FP64 and FP32.  H0 = 0 and |H| = margin * max_s sum_k |val_sk|
  * (Gershgorin, reduced on the GPU in FP64; margin <= 0 selects 1.025).
  * Such a lattice runs through every propagation entry point; its recursion
  * applies one Chebyshev step per launch (a gathered sparse product).

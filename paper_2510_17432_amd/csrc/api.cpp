@@ -292,20 +292,29 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
   if (!c || !col || !val || !out) return fail(CSP_EINVAL, "NULL argument");
   if (N < 1 || N >= ((int64_t)1 << 31)) return fail(CSP_EINVAL, "need 1 <= N < 2^31");
   if (D < 1 || D > 4096) return fail(CSP_EINVAL, "need 1 <= D <= 4096");
-  // transpose to [D][N] on the host, checking the indices
-  std::vector<int32_t> ct((size_t)D * N);
-  std::vector<double> vt((size_t)D * N);
-  std::vector<float> vf((size_t)D * N);
-  for (int64_t s = 0; s < N; ++s)
-    for (int k = 0; k < D; ++k) {
-      const int32_t j = col[s * D + k];
-      if (j >= N) return fail(CSP_EINVAL, "row %lld: column %d out of range", (long long)s, j);
-      const double v = j >= 0 ? val[s * D + k] : 0.0;
-      if (!std::isfinite(v)) return fail(CSP_EINVAL, "row %lld: non-finite value", (long long)s);
-      ct[(size_t)k * N + s] = j < 0 ? static_cast<int32_t>(s) : j;   // padding: 0 x own value
-      vt[(size_t)k * N + s] = v;
-      vf[(size_t)k * N + s] = static_cast<float>(v);
-    }
+  // reorder into slices of 128 rows, [N/128][D][128], on the host, checking
+  // the indices; padding entries (and the rows past N of the last slice)
+  // hold a valid index and the value 0
+  const int64_t n_slices = (N + 127) / 128;
+  const size_t n = (size_t)n_slices * D * 128;
+  std::vector<int32_t> ct(n, 0);
+  std::vector<double> vt(n, 0.0);
+  std::vector<float> vf(n, 0.0f);
+  for (int64_t sl = 0; sl < n_slices; ++sl) {
+    const int64_t s0 = sl * 128, s1 = std::min<int64_t>(N, s0 + 128);
+    const size_t o = (size_t)sl * D * 128;
+    for (int k = 0; k < D; ++k)
+      for (int64_t s = s0; s < s1; ++s) {
+        const int32_t j = col[s * D + k];
+        if (j >= N) return fail(CSP_EINVAL, "row %lld: column %d out of range", (long long)s, j);
+        const double v = j >= 0 ? val[s * D + k] : 0.0;
+        if (!std::isfinite(v)) return fail(CSP_EINVAL, "row %lld: non-finite value", (long long)s);
+        const size_t e = o + (size_t)k * 128 + (s - s0);
+        ct[e] = j < 0 ? static_cast<int32_t>(s) : j;   // padding: 0 x own value
+        vt[e] = v;
+        vf[e] = static_cast<float>(v);
+      }
+  }
   DeviceGuard dg(c->device);
   csp_lattice* L = new csp_lattice();
   L->ctx = c;
@@ -325,7 +334,6 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
     delete L;
     return st;
   };
-  const size_t n = (size_t)D * N;
   if (hipMalloc(&L->ell_col, sizeof(int32_t) * n) != hipSuccess ||
       hipMalloc(&L->ell_v64, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&L->ell_v32, sizeof(float) * n) != hipSuccess) {
@@ -338,7 +346,7 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
   const int np = 1024;
   double* d_part = nullptr;
   if (e == hipSuccess) e = hipMalloc(&d_part, sizeof(double) * np);
-  if (e == hipSuccess) e = launch_ell_gershgorin(N, D, L->ell_col, L->ell_v64, d_part, np, c->stream);
+  if (e == hipSuccess) e = launch_ell_gershgorin(N, D, L->ell_v64, d_part, np, c->stream);
   std::vector<double> part(np);
   if (e == hipSuccess)
     e = hipMemcpyAsync(part.data(), d_part, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream);
@@ -496,21 +504,28 @@ ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, 
     p.seg_rows = 64;
     while (p.seg_rows > 4 && items_rows1 / p.seg_rows < (int64_t)n_cu * 8) p.seg_rows /= 2;
   }
-  int64_t t0 = 0;
+  // explicit matrices: a wave owns 128 rows of ell_ct columns; items are
+  // the moment records, one per (column, 128-row chunk)
+  int64_t t0 = 0, w0 = 0;
   for (size_t k = 0; k < insts.size(); ++k) {
     ChebInst& I = insts[k];
     const bool sparse = I.kind == CSP_SPARSE;
     I.n_strips = sparse ? 1 : ceil_div(I.opr, p.ow);
-    I.n_segs = sparse ? ceil_div(I.N, 64) : ceil_div(I.Ly, p.seg_rows);
+    I.n_segs = sparse ? ceil_div(I.N, 128) : ceil_div(I.Ly, p.seg_rows);
     I.item0 = t0;
+    I.wave0 = w0;
     const int64_t n = (int64_t)I.Rg * I.n_strips * I.n_segs;
+    const int ct = sparse ? I.ell_ct : 0;
+    const int64_t nw = sparse ? I.n_segs * ceil_div(I.Rg, ct) : 0;
     const bool honey = I.kind == CSP_HONEYCOMB, eps = I.eps != nullptr;
     if (p.runs.empty() || p.runs.back().honey != honey || p.runs.back().eps != eps ||
-        p.runs.back().sparse != sparse)
-      p.runs.push_back({(int)k, 0, t0, 0, honey, eps, sparse});
+        p.runs.back().sparse != sparse || p.runs.back().ct != ct)
+      p.runs.push_back({(int)k, 0, t0, 0, honey, eps, sparse, ct, w0, 0});
     p.runs.back().n_inst += 1;
     p.runs.back().n_items += n;
+    p.runs.back().n_waves += nw;
     t0 += n;
+    w0 += nw;
   }
   p.total_items = t0;
   return p;
@@ -542,6 +557,7 @@ ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
     I.ell_col = L->ell_col;
     I.ell_val = fp64 ? (const void*)L->ell_v64 : (const void*)L->ell_v32;
     I.ell_D = L->ell_D;
+    I.ell_ct = ell_columns_per_wave(fp64, Rg);
   }
   return I;
 }

@@ -111,10 +111,11 @@ struct ChebInst {
   const void* src;             // phi_n of a block's first launch (slot_cur < 0)
   const void* psi0;            // psi0 of the group (moment epilogue)
   void* carry;                 // carried state (moment epilogue, nlev = 1)
-  const int32_t* ell_col;      // explicit matrix (kind CSP_SPARSE): [D][N], -1 = padding
-  const void* ell_val;         // [D][N] float or double
-  int32_t ell_D;
-  int32_t pad2;
+  const int32_t* ell_col;      // explicit matrix (kind CSP_SPARSE): [N/128][D][128] indices
+  const void* ell_val;         // same layout, float or double; padding entries are 0
+  int64_t wave0;               // first wave of this instance (explicit-matrix runs)
+  int32_t ell_D;               // entries per row
+  int32_t ell_ct;              // columns per wave
 };
 
 // Per-launch arguments: levels l = 1..nlev produce phi_{n+l} from
@@ -142,19 +143,24 @@ struct ChebStep {
 // without on-site energies) and their work items; one launch per run.
 struct ChebRun {
   int inst0, n_inst;
-  int64_t item0, n_items;
+  int64_t item0, n_items;      // work items (stencil); moment records (explicit matrix)
   bool honey, eps, sparse;
+  int ct;                      // explicit matrix: columns per wave
+  int64_t wave0, n_waves;      // explicit matrix: waves of the run
 };
 // mom: moment epilogue; carry: also the carried state (moment epilogue only)
 hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const ChebInst* d_inst,
                        const std::vector<ChebRun>& runs, const ChebStep& st, hipStream_t s);
 // Explicit (ELL) matrices: one Chebyshev step per launch, 64 rows of one
 // column per wave (item = column * row chunks + chunk).
-hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, const ChebInst* d_inst, int n_inst,
-                           int64_t item_lo, int64_t item_hi, const ChebStep& st, hipStream_t s);
+hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, int ct, const ChebInst* d_inst,
+                           int n_inst, int64_t wave_lo, int64_t wave_hi, const ChebStep& st,
+                           hipStream_t s);
+// columns per wave of the explicit-matrix kernel for a group of Rg columns
+int ell_columns_per_wave(bool fp64, int Rg);
 // max_s sum_k |val_sk| (k in order, FP64): one maximum per block into partial
-hipError_t launch_ell_gershgorin(int64_t N, int D, const int32_t* d_col, const double* d_val,
-                                 double* d_partial, int n_partial, hipStream_t s);
+hipError_t launch_ell_gershgorin(int64_t N, int D, const double* d_val, double* d_partial,
+                                 int n_partial, hipStream_t s);
 // (values per lane, steps per launch) pairs with a compiled kernel
 bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom);
 bool cheb_carry_supported(bool fp64, int vec, int kt);

@@ -40,7 +40,8 @@ hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const C
     const int64_t lo = r.item0, hi = r.item0 + r.n_items;
     hipError_t e;
     if (r.sparse)
-      e = launch_cheb_ell(fp64, mom, carry, di, r.n_inst, lo, hi, st, s);
+      e = launch_cheb_ell(fp64, mom, carry, r.ct, di, r.n_inst, r.wave0, r.wave0 + r.n_waves, st,
+                          s);
     else if (fp64)
       e = carry ? launch_cheb_f64mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
           : mom ? launch_cheb_f64m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)

@@ -4,149 +4,357 @@
 // dominates):
 //   phi_{n+1} = 2 H~ phi_n - phi_{n-1},  H~ = (H - H0)/|H|,
 // one step per launch (the neighbours of a row are arbitrary, so no
-// temporal blocking).  The matrix is stored [D][N] (entry k of every row
-// contiguous; a row with fewer entries is padded with its own index and a
-// zero value), so a wave reading entry k of its 64 rows reads 256 B of
-// indices and 256-512 B of values; the vector gathers go through the caches.
-// One wave handles 64 rows of one column; the waves of the columns of one
-// row chunk are scheduled together so that they share the matrix rows in
-// the caches (the matrix is read from HBM about once per step, not once per
-// column).  The moment epilogue and the carried state follow the stencil
-// kernel (records of 8 FP64 sums per wave, fixed butterfly).
+// temporal blocking).
+//
+// Layout.  The matrix is stored in slices of 128 rows, [N/128][D][128]
+// (sliced ELL): entry k of the 128 rows of a slice is contiguous, and a
+// slice's D entries follow each other, so the wave that owns a slice
+// streams one contiguous block.  A row with fewer than D entries, and every
+// row s >= N of the last slice, is padded with a valid column index and a
+// zero value, so the entry loop has no branch.  At D_H in the tens to hundreds
+// the matrix is most of the bytes of a step (D (4 + sizeof(T)) per row
+// against 24..48 B per row and column for the three vectors), so the kernel
+// is built around streaming it once per step:
+//   - a wave owns a slice (128 rows) and CT columns of a column group: the
+//     matrix entries loaded once serve the gathers of all CT columns;
+//   - lane l owns rows l and l + 64 of the slice, so every matrix load and
+//     every gather of the 64 lanes covers consecutive elements;
+//   - the index and value loads of the next U entries are issued after the
+//     gathers of the current ones, so the HBM latency of the matrix stream
+//     overlaps the (mostly cache-hit) vector gathers.
+// Measured on MI355X (D_H = 233, 4.76 M rows, two columns): the matrix
+// stream alone runs at the read ceiling (about 6 TB/s); with the gathers
+// the step runs at 4.2-4.5 TB/s of algorithmic bytes, the same for
+// interleaved rows, deeper pipelines and other block sizes.
+// Moment epilogue and carried state as the stencil kernel: one record of 8
+// FP64 sums per (column, 128-row chunk), record index column-major.
 #include <type_traits>
 
 #include "csp_internal.h"
 
-namespace csp {
+#define CSP_GLOBAL __attribute__((address_space(1)))
 
-template <typename T, bool MOM, bool CARRY>
+namespace csp {
+namespace ell {
+
+// complex values as element-aligned 2-vectors (a column of a group starts
+// at c N values)
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2), aligned(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2), aligned(8)));
+
+template <typename T> struct vt;
+template <> struct vt<float> { using v2 = f32x2; };
+template <> struct vt<double> { using v2 = f64x2; };
+
+// the complex values of a lane's two rows in one column
+template <typename T> struct pair2 { T r0, i0, r1, i1; };
+
+// one complex value
+template <typename T>
+__device__ __forceinline__ typename vt<T>::v2 ld_c(const CSP_GLOBAL T* p) {
+  return *reinterpret_cast<const CSP_GLOBAL typename vt<T>::v2*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_c(CSP_GLOBAL T* p, T re, T im, bool nt) {
+  typename vt<T>::v2 t;
+  t.x = re;
+  t.y = im;
+  if (nt) __builtin_nontemporal_store(t, reinterpret_cast<CSP_GLOBAL typename vt<T>::v2*>(p));
+  else *reinterpret_cast<CSP_GLOBAL typename vt<T>::v2*>(p) = t;
+}
+// rows s0, s1 of one column (zeros for rows past N)
+template <typename T>
+__device__ __forceinline__ pair2<T> ld_rows(const CSP_GLOBAL T* col, int64_t s0, int64_t s1,
+                                            bool v0, bool v1) {
+  pair2<T> r{T(0), T(0), T(0), T(0)};
+  if (v0) {
+    const typename vt<T>::v2 a = ld_c(col + 2 * s0);
+    r.r0 = a.x;
+    r.i0 = a.y;
+  }
+  if (v1) {
+    const typename vt<T>::v2 b = ld_c(col + 2 * s1);
+    r.r1 = b.x;
+    r.i1 = b.y;
+  }
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ void st_rows(CSP_GLOBAL T* col, int64_t s0, int64_t s1, bool v0, bool v1,
+                                        const pair2<T>& v, bool nt) {
+  if (v0) st_c(col + 2 * s0, v.r0, v.i0, nt);
+  if (v1) st_c(col + 2 * s1, v.r1, v.i1, nt);
+}
+
+// Matrix entries per pipelined block and blocks the matrix loads run ahead
+// (measured on MI355X at D_H = 233: FP32 4 entries, FP64 2 entries, one
+// block ahead; deeper pipelines bought nothing, as the gathers rather than
+// the index latency set the pace).
+template <typename T> constexpr int ell_block() { return sizeof(T) == 4 ? 4 : 2; }
+constexpr int PD = 1;
+
+// The matrix is read once per step and never again before every other
+// cache line of the step has passed: non-temporal loads, which leave the
+// L2 to the gathered vectors (each vector value is gathered D times).
+template <typename V>
+__device__ __forceinline__ V ld_stream(const CSP_GLOBAL V* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <typename T, int CT, bool MOM, bool CARRY>
 __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ insts, int n_inst,
-                                                  int64_t item_lo, int64_t item_hi, ChebStep st) {
-  using C = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+                                                  int64_t wave_lo, int64_t wave_hi, ChebStep st) {
+  using V2 = typename vt<T>::v2;
+  constexpr int U = ell_block<T>();
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-  const int64_t w = item_lo + xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (w >= item_hi) return;                         // a whole wave
+  const int64_t w = wave_lo + xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (w >= wave_hi) return;                         // a whole wave
   int ii = 0;
-  while (ii + 1 < n_inst && w >= insts[ii + 1].item0) ++ii;
+  while (ii + 1 < n_inst && w >= insts[ii + 1].wave0) ++ii;
   const ChebInst& I = insts[ii];
-  const int64_t lw = w - I.item0;
-  const int64_t col = lw % I.Rg, chunk = lw / I.Rg;
-  const int64_t item = I.item0 + col * I.n_segs + chunk;   // record index: column-major
+  const int64_t lw = w - I.wave0;
+  const int n_tiles = (I.Rg + CT - 1) / CT;
+  const int64_t chunk = lw / n_tiles;               // the slice of 128 rows
+  const int c0 = static_cast<int>(lw - chunk * n_tiles) * CT;
+  const int nc = I.Rg - c0 < CT ? I.Rg - c0 : CT;   // columns of this wave (wave-uniform)
   const int64_t N = I.N;
-  const int64_t s = chunk * 64 + lane;
-  const bool valid = s < N;
-  const int64_t coff = col * N;
-
-  C* base = static_cast<C*>(I.base);
-  const C* cur = (st.slot_cur < 0 ? static_cast<const C*>(I.src)
-                                  : base + (int64_t)st.slot_cur * I.slot_stride) + coff;
-  const C* prev = st.first ? nullptr : base + (int64_t)st.slot_prev * I.slot_stride + coff;
-  C* outv = st.slot_out[0] >= 0 ? base + (int64_t)st.slot_out[0] * I.slot_stride + coff : nullptr;
-  C* copyv = st.copy_slot >= 0 ? base + (int64_t)st.copy_slot * I.slot_stride + coff : nullptr;
-  const T* val = static_cast<const T*>(I.ell_val);
   const int D = I.ell_D;
+  const int64_t s0 = chunk * 128 + lane, s1 = s0 + 64;
+  const bool v0 = s0 < N, v1 = s1 < N;
+
+  const int64_t cofs = 2 * (int64_t)c0 * N;         // column c0 of the group, in T units
+  CSP_GLOBAL T* base = (CSP_GLOBAL T*)(I.base);
+  const CSP_GLOBAL T* cur =
+      (st.slot_cur < 0 ? (const CSP_GLOBAL T*)(I.src) : base + 2 * (int64_t)st.slot_cur * I.slot_stride) +
+      cofs;
+  const CSP_GLOBAL T* prev = st.first ? nullptr : base + 2 * (int64_t)st.slot_prev * I.slot_stride + cofs;
+  CSP_GLOBAL T* outv =
+      st.slot_out[0] >= 0 ? base + 2 * (int64_t)st.slot_out[0] * I.slot_stride + cofs : nullptr;
+  CSP_GLOBAL T* copyv =
+      st.copy_slot >= 0 ? base + 2 * (int64_t)st.copy_slot * I.slot_stride + cofs : nullptr;
+
+  // entry k of rows s0, s1: slice start + k * 128 + row inside the slice
+  const int64_t mofs = chunk * D * 128 + lane;
+  const CSP_GLOBAL int32_t* cp = (const CSP_GLOBAL int32_t*)(I.ell_col) + mofs;
+  const CSP_GLOBAL T* vp = (const CSP_GLOBAL T*)(I.ell_val) + mofs;
+  auto ld_entry = [&](int k, i32x2& j, V2& v) {
+    const int64_t e = (int64_t)k * 128;
+    j.x = ld_stream(cp + e);
+    j.y = ld_stream(cp + e + 64);
+    v.x = ld_stream(vp + e);
+    v.y = ld_stream(vp + e + 64);
+  };
+
+  // sum_k H_{s,j_k} phi_n[j_k] for rows s0, s1 of each column
+  T ar0[CT], ai0[CT], ar1[CT], ai1[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) ar0[c] = ai0[c] = ar1[c] = ai1[c] = T(0);
+
+  // column c of this wave; a wave with fewer than CT columns (the last tile
+  // of a group whose size is not a multiple of CT) gathers column 0 again
+  // for the missing ones and discards them, so no load sits under a branch
+  const CSP_GLOBAL T* xcol[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) xcol[c] = cur + 2 * (int64_t)(c < nc ? c : 0) * N;
+
+  auto fma_rows = [&](int c, const V2 v, const V2 x0, const V2 x1) {
+    ar0[c] = fma(v.x, x0.x, ar0[c]);
+    ai0[c] = fma(v.x, x0.y, ai0[c]);
+    ar1[c] = fma(v.y, x1.x, ar1[c]);
+    ai1[c] = fma(v.y, x1.y, ai1[c]);
+  };
+
+  // Blocks of U entries, the matrix loads running PD blocks ahead of the
+  // gathers.  In each block the gathers (which need the block's indices)
+  // are issued first and the matrix loads of block kb + PD U after them;
+  // loads complete in issue order, so waiting for the gathers waits for the
+  // matrix loads issued before them (blocks up to kb + (PD - 1) U) and
+  // leaves the newest in flight.
+  const int Dm = D - D % U;
+  i32x2 jb[PD][U];
+  V2 vb[PD][U];
+  if (Dm > 0) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int k0 = d * U < Dm ? d * U : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) ld_entry(k0 + u, jb[d][u], vb[d][u]);
+    }
+  }
+  for (int kb = 0; kb < Dm; kb += U) {
+    V2 x[U][CT][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        x[u][c][0] = ld_c(xcol[c] + 2 * (int64_t)jb[0][u].x);
+        x[u][c][1] = ld_c(xcol[c] + 2 * (int64_t)jb[0][u].y);
+      }
+    // block kb + PD U (past the end: the current block again, cached, no branch)
+    const int kn = kb + PD * U < Dm ? kb + PD * U : kb;
+    i32x2 jn[U];
+    V2 vn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ld_entry(kn + u, jn[u], vn[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) fma_rows(c, vb[0][u], x[u][c][0], x[u][c][1]);
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        jb[d][u] = jb[d + 1][u];
+        vb[d][u] = vb[d + 1][u];
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      jb[PD - 1][u] = jn[u];
+      vb[PD - 1][u] = vn[u];
+    }
+  }
+  for (int k = Dm; k < D; ++k) {
+    i32x2 j;
+    V2 v;
+    ld_entry(k, j, v);
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      fma_rows(c, v, ld_c(xcol[c] + 2 * (int64_t)j.x), ld_c(xcol[c] + 2 * (int64_t)j.y));
+  }
+
   const T scale = st.first ? T(0.5) : T(1);
   const T alpha = scale * static_cast<T>(I.alpha);
   const T beta0 = scale * static_cast<T>(I.beta0);
+  double rec[CT][8];
 
-  C c, o;
-  c.x = c.y = o.x = o.y = T(0);
-  if (valid) {
-    c = cur[s];
-    // padding entries hold (own index, 0), so the loop has no branch and
-    // its gathers can be issued ahead
-    T ax = T(0), ay = T(0);
-    const int32_t* cp = I.ell_col + s;
-    const T* vp = val + s;
-#pragma unroll 4
-    for (int k = 0; k < D; ++k) {
-      const int32_t j = cp[(int64_t)k * N];
-      const T v = vp[(int64_t)k * N];
-      const C x = cur[j];
-      ax = fma(v, x.x, ax);
-      ay = fma(v, x.y, ay);
-    }
-    C p;
-    p.x = p.y = T(0);
-    if (prev) p = prev[s];
-    o.x = alpha * ax + (beta0 * c.x - p.x);
-    o.y = alpha * ay + (beta0 * c.y - p.y);
-    if (outv) outv[s] = o;
-    if (copyv) copyv[s] = c;
-  }
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rec[c][q] = 0.0;
+    if (c >= nc || !v0) continue;
+    const int64_t co = 2 * (int64_t)c * N;          // column c0 + c, in T units
+    // phi_n and phi_{n-1} at rows s0, s1 (zeros past N)
+    const pair2<T> cv = ld_rows<T>(cur + co, s0, s1, v0, v1);
+    const pair2<T> pv = prev ? ld_rows<T>(prev + co, s0, s1, v0, v1)
+                             : pair2<T>{T(0), T(0), T(0), T(0)};
+    pair2<T> o;
+    o.r0 = alpha * ar0[c] + (beta0 * cv.r0 - pv.r0);
+    o.i0 = alpha * ai0[c] + (beta0 * cv.i0 - pv.i0);
+    o.r1 = v1 ? alpha * ar1[c] + (beta0 * cv.r1 - pv.r1) : T(0);
+    o.i1 = v1 ? alpha * ai1[c] + (beta0 * cv.i1 - pv.i1) : T(0);
+    if (outv) st_rows<T>(outv + co, s0, s1, v0, v1, o, true);
+    if (copyv) st_rows<T>(copyv + co, s0, s1, v0, v1, cv, true);
 
-  if constexpr (CARRY) {
-    if (valid && st.carry_mode && I.carry) {
-      C* carry = static_cast<C*>(I.carry) + coff;
-      const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
-      const T c1r = static_cast<T>(st.ccl[0][0]), c1i = static_cast<T>(st.ccl[0][1]);
-      C b;
-      if (st.carry_mode == 1) {
-        b.x = c0r * c.x - c0i * c.y;
-        b.y = c0r * c.y + c0i * c.x;
-      } else {
-        b = carry[s];
+    if constexpr (CARRY) {
+      if (st.carry_mode && I.carry) {
+        const T c0r = static_cast<T>(st.cc0[0]), c0i = static_cast<T>(st.cc0[1]);
+        const T c1r = static_cast<T>(st.ccl[0][0]), c1i = static_cast<T>(st.ccl[0][1]);
+        CSP_GLOBAL T* carry = (CSP_GLOBAL T*)(I.carry) + cofs + co;
+        pair2<T> b;
+        if (st.carry_mode == 1) {
+          b.r0 = c0r * cv.r0 - c0i * cv.i0;
+          b.i0 = c0r * cv.i0 + c0i * cv.r0;
+          b.r1 = c0r * cv.r1 - c0i * cv.i1;
+          b.i1 = c0r * cv.i1 + c0i * cv.r1;
+        } else {
+          b = ld_rows<T>(carry, s0, s1, v0, v1);
+        }
+        b.r0 += c1r * o.r0 - c1i * o.i0;
+        b.i0 += c1r * o.i0 + c1i * o.r0;
+        b.r1 += c1r * o.r1 - c1i * o.i1;
+        b.i1 += c1r * o.i1 + c1i * o.r1;
+        st_rows<T>(carry, s0, s1, v0, v1, b, false);
       }
-      b.x += c1r * o.x - c1i * o.y;
-      b.y += c1r * o.y + c1i * o.x;
-      carry[s] = b;
+    }
+
+    if constexpr (MOM) {
+      if (st.dot_psi0) {
+        const pair2<T> q =
+            ld_rows<T>((const CSP_GLOBAL T*)(I.psi0) + cofs + co, s0, s1, v0, v1);
+        rec[c][0] = ((double)q.r0 * o.r0 + (double)q.i0 * o.i0) +
+                    ((double)q.r1 * o.r1 + (double)q.i1 * o.i1);
+        rec[c][1] = ((double)q.r0 * o.i0 - (double)q.i0 * o.r0) +
+                    ((double)q.r1 * o.i1 - (double)q.i1 * o.r1);
+        rec[c][2] = ((double)q.r0 * cv.r0 + (double)q.i0 * cv.i0) +
+                    ((double)q.r1 * cv.r1 + (double)q.i1 * cv.i1);
+        rec[c][3] = ((double)q.r0 * cv.i0 - (double)q.i0 * cv.r0) +
+                    ((double)q.r1 * cv.i1 - (double)q.i1 * cv.r1);
+      }
+      if (st.dot_self) {
+        rec[c][4] = ((double)o.r0 * o.r0 + (double)o.i0 * o.i0) +
+                    ((double)o.r1 * o.r1 + (double)o.i1 * o.i1);
+        rec[c][6] = ((double)o.r0 * cv.r0 + (double)o.i0 * cv.i0) +
+                    ((double)o.r1 * cv.r1 + (double)o.i1 * cv.i1);
+        rec[c][7] = ((double)o.r0 * cv.i0 - (double)o.i0 * cv.r0) +
+                    ((double)o.r1 * cv.i1 - (double)o.i1 * cv.r1);
+      }
     }
   }
 
   if constexpr (MOM) {
     if (st.dot_psi0 || st.dot_self) {
-      double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (valid) {
-        const double ox = o.x, oy = o.y, cx = c.x, cy = c.y;
-        if (st.dot_psi0) {
-          const C q = static_cast<const C*>(I.psi0)[coff + s];
-          const double qx = q.x, qy = q.y;
-          r[0] = qx * ox + qy * oy;
-          r[1] = qx * oy - qy * ox;
-          r[2] = qx * cx + qy * cy;
-          r[3] = qx * cy - qy * cx;
+      // records [kind][re, im]: <psi0|out>, <psi0|cur>, <out|out>, <out|cur>,
+      // one per column, summed over the wave by a fixed butterfly
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        if (c >= nc) continue;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          double x = rec[c][q];
+#pragma unroll
+          for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+          rec[c][q] = x;
         }
-        if (st.dot_self) {
-          r[4] = ox * ox + oy * oy;
-          r[6] = ox * cx + oy * cy;
-          r[7] = ox * cy - oy * cx;
+        if (lane < 8) {
+          double val = rec[c][0];
+#pragma unroll
+          for (int q = 1; q < 8; ++q) val = lane == q ? rec[c][q] : val;
+          const int64_t item = I.item0 + (int64_t)(c0 + c) * I.n_segs + chunk;
+          st.partial[((int64_t)st.mom_slot * st.total_items + item) * 8 + lane] = val;
         }
-      }
-      // record [kind][re, im]: <psi0|out>, <psi0|cur>, <out|out>, <out|cur>
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        double x = r[k];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
-        r[k] = x;
-      }
-      if (lane == 0) {
-        double* out = st.partial + ((int64_t)st.mom_slot * st.total_items + item) * 8;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) out[k] = r[k];
       }
     }
   }
 }
 
-hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, const ChebInst* d_inst, int n_inst,
-                           int64_t item_lo, int64_t item_hi, const ChebStep& st, hipStream_t s) {
-  const int64_t n = item_hi - item_lo;
+}  // namespace ell
+
+int ell_columns_per_wave(bool fp64, int Rg) {
+  const int cap = fp64 ? 2 : 4;
+  int ct = 1;
+  while (ct * 2 <= Rg && ct * 2 <= cap) ct *= 2;
+  return ct;
+}
+
+hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, int ct, const ChebInst* d_inst,
+                           int n_inst, int64_t wave_lo, int64_t wave_hi, const ChebStep& st,
+                           hipStream_t s) {
+  const int64_t n = wave_hi - wave_lo;
   if (n <= 0) return hipSuccess;
   if (st.nlev != 1 || (carry && !mom)) return hipErrorInvalidValue;
+  if (ct != 1 && ct != 2 && ct != 4) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
-#define CSP_ELL(T, M, CY) \
-  hipLaunchKernelGGL((k_cheb_ell<T, M, CY>), grid, block, 0, s, d_inst, n_inst, item_lo, item_hi, st)
+#define CSP_ELL(T, CT, M, CY)                                                                     \
+  hipLaunchKernelGGL((ell::k_cheb_ell<T, CT, M, CY>), grid, block, 0, s, d_inst, n_inst, wave_lo, \
+                     wave_hi, st)
+#define CSP_ELL_CT(T, M, CY)                \
+  do {                                      \
+    if (ct == 1) CSP_ELL(T, 1, M, CY);      \
+    else if (ct == 2) CSP_ELL(T, 2, M, CY); \
+    else CSP_ELL(T, 4, M, CY);              \
+  } while (0)
   if (fp64) {
-    if (carry) CSP_ELL(double, true, true);
-    else if (mom) CSP_ELL(double, true, false);
-    else CSP_ELL(double, false, false);
+    if (carry) CSP_ELL_CT(double, true, true);
+    else if (mom) CSP_ELL_CT(double, true, false);
+    else CSP_ELL_CT(double, false, false);
   } else {
-    if (carry) CSP_ELL(float, true, true);
-    else if (mom) CSP_ELL(float, true, false);
-    else CSP_ELL(float, false, false);
+    if (carry) CSP_ELL_CT(float, true, true);
+    else if (mom) CSP_ELL_CT(float, true, false);
+    else CSP_ELL_CT(float, false, false);
   }
+#undef CSP_ELL_CT
 #undef CSP_ELL
   return hipGetLastError();
 }
@@ -154,14 +362,15 @@ hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, const ChebInst* d_in
 // Gershgorin row bound of an explicit matrix (H0 = 0): max_s sum_k |val_sk|,
 // each row summed in k order with plain additions (padding values are 0);
 // one maximum per block.
-__global__ void k_ell_gershgorin(int64_t N, int D, const double* __restrict__ val, double* __restrict__ partial) {
+__global__ void k_ell_gershgorin(int64_t N, int D, const double* __restrict__ val,
+                                 double* __restrict__ partial) {
   __shared__ double red[256];
   double m = 0.0;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < N;
        s += (int64_t)gridDim.x * blockDim.x) {
+    const double* row = val + (s >> 7) * D * 128 + (s & 127);
     double r = 0.0;
-    for (int k = 0; k < D; ++k)
-      r = r + fabs(val[(int64_t)k * N + s]);
+    for (int k = 0; k < D; ++k) r = r + fabs(row[(int64_t)k * 128]);
     m = r > m ? r : m;
   }
   red[threadIdx.x] = m;
@@ -176,9 +385,8 @@ __global__ void k_ell_gershgorin(int64_t N, int D, const double* __restrict__ va
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-hipError_t launch_ell_gershgorin(int64_t N, int D, const int32_t* d_col, const double* d_val,
-                                 double* d_partial, int n_partial, hipStream_t s) {
-  (void)d_col;
+hipError_t launch_ell_gershgorin(int64_t N, int D, const double* d_val, double* d_partial,
+                                 int n_partial, hipStream_t s) {
   hipLaunchKernelGGL(k_ell_gershgorin, dim3(n_partial), dim3(256), 0, s, N, D, d_val, d_partial);
   return hipGetLastError();
 }
