@@ -93,6 +93,14 @@ def long_range_square(L, r_cut, t0=1.0, decay=1.0, W=0.0, seed=0):
     return col, val
 
 
+def long_range_square_positions(L):
+    """Coordinates of the orbitals of long_range_square (orbital s at
+    (s mod L, s div L)) and the periodic box (L, L)."""
+    s = np.arange(L * L)
+    return np.stack([(s % L).astype(np.float64), (s // L).astype(np.float64)], 1), (float(L),
+                                                                                      float(L))
+
+
 def random_symmetric_ell(N, n_pairs, seed=0, diag=True):
     """A random real symmetric matrix of irregular row lengths in ELL form:
     n_pairs off-diagonal pairs (i, j), i != j, drawn uniformly (duplicates

@@ -19,6 +19,10 @@ Contents, each following the passage cited beside it:
   * Hamiltonians given explicitly in ELL form (any matrix density D_H);
   * quasi-eigenstates by forward and backward sequential propagation and
     the sum of Eq. QE_coeff (QE section, QE-Sequential);
+  * site positions, the current operator J = i[H, X], and the electronic
+    conductivity correlation of Eq. dc_corr by sequential propagation
+    (EC-Sequential) and by Chebyshev moments (EC-Concurrent-M), with the
+    conductivity integral of Eq. DC (EC section);
   * band-structure closed forms of clean periodic lattices (any size);
   * DOS from the correlation function -- Sec. III.
 
@@ -97,6 +101,22 @@ def lib():
     L.orc_chebyshev_vectors.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp,
                                         ctypes.c_double, ctypes.c_double, _dp,
                                         ctypes.c_int64, _dp]
+    L.orc_site_positions.restype = None
+    L.orc_site_positions.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _dp, _dp]
+    L.orc_lattice_bond_vectors.restype = ctypes.c_int64
+    L.orc_lattice_bond_vectors.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.orc_current_bonds.restype = None
+    L.orc_current_bonds.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i64p, _dp,
+                                    ctypes.c_double, _dp, _dp]
+    L.orc_current_csr.restype = None
+    L.orc_current_csr.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp, _dp, ctypes.c_double,
+                                  _dp, _dp]
+    L.orc_ec_sequential.restype = ctypes.c_int
+    L.orc_ec_sequential.argtypes = [ctypes.c_int64, _i64p, _i64p, _dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int64, _dp, ctypes.c_int64, _dp,
+                                    _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _dp,
+                                    _i64p]
     _LIB = L
     return L
 
@@ -349,9 +369,11 @@ class SparseLattice:
     (col[s][k], val[s][k]), k < D; col < 0 marks padding.  It is used by
     every propagation routine here exactly as a lattice (CSR rowptr / col /
     val, N), so that general matrices of any density D_H (Sec. II.B) run
-    through the same oracle."""
+    through the same oracle.  pos ([N][2]) and box ((Bx, By), 0 = open) give
+    the orbital coordinates for the current operator; displacements are
+    taken to the nearest periodic image."""
 
-    def __init__(self, col, val):
+    def __init__(self, col, val, pos=None, box=(0.0, 0.0)):
         col = np.asarray(col, dtype=np.int64)
         val = np.asarray(val, dtype=np.float64)
         if col.shape != val.shape or col.ndim != 2:
@@ -364,6 +386,8 @@ class SparseLattice:
         self.rowptr[1:] = np.cumsum(counts)
         self.col = np.ascontiguousarray(col[keep])
         self.val = np.ascontiguousarray(val[keep])
+        self.pos = None if pos is None else np.ascontiguousarray(pos, dtype=np.float64)
+        self.box = (float(box[0]), float(box[1]))
 
     def halfwidth(self, margin=1.025):
         """margin * max_s sum_k |H_sk| (Gershgorin, H0 = 0), the row sum taken
@@ -411,6 +435,145 @@ def quasi_eigenstates(lat, psi0, Nt, energies, Hn=None, H0=0.0, tau=math.pi, eta
         raise RuntimeError("orc_quasi_eigenstates failed (%d)" % rc)
     counters = {"amxsy": int(cnt[0]), "axpy": int(cnt[1])}
     return np.ascontiguousarray(out.transpose(1, 2, 0)), counters
+
+
+# ---------------------------------------------------------------- conductivity
+def positions(lat):
+    """Orbital coordinates [N][2] (conventions in orc_site_positions; for an
+    explicit matrix the ones it was given)."""
+    if isinstance(lat, SparseLattice):
+        if lat.pos is None:
+            raise ValueError("explicit matrix without positions")
+        return lat.pos.copy()
+    x = np.zeros(lat.N)
+    y = np.zeros(lat.N)
+    lib().orc_site_positions(lat.kind, lat.Lx, lat.Ly, _p(x, _dp), _p(y, _dp))
+    return np.stack([x, y], axis=1)
+
+
+def bond_vectors(lat):
+    """r_b - r_a for every bond (a, b) of the lattice, [nbonds][2]."""
+    vx = np.zeros(lat.nbonds)
+    vy = np.zeros(lat.nbonds)
+    n = lib().orc_lattice_bond_vectors(lat.kind, lat.Lx, lat.Ly, lat.px, lat.py,
+                                       _p(vx, _dp), _p(vy, _dp))
+    assert n == lat.nbonds
+    return np.stack([vx, vy], axis=1)
+
+
+def current(lat, alpha, psi):
+    """J_alpha psi with J = i [H, X_alpha] (EC section, hbar = e = 1): from
+    the bond list and bond vectors for a lattice, from the CSR matrix and the
+    coordinates (nearest image) for an explicit matrix.  psi is [N] or [N][R]."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    one = psi.ndim == 1
+    cols = psi[:, None] if one else psi
+    out = np.zeros_like(cols)
+    if isinstance(lat, SparseLattice):
+        x = np.ascontiguousarray(positions(lat)[:, alpha])
+        for r in range(cols.shape[1]):
+            v = np.ascontiguousarray(cols[:, r])
+            o = np.zeros_like(v)
+            lib().orc_current_csr(lat.N, _p(lat.rowptr, _i64p), _p(lat.col, _i64p),
+                                  _p(lat.val, _dp), _p(x, _dp), lat.box[alpha],
+                                  _p(v.view(np.float64), _dp), _p(o.view(np.float64), _dp))
+            out[:, r] = o
+    else:
+        v_a = np.ascontiguousarray(bond_vectors(lat)[:, alpha])
+        for r in range(cols.shape[1]):
+            v = np.ascontiguousarray(cols[:, r])
+            o = np.zeros_like(v)
+            lib().orc_current_bonds(lat.N, lat.nbonds, _p(lat.bond_a, _i64p),
+                                    _p(lat.bond_b, _i64p), _p(v_a, _dp), lat.t,
+                                    _p(v.view(np.float64), _dp), _p(o.view(np.float64), _dp))
+            out[:, r] = o
+    return out[:, 0] if one else out
+
+
+def _ec_inputs(lat, psi0, qe, alpha):
+    psi0 = np.asarray(psi0, dtype=np.complex128)
+    if psi0.ndim == 1:
+        psi0 = psi0[:, None]
+    qe = np.asarray(qe, dtype=np.complex128)
+    if qe.ndim == 2:
+        qe = qe[:, :, None]
+    nE, N, R = qe.shape
+    if psi0.shape != (N, R) or N != lat.N:
+        raise ValueError("shapes: psi0 [N][R], qe [n_E][N][R]")
+    Jpsi = current(lat, alpha, psi0)                           # [N][R]
+    X = np.stack([current(lat, alpha, qe[e]) for e in range(nE)])   # [nE][N][R]
+    nrm = np.abs(np.einsum("sr,esr->er", psi0.conj(), qe))        # [nE][R]
+    return psi0, qe, Jpsi, X, nrm
+
+
+def ec_correlation(lat, psi0, qe, Nt, alpha, Hn=None, H0=0.0, tau=math.pi, eta=1e-14,
+                   margin=1.025):
+    """EC correlation of Eq. dc_corr by EC-Sequential: C(t_j, E) =
+    <psi|J e^{iHt_j} J|Psi(E)> / |<psi|Psi(E)>| = <e^{-iHt_j} J psi|J Psi(E)> /
+    |<psi|Psi(E)>|, t_j = j tau / Hn, j = 0..Nt, propagating J psi step by
+    step.  psi0 is [N][R], qe the quasi-eigenstates [n_E][N][R].  Returns
+    ([n_E][Nt+1][R] complex, counters)."""
+    if Hn is None:
+        Hn = lat.halfwidth(margin)
+    psi0, qe, Jpsi, X, nrm = _ec_inputs(lat, psi0, qe, alpha)
+    nE, N, R = qe.shape
+    Jc = np.ascontiguousarray(Jpsi.T)                              # [R][N]
+    Xc = np.ascontiguousarray(X.transpose(2, 0, 1))                # [R][nE][N]
+    nr = np.ascontiguousarray(nrm.T)                               # [R][nE]
+    out = np.zeros((R, nE, Nt + 1), dtype=np.complex128)
+    cnt = np.zeros(4, dtype=np.int64)
+    rc = lib().orc_ec_sequential(N, _p(lat.rowptr, _i64p), _p(lat.col, _i64p),
+                                 _p(lat.val, _dp), float(H0), float(Hn), R,
+                                 _p(Jc.view(np.float64), _dp), nE, _p(Xc.view(np.float64), _dp),
+                                 _p(nr, _dp), int(Nt), float(tau), float(eta),
+                                 _p(out.view(np.float64), _dp), _p(cnt, _i64p))
+    if rc:
+        raise RuntimeError("orc_ec_sequential failed (%d)" % rc)
+    return (np.ascontiguousarray(out.transpose(1, 2, 0)),
+            {"amxsy": int(cnt[0]), "axpy": int(cnt[1]), "dot": int(cnt[2])})
+
+
+def ec_moments(lat, psi0, qe, Nt, alpha, Hn=None, H0=0.0, tau=math.pi, eta=1e-14, margin=1.025):
+    """EC-Concurrent-M (Eq. dc_mom and the reconstruction after it): moments
+    m_n(E) = <J psi|T_n(H~)|J Psi(E)>, n = 0..N(Nt tau), from the Chebyshev
+    vectors of J psi (no halving: bra and ket differ), then C(t_j, E) =
+    e^{iH0 t_j} sum_{n <= N(j tau)} c_n(j tau)^* m_n(E) / |<psi|Psi(E)>|.
+    Returns ([n_E][Nt+1][R] correlations, [N+1][n_E][R] moments)."""
+    if Hn is None:
+        Hn = lat.halfwidth(margin)
+    psi0, qe, Jpsi, X, nrm = _ec_inputs(lat, psi0, qe, alpha)
+    nE, N, R = qe.shape
+    nmax = truncation(Nt * tau, eta)
+    m = np.zeros((nmax + 1, nE, R), dtype=np.complex128)
+    for r in range(R):
+        phi = chebyshev_vectors(lat, Jpsi[:, r], nmax, Hn, H0)     # [nmax+1][N]
+        m[:, :, r] = phi.conj() @ X[:, :, r].T
+    corr = np.zeros((nE, Nt + 1, R), dtype=np.complex128)
+    tp = tau / Hn
+    for j in range(Nt + 1):
+        nj = 0 if j == 0 else truncation(j * tau, eta)
+        c = cheb_coeffs(j * tau, nj) if j > 0 else np.array([1.0 + 0j])
+        corr[:, j, :] = np.exp(1j * H0 * j * tp) * np.einsum("n,ner->er", c.conj(), m[:nj + 1])
+    return corr / nrm[:, None, :], m
+
+
+def ec_sigma(corr, energies, Hn, tau=math.pi, dos_over_area=None):
+    """Conductivity integral of Eq. DC on the computed times: sigma(E) =
+    D(E)/A * tau_p sum_j w_j Re[e^{-iE t_j} C(t_j, E)], trapezoid weights
+    (1/2 at j = 0 and j = Nt), tau_p = tau / Hn.  corr is [n_E][Nt+1][R];
+    dos_over_area [n_E] (default 1).  Returns [n_E][R]."""
+    corr = np.asarray(corr)
+    nE, T, R = corr.shape
+    E = np.asarray(energies, dtype=np.float64)
+    tp = tau / Hn
+    w = np.ones(T)
+    w[0] = w[-1] = 0.5
+    if T == 1:
+        w[0] = 0.0
+    ph = np.exp(-1j * np.outer(E, np.arange(T) * tp))                # [nE][T]
+    s = tp * np.einsum("t,et,etr->er", w, ph, corr).real
+    dA = np.ones(nE) if dos_over_area is None else np.asarray(dos_over_area, dtype=np.float64)
+    return dA[:, None] * s
 
 
 def chebyshev_vectors(lat, x, nmax, Hn, H0=0.0):

@@ -21,7 +21,11 @@
  *   - moment-based propagation (Sec. II.A) in blocks, and in one block with
  *     the halving of Eq. (cheby_prod) (DOS-Concurrent-M of Sec. III);
  *   - quasi-eigenstates by sequential forward and backward propagation
- *     (QE section, Eq. QE summed as in Eq. QE_coeff).
+ *     (QE section, Eq. QE summed as in Eq. QE_coeff);
+ *   - site positions and bond vectors of the lattices, the current operator
+ *     J_a = i [H, X_a] applied from the bond list or from a CSR matrix with
+ *     positions, and the electronic-conductivity correlation of Eq. dc_corr
+ *     by sequential propagation of J psi (EC-Sequential).
  * Operation counters (amxsy / axpy / dot) follow the definitions of Sec. II.B
  * so that tests can compare them with Tab. (cost).
  *
@@ -646,5 +650,144 @@ int orc_quasi_eigenstates(int64_t n, const int64_t *rowptr, const int64_t *col,
         }
     }
     free(cf); free(cb); free(fw); free(bw); free(nx); free(p0); free(p1);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Geometry and the current operator (EC section).                     */
+/* Chain: site ix at (ix, 0).  Square: (ix, iy).  Honeycomb with unit   */
+/* C-C distance: cell (ix, iy) at ix a1 + iy a2, a1 = (sqrt3, 0),       */
+/* a2 = (sqrt3/2, 3/2); A at the cell origin, B at + d, d = (a1+a2)/3 = */
+/* (sqrt3/2, 1/2), so the three bonds of A(ix,iy) -- to B(ix,iy),       */
+/* B(ix-1,iy), B(ix,iy-1) -- point along d, d - a1, d - a2 (unit        */
+/* length).                                                             */
+/* ------------------------------------------------------------------ */
+void orc_site_positions(int kind, int64_t Lx, int64_t Ly, double *x, double *y)
+{
+    const double r3 = sqrt(3.0);
+    if (kind == 0) {
+        for (int64_t ix = 0; ix < Lx; ++ix) { x[ix] = (double)ix; y[ix] = 0.0; }
+    } else if (kind == 1) {
+        for (int64_t iy = 0; iy < Ly; ++iy)
+            for (int64_t ix = 0; ix < Lx; ++ix) {
+                x[iy * Lx + ix] = (double)ix;
+                y[iy * Lx + ix] = (double)iy;
+            }
+    } else if (kind == 2) {
+        for (int64_t iy = 0; iy < Ly; ++iy)
+            for (int64_t ix = 0; ix < Lx; ++ix) {
+                const int64_t A = 2 * (iy * Lx + ix);
+                x[A] = r3 * (double)ix + 0.5 * r3 * (double)iy;
+                y[A] = 1.5 * (double)iy;
+                x[A + 1] = x[A] + 0.5 * r3;
+                y[A + 1] = y[A] + 0.5;
+            }
+    }
+}
+
+/* Bond vectors r_b - r_a of the bonds (a, b) of orc_lattice_bonds, in the
+ * same order; a bond closing a periodic boundary has the vector of its
+ * kind (the displacement between the two sites as neighbours).  Returns
+ * the number of bonds. */
+int64_t orc_lattice_bond_vectors(int kind, int64_t Lx, int64_t Ly, int px, int py,
+                                 double *vx, double *vy)
+{
+    int64_t nb = 0;
+    const double r3 = sqrt(3.0);
+#define VEC(u, v) do { vx[nb] = (u); vy[nb] = (v); ++nb; } while (0)
+    if (kind == 0) {
+        for (int64_t ix = 0; ix < Lx; ++ix)
+            if (ix + 1 < Lx || px) VEC(1.0, 0.0);
+    } else if (kind == 1) {
+        for (int64_t iy = 0; iy < Ly; ++iy)
+            for (int64_t ix = 0; ix < Lx; ++ix) {
+                if (ix + 1 < Lx || px) VEC(1.0, 0.0);
+                if (iy + 1 < Ly || py) VEC(0.0, 1.0);
+            }
+    } else if (kind == 2) {
+        for (int64_t iy = 0; iy < Ly; ++iy)
+            for (int64_t ix = 0; ix < Lx; ++ix) {
+                VEC(0.5 * r3, 0.5);
+                if (ix >= 1 || px) VEC(-0.5 * r3, 0.5);
+                if (iy >= 1 || py) VEC(0.0, -1.0);
+            }
+    } else {
+        return -1;
+    }
+#undef VEC
+    return nb;
+}
+
+/* out <- J psi for H_ab = t on the bonds (a, b) with bond vectors v (one
+ * Cartesian component): [H, X]_ab = H_ab (x_b - x_a), so J = i [H, X] has
+ * J_ab = i t v and J_ba = -i t v; on-site terms commute with X and drop
+ * out. */
+void orc_current_bonds(int64_t N, int64_t nbonds, const int64_t *a, const int64_t *b,
+                       const double *v, double t, const cplx *psi, cplx *out)
+{
+    for (int64_t s = 0; s < N; ++s) out[s] = 0.0;
+    for (int64_t i = 0; i < nbonds; ++i) {
+        out[a[i]] += I * t * v[i] * psi[b[i]];
+        out[b[i]] += -I * t * v[i] * psi[a[i]];
+    }
+}
+
+/* out <- J psi for a CSR matrix and site coordinates x (one Cartesian
+ * component): (J psi)_s = i sum_p H_{s,col_p} d_p psi_{col_p}, d_p =
+ * x_{col_p} - x_s reduced to the nearest image when box > 0. */
+void orc_current_csr(int64_t N, const int64_t *rowptr, const int64_t *col, const double *val,
+                     const double *x, double box, const cplx *psi, cplx *out)
+{
+    for (int64_t s = 0; s < N; ++s) {
+        cplx acc = 0.0;
+        for (int64_t p = rowptr[s]; p < rowptr[s + 1]; ++p) {
+            double d = x[col[p]] - x[s];
+            if (box > 0.0) d -= box * nearbyint(d / box);
+            acc += I * val[p] * d * psi[col[p]];
+        }
+        out[s] = acc;
+    }
+}
+
+/* EC-Sequential (EC section): for each state r and energy e,
+ *   corr[(r nE + e)(Nt + 1) + j] = <exp(-i H t_j) Jpsi_r | X_{r,e}> / nrm[r nE + e]
+ *                                  (times exp(i H0 t_j)),
+ * t_j = j tau / Hn, with exp(-i (H - H0) tau / Hn) applied step by step by
+ * the Chebyshev expansion c_n(tau); X_{r,e} = J Psi_r(E_e) and nrm the
+ * magnitudes |<psi_r|Psi_r(E_e)>|, all given.  Jpsi is [R][n], X [R][nE][n]. */
+int orc_ec_sequential(int64_t n, const int64_t *rowptr, const int64_t *col, const double *val,
+                      double H0, double Hn, int64_t R, const cplx *Jpsi, int64_t nE,
+                      const cplx *X, const double *nrm, int64_t Nt, double tau, double eta,
+                      cplx *corr, int64_t *counters)
+{
+    orc_ham H = {n, rowptr, col, val, H0, Hn};
+    if (n < 1 || R < 1 || Nt < 0 || nE < 1 || !(Hn > 0.0)) return -1;
+    const int64_t Ntr = orc_truncation(tau, eta);
+    if (Ntr < 1) return -1;
+    cplx *cf = (cplx *)malloc((size_t)(Ntr + 1) * sizeof(cplx));
+    cplx *v = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *nx = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p0 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    cplx *p1 = (cplx *)malloc((size_t)n * sizeof(cplx));
+    if (!cf || !v || !nx || !p0 || !p1) return -2;
+    orc_cheb_coeffs(tau, Ntr, cf);
+    const double tp = tau / Hn;
+    for (int64_t r = 0; r < R; ++r) {
+        memcpy(v, Jpsi + (size_t)r * (size_t)n, (size_t)n * sizeof(cplx));
+        for (int64_t j = 0; j <= Nt; ++j) {
+            if (j > 0) {
+                cheb_apply(&H, cf, Ntr, v, nx, p0, p1, counters);
+                cplx *t = v; v = nx; nx = t;
+            }
+            const cplx ph = cexp(I * H0 * (double)j * tp);
+            for (int64_t e = 0; e < nE; ++e) {
+                const cplx *xe = X + ((size_t)r * (size_t)nE + (size_t)e) * (size_t)n;
+                corr[((size_t)r * (size_t)nE + (size_t)e) * (size_t)(Nt + 1) + (size_t)j] =
+                    ph * dot(n, v, xe) / nrm[r * nE + e];
+                counters[2] += 1;
+            }
+        }
+    }
+    free(cf); free(v); free(nx); free(p0); free(p1);
     return 0;
 }
