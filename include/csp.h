@@ -236,6 +236,17 @@ csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
  * when the device cannot hold the 16 D N bytes of the matrix. */
 csp_status csp_lattice_create_sparse(csp_context *ctx, int64_t N, int32_t D, const int32_t *col,
                                      const double *val, double margin, csp_lattice **out);
+/* Orbital coordinates of an explicit matrix, for the current operator
+ * (EC section): pos [N][2] (x, y) host array, copied; box_x, box_y the
+ * periodic box lengths (0 = open direction); displacements between two
+ * orbitals are taken to the nearest image.  CSP_EUNSUPPORTED for stencil
+ * lattices, whose coordinates are fixed (chain: site ix at (ix, 0); square:
+ * (ix, iy); honeycomb with unit C-C distance: cell (ix, iy) at
+ * ix a1 + iy a2, a1 = (sqrt3, 0), a2 = (sqrt3/2, 3/2), orbital A at the cell
+ * origin and B at + (sqrt3/2, 1/2)); CSP_EINVAL for non-finite values or a
+ * negative box. */
+csp_status csp_lattice_set_positions(csp_lattice *lat, const double *pos, double box_x,
+                                     double box_y);
 csp_status csp_lattice_destroy(csp_lattice *lat);
 csp_status csp_lattice_get_info(const csp_lattice *lat, csp_lattice_info *out);
 
@@ -308,6 +319,38 @@ csp_status csp_quasi_eigenstates(csp_context *ctx, const csp_lattice *lat,
                                  const void *dev_psi0, int32_t R, const csp_params *params,
                                  int32_t n_E, const double *energies, void *dev_qe,
                                  csp_report *rep);
+
+/* Electronic-conductivity correlation (EC section, Eq. dc_corr) by the
+ * moment-based concurrent form EC-Concurrent-M (Eq. dc_mom and the
+ * reconstruction after it): for the R states psi_r (dev_psi0, [N][R]) and
+ * their quasi-eigenstates Psi_r(E_e) (dev_qe, [n_E][N][R], as written by
+ * csp_quasi_eigenstates with the same lattice), direction alpha (0 = x,
+ * 1 = y), t_j = j params->tau_tilde / |H|, j = 0..Nt,
+ *   C_r(t_j, E_e) = <psi_r|J e^{iHt_j} J|Psi_r(E_e)> / |<psi_r|Psi_r(E_e)>|,
+ * J = i [H, X_alpha] (hbar = 1; the charge factor of the current drops out
+ * of C, which is quadratic in J).  Computed as the moments
+ * m_n = <J psi|T_n(H~)|J Psi(E)>, n = 0..N(Nt tau~), of one Chebyshev
+ * recursion of J psi per state (no halving: bra and ket differ) contracted
+ * against all n_E bras at once, then C = e^{iH0 t} sum_n c_n(t~)^* m_n /
+ * |<psi|Psi(E)>| in FP64.  Writes dev_corr [n_E][Nt+1][R] complex128.
+ * dtype of psi0 and qe per params->mode: CSP_FP32_CONC (complex64, moments
+ * on split-bf16 MFMA with FP32 accumulation over slices of orbitals, FP64
+ * across slices; 1 <= n_E <= 32) or CSP_FP64_CONC (complex128, 1 <= n_E
+ * <= 16); 1 <= Nt <= 2^20.  Explicit matrices need
+ * csp_lattice_set_positions first (CSP_EINVAL otherwise).  rep may be NULL. */
+csp_status csp_ec_correlation(csp_context *ctx, const csp_lattice *lat, int32_t alpha,
+                              const void *dev_psi0, int32_t R, const void *dev_qe,
+                              const csp_params *params, int32_t n_E, double *dev_corr,
+                              csp_report *rep);
+
+/* Conductivity of Eq. DC on the computed times: dev_sigma[n_E][R] (FP64,
+ * device) = D(E_e)/A * tau sum_{j=0}^{Nt} w_j Re[e^{-i E_e t_j} C_r(t_j, E_e)],
+ * tau = tau_tilde / halfwidth, t_j = j tau, trapezoid weights (w_0 = w_Nt =
+ * 1/2), from dev_corr [n_E][Nt+1][R] of csp_ec_correlation.  energies and
+ * dos_over_area (D(E)/A per energy; NULL = 1) are host arrays of n_E. */
+csp_status csp_ec_sigma(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t R,
+                        int32_t n_E, const double *energies, double halfwidth,
+                        double tau_tilde, const double *dos_over_area, double *dev_sigma);
 
 /* Many lattices in one set of launches: instance i has lattice lats[i],
  * states dev_psi0[i] ([N_i][R[i]]) and correlations dev_corr[i]

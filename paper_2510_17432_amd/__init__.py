@@ -121,6 +121,7 @@ _sig("csp_context_trim", [_vp])
 _sig("csp_lattice_create", [_vp, _P(LatticeDesc), _P(_vp)])
 _sig("csp_lattice_create_sparse", [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, ctypes.c_double,
                                    _P(_vp)])
+_sig("csp_lattice_set_positions", [_vp, _vp, ctypes.c_double, ctypes.c_double])
 _sig("csp_lattice_destroy", [_vp])
 _sig("csp_lattice_get_info", [_vp, _P(LatticeInfo)])
 _sig("csp_lattice_onsite", [_vp, _vp])
@@ -134,6 +135,11 @@ _sig("csp_chebyshev_coefficients", [_vp, ctypes.c_double, ctypes.c_double, ctype
                                     _P(ctypes.c_int32)])
 _sig("csp_chebyshev_step", [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_int32])
 _sig("csp_propagate", [_vp, _vp, _vp, ctypes.c_int32, _P(Params), _vp, _vp, _P(Report)])
+_sig("csp_ec_correlation", [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _P(Params),
+                           ctypes.c_int32, _vp, _P(Report)])
+_sig("csp_ec_sigma", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                     _P(ctypes.c_double), ctypes.c_double, ctypes.c_double, _P(ctypes.c_double),
+                     _vp])
 _sig("csp_propagate_batch", [_vp, ctypes.c_int32, _P(_vp), _P(_vp), _P(ctypes.c_int32),
                              _P(Params), _P(_vp), _P(Report)])
 _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -273,6 +279,16 @@ class Lattice:
         self._finish(ctx, h)
         return self
 
+    def set_positions(self, pos, box=(0.0, 0.0)):
+        """Orbital coordinates [N][2] of an explicit matrix and its periodic
+        box (0 = open); see csp_lattice_set_positions."""
+        import numpy as np
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        if pos.shape != (self.N, 2):
+            raise ValueError("pos must be [N][2]")
+        _check(_lib.csp_lattice_set_positions(self.handle, pos.ctypes.data_as(_vp),
+                                              float(box[0]), float(box[1])))
+
     def onsite(self):
         import torch
         out = torch.empty(self.N, dtype=torch.float64, device="cuda:%d" % self.ctx.device)
@@ -385,6 +401,38 @@ def csp_quasi_eigenstates(ctx, lat, psi0, params, energies, out=None):
                                       ctypes.byref(params), len(E), Ev, _ptr(out),
                                       ctypes.byref(rep)))
     return out, rep
+
+
+def csp_ec_correlation(ctx, lat, alpha, psi0, qe, params, corr=None):
+    """EC correlation (Eq. dc_corr) by EC-Concurrent-M: [n_E][Nt+1][R]
+    complex128 (device tensor) and the report.  psi0 [N][R], qe [n_E][N][R]
+    (from csp_quasi_eigenstates), dtype per mode."""
+    import torch
+    N, R = psi0.shape
+    nE = qe.shape[0]
+    if tuple(qe.shape) != (nE, N, R) or qe.dtype != psi0.dtype:
+        raise ValueError("qe must be [n_E][N][R] of the dtype of psi0")
+    if corr is None:
+        corr = torch.empty((nE, params.Nt + 1, R), dtype=torch.complex128, device=psi0.device)
+    rep = Report()
+    _check(_lib.csp_ec_correlation(ctx.handle, lat.handle, int(alpha), _ptr(psi0), R, _ptr(qe),
+                                   ctypes.byref(params), nE, _ptr(corr), ctypes.byref(rep)))
+    return corr, rep
+
+
+def csp_ec_sigma(ctx, corr, halfwidth, energies, tau_tilde=math.pi, dos_over_area=None):
+    """Conductivity of Eq. DC from csp_ec_correlation's output: [n_E][R] FP64."""
+    import torch
+    nE, T, R = corr.shape
+    E = [float(e) for e in energies]
+    if len(E) != nE:
+        raise ValueError("one energy per row of corr")
+    Ev = (ctypes.c_double * nE)(*E)
+    dA = None if dos_over_area is None else (ctypes.c_double * nE)(*[float(x) for x in dos_over_area])
+    out = torch.empty((nE, R), dtype=torch.float64, device=corr.device)
+    _check(_lib.csp_ec_sigma(ctx.handle, _ptr(corr), T - 1, R, nE, Ev, float(halfwidth),
+                             float(tau_tilde), dA, _ptr(out)))
+    return out
 
 
 def csp_propagate_batch(ctx, lats, psi0s, params, corrs=None):

@@ -93,6 +93,9 @@ struct csp_lattice {
   double* ell_v64 = nullptr;
   float* ell_v32 = nullptr;
   int ell_D = 0;
+  // orbital coordinates of an explicit matrix ([N][2]) and periodic box
+  double* pos = nullptr;
+  double box[2] = {0.0, 0.0};
 };
 
 namespace {
@@ -372,7 +375,32 @@ extern "C" csp_status csp_lattice_destroy(csp_lattice* L) {
   if (L->ell_col) (void)hipFree(L->ell_col);
   if (L->ell_v64) (void)hipFree(L->ell_v64);
   if (L->ell_v32) (void)hipFree(L->ell_v32);
+  if (L->pos) (void)hipFree(L->pos);
   delete L;
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_lattice_set_positions(csp_lattice* L, const double* pos, double box_x,
+                                                double box_y) {
+  if (!L || !pos) return fail(CSP_EINVAL, "NULL argument");
+  if (L->g.kind != CSP_SPARSE)
+    return fail(CSP_EUNSUPPORTED, "stencil lattices have fixed coordinates");
+  if (!(box_x >= 0.0) || !(box_y >= 0.0) || !std::isfinite(box_x) || !std::isfinite(box_y))
+    return fail(CSP_EINVAL, "box lengths must be finite and >= 0");
+  const int64_t N = L->g.N;
+  for (int64_t i = 0; i < 2 * N; ++i)
+    if (!std::isfinite(pos[i])) return fail(CSP_EINVAL, "coordinate %lld is not finite", (long long)i);
+  DeviceGuard dg(L->ctx->device);
+  if (!L->pos) {
+    if (hipMalloc(&L->pos, sizeof(double) * 2 * N) != hipSuccess) {
+      (void)hipGetLastError();
+      L->pos = nullptr;
+      return fail(CSP_ENOMEM, "coordinates of %lld orbitals", (long long)N);
+    }
+  }
+  HIPCALL(hipMemcpy(L->pos, pos, sizeof(double) * 2 * N, hipMemcpyHostToDevice));
+  L->box[0] = box_x;
+  L->box[1] = box_y;
   return CSP_OK;
 }
 
@@ -1860,6 +1888,279 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     rep->n_passes = 1;
     rep->spmm_steps = kt;
   }
+  return CSP_OK;
+}
+
+// ------------------------------------------------------------------ conductivity
+namespace {
+// J_alpha applied to nvec vectors [nvec][N] of the lattice
+hipError_t apply_current(const csp_lattice* L, bool fp64, int alpha, const void* in, void* out,
+                         int64_t nvec, hipStream_t s) {
+  if (L->g.kind == CSP_SPARSE)
+    return launch_current_ell(fp64, L->g.N, L->ell_D, L->ell_col, L->ell_v64, L->pos,
+                              L->box[alpha], alpha, in, out, nvec, s);
+  return launch_current_stencil(fp64, L->g, L->desc.t, alpha, in, out, nvec, s);
+}
+}  // namespace
+
+extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, int32_t alpha,
+                                         const void* dev_psi0, int32_t R, const void* dev_qe,
+                                         const csp_params* params_in, int32_t n_E,
+                                         double* dev_corr, csp_report* rep) {
+  const double t_start = now_ms();
+  if (!c || !L || !dev_psi0 || !dev_qe || !params_in || !dev_corr)
+    return fail(CSP_EINVAL, "NULL argument");
+  csp_params P;
+  fill_defaults(params_in, &P);
+  if (P.mode != CSP_FP32_CONC && P.mode != CSP_FP64_CONC)
+    return fail(CSP_EINVAL, "the conductivity needs CSP_FP32_CONC or CSP_FP64_CONC");
+  const bool fp64 = P.mode == CSP_FP64_CONC;
+  const int nE = n_E;
+  if (nE < 1 || nE > (fp64 ? 16 : 32)) return fail(CSP_EINVAL, "need 1 <= n_E <= %d", fp64 ? 16 : 32);
+  if (alpha != 0 && alpha != 1) return fail(CSP_EINVAL, "alpha must be 0 (x) or 1 (y)");
+  if (R < 1) return fail(CSP_EINVAL, "R must be >= 1");
+  if (P.Nt < 1 || P.Nt > (1 << 20)) return fail(CSP_EINVAL, "need 1 <= Nt <= 2^20");
+  if (L->ctx->device != c->device) return fail(CSP_EINVAL, "lattice is on another device");
+  if (L->g.kind == CSP_SPARSE && !L->pos)
+    return fail(CSP_EINVAL, "explicit matrix without coordinates (csp_lattice_set_positions)");
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  const int Nt = (int)P.Nt;
+  const int64_t N = L->g.N;
+  const int64_t ldmu = (int64_t)R * nE;
+  const double tau = P.tau_tilde / L->halfwidth;
+
+  struct Free {
+    std::vector<void*> p;
+    ~Free() { for (void* q : p) (void)hipFree(q); }
+  } tmp;
+  auto alloc = [&](void** ptr, size_t bytes) -> csp_status {
+    HIPCALL(hipMalloc(ptr, bytes));
+    tmp.p.push_back(*ptr);
+    return CSP_OK;
+  };
+  // Bessel table for x = j tau~, j = 1..Nt
+  const int nmax_tab = (int)trunc_nmax((double)Nt * P.tau_tilde);
+  const int lda = nmax_tab + 1;
+  double* d_a = nullptr;
+  int32_t* d_ntr = nullptr;
+  CHECK(alloc((void**)&d_a, sizeof(double) * (size_t)Nt * lda));
+  CHECK(alloc((void**)&d_ntr, sizeof(int32_t) * Nt));
+  HIPCALL(launch_bessel(P.tau_tilde, Nt, nmax_tab, P.eta, true, d_a, d_ntr, s));
+  int32_t Nmax = 0;
+  HIPCALL(hipMemcpyAsync(&Nmax, d_ntr + (Nt - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCALL(hipStreamSynchronize(s));
+  if (Nmax < 1) return fail(CSP_ENUMERIC, "no truncation order for x = %g", Nt * P.tau_tilde);
+  double *d_mu = nullptr, *d_G = nullptr, *d_nrm = nullptr;
+  CHECK(alloc((void**)&d_mu, sizeof(double2) * (size_t)(Nmax + 1) * ldmu));
+  CHECK(alloc((void**)&d_G, sizeof(double2) * (size_t)(Nt + 1) * ldmu));
+  CHECK(alloc((void**)&d_nrm, sizeof(double) * ldmu));
+
+  // Column groups, the recursion's launch shape, slices of the moment
+  // contraction (about four workgroups per CU over all columns).
+  std::vector<Group> groups;
+  {
+    int col = 0;
+    for (int Rg : split_columns(R)) {
+      Group g;
+      g.inst = 0;
+      g.col0 = col;
+      g.Rg = Rg;
+      g.M = N * Rg;
+      groups.push_back(g);
+      col += Rg;
+    }
+  }
+  std::vector<ChebInst> sp;
+  for (auto& g : groups) sp.push_back(make_inst(L, g.Rg, fp64));
+  const ChebPlan sp_plan = plan_cheb(sp, fp64, false, c->n_cu, 2, fp64 ? 4 : 8, 0);
+  const int kt = sp_plan.kt;
+  const int64_t target_slices = std::max<int64_t>(1, (int64_t)c->n_cu * 4 / R);
+  const int64_t slice_len = std::max<int64_t>(512, (ceil_div(N, target_slices) + 7) / 8 * 8);
+  const int n_slices = (int)ceil_div(N, slice_len);
+  const size_t psz = fp64 ? sizeof(double2) : sizeof(float2);   // partial element
+
+  int K = std::min(Nmax + 1, 128);
+  size_t cap = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
+  auto ws_need = [&](int K_) {
+    size_t by = 0;
+    for (auto& g : groups)
+      by += align256((size_t)(K_ + kt) * g.stride() * csz) + 2 * align256(g.M * csz) +
+            2 * align256((size_t)nE * g.M * csz) +
+            align256((size_t)g.Rg * n_slices * K_ * 32 * psz);
+    by += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(EcInst) * groups.size()) +
+          align256(sizeof(MomCorrInst));
+    return by;
+  };
+  while (K > 16 && ws_need(K) > cap) K = std::max(16, K - 16);
+  if (ws_need(K) > cap)
+    return fail(CSP_ENOMEM, "conductivity workspace %.2f GB exceeds the cap %.2f GB",
+                ws_need(K) / 1e9, cap / 1e9);
+  const int S = K + kt;
+  CHECK(ws_reserve(c, ws_need(K)));
+  Carver cv(c->ws);
+  std::vector<void*> jpsi(groups.size()), qeg(groups.size()), bra(groups.size()),
+      part(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    g.slots = cv.take((size_t)S * g.stride() * csz);
+    g.psi0g = cv.take(g.M * csz);
+    jpsi[gi] = cv.take(g.M * csz);
+    qeg[gi] = cv.take((size_t)nE * g.M * csz);
+    bra[gi] = cv.take((size_t)nE * g.M * csz);
+    part[gi] = cv.take((size_t)g.Rg * n_slices * K * 32 * psz);
+  }
+  ChebInst* d_inst = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
+  EcInst* d_ei = (EcInst*)cv.take(sizeof(EcInst) * groups.size());
+  MomCorrInst* d_mc = (MomCorrInst*)cv.take(sizeof(MomCorrInst));
+
+  // J psi (recursion start), J Psi(E) (bras), |<psi|Psi(E)>|
+  const int dt = fp64 ? CSP_C128 : CSP_C64;
+  std::vector<EcInst> ei;
+  int wg0 = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    Group& g = groups[gi];
+    HIPCALL(launch_gather_cols(N, R, g.col0, g.Rg, dt, dev_psi0, fp64, g.psi0g, s));
+    HIPCALL(apply_current(L, fp64, alpha, g.psi0g, jpsi[gi], g.Rg, s));
+    for (int e = 0; e < nE; ++e)
+      HIPCALL(launch_gather_cols(N, R, g.col0, g.Rg, dt,
+                                 static_cast<const char*>(dev_qe) + (size_t)e * N * R * csz, fp64,
+                                 static_cast<char*>(qeg[gi]) + (size_t)e * g.M * csz, s));
+    HIPCALL(launch_ec_norm(fp64, N, g.Rg, nE, g.psi0g, qeg[gi], d_nrm, g.col0 * nE, s));
+    HIPCALL(apply_current(L, fp64, alpha, qeg[gi], bra[gi], (int64_t)nE * g.Rg, s));
+    ChebInst& I = sp[gi];
+    I.base = g.slots;
+    I.slot_stride = g.stride();
+    I.src = jpsi[gi];
+    EcInst q{};
+    q.slots = g.slots;
+    q.slot_stride = g.stride();
+    q.bra = bra[gi];
+    q.partial = part[gi];
+    q.N = N;
+    q.slice_len = slice_len;
+    q.Rg = g.Rg;
+    q.n_slices = n_slices;
+    q.wg0 = wg0;
+    q.n_wg = g.Rg * n_slices;
+    q.q0 = g.col0 * nE;
+    wg0 += q.n_wg;
+    ei.push_back(q);
+  }
+  HIPCALL(hipMemcpyAsync(d_inst, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_ei, ei.data(), sizeof(EcInst) * ei.size(), hipMemcpyHostToDevice, s));
+  int rg_max = 1;
+  for (auto& g : groups) rg_max = std::max(rg_max, g.Rg);
+
+  // Recursion launches with a moment contraction after every completed chunk.
+  Profiler prof{c, P.profile != 0};
+  int64_t n_spmm = 0, n_con = 0;
+  const ChebStep st0 = step_args(sp_plan);
+  int produced = 0, n_lo = 0;
+  while (n_lo <= Nmax) {
+    if (produced < Nmax) {
+      ChebStep st = st0;
+      st.nlev = std::min(kt, Nmax - produced);
+      if (produced == 0) {
+        st.first = 1;
+        st.slot_cur = -1;
+        st.copy_slot = 0;
+      } else {
+        st.slot_cur = produced % S;
+        st.slot_prev = (produced - 1) % S;
+      }
+      for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
+      size_t ev = 0;
+      CHECK(prof.begin(0, &ev));
+      HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_inst, sp_plan.runs, st, s));
+      CHECK(prof.end(ev));
+      ++n_spmm;
+      produced += st.nlev;
+    }
+    while (n_lo <= Nmax && (n_lo + K - 1 <= produced || produced == Nmax)) {
+      EcArgs ea{};
+      ea.n_inst = (int)groups.size();
+      ea.n_lo = n_lo;
+      ea.n_cnt = std::min(K, Nmax + 1 - n_lo);
+      ea.S = S;
+      ea.nE = nE;
+      ea.K = K;
+      ea.total_wg = wg0;
+      ea.mu = d_mu;
+      ea.ldmu = ldmu;
+      size_t evc = 0;
+      CHECK(prof.begin(1, &evc));
+      HIPCALL(launch_ec_moments(fp64, d_ei, (int)groups.size(), ea, s));
+      CHECK(prof.end(evc));
+      HIPCALL(launch_ec_mu_finish(fp64, d_ei, (int)groups.size(), rg_max, ea, s));
+      ++n_con;
+      n_lo += ea.n_cnt;
+    }
+  }
+  // G_j = sum_n c_n(j tau~) mu_n (rows 1..Nt), then C = conj(G) e^{iH0 t} / |<psi|Psi>|
+  MomCorrInst mc{};
+  mc.mu = d_mu;
+  mc.corr = d_G;
+  mc.ldc = ldmu;
+  mc.Rg = (int32_t)ldmu;
+  mc.col0 = 0;
+  HIPCALL(hipMemcpyAsync(d_mc, &mc, sizeof(mc), hipMemcpyHostToDevice, s));
+  HIPCALL(launch_mom_corr_only(d_mc, 1, d_a, lda, d_ntr, Nt, 0, (int)ldmu, s));
+  HIPCALL(launch_ec_finish(Nt, R, nE, d_mu, d_G, d_nrm, L->H0, tau, dev_corr, s));
+  HIPCALL(hipStreamSynchronize(s));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    double ms_s = 0, ms_c = 0;
+    CHECK(prof.collect(&ms_s, &ms_c));
+    rep->block_b = Nt;
+    rep->chunk_K = K;
+    rep->n_blocks = 1;
+    rep->n_groups = (int)groups.size();
+    rep->amxsy = Nmax;
+    rep->axpy = 0;
+    rep->dot = (int64_t)(Nmax + 1) * nE;
+    rep->spmm_launches = n_spmm;
+    rep->contract_launches = n_con;
+    rep->ms_total = now_ms() - t_start;
+    rep->ms_spmm = ms_s;
+    rep->ms_contract = ms_c;
+    rep->spmm_bytes = (double)N * R * csz * ((double)Nmax + 2.0 * n_spmm) +
+                      (double)groups.size() * static_bytes(L, fp64) * n_spmm;
+    rep->contract_bytes = (double)N * R * csz * ((double)Nmax + 1.0 + (double)nE * n_con);
+    rep->contract_flops = 8.0 * (double)N * R * (Nmax + 1) * nE * (fp64 ? 1.0 : 3.0);
+    rep->workspace_bytes = c->ws_size;
+    rep->n_passes = 1;
+    rep->spmm_steps = kt;
+  }
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_ec_sigma(csp_context* c, const double* dev_corr, int64_t Nt, int32_t R,
+                                   int32_t n_E, const double* energies, double halfwidth,
+                                   double tau_tilde, const double* dos_over_area,
+                                   double* dev_sigma) {
+  if (!c || !dev_corr || !energies || !dev_sigma) return fail(CSP_EINVAL, "NULL argument");
+  if (Nt < 0 || R < 1 || n_E < 1 || !(halfwidth > 0) || !(tau_tilde > 0))
+    return fail(CSP_EINVAL, "need Nt >= 0, R >= 1, n_E >= 1, |H| > 0, tau~ > 0");
+  DeviceGuard dg(c->device);
+  hipStream_t s = c->stream;
+  std::vector<double> h(2 * (size_t)n_E);
+  for (int e = 0; e < n_E; ++e) {
+    h[e] = energies[e];
+    h[n_E + e] = dos_over_area ? dos_over_area[e] : 1.0;
+    if (!std::isfinite(h[e]) || !std::isfinite(h[n_E + e]))
+      return fail(CSP_EINVAL, "energy or D(E)/A %d is not finite", e);
+  }
+  double* d_h = nullptr;
+  HIPCALL(hipMalloc(&d_h, sizeof(double) * h.size()));
+  hipError_t e = hipMemcpyAsync(d_h, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_ec_sigma(Nt, R, n_E, dev_corr, d_h, d_h + n_E, tau_tilde / halfwidth, dev_sigma, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_h);
+  if (e != hipSuccess) return fail(CSP_EHIP, "conductivity integral: %s", hipGetErrorString(e));
   return CSP_OK;
 }
 

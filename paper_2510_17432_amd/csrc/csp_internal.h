@@ -191,6 +191,51 @@ hipError_t launch_mom_corr(const MomCorrInst* d_mc, int n_inst, int Nk, int halv
                            const double* d_a, int lda, const int32_t* d_ntrunc, int bk,
                            int64_t t0, int rg_max, hipStream_t s);
 
+hipError_t launch_mom_corr_only(const MomCorrInst* d_mc, int n_inst, const double* d_a, int lda,
+                                const int32_t* d_ntrunc, int bk, int64_t t0, int rg_max,
+                                hipStream_t s);
+
+// ------------------------------------------------------------------ conductivity
+// out[v][s] = (J_alpha in[v])[s], J = i [H, X_alpha], for nvec vectors of N
+// complex values (T = float or double): stencil lattices from their bond
+// vectors, explicit matrices from the coordinates pos [N][2] (nearest image
+// in a box of box[alpha] > 0).
+hipError_t launch_current_stencil(bool fp64, const Geom& g, double t, int alpha, const void* in,
+                                  void* out, int64_t nvec, hipStream_t s);
+hipError_t launch_current_ell(bool fp64, int64_t N, int D, const int32_t* ell_col,
+                              const double* ell_v64, const double* pos, double box, int alpha,
+                              const void* in, void* out, int64_t nvec, hipStream_t s);
+// nrm[q0 + c nE + e] = |<psi[c]|qe[e][c]>| for a group (psi [Rg][N], qe [nE][Rg][N])
+hipError_t launch_ec_norm(bool fp64, int64_t N, int Rg, int nE, const void* psi, const void* qe,
+                          double* nrm, int q0, hipStream_t s);
+// Moments of one chunk of orders against the bras of a group (EC-Concurrent-M).
+struct EcInst {
+  const void* slots;        // ring [S][Rg][N]
+  int64_t slot_stride;      // complex values between slots
+  const void* bra;          // J Psi(E): [nE][Rg][N]
+  void* partial;            // [Rg][n_slices][K][32] complex (float or double)
+  int64_t N;
+  int64_t slice_len;        // orbitals per slice (multiple of 8)
+  int32_t Rg, n_slices;
+  int32_t wg0, n_wg;        // workgroups: Rg * n_slices
+  int32_t q0, pad;          // first moment column of the group (col0 * nE)
+};
+struct EcArgs {
+  int32_t n_inst, n_lo, n_cnt, S;
+  int32_t nE, K, total_wg, pad;
+  double* mu;               // [Nmax + 1][ldmu] complex, column q = (col0 + c) nE + e
+  int64_t ldmu;
+};
+hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const EcArgs& a,
+                             hipStream_t s);
+hipError_t launch_ec_mu_finish(bool fp64, const EcInst* d_inst, int n_inst, int rg_max,
+                               const EcArgs& a, hipStream_t s);
+// out[e][j][r] = conj(G_j) e^{i H0 j tau} / nrm, G_0 = mu row 0, G_j (j >= 1) from g
+hipError_t launch_ec_finish(int Nt, int R, int nE, const double* mu, const double* g,
+                            const double* nrm, double H0, double tau, double* out, hipStream_t s);
+hipError_t launch_ec_sigma(int64_t Nt, int R, int nE, const double* corr, const double* E,
+                           const double* dA, double tau, double* sigma, hipStream_t s);
+
 // ------------------------------------------------------------------ contraction
 // Every workgroup of an instance works on one column of the group: column
 // c = (workgroup / wpc) with wpc workgroups per column, so its correlation

@@ -1,0 +1,469 @@
+// Electronic conductivity (EC section) by the moment-based concurrent form
+// EC-Concurrent-M:
+//   C(t, E) = <psi|J e^{iHt} J|Psi(E)> / |<psi|Psi(E)>|        (Eq. dc_corr)
+//   m_n(E)  = <J psi|T_n(H~)|J Psi(E)>                          (Eq. dc_mom)
+//   C(t, E) = e^{iH0 t} sum_n c_n(t~)^* m_n(E) / |<psi|Psi(E)>|
+//   sigma(E) = D(E)/A int_0^T Re[e^{-iEt} C(t, E)] dt             (Eq. DC)
+// with J = i [H, X_alpha].  The recursion of J psi is the ordinary
+// Chebyshev kernel writing into a ring of orders; here are the current
+// operator, the moment contraction of a chunk of orders against all n_E
+// bras J Psi(E) at once, and the FP64 assembly.
+//
+// Moment contraction (FP32 path).  For a chunk of up to 128 orders,
+//   mu_n(E) = <X_E|phi_n> = sum_s conj(X_E[s]) phi_n[s],  X_E = J Psi(E),
+// is a GEMM reducing over the orbitals.  Viewing a complex vector as 2N
+// floats (re, im), Re mu = phi' . X' and Im mu = phi' . Z' with Z = i X
+// (floats (-Xi, Xr)), so both are real GEMMs [orders x 2N] x [2N x energies]
+// on v_mfma_f32_32x32x16_bf16 with split hi + lo bf16 operands (three
+// products each) and FP32 accumulation: A = 32 orders x 8 orbitals (each
+// lane 4 consecutive complex values of one order), B = 8 orbitals x 32
+// energies (4 consecutive values of one bra; Z formed in registers).  A
+// workgroup owns one column and one slice of orbitals, each of its four
+// waves one tile of 32 orders; the FP32 tiles of all slices are summed in
+// FP64 in slice order (no atomics).  The FP64 path forms the same sums with
+// FMAs.  m_n = conj(mu_n).
+#include "csp_internal.h"
+
+namespace csp {
+
+typedef __bf16 ebf16x8 __attribute__((ext_vector_type(8)));
+typedef float ef32x16 __attribute__((ext_vector_type(16)));
+typedef float ef32x2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef __attribute__((address_space(1))) ef32x2 gef2;
+
+// ------------------------------------------------------------------ current operator
+// Bond vectors r_j - r_s of the neighbours of orbital s (stencil
+// conventions of the lattice; a bond closing a periodic boundary has the
+// vector of its kind).  (J psi)_s = i t sum_nb v_alpha psi_j.
+template <typename T>
+__global__ void k_current_stencil(Geom g, double t, int alpha, const T* __restrict__ in,
+                                  T* __restrict__ out, int64_t nvec) {
+  const int64_t total = nvec * g.N;
+  const double r3h = 0.86602540378443864676;   // sqrt(3) / 2
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = i / g.N, s = i - v * g.N;
+    const T* x = in + 2 * v * g.N;
+    int64_t nb[3];
+    double vv[3];
+    int n = 0;
+    auto add = [&](int64_t j, double vx, double vy) {
+      nb[n] = j;
+      vv[n] = alpha == 0 ? vx : vy;
+      ++n;
+    };
+    if (g.kind == CSP_CHAIN) {
+      const int64_t ix = s;
+      if (ix + 1 < g.Lx) add(s + 1, 1.0, 0.0);
+      else if (g.px) add(s + 1 - g.Lx, 1.0, 0.0);
+      if (ix >= 1) add(s - 1, -1.0, 0.0);
+      else if (g.px) add(s + g.Lx - 1, -1.0, 0.0);
+    } else if (g.kind == CSP_SQUARE) {
+      const int64_t iy = s / g.Lx, ix = s - iy * g.Lx;
+      // in-row neighbours, then the rows above and below (at most 3 at a
+      // time in the table: flush the row pair first)
+      double acc_r = 0.0, acc_i = 0.0;
+      auto take = [&](int64_t j, double w) {
+        acc_r += w * (double)x[2 * j];
+        acc_i += w * (double)x[2 * j + 1];
+      };
+      const double wx = alpha == 0 ? 1.0 : 0.0, wy = alpha == 1 ? 1.0 : 0.0;
+      if (ix + 1 < g.Lx) take(s + 1, wx);
+      else if (g.px) take(s + 1 - g.Lx, wx);
+      if (ix >= 1) take(s - 1, -wx);
+      else if (g.px) take(s + g.Lx - 1, -wx);
+      if (iy + 1 < g.Ly) take(s + g.Lx, wy);
+      else if (g.py) take(ix, wy);
+      if (iy >= 1) take(s - g.Lx, -wy);
+      else if (g.py) take(s + (g.Ly - 1) * g.Lx, -wy);
+      // i t (acc_r + i acc_i)
+      out[2 * i] = static_cast<T>(-t * acc_i);
+      out[2 * i + 1] = static_cast<T>(t * acc_r);
+      continue;
+    } else {
+      const int64_t cell = s >> 1, iy = cell / g.Lx, ix = cell - iy * g.Lx;
+      if ((s & 1) == 0) {                          // A
+        add(s + 1, r3h, 0.5);
+        if (ix >= 1) add(2 * (cell - 1) + 1, -r3h, 0.5);
+        else if (g.px) add(2 * (iy * g.Lx + g.Lx - 1) + 1, -r3h, 0.5);
+        if (iy >= 1) add(2 * (cell - g.Lx) + 1, 0.0, -1.0);
+        else if (g.py) add(2 * ((g.Ly - 1) * g.Lx + ix) + 1, 0.0, -1.0);
+      } else {                                     // B
+        add(s - 1, -r3h, -0.5);
+        if (ix + 1 < g.Lx) add(2 * (cell + 1), r3h, -0.5);
+        else if (g.px) add(2 * (iy * g.Lx), r3h, -0.5);
+        if (iy + 1 < g.Ly) add(2 * (cell + g.Lx), 0.0, 1.0);
+        else if (g.py) add(2 * ix, 0.0, 1.0);
+      }
+    }
+    double acc_r = 0.0, acc_i = 0.0;
+    for (int k = 0; k < n; ++k) {
+      acc_r += vv[k] * (double)x[2 * nb[k]];
+      acc_i += vv[k] * (double)x[2 * nb[k] + 1];
+    }
+    out[2 * i] = static_cast<T>(-t * acc_i);
+    out[2 * i + 1] = static_cast<T>(t * acc_r);
+  }
+}
+
+hipError_t launch_current_stencil(bool fp64, const Geom& g, double t, int alpha, const void* in,
+                                  void* out, int64_t nvec, hipStream_t s) {
+  const int64_t total = nvec * g.N;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 65536);
+  if (fp64)
+    hipLaunchKernelGGL(k_current_stencil<double>, dim3(grid), dim3(256), 0, s, g, t, alpha,
+                       static_cast<const double*>(in), static_cast<double*>(out), nvec);
+  else
+    hipLaunchKernelGGL(k_current_stencil<float>, dim3(grid), dim3(256), 0, s, g, t, alpha,
+                       static_cast<const float*>(in), static_cast<float*>(out), nvec);
+  return hipGetLastError();
+}
+
+// Explicit matrix in slices of 128 rows ([N/128][D][128]); padding entries
+// have the value 0.  (J psi)_s = i sum_k H_{s,j_k} (x_{j_k} - x_s) psi_{j_k}.
+template <typename T>
+__global__ void k_current_ell(int64_t N, int D, const int32_t* __restrict__ col,
+                              const double* __restrict__ val, const double* __restrict__ pos,
+                              double box, int alpha, const T* __restrict__ in,
+                              T* __restrict__ out, int64_t nvec) {
+  const int64_t total = nvec * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = i / N, s = i - v * N;
+    const T* x = in + 2 * v * N;
+    const int64_t base = (s >> 7) * (int64_t)D * 128 + (s & 127);
+    const double xs = pos[2 * s + alpha];
+    double acc_r = 0.0, acc_i = 0.0;
+    for (int k = 0; k < D; ++k) {
+      const int64_t j = col[base + (int64_t)k * 128];
+      const double h = val[base + (int64_t)k * 128];
+      double d = pos[2 * j + alpha] - xs;
+      if (box > 0.0) d -= box * rint(d / box);
+      const double w = h * d;
+      acc_r += w * (double)x[2 * j];
+      acc_i += w * (double)x[2 * j + 1];
+    }
+    out[2 * i] = static_cast<T>(-acc_i);
+    out[2 * i + 1] = static_cast<T>(acc_r);
+  }
+}
+
+hipError_t launch_current_ell(bool fp64, int64_t N, int D, const int32_t* ell_col,
+                              const double* ell_v64, const double* pos, double box, int alpha,
+                              const void* in, void* out, int64_t nvec, hipStream_t s) {
+  const int64_t total = nvec * N;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 65536);
+  if (fp64)
+    hipLaunchKernelGGL(k_current_ell<double>, dim3(grid), dim3(256), 0, s, N, D, ell_col,
+                       ell_v64, pos, box, alpha, static_cast<const double*>(in),
+                       static_cast<double*>(out), nvec);
+  else
+    hipLaunchKernelGGL(k_current_ell<float>, dim3(grid), dim3(256), 0, s, N, D, ell_col,
+                       ell_v64, pos, box, alpha, static_cast<const float*>(in),
+                       static_cast<float*>(out), nvec);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ norms
+// Sum of 256 FP64 values of a workgroup: wave butterfly, then the four wave
+// sums in order.
+__device__ inline double block_sum256(double x, double* red) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// workgroup per (c, e)
+template <typename T>
+__global__ __launch_bounds__(256) void k_ec_norm(int64_t N, int Rg, int nE,
+                                                 const T* __restrict__ psi,
+                                                 const T* __restrict__ qe,
+                                                 double* __restrict__ nrm, int q0) {
+  __shared__ double red[4];
+  const int c = blockIdx.x / nE, e = blockIdx.x - c * nE;
+  const T* p = psi + 2 * (int64_t)c * N;
+  const T* q = qe + 2 * ((int64_t)e * Rg + c) * N;
+  double sr = 0.0, si = 0.0;
+  for (int64_t s = threadIdx.x; s < N; s += 256) {
+    const double pr = p[2 * s], pi = p[2 * s + 1], qr = q[2 * s], qi = q[2 * s + 1];
+    sr += pr * qr + pi * qi;
+    si += pr * qi - pi * qr;
+  }
+  sr = block_sum256(sr, red);
+  si = block_sum256(si, red);
+  if (threadIdx.x == 0) nrm[q0 + c * nE + e] = sqrt(sr * sr + si * si);
+}
+
+hipError_t launch_ec_norm(bool fp64, int64_t N, int Rg, int nE, const void* psi, const void* qe,
+                          double* nrm, int q0, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_ec_norm<double>, dim3(Rg * nE), dim3(256), 0, s, N, Rg, nE,
+                       static_cast<const double*>(psi), static_cast<const double*>(qe), nrm, q0);
+  else
+    hipLaunchKernelGGL(k_ec_norm<float>, dim3(Rg * nE), dim3(256), 0, s, N, Rg, nE,
+                       static_cast<const float*>(psi), static_cast<const float*>(qe), nrm, q0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ moments, FP32
+__device__ __forceinline__ void split8(const float (&f)[8], ebf16x8& hi, ebf16x8& lo) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const __bf16 h = static_cast<__bf16>(f[v]);
+    hi[v] = h;
+    lo[v] = static_cast<__bf16>(f[v] - static_cast<float>(h));
+  }
+}
+
+// Workgroup -> (instance, column c, slice); wave w -> orders n_lo + 32 w +
+// 0..31.  Lane (il, h): A = order il, orbitals s + 4h .. s + 4h + 3 of an
+// 8-orbital step; B = bra il (energy), same orbitals; accumulator v =
+// (order 8 (v / 4) + 4 h + v % 4, energy il).
+__global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict__ insts,
+                                                        EcArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int il = lane & 31, h = lane >> 5;
+  if (32 * wave >= a.n_cnt) return;                  // no orders for this wave
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  int ii = 0;
+  while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
+  const EcInst& I = insts[ii];
+  const int64_t wgl = wg - I.wg0;
+  const int c = static_cast<int>(wgl / I.n_slices);
+  const int sl = static_cast<int>(wgl - (int64_t)c * I.n_slices);
+  const int64_t N = I.N;
+  const int64_t s_beg = (int64_t)sl * I.slice_len;
+  const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
+
+  const int rel = 32 * wave + il;                    // A row: order n_lo + rel
+  const bool ov = rel < a.n_cnt;
+  const int e = il;                                  // B column: energy e
+  const bool ev = e < a.nE;
+  const gef2* pa = (const gef2*)(I.slots) +
+                   (int64_t)((a.n_lo + (ov ? rel : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
+  const gef2* pb = (const gef2*)(I.bra) + ((int64_t)(ev ? e : 0) * I.Rg + c) * N;
+
+  ef32x16 accR, accI;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    accR[v] = 0.f;
+    accI[v] = 0.f;
+  }
+  ef32x2 xa[4], xb[4];
+  auto load = [&](int64_t s) {
+    const int64_t o = s + 4 * h;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool in = o + q < s_end;
+      ef32x2 z;
+      z.x = 0.f;
+      z.y = 0.f;
+      xa[q] = (ov && in) ? pa[o + q] : z;
+      xb[q] = (ev && in) ? pb[o + q] : z;
+    }
+  };
+  if (s_beg < s_end) load(s_beg);
+  for (int64_t s = s_beg; s < s_end; s += 8) {
+    float fa[8], fx[8], fz[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      fa[2 * q] = xa[q].x;
+      fa[2 * q + 1] = xa[q].y;
+      fx[2 * q] = xb[q].x;
+      fx[2 * q + 1] = xb[q].y;
+      fz[2 * q] = -xb[q].y;                          // Z = i X
+      fz[2 * q + 1] = xb[q].x;
+    }
+    if (s + 8 < s_end) load(s + 8);
+    ebf16x8 ah, al, xh, xl, zh, zl;
+    split8(fa, ah, al);
+    split8(fx, xh, xl);
+    split8(fz, zh, zl);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh, accR, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh, accR, 0, 0, 0);
+    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl, accR, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zh, accI, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, zh, accI, 0, 0, 0);
+    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zl, accI, 0, 0, 0);
+  }
+  if (ev) {
+    gef2* out = (gef2*)(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * 32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = 32 * wave + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (r < a.n_cnt) {
+        ef32x2 o;
+        o.x = accR[v];
+        o.y = accI[v];
+        out[(int64_t)r * 32 + e] = o;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ moments, FP64
+// Workgroup per (instance, column, slice); for each order of the chunk the
+// 256 threads sum conj(X_E) phi over the slice for all NE energies, then a
+// fixed reduction over the workgroup.
+template <int NE>
+__global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict__ insts,
+                                                        EcArgs a) {
+  __shared__ double red[4];
+  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  int ii = 0;
+  while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
+  const EcInst& I = insts[ii];
+  const int64_t wgl = wg - I.wg0;
+  const int c = static_cast<int>(wgl / I.n_slices);
+  const int sl = static_cast<int>(wgl - (int64_t)c * I.n_slices);
+  const int64_t N = I.N;
+  const int64_t s_beg = (int64_t)sl * I.slice_len;
+  const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
+  const double2* bra = static_cast<const double2*>(I.bra) + (int64_t)c * N;
+  double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * 32;
+  for (int rel = 0; rel < a.n_cnt; ++rel) {
+    const double2* phi = static_cast<const double2*>(I.slots) +
+                         (int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + (int64_t)c * N;
+    double sr[NE], si[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) sr[e] = si[e] = 0.0;
+    for (int64_t s = s_beg + threadIdx.x; s < s_end; s += 256) {
+      const double2 p = phi[s];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        if (e < a.nE) {
+          const double2 x = bra[(int64_t)e * I.Rg * N + s];
+          sr[e] = fma(x.x, p.x, fma(x.y, p.y, sr[e]));
+          si[e] = fma(x.x, p.y, fma(-x.y, p.x, si[e]));
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      if (e < a.nE) {
+        const double r = block_sum256(sr[e], red);
+        const double i = block_sum256(si[e], red);
+        if (threadIdx.x == 0) out[(int64_t)rel * 32 + e] = make_double2(r, i);
+      }
+    }
+  }
+}
+
+// mu[n_lo + rel][q0 + c nE + e] = sum over slices (in order), FP64
+template <typename P>
+__global__ void k_ec_mu_finish(const EcInst* __restrict__ insts, EcArgs a) {
+  const EcInst& I = insts[blockIdx.y];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)a.n_cnt * I.Rg * a.nE;
+  if (t >= per) return;
+  const int rel = static_cast<int>(t / ((int64_t)I.Rg * a.nE));
+  const int rest = static_cast<int>(t - (int64_t)rel * I.Rg * a.nE);
+  const int c = rest / a.nE, e = rest - c * a.nE;
+  const P* part = static_cast<const P*>(I.partial);
+  double sr = 0.0, si = 0.0;
+  for (int sl = 0; sl < I.n_slices; ++sl) {
+    const P* p = part + 2 * ((((int64_t)c * I.n_slices + sl) * a.K + rel) * 32 + e);
+    sr += (double)p[0];
+    si += (double)p[1];
+  }
+  double* m = a.mu + 2 * ((int64_t)(a.n_lo + rel) * a.ldmu + I.q0 + c * a.nE + e);
+  m[0] = sr;
+  m[1] = si;
+}
+
+hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const EcArgs& a,
+                             hipStream_t s) {
+  if (a.n_cnt < 1 || a.n_cnt > a.K || a.K > 128 || a.nE < 1 || a.nE > (fp64 ? 16 : 32))
+    return hipErrorInvalidValue;
+  if (fp64) {
+    int ne = 1;
+    while (ne < a.nE) ne *= 2;
+#define CSP_EC64(NE) \
+  hipLaunchKernelGGL(k_ec_moments_f64<NE>, dim3(a.total_wg), dim3(256), 0, s, d_inst, a)
+    switch (ne) {
+      case 1: CSP_EC64(1); break;
+      case 2: CSP_EC64(2); break;
+      case 4: CSP_EC64(4); break;
+      case 8: CSP_EC64(8); break;
+      default: CSP_EC64(16); break;
+    }
+#undef CSP_EC64
+  } else {
+    hipLaunchKernelGGL(k_ec_moments_f32, dim3(a.total_wg), dim3(256), 0, s, d_inst, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_ec_mu_finish(bool fp64, const EcInst* d_inst, int n_inst, int rg_max,
+                               const EcArgs& a, hipStream_t s) {
+  const int64_t per = (int64_t)a.n_cnt * rg_max * a.nE;
+  const dim3 grid((unsigned)ceil_div(per, 256), n_inst);
+  if (fp64) hipLaunchKernelGGL(k_ec_mu_finish<double>, grid, dim3(256), 0, s, d_inst, a);
+  else hipLaunchKernelGGL(k_ec_mu_finish<float>, grid, dim3(256), 0, s, d_inst, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ assembly
+// out[(e (Nt+1) + j) R + r] = conj(G_j[r nE + e]) e^{i H0 j tau} / nrm[r nE + e]
+__global__ void k_ec_finish(int Nt, int R, int nE, const double2* __restrict__ mu,
+                            const double2* __restrict__ g, const double* __restrict__ nrm,
+                            double H0, double tau, double2* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nE * (Nt + 1) * R;
+  if (t >= total) return;
+  const int r = static_cast<int>(t % R);
+  const int64_t ej = t / R;
+  const int j = static_cast<int>(ej % (Nt + 1));
+  const int e = static_cast<int>(ej / (Nt + 1));
+  const int q = r * nE + e;
+  const double2 G = j == 0 ? mu[q] : g[(int64_t)j * R * nE + q];
+  double sn, cn;
+  sincos(H0 * ((double)j * tau), &sn, &cn);
+  const double inv = 1.0 / nrm[q];
+  // conj(G) (cn + i sn)
+  out[t] = make_double2((G.x * cn + G.y * sn) * inv, (G.x * sn - G.y * cn) * inv);
+}
+
+hipError_t launch_ec_finish(int Nt, int R, int nE, const double* mu, const double* g,
+                            const double* nrm, double H0, double tau, double* out, hipStream_t s) {
+  const int64_t total = (int64_t)nE * (Nt + 1) * R;
+  hipLaunchKernelGGL(k_ec_finish, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Nt, R,
+                     nE, reinterpret_cast<const double2*>(mu), reinterpret_cast<const double2*>(g),
+                     nrm, H0, tau, reinterpret_cast<double2*>(out));
+  return hipGetLastError();
+}
+
+// workgroup per (e, r): tau sum_j w_j Re[e^{-i E t_j} C_j] times D(E)/A
+__global__ __launch_bounds__(256) void k_ec_sigma(int64_t Nt, int R, int nE,
+                                                  const double2* __restrict__ corr,
+                                                  const double* __restrict__ E,
+                                                  const double* __restrict__ dA, double tau,
+                                                  double* __restrict__ sigma) {
+  __shared__ double red[4];
+  const int e = blockIdx.x / R, r = blockIdx.x - e * R;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j <= Nt; j += 256) {
+    const double2 C = corr[((int64_t)e * (Nt + 1) + j) * R + r];
+    double sn, cn;
+    sincos(E[e] * ((double)j * tau), &sn, &cn);
+    const double w = (j == 0 || j == Nt) ? 0.5 : 1.0;
+    acc += w * (C.x * cn + C.y * sn);              // Re[(cn - i sn) C]
+  }
+  acc = block_sum256(acc, red);
+  if (threadIdx.x == 0) sigma[(int64_t)e * R + r] = (Nt == 0 ? 0.0 : dA[e] * tau * acc);
+}
+
+hipError_t launch_ec_sigma(int64_t Nt, int R, int nE, const double* corr, const double* E,
+                           const double* dA, double tau, double* sigma, hipStream_t s) {
+  hipLaunchKernelGGL(k_ec_sigma, dim3(nE * R), dim3(256), 0, s, Nt, R, nE,
+                     reinterpret_cast<const double2*>(corr), E, dA, tau, sigma);
+  return hipGetLastError();
+}
+
+}  // namespace csp

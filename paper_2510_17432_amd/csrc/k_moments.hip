@@ -75,4 +75,15 @@ hipError_t launch_mom_corr(const MomCorrInst* d_mc, int n_inst, int Nk, int halv
   return hipGetLastError();
 }
 
+// Correlations from moments that are already assembled (M.mu filled by the
+// caller): rows t0 + 1 .. t0 + bk of M.corr.
+hipError_t launch_mom_corr_only(const MomCorrInst* d_mc, int n_inst, const double* d_a, int lda,
+                                const int32_t* d_ntrunc, int bk, int64_t t0, int rg_max,
+                                hipStream_t s) {
+  const int64_t nc = (int64_t)bk * rg_max;
+  hipLaunchKernelGGL(k_mom_corr, dim3((unsigned)ceil_div(nc, 256), n_inst), dim3(256), 0, s,
+                     d_mc, d_a, lda, d_ntrunc, bk, t0);
+  return hipGetLastError();
+}
+
 }  // namespace csp

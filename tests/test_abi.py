@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
               "csp_propagate", "csp_propagate_batch", "csp_dos", "csp_last_error",
               "csp_chebyshev_coefficients", "csp_chebyshev_step", "csp_select_block",
               "csp_autotune", "csp_set_tuning", "csp_bandwidth_probe",
-              "csp_quasi_eigenstates", "csp_lattice_create_sparse"):
+              "csp_quasi_eigenstates", "csp_lattice_create_sparse", "csp_ec_correlation",
+              "csp_ec_sigma", "csp_lattice_set_positions"):
         assert n in names
 
 
