@@ -335,8 +335,8 @@ csp_status csp_quasi_eigenstates(csp_context *ctx, const csp_lattice *lat,
  * |<psi|Psi(E)>| in FP64.  Writes dev_corr [n_E][Nt+1][R] complex128.
  * dtype of psi0 and qe per params->mode: CSP_FP32_CONC (complex64, moments
  * on split-bf16 MFMA with FP32 accumulation over slices of orbitals, FP64
- * across slices; 1 <= n_E <= 32) or CSP_FP64_CONC (complex128, 1 <= n_E
- * <= 16); 1 <= Nt <= 2^20.  Explicit matrices need
+ * across slices) or CSP_FP64_CONC (complex128); 1 <= n_E <= 128 (one
+ * recursion serves all energies); 1 <= Nt <= 2^20.  Explicit matrices need
  * csp_lattice_set_positions first (CSP_EINVAL otherwise).  rep may be NULL. */
 csp_status csp_ec_correlation(csp_context *ctx, const csp_lattice *lat, int32_t alpha,
                               const void *dev_psi0, int32_t R, const void *dev_qe,

@@ -1916,7 +1916,9 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
     return fail(CSP_EINVAL, "the conductivity needs CSP_FP32_CONC or CSP_FP64_CONC");
   const bool fp64 = P.mode == CSP_FP64_CONC;
   const int nE = n_E;
-  if (nE < 1 || nE > (fp64 ? 16 : 32)) return fail(CSP_EINVAL, "need 1 <= n_E <= %d", fp64 ? 16 : 32);
+  if (nE < 1 || nE > 128) return fail(CSP_EINVAL, "need 1 <= n_E <= 128");
+  const int e_tile = fp64 ? 16 : 32;
+  const int ldp = (int)ceil_div(nE, e_tile) * e_tile;
   if (alpha != 0 && alpha != 1) return fail(CSP_EINVAL, "alpha must be 0 (x) or 1 (y)");
   if (R < 1) return fail(CSP_EINVAL, "R must be >= 1");
   if (P.Nt < 1 || P.Nt > (1 << 20)) return fail(CSP_EINVAL, "need 1 <= Nt <= 2^20");
@@ -1989,7 +1991,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
     for (auto& g : groups)
       by += align256((size_t)(K_ + kt) * g.stride() * csz) + 2 * align256(g.M * csz) +
             2 * align256((size_t)nE * g.M * csz) +
-            align256((size_t)g.Rg * n_slices * K_ * 32 * psz);
+            align256((size_t)g.Rg * n_slices * K_ * ldp * psz);
     by += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(EcInst) * groups.size()) +
           align256(sizeof(MomCorrInst));
     return by;
@@ -2010,7 +2012,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
     jpsi[gi] = cv.take(g.M * csz);
     qeg[gi] = cv.take((size_t)nE * g.M * csz);
     bra[gi] = cv.take((size_t)nE * g.M * csz);
-    part[gi] = cv.take((size_t)g.Rg * n_slices * K * 32 * psz);
+    part[gi] = cv.take((size_t)g.Rg * n_slices * K * ldp * psz);
   }
   ChebInst* d_inst = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
   EcInst* d_ei = (EcInst*)cv.take(sizeof(EcInst) * groups.size());
@@ -2088,6 +2090,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
       ea.nE = nE;
       ea.K = K;
       ea.total_wg = wg0;
+      ea.ldp = ldp;
       ea.mu = d_mu;
       ea.ldmu = ldmu;
       size_t evc = 0;

@@ -213,7 +213,7 @@ struct EcInst {
   const void* slots;        // ring [S][Rg][N]
   int64_t slot_stride;      // complex values between slots
   const void* bra;          // J Psi(E): [nE][Rg][N]
-  void* partial;            // [Rg][n_slices][K][32] complex (float or double)
+  void* partial;            // [Rg][n_slices][K][ldp] complex (float or double)
   int64_t N;
   int64_t slice_len;        // orbitals per slice (multiple of 8)
   int32_t Rg, n_slices;
@@ -222,7 +222,8 @@ struct EcInst {
 };
 struct EcArgs {
   int32_t n_inst, n_lo, n_cnt, S;
-  int32_t nE, K, total_wg, pad;
+  int32_t nE, K, total_wg;
+  int32_t ldp;              // energies per partial row: n_etiles x tile (32 FP32, 16 FP64)
   double* mu;               // [Nmax + 1][ldmu] complex, column q = (col0 + c) nE + e
   int64_t ldmu;
 };

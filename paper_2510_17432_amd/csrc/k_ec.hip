@@ -18,10 +18,10 @@
 // products each) and FP32 accumulation: A = 32 orders x 8 orbitals (each
 // lane 4 consecutive complex values of one order), B = 8 orbitals x 32
 // energies (4 consecutive values of one bra; Z formed in registers).  A
-// workgroup owns one column and one slice of orbitals, each of its four
-// waves one tile of 32 orders; the FP32 tiles of all slices are summed in
-// FP64 in slice order (no atomics).  The FP64 path forms the same sums with
-// FMAs.  m_n = conj(mu_n).
+// workgroup owns one column, one slice of orbitals and one tile of 32
+// energies (grid y), each of its four waves one tile of 32 orders; the FP32
+// tiles of all slices are summed in FP64 in slice order (no atomics).  The
+// FP64 path forms the same sums with FMAs.  m_n = conj(mu_n).
 #include "csp_internal.h"
 
 namespace csp {
@@ -60,8 +60,7 @@ __global__ void k_current_stencil(Geom g, double t, int alpha, const T* __restri
       else if (g.px) add(s + g.Lx - 1, -1.0, 0.0);
     } else if (g.kind == CSP_SQUARE) {
       const int64_t iy = s / g.Lx, ix = s - iy * g.Lx;
-      // in-row neighbours, then the rows above and below (at most 3 at a
-      // time in the table: flush the row pair first)
+      // four neighbours: summed directly (the table above holds three)
       double acc_r = 0.0, acc_i = 0.0;
       auto take = [&](int64_t j, double w) {
         acc_r += w * (double)x[2 * j];
@@ -241,7 +240,7 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
 
   const int rel = 32 * wave + il;                    // A row: order n_lo + rel
   const bool ov = rel < a.n_cnt;
-  const int e = il;                                  // B column: energy e
+  const int e = 32 * blockIdx.y + il;                // B column: energy e
   const bool ev = e < a.nE;
   const gef2* pa = (const gef2*)(I.slots) +
                    (int64_t)((a.n_lo + (ov ? rel : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
     accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zl, accI, 0, 0, 0);
   }
   if (ev) {
-    gef2* out = (gef2*)(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * 32;
+    gef2* out = (gef2*)(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int r = 32 * wave + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -299,16 +298,17 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
         ef32x2 o;
         o.x = accR[v];
         o.y = accI[v];
-        out[(int64_t)r * 32 + e] = o;
+        out[(int64_t)r * a.ldp + e] = o;
       }
     }
   }
 }
 
 // ------------------------------------------------------------------ moments, FP64
-// Workgroup per (instance, column, slice); for each order of the chunk the
-// 256 threads sum conj(X_E) phi over the slice for all NE energies, then a
-// fixed reduction over the workgroup.
+// Workgroup per (instance, column, slice) and tile of 16 energies (grid y);
+// for each order of the chunk the 256 threads sum conj(X_E) phi over the
+// slice for the NE energies of the tile, then a fixed reduction over the
+// workgroup.
 template <int NE>
 __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict__ insts,
                                                         EcArgs a) {
@@ -323,8 +323,10 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
   const int64_t N = I.N;
   const int64_t s_beg = (int64_t)sl * I.slice_len;
   const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
-  const double2* bra = static_cast<const double2*>(I.bra) + (int64_t)c * N;
-  double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * 32;
+  const int e0 = 16 * blockIdx.y;
+  const int ne = a.nE - e0 < NE ? a.nE - e0 : NE;    // energies of this tile
+  const double2* bra = static_cast<const double2*>(I.bra) + ((int64_t)e0 * I.Rg + c) * N;
+  double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
   for (int rel = 0; rel < a.n_cnt; ++rel) {
     const double2* phi = static_cast<const double2*>(I.slots) +
                          (int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + (int64_t)c * N;
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
       const double2 p = phi[s];
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        if (e < a.nE) {
+        if (e < ne) {
           const double2 x = bra[(int64_t)e * I.Rg * N + s];
           sr[e] = fma(x.x, p.x, fma(x.y, p.y, sr[e]));
           si[e] = fma(x.x, p.y, fma(-x.y, p.x, si[e]));
@@ -344,10 +346,10 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
     }
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
-      if (e < a.nE) {
+      if (e < ne) {
         const double r = block_sum256(sr[e], red);
         const double i = block_sum256(si[e], red);
-        if (threadIdx.x == 0) out[(int64_t)rel * 32 + e] = make_double2(r, i);
+        if (threadIdx.x == 0) out[(int64_t)rel * a.ldp + e0 + e] = make_double2(r, i);
       }
     }
   }
@@ -366,7 +368,7 @@ __global__ void k_ec_mu_finish(const EcInst* __restrict__ insts, EcArgs a) {
   const P* part = static_cast<const P*>(I.partial);
   double sr = 0.0, si = 0.0;
   for (int sl = 0; sl < I.n_slices; ++sl) {
-    const P* p = part + 2 * ((((int64_t)c * I.n_slices + sl) * a.K + rel) * 32 + e);
+    const P* p = part + 2 * ((((int64_t)c * I.n_slices + sl) * a.K + rel) * a.ldp + e);
     sr += (double)p[0];
     si += (double)p[1];
   }
@@ -377,13 +379,15 @@ __global__ void k_ec_mu_finish(const EcInst* __restrict__ insts, EcArgs a) {
 
 hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const EcArgs& a,
                              hipStream_t s) {
-  if (a.n_cnt < 1 || a.n_cnt > a.K || a.K > 128 || a.nE < 1 || a.nE > (fp64 ? 16 : 32))
+  const int tile = fp64 ? 16 : 32;
+  const int n_et = (int)ceil_div(a.nE, tile);
+  if (a.n_cnt < 1 || a.n_cnt > a.K || a.K > 128 || a.nE < 1 || a.ldp != n_et * tile)
     return hipErrorInvalidValue;
   if (fp64) {
     int ne = 1;
-    while (ne < a.nE) ne *= 2;
+    while (ne < std::min(a.nE, 16)) ne *= 2;
 #define CSP_EC64(NE) \
-  hipLaunchKernelGGL(k_ec_moments_f64<NE>, dim3(a.total_wg), dim3(256), 0, s, d_inst, a)
+  hipLaunchKernelGGL(k_ec_moments_f64<NE>, dim3(a.total_wg, n_et), dim3(256), 0, s, d_inst, a)
     switch (ne) {
       case 1: CSP_EC64(1); break;
       case 2: CSP_EC64(2); break;
@@ -393,7 +397,7 @@ hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const 
     }
 #undef CSP_EC64
   } else {
-    hipLaunchKernelGGL(k_ec_moments_f32, dim3(a.total_wg), dim3(256), 0, s, d_inst, a);
+    hipLaunchKernelGGL(k_ec_moments_f32, dim3(a.total_wg, n_et), dim3(256), 0, s, d_inst, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

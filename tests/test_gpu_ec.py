@@ -8,7 +8,8 @@ that the comparison isolates the conductivity path.  Tolerances relative to
 max |C|: complex128 1e-10; complex64 (split-bf16 MFMA moments, FP32
 recursion) 1e-4.  Cases: periodic and open square, honeycomb and chain
 lattices, an explicit long-range matrix with coordinates, one and several
-column groups, one and several chunks of 128 orders, 1..32 energies, both
+column groups, one and several chunks of 128 orders, 1..49 energies (one and
+several energy tiles), both
 directions, a spectral centre H0 != 0.
 """
 import math
@@ -119,10 +120,13 @@ def test_ec_spectral_centre(csp, ctx):
 
 
 def test_ec_many_energies(csp, ctx):
+    # one and several energy tiles (32 per tile in complex64, 16 in complex128)
     spec = dict(kind="honeycomb", Lx=12, Ly=10, t=-2.7, W=1.0, disorder_seed=8)
     g, c = pair(csp, ctx, spec)
     check(csp, ctx, g, c, 2, list(np.linspace(-7.0, 7.0, 32)), 10, 30, 1, "fp32_conc")
+    check(csp, ctx, g, c, 2, list(np.linspace(-7.0, 7.0, 49)), 10, 30, 0, "fp32_conc")
     check(csp, ctx, g, c, 1, list(np.linspace(-7.0, 7.0, 16)), 10, 30, 0, "fp64_conc")
+    check(csp, ctx, g, c, 1, list(np.linspace(-7.0, 7.0, 37)), 10, 30, 1, "fp64_conc")
 
 
 def test_ec_sigma_matches_oracle(csp, ctx):
@@ -159,7 +163,7 @@ def test_ec_errors(csp, ctx):
     p = torch.zeros((64, 1), dtype=torch.complex64, device="cuda:0")
     q = torch.zeros((1, 64, 1), dtype=torch.complex64, device="cuda:0")
     for alpha, kw, qq in ((0, dict(mode="fp64_seq"), q), (2, dict(mode="fp32_conc"), q),
-                          (0, dict(mode="fp32_conc"), q.repeat(33, 1, 1))):
+                          (0, dict(mode="fp32_conc"), q.repeat(129, 1, 1))):
         with pytest.raises(csp.CspError) as e:
             csp.csp_ec_correlation(ctx, g, alpha, p, qq, csp.make_params(10, **kw))
         assert e.value.status == csp.CSP_EINVAL
