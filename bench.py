@@ -70,6 +70,11 @@ def parse():
                          "matrices of density D_H = 61, 121, 233 (4.76 M orbitals, 10 / 5 / 2 "
                          "random columns) by the moment form in complex64 and complex128 "
                          "against the complex128 sequential form timed on a truncated run")
+    ap.add_argument("--ec", action="store_true",
+                    help="instead of the step benchmark: the electronic-conductivity "
+                         "correlation (EC-Concurrent-M, 49 energies, Nt = 1024, 5 random "
+                         "columns) on the D_H = 121 explicit matrix, complex64 and complex128, "
+                         "against the recursion cost of the complex128 sequential form")
     ap.add_argument("--seq-steps", type=int, default=8,
                     help="time steps of the truncated complex128 sequential run "
                          "(--dos-1e9, --dense-dh)")
@@ -319,6 +324,121 @@ def dense_dh(a):
     print(json.dumps(out), flush=True)
 
 
+def ec_bench(a):
+    """Electronic conductivity (EC section, Fig. acc_dc configuration: D_H =
+    120, Nt = 1024, N_E = 49, 5 states) on the long-range stand-in for the
+    4.76 M-atom supercell: EC-Concurrent-M in complex64 and complex128 from
+    the same quasi-eigenstates (complex64 QE-Concurrent-E), the conductivity
+    integral of each, and the complex128 sequential form's recursion cost
+    (time steps of 20 Chebyshev steps each, timed on two truncated runs and
+    scaled to Nt; its n_E dot products per time step are not counted, so the
+    speedup against it is a lower bound)."""
+    import numpy as np
+    import torch
+    import paper_2510_17432_amd as csp
+    w = csp_inputs.LONG_RANGE2182
+    case = w["cases"][1]
+    Nt, nE, R = 1024, 49, case["R"]
+    ctx = csp.Context(0)
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    col, val = csp_inputs.long_range_square(w["L"], case["r_cut"], w["t0"], w["decay"], w["W"],
+                                            w["seed"])
+    lat = csp.Lattice.sparse(ctx, col, val)
+    pos, box = csp_inputs.long_range_square_positions(w["L"])
+    lat.set_positions(pos, box)
+    N, D = col.shape
+    del col, val, pos
+    Hn = lat.halfwidth
+    E = list(np.linspace(-0.8, 0.8, nE) * Hn / 1.025)
+    log("EC: D_H=%d N=%d R=%d n_E=%d Nt=%d |H|=%.6f (set-up %.1f s)" % (
+        D, N, R, nE, Nt, Hn, time.perf_counter() - t0))
+    psi64 = torch.empty((N, R), dtype=torch.complex128, device=dev)
+    csp.csp_states_random_phase(ctx, psi64, R, w["seed_states"])
+    psi32 = psi64.to(torch.complex64)
+    # quasi-eigenstates (complex64, tiles of 32 energies)
+    t = time.perf_counter()
+    qe32 = torch.empty((nE, N, R), dtype=torch.complex64, device=dev)
+    p_qe = csp.make_params(Nt, mode="fp32_conc")
+    for e0 in range(0, nE, 32):
+        e1 = min(nE, e0 + 32)
+        q, _ = csp.csp_quasi_eigenstates(ctx, lat, psi32, p_qe, E[e0:e1])
+        qe32[e0:e1] = q
+        del q
+    torch.cuda.synchronize()
+    t_qe = time.perf_counter() - t
+    log("  quasi-eigenstates: %.1f s" % t_qe)
+    ctx.trim()
+    torch.cuda.empty_cache()
+
+    def run_ec(mode, psi, qe):
+        params = csp.make_params(Nt, mode=mode, profile=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        corr, rep = csp.csp_ec_correlation(ctx, lat, 0, psi, qe, params)
+        sig = csp.csp_ec_sigma(ctx, corr, Hn, E)
+        torch.cuda.synchronize()
+        return corr, sig, time.perf_counter() - t, rep
+
+    c32, s32, t32, r32 = run_ec("fp32_conc", psi32, qe32)
+    log("  EC-Concurrent-M complex64: %.2f s (%d orders, %d chunks)" % (t32, r32.amxsy,
+                                                                       r32.contract_launches))
+    c32h, s32h = c32.cpu().numpy(), s32.cpu().numpy()
+    del c32, s32
+    ctx.trim()
+    torch.cuda.empty_cache()
+    qe64 = qe32.to(torch.complex128)
+    del qe32
+    c64, s64, t64, r64 = run_ec("fp64_conc", psi64, qe64)
+    log("  EC-Concurrent-M complex128: %.2f s" % t64)
+    c64h, s64h = c64.cpu().numpy(), s64.cpu().numpy()
+    del c64, s64, qe64
+    ctx.trim()
+    torch.cuda.empty_cache()
+    # complex128 sequential recursion cost (cost independent of the vector)
+    s1, s2 = a.seq_steps, 3 * a.seq_steps
+    tt = []
+    for steps in (s1, s2):
+        params = csp.make_params(steps, mode="fp64_seq", assembly=csp.CSP_ASSEMBLE_MOMENTS)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        csp.csp_propagate(ctx, lat, psi64, params)
+        torch.cuda.synchronize()
+        tt.append(time.perf_counter() - t)
+    per_step = (tt[1] - tt[0]) / (s2 - s1)
+    t_seq = tt[0] + per_step * (Nt - s1)
+    log("  complex128 sequential recursion: %d steps %.2f s, %d steps %.2f s -> %.0f s for %d" %
+        (s1, tt[0], s2, tt[1], t_seq, Nt))
+    eps = float(np.max(np.abs(c32h - c64h)) / np.max(np.abs(c64h)))
+    sig_err = float(np.max(np.abs(s32h - s64h)) / np.max(np.abs(s64h)))
+
+    def kern(rep):
+        return {"recursion_ms_per_launch": rep.ms_spmm / max(1, rep.spmm_launches),
+                "recursion_alg_GBps": rep.spmm_bytes / max(1e-9, rep.ms_spmm) / 1e6,
+                "moments_ms_per_chunk": rep.ms_contract / max(1, rep.contract_launches),
+                "moments_alg_GBps": rep.contract_bytes / max(1e-9, rep.ms_contract) / 1e6,
+                "moments_TFLOPs": rep.contract_flops / max(1e-9, rep.ms_contract) / 1e9,
+                "orders": rep.amxsy, "chunks": rep.contract_launches}
+
+    out = {"workload": "EC on the long-range square lattice %dx%d (N=%d, D_H=%d), %d random "
+                       "columns (seed %d), n_E=%d energies in +-0.8 |H|/1.025, Nt=%d, direction x"
+                       % (w["L"], w["L"], N, D, R, w["seed_states"], nE, Nt),
+           "quasi_eigenstates_s": t_qe,
+           "fp32_ec_concurrent_m_s": t32, "fp64_ec_concurrent_m_s": t64,
+           "fp64_sequential_recursion_s_extrapolated": t_seq,
+           "fp64_sequential_sample": "%d and %d of %d steps in %.2f s and %.2f s" % (
+               s1, s2, Nt, tt[0], tt[1]),
+           "speedup_fp64_vs_fp64_sequential_lower_bound": t_seq / t64,
+           "speedup_fp32_vs_fp64_sequential_lower_bound": t_seq / t32,
+           "fp32_corr_rel_err": eps, "fp32_sigma_rel_err": sig_err,
+           "fp32_kernels": kern(r32), "fp64_kernels": kern(r64)}
+    log("  speedup vs sequential recursion: complex128 %.1fx, complex64 %.1fx; sigma rel err "
+        "%.2e" % (t_seq / t64, t_seq / t32, sig_err))
+    lat.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -330,6 +450,9 @@ def main():
         return
     if a.dense_dh:
         dense_dh(a)
+        return
+    if a.ec:
+        ec_bench(a)
         return
     import numpy as np
     import torch

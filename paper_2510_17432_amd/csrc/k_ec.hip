@@ -19,9 +19,13 @@
 // lane 4 consecutive complex values of one order), B = 8 orbitals x 32
 // energies (4 consecutive values of one bra; Z formed in registers).  A
 // workgroup owns one column, one slice of orbitals and one tile of 32
-// energies (grid y), each of its four waves one tile of 32 orders; the FP32
-// tiles of all slices are summed in FP64 in slice order (no atomics).  The
-// FP64 path forms the same sums with FMAs.  m_n = conj(mu_n).
+// energies (grid y); it stages 32-orbital tiles of the chunk's orders and
+// of the bras in LDS with coalesced loads (one ring slot per order, so a
+// load instruction whose lanes each read a different order would touch 32
+// pages), and each of its four waves multiplies one tile of 32 orders.
+// The FP32 tiles of all slices are summed in FP64 in slice order (no
+// atomics).  The FP64 path stages the same tiles and forms the sums with
+// FMAs.  m_n = conj(mu_n).
 #include "csp_internal.h"
 
 namespace csp {
@@ -217,16 +221,42 @@ __device__ __forceinline__ void split8(const float (&f)[8], ebf16x8& hi, ebf16x8
   }
 }
 
-// Workgroup -> (instance, column c, slice); wave w -> orders n_lo + 32 w +
-// 0..31.  Lane (il, h): A = order il, orbitals s + 4h .. s + 4h + 3 of an
-// 8-orbital step; B = bra il (energy), same orbitals; accumulator v =
-// (order 8 (v / 4) + 4 h + v % 4, energy il).
+typedef float ef32x4 __attribute__((ext_vector_type(4), aligned(8)));
+typedef __attribute__((address_space(1))) ef32x4 gef4;
+typedef float lf32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kEcOrb = 32;           // orbitals per staged tile
+constexpr int kEcLds = 2 * kEcOrb + 8;   // floats per LDS row (padded)
+
+// Two complex values (orbitals o, o + 1) of a column, zeros past s_end.
+__device__ __forceinline__ ef32x4 ld2c(const gef2* p, int64_t o, int64_t s_end, bool ok) {
+  ef32x4 r = {0.f, 0.f, 0.f, 0.f};
+  if (ok && o + 1 < s_end) {
+    r = *reinterpret_cast<const gef4*>(p + o);
+  } else if (ok && o < s_end) {
+    const ef32x2 z = p[o];
+    r.x = z.x;
+    r.y = z.y;
+  }
+  return r;
+}
+
+// Workgroup -> (instance, column c, slice) and tile of 32 energies
+// (grid y).  Per step of 32 orbitals the workgroup stages the 128 orders x
+// 32 orbitals of the chunk and the 32 bras x 32 orbitals in LDS with
+// coalesced loads (16 lanes read one 256-byte row), then wave w multiplies
+// orders 32 w .. 32 w + 31 by the 32 bras in four MFMA k-steps of 8
+// orbitals.  MFMA lane (il, h): A = order il, B = bra il, floats
+// 16 kk + 8 h .. + 7 of the staged row (orbitals 8 kk + 4 h .. + 3);
+// accumulator v = (order 8 (v / 4) + 4 h + v % 4, energy il).
 __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict__ insts,
                                                         EcArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  __shared__ __align__(16) float sa[128 * kEcLds];
+  __shared__ __align__(16) float sb[32 * kEcLds];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(tid >> 6));
   const int il = lane & 31, h = lane >> 5;
-  if (32 * wave >= a.n_cnt) return;                  // no orders for this wave
   const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
@@ -237,14 +267,35 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
   const int64_t N = I.N;
   const int64_t s_beg = (int64_t)sl * I.slice_len;
   const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
+  const int e_tile = 32 * blockIdx.y;
 
-  const int rel = 32 * wave + il;                    // A row: order n_lo + rel
-  const bool ov = rel < a.n_cnt;
-  const int e = 32 * blockIdx.y + il;                // B column: energy e
-  const bool ev = e < a.nE;
-  const gef2* pa = (const gef2*)(I.slots) +
-                   (int64_t)((a.n_lo + (ov ? rel : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
-  const gef2* pb = (const gef2*)(I.bra) + ((int64_t)(ev ? e : 0) * I.Rg + c) * N;
+  // staging roles: row (lane >> 4) of each group of four, 2 orbitals at 2 (lane & 15)
+  const int sub = lane >> 4, ch = lane & 15;
+  const gef2* arow[8];
+  bool aok[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int r = wave * 32 + j * 4 + sub;
+    aok[j] = r < a.n_cnt;
+    arow[j] = (const gef2*)(I.slots) +
+              (int64_t)((a.n_lo + (aok[j] ? r : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
+  }
+  const gef2* brow[2];
+  bool bok[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int e = e_tile + (wave * 2 + j) * 4 + sub;
+    bok[j] = e < a.nE;
+    brow[j] = (const gef2*)(I.bra) + ((int64_t)(bok[j] ? e : 0) * I.Rg + c) * N;
+  }
+  ef32x4 ra[8], rb[2];
+  auto fetch = [&](int64_t s) {
+    const int64_t o = s + 2 * ch;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ra[j] = ld2c(arow[j], o, s_end, aok[j]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) rb[j] = ld2c(brow[j], o, s_end, bok[j]);
+  };
 
   ef32x16 accR, accI;
 #pragma unroll
@@ -252,44 +303,52 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
     accR[v] = 0.f;
     accI[v] = 0.f;
   }
-  ef32x2 xa[4], xb[4];
-  auto load = [&](int64_t s) {
-    const int64_t o = s + 4 * h;
+  const bool active = 32 * wave < a.n_cnt;           // wave-uniform
+  if (s_beg < s_end) fetch(s_beg);
+  for (int64_t s = s_beg; s < s_end; s += kEcOrb) {
+    __syncthreads();                                 // previous tile consumed
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool in = o + q < s_end;
-      ef32x2 z;
-      z.x = 0.f;
-      z.y = 0.f;
-      xa[q] = (ov && in) ? pa[o + q] : z;
-      xb[q] = (ev && in) ? pb[o + q] : z;
+    for (int j = 0; j < 8; ++j) {
+      const ef32x4 v = ra[j];
+      *reinterpret_cast<lf32x4*>(&sa[(wave * 32 + j * 4 + sub) * kEcLds + 4 * ch]) =
+          lf32x4{v.x, v.y, v.z, v.w};
     }
-  };
-  if (s_beg < s_end) load(s_beg);
-  for (int64_t s = s_beg; s < s_end; s += 8) {
-    float fa[8], fx[8], fz[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      fa[2 * q] = xa[q].x;
-      fa[2 * q + 1] = xa[q].y;
-      fx[2 * q] = xb[q].x;
-      fx[2 * q + 1] = xb[q].y;
-      fz[2 * q] = -xb[q].y;                          // Z = i X
-      fz[2 * q + 1] = xb[q].x;
+    for (int j = 0; j < 2; ++j) {
+      const ef32x4 v = rb[j];
+      *reinterpret_cast<lf32x4*>(&sb[((wave * 2 + j) * 4 + sub) * kEcLds + 4 * ch]) =
+          lf32x4{v.x, v.y, v.z, v.w};
     }
-    if (s + 8 < s_end) load(s + 8);
-    ebf16x8 ah, al, xh, xl, zh, zl;
-    split8(fa, ah, al);
-    split8(fx, xh, xl);
-    split8(fz, zh, zl);
-    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh, accR, 0, 0, 0);
-    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh, accR, 0, 0, 0);
-    accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl, accR, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zh, accI, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, zh, accI, 0, 0, 0);
-    accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zl, accI, 0, 0, 0);
+    __syncthreads();
+    if (s + kEcOrb < s_end) fetch(s + kEcOrb);
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const float* pa = &sa[(wave * 32 + il) * kEcLds + 16 * kk + 8 * h];
+        const float* pb = &sb[il * kEcLds + 16 * kk + 8 * h];
+        const lf32x4 a0 = *reinterpret_cast<const lf32x4*>(pa);
+        const lf32x4 a1 = *reinterpret_cast<const lf32x4*>(pa + 4);
+        const lf32x4 b0 = *reinterpret_cast<const lf32x4*>(pb);
+        const lf32x4 b1 = *reinterpret_cast<const lf32x4*>(pb + 4);
+        const float fa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const float fx[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        // Z = i X: (-Xi, Xr) per complex value
+        const float fz[8] = {-b0.y, b0.x, -b0.w, b0.z, -b1.y, b1.x, -b1.w, b1.z};
+        ebf16x8 ah, al, xh, xl, zh, zl;
+        split8(fa, ah, al);
+        split8(fx, xh, xl);
+        split8(fz, zh, zl);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zh, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, zh, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, zl, accI, 0, 0, 0);
+      }
+    }
   }
-  if (ev) {
+  const int e = e_tile + il;
+  if (active && e < a.nE) {
     gef2* out = (gef2*)(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -305,14 +364,19 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
 }
 
 // ------------------------------------------------------------------ moments, FP64
-// Workgroup per (instance, column, slice) and tile of 16 energies (grid y);
-// for each order of the chunk the 256 threads sum conj(X_E) phi over the
-// slice for the NE energies of the tile, then a fixed reduction over the
-// workgroup.
+// Workgroup per (instance, column, slice) and tile of 16 energies (grid y).
+// Per step of 32 orbitals the chunk's 128 orders and the 16 bras are staged
+// in LDS with coalesced loads (32 lanes read one 512-byte row); thread t
+// accumulates energy t % 16 against orders t / 16 + 16 p, p = 0..7, with
+// FMAs, reading each bra value once for its eight orders.
+constexpr int kEc64Row = 33;         // complex values per LDS row (padded)
+
 template <int NE>
 __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict__ insts,
                                                         EcArgs a) {
-  __shared__ double red[4];
+  __shared__ double2 sa[128 * kEc64Row];
+  __shared__ double2 sb[16 * kEc64Row];
+  const int tid = threadIdx.x;
   const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
@@ -324,33 +388,66 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
   const int64_t s_beg = (int64_t)sl * I.slice_len;
   const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
   const int e0 = 16 * blockIdx.y;
-  const int ne = a.nE - e0 < NE ? a.nE - e0 : NE;    // energies of this tile
-  const double2* bra = static_cast<const double2*>(I.bra) + ((int64_t)e0 * I.Rg + c) * N;
-  double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
-  for (int rel = 0; rel < a.n_cnt; ++rel) {
-    const double2* phi = static_cast<const double2*>(I.slots) +
-                         (int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + (int64_t)c * N;
-    double sr[NE], si[NE];
+  const int col = tid & 31, rsub = tid >> 5;        // staging: orbital col of row 8 j + rsub
+
+  const double2* arow[16];
+  bool aok[16];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) sr[e] = si[e] = 0.0;
-    for (int64_t s = s_beg + threadIdx.x; s < s_end; s += 256) {
-      const double2 p = phi[s];
+  for (int j = 0; j < 16; ++j) {
+    const int r = 8 * j + rsub;
+    aok[j] = r < a.n_cnt;
+    arow[j] = static_cast<const double2*>(I.slots) +
+              (int64_t)((a.n_lo + (aok[j] ? r : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
+  }
+  const double2* brow[2];
+  bool bok[2];
 #pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        if (e < ne) {
-          const double2 x = bra[(int64_t)e * I.Rg * N + s];
-          sr[e] = fma(x.x, p.x, fma(x.y, p.y, sr[e]));
-          si[e] = fma(x.x, p.y, fma(-x.y, p.x, si[e]));
+  for (int j = 0; j < 2; ++j) {
+    const int e = e0 + 8 * j + rsub;
+    bok[j] = e < a.nE && 8 * j + rsub < NE;
+    brow[j] = static_cast<const double2*>(I.bra) + ((int64_t)(bok[j] ? e : 0) * I.Rg + c) * N;
+  }
+  double2 ra[16], rb[2];
+  auto fetch = [&](int64_t s) {
+    const int64_t o = s + col;
+    const bool in = o < s_end;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ra[j] = (aok[j] && in) ? arow[j][o] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) rb[j] = (bok[j] && in) ? brow[j][o] : make_double2(0.0, 0.0);
+  };
+
+  const int e = tid & 15, p0 = tid >> 4;
+  double sr[8], si[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) sr[p] = si[p] = 0.0;
+  if (s_beg < s_end) fetch(s_beg);
+  for (int64_t s = s_beg; s < s_end; s += 32) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sa[(8 * j + rsub) * kEc64Row + col] = ra[j];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) sb[(8 * j + rsub) * kEc64Row + col] = rb[j];
+    __syncthreads();
+    if (s + 32 < s_end) fetch(s + 32);
+    if (e < NE) {
+      for (int o = 0; o < 32; ++o) {
+        const double2 x = sb[e * kEc64Row + o];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const double2 f = sa[(p0 + 16 * p) * kEc64Row + o];
+          sr[p] = fma(x.x, f.x, fma(x.y, f.y, sr[p]));
+          si[p] = fma(x.x, f.y, fma(-x.y, f.x, si[p]));
         }
       }
     }
+  }
+  if (e < NE && e0 + e < a.nE) {
+    double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      if (e < ne) {
-        const double r = block_sum256(sr[e], red);
-        const double i = block_sum256(si[e], red);
-        if (threadIdx.x == 0) out[(int64_t)rel * a.ldp + e0 + e] = make_double2(r, i);
-      }
+    for (int p = 0; p < 8; ++p) {
+      const int r = p0 + 16 * p;
+      if (r < a.n_cnt) out[(int64_t)r * a.ldp + e0 + e] = make_double2(sr[p], si[p]);
     }
   }
 }
