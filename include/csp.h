@@ -314,7 +314,15 @@ csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *d
  * recursion, split-bf16 MFMA accumulation, 1 <= n_E <= 32) or CSP_FP64_CONC
  * (complex128, 1 <= n_E <= 16); 1 <= Nt <= 2^20.  Coefficients are FP64 on
  * the GPU.  CSP_ENOMEM when a 16-order ring of all columns with the n_E
- * accumulated states does not fit (call per column then).  rep may be NULL. */
+ * accumulated states does not fit (call per column then).  rep may be NULL.
+ * params->block_b >= 1 selects the state-based form QE-Concurrent-S
+ * instead: time blocks of b steps carry psi(+-t_kb) forward and backward
+ * (Eq. TE per block, as in the propagation), and each block adds
+ * sum_n C_n^k(E) T_n s_k^+ + conj(C_n^k(E)) T_n s_k^- with the complex block
+ * coefficients C_n^k(E) = tau sum_{j=1..b_k} c_n(j tau~) e^{iE' t_{kb+j}} (the
+ * j = 0 term tau psi0 on the first block, half on each side), the next
+ * carried states being one more row of the same contraction; the same
+ * result up to rounding, with 1 <= n_E <= 31 (FP32) or 15 (FP64). */
 csp_status csp_quasi_eigenstates(csp_context *ctx, const csp_lattice *lat,
                                  const void *dev_psi0, int32_t R, const csp_params *params,
                                  int32_t n_E, const double *energies, void *dev_qe,

@@ -1658,6 +1658,231 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
 // N(Nt tau~) are produced by the recursion into a ring of K + kt slots and
 // contracted chunk by chunk with the real coefficients C_n(E) of Eq.
 // QE_coeff into one accumulated state per energy and column.
+namespace {
+// QE-Concurrent-S: forward and backward carried states per column, time
+// blocks of b steps; per block one recursion of each carried state into a
+// ring and contractions with the block's complex coefficients (energies and
+// the next carried state as one more row).  Arguments validated by the caller.
+csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_psi0, int32_t R,
+                          const csp_params& P, int nE, const double* energies, void* dev_qe,
+                          csp_report* rep, double t_start) {
+  const bool fp64 = P.mode == CSP_FP64_CONC;
+  hipStream_t s = c->stream;
+  const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
+  const int Nt = (int)P.Nt;
+  const int b = (int)std::min<int64_t>(P.block_b, P.Nt);
+  const int64_t N = L->g.N;
+  const int rows = nE + 1;
+  const double tau = P.tau_tilde / L->halfwidth;
+  struct Free {
+    std::vector<void*> p;
+    ~Free() { for (void* q : p) (void)hipFree(q); }
+  } tmp;
+  auto alloc = [&](void** ptr, size_t bytes) -> csp_status {
+    HIPCALL(hipMalloc(ptr, bytes));
+    tmp.p.push_back(*ptr);
+    return CSP_OK;
+  };
+  // Bessel table for x = j tau~, j = 1..b
+  const int nmax_tab = (int)trunc_nmax((double)b * P.tau_tilde);
+  const int lda = nmax_tab + 1;
+  double *d_a = nullptr, *d_E = nullptr, *d_C = nullptr;
+  int32_t* d_ntr = nullptr;
+  CHECK(alloc((void**)&d_a, sizeof(double) * (size_t)b * lda));
+  CHECK(alloc((void**)&d_ntr, sizeof(int32_t) * b));
+  HIPCALL(launch_bessel(P.tau_tilde, b, nmax_tab, P.eta, true, d_a, d_ntr, s));
+  std::vector<int32_t> ntr(b);
+  HIPCALL(hipMemcpyAsync(ntr.data(), d_ntr, sizeof(int32_t) * b, hipMemcpyDeviceToHost, s));
+  HIPCALL(hipStreamSynchronize(s));
+  const int NkMax = ntr[b - 1];
+  if (NkMax < 1) return fail(CSP_ENUMERIC, "no truncation order for x = %g", b * P.tau_tilde);
+  CHECK(alloc((void**)&d_E, sizeof(double) * nE));
+  CHECK(alloc((void**)&d_C, sizeof(double2) * (size_t)rows * (NkMax + 1)));
+  HIPCALL(hipMemcpyAsync(d_E, energies, sizeof(double) * nE, hipMemcpyHostToDevice, s));
+
+  // instances: forward and backward of every column group
+  std::vector<Group> groups;
+  {
+    int col = 0;
+    for (int Rg : split_columns(R)) {
+      Group g;
+      g.inst = 0;
+      g.col0 = col;
+      g.Rg = Rg;
+      g.M = N * Rg;
+      groups.push_back(g);
+      col += Rg;
+    }
+  }
+  std::vector<ChebInst> sp;
+  for (auto& g : groups)
+    for (int d = 0; d < 2; ++d) sp.push_back(make_inst(L, g.Rg, fp64));
+  const ChebPlan sp_plan = plan_cheb(sp, fp64, false, c->n_cu, 2, fp64 ? 4 : 8, 0);
+  const int kt = sp_plan.kt;
+  int B64 = 1;
+  while (B64 < rows) B64 *= 2;
+  const int kcap = fp64 ? (int)((60 * 1024) / (sizeof(double2) * B64)) / 16 * 16 : 240;
+  size_t cap = 0;
+  CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
+  auto ws_need = [&](int K_) {
+    size_t by = 0;
+    for (auto& g : groups)
+      by += 2 * (align256((size_t)(K_ + kt) * g.stride() * csz) + align256(g.M * csz) +
+                 align256((size_t)nE * g.M * csz));
+    by += fp64 ? align256(sizeof(double2) * (size_t)K_ * B64)
+               : align256((size_t)64 * 64 * ceil_div(K_, 16));
+    by += align256(sizeof(ChebInst) * sp.size()) + align256(sizeof(QeInst) * sp.size());
+    return by;
+  };
+  int K = std::min(NkMax + 1, kcap);
+  if (K < NkMax + 1) K = std::max(16, K / 16 * 16);
+  while (K > 16 && ws_need(K) > cap) K = (K > 32 ? (K - 1) / 16 * 16 : 16);
+  if (ws_need(K) > cap)
+    return fail(CSP_ENOMEM, "quasi-eigenstate workspace %.2f GB exceeds the cap %.2f GB",
+                ws_need(K) / 1e9, cap / 1e9);
+  const int S = K + kt;
+  CHECK(ws_reserve(c, ws_need(K)));
+  Carver cv(c->ws);
+  std::vector<void*> carry(sp.size()), acc(sp.size()), slots(sp.size());
+  for (size_t i = 0; i < sp.size(); ++i) {
+    const Group& g = groups[i / 2];
+    slots[i] = cv.take((size_t)S * g.stride() * csz);
+    carry[i] = cv.take(g.M * csz);
+    acc[i] = cv.take((size_t)nE * g.M * csz);
+  }
+  void* d_bop = nullptr;
+  double* d_coef = nullptr;
+  if (fp64) d_coef = (double*)cv.take(sizeof(double2) * (size_t)K * B64);
+  else d_bop = cv.take((size_t)64 * 64 * ceil_div(K, 16));
+  ChebInst* d_inst = (ChebInst*)cv.take(sizeof(ChebInst) * sp.size());
+  QeInst* d_qi = (QeInst*)cv.take(sizeof(QeInst) * sp.size());
+
+  int64_t Msum = 0;
+  for (auto& g : groups) Msum += 2 * g.M;
+  std::vector<QeInst> qi;
+  int wg0 = 0;
+  for (size_t i = 0; i < sp.size(); ++i) {
+    const Group& g = groups[i / 2];
+    // both carried states start from psi0
+    HIPCALL(launch_gather_cols(N, R, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, dev_psi0, fp64,
+                               carry[i], s));
+    ChebInst& I = sp[i];
+    I.base = slots[i];
+    I.slot_stride = g.stride();
+    I.src = carry[i];
+    const int64_t units = fp64 ? ceil_div(N, kContractThreads) : ceil_div(ceil_div(N, 32), 4);
+    const double share = (double)c->n_cu * 4.0 * (double)g.M / (double)Msum / g.Rg;
+    const int wpc = (int)std::max<int64_t>(1, std::min<int64_t>(std::llround(share), units));
+    QeInst q{};
+    q.slots = slots[i];
+    q.slot_stride = g.stride();
+    q.N = N;
+    q.Rg = g.Rg;
+    q.wpc = wpc;
+    q.out = acc[i];
+    q.wg0 = wg0;
+    q.n_wg = g.Rg * wpc;
+    q.carry = carry[i];
+    q.conj = (int)(i & 1);                     // odd instances propagate backward
+    wg0 += q.n_wg;
+    qi.push_back(q);
+  }
+  HIPCALL(hipMemcpyAsync(d_inst, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
+  HIPCALL(hipMemcpyAsync(d_qi, qi.data(), sizeof(QeInst) * qi.size(), hipMemcpyHostToDevice, s));
+
+  Profiler prof{c, P.profile != 0};
+  int64_t n_spmm = 0, n_con = 0, amxsy = 0, axpy = 0;
+  const ChebStep st0 = step_args(sp_plan);
+  const int n_blk = (int)ceil_div(Nt, b);
+  for (int k = 0; k < n_blk; ++k) {
+    const int bk = std::min(b, Nt - k * b);
+    const int Nk = ntr[bk - 1];
+    HIPCALL(launch_qes_coeffs(d_a, lda, d_ntr, bk, (int64_t)k * b, nE, d_E, L->H0, tau,
+                              k == 0 ? 1 : 0, Nk, d_C, s));
+    amxsy += 2 * Nk;
+    axpy += 2 * (int64_t)(Nk + 1) * rows;
+    int produced = 0, n_lo = 0;
+    while (n_lo <= Nk) {
+      if (produced < Nk) {
+        ChebStep st = st0;
+        st.nlev = std::min(kt, Nk - produced);
+        if (produced == 0) {
+          st.first = 1;
+          st.slot_cur = -1;
+          st.copy_slot = 0;
+        } else {
+          st.slot_cur = produced % S;
+          st.slot_prev = (produced - 1) % S;
+        }
+        for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
+        size_t ev = 0;
+        CHECK(prof.begin(0, &ev));
+        HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_inst, sp_plan.runs, st, s));
+        CHECK(prof.end(ev));
+        ++n_spmm;
+        produced += st.nlev;
+      }
+      while (n_lo <= Nk && (n_lo + K - 1 <= produced || produced == Nk)) {
+        const int n_cnt = std::min(K, Nk + 1 - n_lo);
+        if (fp64) HIPCALL(launch_pack_qes64(d_C, Nk + 1, rows, B64, n_lo, n_cnt, d_coef, s));
+        else HIPCALL(launch_pack_qes(d_C, Nk + 1, rows, n_lo, n_cnt, d_bop, s));
+        QeArgs qa{};
+        qa.n_inst = (int)sp.size();
+        qa.n_lo = n_lo;
+        qa.n_cnt = n_cnt;
+        qa.S = S;
+        qa.first_chunk = (k == 0 && n_lo == 0) ? 1 : 0;
+        qa.nE = nE;
+        qa.total_wg = wg0;
+        qa.cplx = 1;
+        qa.carry_first = n_lo == 0 ? 1 : 0;
+        qa.bop = d_bop;
+        qa.coef = d_coef;
+        size_t evc = 0;
+        CHECK(prof.begin(1, &evc));
+        HIPCALL(launch_contract_qe(fp64, d_qi, qa, s));
+        CHECK(prof.end(evc));
+        ++n_con;
+        n_lo += n_cnt;
+      }
+    }
+  }
+  // Psi(E) = forward + backward accumulators, to the caller's layout
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    HIPCALL(launch_add_complex(fp64, (int64_t)nE * groups[gi].M, acc[2 * gi], acc[2 * gi + 1], s));
+    HIPCALL(launch_qe_scatter(N, groups[gi].Rg, nE, R, groups[gi].col0, fp64, acc[2 * gi],
+                              fp64 ? CSP_C128 : CSP_C64, dev_qe, s));
+  }
+  HIPCALL(hipStreamSynchronize(s));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    double ms_s = 0, ms_c = 0;
+    CHECK(prof.collect(&ms_s, &ms_c));
+    rep->block_b = b;
+    rep->chunk_K = K;
+    rep->n_blocks = n_blk;
+    rep->n_groups = (int)groups.size();
+    rep->amxsy = amxsy;
+    rep->axpy = axpy;
+    rep->dot = 0;
+    rep->spmm_launches = n_spmm;
+    rep->contract_launches = n_con;
+    rep->ms_total = now_ms() - t_start;
+    rep->ms_spmm = ms_s;
+    rep->ms_contract = ms_c;
+    rep->spmm_bytes = (double)N * R * csz * ((double)amxsy + 4.0 * n_spmm) +
+                      (double)sp.size() * static_bytes(L, fp64) * n_spmm;
+    rep->contract_bytes = (double)N * R * csz * ((double)amxsy + 2.0 * n_blk +
+                                                 2.0 * 2.0 * rows * n_con);
+    rep->contract_flops = 4.0 * 2.0 * (double)N * R * (double)axpy / 2.0 * (fp64 ? 1.0 : 3.0);
+    rep->workspace_bytes = c->ws_size;
+    rep->n_passes = 1;
+    rep->spmm_steps = kt;
+  }
+  return CSP_OK;
+}
+}  // namespace
+
 extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L,
                                             const void* dev_psi0, int32_t R,
                                             const csp_params* params_in, int32_t n_E,
@@ -1679,7 +1904,11 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
   if (L->ctx->device != c->device) return fail(CSP_EINVAL, "lattice is on another device");
   for (int e = 0; e < nE; ++e)
     if (!std::isfinite(energies[e])) return fail(CSP_EINVAL, "energy %d is not finite", e);
+  if (P.block_b < 0) return fail(CSP_EINVAL, "block_b must be >= 0");
+  if (P.block_b >= 1 && nE > (fp64 ? 15 : 31))
+    return fail(CSP_EINVAL, "the state-based form takes 1 <= n_E <= %d", fp64 ? 15 : 31);
   DeviceGuard dg(c->device);
+  if (P.block_b >= 1) return qe_state_based(c, L, dev_psi0, R, P, nE, energies, dev_qe, rep, t_start);
   hipStream_t s = c->stream;
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   const int Nt = (int)P.Nt;

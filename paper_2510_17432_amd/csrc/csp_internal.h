@@ -295,6 +295,9 @@ struct QeInst {
   int32_t Rg, wpc;          // columns, workgroups per column
   void* out;
   int32_t wg0, n_wg;
+  void* carry;              // carried state (row nE of complex coefficients), [Rg][N]
+  int32_t conj;             // use the conjugate coefficients (backward propagation)
+  int32_t pad;
 };
 struct QeArgs {
   int32_t n_inst;
@@ -303,10 +306,27 @@ struct QeArgs {
   int32_t first_chunk;      // write (1) or accumulate (0) the states
   int32_t nE;               // energies
   int32_t total_wg;
+  int32_t cplx;             // complex coefficients (state-based form) with a carry row nE
+  int32_t carry_first;      // write (1) or accumulate (0) the carried state
   int32_t pad;
   const void* bop;          // FP32: A operands C_n(E) in the MFMA lane layout
-  const void* coef;         // FP64: [n_cnt][B] complex (imaginary part 0)
+  const void* coef;         // FP64: [n_cnt][B] complex
 };
+// QE-Concurrent-S, one time block of bk steps starting at time index J0:
+// C[e][n] = tau sum_{j=1..bk, n <= N(j tau~)} c_n(j tau~) e^{i (E_e - H0)(J0 + j) tau}
+// (+ tau/2 at n = 0 when first: the j = 0 term, shared by both directions),
+// e < nE, and the carry row C[nE][n] = c_n(bk tau~);
+// n = 0..Nk, complex, ldc = Nk + 1.
+hipError_t launch_qes_coeffs(const double* d_a, int lda, const int32_t* d_ntr, int bk,
+                             int64_t J0, int nE, const double* d_E, double H0, double tau,
+                             int first, int Nk, double* d_C, hipStream_t s);
+// FP32: complex A operands (rows x 16 orders per step, MFMA lane layout); FP64: [n_cnt][B]
+hipError_t launch_pack_qes(const double* d_C, int ldc, int rows, int n_lo, int n_cnt,
+                           void* d_bop, hipStream_t s);
+hipError_t launch_pack_qes64(const double* d_C, int ldc, int rows, int B, int n_lo, int n_cnt,
+                             double* d_coef, hipStream_t s);
+// a += b over n complex values (float or double)
+hipError_t launch_add_complex(bool fp64, int64_t n, void* d_a, const void* d_b, hipStream_t s);
 // C[e][n] = tau (delta_n0 + sum_j 2 a_n(j tau~) Re((-i)^n e^{i (E_e - H0) j tau})), n <= nmax;
 // d_cs: scratch [nE][Nt] double2.
 hipError_t launch_qe_coeffs(const double* d_a, int lda, const int32_t* d_ntr, int Nt, int nE,

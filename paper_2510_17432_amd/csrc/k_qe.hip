@@ -16,6 +16,8 @@
 // 256-byte coalesced writes.  The FP64 path multiplies complex128 values by
 // the real coefficients with FMAs.  Coefficients are FP64 on the GPU, summed
 // over j in a fixed order.
+#include <type_traits>
+
 #include "csp_internal.h"
 
 namespace csp {
@@ -29,6 +31,16 @@ struct QeBop {
   qbf16x8 hi;
   qbf16x8 lo;
 };
+// complex A operand of the state-based form: real and imaginary parts
+struct QeBop4 {
+  qbf16x8 rhi, rlo, ihi, ilo;
+};
+typedef unsigned short qu16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ qbf16x8 neg_bf16(qbf16x8 x) {
+  qu16x8 u = __builtin_bit_cast(qu16x8, x);
+  u ^= (unsigned short)0x8000;
+  return __builtin_bit_cast(qbf16x8, u);
+}
 
 // cs[e][j-1] = (cos, sin) of (E_e - H0) j tau, j = 1..Nt
 __global__ void k_qe_phase(int nE, int Nt, const double* __restrict__ E, double H0, double tau,
@@ -96,22 +108,148 @@ hipError_t launch_pack_qe64(const double* d_C, int ldc, int nE, int B, int n_lo,
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ state-based form
+// QE-Concurrent-S: within a time block starting at t_{J0} from the carried
+// states s^+ = psi(t_{J0}) and s^- = psi(-t_{J0}),
+//   psi(+-t_{J0+j}) = sum_n c_n(j tau~)^{(*)} T_n(H~) s^+-,
+// so the block's share of Eq. QE is sum_n C_n(E) T_n s^+ + conj(C_n(E)) T_n s^-
+// with the complex block coefficients below (the j = 0 term tau psi0 rides
+// on C_0 of the first block, tau/2 on each side), and the next carried states take the
+// coefficients c_n(bk tau~) (and their conjugates) as one more row.
+__global__ void k_qes_coeffs(const double* __restrict__ a, int lda, const int32_t* __restrict__ ntr,
+                             int bk, int64_t J0, int nE, const double* __restrict__ E, double H0,
+                             double tau, int first, int Nk, double2* __restrict__ C) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (n > Nk || e > nE) return;
+  double2 out = make_double2(0.0, 0.0);
+  if (e == nE) {                                  // carry row: c_n(bk tau~)
+    if (n <= ntr[bk - 1]) {
+      const double an = a[(int64_t)(bk - 1) * lda + n];
+      switch (n & 3) {                            // (-i)^n an
+        case 0: out = make_double2(an, 0.0); break;
+        case 1: out = make_double2(0.0, -an); break;
+        case 2: out = make_double2(-an, 0.0); break;
+        default: out = make_double2(0.0, an); break;
+      }
+    }
+  } else {
+    double sr = 0.0, si = 0.0;
+    for (int j = 1; j <= bk; ++j) {
+      if (n > ntr[j - 1]) continue;
+      const double an = a[(int64_t)(j - 1) * lda + n];
+      double sn, cn;
+      sincos((E[e] - H0) * ((double)(J0 + j) * tau), &sn, &cn);
+      double xr, xi;                              // (-i)^n (cn + i sn)
+      switch (n & 3) {
+        case 0: xr = cn; xi = sn; break;
+        case 1: xr = sn; xi = -cn; break;
+        case 2: xr = -cn; xi = -sn; break;
+        default: xr = -sn; xi = cn; break;
+      }
+      sr = fma(an, xr, sr);
+      si = fma(an, xi, si);
+    }
+    // j = 0: (1/2)(psi0 + psi0), half on the forward and half on the backward side
+    out = make_double2(tau * ((first && n == 0 ? 0.5 : 0.0) + sr), tau * si);
+  }
+  C[(int64_t)e * (Nk + 1) + n] = out;
+}
+
+hipError_t launch_qes_coeffs(const double* d_a, int lda, const int32_t* d_ntr, int bk,
+                             int64_t J0, int nE, const double* d_E, double H0, double tau,
+                             int first, int Nk, double* d_C, hipStream_t s) {
+  hipLaunchKernelGGL(k_qes_coeffs, dim3((unsigned)ceil_div(Nk + 1, 128), nE + 1), dim3(128), 0, s,
+                     d_a, lda, d_ntr, bk, J0, nE, d_E, H0, tau, first, Nk,
+                     reinterpret_cast<double2*>(d_C));
+  return hipGetLastError();
+}
+
+// entry (kb, lane): row il of orders n_lo + 16 kb + 8 h .. + 7, split hi + lo
+__global__ void k_pack_qes(const double2* __restrict__ C, int ldc, int rows, int n_lo, int n_cnt,
+                           QeBop4* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_kb = (n_cnt + 15) >> 4;
+  if (i >= n_kb * 64) return;
+  const int kb = i >> 6, lane = i & 63, il = lane & 31, h = lane >> 5;
+  QeBop4 b;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int rel = 16 * kb + 8 * h + v;
+    double2 c = make_double2(0.0, 0.0);
+    if (il < rows && rel < n_cnt) c = C[(int64_t)il * ldc + n_lo + rel];
+    const float re = static_cast<float>(c.x), im = static_cast<float>(c.y);
+    const __bf16 rh = static_cast<__bf16>(re), ih = static_cast<__bf16>(im);
+    b.rhi[v] = rh;
+    b.rlo[v] = static_cast<__bf16>(re - static_cast<float>(rh));
+    b.ihi[v] = ih;
+    b.ilo[v] = static_cast<__bf16>(im - static_cast<float>(ih));
+  }
+  out[i] = b;
+}
+
+hipError_t launch_pack_qes(const double* d_C, int ldc, int rows, int n_lo, int n_cnt,
+                           void* d_bop, hipStream_t s) {
+  const int n = 64 * ((n_cnt + 15) >> 4);
+  hipLaunchKernelGGL(k_pack_qes, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(d_C), ldc, rows, n_lo, n_cnt,
+                     static_cast<QeBop4*>(d_bop));
+  return hipGetLastError();
+}
+
+__global__ void k_pack_qes64(const double2* __restrict__ C, int ldc, int rows, int B, int n_lo,
+                             int n_cnt, double2* __restrict__ coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cnt * B) return;
+  const int rel = i / B, e = i - rel * B;
+  coef[i] = e < rows ? C[(int64_t)e * ldc + n_lo + rel] : make_double2(0.0, 0.0);
+}
+
+hipError_t launch_pack_qes64(const double* d_C, int ldc, int rows, int B, int n_lo, int n_cnt,
+                             double* d_coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_qes64, dim3((unsigned)ceil_div(n_cnt * B, 256)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(d_C), ldc, rows, B, n_lo, n_cnt,
+                     reinterpret_cast<double2*>(d_coef));
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_add_complex(int64_t n, T* __restrict__ a, const T* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] += b[i];
+}
+
+hipError_t launch_add_complex(bool fp64, int64_t n, void* d_a, const void* d_b, hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(2 * n, 256), 65536);
+  if (fp64)
+    hipLaunchKernelGGL(k_add_complex<double>, dim3(grid), dim3(256), 0, s, n,
+                       static_cast<double*>(d_a), static_cast<const double*>(d_b));
+  else
+    hipLaunchKernelGGL(k_add_complex<float>, dim3(grid), dim3(256), 0, s, n,
+                       static_cast<float*>(d_a), static_cast<const float*>(d_b));
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ FP32 contraction
 // Workgroup -> (instance, column, sub) as in the state assembly; each wave
 // owns one 32-value tile of its column at a time.  Lane (i, h): B operand =
 // value i of orders 8h..8h+7 of a 16-order step; A operand (LDS) =
 // C_n(E_i) for the same orders; accumulator = Psi(E_e) at value i for
-// e = 8(v/4) + 4h + v%4.
+// e = 8(v/4) + 4h + v%4.  CPLX: complex coefficients (state-based form),
+// conjugated for backward instances, and row nE the carried state.
+template <bool CPLX>
 __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
     const QeInst* __restrict__ insts, QeArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  using Bop = typename std::conditional<CPLX, QeBop4, QeBop>::type;
   const int n_kb = (a.n_cnt + 15) >> 4;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int il = lane & 31, h = lane >> 5;
-  QeBop* sb = reinterpret_cast<QeBop*>(smem);
+  Bop* sb = reinterpret_cast<Bop*>(smem);
   {
-    const QeBop* gb = static_cast<const QeBop*>(a.bop);
+    const Bop* gb = static_cast<const Bop*>(a.bop);
     for (int e = tid; e < n_kb * 64; e += kContractThreads) sb[e] = gb[e];
   }
   __syncthreads();
@@ -167,24 +305,52 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
         qlo[v] = static_cast<__bf16>(q - static_cast<float>(qh));
       }
       if (kb + 1 < n_kb) load_step(kb + 1);
-      const QeBop be = sb[kb * 64 + lane];
-      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, phi, accR, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.lo, phi, accR, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, plo, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, qhi, accI, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.lo, qhi, accI, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, qlo, accI, 0, 0, 0);
+      if constexpr (!CPLX) {
+        const QeBop be = sb[kb * 64 + lane];
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, phi, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.lo, phi, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, plo, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, qhi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.lo, qhi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.hi, qlo, accI, 0, 0, 0);
+      } else {
+        // (Cr + i Ci)(p + i q): Re = Cr p - Ci q, Im = Cr q + Ci p, with Ci
+        // negated for the conjugate coefficients of a backward instance
+        const QeBop4 be = sb[kb * 64 + lane];
+        const qbf16x8 ip_h = I.conj ? neg_bf16(be.ihi) : be.ihi;
+        const qbf16x8 ip_l = I.conj ? neg_bf16(be.ilo) : be.ilo;
+        const qbf16x8 im_h = neg_bf16(ip_h), im_l = neg_bf16(ip_l);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.rhi, phi, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.rlo, phi, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.rhi, plo, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(im_h, qhi, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(im_l, qhi, accR, 0, 0, 0);
+        accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(im_h, qlo, accR, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.rhi, qhi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.rlo, qhi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(be.rhi, qlo, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ip_h, phi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ip_l, phi, accI, 0, 0, 0);
+        accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ip_h, plo, accI, 0, 0, 0);
+      }
     }
     if (mv) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int e = 8 * (v >> 2) + 4 * h + (v & 3);
+        gq2* p = nullptr;
+        bool first = a.first_chunk != 0;
         if (e < a.nE) {
-          gq2* p = out + (int64_t)e * N + m;
+          p = out + (int64_t)e * N + m;
+        } else if (CPLX && a.cplx && e == a.nE && I.carry) {
+          p = (gq2*)(I.carry) + col * N + m;
+          first = a.carry_first != 0;
+        }
+        if (p) {
           qf32x2 o;
           o.x = accR[v];
           o.y = accI[v];
-          if (!a.first_chunk) {
+          if (!first) {
             const qf32x2 old = *p;
             o.x += old.x;
             o.y += old.y;
@@ -228,17 +394,25 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
       const double2 x = slots[(int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + m];
 #pragma unroll
       for (int e = 0; e < B; ++e) {
-        const double c = scoef[rel * B + e].x;
-        acc[e].x = fma(c, x.x, acc[e].x);
-        acc[e].y = fma(c, x.y, acc[e].y);
+        const double2 c = scoef[rel * B + e];
+        const double ci = I.conj ? -c.y : c.y;
+        acc[e].x = fma(c.x, x.x, fma(-ci, x.y, acc[e].x));
+        acc[e].y = fma(c.x, x.y, fma(ci, x.x, acc[e].y));
       }
     }
 #pragma unroll
     for (int e = 0; e < B; ++e) {
+      double2* p = nullptr;
+      bool first = a.first_chunk != 0;
       if (e < a.nE) {
-        double2* p = out + (int64_t)e * N + m;
+        p = out + (int64_t)e * N + m;
+      } else if (a.cplx && e == a.nE && I.carry) {
+        p = static_cast<double2*>(I.carry) + col * N + m;
+        first = a.carry_first != 0;
+      }
+      if (p) {
         double2 o = acc[e];
-        if (!a.first_chunk) {
+        if (!first) {
           const double2 old = *p;
           o.x += old.x;
           o.y += old.y;
@@ -252,14 +426,20 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
 hipError_t launch_contract_qe(bool fp64, const QeInst* d_inst, const QeArgs& a, hipStream_t s) {
   if (a.total_wg <= 0 || a.n_cnt <= 0) return hipSuccess;
   const dim3 grid(a.total_wg), block(kContractThreads);
+  const int rows = a.nE + (a.cplx ? 1 : 0);          // energies (+ the carried state)
   if (!fp64) {
-    if (a.nE < 1 || a.nE > 32) return hipErrorInvalidValue;
-    const size_t lds = sizeof(QeBop) * 64 * (size_t)ceil_div(a.n_cnt, 16);
-    hipLaunchKernelGGL(k_contract_qe_f32, grid, block, lds, s, d_inst, a);
+    if (a.nE < 1 || rows > 32) return hipErrorInvalidValue;
+    if (a.cplx) {
+      const size_t lds = sizeof(QeBop4) * 64 * (size_t)ceil_div(a.n_cnt, 16);
+      hipLaunchKernelGGL(k_contract_qe_f32<true>, grid, block, lds, s, d_inst, a);
+    } else {
+      const size_t lds = sizeof(QeBop) * 64 * (size_t)ceil_div(a.n_cnt, 16);
+      hipLaunchKernelGGL(k_contract_qe_f32<false>, grid, block, lds, s, d_inst, a);
+    }
     return hipGetLastError();
   }
   int B = 1;
-  while (B < a.nE) B *= 2;
+  while (B < rows) B *= 2;
   const size_t lds = sizeof(double2) * (size_t)a.n_cnt * B;
   switch (B) {
     case 1: hipLaunchKernelGGL(k_contract_qe_f64<1>, grid, block, lds, s, d_inst, a); break;

@@ -103,3 +103,58 @@ def test_quasi_eigenstates_errors(csp, ctx):
     with pytest.raises(csp.CspError) as e:
         csp.csp_quasi_eigenstates(ctx, g, p, csp.make_params(0, mode="fp32_conc"), [0.0])
     assert e.value.status == csp.CSP_EINVAL
+
+
+# ---------------------------------------------------------------- QE-Concurrent-S
+QES_CASES = [
+    # spec, R, energies, Nt, b
+    (dict(kind="square", Lx=23, Ly=19, t=1.0, W=1.0, disorder_seed=3), 1, [0.35], 40, 1),
+    (dict(kind="honeycomb", Lx=15, Ly=11, t=-2.7, W=0.5, disorder_seed=4), 5,
+     [-6.0, -2.7, 0.0, 1.1, 4.2], 60, 7),
+    (dict(kind="chain", Lx=301, t=1.0, W=0.0, periodic_x=False), 2, [-1.5, 0.2, 1.9], 200, 32),
+    (dict(kind="square", Lx=17, Ly=13, t=-1.0, W=0.3, disorder_seed=9, periodic_y=False), 3,
+     list(np.linspace(-4.0, 4.0, 15)), 100, 64),
+    (dict(kind="honeycomb", Lx=9, Ly=8, t=-2.7, W=1.0, disorder_seed=2), 2, [0.5, -1.0], 30, 30),
+]
+
+
+@pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
+@pytest.mark.parametrize("case", range(len(QES_CASES)))
+def test_quasi_eigenstates_state_based(csp, ctx, mode, case):
+    spec, R, E, Nt, b = QES_CASES[case]
+    print("[gpu] QE-Concurrent-S %s case %d (b = %d)" % (mode, case, b), flush=True)
+    g, c = pair(csp, ctx, spec)
+    psi = o.random_phase_states_fast(c.N, R, 19)
+    ref, _ = o.quasi_eigenstates(c, psi, Nt, E, Hn=g.halfwidth)
+    dt = torch.complex128 if mode == "fp64_conc" else torch.complex64
+    p = torch.from_numpy(psi).to("cuda:0").to(dt)
+    q, rep = csp.csp_quasi_eigenstates(ctx, g, p, csp.make_params(Nt, mode=mode, block_b=b), E)
+    got = host(q)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print("[gpu]   max rel error %.2e, blocks %d, chunks %d" % (err, rep.n_blocks,
+                                                               rep.contract_launches), flush=True)
+    assert err < (1e-10 if mode == "fp64_conc" else 1e-4)
+    bb = min(b, Nt)
+    nb = -(-Nt // bb)
+    assert rep.block_b == bb and rep.n_blocks == nb
+    Nks = [o.truncation(min(bb, Nt - k * bb) * math.pi) for k in range(nb)]
+    assert rep.amxsy == 2 * sum(Nks)
+
+
+def test_quasi_eigenstates_state_based_largest_and_errors(csp, ctx):
+    spec = dict(kind="honeycomb", Lx=11, Ly=9, t=-2.7, W=1.0, disorder_seed=6)
+    g, c = pair(csp, ctx, spec)
+    psi = o.random_phase_states_fast(c.N, 3, 17)
+    E = list(np.linspace(-8.0, 8.0, 31))
+    ref, _ = o.quasi_eigenstates(c, psi, 50, E, Hn=g.halfwidth)
+    p = torch.from_numpy(psi).to("cuda:0").to(torch.complex64)
+    q, _ = csp.csp_quasi_eigenstates(ctx, g, p, csp.make_params(50, mode="fp32_conc", block_b=16), E)
+    assert np.max(np.abs(host(q) - ref)) < 1e-4 * np.max(np.abs(ref))
+    # the energy-based and the state-based forms agree
+    qe_e, _ = csp.csp_quasi_eigenstates(ctx, g, p, csp.make_params(50, mode="fp32_conc"), E)
+    assert np.max(np.abs(host(q) - host(qe_e))) < 1e-4 * np.max(np.abs(ref))
+    for mode, nE in (("fp32_conc", 32), ("fp64_conc", 16)):
+        with pytest.raises(csp.CspError) as e:
+            csp.csp_quasi_eigenstates(ctx, g, p if mode == "fp32_conc" else p.to(torch.complex128),
+                                      csp.make_params(10, mode=mode, block_b=4), [0.0] * nE)
+        assert e.value.status == csp.CSP_EINVAL
