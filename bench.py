@@ -70,6 +70,8 @@ def parse():
                          "matrices of density D_H = 61, 121, 233 (4.76 M orbitals, 10 / 5 / 2 "
                          "random columns) by the moment form in complex64 and complex128 "
                          "against the complex128 sequential form timed on a truncated run")
+    ap.add_argument("--dh", type=int, nargs="*", default=None,
+                    help="with --dense-dh: only these matrix densities (61, 121, 233)")
     ap.add_argument("--ec", action="store_true",
                     help="instead of the step benchmark: the electronic-conductivity "
                          "correlation (EC-Concurrent-M, 49 energies, Nt = 1024, 5 random "
@@ -256,7 +258,15 @@ def dense_dh(a):
                        "bilayer graphene supercell" % (w["L"], w["L"], w["L"] ** 2, w["t0"],
                                                         w["decay"], w["W"], w["seed"], Nt),
            "cases": []}
+    if a.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for case in w["cases"]:
+        if a.dh and case["D"] not in a.dh:
+            continue
         t0 = time.perf_counter()
         col, val = csp_inputs.long_range_square(w["L"], case["r_cut"], w["t0"], w["decay"],
                                                 w["W"], w["seed"])
@@ -592,8 +602,9 @@ def main():
         pq32 = psi[:, :Rr].contiguous()
         pq64 = pq32.to(torch.complex128)
         res_q = {}
-        for name, pin, mode in (("fp32", pq32, "fp32_conc"), ("fp64", pq64, "fp64_conc")):
-            prm = csp.make_params(Ntq, mode=mode)
+        for name, pin, mode, bq in (("fp32", pq32, "fp32_conc", 0), ("fp64", pq64, "fp64_conc", 0),
+                                    ("fp32_state_b32", pq32, "fp32_conc", 32)):
+            prm = csp.make_params(Ntq, mode=mode, block_b=bq)
             csp.csp_quasi_eigenstates(ctx, lat, pin, prm, Eq)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -602,8 +613,9 @@ def main():
             res_q[name] = (q, time.perf_counter() - t0, qrep)
             log("quasi-eigenstates %s: %.3f s, %d orders, %d chunks" %
                 (name, res_q[name][1], qrep.amxsy, qrep.contract_launches))
-        q32, q64 = res_q["fp32"][0], res_q["fp64"][0]
+        q32, q64, qs = res_q["fp32"][0], res_q["fp64"][0], res_q["fp32_state_b32"][0]
         qerr = float((q32.to(torch.complex128) - q64).abs().max().item() / q64.abs().max().item())
+        serr = float((qs.to(torch.complex128) - q64).abs().max().item() / q64.abs().max().item())
         seq_steps = 2 * Ntq * 20
         out["quasi_eigenstates"] = {
             "form": "QE-Concurrent-E (energy-based, forward and backward merged)",
@@ -612,8 +624,12 @@ def main():
             "fp32_max_rel_err_vs_fp64": qerr,
             "chebyshev_orders": res_q["fp32"][2].amxsy,
             "sequential_chebyshev_steps": seq_steps,
-            "step_ratio_vs_sequential": seq_steps / res_q["fp32"][2].amxsy}
-        del q32, q64, res_q, pq32, pq64
+            "step_ratio_vs_sequential": seq_steps / res_q["fp32"][2].amxsy,
+            "state_based_b32": {"form": "QE-Concurrent-S, b = 32, complex64",
+                                "s": res_q["fp32_state_b32"][1],
+                                "chebyshev_steps": res_q["fp32_state_b32"][2].amxsy,
+                                "max_rel_err_vs_fp64_energy_based": serr}}
+        del q32, q64, qs, res_q, pq32, pq64
 
     # time-to-accuracy: DOS of the random columns on this GPU, complex64
     # concurrent forms vs the plain complex128 sequential form; each run is
