@@ -345,7 +345,8 @@ csp_status csp_quasi_eigenstates(csp_context *ctx, const csp_lattice *lat,
  * on split-bf16 MFMA with FP32 accumulation over slices of orbitals, FP64
  * across slices) or CSP_FP64_CONC (complex128); 1 <= n_E <= 128 (one
  * recursion serves all energies); 1 <= Nt <= 2^20.  Explicit matrices need
- * csp_lattice_set_positions first (CSP_EINVAL otherwise).  rep may be NULL. */
+ * csp_lattice_set_positions first (CSP_EINVAL otherwise); CSP_EUNSUPPORTED
+ * when Nt R n_E exceeds 2^31 - 1 (call per group of columns).  rep may be NULL. */
 csp_status csp_ec_correlation(csp_context *ctx, const csp_lattice *lat, int32_t alpha,
                               const void *dev_psi0, int32_t R, const void *dev_qe,
                               const csp_params *params, int32_t n_E, double *dev_corr,

@@ -2160,6 +2160,9 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
   const int Nt = (int)P.Nt;
   const int64_t N = L->g.N;
   const int64_t ldmu = (int64_t)R * nE;
+  if ((int64_t)Nt * ldmu > INT32_MAX)
+    return fail(CSP_EUNSUPPORTED, "Nt x R x n_E = %lld exceeds 2^31 - 1 (split the columns)",
+                (long long)Nt * ldmu);
   const double tau = P.tau_tilde / L->halfwidth;
 
   struct Free {

@@ -129,6 +129,15 @@ def test_ec_many_energies(csp, ctx):
     check(csp, ctx, g, c, 1, list(np.linspace(-7.0, 7.0, 37)), 10, 30, 1, "fp64_conc")
 
 
+@pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
+def test_ec_three_groups_and_one_step(csp, ctx, mode):
+    # 7 columns (groups 4 + 2 + 1), Nt = 1 (one chunk of N(pi) + 1 orders), ragged N
+    spec = dict(kind="square", Lx=21, Ly=13, t=-1.0, W=0.8, disorder_seed=10)
+    g, c = pair(csp, ctx, spec)
+    check(csp, ctx, g, c, 7, [-0.5, 1.3], 8, 1, 1, mode)
+    check(csp, ctx, g, c, 7, [0.2], 8, 33, 0, mode)
+
+
 def test_ec_sigma_matches_oracle(csp, ctx):
     spec = CASES[0][0]
     g, c = pair(csp, ctx, spec)

@@ -115,6 +115,7 @@ QES_CASES = [
     (dict(kind="square", Lx=17, Ly=13, t=-1.0, W=0.3, disorder_seed=9, periodic_y=False), 3,
      list(np.linspace(-4.0, 4.0, 15)), 100, 64),
     (dict(kind="honeycomb", Lx=9, Ly=8, t=-2.7, W=1.0, disorder_seed=2), 2, [0.5, -1.0], 30, 30),
+    (dict(kind="square", Lx=21, Ly=13, t=1.0, W=0.8, disorder_seed=11), 7, [0.1, 1.9], 25, 10),
 ]
 
 
