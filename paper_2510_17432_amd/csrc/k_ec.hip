@@ -124,37 +124,57 @@ hipError_t launch_current_stencil(bool fp64, const Geom& g, double t, int alpha,
 
 // Explicit matrix in slices of 128 rows ([N/128][D][128]); padding entries
 // have the value 0.  (J psi)_s = i sum_k H_{s,j_k} (x_{j_k} - x_s) psi_{j_k}.
+// A thread owns row s of up to 8 vectors, so each matrix entry and its
+// displacement serve 8 gathers.
+constexpr int kCurVec = 8;
+
 template <typename T>
 __global__ void k_current_ell(int64_t N, int D, const int32_t* __restrict__ col,
                               const double* __restrict__ val, const double* __restrict__ pos,
                               double box, int alpha, const T* __restrict__ in,
                               T* __restrict__ out, int64_t nvec) {
-  const int64_t total = nvec * N;
+  const int64_t n_vt = (nvec + kCurVec - 1) / kCurVec;
+  const int64_t total = n_vt * N;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t v = i / N, s = i - v * N;
-    const T* x = in + 2 * v * N;
+    const int64_t vt = i / N, s = i - vt * N;
+    const int64_t v0 = vt * kCurVec;
+    const int nv = nvec - v0 < kCurVec ? static_cast<int>(nvec - v0) : kCurVec;
     const int64_t base = (s >> 7) * (int64_t)D * 128 + (s & 127);
     const double xs = pos[2 * s + alpha];
-    double acc_r = 0.0, acc_i = 0.0;
+    double acc_r[kCurVec], acc_i[kCurVec];
+#pragma unroll
+    for (int v = 0; v < kCurVec; ++v) acc_r[v] = acc_i[v] = 0.0;
     for (int k = 0; k < D; ++k) {
       const int64_t j = col[base + (int64_t)k * 128];
       const double h = val[base + (int64_t)k * 128];
       double d = pos[2 * j + alpha] - xs;
       if (box > 0.0) d -= box * rint(d / box);
       const double w = h * d;
-      acc_r += w * (double)x[2 * j];
-      acc_i += w * (double)x[2 * j + 1];
+#pragma unroll
+      for (int v = 0; v < kCurVec; ++v) {
+        if (v < nv) {
+          const T* x = in + 2 * ((v0 + v) * N + j);
+          acc_r[v] += w * (double)x[0];
+          acc_i[v] += w * (double)x[1];
+        }
+      }
     }
-    out[2 * i] = static_cast<T>(-acc_i);
-    out[2 * i + 1] = static_cast<T>(acc_r);
+#pragma unroll
+    for (int v = 0; v < kCurVec; ++v) {
+      if (v < nv) {
+        T* o = out + 2 * ((v0 + v) * N + s);
+        o[0] = static_cast<T>(-acc_i[v]);
+        o[1] = static_cast<T>(acc_r[v]);
+      }
+    }
   }
 }
 
 hipError_t launch_current_ell(bool fp64, int64_t N, int D, const int32_t* ell_col,
                               const double* ell_v64, const double* pos, double box, int alpha,
                               const void* in, void* out, int64_t nvec, hipStream_t s) {
-  const int64_t total = nvec * N;
+  const int64_t total = ceil_div(nvec, kCurVec) * N;
   const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 65536);
   if (fp64)
     hipLaunchKernelGGL(k_current_ell<double>, dim3(grid), dim3(256), 0, s, N, D, ell_col,
