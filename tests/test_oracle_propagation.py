@@ -266,3 +266,34 @@ def test_spectral_centre_shift():
         t = np.arange(Nt + 1) * math.pi / Hn
         ref = exact_corr(lat, psi, Nt, Hn)[:, 0] * np.exp(1j * H0 * t)
         assert np.max(np.abs(corr[:, 0] - ref)) < 1e-10
+
+
+def test_graphene_dos_features():
+    # textbook features of the clean graphene DOS (Sec. III's lattice family):
+    # linear vanishing at the Dirac point, van Hove peaks at +-|t|, band edges
+    # at +-3|t|, one state per orbital; from the Bloch closed form of the
+    # propagation (all cells, random-phase state) on a large periodic lattice
+    tt, L, Nt = -2.7, 256, 2048
+    psi = o.random_phase_states_fast(2 * L * L, 1, 4)
+    Hn = 1.025 * 3 * abs(tt)
+    corr = o.bloch_corr_uniform("honeycomb", L, L, tt, psi, math.pi / Hn, Nt + 1)
+    E, D, _ = o.dos(corr, Hn)
+    D = D[:, 0]
+    dE = E[1] - E[0]
+    assert abs(np.sum(D) * dE - 1.0) < 1e-6
+    # peaks of the two halves at +-|t| (within the resolution of the window)
+    for sgn in (-1, 1):
+        half = (sgn * E > 0.3 * abs(tt)) & (sgn * E < 2.5 * abs(tt))
+        Ep = E[half][np.argmax(D[half])]
+        assert abs(abs(Ep) - abs(tt)) < 0.1 * abs(tt)
+    # Dirac point: far below the van Hove peak, and rising linearly near it
+    d0 = D[np.argmin(np.abs(E))]
+    assert d0 < 0.1 * np.max(D)
+    small = (np.abs(E) > 0.2 * abs(tt)) & (np.abs(E) < 0.5 * abs(tt))
+    slope = np.polyfit(np.abs(E[small]), D[small], 1)[0]
+    assert slope > 0
+    # outside the band (|E| > 3|t| plus a few window widths, up to the grid
+    # edge |H| = 1.025 x 3|t|) the DOS vanishes
+    outside = np.abs(E) > 3 * abs(tt) * 1.01
+    assert np.count_nonzero(outside) > 10
+    assert np.max(np.abs(D[outside])) < 1e-3 * np.max(D)
