@@ -366,15 +366,9 @@ def ec_bench(a):
     psi64 = torch.empty((N, R), dtype=torch.complex128, device=dev)
     csp.csp_states_random_phase(ctx, psi64, R, w["seed_states"])
     psi32 = psi64.to(torch.complex64)
-    # quasi-eigenstates (complex64, tiles of 32 energies)
+    # quasi-eigenstates (complex64 QE-Concurrent-E, all energies in one call)
     t = time.perf_counter()
-    qe32 = torch.empty((nE, N, R), dtype=torch.complex64, device=dev)
-    p_qe = csp.make_params(Nt, mode="fp32_conc")
-    for e0 in range(0, nE, 32):
-        e1 = min(nE, e0 + 32)
-        q, _ = csp.csp_quasi_eigenstates(ctx, lat, psi32, p_qe, E[e0:e1])
-        qe32[e0:e1] = q
-        del q
+    qe32, _ = csp.csp_quasi_eigenstates(ctx, lat, psi32, csp.make_params(Nt, mode="fp32_conc"), E)
     torch.cuda.synchronize()
     t_qe = time.perf_counter() - t
     log("  quasi-eigenstates: %.1f s" % t_qe)

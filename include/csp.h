@@ -311,8 +311,9 @@ csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *d
  * tau sum_{j=0}^{Nt} (2 - delta_j0)/2 [e^{iE't_j} psi(t_j) + e^{-iE't_j} psi(-t_j)]
  * of the sequentially propagated states up to rounding.  Writes dev_qe
  * [n_E][N][R] in the dtype of psi0.  params->mode CSP_FP32_CONC (complex64
- * recursion, split-bf16 MFMA accumulation, 1 <= n_E <= 32) or CSP_FP64_CONC
- * (complex128, 1 <= n_E <= 16); 1 <= Nt <= 2^20.  Coefficients are FP64 on
+ * recursion, split-bf16 MFMA accumulation) or CSP_FP64_CONC (complex128);
+ * 1 <= n_E <= 128 (one recursion serves all energies, contracted in tiles of
+ * 32 or 16 energies); 1 <= Nt <= 2^20.  Coefficients are FP64 on
  * the GPU.  CSP_ENOMEM when a 16-order ring of all columns with the n_E
  * accumulated states does not fit (call per column then).  rep may be NULL.
  * params->block_b >= 1 selects the state-based form QE-Concurrent-S

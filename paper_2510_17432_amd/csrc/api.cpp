@@ -1897,8 +1897,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     return fail(CSP_EINVAL, "quasi-eigenstates need CSP_FP32_CONC or CSP_FP64_CONC");
   const bool fp64 = P.mode == CSP_FP64_CONC;
   const int nE = n_E;
-  if (nE < 1 || nE > (fp64 ? kMaxFp64B : 32))
-    return fail(CSP_EINVAL, "need 1 <= n_E <= %d", fp64 ? kMaxFp64B : 32);
+  if (nE < 1 || nE > 128) return fail(CSP_EINVAL, "need 1 <= n_E <= 128");
   if (R < 1) return fail(CSP_EINVAL, "R must be >= 1");
   if (P.Nt < 1 || P.Nt > (1 << 20)) return fail(CSP_EINVAL, "need 1 <= Nt <= 2^20");
   if (L->ctx->device != c->device) return fail(CSP_EINVAL, "lattice is on another device");
@@ -1969,9 +1968,11 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
   const int kt = sp_plan.kt;
 
   // Orders per contraction chunk: all of them when they fit, else a multiple
-  // of 16 (LDS holds the chunk's coefficients; the ring K + kt slots).
+  // of 16 (LDS holds the chunk's coefficients of one energy tile; the ring
+  // K + kt slots).  Energy tiles of 32 (FP32) or B64 (FP64) energies.
   int B64 = 1;
-  while (B64 < nE) B64 *= 2;
+  while (B64 < nE && B64 < 16) B64 *= 2;
+  const int n_et = (int)ceil_div(nE, fp64 ? B64 : 32);
   const int kcap = fp64 ? (int)((60 * 1024) / (sizeof(double2) * B64)) / 16 * 16 : 496;
   size_t cap = 0;
   CHECK(memory_cap(c, P.mem_cap_bytes, &cap));
@@ -1980,8 +1981,8 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     for (auto& g : groups)
       by += align256((size_t)(K_ + kt) * g.stride() * csz) + align256(g.M * csz) +
             align256((size_t)nE * g.M * csz);
-    by += fp64 ? align256(sizeof(double2) * (size_t)K_ * B64)
-               : align256(bop_bytes(1, K_)) + align256(sizeof(float) * 16 * ceil_div(K_, 16));
+    by += fp64 ? align256(sizeof(double2) * (size_t)K_ * B64 * n_et)
+               : align256(bop_bytes(1, K_) * n_et) + align256(sizeof(float) * 16 * ceil_div(K_, 16));
     by += align256(sizeof(ChebInst) * groups.size()) + align256(sizeof(QeInst) * groups.size());
     return by;
   };
@@ -2005,9 +2006,9 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
   float* d_ccd = nullptr;
   double* d_coef = nullptr;
   if (fp64) {
-    d_coef = (double*)cv.take(sizeof(double2) * (size_t)K * B64);
+    d_coef = (double*)cv.take(sizeof(double2) * (size_t)K * B64 * n_et);
   } else {
-    d_bop = cv.take(bop_bytes(1, K));
+    d_bop = cv.take(bop_bytes(1, K) * n_et);
     d_ccd = (float*)cv.take(sizeof(float) * 16 * ceil_div(K, 16));
   }
   ChebInst* d_inst = (ChebInst*)cv.take(sizeof(ChebInst) * groups.size());
@@ -2069,9 +2070,18 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     produced += st.nlev;
     while (n_lo <= Nmax && (n_lo + K - 1 <= produced || produced == Nmax)) {
       const int n_cnt = std::min(K, Nmax + 1 - n_lo);
-      if (fp64) HIPCALL(launch_pack_qe64(d_C, ldc, nE, B64, n_lo, n_cnt, d_coef, s));
-      else HIPCALL(launch_pack_bop(d_C, ldc, d_ntrq, nE, 1, n_lo, n_cnt, d_bop, d_ccd, s));
+      for (int t = 0; t < n_et; ++t) {
+        const int w = fp64 ? B64 : 32, e0 = t * w, ne = std::min(w, nE - e0);
+        if (fp64)
+          HIPCALL(launch_pack_qe64(d_C + (size_t)e0 * ldc, ldc, ne, B64, n_lo, n_cnt,
+                                   d_coef + 2 * (size_t)t * K * B64, s));
+        else
+          HIPCALL(launch_pack_bop(d_C + (size_t)e0 * ldc, ldc, d_ntrq, ne, 1, n_lo, n_cnt,
+                                  static_cast<char*>(d_bop) + (size_t)t * bop_bytes(1, K), d_ccd,
+                                  s));
+      }
       QeArgs qa{};
+      qa.e_tile_stride = fp64 ? K * B64 : (int)(bop_bytes(1, K) / (2 * 16));
       qa.n_inst = (int)groups.size();
       qa.n_lo = n_lo;
       qa.n_cnt = n_cnt;

@@ -308,9 +308,10 @@ struct QeArgs {
   int32_t total_wg;
   int32_t cplx;             // complex coefficients (state-based form) with a carry row nE
   int32_t carry_first;      // write (1) or accumulate (0) the carried state
-  int32_t pad;
-  const void* bop;          // FP32: A operands C_n(E) in the MFMA lane layout
-  const void* coef;         // FP64: [n_cnt][B] complex
+  int32_t e_tile_stride;    // operand entries between energy tiles (grid y): 32 energies
+                            // per tile in FP32, B in FP64
+  const void* bop;          // FP32: A operands C_n(E) in the MFMA lane layout, per tile
+  const void* coef;         // FP64: [n_cnt][B] complex, per tile
 };
 // QE-Concurrent-S, one time block of bk steps starting at time index J0:
 // C[e][n] = tau sum_{j=1..bk, n <= N(j tau~)} c_n(j tau~) e^{i (E_e - H0)(J0 + j) tau}

@@ -248,8 +248,9 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
   const int lane = tid & 63, wave = tid >> 6;
   const int il = lane & 31, h = lane >> 5;
   Bop* sb = reinterpret_cast<Bop*>(smem);
+  const int e_base = 32 * blockIdx.y;                 // energy tile
   {
-    const Bop* gb = static_cast<const Bop*>(a.bop);
+    const Bop* gb = static_cast<const Bop*>(a.bop) + (int64_t)blockIdx.y * a.e_tile_stride;
     for (int e = tid; e < n_kb * 64; e += kContractThreads) sb[e] = gb[e];
   }
   __syncthreads();
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
     if (mv) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int e = 8 * (v >> 2) + 4 * h + (v & 3);
+        const int e = e_base + 8 * (v >> 2) + 4 * h + (v & 3);
         gq2* p = nullptr;
         bool first = a.first_chunk != 0;
         if (e < a.nE) {
@@ -371,8 +372,9 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
   extern __shared__ __align__(16) unsigned char smem[];
   double2* scoef = reinterpret_cast<double2*>(smem);   // [n_cnt][B]
   const int tid = threadIdx.x;
+  const int e_base = B * blockIdx.y;                   // energy tile
   {
-    const double2* gc = static_cast<const double2*>(a.coef);
+    const double2* gc = static_cast<const double2*>(a.coef) + (int64_t)blockIdx.y * a.e_tile_stride;
     for (int e = tid; e < a.n_cnt * B; e += kContractThreads) scoef[e] = gc[e];
   }
   __syncthreads();
@@ -404,9 +406,9 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
     for (int e = 0; e < B; ++e) {
       double2* p = nullptr;
       bool first = a.first_chunk != 0;
-      if (e < a.nE) {
-        p = out + (int64_t)e * N + m;
-      } else if (a.cplx && e == a.nE && I.carry) {
+      if (e_base + e < a.nE) {
+        p = out + (int64_t)(e_base + e) * N + m;
+      } else if (a.cplx && e_base + e == a.nE && I.carry) {
         p = static_cast<double2*>(I.carry) + col * N + m;
         first = a.carry_first != 0;
       }
@@ -425,28 +427,30 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
 
 hipError_t launch_contract_qe(bool fp64, const QeInst* d_inst, const QeArgs& a, hipStream_t s) {
   if (a.total_wg <= 0 || a.n_cnt <= 0) return hipSuccess;
-  const dim3 grid(a.total_wg), block(kContractThreads);
+  const dim3 block(kContractThreads);
   const int rows = a.nE + (a.cplx ? 1 : 0);          // energies (+ the carried state)
+  if (a.nE < 1 || rows > 129 || (a.cplx && rows > (fp64 ? 16 : 32))) return hipErrorInvalidValue;
   if (!fp64) {
-    if (a.nE < 1 || rows > 32) return hipErrorInvalidValue;
+    const dim3 g2(a.total_wg, (unsigned)ceil_div(rows, 32));
     if (a.cplx) {
       const size_t lds = sizeof(QeBop4) * 64 * (size_t)ceil_div(a.n_cnt, 16);
-      hipLaunchKernelGGL(k_contract_qe_f32<true>, grid, block, lds, s, d_inst, a);
+      hipLaunchKernelGGL(k_contract_qe_f32<true>, g2, block, lds, s, d_inst, a);
     } else {
       const size_t lds = sizeof(QeBop) * 64 * (size_t)ceil_div(a.n_cnt, 16);
-      hipLaunchKernelGGL(k_contract_qe_f32<false>, grid, block, lds, s, d_inst, a);
+      hipLaunchKernelGGL(k_contract_qe_f32<false>, g2, block, lds, s, d_inst, a);
     }
     return hipGetLastError();
   }
   int B = 1;
-  while (B < rows) B *= 2;
+  while (B < rows && B < 16) B *= 2;
+  const dim3 grid2(a.total_wg, (unsigned)ceil_div(rows, B));
   const size_t lds = sizeof(double2) * (size_t)a.n_cnt * B;
   switch (B) {
-    case 1: hipLaunchKernelGGL(k_contract_qe_f64<1>, grid, block, lds, s, d_inst, a); break;
-    case 2: hipLaunchKernelGGL(k_contract_qe_f64<2>, grid, block, lds, s, d_inst, a); break;
-    case 4: hipLaunchKernelGGL(k_contract_qe_f64<4>, grid, block, lds, s, d_inst, a); break;
-    case 8: hipLaunchKernelGGL(k_contract_qe_f64<8>, grid, block, lds, s, d_inst, a); break;
-    case 16: hipLaunchKernelGGL(k_contract_qe_f64<16>, grid, block, lds, s, d_inst, a); break;
+    case 1: hipLaunchKernelGGL(k_contract_qe_f64<1>, grid2, block, lds, s, d_inst, a); break;
+    case 2: hipLaunchKernelGGL(k_contract_qe_f64<2>, grid2, block, lds, s, d_inst, a); break;
+    case 4: hipLaunchKernelGGL(k_contract_qe_f64<4>, grid2, block, lds, s, d_inst, a); break;
+    case 8: hipLaunchKernelGGL(k_contract_qe_f64<8>, grid2, block, lds, s, d_inst, a); break;
+    case 16: hipLaunchKernelGGL(k_contract_qe_f64<16>, grid2, block, lds, s, d_inst, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -92,10 +92,25 @@ def test_quasi_eigenstates_32_energies_and_chunks(csp, ctx):
     assert np.max(np.abs(host(q) - ref)) < 1e-4 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("mode,nE", [("fp32_conc", 49), ("fp64_conc", 37)])
+def test_quasi_eigenstates_energy_tiles(csp, ctx, mode, nE):
+    # several tiles of energies (32 per tile in complex64, 16 in complex128)
+    spec = dict(kind="honeycomb", Lx=13, Ly=9, t=-2.7, W=1.0, disorder_seed=7)
+    g, c = pair(csp, ctx, spec)
+    psi = o.random_phase_states_fast(c.N, 3, 23)
+    E = list(np.linspace(-8.0, 8.0, nE))
+    ref, _ = o.quasi_eigenstates(c, psi, 40, E, Hn=g.halfwidth)
+    dt = torch.complex128 if mode == "fp64_conc" else torch.complex64
+    p = torch.from_numpy(psi).to("cuda:0").to(dt)
+    q, rep = csp.csp_quasi_eigenstates(ctx, g, p, csp.make_params(40, mode=mode), E)
+    err = np.max(np.abs(host(q) - ref)) / np.max(np.abs(ref))
+    assert err < (1e-10 if mode == "fp64_conc" else 1e-4)
+
+
 def test_quasi_eigenstates_errors(csp, ctx):
     g = csp.Lattice(ctx, "square", 8, 8)
     p = torch.zeros((64, 1), dtype=torch.complex64, device="cuda:0")
-    for kw, E in ((dict(mode="fp64_seq"), [0.0]), (dict(mode="fp32_conc"), [0.0] * 33),
+    for kw, E in ((dict(mode="fp64_seq"), [0.0]), (dict(mode="fp32_conc"), [0.0] * 129),
                   (dict(mode="fp32_conc"), [])):
         with pytest.raises(csp.CspError) as e:
             csp.csp_quasi_eigenstates(ctx, g, p, csp.make_params(10, **kw), E)
