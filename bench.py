@@ -416,6 +416,29 @@ def ec_bench(a):
     eps = float(np.max(np.abs(c32h - c64h)) / np.max(np.abs(c64h)))
     sig_err = float(np.max(np.abs(s32h - s64h)) / np.max(np.abs(s64h)))
 
+    # quasi-eigenstates in the paper's QE configuration (D_H = 120, Nt = 1024,
+    # N_E = 5): both concurrent forms against the sequential form, whose cost
+    # is two propagations (forward, backward) of 20 Chebyshev steps per time
+    # step: twice the per-step time of the truncated runs above
+    E5 = list(np.linspace(-0.5, 0.5, 5) * Hn / 1.025)
+    qe_t = {}
+    for name, psi, mode, bq in (("fp64_energy_based", psi64, "fp64_conc", 0),
+                                ("fp64_state_based_b40", psi64, "fp64_conc", 40),
+                                ("fp32_energy_based", psi32, "fp32_conc", 0)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        q, qrep = csp.csp_quasi_eigenstates(ctx, lat, psi, csp.make_params(Nt, mode=mode,
+                                                                         block_b=bq), E5)
+        torch.cuda.synchronize()
+        qe_t[name] = {"s": time.perf_counter() - t, "chebyshev_steps": qrep.amxsy}
+        del q
+        ctx.trim()
+        log("  QE %s (5 energies): %.2f s, %d Chebyshev steps" % (name, qe_t[name]["s"],
+                                                                  qrep.amxsy))
+    qe_seq = 2 * per_step * Nt
+    for v in qe_t.values():
+        v["speedup_vs_fp64_sequential"] = qe_seq / v["s"]
+
     def kern(rep):
         return {"recursion_ms_per_launch": rep.ms_spmm / max(1, rep.spmm_launches),
                 "recursion_alg_GBps": rep.spmm_bytes / max(1e-9, rep.ms_spmm) / 1e6,
@@ -435,6 +458,7 @@ def ec_bench(a):
            "speedup_fp64_vs_fp64_sequential_lower_bound": t_seq / t64,
            "speedup_fp32_vs_fp64_sequential_lower_bound": t_seq / t32,
            "fp32_corr_rel_err": eps, "fp32_sigma_rel_err": sig_err,
+           "qe_5_energies": dict(qe_t, fp64_sequential_s_extrapolated=qe_seq),
            "fp32_kernels": kern(r32), "fp64_kernels": kern(r64)}
     log("  speedup vs sequential recursion: complex128 %.1fx, complex64 %.1fx; sigma rel err "
         "%.2e" % (t_seq / t64, t_seq / t32, sig_err))
