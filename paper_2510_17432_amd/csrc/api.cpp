@@ -681,11 +681,19 @@ struct BlockTab {
   std::vector<ChunkTab> chunks;
 };
 
-std::vector<int> split_columns(int R) {
+// Column groups: powers of two up to kMaxGroupCols for stencil lattices.  An
+// explicit matrix takes groups of any size up to kMaxGroupCols, since its
+// recursion reads the matrix once per group and step (5 columns as 4 + 1
+// would read it twice).
+std::vector<int> split_columns(int R, bool any_size = false) {
   std::vector<int> g;
   while (R > 0) {
     int p = 1;
-    while (p * 2 <= std::min(R, kMaxGroupCols)) p *= 2;
+    if (any_size) {
+      p = std::min(R, kMaxGroupCols);
+    } else {
+      while (p * 2 <= std::min(R, kMaxGroupCols)) p *= 2;
+    }
     g.push_back(p);
     R -= p;
   }
@@ -956,7 +964,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   int64_t vec_elems = 0;   // complex values of one vector over all groups
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
-    for (int Rg : split_columns(ins[i].R)) {
+    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = (int)i;
       g.col0 = col;
@@ -1408,7 +1416,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
-    for (int Rg : split_columns(ins[i].R)) {
+    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = (int)i;
       g.col0 = col;
@@ -1704,7 +1712,7 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
   std::vector<Group> groups;
   {
     int col = 0;
-    for (int Rg : split_columns(R)) {
+    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = 0;
       g.col0 = col;
@@ -1952,7 +1960,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
   std::vector<Group> groups;
   {
     int col = 0;
-    for (int Rg : split_columns(R)) {
+    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = 0;
       g.col0 = col;
@@ -2206,7 +2214,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
   std::vector<Group> groups;
   {
     int col = 0;
-    for (int Rg : split_columns(R)) {
+    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = 0;
       g.col0 = col;
@@ -2483,7 +2491,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
-    for (int Rg : split_columns(ins[i].R)) {
+    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = (int)i;
       g.col0 = col;

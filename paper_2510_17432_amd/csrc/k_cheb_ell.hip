@@ -102,23 +102,13 @@ __device__ __forceinline__ V ld_stream(const CSP_GLOBAL V* p) {
   return __builtin_nontemporal_load(p);
 }
 
+// One wave: rows chunk * 128 + lane and + 64 of the CT columns c0 .. c0 +
+// CT - 1 of its group.
 template <typename T, int CT, bool MOM, bool CARRY>
-__global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ insts, int n_inst,
-                                                  int64_t wave_lo, int64_t wave_hi, ChebStep st) {
+__device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c0, int lane,
+                                         const ChebStep& st) {
   using V2 = typename vt<T>::v2;
   constexpr int U = ell_block<T>();
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-  const int64_t w = wave_lo + xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (w >= wave_hi) return;                         // a whole wave
-  int ii = 0;
-  while (ii + 1 < n_inst && w >= insts[ii + 1].wave0) ++ii;
-  const ChebInst& I = insts[ii];
-  const int64_t lw = w - I.wave0;
-  const int n_tiles = (I.Rg + CT - 1) / CT;
-  const int64_t chunk = lw / n_tiles;               // the slice of 128 rows
-  const int c0 = static_cast<int>(lw - chunk * n_tiles) * CT;
-  const int nc = I.Rg - c0 < CT ? I.Rg - c0 : CT;   // columns of this wave (wave-uniform)
   const int64_t N = I.N;
   const int D = I.ell_D;
   const int64_t s0 = chunk * 128 + lane, s1 = s0 + 64;
@@ -152,12 +142,9 @@ __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ i
 #pragma unroll
   for (int c = 0; c < CT; ++c) ar0[c] = ai0[c] = ar1[c] = ai1[c] = T(0);
 
-  // column c of this wave; a wave with fewer than CT columns (the last tile
-  // of a group whose size is not a multiple of CT) gathers column 0 again
-  // for the missing ones and discards them, so no load sits under a branch
   const CSP_GLOBAL T* xcol[CT];
 #pragma unroll
-  for (int c = 0; c < CT; ++c) xcol[c] = cur + 2 * (int64_t)(c < nc ? c : 0) * N;
+  for (int c = 0; c < CT; ++c) xcol[c] = cur + 2 * (int64_t)c * N;
 
   auto fma_rows = [&](int c, const V2 v, const V2 x0, const V2 x1) {
     ar0[c] = fma(v.x, x0.x, ar0[c]);
@@ -233,7 +220,7 @@ __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ i
   for (int c = 0; c < CT; ++c) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) rec[c][q] = 0.0;
-    if (c >= nc || !v0) continue;
+    if (!v0) continue;
     const int64_t co = 2 * (int64_t)c * N;          // column c0 + c, in T units
     // phi_n and phi_{n-1} at rows s0, s1 (zeros past N)
     const pair2<T> cv = ld_rows<T>(cur + co, s0, s1, v0, v1);
@@ -299,7 +286,6 @@ __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ i
       // one per column, summed over the wave by a fixed butterfly
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        if (c >= nc) continue;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           double x = rec[c][q];
@@ -315,6 +301,38 @@ __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ i
           st.partial[((int64_t)st.mom_slot * st.total_items + item) * 8 + lane] = val;
         }
       }
+    }
+  }
+}
+
+// Waves of CT columns; the last tile of a group whose size is not a
+// multiple of CT runs a body for its own column count (wave-uniform
+// branch), so no wave gathers for a column it does not have.
+template <typename T, int CT, bool MOM, bool CARRY>
+__global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ insts, int n_inst,
+                                                  int64_t wave_lo, int64_t wave_hi, ChebStep st) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int64_t w = wave_lo + xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (w >= wave_hi) return;                         // a whole wave
+  int ii = 0;
+  while (ii + 1 < n_inst && w >= insts[ii + 1].wave0) ++ii;
+  const ChebInst& I = insts[ii];
+  const int64_t lw = w - I.wave0;
+  const int n_tiles = (I.Rg + CT - 1) / CT;
+  const int64_t chunk = lw / n_tiles;               // the slice of 128 rows
+  const int c0 = static_cast<int>(lw - chunk * n_tiles) * CT;
+  const int nc = I.Rg - c0 < CT ? I.Rg - c0 : CT;   // columns of this wave
+  if (nc >= CT) {
+    ell_wave<T, CT, MOM, CARRY>(I, chunk, c0, lane, st);
+  } else if constexpr (CT >= 2) {
+    if (nc == 1) {
+      ell_wave<T, 1, MOM, CARRY>(I, chunk, c0, lane, st);
+    } else if constexpr (CT >= 4) {
+      if (nc == 2)
+        ell_wave<T, 2, MOM, CARRY>(I, chunk, c0, lane, st);
+      else
+        ell_wave<T, 3, MOM, CARRY>(I, chunk, c0, lane, st);
     }
   }
 }

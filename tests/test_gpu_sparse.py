@@ -125,7 +125,8 @@ def run(csp, ctx, g, psi, Nt, mode, b=0, assembly=None, final=False):
 def test_state_assembly_matches_oracle(csp, ctx, name, mode, b):
     print("[gpu] sparse %s %s b=%d" % (name, mode, b), flush=True)
     g, c = pair(csp, ctx, name)
-    psi = o.random_phase_states_fast(c.N, 5, 5)        # column groups 4 + 1
+    # one group of 5: waves of 4 + 1 columns (FP32), 2 + 2 + 1 (FP64)
+    psi = o.random_phase_states_fast(c.N, 5, 5)
     Nt = 120
     ref, cnt = o.propagate(c, psi, Nt, b=0, Hn=g.halfwidth)
     got, rep, _ = run(csp, ctx, g, psi, Nt, mode, b=b)
@@ -137,6 +138,22 @@ def test_state_assembly_matches_oracle(csp, ctx, name, mode, b):
     else:
         assert np.max(np.abs(got - ref)) < 2e-5
         assert rel_dos_err(got, ref, g.halfwidth) < 1e-4
+
+
+@pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
+def test_odd_column_counts(csp, ctx, mode):
+    # groups of any size on an explicit matrix: 3 (waves of 2 + 1), 7 (4 + 3
+    # in FP32, 2 + 2 + 2 + 1 in FP64) and 33 (a group of 32 and a group of 1)
+    g, c = pair(csp, ctx, "rand")
+    for R, seed in ((3, 31), (7, 32), (33, 33)):
+        print("[gpu] sparse %s R=%d" % (mode, R), flush=True)
+        psi = o.random_phase_states_fast(c.N, R, seed)
+        ref, _ = o.propagate(c, psi, 50, b=0, Hn=g.halfwidth)
+        got, _, _ = run(csp, ctx, g, psi, 50, mode, b=16)
+        assert np.max(np.abs(got - ref)) < (1e-10 if mode == "fp64_conc" else 2e-5)
+        mref, _ = o.propagate_moments(c, psi, 50, b=8, halving=False, Hn=g.halfwidth)
+        mgot, _, _ = run(csp, ctx, g, psi, 50, mode, b=8, assembly=csp.CSP_ASSEMBLE_MOMENTS)
+        assert np.max(np.abs(mgot - mref)) < (1e-10 if mode == "fp64_conc" else 2e-5)
 
 
 @pytest.mark.parametrize("name", ["lr4", "rand"])
@@ -174,14 +191,16 @@ def test_moments_final_state(csp, ctx):
 @pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
 def test_quasi_eigenstates(csp, ctx, mode):
     g, c = pair(csp, ctx, "lr3")
-    psi = o.random_phase_states_fast(c.N, 2, 13)
+    psi = o.random_phase_states_fast(c.N, 3, 13)      # waves of 2 + 1 columns
     E = [-3.0, -0.4, 0.0, 1.7]
     Nt = 60
     ref, _ = o.quasi_eigenstates(c, psi, Nt, E, Hn=g.halfwidth)
     dt = torch.complex128 if mode == "fp64_conc" else torch.complex64
-    q, rep = csp.csp_quasi_eigenstates(ctx, g, dev(psi).to(dt), csp.make_params(Nt, mode=mode), E)
-    err = np.max(np.abs(host(q) - ref)) / np.max(np.abs(ref))
-    assert err < (1e-10 if mode == "fp64_conc" else 1e-4)
+    for b in (0, 8):                                  # energy-based, then state-based
+        q, rep = csp.csp_quasi_eigenstates(ctx, g, dev(psi).to(dt),
+                                           csp.make_params(Nt, mode=mode, block_b=b), E)
+        err = np.max(np.abs(host(q) - ref)) / np.max(np.abs(ref))
+        assert err < (1e-10 if mode == "fp64_conc" else 1e-4)
 
 
 def test_stencil_matrix_as_ell_matches_stencil_path(csp, ctx):
