@@ -480,16 +480,16 @@ extern "C" csp_status csp_chebyshev_coefficients(csp_context* c, double x, doubl
   const int64_t nm = std::max<int64_t>(nmax, trunc_nmax(x));
   double* d_a = nullptr;
   int32_t* d_n = nullptr;
-  HIPCALL(hipMalloc(&d_a, sizeof(double) * (nm + 1)));
-  HIPCALL(hipMalloc(&d_n, sizeof(int32_t)));
-  hipError_t e = launch_bessel(x, 1, (int)nm, eta, false, d_a, d_n, c->stream);
+  hipError_t e = hipMalloc(&d_a, sizeof(double) * (nm + 1));
+  if (e == hipSuccess) e = hipMalloc(&d_n, sizeof(int32_t));
+  if (e == hipSuccess) e = launch_bessel(x, 1, (int)nm, eta, false, d_a, d_n, c->stream);
   if (e == hipSuccess) e = launch_complex_coeffs(d_a, nmax, dev_c, c->stream);
   int32_t nt = -1;
   if (e == hipSuccess)
     e = hipMemcpyAsync(&nt, d_n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(d_a);
-  (void)hipFree(d_n);
+  if (d_a) (void)hipFree(d_a);
+  if (d_n) (void)hipFree(d_n);
   if (e != hipSuccess) return fail(CSP_EHIP, "coefficients: %s", hipGetErrorString(e));
   if (n_trunc) *n_trunc = nt;
   return CSP_OK;
@@ -949,13 +949,13 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   std::vector<int32_t> ntr(ncol);
   double* d_a = nullptr;
   int32_t* d_ntr = nullptr;
-  HIPCALL(hipMalloc(&d_a, sizeof(double) * (size_t)ncol * lda));
-  HIPCALL(hipMalloc(&d_ntr, sizeof(int32_t) * ncol));
   struct Free {
     std::vector<void*> p;
     ~Free() { for (void* q : p) (void)hipFree(q); }
   } tmp;
+  HIPCALL(hipMalloc(&d_a, sizeof(double) * (size_t)ncol * lda));
   tmp.p.push_back(d_a);
+  HIPCALL(hipMalloc(&d_ntr, sizeof(int32_t) * ncol));
   tmp.p.push_back(d_ntr);
   HIPCALL(launch_bessel(P.tau_tilde, ncol, nmax, P.eta, true, d_a, d_ntr, s));
   HIPCALL(hipMemcpyAsync(ntr.data(), d_ntr, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, s));
