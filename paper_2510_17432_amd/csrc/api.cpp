@@ -75,6 +75,8 @@ struct csp_context {
   int n_cu = 256;
   void* ws = nullptr;
   size_t ws_size = 0;
+  void* ell_sh = nullptr;           // shadows of explicit-matrix instances (grow-only)
+  size_t ell_sh_size = 0;
   std::vector<hipEvent_t> events;   // pool for profiling
   std::map<std::string, csp_tuning> tuned;  // autotuner results per shape
   hipStream_t cap = nullptr;                 // library stream for HIP graph capture
@@ -210,12 +212,13 @@ extern "C" csp_status csp_context_create(int device, void* hip_stream, csp_conte
 extern "C" csp_status csp_context_trim(csp_context* c) {
   if (!c) return fail(CSP_EINVAL, "context is NULL");
   DeviceGuard dg(c->device);
-  if (c->ws) {
-    HIPCALL(hipStreamSynchronize(c->stream));
-    HIPCALL(hipFree(c->ws));
-  }
+  if (c->ws || c->ell_sh) HIPCALL(hipStreamSynchronize(c->stream));
+  if (c->ws) HIPCALL(hipFree(c->ws));
   c->ws = nullptr;
   c->ws_size = 0;
+  if (c->ell_sh) HIPCALL(hipFree(c->ell_sh));
+  c->ell_sh = nullptr;
+  c->ell_sh_size = 0;
   return CSP_OK;
 }
 
@@ -596,8 +599,55 @@ ChebStep step_args(const ChebPlan& p) {
   st.ow = p.ow;
   st.total_items = p.total_items;
   st.copy_slot = -1;
+  st.sh_in = -1;
+  st.sh_out = -1;
   for (int l = 0; l < 8; ++l) st.slot_out[l] = -1;
   return st;
+}
+
+// Orbital-major shadows of phi_n for the complex64 explicit-matrix instances
+// of two or more columns: two buffers of Rg/2 column pairs each, in the
+// context's own grow-only allocation (outside the workspace).  A step
+// gathers phi_n from one buffer and writes phi_{n+1} to the other.
+csp_status attach_ell_shadows(csp_context* c, std::vector<ChebInst>& sp, bool fp64) {
+  size_t need = 0;
+  for (const ChebInst& I : sp)
+    if (!fp64 && I.kind == CSP_SPARSE && I.Rg >= 2) need += align256((size_t)(I.Rg / 2) * I.N * 32);
+  if (need > c->ell_sh_size) {
+    if (c->ell_sh) {
+      HIPCALL(hipStreamSynchronize(c->stream));
+      HIPCALL(hipFree(c->ell_sh));
+      c->ell_sh = nullptr;
+      c->ell_sh_size = 0;
+    }
+    hipError_t e = hipMalloc(&c->ell_sh, need);
+    if (e != hipSuccess) {
+      c->ell_sh = nullptr;
+      (void)hipGetLastError();
+      return fail(CSP_ENOMEM, "explicit-matrix shadows of %.3f GB could not be allocated (%s)",
+                  need / 1e9, hipGetErrorString(e));
+    }
+    c->ell_sh_size = need;
+  }
+  size_t off = 0;
+  for (ChebInst& I : sp) {
+    I.ell_shadow = nullptr;
+    I.sh_pairs = 0;
+    if (!fp64 && I.kind == CSP_SPARSE && I.Rg >= 2) {
+      I.ell_shadow = static_cast<char*>(c->ell_sh) + off;
+      I.sh_pairs = I.Rg / 2;
+      off += align256((size_t)(I.Rg / 2) * I.N * 32);
+    }
+  }
+  return CSP_OK;
+}
+
+// Shadow buffers of the launch that advances phi_n to phi_{n+1}: phi_n's
+// shadow sits in buffer n mod 2, except at a block start (phi_0 is new and
+// has none).
+void set_shadow(ChebStep& st, int64_t n) {
+  st.sh_in = st.first ? -1 : static_cast<int32_t>(n & 1);
+  st.sh_out = static_cast<int32_t>((n + 1) & 1);
 }
 
 }  // namespace
@@ -1148,6 +1198,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     F.col0 = g.col0;
     fi.push_back(F);
   }
+  CHECK(attach_ell_shadows(c, sp, fp64));
   HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_con, ct.data(), sizeof(ContractInst) * ct.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_fin, fi.data(), sizeof(FinishInst) * fi.size(), hipMemcpyHostToDevice, s));
@@ -1228,6 +1279,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       for (int l = 1; l <= stb.nlev; ++l) stb.slot_out[l - 1] = (produced + l) % S;
       size_t ev = 0;
       if (!from_dev) CHECK(prof.begin(0, &ev));
+      set_shadow(stb, produced);
       HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_spmm, sp_plan.runs, stb, strm));
       if (!from_dev) CHECK(prof.end(ev));
       produced += stb.nlev;
@@ -1545,6 +1597,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         I.carry = nullptr;
       }
     }
+    CHECK(attach_ell_shadows(c, sp, fp64));
     HIPCALL(hipMemcpyAsync(d_spmm, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
     // four slots: phi_n, phi_{n-1} and the two newest levels of a launch
     int cur_slot = -1, prev_slot = -1;
@@ -1595,6 +1648,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
       }
       size_t ev = 0;
       CHECK(prof.begin(0, &ev));
+      set_shadow(st, produced);
       HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, true, carry, d_spmm, sp_plan.runs, st, s));
       CHECK(prof.end(ev));
       ++n_spmm;
@@ -1799,6 +1853,7 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
     wg0 += q.n_wg;
     qi.push_back(q);
   }
+  CHECK(attach_ell_shadows(c, sp, fp64));
   HIPCALL(hipMemcpyAsync(d_inst, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_qi, qi.data(), sizeof(QeInst) * qi.size(), hipMemcpyHostToDevice, s));
 
@@ -1829,6 +1884,7 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
         for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
         size_t ev = 0;
         CHECK(prof.begin(0, &ev));
+        set_shadow(st, produced);
         HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_inst, sp_plan.runs, st, s));
         CHECK(prof.end(ev));
         ++n_spmm;
@@ -2054,6 +2110,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     wg0 += q.n_wg;
     qi.push_back(q);
   }
+  CHECK(attach_ell_shadows(c, sp, fp64));
   HIPCALL(hipMemcpyAsync(d_inst, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_qi, qi.data(), sizeof(QeInst) * qi.size(), hipMemcpyHostToDevice, s));
 
@@ -2076,6 +2133,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
     size_t ev = 0;
     CHECK(prof.begin(0, &ev));
+    set_shadow(st, produced);
     HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_inst, sp_plan.runs, st, s));
     CHECK(prof.end(ev));
     ++n_spmm;
@@ -2305,6 +2363,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
     wg0 += q.n_wg;
     ei.push_back(q);
   }
+  CHECK(attach_ell_shadows(c, sp, fp64));
   HIPCALL(hipMemcpyAsync(d_inst, sp.data(), sizeof(ChebInst) * sp.size(), hipMemcpyHostToDevice, s));
   HIPCALL(hipMemcpyAsync(d_ei, ei.data(), sizeof(EcInst) * ei.size(), hipMemcpyHostToDevice, s));
   int rg_max = 1;
@@ -2330,6 +2389,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
       for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
       size_t ev = 0;
       CHECK(prof.begin(0, &ev));
+      set_shadow(st, produced);
       HIPCALL(launch_cheb(fp64, sp_plan.vec, kt, false, false, d_inst, sp_plan.runs, st, s));
       CHECK(prof.end(ev));
       ++n_spmm;
@@ -2608,12 +2668,14 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
       tsp[gi].slot_stride = groups[gi].stride();
       tsp[gi].psi0 = groups[gi].psi0g;
     }
+    CHECK(attach_ell_shadows(c, tsp, fp64));
     HIPCALL(hipMemcpyAsync(d_spmm, tsp.data(), sizeof(ChebInst) * tsp.size(),
                            hipMemcpyHostToDevice, s));
     ChebStep st = step_args(p);
     st.nlev = p.kt;
     st.slot_cur = 1;
     st.slot_prev = 0;
+    set_shadow(st, 1);   // a step inside a block, as the recursion runs it
     if (mom) {
       // moment form: the two newest levels are kept
       st.slot_out[p.kt - 1] = 2;

@@ -116,6 +116,11 @@ struct ChebInst {
   int64_t wave0;               // first wave of this instance (explicit-matrix runs)
   int32_t ell_D;               // entries per row
   int32_t ell_ct;              // columns per wave
+  // explicit matrix, complex64: orbital-major copies of phi_n for the gathers,
+  // two buffers of sh_pairs column pairs, [2][sh_pairs][N][2] complex values
+  // (null: gathers read the column-major vectors)
+  void* ell_shadow;
+  int64_t sh_pairs;
 };
 
 // Per-launch arguments: levels l = 1..nlev produce phi_{n+l} from
@@ -132,6 +137,9 @@ struct ChebStep {
   int32_t carry_mode;          // 0 none; 1 carry = cc0 phi_n + sum_l ccl[l-1] phi_{n+l};
                                // 2 carry += sum_l ccl[l-1] phi_{n+l}
   int32_t mom_slot;            // launch index inside the partial-sum buffer
+  // explicit matrices: shadow buffer holding phi_n (-1: none, gather from the
+  // column-major vector) and the one receiving phi_{n+1} (-1: not written)
+  int32_t sh_in, sh_out;
   int32_t pad;
   double cc0[2];               // complex coefficient of phi_n (carry_mode 1)
   double ccl[8][2];            // complex coefficient of level l (phi_{n+l})

@@ -42,6 +42,7 @@ namespace ell {
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2), aligned(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct vt;
 template <> struct vt<float> { using v2 = f32x2; };
@@ -103,12 +104,17 @@ __device__ __forceinline__ V ld_stream(const CSP_GLOBAL V* p) {
 }
 
 // One wave: rows chunk * 128 + lane and + 64 of the CT columns c0 .. c0 +
-// CT - 1 of its group.
-template <typename T, int CT, bool MOM, bool CARRY>
+// CT - 1 of its group (c0 even when CT >= 2).  SH: the gathers of the column
+// pairs (c0 + 2p, c0 + 2p + 1) read the orbital-major shadow of phi_n, one
+// 16-byte load per row for both columns (complex64 only); an odd last column
+// is gathered from its column-major vector.
+template <typename T, int CT, bool MOM, bool CARRY, bool SH>
 __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c0, int lane,
                                          const ChebStep& st) {
   using V2 = typename vt<T>::v2;
   constexpr int U = ell_block<T>();
+  static_assert(!SH || std::is_same<T, float>::value, "shadows hold complex64 values");
+  constexpr int NP = SH ? CT / 2 : 0;               // column pairs read from the shadow
   const int64_t N = I.N;
   const int D = I.ell_D;
   const int64_t s0 = chunk * 128 + lane, s1 = s0 + 64;
@@ -145,6 +151,33 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
   const CSP_GLOBAL T* xcol[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) xcol[c] = cur + 2 * (int64_t)c * N;
+  const CSP_GLOBAL f32x4* xsh[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+    xsh[q] = (const CSP_GLOBAL f32x4*)(I.ell_shadow) +
+             ((int64_t)st.sh_in * I.sh_pairs + c0 / 2 + q) * N;
+  // phi_n[j] of column c for rows s0 (j.x) and s1 (j.y)
+  auto gather = [&](const i32x2 j, V2 (&xu)[CT][2]) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      if (c < 2 * NP) {
+        if (c % 2 == 0) {
+          const f32x4 p = xsh[c / 2][j.x], q = xsh[c / 2][j.y];
+          xu[c][0].x = p.x;
+          xu[c][0].y = p.y;
+          xu[c + 1][0].x = p.z;
+          xu[c + 1][0].y = p.w;
+          xu[c][1].x = q.x;
+          xu[c][1].y = q.y;
+          xu[c + 1][1].x = q.z;
+          xu[c + 1][1].y = q.w;
+        }
+      } else {
+        xu[c][0] = ld_c(xcol[c] + 2 * (int64_t)j.x);
+        xu[c][1] = ld_c(xcol[c] + 2 * (int64_t)j.y);
+      }
+    }
+  };
 
   auto fma_rows = [&](int c, const V2 v, const V2 x0, const V2 x1) {
     ar0[c] = fma(v.x, x0.x, ar0[c]);
@@ -173,12 +206,7 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
   for (int kb = 0; kb < Dm; kb += U) {
     V2 x[U][CT][2];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        x[u][c][0] = ld_c(xcol[c] + 2 * (int64_t)jb[0][u].x);
-        x[u][c][1] = ld_c(xcol[c] + 2 * (int64_t)jb[0][u].y);
-      }
+    for (int u = 0; u < U; ++u) gather(jb[0][u], x[u]);
     // block kb + PD U (past the end: the current block again, cached, no branch)
     const int kn = kb + PD * U < Dm ? kb + PD * U : kb;
     i32x2 jn[U];
@@ -206,15 +234,17 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
     i32x2 j;
     V2 v;
     ld_entry(k, j, v);
+    V2 x[CT][2];
+    gather(j, x);
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      fma_rows(c, v, ld_c(xcol[c] + 2 * (int64_t)j.x), ld_c(xcol[c] + 2 * (int64_t)j.y));
+    for (int c = 0; c < CT; ++c) fma_rows(c, v, x[c][0], x[c][1]);
   }
 
   const T scale = st.first ? T(0.5) : T(1);
   const T alpha = scale * static_cast<T>(I.alpha);
   const T beta0 = scale * static_cast<T>(I.beta0);
   double rec[CT][8];
+  pair2<T> outs[CT];
 
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
@@ -231,6 +261,7 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
     o.i0 = alpha * ai0[c] + (beta0 * cv.i0 - pv.i0);
     o.r1 = v1 ? alpha * ar1[c] + (beta0 * cv.r1 - pv.r1) : T(0);
     o.i1 = v1 ? alpha * ai1[c] + (beta0 * cv.i1 - pv.i1) : T(0);
+    outs[c] = o;
     if (outv) st_rows<T>(outv + co, s0, s1, v0, v1, o, true);
     if (copyv) st_rows<T>(copyv + co, s0, s1, v0, v1, cv, true);
 
@@ -280,6 +311,22 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
     }
   }
 
+  // phi_{n+1} of the column pairs into the other shadow buffer, for the
+  // next step's gathers (complex64 instances with a shadow)
+  if constexpr (std::is_same<T, float>::value && CT >= 2) {
+    if (st.sh_out >= 0 && I.ell_shadow && v0) {
+#pragma unroll
+      for (int q = 0; q < CT / 2; ++q) {
+        CSP_GLOBAL f32x4* d = (CSP_GLOBAL f32x4*)(I.ell_shadow) +
+                              ((int64_t)st.sh_out * I.sh_pairs + c0 / 2 + q) * N;
+        const pair2<T>& a0 = outs[2 * q];
+        const pair2<T>& a1 = outs[2 * q + 1];
+        d[s0] = f32x4{a0.r0, a0.i0, a1.r0, a1.i0};
+        if (v1) d[s1] = f32x4{a0.r1, a0.i1, a1.r1, a1.i1};
+      }
+    }
+  }
+
   if constexpr (MOM) {
     if (st.dot_psi0 || st.dot_self) {
       // records [kind][re, im]: <psi0|out>, <psi0|cur>, <out|out>, <out|cur>,
@@ -308,7 +355,7 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
 // Waves of CT columns; the last tile of a group whose size is not a
 // multiple of CT runs a body for its own column count (wave-uniform
 // branch), so no wave gathers for a column it does not have.
-template <typename T, int CT, bool MOM, bool CARRY>
+template <typename T, int CT, bool MOM, bool CARRY, bool SH>
 __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ insts, int n_inst,
                                                   int64_t wave_lo, int64_t wave_hi, ChebStep st) {
   const int lane = threadIdx.x & 63;
@@ -324,15 +371,15 @@ __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ i
   const int c0 = static_cast<int>(lw - chunk * n_tiles) * CT;
   const int nc = I.Rg - c0 < CT ? I.Rg - c0 : CT;   // columns of this wave
   if (nc >= CT) {
-    ell_wave<T, CT, MOM, CARRY>(I, chunk, c0, lane, st);
+    ell_wave<T, CT, MOM, CARRY, SH>(I, chunk, c0, lane, st);
   } else if constexpr (CT >= 2) {
     if (nc == 1) {
-      ell_wave<T, 1, MOM, CARRY>(I, chunk, c0, lane, st);
+      ell_wave<T, 1, MOM, CARRY, false>(I, chunk, c0, lane, st);
     } else if constexpr (CT >= 4) {
       if (nc == 2)
-        ell_wave<T, 2, MOM, CARRY>(I, chunk, c0, lane, st);
+        ell_wave<T, 2, MOM, CARRY, SH>(I, chunk, c0, lane, st);
       else
-        ell_wave<T, 3, MOM, CARRY>(I, chunk, c0, lane, st);
+        ell_wave<T, 3, MOM, CARRY, SH>(I, chunk, c0, lane, st);
     }
   }
 }
@@ -354,23 +401,30 @@ hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, int ct, const ChebIn
   if (st.nlev != 1 || (carry && !mom)) return hipErrorInvalidValue;
   if (ct != 1 && ct != 2 && ct != 4) return hipErrorInvalidValue;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
-#define CSP_ELL(T, CT, M, CY)                                                                     \
-  hipLaunchKernelGGL((ell::k_cheb_ell<T, CT, M, CY>), grid, block, 0, s, d_inst, n_inst, wave_lo, \
-                     wave_hi, st)
-#define CSP_ELL_CT(T, M, CY)                \
-  do {                                      \
-    if (ct == 1) CSP_ELL(T, 1, M, CY);      \
-    else if (ct == 2) CSP_ELL(T, 2, M, CY); \
-    else CSP_ELL(T, 4, M, CY);              \
+  // complex64 waves of two or four columns gather phi_n from its shadow
+  // when the previous step wrote one
+  const bool sh = !fp64 && ct >= 2 && st.sh_in >= 0;
+#define CSP_ELL(T, CT, M, CY, SH)                                                                 \
+  hipLaunchKernelGGL((ell::k_cheb_ell<T, CT, M, CY, SH>), grid, block, 0, s, d_inst, n_inst,      \
+                     wave_lo, wave_hi, st)
+#define CSP_ELL_CT(T, M, CY, SH)                \
+  do {                                          \
+    if (ct == 1) CSP_ELL(T, 1, M, CY, false);   \
+    else if (ct == 2) CSP_ELL(T, 2, M, CY, SH); \
+    else CSP_ELL(T, 4, M, CY, SH);              \
   } while (0)
   if (fp64) {
-    if (carry) CSP_ELL_CT(double, true, true);
-    else if (mom) CSP_ELL_CT(double, true, false);
-    else CSP_ELL_CT(double, false, false);
+    if (carry) CSP_ELL_CT(double, true, true, false);
+    else if (mom) CSP_ELL_CT(double, true, false, false);
+    else CSP_ELL_CT(double, false, false, false);
+  } else if (sh) {
+    if (carry) CSP_ELL_CT(float, true, true, true);
+    else if (mom) CSP_ELL_CT(float, true, false, true);
+    else CSP_ELL_CT(float, false, false, true);
   } else {
-    if (carry) CSP_ELL_CT(float, true, true);
-    else if (mom) CSP_ELL_CT(float, true, false);
-    else CSP_ELL_CT(float, false, false);
+    if (carry) CSP_ELL_CT(float, true, true, false);
+    else if (mom) CSP_ELL_CT(float, true, false, false);
+    else CSP_ELL_CT(float, false, false, false);
   }
 #undef CSP_ELL_CT
 #undef CSP_ELL
