@@ -22,10 +22,19 @@
 //   - the index and value loads of the next U entries are issued after the
 //     gathers of the current ones, so the HBM latency of the matrix stream
 //     overlaps the (mostly cache-hit) vector gathers.
+//   - complex64: the gathers read an orbital-major copy of phi_n ("shadow",
+//     [pairs][N][2] complex values), so one 16-byte load per row serves two
+//     columns; each step writes phi_{n+1}'s copy beside its column-major
+//     store, into the other of two buffers.  A block's first step (phi_0
+//     new) and an odd last column gather from the column-major vectors.
 // Measured on MI355X (D_H = 233, 4.76 M rows, two columns): the matrix
-// stream alone runs at the read ceiling (about 6 TB/s); with the gathers
-// the step runs at 4.2-4.5 TB/s of algorithmic bytes, the same for
-// interleaved rows, deeper pipelines and other block sizes.
+// stream alone runs at the read ceiling (about 6 TB/s); the gathers set the
+// pace.  The cost follows both the load instructions and the cache lines
+// they touch: two columns in one 16-byte load (1 KB per wave, 8 lines) beat
+// two 8-byte loads (2 x 4 lines) by 15-19 % in isolation, whereas four
+// columns in two 16-byte loads (16 half-used lines each) lost to four
+// 8-byte loads; interleaved row pairs, deeper pipelines and other block
+// sizes changed nothing.
 // Moment epilogue and carried state as the stencil kernel: one record of 8
 // FP64 sums per (column, 128-row chunk), record index column-major.
 #include <type_traits>
@@ -186,58 +195,75 @@ __device__ __forceinline__ void ell_wave(const ChebInst& I, int64_t chunk, int c
     ai1[c] = fma(v.y, x1.y, ai1[c]);
   };
 
-  // Blocks of U entries, the matrix loads running PD blocks ahead of the
-  // gathers.  In each block the gathers (which need the block's indices)
-  // are issued first and the matrix loads of block kb + PD U after them;
-  // loads complete in issue order, so waiting for the gathers waits for the
-  // matrix loads issued before them (blocks up to kb + (PD - 1) U) and
-  // leaves the newest in flight.
-  const int Dm = D - D % U;
-  i32x2 jb[PD][U];
-  V2 vb[PD][U];
-  if (Dm > 0) {
+  if constexpr (SH) {
+    // Two columns per 16-byte gather: a plain loop unrolled by 4 lets the
+    // compiler batch the loads of four entries (measured faster here than
+    // the explicit pipeline below: 1.92 against 1.95 ms per step at D_H =
+    // 233, 1.93 against 2.06 ms at D_H = 61 with 10 columns).
+#pragma unroll 4
+    for (int k = 0; k < D; ++k) {
+      i32x2 j;
+      V2 v;
+      ld_entry(k, j, v);
+      V2 x[CT][2];
+      gather(j, x);
 #pragma unroll
-    for (int d = 0; d < PD; ++d) {
-      const int k0 = d * U < Dm ? d * U : 0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) ld_entry(k0 + u, jb[d][u], vb[d][u]);
+      for (int c = 0; c < CT; ++c) fma_rows(c, v, x[c][0], x[c][1]);
     }
-  }
-  for (int kb = 0; kb < Dm; kb += U) {
-    V2 x[U][CT][2];
+  } else {
+    // Blocks of U entries, the matrix loads running PD blocks ahead of the
+    // gathers.  In each block the gathers (which need the block's indices)
+    // are issued first and the matrix loads of block kb + PD U after them;
+    // loads complete in issue order, so waiting for the gathers waits for the
+    // matrix loads issued before them (blocks up to kb + (PD - 1) U) and
+    // leaves the newest in flight.
+    const int Dm = D - D % U;
+    i32x2 jb[PD][U];
+    V2 vb[PD][U];
+    if (Dm > 0) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) gather(jb[0][u], x[u]);
-    // block kb + PD U (past the end: the current block again, cached, no branch)
-    const int kn = kb + PD * U < Dm ? kb + PD * U : kb;
-    i32x2 jn[U];
-    V2 vn[U];
+      for (int d = 0; d < PD; ++d) {
+        const int k0 = d * U < Dm ? d * U : 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) ld_entry(kn + u, jn[u], vn[u]);
+        for (int u = 0; u < U; ++u) ld_entry(k0 + u, jb[d][u], vb[d][u]);
+      }
+    }
+    for (int kb = 0; kb < Dm; kb += U) {
+      V2 x[U][CT][2];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+      for (int u = 0; u < U; ++u) gather(jb[0][u], x[u]);
+      // block kb + PD U (past the end: the current block again, cached, no branch)
+      const int kn = kb + PD * U < Dm ? kb + PD * U : kb;
+      i32x2 jn[U];
+      V2 vn[U];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) fma_rows(c, vb[0][u], x[u][c][0], x[u][c][1]);
+      for (int u = 0; u < U; ++u) ld_entry(kn + u, jn[u], vn[u]);
 #pragma unroll
-    for (int d = 0; d + 1 < PD; ++d)
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) fma_rows(c, vb[0][u], x[u][c][0], x[u][c][1]);
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          jb[d][u] = jb[d + 1][u];
+          vb[d][u] = vb[d + 1][u];
+        }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        jb[d][u] = jb[d + 1][u];
-        vb[d][u] = vb[d + 1][u];
+        jb[PD - 1][u] = jn[u];
+        vb[PD - 1][u] = vn[u];
       }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      jb[PD - 1][u] = jn[u];
-      vb[PD - 1][u] = vn[u];
     }
-  }
-  for (int k = Dm; k < D; ++k) {
-    i32x2 j;
-    V2 v;
-    ld_entry(k, j, v);
-    V2 x[CT][2];
-    gather(j, x);
+    for (int k = Dm; k < D; ++k) {
+      i32x2 j;
+      V2 v;
+      ld_entry(k, j, v);
+      V2 x[CT][2];
+      gather(j, x);
 #pragma unroll
-    for (int c = 0; c < CT; ++c) fma_rows(c, v, x[c][0], x[c][1]);
+      for (int c = 0; c < CT; ++c) fma_rows(c, v, x[c][0], x[c][1]);
+    }
   }
 
   const T scale = st.first ? T(0.5) : T(1);
