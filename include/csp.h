@@ -229,7 +229,10 @@ csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
  * FP64 and FP32.  H0 = 0 and |H| = margin * max_s sum_k |val_sk|
  * (Gershgorin, reduced on the GPU in FP64; margin <= 0 selects 1.025).
  * Such a lattice runs through every propagation entry point; its recursion
- * applies one Chebyshev step per launch (a gathered sparse product).
+ * applies one Chebyshev step per launch (a gathered sparse product).  In
+ * complex64 a call on it also keeps, per group of Rg columns, two
+ * orbital-major copies of floor(Rg/2) column pairs (32 floor(Rg/2) N bytes)
+ * in context memory outside mem_cap_bytes, released by csp_context_trim. 
  * csp_lattice_onsite and csp_lattice_neighbors return CSP_EUNSUPPORTED for
  * it.  Errors: CSP_EINVAL for N outside [1, 2^31), D outside [1, 4096], a
  * column index >= N, a non-finite value or an all-zero matrix; CSP_ENOMEM
@@ -428,7 +431,7 @@ csp_status csp_select_block(csp_context *ctx, const csp_lattice *lat, int32_t R,
  * These are the practical ceilings beside the published HBM peak. */
 csp_status csp_bandwidth_probe(csp_context *ctx, uint64_t bytes, double *gbs_out);
 
-/* Free cached workspace of the context. */
+/* Free cached workspace of the context (and the explicit-matrix copies). */
 csp_status csp_context_trim(csp_context *ctx);
 
 #ifdef __cplusplus
