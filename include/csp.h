@@ -232,7 +232,7 @@ csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
  * applies one Chebyshev step per launch (a gathered sparse product).  In
  * complex64 a call on it also keeps, per group of Rg columns, two
  * orbital-major copies of floor(Rg/2) column pairs (32 floor(Rg/2) N bytes)
- * in context memory outside mem_cap_bytes, released by csp_context_trim. 
+ * in context memory outside mem_cap_bytes, released by csp_context_trim.
  * csp_lattice_onsite and csp_lattice_neighbors return CSP_EUNSUPPORTED for
  * it.  Errors: CSP_EINVAL for N outside [1, 2^31), D outside [1, 4096], a
  * column index >= N, a non-finite value or an all-zero matrix; CSP_ENOMEM
