@@ -154,6 +154,10 @@ def test_odd_column_counts(csp, ctx, mode):
         mref, _ = o.propagate_moments(c, psi, 50, b=8, halving=False, Hn=g.halfwidth)
         mgot, _, _ = run(csp, ctx, g, psi, 50, mode, b=8, assembly=csp.CSP_ASSEMBLE_MOMENTS)
         assert np.max(np.abs(mgot - mref)) < (1e-10 if mode == "fp64_conc" else 2e-5)
+    # released workspace and orbital-major copies are rebuilt by the next call
+    ctx.trim()
+    again, _, _ = run(csp, ctx, g, psi, 50, mode, b=16)
+    assert np.array_equal(again, got)
 
 
 @pytest.mark.parametrize("name", ["lr4", "rand"])
