@@ -186,6 +186,24 @@ def test_fp64_concurrent(csp, ctx, b):
     assert rep.amxsy * 3 == cnt["amxsy"] and rep.axpy * 3 == cnt["axpy"]
 
 
+@pytest.mark.parametrize("mode", ["fp64_seq", "fp64_conc", "fp32_conc"])
+def test_smallest_lattices(csp, ctx, mode):
+    # side 3 (the smallest without doubled bonds), periodic and open, one time
+    # step and several blocks; a strip of 64 V values covers the whole row
+    print("[gpu] smallest lattices %s" % mode, flush=True)
+    for spec in (dict(kind="chain", Lx=3, t=1.0, W=0.5, disorder_seed=1),
+                 dict(kind="square", Lx=3, Ly=3, t=-1.0, W=1.0, disorder_seed=2),
+                 dict(kind="honeycomb", Lx=3, Ly=3, t=-2.7, W=0.3, disorder_seed=3),
+                 dict(kind="square", Lx=3, Ly=4, t=1.0, periodic_x=False, periodic_y=False)):
+        g, c = pair(csp, ctx, spec)
+        for Nt, b in ((1, 0), (9, 4)):
+            b = 0 if mode == "fp64_seq" else b
+            psi = o.random_phase_states_fast(c.N, 2, 6)
+            ref, _ = o.propagate(c, psi, Nt, b=0)
+            got, _, _ = run_gpu(csp, ctx, g, psi, Nt, mode, b=b)
+            assert np.max(np.abs(got - ref)) < (2e-5 if mode == "fp32_conc" else 1e-12), spec
+
+
 def rel_dos_err(c32, c64, Hn):
     _, D32, _ = o.dos(c32, Hn)
     _, D64, _ = o.dos(c64, Hn)

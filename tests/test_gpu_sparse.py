@@ -140,6 +140,21 @@ def test_state_assembly_matches_oracle(csp, ctx, name, mode, b):
         assert rel_dos_err(got, ref, g.halfwidth) < 1e-4
 
 
+@pytest.mark.parametrize("mode", ["fp64_seq", "fp64_conc", "fp32_conc"])
+def test_matrix_smaller_than_one_slice(csp, ctx, mode):
+    # N = 50 < the 128 rows of one slice (rows past N padded), irregular rows;
+    # one and several columns, one time step and several blocks
+    col, val = ci.random_symmetric_ell(50, 120, seed=8)
+    g = csp.Lattice.sparse(ctx, col, val)
+    c = o.SparseLattice(col, val)
+    for R, Nt, b in ((1, 1, 0), (2, 1, 0), (2, 9, 4), (3, 9, 0)):
+        b = 0 if mode == "fp64_seq" else b
+        psi = o.random_phase_states_fast(c.N, R, 40 + R)
+        ref, _ = o.propagate(c, psi, Nt, b=0, Hn=g.halfwidth)
+        got, _, _ = run(csp, ctx, g, psi, Nt, mode, b=b)
+        assert np.max(np.abs(got - ref)) < (2e-5 if mode == "fp32_conc" else 1e-12), (R, Nt, b)
+
+
 @pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
 def test_odd_column_counts(csp, ctx, mode):
     # column groups of an explicit matrix: 3 (FP32 one group, waves of 2 + 1;
