@@ -732,19 +732,16 @@ struct BlockTab {
 };
 
 // Column groups: powers of two up to kMaxGroupCols for stencil lattices.  An
-// explicit matrix is read once per group and step, so it takes larger groups:
-// any size up to kMaxGroupCols in FP32 (the last wave of a group runs a body
-// for its own column count), even sizes in FP64, whose two-column waves ran
-// 5 % slower beside a one-column wave than with that column as a group of its
-// own (MI355X, D_H = 121, 5 columns).
-std::vector<int> split_columns(int R, bool sparse = false, bool fp64 = false) {
+// explicit matrix is read once per group and step, so it takes groups of any
+// size up to kMaxGroupCols (the last wave of a group runs a body for its own
+// column count; 5 columns as one group instead of 4 + 1: 3.93 -> 3.83 ms per
+// complex128 step at D_H = 121 on MI355X).
+std::vector<int> split_columns(int R, bool sparse = false) {
   std::vector<int> g;
   while (R > 0) {
     int p = 1;
-    if (sparse && !fp64) {
+    if (sparse) {
       p = std::min(R, kMaxGroupCols);
-    } else if (sparse && R >= 2) {
-      p = std::min(R, kMaxGroupCols) & ~1;
     } else {
       while (p * 2 <= std::min(R, kMaxGroupCols)) p *= 2;
     }
@@ -1018,7 +1015,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   int64_t vec_elems = 0;   // complex values of one vector over all groups
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
-    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE, fp64)) {
+    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = (int)i;
       g.col0 = col;
@@ -1472,7 +1469,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
-    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE, fp64)) {
+    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = (int)i;
       g.col0 = col;
@@ -1770,7 +1767,7 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
   std::vector<Group> groups;
   {
     int col = 0;
-    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE, fp64)) {
+    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = 0;
       g.col0 = col;
@@ -2020,7 +2017,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
   std::vector<Group> groups;
   {
     int col = 0;
-    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE, fp64)) {
+    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = 0;
       g.col0 = col;
@@ -2276,7 +2273,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
   std::vector<Group> groups;
   {
     int col = 0;
-    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE, fp64)) {
+    for (int Rg : split_columns(R, L->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = 0;
       g.col0 = col;
@@ -2555,7 +2552,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
-    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE, fp64)) {
+    for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
       Group g;
       g.inst = (int)i;
       g.col0 = col;

@@ -412,10 +412,13 @@ __global__ __launch_bounds__(256) void k_cheb_ell(const ChebInst* __restrict__ i
 
 }  // namespace ell
 
+// Up to four columns per wave in both precisions (measured on MI355X at
+// D_H = 121 with 5 columns, complex128: 4.63 ms per step with two-column
+// waves, 3.83 ms with four).
 int ell_columns_per_wave(bool fp64, int Rg) {
-  const int cap = fp64 ? 2 : 4;
+  (void)fp64;
   int ct = 1;
-  while (ct * 2 <= Rg && ct * 2 <= cap) ct *= 2;
+  while (ct * 2 <= Rg && ct * 2 <= 4) ct *= 2;
   return ct;
 }
 

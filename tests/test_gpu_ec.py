@@ -109,8 +109,8 @@ def test_ec_correlation_matches_oracle(csp, ctx, mode, case):
 def test_ec_explicit_matrix(csp, ctx, mode):
     g, c = sparse_pair(csp, ctx, 14, 3.0, 2)
     for alpha in (0, 1):
-        # 5 energies x 3 columns (FP32 waves of 2 + 1, FP64 groups of 2 and 1):
-        # the current operator over two tiles of 8 bras
+        # 5 energies x 3 columns (waves of 2 + 1): the current operator over
+        # two tiles of 8 bras
         check(csp, ctx, g, c, 3, [-2.0, -0.7, 0.1, 0.9, 1.5], 15, 45, alpha, mode)
 
 

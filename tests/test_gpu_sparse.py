@@ -125,7 +125,7 @@ def run(csp, ctx, g, psi, Nt, mode, b=0, assembly=None, final=False):
 def test_state_assembly_matches_oracle(csp, ctx, name, mode, b):
     print("[gpu] sparse %s %s b=%d" % (name, mode, b), flush=True)
     g, c = pair(csp, ctx, name)
-    # FP32: one group of 5 (waves of 4 + 1 columns); FP64: groups of 4 and 1
+    # one group of 5 columns: waves of 4 + 1
     psi = o.random_phase_states_fast(c.N, 5, 5)
     Nt = 120
     ref, cnt = o.propagate(c, psi, Nt, b=0, Hn=g.halfwidth)
@@ -157,8 +157,8 @@ def test_matrix_smaller_than_one_slice(csp, ctx, mode):
 
 @pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
 def test_odd_column_counts(csp, ctx, mode):
-    # column groups of an explicit matrix: 3 (FP32 one group, waves of 2 + 1;
-    # FP64 2 + 1), 7 (FP32 waves of 4 + 3; FP64 groups of 6 and 1) and 33 (32 + 1)
+    # column groups of an explicit matrix: 3 (waves of 2 + 1), 7 (waves of
+    # 4 + 3) and 33 (groups of 32 and 1)
     g, c = pair(csp, ctx, "rand")
     for R, seed in ((3, 31), (7, 32), (33, 33)):
         print("[gpu] sparse %s R=%d" % (mode, R), flush=True)
@@ -210,7 +210,7 @@ def test_moments_final_state(csp, ctx):
 @pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
 def test_quasi_eigenstates(csp, ctx, mode):
     g, c = pair(csp, ctx, "lr3")
-    psi = o.random_phase_states_fast(c.N, 3, 13)      # FP32 waves of 2 + 1 columns
+    psi = o.random_phase_states_fast(c.N, 3, 13)      # waves of 2 + 1 columns
     E = [-3.0, -0.4, 0.0, 1.7]
     Nt = 60
     ref, _ = o.quasi_eigenstates(c, psi, Nt, E, Hn=g.halfwidth)
