@@ -48,6 +48,12 @@ __device__ __forceinline__ float2 ldg2(const gf2* p) {
   const f32x2 t = *p;
   return make_float2(t.x, t.y);
 }
+// Chebyshev vectors are read once per contraction: non-temporal loads
+// (measured on MI355X, graphene workload: 29.65 -> 29.23 ms per launch)
+__device__ __forceinline__ float2 ldg2_stream(const gf2* p) {
+  const f32x2 t = __builtin_nontemporal_load(p);
+  return make_float2(t.x, t.y);
+}
 __device__ __forceinline__ void stg2(gf2* p, float2 v) {
   f32x2 t;
   t.x = v.x;
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
       int64_t off = (int64_t)((a.n_lo + rel0) % a.S) * sstr;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        xn[v] = (mv && rel0 + v < a.n_cnt) ? ldg2(slots + off + m) : make_float2(0.f, 0.f);
+        xn[v] = (mv && rel0 + v < a.n_cnt) ? ldg2_stream(slots + off + m) : make_float2(0.f, 0.f);
         off += sstr;
         if (off >= wrap) off -= wrap;
       }
