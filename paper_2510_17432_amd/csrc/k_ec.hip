@@ -387,8 +387,9 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
 // Workgroup per (instance, column, slice) and tile of 16 energies (grid y).
 // Per step of 32 orbitals the chunk's 128 orders and the 16 bras are staged
 // in LDS with coalesced loads (32 lanes read one 512-byte row); thread t
-// accumulates energy t % 16 against orders t / 16 + 16 p, p = 0..7, with
-// FMAs, reading each bra value once for its eight orders.
+// accumulates energies t % 8 and t % 8 + 8 against orders t / 8 + 32 p,
+// p = 0..3, with FMAs: six LDS reads per eight complex products (the kernel
+// is bound by LDS reads; one energy against eight orders took nine).
 constexpr int kEc64Row = 33;         // complex values per LDS row (padded)
 
 template <int NE>
@@ -437,10 +438,13 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
     for (int j = 0; j < 2; ++j) rb[j] = (bok[j] && in) ? brow[j][o] : make_double2(0.0, 0.0);
   };
 
-  const int e = tid & 15, p0 = tid >> 4;
-  double sr[8], si[8];
+  constexpr int NQ = NE > 8 ? 2 : 1;                // energies per thread
+  const int eq = tid & 7, og = tid >> 3;           // energies eq + 8 q, orders og + 32 p
+  double sr[NQ][4], si[NQ][4];
 #pragma unroll
-  for (int p = 0; p < 8; ++p) sr[p] = si[p] = 0.0;
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) sr[q][p] = si[q][p] = 0.0;
   if (s_beg < s_end) fetch(s_beg);
   for (int64_t s = s_beg; s < s_end; s += 32) {
     __syncthreads();
@@ -450,24 +454,33 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
     for (int j = 0; j < 2; ++j) sb[(8 * j + rsub) * kEc64Row + col] = rb[j];
     __syncthreads();
     if (s + 32 < s_end) fetch(s + 32);
-    if (e < NE) {
+    if (eq < NE) {
       for (int o = 0; o < 32; ++o) {
-        const double2 x = sb[e * kEc64Row + o];
+        double2 x[NQ];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          const double2 f = sa[(p0 + 16 * p) * kEc64Row + o];
-          sr[p] = fma(x.x, f.x, fma(x.y, f.y, sr[p]));
-          si[p] = fma(x.x, f.y, fma(-x.y, f.x, si[p]));
+        for (int q = 0; q < NQ; ++q) x[q] = sb[(eq + 8 * q) * kEc64Row + o];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const double2 f = sa[(og + 32 * p) * kEc64Row + o];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            sr[q][p] = fma(x[q].x, f.x, fma(x[q].y, f.y, sr[q][p]));
+            si[q][p] = fma(x[q].x, f.y, fma(-x[q].y, f.x, si[q][p]));
+          }
         }
       }
     }
   }
-  if (e < NE && e0 + e < a.nE) {
-    double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
+  double2* out = static_cast<double2*>(I.partial) + ((int64_t)c * I.n_slices + sl) * a.K * a.ldp;
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int r = p0 + 16 * p;
-      if (r < a.n_cnt) out[(int64_t)r * a.ldp + e0 + e] = make_double2(sr[p], si[p]);
+  for (int q = 0; q < NQ; ++q) {
+    const int e = eq + 8 * q;
+    if (e < NE && e0 + e < a.nE) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int r = og + 32 * p;
+        if (r < a.n_cnt) out[(int64_t)r * a.ldp + e0 + e] = make_double2(sr[q][p], si[q][p]);
+      }
     }
   }
 }
