@@ -263,6 +263,28 @@ def test_batch_mixes_stencil_and_explicit(csp, ctx):
         assert np.max(np.abs(host(corr) - ref)) < 2e-5
 
 
+def test_batch_of_two_explicit_matrices(csp, ctx):
+    # two complex64 explicit instances of different sizes and column counts
+    # (each with its own orbital-major copies) beside a stencil lattice, in
+    # several time blocks
+    ga, ca = pair(csp, ctx, "rand")
+    gb, cb = pair(csp, ctx, "lr4")
+    gs = csp.Lattice(ctx, "square", 17, 15, t=1.0, W=1.0, disorder_seed=2)
+    cs = o.Lattice("square", 17, 15, t=1.0, W=1.0, disorder_seed=2)
+    Nt = 40
+    psis, refs = [], []
+    for c, R, seed, Hn in ((ca, 3, 21, ga.halfwidth), (cs, 2, 22, gs.halfwidth),
+                           (cb, 6, 23, gb.halfwidth)):
+        psi = o.random_phase_states_fast(c.N, R, seed)
+        psis.append(dev(psi).to(torch.complex64))
+        refs.append(o.propagate(c, psi, Nt, b=0, Hn=Hn)[0])
+    for b in (8, 0):
+        params = csp.make_params(Nt, mode="fp32_conc", block_b=b)
+        corrs, _ = csp.csp_propagate_batch(ctx, [ga, gs, gb], psis, params)
+        for corr, ref in zip(corrs, refs):
+            assert np.max(np.abs(host(corr) - ref)) < 2e-5
+
+
 def test_autotune_explicit_matrix(csp, ctx):
     g, c = pair(csp, ctx, "lr4")
     params = csp.make_params(256, mode="fp32_conc")
