@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CSP_ABI_VERSION 1
+#define CSP_ABI_VERSION 2
 
 typedef enum {
     CSP_OK = 0,
@@ -296,8 +296,13 @@ csp_status csp_chebyshev_step(csp_context *ctx, const csp_lattice *lat, int32_t 
 /* Propagate the R states dev_psi0 ([N][R], dtype per mode) for Nt steps of
  * the rescaled size params->tau_tilde and write the correlations
  * dev_corr[(Nt+1)][R] (complex128, device) with
- * C_r(t_j) = <psi0_r|psi_r(t_j)>.  dev_final (may be NULL) receives
- * psi(t_Nt) in the layout and dtype of psi0.  rep may be NULL. */
+ * C_r(t_j) = <psi0_r|psi_r(t_j)>, psi_r(t_j) = exp(-i H~ j tau~) psi0_r: the
+ * propagator is the Chebyshev expansion of exp(-i H~ tau~) of Sec. II.A, so
+ * with a spectral centre H0 != 0 the states and correlations carry
+ * exp(-i (H - H0) t_j), i.e. C_r(t_j) = exp(i H0 t_j) <psi0_r|exp(-i H t_j)|psi0_r>
+ * (csp_dos takes H0 as its centre to place the DOS on the true energies).
+ * dev_final (may be NULL) receives psi(t_Nt) in the layout and dtype of
+ * psi0.  rep may be NULL. */
 csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *dev_psi0,
                          int32_t R, const csp_params *params, double *dev_corr,
                          void *dev_final, csp_report *rep);
@@ -312,7 +317,10 @@ csp_status csp_propagate(csp_context *ctx, const csp_lattice *lat, const void *d
  * (a_0 = J_0, a_n = 2 J_n): the forward and backward time sums of Eq. QE
  * merged as in Eq. QE_coeff, no window.  This equals
  * tau sum_{j=0}^{Nt} (2 - delta_j0)/2 [e^{iE't_j} psi(t_j) + e^{-iE't_j} psi(-t_j)]
- * of the sequentially propagated states up to rounding.  Writes dev_qe
+ * of the sequentially propagated states up to rounding.  This is Eq. QE_coeff
+ * as printed: its quadrature weight is tau with no factor 1/(2 pi), so
+ * Psi(E) is 2 pi times the integral of Eq. QE (the factor cancels in the
+ * normalised conductivity correlation).  Writes dev_qe
  * [n_E][N][R] in the dtype of psi0.  params->mode CSP_FP32_CONC (complex64
  * recursion, split-bf16 MFMA accumulation) or CSP_FP64_CONC (complex128);
  * 1 <= n_E <= 128 (one recursion serves all energies, contracted in tiles of
@@ -379,13 +387,20 @@ csp_status csp_propagate_batch(csp_context *ctx, int32_t n_inst, const csp_latti
 
 /* Density of states from correlations (Sec. III): with t_j = j*tau,
  * tau = tau_tilde/halfwidth, C_{-j} = conj(C_j) and window w_j,
- * D_r(E_k) = (tau/2pi) Re sum_{j=-Nt}^{Nt-1} w_j C_j exp(i E_k t_j) at
- * E_k = k*pi/(Nt*tau), k = -Nt..Nt-1.  dev_corr is [(Nt+1)][R] complex128;
- * writes dev_E[2Nt], dev_D[2Nt][R] and, if not NULL, the column mean
- * dev_Dmean[2Nt], all FP64 on the device. */
+ * D_r(H0 + E_k) = (tau/2pi) Re sum_{j=-Nt}^{Nt-1} w_j C_j exp(i E_k t_j) at
+ * E_k = k*pi/(Nt*tau), k = -Nt..Nt-1.  The correlations are those of
+ * csp_propagate, which carry the centred propagator exp(-i (H - H0) t), so
+ * this is the transform of Sec. III placed on the energies H0 + E_k of the
+ * true spectrum [H0 - halfwidth, H0 + halfwidth]: pass the lattice's H0 as
+ * `center` (0 for the default lattices).  dev_corr is [(Nt+1)][R]
+ * complex128; writes dev_E[2Nt] (= center + E_k), dev_D[2Nt][R] and, if not
+ * NULL, the column mean dev_Dmean[2Nt], all FP64 on the device.  Uses a
+ * table of 2Nt complex128 twiddles that it allocates and frees; returns
+ * after the stream has finished.  Errors: CSP_EINVAL for Nt < 1, R < 1,
+ * halfwidth <= 0, a non-finite center or an unknown window. */
 csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t R,
-                   double halfwidth, double tau_tilde, int32_t window, double *dev_E,
-                   double *dev_D, double *dev_Dmean);
+                   double halfwidth, double center, double tau_tilde, int32_t window,
+                   double *dev_E, double *dev_D, double *dev_Dmean);
 
 /* Autotuner.  For the instances (lats[i], R[i]) with params->mode and
  * params->assembly, times on this device every recursion launch shape

@@ -411,7 +411,9 @@ def quasi_eigenstates(lat, psi0, Nt, energies, Hn=None, H0=0.0, tau=math.pi, eta
     forward and backward propagation by exp(-+iH tau_p) step by step and the
     sum of Eq. QE_coeff over the propagated states,
       Psi(E) = tau_p sum_{j=0}^{Nt} (2 - delta_j0)/2 [e^{iE't_j} psi(t_j) + e^{-iE't_j} psi(-t_j)],
-    tau_p = tau / Hn, t_j = j tau_p, E' = E - H0.  psi0 is [N][R]; returns
+    tau_p = tau / Hn, t_j = j tau_p, E' = E - H0.  The weights are those of
+    Eq. QE_coeff as printed (quadrature weight tau_p, no 1/(2 pi)), so Psi(E)
+    is 2 pi times the integral of Eq. QE.  psi0 is [N][R]; returns
     ([n_E][N][R] complex, counters)."""
     psi0 = np.asarray(psi0, dtype=np.complex128)
     if psi0.ndim == 1:
@@ -595,15 +597,19 @@ def hann(Nt):
     return 0.5 * (1.0 + np.cos(np.pi * j / Nt))
 
 
-def dos(corr, Hn, window="hann"):
+def dos(corr, Hn, window="hann", H0=0.0):
     """Density of states from correlations (Sec. III).
 
     D(E) = (1/2pi) int exp(iEt) C(t) dt with C(-t) = conj C(t), sampled at
     t_j = j tau, tau = pi/|H|, j = -Nt..Nt-1, windowed by w_j, at energies
     E_k = |H| k / Nt, k = -Nt..Nt-1:
         D(E_k) = (tau/2pi) sum_j w_j C_j exp(i pi k j / Nt),
-    evaluated as a 2Nt-point inverse FFT.  corr is [(Nt+1)][R]; returns
-    (E [2Nt], D [2Nt][R] real, max |Im D| as a check)."""
+    evaluated as a 2Nt-point inverse FFT.  The correlations of propagate()
+    carry the centred propagator exp(-i (H - H0) t) of the rescaled
+    expansion (Sec. II.A), so their transform at E_k is the density at the
+    true energy H0 + E_k; the returned energies are H0 + E_k.  corr is
+    [(Nt+1)][R]; returns (E [2Nt], D [2Nt][R] real, max |Im D| as a
+    check)."""
     corr = np.asarray(corr, dtype=np.complex128)
     if corr.ndim == 1:
         corr = corr[:, None]
@@ -625,11 +631,11 @@ def dos(corr, Hn, window="hann"):
     k = np.arange(-Nt, Nt)
     tau = math.pi / Hn
     D = (tau / (2 * math.pi)) * S[k % (2 * Nt)]
-    E = Hn * k / Nt
+    E = H0 + Hn * k / Nt
     return E, D.real.copy(), float(np.max(np.abs(D.imag)))
 
 
-def dos_direct(corr, Hn, window="hann"):
+def dos_direct(corr, Hn, window="hann", H0=0.0):
     """The same sum as dos(), written out term by term (small Nt only)."""
     corr = np.asarray(corr, dtype=np.complex128)
     if corr.ndim == 1:
@@ -640,7 +646,7 @@ def dos_direct(corr, Hn, window="hann"):
     E = np.zeros(2 * Nt)
     D = np.zeros((2 * Nt, corr.shape[1]), dtype=np.complex128)
     for ik, k in enumerate(range(-Nt, Nt)):
-        E[ik] = Hn * k / Nt
+        E[ik] = H0 + Hn * k / Nt
         for ij, jj in enumerate(range(-Nt, Nt)):
             Cj = corr[jj] if jj >= 0 else np.conj(corr[-jj])
             D[ik] += w[ij] * Cj * np.exp(1j * math.pi * k * jj / Nt)

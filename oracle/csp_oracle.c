@@ -587,6 +587,8 @@ int orc_propagate_moments(int64_t n, const int64_t *rowptr, const int64_t *col,
 /*   Psi(E) = tau_p sum_{j=0}^{Nt} (2 - delta_{j0})/2                        */
 /*            [ e^{i E' t_j} psi(t_j) + e^{-i E' t_j} psi(-t_j) ],            */
 /* t_j = j tau_p, tau_p = tau / Hn (physical time step), E' = E - H0.        */
+/* Eq. QE_coeff as printed weighs by tau_p with no 1/(2 pi), so this is     */
+/* 2 pi times the integral of Eq. QE.                                       */
 /* ------------------------------------------------------------------ */
 
 /* out <- sum_{k=0}^{Ntr} c[k] T_k(Ht) in, with p0, p1 scratch (amxsy and

@@ -143,7 +143,7 @@ _sig("csp_ec_sigma", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
 _sig("csp_propagate_batch", [_vp, ctypes.c_int32, _P(_vp), _P(_vp), _P(ctypes.c_int32),
                              _P(Params), _P(_vp), _P(Report)])
 _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                 ctypes.c_int32, _vp, _vp, _vp])
+                 ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp])
 _sig("csp_select_block", [_vp, _vp, ctypes.c_int32, _P(Params), _P(ctypes.c_int32), _P(Report)])
 _sig("csp_quasi_eigenstates", [_vp, _vp, _vp, ctypes.c_int32, _P(Params), ctypes.c_int32,
                                _P(ctypes.c_double), _vp, _P(Report)])
@@ -451,8 +451,9 @@ def csp_propagate_batch(ctx, lats, psi0s, params, corrs=None):
     return corrs, rep
 
 
-def csp_dos(ctx, corr, halfwidth, tau_tilde=math.pi, window=CSP_WINDOW_HANN):
-    """(E [2Nt], D [2Nt][R], Dmean [2Nt]) as float64 device tensors."""
+def csp_dos(ctx, corr, halfwidth, tau_tilde=math.pi, window=CSP_WINDOW_HANN, center=0.0):
+    """(E [2Nt], D [2Nt][R], Dmean [2Nt]) as float64 device tensors; center is
+    the lattice's spectral centre H0 (the energies are center + E_k)."""
     import torch
     Nt = corr.shape[0] - 1
     R = corr.shape[1]
@@ -460,8 +461,8 @@ def csp_dos(ctx, corr, halfwidth, tau_tilde=math.pi, window=CSP_WINDOW_HANN):
     E = torch.empty(2 * Nt, dtype=torch.float64, device=dev)
     D = torch.empty((2 * Nt, R), dtype=torch.float64, device=dev)
     Dm = torch.empty(2 * Nt, dtype=torch.float64, device=dev)
-    _check(_lib.csp_dos(ctx.handle, _ptr(corr), Nt, R, float(halfwidth), float(tau_tilde),
-                        int(window), _ptr(E), _ptr(D), _ptr(Dm)))
+    _check(_lib.csp_dos(ctx.handle, _ptr(corr), Nt, R, float(halfwidth), float(center),
+                        float(tau_tilde), int(window), _ptr(E), _ptr(D), _ptr(Dm)))
     return E, D, Dm
 
 

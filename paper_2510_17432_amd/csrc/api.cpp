@@ -2480,17 +2480,18 @@ extern "C" csp_status csp_ec_sigma(csp_context* c, const double* dev_corr, int64
 
 // ------------------------------------------------------------------ DOS
 extern "C" csp_status csp_dos(csp_context* c, const double* dev_corr, int64_t Nt, int32_t R,
-                              double halfwidth, double tau_tilde, int32_t window, double* dev_E,
-                              double* dev_D, double* dev_Dmean) {
+                              double halfwidth, double center, double tau_tilde, int32_t window,
+                              double* dev_E, double* dev_D, double* dev_Dmean) {
   if (!c || !dev_corr || !dev_E || !dev_D) return fail(CSP_EINVAL, "NULL argument");
   if (Nt < 1 || R < 1 || !(halfwidth > 0)) return fail(CSP_EINVAL, "need Nt >= 1, R >= 1, |H| > 0");
+  if (!std::isfinite(center)) return fail(CSP_EINVAL, "center is not finite");
   if (window != CSP_WINDOW_HANN && window != CSP_WINDOW_NONE) return fail(CSP_EINVAL, "bad window");
   if (!(tau_tilde > 0)) tau_tilde = M_PI;
   DeviceGuard dg(c->device);
   double* tw = nullptr;
   HIPCALL(hipMalloc(&tw, sizeof(double2) * 2 * Nt));
-  hipError_t e = launch_dos(dev_corr, Nt, R, halfwidth, tau_tilde, window, dev_E, dev_D, dev_Dmean,
-                            tw, c->stream);
+  hipError_t e = launch_dos(dev_corr, Nt, R, halfwidth, center, tau_tilde, window, dev_E, dev_D,
+                            dev_Dmean, tw, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(tw);
   if (e != hipSuccess) return fail(CSP_EHIP, "dos: %s", hipGetErrorString(e));

@@ -322,19 +322,20 @@ __global__ void k_dos(const double2* __restrict__ corr, int64_t Nt, int R, doubl
   D[kk * R + r] = pref * acc;
 }
 
+// Column mean, and the energies center + E_k of the centred transform.
 __global__ void k_dos_mean(int64_t n, int R, const double* __restrict__ D, double* __restrict__ Dm,
-                           double* __restrict__ E, double dE, int64_t Nt) {
+                           double* __restrict__ E, double dE, int64_t Nt, double center) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double s = 0.0;
   for (int r = 0; r < R; ++r) s += D[k * R + r];
   if (Dm) Dm[k] = s / R;
-  E[k] = dE * static_cast<double>(k - Nt);
+  E[k] = center + dE * static_cast<double>(k - Nt);
 }
 
-hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth, double tau_tilde,
-                      int window, double* d_E, double* d_D, double* d_Dmean, double* d_twiddle,
-                      hipStream_t s) {
+hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth, double center,
+                      double tau_tilde, int window, double* d_E, double* d_D, double* d_Dmean,
+                      double* d_twiddle, hipStream_t s) {
   const int64_t n = 2 * Nt;
   double2* tw = reinterpret_cast<double2*>(d_twiddle);
   hipLaunchKernelGGL(k_twiddle, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, Nt, tw);
@@ -344,7 +345,7 @@ hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth,
                      reinterpret_cast<const double2*>(d_corr), Nt, R, pref, window, tw, d_D);
   const double dE = M_PI / (static_cast<double>(Nt) * tau);
   hipLaunchKernelGGL(k_dos_mean, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, R, d_D,
-                     d_Dmean, d_E, dE, Nt);
+                     d_Dmean, d_E, dE, Nt, center);
   return hipGetLastError();
 }
 

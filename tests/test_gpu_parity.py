@@ -259,6 +259,27 @@ def test_dos_kernel(csp, ctx):
         assert np.max(np.abs(host(Dm) - Dr.mean(1))) < 1e-12
 
 
+def test_dos_with_spectral_centre(csp, ctx):
+    # a lattice with H0 != 0: the propagation carries exp(-i (H - H0) t) on
+    # both sides, and csp_dos places the density on center + E_k
+    spec = dict(kind="honeycomb", Lx=9, Ly=8, t=-1.0, W=1.2, disorder_seed=3)
+    g = csp.Lattice(ctx, halfwidth_override=4.2, center=0.35, **spec)
+    c = o.Lattice("honeycomb", 9, 8, t=-1.0, W=1.2, disorder_seed=3)
+    assert g.info.H0 == 0.35 and g.halfwidth == 4.2
+    psi = o.random_phase_states_fast(c.N, 2, 7)
+    Nt = 96
+    ref, _ = o.propagate(c, psi, Nt, b=0, Hn=4.2, H0=0.35)
+    corr, _ = csp.csp_propagate(ctx, g, dev(psi), csp.make_params(Nt, mode="fp64_conc",
+                                                                  block_b=16))
+    assert np.max(np.abs(host(corr) - ref)) < 1e-10
+    E, D, Dm = csp.csp_dos(ctx, corr, g.halfwidth, center=g.info.H0)
+    Er, Dr, _ = o.dos(ref, 4.2, H0=0.35)
+    assert np.max(np.abs(host(E) - Er)) < 1e-12
+    assert host(E)[Nt] == 0.35
+    assert np.max(np.abs(host(D) - Dr)) < 1e-10
+    assert np.max(np.abs(host(Dm) - Dr.mean(1))) < 1e-10
+
+
 def test_batch_matches_oracle(csp, ctx):
     specs = [dict(kind="square", Lx=20, Ly=18, t=1.0, W=1.5, disorder_seed=1),
              dict(kind="honeycomb", Lx=9, Ly=14, t=-2.7, W=0.5, disorder_seed=2),

@@ -212,6 +212,46 @@ def test_dos_of_exact_spectrum():
         assert D[ik, 0] == pytest.approx(float(np.dot(wts, kern)), abs=1e-12)
 
 
+def test_dos_with_spectral_centre_on_exact_spectrum():
+    # with H~ = (H - H0)/|H| the correlations carry exp(-i (H - H0) t), and
+    # the DOS placed at H0 + E_k is the window kernel on each true level
+    # (a spectrum that is not centred on 0: on-site energies shifted by +0.9)
+    lat = o.Lattice("chain", 11, t=1.0, W=1.0, disorder_seed=5)
+    H = lat.dense() + 0.9 * np.eye(lat.N)
+    shifted = o.SparseLattice(*_ell_of_dense(H))
+    lev, V = np.linalg.eigh(H)
+    H0 = 0.5 * (lev[0] + lev[-1])
+    Hn = 1.025 * 0.5 * (lev[-1] - lev[0])
+    psi = o.random_phase_states(lat.N, 1, 3)
+    Nt = 40
+    corr, _ = o.propagate(shifted, psi, Nt, b=0, Hn=Hn, H0=H0)
+    E, D, _ = o.dos(corr, Hn, H0=H0)
+    assert E[Nt] == H0 and E[0] == pytest.approx(H0 - Hn, abs=1e-14)
+    wts = np.abs(V.conj().T @ psi[:, 0]) ** 2
+    tau = math.pi / Hn
+    j = np.arange(-Nt, Nt)
+    w = 0.5 * (1 + np.cos(np.pi * j / Nt))
+    for ik in (3, 25, Nt, 61):
+        kern = [(tau / (2 * math.pi)) * np.sum(w * np.cos((E[ik] - e) * j * tau)) for e in lev]
+        assert D[ik, 0] == pytest.approx(float(np.dot(wts, kern)), abs=1e-12)
+    # the density peaks inside the true band [lev[0], lev[-1]], not around 0
+    assert lev[0] - 0.3 < E[int(np.argmax(D[:, 0]))] < lev[-1] + 0.3
+    E2, D2 = o.dos_direct(corr, Hn, H0=H0)
+    assert np.allclose(E, E2, atol=1e-15) and np.max(np.abs(D - D2.real)) < 1e-13
+
+
+def _ell_of_dense(H):
+    N = H.shape[0]
+    D = int(max(np.count_nonzero(H[s]) for s in range(N)))
+    col = -np.ones((N, D), dtype=np.int64)
+    val = np.zeros((N, D))
+    for s in range(N):
+        nz = np.nonzero(H[s])[0]
+        col[s, :len(nz)] = nz
+        val[s, :len(nz)] = H[s, nz]
+    return col, val
+
+
 @pytest.mark.parametrize("b", [2, 16, 32, 40, 256])
 def test_concurrent_equals_sequential(b, golden):
     scale = float(golden("dos_accuracy.txt")["eps_inf_correlation"])
