@@ -10,10 +10,14 @@
 // two real products of a [32 values x K orders] tile with one real
 // [K x 32 times] coefficient tile, which run on v_mfma_f32_32x32x16_bf16.
 // Each FP32 operand is split x = hi + lo with hi = bf16(x),
-// lo = bf16(x - hi), and the product is hi*hi + hi*lo + lo*hi (the lo*lo term
-// is below FP32 resolution), accumulated in FP32.  The carried state uses
-// plain FP32 FMAs on the same loaded values, since its error would feed
-// every later block.
+// lo = bf16(x - hi), and the product is hi*hi + hi*lo + lo*hi, accumulated
+// in FP32.  This is not FP32-exact: hi + lo keeps 16 significant bits
+// (|x - hi - lo| <= 2^-18 |x|), and the dropped lo*lo term is up to
+// 2^-18 |ab|, so each product carries a relative error of at most about
+// 3 * 2^-18 = 1.1e-5; the observed DOS error against complex128 (about 1e-5
+// relative on the graphene and 1e9-orbital workloads) is of that size, ten
+// times inside the 1e-4 target.  The carried state uses plain FP32 FMAs on
+// the same loaded values, since its error would feed every later block.
 //
 // Every workgroup works on one column of the group (groups are stored
 // column-major, [Rg][N]), so all of its correlation sums belong to that
