@@ -1,23 +1,39 @@
 """Throughput of the concurrent stochastic propagation hot path on one GPU.
 
-One step = one pass of the whole path over one batch of synthetic input on
-graphene (honeycomb 1024 x 1024 cells, 2 097 152 orbitals, periodic,
-t = -2.7 eV, no disorder): random-phase states for 4 columns and localized
-states on 64 sampled sites (generated on the GPU), the Chebyshev
-coefficients (FP64, on the GPU), the complex64 Chebyshev recursion, the
-split-bf16 MFMA block contraction fused with <psi0|psi(t_j)>, the FP32
-carried state, 2048 time points, and the DOS / LDOS transform.
+Workload: the 1e9-orbital square lattice (31623 x 31623 sites,
+1 000 014 129 orbitals, periodic, t = 1, Anderson disorder W = 0.5 drawn
+from seed 6), 4 random-phase columns (seed 7), 4096 time steps of
+tau~ = pi, complex64.
+
+One step = one time block of b = 32 time steps of the state-based
+concurrent form over all 4 columns: random-phase states generated on the
+GPU, the Chebyshev coefficients (FP64, on the GPU), the complex64 Chebyshev
+recursion (N(32 pi) = 148 steps), the split-bf16 MFMA block contraction
+fused with <psi0|psi(t_j)>, the FP32 carried state, and the DOS transform
+of the block's correlations.  The 4096 steps of the workload are 128 such
+blocks.  The columns run one after another (a window of one column: the
+ring of Chebyshev vectors of one 8 GB column fills most of the 288 GB).
 
 The reported value is orbital-state Chebyshev steps per second:
 N * R * (recursion steps executed) / wall time of a step.  Beside it:
   roofline      the recursion kernel's algorithmic HBM bytes per launch over
-                its average launch time (HIP events on the library stream);
+                its average launch time (HIP events on the library stream),
+                with the rocprofv3 FETCH/WRITE bytes of the same kernel;
+  contraction   the MFMA contraction's bandwidth and its MFMA utilisation
+                from rocprofv3 counters;
   time_to_accuracy
-                the DOS of the 4 random columns by the complex64 concurrent
-                form and by the plain complex128 sequential form on the same
-                GPU, with the relative DOS difference between them;
-  cpu_baseline  the FP64 CPU oracle (sequential form) on a bounded sample of
-                the same lattice, timed on the host cores.
+                the DOS of the workload's 4096 steps by the complex64 moment
+                form (DOS-Concurrent-M: one block, halving) and by the
+                complex64 state form (the timed block rate times 128 blocks),
+                against the complex128 sequential form on the same GPU
+                (truncated runs scaled to 4096 steps); the complex64 DOS
+                error is taken against the complex128 moment form;
+  graphene      the graphene workload (honeycomb 1024 x 1024 cells, 4
+                random + 64 LDOS columns, Nt = 2048, b = 32) as extra keys;
+  batch         the batch of 32 uneven lattices in one csp_propagate_batch
+                call with HIP-graph replay;
+  cpu_baseline  the FP64 CPU oracle (sequential form) on a bounded sample,
+                timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -35,15 +51,20 @@ if ROOT not in sys.path:
 
 import csp_inputs  # noqa: E402  (seeded workload recipes)
 
-# Graphene, 1024 x 1024 cells, 4 random-phase states + 64 LDOS sites, 2048
-# time points (Sec. III DOS / LDOS on a lattice of the paper's size range).
-_G = csp_inputs.GRAPHENE1024
-WORKLOAD = dict(kind=_G["kind"], Lx=_G["Lx"], Ly=_G["Ly"], t=_G["t"], W=_G["W"], R_rand=_G["R"],
-                n_sites=_G["n_sites"], Nt=_G["Nt"], seed_states=_G["seed_states"],
-                seed_sites=_G["seed_sites"], block_b=32)
-
-HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16 MFMA, published
+N_CU = 256
 COPY_PROBE_BYTES = 2 << 30
+
+# The 1e9-orbital square lattice; one step is one time block of BLOCK_B steps.
+BLOCK_B = 32
+W5 = csp_inputs.SQUARE31623
+
+# Kernel sources whose counters profiles/ holds (a changed source voids them).
+CHEB_SOURCES = ("k_cheb_body.h", "k_cheb_f32.hip")
+CONTRACT_SOURCES = ("k_contract.hip",)
+CHEB_COUNTERS = "k_cheb_square31623_cols4_counters.json"
+CONTRACT_COUNTERS = "k_contract_f32_square31623_cols4_mfma.json"
 
 
 def parse():
@@ -51,21 +72,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--block-b", type=int, default=WORKLOAD["block_b"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-seq", action="store_true",
-                    help="skip the complex128 sequential comparison run")
-    ap.add_argument("--no-moments", action="store_true",
-                    help="skip the moment-based form runs")
+    ap.add_argument("--no-tta", action="store_true",
+                    help="skip the time-to-accuracy legs on the 1e9-orbital lattice")
+    ap.add_argument("--no-graphene", action="store_true", help="skip the graphene legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample")
-    ap.add_argument("--no-qe", action="store_true",
-                    help="skip the quasi-eigenstate runs")
-    ap.add_argument("--dos-1e9", action="store_true",
-                    help="instead of the step benchmark: the DOS of the 1e9-orbital square "
-                         "lattice (31623^2, W = 0.5, 4 random columns, Nt = 4096) in the "
-                         "complex64 moment and state forms against the complex128 moment form, "
-                         "and the complex128 sequential form timed on a truncated run")
+    ap.add_argument("--seq-steps", type=int, default=8,
+                    help="time steps of the truncated complex128 sequential runs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 2 GiB device to device (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL",
+                                                         "OUT_JSON"),
+                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --copy-probe run into the scaled "
+                         "per-launch HBM bytes of the kernels whose name contains KERNEL")
     ap.add_argument("--dense-dh", action="store_true",
                     help="instead of the step benchmark: the DOS (Nt = 4096) of explicit "
                          "matrices of density D_H = 61, 121, 233 (4.76 M orbitals, 10 / 5 / 2 "
@@ -78,12 +101,6 @@ def parse():
                          "correlation (EC-Concurrent-M, 49 energies, Nt = 1024, 5 random "
                          "columns) on the D_H = 121 explicit matrix, complex64 and complex128, "
                          "against the recursion cost of the complex128 sequential form")
-    ap.add_argument("--seq-steps", type=int, default=8,
-                    help="time steps of the truncated complex128 sequential run "
-                         "(--dos-1e9, --dense-dh)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="first copy 2 GiB device to device (a kernel of known traffic for "
-                         "scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -91,160 +108,390 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-# sources of the recursion kernel whose counters profiles/ holds
-KERNEL_SOURCES = ("k_cheb_body.h", "k_cheb_f32.hip")
-
-
-def traffic_from_profiles():
-    """HBM bytes per launch of the recursion kernel: the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, each scaled by what the same counter
-    read for a device copy of known size.  None when there is no summary or
-    when the kernel source has changed since the counters were taken."""
+def _sources_sha256(names):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cheb_graphene1024_cols68_counters.json")
+    h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2510_17432_amd", "csrc")
+    for name in names:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _profile(name, sources):
+    """A committed counter summary, or None when it is missing or the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             d = json.load(f)
-        h = hashlib.sha256()
-        for name in KERNEL_SOURCES:
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
-        h = h.hexdigest()
-        if d.get("source_sha256") != h:
+        if d.get("source_sha256") != _sources_sha256(sources):
             return None
-        return float(d["hbm_bytes_per_launch"])
-    except Exception:
+        return d
+    except (OSError, ValueError):
         return None
 
 
-def cpu_baseline(W, seconds):
-    """FP64 sequential oracle on the same lattice, one random column, for as
-    many time steps as fit in about `seconds`."""
-    import numpy as np
+def summarize_pmc(fetch_csv, write_csv, kernel, out_json):
+    """Per-launch HBM bytes of the kernels named `kernel` from two
+    rocprofv3 --pmc runs of the same command, each counter scaled by what it
+    read for the 2 GiB device copy the command starts with."""
+    import csv
+
+    def rows(path, counter):
+        out = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") == counter:
+                    out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
+
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rr = rows(path, counter)
+        copy = [v for k, v in rr if "copyBuffer" in k or "copy" in k.lower()]
+        mine = [v for k, v in rr if kernel in k]
+        if not copy or not mine:
+            raise SystemExit("no copy dispatch or no %s dispatch for %s" % (kernel, counter))
+        probe_kib = max(copy)
+        scale = (COPY_PROBE_BYTES / 1024.0) / probe_kib
+        res[counter] = {"dispatches": len(mine), "kib_per_dispatch": sum(mine) / len(mine),
+                        "copy_probe_kib": probe_kib, "scale": scale,
+                        "bytes_per_dispatch": sum(mine) / len(mine) * 1024.0 * scale}
+    res["hbm_bytes_per_launch"] = (res["FETCH_SIZE"]["bytes_per_dispatch"] +
+                                   res["WRITE_SIZE"]["bytes_per_dispatch"])
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def cpu_baseline(seconds):
+    """FP64 sequential oracle on a 31623 x 128 strip of the large square
+    lattice (same hopping and disorder recipe), one random column, for as
+    many time steps as fit in about `seconds`.  Its cost per orbital and
+    Chebyshev step does not depend on the number of rows."""
     import oracle as o
     t0 = time.perf_counter()
-    lat = o.Lattice(W["kind"], W["Lx"], W["Ly"], t=W["t"], W=W["W"])
-    psi = o.random_phase_states_fast(lat.N, 1, W["seed_states"])
+    rows = 128
+    lat = o.Lattice(W5["kind"], W5["Lx"], rows, t=W5["t"], W=W5["W"],
+                    disorder_seed=W5["disorder_seed"])
+    psi = o.random_phase_states_fast(lat.N, 1, W5["seed_states"])
     t_setup = time.perf_counter() - t0
-    # size the sample from a short probe after one warm-up step
-    o.propagate(lat, psi, 1, b=0)
+    o.propagate(lat, psi, 1, b=0)                       # warm-up
     t0 = time.perf_counter()
-    o.propagate(lat, psi, 8, b=0)
-    t8 = (time.perf_counter() - t0) / 8
-    nt = max(1, int(seconds / max(t8, 1e-4)))
+    o.propagate(lat, psi, 4, b=0)
+    t4 = (time.perf_counter() - t0) / 4
+    nt = max(1, int(seconds / max(t4, 1e-4)))
     t0 = time.perf_counter()
     _, cnt = o.propagate(lat, psi, nt, b=0)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    rate = lat.N * 1 * cnt["amxsy"] / el
+    rate = lat.N * cnt["amxsy"] / el
     return {"value": rate, "unit": "orbital*steps/s", "cores": cores, "kind": "oracle",
-            "sample": "FP64 sequential form, graphene 1024x1024 cells (N=%d), 1 random column, "
-                      "%d time steps (%d Chebyshev steps) in %.1f s; lattice set-up %.1f s "
-                      "excluded" % (lat.N, nt, cnt["amxsy"], el, t_setup)}
+            "sample": "FP64 sequential form of the oracle on a %d x %d strip of the square "
+                      "lattice (N=%d, t=1, W=0.5, seed 6), 1 random column, %d time steps "
+                      "(%d Chebyshev steps) in %.1f s; lattice set-up %.1f s excluded; the "
+                      "rate per orbital-step carries over to the 31623^2 lattice (cost linear "
+                      "in N); extrapolated time for the full workload (4 columns, 4096 "
+                      "steps): %.0f h" % (W5["Lx"], rows, lat.N, nt, cnt["amxsy"], el, t_setup,
+                                          1000014129 * 4 * 20 * 4096 / rate / 3600.0)}
 
 
-def dos_1e9(a):
-    """DOS of the 1e9-orbital square lattice: complex64 concurrent forms against
-    the complex128 moment form (checked against the oracle on small lattices by
-    the parity tests), with the time of each, and the complex128 sequential
-    form timed on a truncated run and scaled to all Nt steps (its cost is
-    linear in the steps, Tab. cost)."""
+def c5_legs(a, out):
+    """The timed steps on the 1e9-orbital lattice, and its time-to-accuracy
+    legs.  Fills `out` (the JSON line)."""
     import numpy as np
     import torch
     import paper_2510_17432_amd as csp
-    w = csp_inputs.SQUARE31623
-    Nt = w["Nt"]
+    dev = "cuda:0"
+    Nt = W5["Nt"]
+    R = W5["R"]
+    b = BLOCK_B
     ctx = csp.Context(0)
     t0 = time.perf_counter()
-    lat = csp.Lattice(ctx, w["kind"], w["Lx"], w["Ly"], t=w["t"], W=w["W"],
-                      disorder_seed=w["disorder_seed"])
-    N, R = lat.N, w["R"]
-    log("lattice N=%d |H|=%.6f R=%d Nt=%d (%.1f s)" % (N, lat.halfwidth, R, Nt,
-                                                       time.perf_counter() - t0))
-    dev = "cuda:0"
+    lat = csp.Lattice(ctx, W5["kind"], W5["Lx"], W5["Ly"], t=W5["t"], W=W5["W"],
+                      disorder_seed=W5["disorder_seed"])
+    N = lat.N
+    log("square 31623^2: N=%d |H|=%.6f R=%d (set-up %.1f s)" % (N, lat.halfwidth, R,
+                                                               time.perf_counter() - t0))
+    psi = torch.empty((N, R), dtype=torch.complex64, device=dev)
+    corr = torch.empty((b + 1, R), dtype=torch.complex128, device=dev)
+    params = csp.make_params(b, mode="fp32_conc", block_b=b, profile=True)
+
+    def step():
+        csp.csp_states_random_phase(ctx, psi, R, W5["seed_states"])
+        _, rep = csp.csp_propagate(ctx, lat, psi, params, corr=corr)
+        csp.csp_dos(ctx, corr, lat.halfwidth)
+        return rep
+
+    for i in range(a.warmup):
+        rep = step()
+        log("warmup %d done: %.1f ms (recursion %.1f ms over %d launches, contraction %.1f ms "
+            "over %d)" % (i, rep.ms_total, rep.ms_spmm, rep.spmm_launches, rep.ms_contract,
+                          rep.contract_launches))
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        reps.append(step())
+        log("step %d done: %.1f ms" % (i, reps[-1].ms_total))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s_step = el / a.steps
+    rep = reps[-1]
+    steps_exec = rep.amxsy
+    n_spmm = sum(r.spmm_launches for r in reps)
+    launch_s = sum(r.ms_spmm for r in reps) / 1000.0 / n_spmm
+    bytes_launch = sum(r.spmm_bytes for r in reps) / n_spmm
+    achieved = bytes_launch / launch_s / 1e9
+    n_con = sum(r.contract_launches for r in reps)
+    con_s = sum(r.ms_contract for r in reps) / 1000.0
+    con_bytes = sum(r.contract_bytes for r in reps)
+    con_flops = sum(r.contract_flops for r in reps)
+    cheb_prof = _profile(CHEB_COUNTERS, CHEB_SOURCES)
+    con_prof = _profile(CONTRACT_COUNTERS, CONTRACT_SOURCES)
+    bw_read, bw_write, bw_r2w1 = csp.csp_bandwidth_probe(ctx, 1 << 30)
+    ctx.trim()
+    n_blocks = math.ceil(Nt / b)
+    out.update({
+        "value": N * R * steps_exec / s_step,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1000.0 * s_step,
+        "config": {"workload": "square lattice 31623x31623 (N=%d), periodic, t=1, W=0.5 (seed 6), "
+                               "4 random-phase columns (seed 7), Nt=4096 in time blocks of b=%d; "
+                               "one step = one time block over all columns, complex64 "
+                               "recursion + split-bf16 MFMA contraction" % (N, b),
+                   "orbitals": N, "columns": R, "Nt": Nt, "block_b": rep.block_b,
+                   "chunk_K": rep.chunk_K, "column_windows": rep.n_passes,
+                   "recursion_steps_per_step": steps_exec, "time_steps_per_step": b,
+                   "blocks_in_workload": n_blocks},
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_cheb<float, 2, %d, square, on-site> (Chebyshev recursion, %d "
+                               "steps per launch)" % (rep.spmm_steps, rep.spmm_steps),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": cheb_prof["hbm_bytes_per_launch"] if cheb_prof else None,
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": launch_s * 1e6,
+                     "launches_per_step": n_spmm / a.steps,
+                     "streaming_ceiling_GBs": {"read": bw_read, "write": bw_write,
+                                               "two_reads_one_write": bw_r2w1}},
+        "effective_rate": N * R * b * 20 / s_step,
+    })
+    con = {"kernel": "k_contract_f32 (split-bf16 MFMA, FP32 accumulation)",
+           "avg_launch_us": 1e6 * con_s / max(n_con, 1), "launches_per_step": n_con / a.steps,
+           "achieved_GBs": con_bytes / max(con_s, 1e-12) / 1e9,
+           "issued_mfma_TFLOPs": con_flops / max(con_s, 1e-12) / 1e12,
+           "share_of_step": con_s / a.steps / s_step}
+    if con_prof:
+        con.update({k: con_prof[k] for k in ("mfma_busy_frac", "useful_over_issued_flops",
+                                             "useful_mfma_TFLOPs", "hbm_bytes_per_launch")
+                    if k in con_prof})
+    out["contraction"] = con
+    log("C5 step: %.3f s, %.3e orbital*steps/s, recursion %.1f us/launch (%.0f GB/s), "
+        "contraction %.1f us/launch" % (s_step, out["value"], launch_s * 1e6, achieved,
+                                        con["avg_launch_us"]))
+    if a.no_tta:
+        lat.close()
+        ctx.close()
+        return
+
+    # ---- time to accuracy over the workload's 4096 steps
+    tta = {"target_rel_err": 1e-4, "columns": R, "Nt": Nt}
+    del corr
+    torch.cuda.empty_cache()
+
+    def dos_of(c):
+        _, _, Dm = csp.csp_dos(ctx, c, lat.halfwidth)
+        return Dm.cpu().numpy()
+
+    # complex128 moment form (one block, halving): the reference, one call
+    # per column (each about half a minute)
     psi64 = torch.empty((N, R), dtype=torch.complex128, device=dev)
-    csp.csp_states_random_phase(ctx, psi64, R, w["seed_states"])
-    out = {"workload": "square 31623x31623 (N=%d), t=1, W=0.5 (seed %d), periodic, %d random "
-                       "columns (seed %d), Nt=%d" % (N, w["disorder_seed"], R, w["seed_states"], Nt),
-           "halfwidth": lat.halfwidth}
-
-    def run(psi, mode, assembly, b=0, steps=Nt, per_column=False):
-        # per_column: one call per column (each finishes in about a minute)
-        corr = torch.empty((steps + 1, R), dtype=torch.complex128, device=dev)
-        params = csp.make_params(steps, mode=mode, block_b=b, assembly=assembly)
+    csp.csp_states_random_phase(ctx, psi64, R, W5["seed_states"])
+    c64 = torch.empty((Nt + 1, R), dtype=torch.complex128, device=dev)
+    t0 = time.perf_counter()
+    pm64 = csp.make_params(Nt, mode="fp64_conc", assembly=csp.CSP_ASSEMBLE_MOMENTS)
+    for k in range(R):
+        p = psi64[:, k:k + 1].contiguous()
+        ck, _ = csp.csp_propagate(ctx, lat, p, pm64)
+        c64[:, k:k + 1] = ck
+        del p, ck
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        cols = [(k, k + 1) for k in range(R)] if per_column else [(0, R)]
-        passes = 0
-        col_s = []          # seconds of each call
-        for (c0, c1) in cols:
-            tc = time.perf_counter()
-            p = psi[:, c0:c1].contiguous() if per_column else psi
-            cc = torch.empty((steps + 1, c1 - c0), dtype=torch.complex128, device=dev)
-            _, rep = csp.csp_propagate(ctx, lat, p, params, corr=cc)
-            corr[:, c0:c1] = cc
-            passes += rep.n_passes
-            del p
-            torch.cuda.synchronize()
-            col_s.append(time.perf_counter() - tc)
-            log("  %s assembly %d columns %d..%d: %.1f s" % (mode, assembly, c0, c1 - 1,
-                                                          time.perf_counter() - t))
-        _, _, Dm = csp.csp_dos(ctx, corr, lat.halfwidth)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        ctx.trim()
-        run.col_s = col_s
-        return corr, Dm, el, rep, passes
-
-    c64, D64, t64m, r64, p64 = run(psi64, "fp64_conc", csp.CSP_ASSEMBLE_MOMENTS, per_column=True)
-    log("complex128 moments: %.1f s" % t64m)
-    # complex128 sequential (b = 1, psi(t_j) accumulated in the recursion, one
-    # dot per step): two truncated runs; the cost per time step is their
-    # difference over the extra steps (set-up excluded), scaled to Nt steps;
-    # per-column medians, as the first call after the workspace was released
-    # also pays for its allocation
-    s1, s2 = a.seq_steps, 3 * a.seq_steps
-    _, _, t1, _, _ = run(psi64, "fp64_seq", csp.CSP_ASSEMBLE_MOMENTS, 1, s1, per_column=True)
-    m1 = statistics.median(run.col_s)
-    _, _, t2, _, _ = run(psi64, "fp64_seq", csp.CSP_ASSEMBLE_MOMENTS, 1, s2, per_column=True)
-    m2 = statistics.median(run.col_s)
-    per_step = R * (m2 - m1) / (s2 - s1)
-    t_seq = R * m1 + per_step * (Nt - s1)
-    ts = t2
-    log("complex128 sequential: %d steps %.1f s, %d steps %.1f s -> %.0f s for %d" %
-        (s1, t1, s2, t2, t_seq, Nt))
-    psi32 = psi64.to(torch.complex64)
+        log("complex128 moment form, column %d: %.1f s" % (k, time.perf_counter() - t0))
+    t64m = time.perf_counter() - t0
+    d64 = dos_of(c64)
+    tta["fp64_moments_s"] = t64m
+    # complex128 sequential form: column 0 over two truncated runs; the cost
+    # per time step is their difference over the extra steps, scaled to Nt
+    # steps and R columns (the cost is linear in both, Tab. cost)
+    p0 = psi64[:, :1].contiguous()
     del psi64
     ctx.trim()
+    ts = []
+    for steps in (a.seq_steps, 3 * a.seq_steps):
+        prm = csp.make_params(steps, mode="fp64_seq", assembly=csp.CSP_ASSEMBLE_MOMENTS)
+        csp.csp_propagate(ctx, lat, p0, prm)          # workspace allocated
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        csp.csp_propagate(ctx, lat, p0, prm)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    per_step = (ts[1] - ts[0]) / (2 * a.seq_steps)
+    t_seq = R * (ts[0] + per_step * (Nt - a.seq_steps))
+    tta["fp64_sequential_s"] = t_seq
+    tta["fp64_sequential_sample"] = ("extrapolated: column 0 over %d and %d of %d steps in %.2f s "
+                                     "and %.2f s, %.3f s per step, times %d columns" %
+                                     (a.seq_steps, 3 * a.seq_steps, Nt, ts[0], ts[1], per_step, R))
+    log("complex128 sequential: %.0f s (extrapolated)" % t_seq)
+    del p0
+    ctx.trim()
     torch.cuda.empty_cache()
-    ref_c, ref_d = c64.cpu().numpy(), D64.cpu().numpy()
-    del c64, D64
-    res = {}
-    for name, assembly, b, pc in (("fp32_moments", csp.CSP_ASSEMBLE_MOMENTS, 0, False),
-                                  ("fp32_states", csp.CSP_ASSEMBLE_STATES, 16, True)):
-        c32, D32, el, rep, npass = run(psi32, "fp32_conc", assembly, b, per_column=pc)
-        rel = float(np.max(np.abs(D32.cpu().numpy() - ref_d)) / np.max(np.abs(ref_d)))
-        eps = float(np.max(np.abs(c32.cpu().numpy() - ref_c)))
-        res[name] = {"s": el, "dos_rel_err": rel, "corr_eps_inf": eps, "block_b": rep.block_b,
-                     "chunk_K": rep.chunk_K, "calls_x_passes": npass,
-                     "recursion_steps_per_column": rep.amxsy}
-        log("%s: %.1f s, DOS rel err %.2e, eps_inf %.2e" % (name, el, rel, eps))
-        del c32, D32
-    del psi32
-    out.update({"fp64_moments_s": t64m, "fp64_moments_calls_x_passes": p64,
-                "fp64_sequential_s_extrapolated": t_seq,
-                "fp64_sequential_sample": "%d and %d of %d steps in %.2f s and %.2f s; "
-                                          "%.3f s per step" % (s1, s2, Nt, t1, t2, per_step),
-                "target_rel_err": 1e-4})
-    for k, v in res.items():
-        out[k] = v
-        out[k]["speedup_vs_fp64_sequential"] = t_seq / v["s"]
+    # complex64 moment form (DOS-Concurrent-M), all columns in one call
+    pm32 = csp.make_params(Nt, mode="fp32_conc", assembly=csp.CSP_ASSEMBLE_MOMENTS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c32, r32 = csp.csp_propagate(ctx, lat, psi, pm32)
+    d32 = dos_of(c32)
+    t32m = time.perf_counter() - t0
+    rel = float(np.max(np.abs(d32 - d64)) / np.max(np.abs(d64)))
+    eps = float((c32 - c64).abs().max().item())
+    tta.update({"fp32_moments_s": t32m, "fp32_moments_dos_rel_err": rel,
+                "fp32_moments_corr_eps_inf": eps, "fp32_moments_recursion_steps": r32.amxsy,
+                "fp32_moments_speedup": t_seq / t32m})
+    log("complex64 moment form: %.1f s, DOS rel err %.2e, eps_inf %.2e" % (t32m, rel, eps))
+    # complex64 state form: the timed block rate times the number of blocks
+    t32s = s_step * n_blocks
+    tta.update({"fp32_states_s": t32s,
+                "fp32_states_sample": "the timed step (one block of b=%d over all columns) times "
+                                      "%d blocks; its accuracy at this size is checked against "
+                                      "the complex128 moment form by the GPU tests" % (b, n_blocks),
+                "fp32_states_speedup": t_seq / t32s})
+    out["time_to_accuracy"] = tta
+    del c32, c64, psi
     lat.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    torch.cuda.empty_cache()
+
+
+def graphene_leg(a, out):
+    """The graphene workload: state assembly of 68 columns (4 random, 64
+    LDOS sites) with b = 32, the moment form on the same columns, and the
+    DOS of the 4 random columns against the complex128 sequential form."""
+    import numpy as np
+    import torch
+    import paper_2510_17432_amd as csp
+    G = csp_inputs.GRAPHENE1024
+    dev = "cuda:0"
+    ctx = csp.Context(0)
+    lat = csp.Lattice(ctx, G["kind"], G["Lx"], G["Ly"], t=G["t"], W=G["W"])
+    N, Rr, Nt = lat.N, G["R"], G["Nt"]
+    R = Rr + G["n_sites"]
+    psi = torch.empty((N, R), dtype=torch.complex64, device=dev)
+    csp.csp_states_random_phase(ctx, psi, Rr, G["seed_states"], col0=0)
+    sites = csp.csp_ldos_sites(ctx, N, G["n_sites"], G["seed_sites"])
+    csp.csp_states_sites(ctx, psi, sites, col0=Rr)
+    res = {"workload": "graphene honeycomb 1024x1024 cells (N=%d), t=-2.7 eV, periodic, %d "
+                       "random-phase + %d LDOS columns, Nt=%d" % (N, Rr, G["n_sites"], Nt)}
+    for name, prm in (("state_assembly_b32", csp.make_params(Nt, mode="fp32_conc", block_b=32,
+                                                              profile=True)),
+                      ("moments", csp.make_params(Nt, mode="fp32_conc",
+                                                  assembly=csp.CSP_ASSEMBLE_MOMENTS,
+                                                  profile=True))):
+        csp.csp_propagate(ctx, lat, psi, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep = csp.csp_propagate(ctx, lat, psi, prm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"s": el, "recursion_steps": rep.amxsy, "value": N * R * rep.amxsy / el,
+                     "recursion_us_per_launch": 1000.0 * rep.ms_spmm / rep.spmm_launches,
+                     "recursion_alg_GBs": rep.spmm_bytes / rep.ms_spmm / 1e6,
+                     "recursion_frac": rep.spmm_bytes / rep.ms_spmm / 1e6 / HBM_PEAK_GBS,
+                     "steps_per_launch": rep.spmm_steps}
+        if rep.contract_launches:
+            res[name]["contraction_GBs"] = rep.contract_bytes / rep.ms_contract / 1e6
+        log("graphene %s: %.3f s, recursion %.0f GB/s" % (name, el,
+                                                          res[name]["recursion_alg_GBs"]))
+    ctx.trim()
+    p4 = psi[:, :Rr].contiguous()
+    p64 = p4.to(torch.complex128)
+    del psi
+
+    def timed(pin, **kw):
+        prm = csp.make_params(Nt, **kw)
+        c, _ = csp.csp_propagate(ctx, lat, pin, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, _ = csp.csp_propagate(ctx, lat, pin, prm, corr=c)
+        _, _, Dm = csp.csp_dos(ctx, c, lat.halfwidth)
+        torch.cuda.synchronize()
+        return c, Dm.cpu().numpy(), time.perf_counter() - t0
+
+    c64, d64, t64 = timed(p64, mode="fp64_seq")
+    tta = {"fp64_sequential_s": t64, "columns": Rr}
+    for name, kw in (("fp32_states_b32", dict(mode="fp32_conc", block_b=32)),
+                     ("fp32_moments", dict(mode="fp32_conc", assembly=csp.CSP_ASSEMBLE_MOMENTS))):
+        c, d, t = timed(p4, **kw)
+        tta[name] = {"s": t, "speedup": t64 / t,
+                     "dos_rel_err": float(np.max(np.abs(d - d64)) / np.max(np.abs(d64))),
+                     "corr_eps_inf": float((c - c64).abs().max().item())}
+        log("graphene DOS %s: %.3f s (%.1fx), rel err %.2e" % (name, t, t64 / t,
+                                                               tta[name]["dos_rel_err"]))
+    res["time_to_accuracy"] = tta
+    out["graphene"] = res
+    del p4, p64, c64
+    lat.close()
+    ctx.close()
+    torch.cuda.empty_cache()
+
+
+def batch_leg(a, out):
+    """The batch of 32 uneven lattices (square and honeycomb, 128^2 to
+    2048^2 cells, 1-8 columns each, Nt = 1024) in one csp_propagate_batch
+    call: autotuned launch shapes and block size, one recursion launch and
+    one contraction launch over all instances, every full time block
+    replayed from a HIP graph; timed after a first call."""
+    import torch
+    import paper_2510_17432_amd as csp
+    insts, Nt = csp_inputs.batch32()
+    ctx = csp.Context(0)
+    lats = [csp.Lattice(ctx, d["kind"], d["Lx"], d["Ly"], t=d["t"], W=d["W"],
+                        disorder_seed=d["disorder_seed"]) for d in insts]
+    psis = []
+    for l, d in zip(lats, insts):
+        p = torch.empty((l.N, d["R"]), dtype=torch.complex64, device="cuda:0")
+        csp.csp_states_random_phase(ctx, p, d["R"], d["seed_states"])
+        psis.append(p)
+    params = csp.make_params(Nt, mode="fp32_conc", block_b=0, graph=1)
+    t0 = time.perf_counter()
+    T = csp.csp_autotune(ctx, lats, [d["R"] for d in insts], params)
+    t_tune = time.perf_counter() - t0
+    corrs, rep = csp.csp_propagate_batch(ctx, lats, psis, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    corrs, rep = csp.csp_propagate_batch(ctx, lats, psis, params, corrs=corrs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ostates = sum(l.N * d["R"] for l, d in zip(lats, insts))
+    out["batch"] = {"workload": "32 lattices (square / honeycomb, 128^2..2048^2 cells, W ~ U[0,2], "
+                                "1-8 columns, seed 8), Nt=%d, complex64 state assembly" % Nt,
+                    "orbital_states": ostates, "s": el, "block_b": rep.block_b,
+                    "chunk_K": rep.chunk_K, "graph_blocks": rep.graph_blocks,
+                    "n_blocks": rep.n_blocks, "passes": rep.n_passes,
+                    "value": ostates * rep.amxsy / el, "autotune_s": t_tune,
+                    "tuned": {"spmm_vec": T.spmm_vec, "spmm_seg_rows": T.spmm_seg_rows,
+                              "spmm_steps": T.spmm_steps, "contract_wg_per_cu":
+                              T.contract_wg_per_cu}}
+    log("batch: %.2f s, b=%d, %d of %d blocks from the graph" % (el, rep.block_b,
+                                                                 rep.graph_blocks, rep.n_blocks))
+    del corrs, psis
+    for l in lats:
+        l.close()
+    ctx.close()
+    torch.cuda.empty_cache()
 
 
 def dense_dh(a):
@@ -482,8 +729,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
-    if a.dos_1e9:
-        dos_1e9(a)
+    if a.summarize_pmc:
+        summarize_pmc(*a.summarize_pmc)
         return
     if a.dense_dh:
         dense_dh(a)
@@ -491,233 +738,38 @@ def main():
     if a.ec:
         ec_bench(a)
         return
-    import numpy as np
     import torch
-    import paper_2510_17432_amd as csp
-
-    W = dict(WORKLOAD)
-    W["block_b"] = a.block_b
-    dev = "cuda:0"
     torch.cuda.set_device(0)
     if a.copy_probe:
-        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy probe: %d bytes read, %d written" % (COPY_PROBE_BYTES, COPY_PROBE_BYTES))
         del src, dst
-    ctx = csp.Context(0)
-    stream = ctx.stream
-    lat = csp.Lattice(ctx, W["kind"], W["Lx"], W["Ly"], t=W["t"], W=W["W"])
-    N = lat.N
-    R = W["R_rand"] + W["n_sites"]
-    Nt = W["Nt"]
-    psi = torch.empty((N, R), dtype=torch.complex64, device=dev)
-    corr = torch.empty((Nt + 1, R), dtype=torch.complex128, device=dev)
-    params = csp.make_params(Nt, mode="fp32_conc", block_b=W["block_b"], profile=True)
-    log("lattice N=%d |H|=%.6f R=%d Nt=%d b=%d" % (N, lat.halfwidth, R, Nt, W["block_b"]))
-
-    def step():
-        csp.csp_states_random_phase(ctx, psi, W["R_rand"], W["seed_states"], col0=0)
-        sites = csp.csp_ldos_sites(ctx, N, W["n_sites"], W["seed_sites"])
-        csp.csp_states_sites(ctx, psi, sites, col0=W["R_rand"])
-        _, rep = csp.csp_propagate(ctx, lat, psi, params, corr=corr)
-        E, D, Dm = csp.csp_dos(ctx, corr[:, :W["R_rand"]].contiguous(), lat.halfwidth)
-        E2, D2, _ = csp.csp_dos(ctx, corr[:, W["R_rand"]:].contiguous(), lat.halfwidth)
-        return rep, Dm
-
-    for i in range(a.warmup):
-        rep, _ = step()
-        log("warmup %d done: %.1f ms, spmm %.1f ms over %d launches" %
-            (i, rep.ms_total, rep.ms_spmm, rep.spmm_launches))
-    torch.cuda.synchronize()
-    reps = []
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        rep, Dm = step()
-        reps.append(rep)
-        log("step %d done: %.1f ms" % (i, rep.ms_total))
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_step = 1000.0 * el / a.steps
-    steps_exec = reps[-1].amxsy
-    value = N * R * steps_exec / (el / a.steps)
-
-    ms_spmm = sum(r.ms_spmm for r in reps)
-    n_spmm = sum(r.spmm_launches for r in reps)
-    bytes_spmm = sum(r.spmm_bytes for r in reps)
-    avg_launch_s = ms_spmm / 1000.0 / n_spmm
-    bytes_per_launch = bytes_spmm / n_spmm
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    ms_con = sum(r.ms_contract for r in reps)
-    n_con = sum(r.contract_launches for r in reps)
-    con_flops = sum(r.contract_flops for r in reps)
-    con_bytes = sum(r.contract_bytes for r in reps)
-    traffic = traffic_from_profiles()
-    # practical streaming ceilings of this device (context for the roofline)
-    bw_read, bw_write, bw_r2w1 = csp.csp_bandwidth_probe(ctx, 1 << 30)
-    ctx.trim()
     out = {
         "metric": "orbital·Chebyshev-steps/s + DOS time-to-accuracy, FP32 concurrent vs FP64 seq",
-        "value": value,
+        "value": None,
         "unit": "orbital*steps/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "graphene honeycomb 1024x1024 cells (N=%d), t=-2.7 eV, periodic, "
-                               "4 random-phase + 64 LDOS columns, Nt=2048, complex64 concurrent "
-                               "b=%d, split-bf16 MFMA contraction" % (N, rep.block_b),
-                   "orbitals": N, "columns": R, "Nt": Nt, "block_b": rep.block_b,
-                   "chunk_K": rep.chunk_K, "recursion_steps": steps_exec,
-                   "sequential_equivalent_steps": Nt * 20},
-        "roofline": {"bound": "hbm", "kernel": "k_cheb<float> (Chebyshev recursion, %d steps per launch)" % rep.spmm_steps,
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": avg_launch_s * 1e6,
-                     "streaming_ceiling_GBs": {"read": bw_read, "write": bw_write,
-                                               "two_reads_one_write": bw_r2w1},
-                     "frac_of_streaming_ceiling": achieved / bw_r2w1},
-        "contraction": {"kernel": "k_contract_f32 (split-bf16 MFMA)",
-                        "avg_launch_us": 1000.0 * ms_con / max(n_con, 1),
-                        "achieved_GBs": con_bytes / max(ms_con, 1e-9) / 1e6,
-                        "mfma_TFLOPs": con_flops / max(ms_con, 1e-9) / 1e9,
-                        "share_of_step": ms_con / max(ms_con + ms_spmm, 1e-9)},
-        "effective_rate": N * R * Nt * 20 / (el / a.steps),
     }
-
-    # the moment-based form (DOS-Concurrent-M of Sec. III: one block, halving)
-    # on the same step, outside the timed region
-    if not a.no_moments:
-        pm = csp.make_params(Nt, mode="fp32_conc", block_b=0, assembly=csp.CSP_ASSEMBLE_MOMENTS,
-                             profile=True)
-        csp.csp_propagate(ctx, lat, psi, pm, corr=corr)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, mrep = csp.csp_propagate(ctx, lat, psi, pm, corr=corr)
-        csp.csp_dos(ctx, corr[:, :W["R_rand"]].contiguous(), lat.halfwidth)
-        csp.csp_dos(ctx, corr[:, W["R_rand"]:].contiguous(), lat.halfwidth)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        mb = mrep.spmm_bytes / mrep.spmm_launches
-        mt = mrep.ms_spmm / 1000.0 / mrep.spmm_launches
-        out["moments"] = {"form": "moment-based, one block of %d steps, halving (DOS-Concurrent-M)"
-                                  % Nt,
-                          "ms_per_step": 1000.0 * tm, "recursion_steps": mrep.amxsy,
-                          "value": N * R * mrep.amxsy / tm,
-                          "sequential_equivalent_rate": N * R * Nt * 20 / tm,
-                          "kernel": "k_cheb<float, moments>", "bytes_per_launch": mb,
-                          "avg_launch_us": mt * 1e6, "achieved_GBs": mb / mt / 1e9,
-                          "frac": mb / mt / 1e9 / HBM_PEAK_GBS}
-        log("moments: %.3f s per step, %d recursion steps" % (tm, mrep.amxsy))
-
-    # quasi-eigenstates (QE-Concurrent-E) of the random columns at 5
-    # energies, Nt = 1024 (the paper's QE benchmark sizes), complex64 against
-    # complex128, outside the timed region
-    if not a.no_qe:
-        Rr = W["R_rand"]
-        Ntq = 1024
-        Eq = [-6.0, -2.7, 0.5, 2.7, 5.0]
-        pq32 = psi[:, :Rr].contiguous()
-        pq64 = pq32.to(torch.complex128)
-        res_q = {}
-        for name, pin, mode, bq in (("fp32", pq32, "fp32_conc", 0), ("fp64", pq64, "fp64_conc", 0),
-                                    ("fp32_state_b32", pq32, "fp32_conc", 32)):
-            prm = csp.make_params(Ntq, mode=mode, block_b=bq)
-            csp.csp_quasi_eigenstates(ctx, lat, pin, prm, Eq)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            q, qrep = csp.csp_quasi_eigenstates(ctx, lat, pin, prm, Eq)
-            torch.cuda.synchronize()
-            res_q[name] = (q, time.perf_counter() - t0, qrep)
-            log("quasi-eigenstates %s: %.3f s, %d orders, %d chunks" %
-                (name, res_q[name][1], qrep.amxsy, qrep.contract_launches))
-        q32, q64, qs = res_q["fp32"][0], res_q["fp64"][0], res_q["fp32_state_b32"][0]
-        qerr = float((q32.to(torch.complex128) - q64).abs().max().item() / q64.abs().max().item())
-        serr = float((qs.to(torch.complex128) - q64).abs().max().item() / q64.abs().max().item())
-        seq_steps = 2 * Ntq * 20
-        out["quasi_eigenstates"] = {
-            "form": "QE-Concurrent-E (energy-based, forward and backward merged)",
-            "Nt": Ntq, "energies_eV": Eq, "columns": Rr,
-            "fp32_s": res_q["fp32"][1], "fp64_s": res_q["fp64"][1],
-            "fp32_max_rel_err_vs_fp64": qerr,
-            "chebyshev_orders": res_q["fp32"][2].amxsy,
-            "sequential_chebyshev_steps": seq_steps,
-            "step_ratio_vs_sequential": seq_steps / res_q["fp32"][2].amxsy,
-            "state_based_b32": {"form": "QE-Concurrent-S, b = 32, complex64",
-                                "s": res_q["fp32_state_b32"][1],
-                                "chebyshev_steps": res_q["fp32_state_b32"][2].amxsy,
-                                "max_rel_err_vs_fp64_energy_based": serr}}
-        del q32, q64, qs, res_q, pq32, pq64
-
-    # time-to-accuracy: DOS of the random columns on this GPU, complex64
-    # concurrent forms vs the plain complex128 sequential form; each run is
-    # timed after a warm-up call (workspace allocated).  Every form is timed
-    # at eta = 1e-14 and at the loosest eta of 1e-4 .. 1e-12 whose DOS stays
-    # within 1e-4 of the complex128 sequential DOS at eta = 1e-14.
-    if not a.no_seq:
-        Rr = W["R_rand"]
-        p4 = psi[:, :Rr].contiguous()
-        p64 = p4.to(torch.complex128)
-
-        def timed(pin, **kw):
-            c = torch.empty((Nt + 1, Rr), dtype=torch.complex128, device=dev)
-            prm = csp.make_params(Nt, **kw)
-            csp.csp_propagate(ctx, lat, pin, prm, corr=c)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            csp.csp_propagate(ctx, lat, pin, prm, corr=c)
-            _, _, Dm = csp.csp_dos(ctx, c, lat.halfwidth)
-            torch.cuda.synchronize()
-            return c, Dm.cpu().numpy(), time.perf_counter() - t0
-
-        c64, d64, t64 = timed(p64, mode="fp64_seq")
-        log("fp64 sequential DOS (%d columns): %.3f s" % (Rr, t64))
-
-        def rel_err(d):
-            return float(np.max(np.abs(d - d64)) / np.max(np.abs(d64)))
-
-        forms = [("fp32_concurrent", p4, dict(mode="fp32_conc", block_b=W["block_b"])),
-                 ("fp64_sequential", p64, dict(mode="fp64_seq"))]
-        if not a.no_moments:
-            forms.insert(1, ("fp32_moments", p4, dict(mode="fp32_conc", block_b=0,
-                                                      assembly=csp.CSP_ASSEMBLE_MOMENTS)))
-        tta = {"target_rel_err": 1e-4, "columns": Rr, "fp64_sequential_s": t64}
-        for name, pin, kw in forms:
-            if name != "fp64_sequential":
-                c, d, t = timed(pin, **kw)
-                tta[name + "_s"] = t
-                tta[name + "_dos_rel_err"] = rel_err(d)
-                tta[name + "_corr_eps_inf"] = float((c - c64).abs().max().item())
-                tta[name + "_speedup"] = t64 / t
-                log("%s DOS (%d columns): %.3f s, rel err %.2e" % (name, Rr, t, rel_err(d)))
-            for eta in (1e-4, 1e-6, 1e-8, 1e-10, 1e-12):
-                _, d, t = timed(pin, eta=eta, **kw)
-                if rel_err(d) < 1e-4:
-                    tta[name + "_loosest_eta"] = {"eta": eta, "s": t, "dos_rel_err": rel_err(d)}
-                    log("%s at eta %.0e: %.3f s, rel err %.2e" % (name, eta, t, rel_err(d)))
-                    break
-        t64l = tta.get("fp64_sequential_loosest_eta", {}).get("s", t64)
-        for name in ("fp32_concurrent", "fp32_moments"):
-            if name + "_loosest_eta" in tta:
-                tta[name + "_speedup_at_loosest_eta"] = t64l / tta[name + "_loosest_eta"]["s"]
-        out["time_to_accuracy"] = tta
-    del psi, corr
-    lat.close()
-    ctx.close()
-    torch.cuda.synchronize()
-
+    c5_legs(a, out)
+    if not a.no_graphene:
+        graphene_leg(a, out)
+    if not a.no_batch:
+        batch_leg(a, out)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(W, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,8 @@
 """GPU parity at full size: graphene, honeycomb 1024 x 1024 cells
 (2 097 152 orbitals), periodic, t = -2.7 eV, 4 random-phase columns (seed 2)
 and 64 LDOS sites (seed 3), 2048 time steps, in the launch configuration
-that bench.py times (complex64, b = 32, split-bf16 MFMA contraction).
+of the graphene leg that bench.py times (complex64, b = 32, split-bf16 MFMA
+contraction).
 
 The reference is the oracle's band-structure closed form of the clean
 periodic lattice, valid at any size: every correlation at every time
