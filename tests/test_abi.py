@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(csp.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert csp.abi_version() == 1
+    assert csp.abi_version() == 2
 
 
 def test_struct_layouts():
