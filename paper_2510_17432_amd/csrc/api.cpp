@@ -1625,7 +1625,9 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
       st.slot_out[st.nlev - 1] = new_cur;
       if (st.nlev >= 2) st.slot_out[st.nlev - 2] = new_prev;
       st.dot_psi0 = (!halving || produced + 1 <= h || produced == 0) ? 1 : 0;
-      st.dot_self = halving ? 1 : 0;
+      // The halving identity reads <phi_k|phi_k> and <phi_k|phi_k-1> only for
+      // 2k - 1 > h, i.e. k >= floor(h/2) + 1: launches below that skip them.
+      st.dot_self = (halving && produced + st.nlev >= h / 2 + 1) ? 1 : 0;
       st.mom_slot = launches;
       st.partial = d_part;
       if (carry) {
