@@ -402,6 +402,24 @@ csp_status csp_dos(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t
                    double halfwidth, double center, double tau_tilde, int32_t window,
                    double *dev_E, double *dev_D, double *dev_Dmean);
 
+/* The same DOS transform as csp_dos, for callers that cannot allocate
+ * device memory: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, layout and results are those
+ * of csp_dos.  The 2 Nt complex128 twiddles live in a static device array
+ * of the library instead of a per-call allocation, so Nt is limited to
+ * CSP_DOS_NOALLOC_MAX_NT (8 MiB of device memory, held on every device the
+ * library runs on until the process ends); a larger Nt is rejected with
+ * CSP_EINVAL before any work is enqueued.  The call allocates nothing,
+ * enqueues its kernels on the context's stream and returns without
+ * synchronising (launch errors are reported; results are ready when the
+ * stream reaches them).  Every call on one device shares that device's
+ * array: calls that overlap on one device (other streams, other host
+ * threads) race on it; calls ordered on one stream do not. */
+#define CSP_DOS_NOALLOC_MAX_NT 262144
+csp_status csp_dos_noalloc(csp_context *ctx, const double *dev_corr, int64_t Nt, int32_t R,
+                           double halfwidth, double center, double tau_tilde, int32_t window,
+                           double *dev_E, double *dev_D, double *dev_Dmean);
+
 /* Autotuner.  For the instances (lats[i], R[i]) with params->mode and
  * params->assembly, times on this device every recursion launch shape
  * (values per lane in {2, 4}, Chebyshev steps per launch in {1, 2, 4, 8} as

@@ -144,6 +144,8 @@ _sig("csp_propagate_batch", [_vp, ctypes.c_int32, _P(_vp), _P(_vp), _P(ctypes.c_
                              _P(Params), _P(_vp), _P(Report)])
 _sig("csp_dos", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                  ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp])
+_sig("csp_dos_noalloc", [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp])
 _sig("csp_select_block", [_vp, _vp, ctypes.c_int32, _P(Params), _P(ctypes.c_int32), _P(Report)])
 _sig("csp_quasi_eigenstates", [_vp, _vp, _vp, ctypes.c_int32, _P(Params), ctypes.c_int32,
                                _P(ctypes.c_double), _vp, _P(Report)])
@@ -464,6 +466,17 @@ def csp_dos(ctx, corr, halfwidth, tau_tilde=math.pi, window=CSP_WINDOW_HANN, cen
     _check(_lib.csp_dos(ctx.handle, _ptr(corr), Nt, R, float(halfwidth), float(center),
                         float(tau_tilde), int(window), _ptr(E), _ptr(D), _ptr(Dm)))
     return E, D, Dm
+
+
+def csp_dos_noalloc(ctx, corr, halfwidth, E, D, Dmean=None, tau_tilde=math.pi,
+                    window=CSP_WINDOW_HANN, center=0.0):
+    """csp_dos into caller-owned float64 device tensors E [2Nt], D [2Nt][R]
+    and Dmean [2Nt] (or None); the library allocates nothing and does not
+    synchronise the stream."""
+    Nt = corr.shape[0] - 1
+    R = corr.shape[1]
+    _check(_lib.csp_dos_noalloc(ctx.handle, _ptr(corr), Nt, R, float(halfwidth), float(center),
+                                float(tau_tilde), int(window), _ptr(E), _ptr(D), _ptr(Dmean)))
 
 
 def csp_select_block(ctx, lat, R, params):

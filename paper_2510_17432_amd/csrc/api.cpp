@@ -80,6 +80,7 @@ struct csp_context {
   std::vector<hipEvent_t> events;   // pool for profiling
   std::map<std::string, csp_tuning> tuned;  // autotuner results per shape
   hipStream_t cap = nullptr;                 // library stream for HIP graph capture
+  double* dos_scratch = nullptr;             // this device's csp_dos_noalloc twiddles
 };
 
 struct csp_lattice {
@@ -201,10 +202,13 @@ extern "C" csp_status csp_context_create(int device, void* hip_stream, csp_conte
   HIPCALL(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(CSP_EUNSUPPORTED, "libcsp is built for gfx950, device is %s", prop.gcnArchName);
+  double* scratch = nullptr;
+  HIPCALL(dos_noalloc_scratch(device, &scratch));   // once per device, device current
   csp_context* c = new csp_context();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->dos_scratch = scratch;
   *out = c;
   return CSP_OK;
 }
@@ -2497,6 +2501,26 @@ extern "C" csp_status csp_dos(csp_context* c, const double* dev_corr, int64_t Nt
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(tw);
   if (e != hipSuccess) return fail(CSP_EHIP, "dos: %s", hipGetErrorString(e));
+  return CSP_OK;
+}
+
+extern "C" csp_status csp_dos_noalloc(csp_context* c, const double* dev_corr, int64_t Nt,
+                                      int32_t R, double halfwidth, double center,
+                                      double tau_tilde, int32_t window, double* dev_E,
+                                      double* dev_D, double* dev_Dmean) {
+  if (!c || !dev_corr || !dev_E || !dev_D) return fail(CSP_EINVAL, "NULL argument");
+  if (Nt < 1 || R < 1 || !(halfwidth > 0)) return fail(CSP_EINVAL, "need Nt >= 1, R >= 1, |H| > 0");
+  if (Nt > CSP_DOS_NOALLOC_MAX_NT)
+    return fail(CSP_EINVAL, "Nt = %lld exceeds the %d time steps of the static twiddle scratch",
+                (long long)Nt, CSP_DOS_NOALLOC_MAX_NT);
+  if (!std::isfinite(center)) return fail(CSP_EINVAL, "center is not finite");
+  if (window != CSP_WINDOW_HANN && window != CSP_WINDOW_NONE) return fail(CSP_EINVAL, "bad window");
+  if (!(tau_tilde > 0)) tau_tilde = M_PI;
+  if (!c->dos_scratch) return fail(CSP_EHIP, "no scratch address for device %d", c->device);
+  DeviceGuard dg(c->device);
+  const hipError_t e = launch_dos(dev_corr, Nt, R, halfwidth, center, tau_tilde, window, dev_E,
+                                  dev_D, dev_Dmean, c->dos_scratch, c->stream);
+  if (e != hipSuccess) return fail(CSP_EHIP, "dos_noalloc: %s", hipGetErrorString(e));
   return CSP_OK;
 }
 

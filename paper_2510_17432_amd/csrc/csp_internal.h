@@ -398,6 +398,10 @@ hipError_t launch_guard(int64_t N, int Rg, const void* d_carry, bool fp64, const
                         int64_t ldc, int col0, int64_t t0, int bk, double tol, int block,
                         const int64_t* blk_dev, int* d_flag, double* d_scratch,
                         int n_scratch_wg, hipStream_t s);
+// Device address of this device's static twiddle scratch of
+// csp_dos_noalloc (2 CSP_DOS_NOALLOC_MAX_NT complex128), looked up once per
+// device with that device current and kept for the process.
+hipError_t dos_noalloc_scratch(int device, double** out);
 // DOS of the centred correlations on the energies center + E_k; d_twiddle
 // holds 2 Nt complex128 values (written here before they are read).
 hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth, double center,

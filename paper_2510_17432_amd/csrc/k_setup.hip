@@ -1,6 +1,8 @@
 // Set-up and small kernels: on-site disorder, spectral bound, neighbour
 // table, random-phase and localized states, column-group gather/scatter,
 // <psi0|psi0>, and the DOS transform (Sec. III).
+#include <mutex>
+
 #include "csp_internal.h"
 
 namespace csp {
@@ -347,6 +349,32 @@ hipError_t launch_dos(const double* d_corr, int64_t Nt, int R, double halfwidth,
   hipLaunchKernelGGL(k_dos_mean, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, n, R, d_D,
                      d_Dmean, d_E, dE, Nt, center);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ DOS without allocation
+// The twiddle table of csp_dos_noalloc: a static device array, one copy per
+// device for the life of the process.  In host code `scratch` is a host-side
+// stand-in; kernels get the device address from hipGetSymbolAddress, looked
+// up once per device (that device current) and kept in g_scratch.
+static __device__ __align__(256) double2 scratch[2 * CSP_DOS_NOALLOC_MAX_NT];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t dos_noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
 }
 
 }  // namespace csp
