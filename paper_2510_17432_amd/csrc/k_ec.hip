@@ -277,7 +277,13 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(tid >> 6));
   const int il = lane & 31, h = lane >> 5;
-  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  // logical workgroup (slice, energy tile), the tiles of a slice adjacent:
+  // they land on one XCD at the same time and stream the same orders, which
+  // the second and later tiles find in that XCD's L2
+  const int n_et = (a.nE + 31) / 32;
+  const int64_t lwg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t wg = lwg / n_et;
+  const int e_tile = 32 * static_cast<int>(lwg - wg * n_et);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const EcInst& I = insts[ii];
@@ -287,7 +293,6 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
   const int64_t N = I.N;
   const int64_t s_beg = (int64_t)sl * I.slice_len;
   const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
-  const int e_tile = 32 * blockIdx.y;
 
   // staging roles: row (lane >> 4) of each group of four, 2 orbitals at 2 (lane & 15)
   const int sub = lane >> 4, ch = lane & 15;
@@ -398,7 +403,12 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
   __shared__ double2 sa[128 * kEc64Row];
   __shared__ double2 sb[16 * kEc64Row];
   const int tid = threadIdx.x;
-  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+  // logical workgroup (slice, energy tile), the tiles of a slice adjacent
+  // (one XCD, the same orders at the same time: L2 hits after the first)
+  const int n_et = (a.nE + 15) / 16;
+  const int64_t lwg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t wg = lwg / n_et;
+  const int e0 = 16 * static_cast<int>(lwg - wg * n_et);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const EcInst& I = insts[ii];
@@ -408,7 +418,6 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
   const int64_t N = I.N;
   const int64_t s_beg = (int64_t)sl * I.slice_len;
   const int64_t s_end = s_beg + I.slice_len < N ? s_beg + I.slice_len : N;
-  const int e0 = 16 * blockIdx.y;
   const int col = tid & 31, rsub = tid >> 5;        // staging: orbital col of row 8 j + rsub
 
   const double2* arow[16];
@@ -517,7 +526,7 @@ hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const 
     int ne = 1;
     while (ne < std::min(a.nE, 16)) ne *= 2;
 #define CSP_EC64(NE) \
-  hipLaunchKernelGGL(k_ec_moments_f64<NE>, dim3(a.total_wg, n_et), dim3(256), 0, s, d_inst, a)
+  hipLaunchKernelGGL(k_ec_moments_f64<NE>, dim3(a.total_wg * n_et), dim3(256), 0, s, d_inst, a)
     switch (ne) {
       case 1: CSP_EC64(1); break;
       case 2: CSP_EC64(2); break;
@@ -527,7 +536,7 @@ hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const 
     }
 #undef CSP_EC64
   } else {
-    hipLaunchKernelGGL(k_ec_moments_f32, dim3(a.total_wg, n_et), dim3(256), 0, s, d_inst, a);
+    hipLaunchKernelGGL(k_ec_moments_f32, dim3(a.total_wg * n_et), dim3(256), 0, s, d_inst, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -248,14 +248,20 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
   const int lane = tid & 63, wave = tid >> 6;
   const int il = lane & 31, h = lane >> 5;
   Bop* sb = reinterpret_cast<Bop*>(smem);
-  const int e_base = 32 * blockIdx.y;                 // energy tile
+  // logical workgroup (tile of values, energy tile), the energy tiles of a
+  // value tile adjacent: they run on one XCD at the same time and read the
+  // same Chebyshev values, which the later tiles find in that XCD's L2
+  const int n_et = (a.nE + (a.cplx ? 1 : 0) + 31) / 32;
+  const int64_t lwg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t wg = lwg / n_et;
+  const int et = static_cast<int>(lwg - wg * n_et);
+  const int e_base = 32 * et;                         // energy tile
   {
-    const Bop* gb = static_cast<const Bop*>(a.bop) + (int64_t)blockIdx.y * a.e_tile_stride;
+    const Bop* gb = static_cast<const Bop*>(a.bop) + (int64_t)et * a.e_tile_stride;
     for (int e = tid; e < n_kb * 64; e += kContractThreads) sb[e] = gb[e];
   }
   __syncthreads();
 
-  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const QeInst& I = insts[ii];
@@ -372,13 +378,18 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
   extern __shared__ __align__(16) unsigned char smem[];
   double2* scoef = reinterpret_cast<double2*>(smem);   // [n_cnt][B]
   const int tid = threadIdx.x;
-  const int e_base = B * blockIdx.y;                   // energy tile
+  // logical workgroup (tile of values, energy tile), energy tiles adjacent
+  // (one XCD, the same Chebyshev values at the same time: L2 hits)
+  const int n_et = (a.nE + (a.cplx ? 1 : 0) + B - 1) / B;
+  const int64_t lwg = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t wg = lwg / n_et;
+  const int et = static_cast<int>(lwg - wg * n_et);
+  const int e_base = B * et;                           // energy tile
   {
-    const double2* gc = static_cast<const double2*>(a.coef) + (int64_t)blockIdx.y * a.e_tile_stride;
+    const double2* gc = static_cast<const double2*>(a.coef) + (int64_t)et * a.e_tile_stride;
     for (int e = tid; e < a.n_cnt * B; e += kContractThreads) scoef[e] = gc[e];
   }
   __syncthreads();
-  const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const QeInst& I = insts[ii];
@@ -431,7 +442,7 @@ hipError_t launch_contract_qe(bool fp64, const QeInst* d_inst, const QeArgs& a, 
   const int rows = a.nE + (a.cplx ? 1 : 0);          // energies (+ the carried state)
   if (a.nE < 1 || rows > 129 || (a.cplx && rows > (fp64 ? 16 : 32))) return hipErrorInvalidValue;
   if (!fp64) {
-    const dim3 g2(a.total_wg, (unsigned)ceil_div(rows, 32));
+    const dim3 g2((unsigned)(a.total_wg * ceil_div(rows, 32)));
     if (a.cplx) {
       const size_t lds = sizeof(QeBop4) * 64 * (size_t)ceil_div(a.n_cnt, 16);
       hipLaunchKernelGGL(k_contract_qe_f32<true>, g2, block, lds, s, d_inst, a);
@@ -443,7 +454,7 @@ hipError_t launch_contract_qe(bool fp64, const QeInst* d_inst, const QeArgs& a, 
   }
   int B = 1;
   while (B < rows && B < 16) B *= 2;
-  const dim3 grid2(a.total_wg, (unsigned)ceil_div(rows, B));
+  const dim3 grid2((unsigned)(a.total_wg * ceil_div(rows, B)));
   const size_t lds = sizeof(double2) * (size_t)a.n_cnt * B;
   switch (B) {
     case 1: hipLaunchKernelGGL(k_contract_qe_f64<1>, grid2, block, lds, s, d_inst, a); break;
