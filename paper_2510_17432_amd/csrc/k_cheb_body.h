@@ -308,24 +308,16 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     outv[l] = st.slot_out[l] >= 0 ? base + 2 * (int64_t)st.slot_out[l] * I.slot_stride + coff
                                   : nullptr;
 
-  // ---- register rows: the last three rows of levels 0..KT-1.  With ROT
-  // (the moment kernels, whose epilogue makes them instruction-bound)
-  // rw[l][k] holds them in slots that rotate with the row index: before an
-  // iteration of phase P = i mod 3, slot P is the oldest row, P+1 the middle
-  // one and P+2 the newest; the iteration overwrites slot P with the new
-  // row, and the row loop is unrolled by three so that every slot index is
-  // a constant (rotation by renaming, no register moves).  Without ROT (the
-  // plain recursion, bound by memory, where the unrolled loop costs
-  // registers and occupancy) every iteration moves the rows down by one
-  // slot and writes the new row into slot 2.
-  constexpr bool ROT = MOM;
-  C rw[KT][3][V];
+  // ---- register rows: lo/mid/hi = the last three rows of levels 0..KT-1
+  C lo[KT][V], mid[KT][V], hi[KT][V];
 #pragma unroll
   for (int l = 0; l < KT; ++l)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int v = 0; v < V; ++v) rw[l][k][v] = {T(0), T(0)};
+    for (int v = 0; v < V; ++v) {
+      lo[l][v] = {T(0), T(0)};
+      mid[l][v] = {T(0), T(0)};
+      hi[l][v] = {T(0), T(0)};
+    }
   T er[EPS ? KT + 1 : 1][V];                         // on-site energies of rows r0 - k
 #pragma unroll
   for (int k = 0; k < (EPS ? KT + 1 : 1); ++k)
@@ -343,27 +335,12 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
   for (int k = 0; k < NQ; ++k) sq[k] = T(0);
   double accq = 0.0;
-  // psi0 rows r0 - k (moment epilogue) in a ring of KT + 1 rows in LDS,
-  // private to the wave: row r0 = rbase + i sits in slot i mod (KT + 1) and
-  // level l reads slot (i - l) mod (KT + 1).  A lane writes and reads only
-  // its own V values, and the LDS operations of a wave complete in order,
-  // so no barrier is needed.
-  constexpr int PQR = MOM ? KT + 1 : 1;
-  __shared__ __align__(16) T pq_lds[MOM ? 4 * PQR * 64 * 2 * V : 2];
-  T* pq_wave = pq_lds + (MOM ? (int64_t)wave * PQR * 64 * 2 * V : 0);
-  auto pq_put = [&](int slot, const C (&d)[V]) {
-    T* q = pq_wave + ((int64_t)slot * 64 + lane) * 2 * V;
+  // psi0 rows r0 - k (moment epilogue)
+  C pq[MOM ? KT + 1 : 1][V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      q[2 * v] = d[v].x;
-      q[2 * v + 1] = d[v].y;
-    }
-  };
-  auto pq_get = [&](int slot, C (&d)[V]) {
-    const T* q = pq_wave + ((int64_t)slot * 64 + lane) * 2 * V;
+  for (int k = 0; k < (MOM ? KT + 1 : 1); ++k)
 #pragma unroll
-    for (int v = 0; v < V; ++v) d[v] = {q[2 * v], q[2 * v + 1]};
-  };
+    for (int v = 0; v < V; ++v) pq[k][v] = {T(0), T(0)};
   const bool dots = MOM && (st.dot_psi0 || st.dot_self);
   const bool want_psi0 = MOM && st.dot_psi0;
   // carried state: partial sums of rows r0 - 1 - j (j < KT) in registers;
@@ -380,11 +357,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   const T beta0 = static_cast<T>(I.beta0);
   const T oscale = static_cast<T>(I.onsite_scale);
   const bool vert = I.kind != CSP_CHAIN;
-  // iterations: the segment's rows and nlev margin rows on each side, with
-  // ROT rounded up to a multiple of three (the extra iterations compute
-  // rows past the segment, which are neither stored nor summed; their loads
-  // are of rows inside the lattice)
-  const int n_iter = ROT ? ((y1 - y0) + 2 * nlev + 2) / 3 * 3 : (y1 - y0) + 2 * nlev;
+  const int n_iter = (y1 - y0) + 2 * nlev;
   const int rbase = y0 - nlev;                       // level-0 row of iteration 0
 
   // The row loop, compiled twice: FAST for strips inside the row (no wrap,
@@ -394,13 +367,13 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     constexpr bool FAST = decltype(fast_tag)::value;
     auto load_row = [&](const gT* vec, int r, C (&d)[V]) {
       bool rp;
-      const int rw_ = row_of(r, rp);
+      const int rw = row_of(r, rp);
       if (!rp) {
 #pragma unroll
         for (int v = 0; v < V; ++v) d[v] = {T(0), T(0)};
         return;
       }
-      const gT* rowp = vec + row_off(rw_);
+      const gT* rowp = vec + row_off(rw);
       if constexpr (FAST) {
         ldv<V>(rowp + 2 * p0 + 2 * lq, d);
       } else {
@@ -410,13 +383,13 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     };
     auto load_eps = [&](int r, T (&d)[V]) {
       bool rp;
-      const int rw_ = row_of(r, rp);
+      const int rw = row_of(r, rp);
       if (!rp) {
 #pragma unroll
         for (int v = 0; v < V; ++v) d[v] = T(0);
         return;
       }
-      const gT* rowp = eps + row_off(rw_) / 2;
+      const gT* rowp = eps + row_off(rw) / 2;
       if constexpr (FAST) {
         ldr<V>(rowp + p0 + lq, d);
       } else {
@@ -425,8 +398,8 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
       }
     };
     // row rw must be inside [0, Ly); nt: non-temporal (Chebyshev slots)
-    auto store_row = [&](gT* vec, int rw_, const C (&o)[V], bool nt) {
-      gT* rowp = vec + row_off(rw_);
+    auto store_row = [&](gT* vec, int rw, const C (&o)[V], bool nt) {
+      gT* rowp = vec + row_off(rw);
       if constexpr (FAST) {
         if (lane_own) {
           if (nt) stv_nt<V>(rowp + 2 * p0 + 2 * lq, o);
@@ -454,29 +427,15 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     if (carry_in) load_row(carry, rbase - nlev, ncar);
 
     int flush_in = kFlush;                           // rows left before the next flush
-    // one iteration: level 0 takes row r0 = rbase + i, level l computes row
-    // r0 - l; P = i mod 3 selects the register slots
-    auto iter = [&](auto phase_tag, int i) {
-      constexpr int P = ROT ? decltype(phase_tag)::value : 2;
-      // slots after this iteration's new rows: oldest, middle, newest
-      constexpr int SLO = (P + 1) % 3, SMI = (P + 2) % 3, SHI = P;
+#pragma unroll 1
+    for (int i = 0; i < n_iter; ++i) {
       const int r0 = rbase + i;
-      // without ROT each level moves its rows down one slot just before it
-      // writes its new row (level 0 here, level l after computing it)
-      auto shift_down = [&](int l) {
-        if constexpr (!ROT) {
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            rw[l][0][v] = rw[l][1][v];
-            rw[l][1][v] = rw[l][2][v];
-          }
-        }
-      };
-      shift_down(0);
       // level 0 takes row r0
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        rw[0][SHI][v] = ncur[v];
+        lo[0][v] = mid[0][v];
+        mid[0][v] = hi[0][v];
+        hi[0][v] = ncur[v];
         pv[v] = nprev[v];
       }
       if constexpr (EPS) {
@@ -488,9 +447,15 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
         for (int v = 0; v < V; ++v) er[0][v] = neps[v];
       }
       if constexpr (MOM) {
-        if (want_psi0) pq_put(i % PQR, npq);
 #pragma unroll
-        for (int v = 0; v < V; ++v) car[v] = ncar[v];
+        for (int k = KT; k >= 1; --k)
+#pragma unroll
+          for (int v = 0; v < V; ++v) pq[k][v] = pq[k - 1][v];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          pq[0][v] = npq[v];
+          car[v] = ncar[v];
+        }
       }
       if constexpr (CARRY) {
 #pragma unroll
@@ -508,20 +473,20 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
         if (carry_in) load_row(carry, r0 + 1 - nlev, ncar);
       }
       // phi_n itself for the contraction (order 0 of a block)
-      if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, rw[0][SHI], true);
+      if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0], true);
 
 #pragma unroll
       for (int l = 1; l <= KT; ++l) {
         if (l > nlev || i < 2 * l) break;
         const int r = r0 - l;
         bool rp;
-        const int rwr = row_of(r, rp);
+        const int rw = row_of(r, rp);
         const T scale = (l == 1 && st.first) ? T(0.5) : T(1);
         const T as = scale * alpha, bs = scale * beta0, os_ = scale * oscale;
         // level l-1 rows r - 1, r, r + 1 and level l-2 row r (phi_{n+l-2})
-        const C(&up)[V] = rw[l - 1][SLO];
-        const C(&c)[V] = rw[l - 1][SMI];
-        const C(&dn)[V] = rw[l - 1][SHI];
+        const C(&up)[V] = lo[l - 1];
+        const C(&c)[V] = mid[l - 1];
+        const C(&dn)[V] = hi[l - 1];
         C o[V];
         if (rp) {
           const T lx = shr1(c[V - 1].x), ly = shr1(c[V - 1].y);
@@ -545,7 +510,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                 ny += up[v].y + dn[v].y;
               }
             }
-            const C p = l == 1 ? pv[v] : rw[l - 2 >= 0 ? l - 2 : 0][SLO][v];
+            const C p = l == 1 ? pv[v] : lo[l - 2 >= 0 ? l - 2 : 0][v];
             T beta = bs;
             if constexpr (EPS) beta = bs + os_ * er[l][v];
             o[v].x = as * nx + (beta * c[v].x - p.x);
@@ -561,12 +526,15 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
           for (int v = 0; v < V; ++v) o[v] = {T(0), T(0)};
         }
         if (l < KT) {
-          shift_down(l < KT ? l : 0);
 #pragma unroll
-          for (int v = 0; v < V; ++v) rw[l < KT ? l : 0][SHI][v] = o[v];
+          for (int v = 0; v < V; ++v) {
+            lo[l][v] = mid[l][v];
+            mid[l][v] = hi[l][v];
+            hi[l][v] = o[v];
+          }
         }
         if (r >= y0 && r < y1) {
-          if (outv[l - 1]) store_row(outv[l - 1], rwr, o, true);
+          if (outv[l - 1]) store_row(outv[l - 1], rw, o, true);
           if constexpr (MOM) {
             if (dots) {
               // values outside the owned positions take no part in the sums
@@ -579,12 +547,11 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                 oo[v] = w ? o[v] : C{T(0), T(0)};
                 cc[v] = w ? c[v] : C{T(0), T(0)};
               }
+              const C(&q)[V] = pq[l];
               const int q0 = 5 * (l - 1);
-              if (want_psi0) {
-                C q[V];
-                pq_get((i - l) % PQR, q);            // psi0 row r0 - l
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
+              for (int v = 0; v < V; ++v) {
+                if (want_psi0) {
                   sq[q0] += q[v].x * oo[v].x + q[v].y * oo[v].y;
                   sq[q0 + 1] += q[v].x * oo[v].y - q[v].y * oo[v].x;
                   if (l == 1) {
@@ -592,10 +559,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                     sq[5 * KT + 1] += q[v].x * cc[v].y - q[v].y * cc[v].x;
                   }
                 }
-              }
-              if (st.dot_self) {
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
+                if (st.dot_self) {
                   sq[q0 + 2] += oo[v].x * oo[v].x + oo[v].y * oo[v].y;
                   sq[q0 + 3] += oo[v].x * c[v].x + oo[v].y * c[v].y;
                   sq[q0 + 4] += oo[v].x * c[v].y - oo[v].y * c[v].x;
@@ -629,7 +593,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                     b[v].y += car[v].y;
                   }
                 }
-                store_row(carry, rwr, b, false);
+                store_row(carry, rw, b, false);
               }
             }
           }
@@ -648,17 +612,6 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
           }
         }
       }
-    };
-    if constexpr (ROT) {
-#pragma unroll 1
-      for (int i = 0; i < n_iter; i += 3) {
-        iter(std::integral_constant<int, 0>{}, i);
-        iter(std::integral_constant<int, 1>{}, i + 1);
-        iter(std::integral_constant<int, 2>{}, i + 2);
-      }
-    } else {
-#pragma unroll 1
-      for (int i = 0; i < n_iter; ++i) iter(std::integral_constant<int, 2>{}, i);
     }
   };
   if (fast) run(std::true_type{});
