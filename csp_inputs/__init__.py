@@ -130,3 +130,33 @@ def random_symmetric_ell(N, n_pairs, seed=0, diag=True):
             col[s, k] = c
             val[s, k] = x
     return col, val
+
+
+def long_range_with_far_pairs(L=48, r_cut=3.0, n_rows=160, extra=70, seed=6):
+    """The long-range square lattice of long_range_square (t0 = -1,
+    decay 1.5, W = 0.7) with `extra` additional symmetric entries of normal
+    values (scale 0.3) between each of the first n_rows rows and uniformly
+    drawn far rows: most slices of 128 neighbouring rows still name a few
+    hundred columns, the slices that hold those rows name thousands.
+    Rows are padded to the longest with col = -1.  Returns (col int32
+    [N][D], val float64 [N][D])."""
+    col, val = long_range_square(L, r_cut, t0=-1.0, decay=1.5, W=0.7, seed=seed)
+    N = col.shape[0]
+    rng = np.random.default_rng(seed)
+    rows = [list(zip(col[s].tolist(), val[s].tolist())) for s in range(N)]
+    for s in range(n_rows):
+        for j in rng.choice(N, size=extra, replace=False):
+            j = int(j)
+            if j == s or any(c == j for c, _ in rows[s]):
+                continue
+            v = float(rng.normal()) * 0.3
+            rows[s].append((j, v))
+            rows[j].append((s, v))
+    D = max(len(r) for r in rows)
+    c2 = np.full((N, D), -1, dtype=np.int32)
+    v2 = np.zeros((N, D), dtype=np.float64)
+    for s, r in enumerate(rows):
+        for k, (c, v) in enumerate(r):
+            c2[s, k] = c
+            v2[s, k] = v
+    return c2, v2

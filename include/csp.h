@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CSP_ABI_VERSION 2
+#define CSP_ABI_VERSION 3
 
 typedef enum {
     CSP_OK = 0,
@@ -117,6 +117,10 @@ typedef struct {
     double gershgorin;         /* max_s |eps_s - H0| + deg(s)|t| */
     int32_t max_degree;        /* 2, 4 or 3 bond ends per orbital */
     int32_t has_onsite;        /* W != 0 */
+    int32_t ell_windowed;      /* explicit matrix: its recursion stages each
+                                  slice's window of phi_n in LDS (see
+                                  csp_lattice_create_sparse) */
+    int32_t ell_max_window;    /* explicit matrix, windowed: largest window */
 } csp_lattice_info;
 
 typedef struct {
@@ -229,14 +233,22 @@ csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
  * FP64 and FP32.  H0 = 0 and |H| = margin * max_s sum_k |val_sk|
  * (Gershgorin, reduced on the GPU in FP64; margin <= 0 selects 1.025).
  * Such a lattice runs through every propagation entry point; its recursion
- * applies one Chebyshev step per launch (a gathered sparse product).  In
- * complex64 a call on it also keeps, per group of Rg columns, two
- * orbital-major copies of floor(Rg/2) column pairs (32 floor(Rg/2) N bytes)
- * in context memory outside mem_cap_bytes, released by csp_context_trim.
+ * applies one Chebyshev step per launch (a gathered sparse product).  When
+ * at least half of the slices of 128 rows, regrouped to be compact in the
+ * matrix graph, name at most 2048 distinct columns that each serve four or
+ * more entries, a second, windowed copy of the matrix is kept (rows per
+ * slice, 16-bit window-local and 32-bit global columns, FP32 values: 10 B
+ * per entry, rows padded to a multiple of 4 entries, besides the 16 of the
+ * slice layout) and the complex64 recursion stages each slice's window of
+ * phi_n in LDS; csp_lattice_get_info reports it.  Otherwise, in complex64 a
+ * call on it keeps, per group of Rg columns, two orbital-major copies of
+ * floor(Rg/2) column pairs (32 floor(Rg/2) N bytes) in context memory
+ * outside mem_cap_bytes, released by csp_context_trim.
  * csp_lattice_onsite and csp_lattice_neighbors return CSP_EUNSUPPORTED for
  * it.  Errors: CSP_EINVAL for N outside [1, 2^31), D outside [1, 4096], a
  * column index >= N, a non-finite value or an all-zero matrix; CSP_ENOMEM
- * when the device cannot hold the 16 D N bytes of the matrix. */
+ * when the device cannot hold the 16 D N bytes of the matrix (about 26 D N
+ * with the windowed copy). */
 csp_status csp_lattice_create_sparse(csp_context *ctx, int64_t N, int32_t D, const int32_t *col,
                                      const double *val, double margin, csp_lattice **out);
 /* Orbital coordinates of an explicit matrix, for the current operator

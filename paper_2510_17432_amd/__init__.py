@@ -57,7 +57,8 @@ class LatticeInfo(ctypes.Structure):
     _fields_ = [("n_orb", ctypes.c_int64), ("rows", ctypes.c_int64),
                 ("orb_per_row", ctypes.c_int64), ("H0", ctypes.c_double),
                 ("halfwidth", ctypes.c_double), ("gershgorin", ctypes.c_double),
-                ("max_degree", ctypes.c_int32), ("has_onsite", ctypes.c_int32)]
+                ("max_degree", ctypes.c_int32), ("has_onsite", ctypes.c_int32),
+                ("ell_windowed", ctypes.c_int32), ("ell_max_window", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):

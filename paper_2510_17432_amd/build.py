@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 SOURCES = ["k_cheb_f32.hip", "k_cheb_f32m.hip", "k_cheb_f32mc.hip", "k_cheb_f64.hip",
            "k_cheb_f64mc.hip", "k_setup.hip", "k_coeffs.hip",
            "k_cheb.hip", "k_cheb_ell.hip", "k_contract.hip", "k_moments.hip",
-           "k_probe.hip", "k_qe.hip", "k_ec.hip", "api.cpp"]
+           "k_probe.hip", "k_qe.hip", "k_ec.hip", "k_cheb_ellw.hip", "ell_windows.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I" + INCLUDE, "-I" + SRC,

@@ -99,6 +99,16 @@ struct csp_lattice {
   // orbital coordinates of an explicit matrix ([N][2]) and periodic box
   double* pos = nullptr;
   double box[2] = {0.0, 0.0};
+  // windowed layout of an explicit matrix (see ell_windows.cpp); null when
+  // the matrix's slices are not compact enough for it to pay
+  int32_t* ellw_rows = nullptr;
+  uint16_t* ellw_loc = nullptr;
+  int32_t* ellw_col = nullptr;
+  float* ellw_v32 = nullptr;
+  int64_t* ellw_off = nullptr;
+  int32_t* ellw_idx = nullptr;
+  std::vector<int32_t> ellw_sizes;   // window size of every slice (host)
+  std::vector<int32_t> ellw_sorted;  // the same, ascending
 };
 
 namespace {
@@ -341,6 +351,10 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
     if (L->ell_col) (void)hipFree(L->ell_col);
     if (L->ell_v64) (void)hipFree(L->ell_v64);
     if (L->ell_v32) (void)hipFree(L->ell_v32);
+    for (void* q : {(void*)L->ellw_rows, (void*)L->ellw_loc, (void*)L->ellw_col,
+                    (void*)L->ellw_v32, (void*)L->ellw_off,
+                    (void*)L->ellw_idx})
+      if (q) (void)hipFree(q);
     delete L;
     return st;
   };
@@ -363,6 +377,43 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (d_part) (void)hipFree(d_part);
   if (e != hipSuccess) return cleanup(fail(CSP_EHIP, "matrix set-up: %s", hipGetErrorString(e)));
+  {
+    // The windowed layout pays when most slices name few distinct columns:
+    // at least half of them with a window that fits a 4-column complex64
+    // workgroup's LDS and is read four or more times per step.
+    EllWindows w;
+    build_ell_windows(N, D, col, val, &w);
+    const int64_t cap4 = kEllwLdsBytes / (4 * (int64_t)sizeof(float2));
+    int64_t good = 0;
+    for (int64_t k = 0; k < w.n_slices; ++k) {
+      const int64_t W = w.off[k + 1] - w.off[k];
+      if (W > 0 && W <= cap4 && 128 * (int64_t)D >= 4 * W) ++good;
+    }
+    if (2 * good >= w.n_slices) {
+      const size_t ne = w.loc.size();
+      auto up = [&](void** dst, const void* src, size_t bytes) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(dst, bytes ? bytes : 1);
+        if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+      };
+      up((void**)&L->ellw_rows, w.rows.data(), sizeof(int32_t) * w.rows.size());
+      up((void**)&L->ellw_loc, w.loc.data(), sizeof(uint16_t) * ne);
+      up((void**)&L->ellw_col, w.col.data(), sizeof(int32_t) * ne);
+      up((void**)&L->ellw_v32, w.v32.data(), sizeof(float) * ne);
+      up((void**)&L->ellw_off, w.off.data(), sizeof(int64_t) * w.off.size());
+      up((void**)&L->ellw_idx, w.idx.data(), sizeof(int32_t) * w.idx.size());
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return cleanup(fail(CSP_ENOMEM, "windowed explicit matrix of %lld entries: %s",
+                            (long long)ne, hipGetErrorString(e)));
+      }
+      L->ellw_sizes.resize(w.n_slices);
+      for (int64_t k = 0; k < w.n_slices; ++k)
+        L->ellw_sizes[k] = static_cast<int32_t>(w.off[k + 1] - w.off[k]);
+      L->ellw_sorted = L->ellw_sizes;
+      std::sort(L->ellw_sorted.begin(), L->ellw_sorted.end());
+    }
+  }
   double m = 0.0;
   for (double v : part) m = std::max(m, v);
   L->gersh = m;
@@ -383,6 +434,10 @@ extern "C" csp_status csp_lattice_destroy(csp_lattice* L) {
   if (L->ell_v64) (void)hipFree(L->ell_v64);
   if (L->ell_v32) (void)hipFree(L->ell_v32);
   if (L->pos) (void)hipFree(L->pos);
+  for (void* q : {(void*)L->ellw_rows, (void*)L->ellw_loc, (void*)L->ellw_col,
+                  (void*)L->ellw_v32, (void*)L->ellw_off,
+                  (void*)L->ellw_idx})
+    if (q) (void)hipFree(q);
   delete L;
   return CSP_OK;
 }
@@ -421,6 +476,10 @@ extern "C" csp_status csp_lattice_get_info(const csp_lattice* L, csp_lattice_inf
   o->gershgorin = L->gersh;
   o->max_degree = L->g.kind == CSP_SPARSE ? L->ell_D : max_degree(L->g.kind);
   o->has_onsite = L->has_onsite ? 1 : 0;
+  o->ell_windowed = L->ellw_rows ? 1 : 0;
+  int32_t mw = 0;
+  for (int32_t W : L->ellw_sizes) mw = std::max(mw, W);
+  o->ell_max_window = mw;
   return CSP_OK;
 }
 
@@ -553,10 +612,14 @@ ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, 
     const int ct = sparse ? I.ell_ct : 0;
     const int64_t nw = sparse ? I.n_segs * ceil_div(I.Rg, ct) : 0;
     const bool honey = I.kind == CSP_HONEYCOMB, eps = I.eps != nullptr;
+    const bool win = sparse && I.ellw_rows != nullptr;   // set for complex64 only
     if (p.runs.empty() || p.runs.back().honey != honey || p.runs.back().eps != eps ||
-        p.runs.back().sparse != sparse || p.runs.back().ct != ct)
-      p.runs.push_back({(int)k, 0, t0, 0, honey, eps, sparse, ct, w0, 0});
+        p.runs.back().sparse != sparse || p.runs.back().ct != ct || p.runs.back().win != win)
+      p.runs.push_back({(int)k, 0, t0, 0, honey, eps, sparse, ct, w0, 0, win, 0});
     p.runs.back().n_inst += 1;
+    if (win)   // LDS values (window entries x columns) of the run's largest tile
+      p.runs.back().win_cap = std::max<int64_t>(p.runs.back().win_cap,
+                                                I.ellw_lds_cap * std::min(I.ell_ct, I.Rg));
     p.runs.back().n_items += n;
     p.runs.back().n_waves += nw;
     t0 += n;
@@ -593,6 +656,30 @@ ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
     I.ell_val = fp64 ? (const void*)L->ell_v64 : (const void*)L->ell_v32;
     I.ell_D = L->ell_D;
     I.ell_ct = ell_columns_per_wave(fp64, Rg);
+    // complex64 only: for complex128 the slice-layout kernel, whose 16-byte
+    // gathers already fill whole lanes, measured faster (3.96 against 5.63 ms
+    // per step at D_H = 121, 5 columns, on MI355X)
+    if (L->ellw_rows && !fp64) {
+      I.ell_ct = ellw_columns_per_group(fp64, Rg);
+      I.ellw_rows = L->ellw_rows;
+      I.ellw_loc = L->ellw_loc;
+      I.ellw_col = L->ellw_col;
+      I.ellw_val = L->ellw_v32;
+      I.ellw_off = L->ellw_off;
+      I.ellw_idx = L->ellw_idx;
+      // LDS of a workgroup: its tile's columns (at most min(ct, Rg)) of the
+      // largest window within the budget and the 97th percentile of the
+      // window sizes, so that the few slices with far larger windows (they
+      // gather from global memory) do not make every workgroup reserve
+      // their LDS
+      const int64_t ncs = std::min(I.ell_ct, Rg);
+      const int64_t cap = kEllwLdsBytes / (ncs * (int64_t)(fp64 ? 16 : 8));
+      const int64_t p97 = L->ellw_sorted[(L->ellw_sorted.size() * 97) / 100];
+      int64_t best = 0;
+      for (int32_t W : L->ellw_sizes)
+        if (W <= cap && W <= p97 && W > best) best = W;
+      I.ellw_lds_cap = best;
+    }
   }
   return I;
 }
@@ -615,8 +702,11 @@ ChebStep step_args(const ChebPlan& p) {
 // gathers phi_n from one buffer and writes phi_{n+1} to the other.
 csp_status attach_ell_shadows(csp_context* c, std::vector<ChebInst>& sp, bool fp64) {
   size_t need = 0;
+  auto wants = [&](const ChebInst& I) {
+    return !fp64 && I.kind == CSP_SPARSE && I.Rg >= 2 && !I.ellw_rows;
+  };
   for (const ChebInst& I : sp)
-    if (!fp64 && I.kind == CSP_SPARSE && I.Rg >= 2) need += align256((size_t)(I.Rg / 2) * I.N * 32);
+    if (wants(I)) need += align256((size_t)(I.Rg / 2) * I.N * 32);
   if (need > c->ell_sh_size) {
     if (c->ell_sh) {
       HIPCALL(hipStreamSynchronize(c->stream));
@@ -637,7 +727,7 @@ csp_status attach_ell_shadows(csp_context* c, std::vector<ChebInst>& sp, bool fp
   for (ChebInst& I : sp) {
     I.ell_shadow = nullptr;
     I.sh_pairs = 0;
-    if (!fp64 && I.kind == CSP_SPARSE && I.Rg >= 2) {
+    if (wants(I)) {
       I.ell_shadow = static_cast<char*>(c->ell_sh) + off;
       I.sh_pairs = I.Rg / 2;
       off += align256((size_t)(I.Rg / 2) * I.N * 32);

@@ -115,12 +115,23 @@ struct ChebInst {
   const void* ell_val;         // same layout, float or double; padding entries are 0
   int64_t wave0;               // first wave of this instance (explicit-matrix runs)
   int32_t ell_D;               // entries per row
-  int32_t ell_ct;              // columns per wave
+  int32_t ell_ct;              // columns per wave (windowed: per workgroup tile)
   // explicit matrix, complex64: orbital-major copies of phi_n for the gathers,
   // two buffers of sh_pairs column pairs, [2][sh_pairs][N][2] complex values
   // (null: gathers read the column-major vectors)
   void* ell_shadow;
   int64_t sh_pairs;
+  // explicit matrix, windowed layout (null: the slice layout above): slices
+  // of 128 rows compact in the matrix graph, [n_segs][128] rows, entries in
+  // quads [n_segs][ceil(D/4)][128][4] with window-local and global columns,
+  // per-slice windows (the distinct columns a slice names, ascending)
+  const int32_t* ellw_rows;    // row of each lane (-1: none)
+  const uint16_t* ellw_loc;    // window-local column of each entry
+  const int32_t* ellw_col;     // column of each entry (slices not staged)
+  const void* ellw_val;        // value of each entry, float or double
+  const int64_t* ellw_off;     // [n_segs + 1] window offsets into ellw_idx
+  const int32_t* ellw_idx;     // window columns
+  int64_t ellw_lds_cap;        // largest window a workgroup stages (x its columns)
 };
 
 // Per-launch arguments: levels l = 1..nlev produce phi_{n+l} from
@@ -153,8 +164,10 @@ struct ChebRun {
   int inst0, n_inst;
   int64_t item0, n_items;      // work items (stencil); moment records (explicit matrix)
   bool honey, eps, sparse;
-  int ct;                      // explicit matrix: columns per wave
-  int64_t wave0, n_waves;      // explicit matrix: waves of the run
+  int ct;                      // explicit matrix: columns per wave (workgroup if windowed)
+  int64_t wave0, n_waves;      // explicit matrix: waves (workgroups if windowed) of the run
+  bool win;                    // explicit matrix in the windowed layout
+  int64_t win_cap;             // windowed: LDS complex values of the run's largest tile
 };
 // mom: moment epilogue; carry: also the carried state (moment epilogue only)
 hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const ChebInst* d_inst,
@@ -166,6 +179,30 @@ hipError_t launch_cheb_ell(bool fp64, bool mom, bool carry, int ct, const ChebIn
                            hipStream_t s);
 // columns per wave of the explicit-matrix kernel for a group of Rg columns
 int ell_columns_per_wave(bool fp64, int Rg);
+// Windowed layout: one workgroup of 128 threads per (slice, tile of ct
+// columns) stages the slice's window of phi_n in LDS (wg_lo .. wg_hi - 1
+// over the run's instances, I.wave0 = first workgroup of an instance).
+hipError_t launch_cheb_ellw(bool fp64, bool mom, bool carry, int ct, int64_t lds_values,
+                            const ChebInst* d_inst, int n_inst, int64_t wg_lo, int64_t wg_hi,
+                            const ChebStep& st, hipStream_t s);
+// columns per workgroup of the windowed kernel for a group of Rg columns
+int ellw_columns_per_group(bool fp64, int Rg);
+// LDS bytes a windowed workgroup may stage
+constexpr int64_t kEllwLdsBytes = 64 * 1024;
+
+// Host side of the windowed layout (built at lattice creation).
+struct EllWindows {
+  int64_t n_slices = 0;
+  int64_t max_window = 0;
+  int D4 = 0;                    // quads of entries per row
+  std::vector<int32_t> rows;     // [n_slices][128]
+  std::vector<int64_t> off;      // [n_slices + 1]
+  std::vector<int32_t> idx;      // windows, ascending per slice
+  std::vector<uint16_t> loc;     // [n_slices][D4][128][4]
+  std::vector<int32_t> col;      // [n_slices][D4][128][4]
+  std::vector<float> v32;        // [n_slices][D4][128][4]
+};
+bool build_ell_windows(int64_t N, int D, const int32_t* col, const double* val, EllWindows* w);
 // max_s sum_k |val_sk| (k in order, FP64): one maximum per block into partial
 hipError_t launch_ell_gershgorin(int64_t N, int D, const double* d_val, double* d_partial,
                                  int n_partial, hipStream_t s);

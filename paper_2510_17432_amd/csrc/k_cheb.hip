@@ -39,7 +39,10 @@ hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const C
     const ChebInst* di = d_inst + r.inst0;
     const int64_t lo = r.item0, hi = r.item0 + r.n_items;
     hipError_t e;
-    if (r.sparse)
+    if (r.sparse && r.win)
+      e = launch_cheb_ellw(fp64, mom, carry, r.ct, r.win_cap, di, r.n_inst, r.wave0,
+                           r.wave0 + r.n_waves, st, s);
+    else if (r.sparse)
       e = launch_cheb_ell(fp64, mom, carry, r.ct, di, r.n_inst, r.wave0, r.wave0 + r.n_waves, st,
                           s);
     else if (fp64)

@@ -32,14 +32,14 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(csp.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert csp.abi_version() == 2
+    assert csp.abi_version() == 3
 
 
 def test_struct_layouts():
     import paper_2510_17432_amd as csp
     # sizes implied by include/csp.h with natural alignment
     assert ctypes.sizeof(csp.LatticeDesc) == 16 + 16 + 16 + 8 + 24
-    assert ctypes.sizeof(csp.LatticeInfo) == 24 + 24 + 8
+    assert ctypes.sizeof(csp.LatticeInfo) == 24 + 24 + 8 + 8
     assert ctypes.sizeof(csp.Params) == 8 + 16 + 16 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(csp.Report) == 16 + 40 + 48 + 8 + 64 + 16
     assert ctypes.sizeof(csp.Tuning) == 16 + 8 + 16 + 64 + 8

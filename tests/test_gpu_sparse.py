@@ -7,6 +7,10 @@ times the margin).  FP64 paths: 1e-10 on correlations and quasi-eigenstates
 2e-5 absolute and DOS within 1e-4 relative, as for the stencil lattices.
 Matrices: the long-range square lattice (every row D = 29 or 49 entries,
 no padding) and random symmetric matrices with irregular rows (padding).
+All but the largest random matrix run the LDS-staged (windowed) recursion;
+that one, the stencil written out in ELL form, and the slices of the
+overflow matrix whose windows exceed the LDS budget gather from global
+memory.
 """
 import math
 
@@ -49,6 +53,7 @@ MATS = {
     "lr4": lambda: ci.long_range_square(19, 4.0, t0=1.0, decay=1.0, W=0.5, seed=5),
     "rand": lambda: ci.random_symmetric_ell(700, 2500, seed=3),
     "rand_nodiag": lambda: ci.random_symmetric_ell(301, 400, seed=4, diag=False),
+    "rand_big": lambda: ci.random_symmetric_ell(6000, 20000, seed=9),
 }
 
 
@@ -74,6 +79,42 @@ def test_halfwidth_bit_exact_and_info(csp, ctx, name, margin):
         with pytest.raises(csp.CspError) as e:
             f()
         assert e.value.status == csp.CSP_EUNSUPPORTED
+
+
+def test_windowed_layout_in_use(csp, ctx):
+    # lattices whose slices of 128 neighbouring rows name few columns, and
+    # matrices small enough that a slice's window is most of the vector, run
+    # the LDS-staged recursion; a large random matrix (every slice names
+    # about as many columns as it has entries) keeps the slice layout
+    for name, want in (("lr3", 1), ("lr4", 1), ("rand", 1), ("rand_nodiag", 1),
+                       ("rand_big", 0)):
+        g, c = pair(csp, ctx, name)
+        assert g.info.ell_windowed == want, name
+        if want:
+            assert 0 < g.info.ell_max_window <= c.N
+
+
+@pytest.mark.parametrize("mode,b,R", [("fp32_conc", 16, 5), ("fp64_conc", 8, 3),
+                                      ("fp32_conc", 0, 2), ("fp64_seq", 0, 1)])
+def test_windows_that_overflow_the_lds(csp, ctx, mode, b, R):
+    # most slices stage their window, the slices holding the rows with far
+    # entries (windows above the LDS budget of 8 or 4 columns) gather from
+    # global memory, in the same launch
+    print("[gpu] sparse windows overflow %s b=%d R=%d" % (mode, b, R), flush=True)
+    col, val = ci.long_range_with_far_pairs()
+    g = csp.Lattice.sparse(ctx, col, val)
+    c = o.SparseLattice(col, val)
+    assert g.info.ell_windowed == 1 and g.info.ell_max_window > 2048
+    psi = o.random_phase_states_fast(c.N, R, 17)
+    Nt = 60
+    ref, _ = o.propagate(c, psi, Nt, b=0, Hn=g.halfwidth)
+    got, _, _ = run(csp, ctx, g, psi, Nt, mode, b=b)
+    tol = 2e-5 if mode == "fp32_conc" else 1e-10
+    assert np.max(np.abs(got - ref)) < tol
+    if mode != "fp64_seq":
+        mref, _ = o.propagate_moments(c, psi, Nt, b=None, halving=True, Hn=g.halfwidth)
+        mgot, _, _ = run(csp, ctx, g, psi, Nt, mode, assembly=csp.CSP_ASSEMBLE_MOMENTS)
+        assert np.max(np.abs(mgot - mref)) < tol
 
 
 def test_creation_errors(csp, ctx):
@@ -119,7 +160,7 @@ def run(csp, ctx, g, psi, Nt, mode, b=0, assembly=None, final=False):
     return host(corr), rep, (host(fin) if final else None)
 
 
-@pytest.mark.parametrize("name", ["lr3", "rand", "rand_nodiag"])
+@pytest.mark.parametrize("name", ["lr3", "rand", "rand_nodiag", "rand_big"])
 @pytest.mark.parametrize("mode,b", [("fp64_seq", 0), ("fp64_conc", 13), ("fp32_conc", 32),
                                     ("fp32_conc", 7)])
 def test_state_assembly_matches_oracle(csp, ctx, name, mode, b):
@@ -158,9 +199,10 @@ def test_matrix_smaller_than_one_slice(csp, ctx, mode):
 @pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
 def test_odd_column_counts(csp, ctx, mode):
     # column groups of an explicit matrix: 3 (waves of 2 + 1), 7 (waves of
-    # 4 + 3) and 33 (groups of 32 and 1)
+    # 4 + 3), 10 and 17 (windowed tiles of 5 + 5 and 6 + 6 + 5) and 33
+    # (groups of 32 and 1)
     g, c = pair(csp, ctx, "rand")
-    for R, seed in ((3, 31), (7, 32), (33, 33)):
+    for R, seed in ((3, 31), (7, 32), (10, 34), (17, 35), (33, 33)):
         print("[gpu] sparse %s R=%d" % (mode, R), flush=True)
         psi = o.random_phase_states_fast(c.N, R, seed)
         ref, _ = o.propagate(c, psi, 50, b=0, Hn=g.halfwidth)
