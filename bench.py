@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-tta", action="store_true",
                     help="skip the time-to-accuracy legs on the 1e9-orbital lattice")
     ap.add_argument("--no-graphene", action="store_true", help="skip the graphene legs")
+    ap.add_argument("--no-graphene-tta", action="store_true",
+                    help="graphene legs without their DOS time-to-accuracy comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the CPU oracle sample")
@@ -84,11 +86,13 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 2 GiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
-    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "KERNEL",
-                                                         "OUT_JSON"),
-                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files "
-                         "(FETCH_SIZE, WRITE_SIZE) of a --copy-probe run into the scaled "
-                         "per-launch HBM bytes of the kernels whose name contains KERNEL")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
+                    help="no GPU work: KERNEL OUT_JSON CSV [CSV ...]; turn rocprofv3 --pmc "
+                         "counter_collection.csv files of a --copy-probe run (FETCH_SIZE, "
+                         "WRITE_SIZE, SQ_INSTS_VALU_MFMA_MOPS_BF16, ...) into per-launch "
+                         "figures of the kernels whose name contains KERNEL")
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="with --summarize-pmc: a command that produced the files (recorded)")
     ap.add_argument("--dense-dh", action="store_true",
                     help="instead of the step benchmark: the DOS (Nt = 4096) of explicit "
                          "matrices of density D_H = 61, 121, 233 (4.76 M orbitals, 10 / 5 / 2 "
@@ -101,6 +105,14 @@ def parse():
                          "correlation (EC-Concurrent-M, 49 energies, Nt = 1024, 5 random "
                          "columns) on the D_H = 121 explicit matrix, complex64 and complex128, "
                          "against the recursion cost of the complex128 sequential form")
+    ap.add_argument("--ec-kernels-only", action="store_true",
+                    help="with --ec: only the quasi-eigenstates and the two EC-Concurrent-M "
+                         "calls (no sequential estimate, no QE configuration legs)")
+    ap.add_argument("--ell-steps", action="store_true",
+                    help="instead of the step benchmark: the explicit-matrix recursion alone, "
+                         "64 Chebyshev steps of the state form (b = 16) and of the moment "
+                         "form, complex64, on the D_H = 61 / 121 / 233 matrices with 10 / 5 / 2 "
+                         "random columns (--dh selects densities)")
     return ap.parse_args()
 
 
@@ -134,34 +146,62 @@ def _profile(name, sources):
         return None
 
 
-def summarize_pmc(fetch_csv, write_csv, kernel, out_json):
-    """Per-launch HBM bytes of the kernels named `kernel` from two
-    rocprofv3 --pmc runs of the same command, each counter scaled by what it
-    read for the 2 GiB device copy the command starts with."""
+def summarize_pmc(kernel, out_json, csvs, commands):
+    """Per-launch counter figures of the kernels whose name contains
+    `kernel`, from rocprofv3 --pmc runs of a command that starts with the
+    2 GiB device copy (--copy-probe).  FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) are each scaled by (known bytes of that copy) / (what the
+    same counter read for the copy dispatch).  SQ_INSTS_VALU_MFMA_MOPS_BF16
+    counts 512 multiply-adds per unit (one v_mfma_f32_32x32x16_bf16 is 32
+    units); the issued MFMA rate is taken over the dispatch's own duration in
+    the counter run.  The summary records the SHA-256 of the kernel's
+    sources, so that a changed kernel voids it."""
     import csv
-
-    def rows(path, counter):
-        out = []
+    vals, copy, dur, names = {}, {}, [], set()
+    for path in csvs:
         with open(path) as f:
             for r in csv.DictReader(f):
-                if r.get("Counter_Name") == counter:
-                    out.append((r["Kernel_Name"], float(r["Counter_Value"])))
-        return out
-
-    res = {}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        rr = rows(path, counter)
-        copy = [v for k, v in rr if "copyBuffer" in k or "copy" in k.lower()]
-        mine = [v for k, v in rr if kernel in k]
-        if not copy or not mine:
-            raise SystemExit("no copy dispatch or no %s dispatch for %s" % (kernel, counter))
-        probe_kib = max(copy)
-        scale = (COPY_PROBE_BYTES / 1024.0) / probe_kib
-        res[counter] = {"dispatches": len(mine), "kib_per_dispatch": sum(mine) / len(mine),
-                        "copy_probe_kib": probe_kib, "scale": scale,
-                        "bytes_per_dispatch": sum(mine) / len(mine) * 1024.0 * scale}
-    res["hbm_bytes_per_launch"] = (res["FETCH_SIZE"]["bytes_per_dispatch"] +
-                                   res["WRITE_SIZE"]["bytes_per_dispatch"])
+                c, k, v = r["Counter_Name"], r["Kernel_Name"], float(r["Counter_Value"])
+                if "copyBuffer" in k:
+                    copy.setdefault(c, []).append((int(r["Dispatch_Id"]), v))
+                elif kernel in k:
+                    names.add(k)
+                    vals.setdefault(c, []).append(v)
+                    if c == "FETCH_SIZE" or not dur:
+                        dur.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    if not vals:
+        raise SystemExit("no dispatch of %s in %s" % (kernel, csvs))
+    mean = lambda x: sum(x) / len(x)  # noqa: E731
+    res = {"kernel": sorted(names), "counter_files": [os.path.basename(p) for p in csvs]}
+    if "k_cheb" in kernel:
+        res["source_files"] = ["paper_2510_17432_amd/csrc/" + n for n in CHEB_SOURCES]
+        res["source_sha256"] = _sources_sha256(CHEB_SOURCES)
+    elif "k_contract" in kernel:
+        res["source_files"] = ["paper_2510_17432_amd/csrc/" + n for n in CONTRACT_SOURCES]
+        res["source_sha256"] = _sources_sha256(CONTRACT_SOURCES)
+    for c, v in sorted(vals.items()):
+        res[c] = {"dispatches": len(v), "mean_per_dispatch": mean(v)}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        if c in vals:
+            if c not in copy:
+                raise SystemExit("no copy dispatch for %s" % c)
+            probe = min(copy[c])[1]            # the first copy of the run
+            scale = (COPY_PROBE_BYTES / 1024.0) / probe
+            res[c].update({"unit": "KiB", "copy_probe_kib": probe, "scale": scale,
+                           "bytes_per_dispatch": mean(vals[c]) * 1024.0 * scale})
+    if "FETCH_SIZE" in vals and "WRITE_SIZE" in vals:
+        res["hbm_read_bytes_per_launch"] = res["FETCH_SIZE"]["bytes_per_dispatch"]
+        res["hbm_write_bytes_per_launch"] = res["WRITE_SIZE"]["bytes_per_dispatch"]
+        res["hbm_bytes_per_launch"] = (res["hbm_read_bytes_per_launch"] +
+                                       res["hbm_write_bytes_per_launch"])
+    if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in vals:
+        flops = mean(vals["SQ_INSTS_VALU_MFMA_MOPS_BF16"]) * 512 * 2
+        t = mean(dur)
+        res["mfma_issued_flops_per_launch"] = flops
+        res["counter_run_launch_s"] = t
+        res["mfma_issued_TFLOPs"] = flops / t / 1e12
+        res["mfma_busy_frac"] = flops / t / 1e12 / BF16_PEAK_TFLOPS
+    res["commands"] = ["cd /tmp && export TMPDIR=/tmp"] + list(commands)
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
@@ -285,9 +325,14 @@ def c5_legs(a, out):
            "achieved_GBs": con_bytes / max(con_s, 1e-12) / 1e9,
            "issued_mfma_TFLOPs": con_flops / max(con_s, 1e-12) / 1e12,
            "share_of_step": con_s / a.steps / s_step}
+    # useful work of Eq. TE: one complex multiply-add (8 real flops) per
+    # orbital, column, Chebyshev order and time point of the block
+    useful = 8.0 * N * R * (steps_exec + 1) * (b + 1) * a.steps
+    con["useful_over_issued_flops"] = useful / max(con_flops, 1.0)
+    con["useful_TFLOPs"] = useful / max(con_s, 1e-12) / 1e12
     if con_prof:
-        con.update({k: con_prof[k] for k in ("mfma_busy_frac", "useful_over_issued_flops",
-                                             "useful_mfma_TFLOPs", "hbm_bytes_per_launch")
+        con.update({k: con_prof[k] for k in ("mfma_busy_frac", "mfma_issued_TFLOPs",
+                                             "hbm_bytes_per_launch")
                     if k in con_prof})
     out["contraction"] = con
     log("C5 step: %.3f s, %.3e orbital*steps/s, recursion %.1f us/launch (%.0f GB/s), "
@@ -416,6 +461,12 @@ def graphene_leg(a, out):
         log("graphene %s: %.3f s, recursion %.0f GB/s" % (name, el,
                                                           res[name]["recursion_alg_GBs"]))
     ctx.trim()
+    if a.no_graphene_tta:
+        out["graphene"] = res
+        del psi
+        lat.close()
+        ctx.close()
+        return
     p4 = psi[:, :Rr].contiguous()
     p64 = p4.to(torch.complex128)
     del psi
@@ -494,6 +545,67 @@ def batch_leg(a, out):
     torch.cuda.empty_cache()
 
 
+def _copy_probe():
+    """A device-to-device copy of COPY_PROBE_BYTES (read once, written once):
+    the kernel of known traffic that scales the hardware byte counters."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: %d bytes read, %d written" % (COPY_PROBE_BYTES, COPY_PROBE_BYTES))
+    del src, dst
+
+
+def ell_steps(a):
+    """The explicit-matrix Chebyshev step alone (Sec. II.B, matrix density
+    D_H): 64 steps of the state form (b = 16) and of the moment form with
+    halving, complex64, on the long-range matrices of D_H = 61 / 121 / 233
+    with 10 / 5 / 2 random columns; each timed on a second call with HIP
+    events around every recursion launch."""
+    import torch
+    import paper_2510_17432_amd as csp
+    w = csp_inputs.LONG_RANGE2182
+    ctx = csp.Context(0)
+    if a.copy_probe:
+        _copy_probe()
+    out = {"workload": "long-range square lattice %dx%d (N=%d), complex64, 64 steps"
+                       % (w["L"], w["L"], w["L"] ** 2), "cases": []}
+    for case in w["cases"]:
+        if a.dh and case["D"] not in a.dh:
+            continue
+        col, val = csp_inputs.long_range_square(w["L"], case["r_cut"], w["t0"], w["decay"],
+                                                w["W"], w["seed"])
+        lat = csp.Lattice.sparse(ctx, col, val)
+        D = col.shape[1]
+        del col, val
+        R = case["R"]
+        psi = torch.empty((lat.N, R), dtype=torch.complex64, device="cuda:0")
+        csp.csp_states_random_phase(ctx, psi, R, w["seed_states"])
+        res = {"D_H": D, "columns": R, "windowed": lat.info.ell_windowed,
+               "max_window": lat.info.ell_max_window}
+        for name, asm, b in (("states_b16", csp.CSP_ASSEMBLE_STATES, 16),
+                             ("moments", csp.CSP_ASSEMBLE_MOMENTS, 0)):
+            prm = csp.make_params(64, mode="fp32_conc", assembly=asm, block_b=b, profile=True)
+            csp.csp_propagate(ctx, lat, psi, prm)
+            torch.cuda.synchronize()
+            _, rep = csp.csp_propagate(ctx, lat, psi, prm)
+            torch.cuda.synchronize()
+            us = 1000.0 * rep.ms_spmm / rep.spmm_launches
+            gbs = rep.spmm_bytes / rep.ms_spmm / 1e6
+            res[name] = {"us_per_step": us, "alg_bytes_per_step": rep.spmm_bytes /
+                         rep.spmm_launches, "alg_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            log("D_H=%d R=%d %s: %.1f us per step, %.0f GB/s algorithmic" % (D, R, name, us, gbs))
+        out["cases"].append(res)
+        del psi
+        lat.close()
+        ctx.trim()
+        torch.cuda.empty_cache()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def dense_dh(a):
     """DOS of explicit Hamiltonians of matrix density D_H = 61, 121, 233
     (Sec. III: the speedup of the concurrent method grows with D_H; the
@@ -515,11 +627,7 @@ def dense_dh(a):
                                                         w["decay"], w["W"], w["seed"], Nt),
            "cases": []}
     if a.copy_probe:
-        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        _copy_probe()
     for case in w["cases"]:
         if a.dh and case["D"] not in a.dh:
             continue
@@ -607,6 +715,8 @@ def ec_bench(a):
     Nt, nE, R = 1024, 49, case["R"]
     ctx = csp.Context(0)
     dev = "cuda:0"
+    if a.copy_probe:
+        _copy_probe()
     t0 = time.perf_counter()
     col, val = csp_inputs.long_range_square(w["L"], case["r_cut"], w["t0"], w["decay"], w["W"],
                                             w["seed"])
@@ -655,6 +765,10 @@ def ec_bench(a):
     del c64, s64, qe64
     ctx.trim()
     torch.cuda.empty_cache()
+    if a.ec_kernels_only:
+        lat.close()
+        ctx.close()
+        return
     # complex128 sequential recursion cost (cost independent of the vector)
     s1, s2 = a.seq_steps, 3 * a.seq_steps
     tt = []
@@ -730,7 +844,10 @@ def main():
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     if a.summarize_pmc:
-        summarize_pmc(*a.summarize_pmc)
+        if len(a.summarize_pmc) < 3:
+            raise SystemExit("--summarize-pmc KERNEL OUT_JSON CSV [CSV ...]")
+        summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.summarize_pmc[2:],
+                      a.pmc_command)
         return
     if a.dense_dh:
         dense_dh(a)
@@ -738,16 +855,13 @@ def main():
     if a.ec:
         ec_bench(a)
         return
+    if a.ell_steps:
+        ell_steps(a)
+        return
     import torch
     torch.cuda.set_device(0)
     if a.copy_probe:
-        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: %d bytes read, %d written" % (COPY_PROBE_BYTES, COPY_PROBE_BYTES))
-        del src, dst
+        _copy_probe()
     out = {
         "metric": "orbital·Chebyshev-steps/s + DOS time-to-accuracy, FP32 concurrent vs FP64 seq",
         "value": None,
