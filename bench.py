@@ -93,6 +93,13 @@ def parse():
                          "figures of the kernels whose name contains KERNEL")
     ap.add_argument("--pmc-command", action="append", default=[],
                     help="with --summarize-pmc: a command that produced the files (recorded)")
+    ap.add_argument("--pmc-grid", type=int, default=None,
+                    help="with --summarize-pmc: only the dispatches of this grid size")
+    ap.add_argument("--pmc-note", default=None,
+                    help="with --summarize-pmc: what the dispatches are (recorded)")
+    ap.add_argument("--pmc-alg-bytes", type=float, default=None,
+                    help="with --summarize-pmc: algorithmic bytes per launch, recorded with the "
+                         "ratio of the counted HBM bytes to them")
     ap.add_argument("--dense-dh", action="store_true",
                     help="instead of the step benchmark: the DOS (Nt = 4096) of explicit "
                          "matrices of density D_H = 61, 121, 233 (4.76 M orbitals, 10 / 5 / 2 "
@@ -146,15 +153,16 @@ def _profile(name, sources):
         return None
 
 
-def summarize_pmc(kernel, out_json, csvs, commands):
+def summarize_pmc(kernel, out_json, csvs, commands, grid=None, note=None, alg_bytes=None):
     """Per-launch counter figures of the kernels whose name contains
     `kernel`, from rocprofv3 --pmc runs of a command that starts with the
     2 GiB device copy (--copy-probe).  FETCH_SIZE and WRITE_SIZE (KiB per
     dispatch) are each scaled by (known bytes of that copy) / (what the
     same counter read for the copy dispatch).  SQ_INSTS_VALU_MFMA_MOPS_BF16
-    counts 512 multiply-adds per unit (one v_mfma_f32_32x32x16_bf16 is 32
-    units); the issued MFMA rate is taken over the dispatch's own duration in
-    the counter run.  The summary records the SHA-256 of the kernel's
+    (units of 512 flops: one v_mfma_f32_32x32x16_bf16 counts 64) gives the
+    issued MFMA rate over the dispatch's own duration in the counter run, and
+    SQ_VALU_MFMA_BUSY_CYCLES (summed over the SIMDs) the busy share of the
+    matrix units.  The summary records the SHA-256 of the kernel's
     sources, so that a changed kernel voids it."""
     import csv
     vals, copy, dur, names = {}, {}, [], set()
@@ -164,15 +172,16 @@ def summarize_pmc(kernel, out_json, csvs, commands):
                 c, k, v = r["Counter_Name"], r["Kernel_Name"], float(r["Counter_Value"])
                 if "copyBuffer" in k:
                     copy.setdefault(c, []).append((int(r["Dispatch_Id"]), v))
-                elif kernel in k:
+                elif kernel in k and (grid is None or int(r["Grid_Size"]) == grid):
                     names.add(k)
                     vals.setdefault(c, []).append(v)
-                    if c == "FETCH_SIZE" or not dur:
+                    if c == "SQ_INSTS_VALU_MFMA_MOPS_BF16":
                         dur.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
     if not vals:
         raise SystemExit("no dispatch of %s in %s" % (kernel, csvs))
     mean = lambda x: sum(x) / len(x)  # noqa: E731
-    res = {"kernel": sorted(names), "counter_files": [os.path.basename(p) for p in csvs]}
+    res = {"kernel": sorted(names), "grid_size": grid, "note": note,
+           "counter_files": [os.path.relpath(p, ROOT) for p in csvs]}
     if "k_cheb" in kernel:
         res["source_files"] = ["paper_2510_17432_amd/csrc/" + n for n in CHEB_SOURCES]
         res["source_sha256"] = _sources_sha256(CHEB_SOURCES)
@@ -194,13 +203,21 @@ def summarize_pmc(kernel, out_json, csvs, commands):
         res["hbm_write_bytes_per_launch"] = res["WRITE_SIZE"]["bytes_per_dispatch"]
         res["hbm_bytes_per_launch"] = (res["hbm_read_bytes_per_launch"] +
                                        res["hbm_write_bytes_per_launch"])
+    if alg_bytes:
+        res["algorithmic_bytes_per_launch"] = alg_bytes
+        if "hbm_bytes_per_launch" in res:
+            res["ratio_hbm_to_algorithmic"] = res["hbm_bytes_per_launch"] / alg_bytes
     if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in vals:
-        flops = mean(vals["SQ_INSTS_VALU_MFMA_MOPS_BF16"]) * 512 * 2
+        flops = mean(vals["SQ_INSTS_VALU_MFMA_MOPS_BF16"]) * 512
         t = mean(dur)
         res["mfma_issued_flops_per_launch"] = flops
         res["counter_run_launch_s"] = t
         res["mfma_issued_TFLOPs"] = flops / t / 1e12
-        res["mfma_busy_frac"] = flops / t / 1e12 / BF16_PEAK_TFLOPS
+        res["mfma_issued_frac"] = flops / t / 1e12 / BF16_PEAK_TFLOPS
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in vals:
+            # summed over the 1024 SIMDs; 2.4 GHz
+            res["mfma_busy_frac"] = (mean(vals["SQ_VALU_MFMA_BUSY_CYCLES"]) /
+                                     (N_CU * 4 * t * 2.4e9))
     res["commands"] = ["cd /tmp && export TMPDIR=/tmp"] + list(commands)
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
@@ -326,13 +343,13 @@ def c5_legs(a, out):
            "issued_mfma_TFLOPs": con_flops / max(con_s, 1e-12) / 1e12,
            "share_of_step": con_s / a.steps / s_step}
     # useful work of Eq. TE: one complex multiply-add (8 real flops) per
-    # orbital, column, Chebyshev order and time point of the block
-    useful = 8.0 * N * R * (steps_exec + 1) * (b + 1) * a.steps
+    # orbital, column, Chebyshev order and time point t_1 .. t_b of the block
+    useful = 8.0 * N * R * (steps_exec + 1) * b * a.steps
     con["useful_over_issued_flops"] = useful / max(con_flops, 1.0)
     con["useful_TFLOPs"] = useful / max(con_s, 1e-12) / 1e12
     if con_prof:
-        con.update({k: con_prof[k] for k in ("mfma_busy_frac", "mfma_issued_TFLOPs",
-                                             "hbm_bytes_per_launch")
+        con.update({k: con_prof[k] for k in ("mfma_busy_frac", "mfma_issued_frac",
+                                             "mfma_issued_TFLOPs", "hbm_bytes_per_launch")
                     if k in con_prof})
     out["contraction"] = con
     log("C5 step: %.3f s, %.3e orbital*steps/s, recursion %.1f us/launch (%.0f GB/s), "
@@ -847,7 +864,7 @@ def main():
         if len(a.summarize_pmc) < 3:
             raise SystemExit("--summarize-pmc KERNEL OUT_JSON CSV [CSV ...]")
         summarize_pmc(a.summarize_pmc[0], a.summarize_pmc[1], a.summarize_pmc[2:],
-                      a.pmc_command)
+                      a.pmc_command, a.pmc_grid, a.pmc_note, a.pmc_alg_bytes)
         return
     if a.dense_dh:
         dense_dh(a)
