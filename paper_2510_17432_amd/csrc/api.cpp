@@ -18,6 +18,12 @@
 
 using namespace csp;
 
+int csp::ring_parts(int S) {
+  for (int g : {3, 4, 2})
+    if (S >= g && S % g == 0) return g;
+  return 1;
+}
+
 // ------------------------------------------------------------------ errors
 namespace {
 thread_local std::string g_err;
@@ -1181,6 +1187,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     while (K > 16 && ws_need(K, wg_bound) > cap) K -= 16;
   }
   const int S = ring_slots(K);
+  const int RG = ring_parts(S);    // ring parts (slot of position k: ring_slot)
   if (ws_need(K, wg_bound) > cap)
     return fail(CSP_ENOMEM, "workspace for b=%d, K=%d exceeds the cap (%.2f GB)", b, K, cap / 1e9);
 
@@ -1317,6 +1324,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   ContractArgs ca{};
   ca.n_inst = (int)groups.size();
   ca.S = S;
+  ca.G = RG;
   ca.jtiles = jtiles;
   ca.total_wg = total_wg;
   const ChebStep st0 = step_args(sp_plan);
@@ -1364,10 +1372,11 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
         stb.slot_cur = -1;
         stb.copy_slot = 0;
       } else {
-        stb.slot_cur = produced % S;
-        stb.slot_prev = (produced - 1) % S;
+        stb.slot_cur = ring_slot(produced % S, S, RG);
+        stb.slot_prev = ring_slot((produced - 1) % S, S, RG);
       }
-      for (int l = 1; l <= stb.nlev; ++l) stb.slot_out[l - 1] = (produced + l) % S;
+      for (int l = 1; l <= stb.nlev; ++l)
+        stb.slot_out[l - 1] = ring_slot((produced + l) % S, S, RG);
       size_t ev = 0;
       if (!from_dev) CHECK(prof.begin(0, &ev));
       set_shadow(stb, produced);
@@ -1900,6 +1909,7 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
     return fail(CSP_ENOMEM, "quasi-eigenstate workspace %.2f GB exceeds the cap %.2f GB",
                 ws_need(K) / 1e9, cap / 1e9);
   const int S = K + kt;
+  const int RG = ring_parts(S);    // ring parts (slot of position k: ring_slot)
   CHECK(ws_reserve(c, ws_need(K)));
   Carver cv(c->ws);
   std::vector<void*> carry(sp.size()), acc(sp.size()), slots(sp.size());
@@ -1971,10 +1981,11 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
           st.slot_cur = -1;
           st.copy_slot = 0;
         } else {
-          st.slot_cur = produced % S;
-          st.slot_prev = (produced - 1) % S;
+          st.slot_cur = ring_slot(produced % S, S, RG);
+          st.slot_prev = ring_slot((produced - 1) % S, S, RG);
         }
-        for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
+        for (int l = 1; l <= st.nlev; ++l)
+          st.slot_out[l - 1] = ring_slot((produced + l) % S, S, RG);
         size_t ev = 0;
         CHECK(prof.begin(0, &ev));
         set_shadow(st, produced);
@@ -1992,6 +2003,7 @@ csp_status qe_state_based(csp_context* c, const csp_lattice* L, const void* dev_
         qa.n_lo = n_lo;
         qa.n_cnt = n_cnt;
         qa.S = S;
+        qa.G = RG;
         qa.first_chunk = (k == 0 && n_lo == 0) ? 1 : 0;
         qa.nE = nE;
         qa.total_wg = wg0;
@@ -2154,6 +2166,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
     return fail(CSP_ENOMEM, "quasi-eigenstate workspace %.2f GB exceeds the cap %.2f GB",
                 ws_need(K) / 1e9, cap / 1e9);
   const int S = K + kt;
+  const int RG = ring_parts(S);    // ring parts (slot of position k: ring_slot)
   CHECK(ws_reserve(c, ws_need(K)));
   Carver cv(c->ws);
   std::vector<void*> outs(groups.size());
@@ -2220,10 +2233,11 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
       st.slot_cur = -1;
       st.copy_slot = 0;
     } else {
-      st.slot_cur = produced % S;
-      st.slot_prev = (produced - 1) % S;
+      st.slot_cur = ring_slot(produced % S, S, RG);
+      st.slot_prev = ring_slot((produced - 1) % S, S, RG);
     }
-    for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
+    for (int l = 1; l <= st.nlev; ++l)
+      st.slot_out[l - 1] = ring_slot((produced + l) % S, S, RG);
     size_t ev = 0;
     CHECK(prof.begin(0, &ev));
     set_shadow(st, produced);
@@ -2249,6 +2263,7 @@ extern "C" csp_status csp_quasi_eigenstates(csp_context* c, const csp_lattice* L
       qa.n_lo = n_lo;
       qa.n_cnt = n_cnt;
       qa.S = S;
+      qa.G = RG;
       qa.first_chunk = n_lo == 0 ? 1 : 0;
       qa.nE = nE;
       qa.total_wg = wg0;
@@ -2406,6 +2421,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
     return fail(CSP_ENOMEM, "conductivity workspace %.2f GB exceeds the cap %.2f GB",
                 ws_need(K) / 1e9, cap / 1e9);
   const int S = K + kt;
+  const int RG = ring_parts(S);    // ring parts (slot of position k: ring_slot)
   CHECK(ws_reserve(c, ws_need(K)));
   Carver cv(c->ws);
   std::vector<void*> jpsi(groups.size()), qeg(groups.size()), bra(groups.size()),
@@ -2476,10 +2492,11 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
         st.slot_cur = -1;
         st.copy_slot = 0;
       } else {
-        st.slot_cur = produced % S;
-        st.slot_prev = (produced - 1) % S;
+        st.slot_cur = ring_slot(produced % S, S, RG);
+        st.slot_prev = ring_slot((produced - 1) % S, S, RG);
       }
-      for (int l = 1; l <= st.nlev; ++l) st.slot_out[l - 1] = (produced + l) % S;
+      for (int l = 1; l <= st.nlev; ++l)
+        st.slot_out[l - 1] = ring_slot((produced + l) % S, S, RG);
       size_t ev = 0;
       CHECK(prof.begin(0, &ev));
       set_shadow(st, produced);
@@ -2494,6 +2511,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
       ea.n_lo = n_lo;
       ea.n_cnt = std::min(K, Nmax + 1 - n_lo);
       ea.S = S;
+      ea.G = RG;
       ea.nE = nE;
       ea.K = K;
       ea.total_wg = wg0;
@@ -2863,6 +2881,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
       ca.n_lo = 0;
       ca.n_cnt = K;
       ca.S = K_t;
+      ca.G = ring_parts(K_t);
       ca.first_chunk = 0;
       ca.jtiles = jt;
       ca.bcols = fp64 ? kMaxFp64B : 32 * jt;

@@ -253,6 +253,19 @@ hipError_t launch_current_ell(bool fp64, int64_t N, int D, const int32_t* ell_co
 // nrm[q0 + c nE + e] = |<psi[c]|qe[e][c]>| for a group (psi [Rg][N], qe [nE][Rg][N])
 hipError_t launch_ec_norm(bool fp64, int64_t N, int Rg, int nE, const void* psi, const void* qe,
                           double* nrm, int q0, hipStream_t s);
+// Ring of S Chebyshev slots split into G parts of S / G slots: ring
+// position k (order n sits at k = n mod S) is stored in slot
+// (k mod G) S / G + k / G, so the consecutive orders that one recursion
+// launch writes and one contraction chunk reads lie in all G parts of the
+// ring's address range instead of one (measured faster on MI355X for rings
+// of tens of GB).  The next position's slot is S / G further, less S - 1
+// when that passes the end.
+__host__ __device__ inline int ring_slot(int k, int S, int G) {
+  return (k % G) * (S / G) + k / G;
+}
+// G for a ring of S slots: 3, 4 or 2 when it divides S, else 1 (in order).
+int ring_parts(int S);
+
 // Moments of one chunk of orders against the bras of a group (EC-Concurrent-M).
 struct EcInst {
   const void* slots;        // ring [S][Rg][N]
@@ -267,6 +280,7 @@ struct EcInst {
 };
 struct EcArgs {
   int32_t n_inst, n_lo, n_cnt, S;
+  int32_t G;                // ring parts: position k in slot ring_slot(k, S, G)
   int32_t nE, K, total_wg;
   int32_t ldp;              // energies per partial row: n_etiles x tile (32 FP32, 16 FP64)
   double* mu;               // [Nmax + 1][ldmu] complex, column q = (col0 + c) nE + e
@@ -301,7 +315,8 @@ struct ContractInst {
 struct ContractArgs {
   int32_t n_inst;
   int32_t n_lo, n_cnt;      // orders n_lo .. n_lo + n_cnt - 1 of this chunk
-  int32_t S;                // ring size: order n lives in slot n % S
+  int32_t S;                // ring size: order n at ring position n % S
+  int32_t G;                // ring parts: position k in slot ring_slot(k, S, G)
   int32_t first_chunk;      // write (1) or accumulate (0) carry and partials
   int32_t jtiles;           // 32-wide time tiles (FP32 MFMA path)
   int32_t bcols;            // time points of the block (b_k)
@@ -347,7 +362,8 @@ struct QeInst {
 struct QeArgs {
   int32_t n_inst;
   int32_t n_lo, n_cnt;      // orders n_lo .. n_lo + n_cnt - 1 of this chunk
-  int32_t S;                // ring size: order n lives in slot n % S
+  int32_t S;                // ring size: order n at ring position n % S
+  int32_t G;                // ring parts: position k in slot ring_slot(k, S, G)
   int32_t first_chunk;      // write (1) or accumulate (0) the states
   int32_t nE;               // energies
   int32_t total_wg;

@@ -106,7 +106,6 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
   gf2* carry = (gf2*)(I.carry) + coff;
   const int64_t n_tiles = ceil_div(N, 32);
   const int64_t sstr = I.slot_stride;
-  const int64_t wrap = (int64_t)a.S * sstr;
 
   // per-lane correlation sums of time lane%32 (+ 32 jt) over the rows seen
   float pr[JT], pi[JT];
@@ -130,15 +129,20 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
     // is multiplied (its values are converted to bf16 first, so the loads
     // can reuse their registers).
     float2 xn[8];
-    // order n lives in slot n % S; consecutive orders in consecutive slots
+    // order n sits at ring position n % S, in slot ring_slot(n % S)
+    const int part = a.S / a.G;
     auto load_step = [&](int kb) {
       const int rel0 = kb * 16 + h * 8;
-      int64_t off = (int64_t)((a.n_lo + rel0) % a.S) * sstr;
+      int k = (a.n_lo + rel0) % a.S;
+      int ps = ring_slot(k, a.S, a.G);
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        xn[v] = (mv && rel0 + v < a.n_cnt) ? ldg2_stream(slots + off + m) : make_float2(0.f, 0.f);
-        off += sstr;
-        if (off >= wrap) off -= wrap;
+        xn[v] = (mv && rel0 + v < a.n_cnt) ? ldg2_stream(slots + (int64_t)ps * sstr + m)
+                                            : make_float2(0.f, 0.f);
+        // next position (S wraps to 0) and its slot, without branches
+        const int kn = k + 1, pn = ps + part;
+        ps = kn == a.S ? 0 : (pn >= a.S ? pn - (a.S - 1) : pn);
+        k = kn == a.S ? 0 : kn;
       }
     };
     load_step(0);
@@ -301,7 +305,8 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_f64(
     for (int j = 0; j < B; ++j) acc[j] = make_double2(0.0, 0.0);
     double2 cy = make_double2(0.0, 0.0);
     for (int rel = 0; rel < a.n_cnt; ++rel) {
-      const double2 x = slots[(int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + m];
+      const double2 x =
+          slots[(int64_t)ring_slot((a.n_lo + rel) % a.S, a.S, a.G) * I.slot_stride + m];
 #pragma unroll
       for (int j = 0; j < B; ++j) {
         const double2 c = scoef[rel * B + j];

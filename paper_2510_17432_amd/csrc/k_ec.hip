@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
     const int r = wave * 32 + j * 4 + sub;
     aok[j] = r < a.n_cnt;
     arow[j] = (const gef2*)(I.slots) +
-              (int64_t)((a.n_lo + (aok[j] ? r : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
+              (int64_t)ring_slot((a.n_lo + (aok[j] ? r : 0)) % a.S, a.S, a.G) * I.slot_stride +
+              (int64_t)c * N;
   }
   const gef2* brow[2];
   bool bok[2];
@@ -427,7 +428,8 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
     const int r = 8 * j + rsub;
     aok[j] = r < a.n_cnt;
     arow[j] = static_cast<const double2*>(I.slots) +
-              (int64_t)((a.n_lo + (aok[j] ? r : 0)) % a.S) * I.slot_stride + (int64_t)c * N;
+              (int64_t)ring_slot((a.n_lo + (aok[j] ? r : 0)) % a.S, a.S, a.G) * I.slot_stride +
+              (int64_t)c * N;
   }
   const double2* brow[2];
   bool bok[2];

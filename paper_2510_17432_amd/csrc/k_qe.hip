@@ -272,7 +272,6 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
   gq2* out = (gq2*)(I.out) + col * (int64_t)a.nE * N;
   const int64_t n_tiles = ceil_div(N, 32);
   const int64_t sstr = I.slot_stride;
-  const int64_t wrap = (int64_t)a.S * sstr;
 
   const int64_t stride_tiles = (int64_t)I.wpc * 4;
   for (int64_t tile = sub * 4 + wave; tile < n_tiles; tile += stride_tiles) {
@@ -285,17 +284,22 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f32(
       accI[v] = 0.f;
     }
     qf32x2 xn[8];
+    // order n in slot ring_slot(n % S)
+    const int part = a.S / a.G;
     auto load_step = [&](int kb) {
       const int rel0 = kb * 16 + h * 8;
-      int64_t off = (int64_t)((a.n_lo + rel0) % a.S) * sstr;
+      int k = (a.n_lo + rel0) % a.S;
+      int ps = ring_slot(k, a.S, a.G);
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
         qf32x2 z;
         z.x = 0.f;
         z.y = 0.f;
-        xn[v] = (mv && rel0 + v < a.n_cnt) ? slots[off + m] : z;
-        off += sstr;
-        if (off >= wrap) off -= wrap;
+        xn[v] = (mv && rel0 + v < a.n_cnt) ? slots[(int64_t)ps * sstr + m] : z;
+        // next position (S wraps to 0) and its slot, without branches
+        const int kn = k + 1, pn = ps + part;
+        ps = kn == a.S ? 0 : (pn >= a.S ? pn - (a.S - 1) : pn);
+        k = kn == a.S ? 0 : kn;
       }
     };
     load_step(0);
@@ -404,7 +408,8 @@ __global__ __launch_bounds__(kContractThreads) void k_contract_qe_f64(
 #pragma unroll
     for (int e = 0; e < B; ++e) acc[e] = make_double2(0.0, 0.0);
     for (int rel = 0; rel < a.n_cnt; ++rel) {
-      const double2 x = slots[(int64_t)((a.n_lo + rel) % a.S) * I.slot_stride + m];
+      const double2 x =
+          slots[(int64_t)ring_slot((a.n_lo + rel) % a.S, a.S, a.G) * I.slot_stride + m];
 #pragma unroll
       for (int e = 0; e < B; ++e) {
         const double2 c = scoef[rel * B + e];
