@@ -118,8 +118,8 @@ def parse():
     ap.add_argument("--ell-steps", action="store_true",
                     help="instead of the step benchmark: the explicit-matrix recursion alone, "
                          "64 Chebyshev steps of the state form (b = 16) and of the moment "
-                         "form, complex64, on the D_H = 61 / 121 / 233 matrices with 10 / 5 / 2 "
-                         "random columns (--dh selects densities)")
+                         "form, complex64 and complex128, on the D_H = 61 / 121 / 233 matrices "
+                         "with 10 / 5 / 2 random columns (--dh selects densities)")
     return ap.parse_args()
 
 
@@ -578,7 +578,7 @@ def _copy_probe():
 def ell_steps(a):
     """The explicit-matrix Chebyshev step alone (Sec. II.B, matrix density
     D_H): 64 steps of the state form (b = 16) and of the moment form with
-    halving, complex64, on the long-range matrices of D_H = 61 / 121 / 233
+    halving, complex64 and complex128, on the long-range matrices of D_H = 61 / 121 / 233
     with 10 / 5 / 2 random columns; each timed on a second call with HIP
     events around every recursion launch."""
     import torch
@@ -602,12 +602,16 @@ def ell_steps(a):
         csp.csp_states_random_phase(ctx, psi, R, w["seed_states"])
         res = {"D_H": D, "columns": R, "windowed": lat.info.ell_windowed,
                "max_window": lat.info.ell_max_window}
-        for name, asm, b in (("states_b16", csp.CSP_ASSEMBLE_STATES, 16),
-                             ("moments", csp.CSP_ASSEMBLE_MOMENTS, 0)):
-            prm = csp.make_params(64, mode="fp32_conc", assembly=asm, block_b=b, profile=True)
-            csp.csp_propagate(ctx, lat, psi, prm)
+        psi64 = psi.to(torch.complex128)
+        for name, asm, b, mode, p in (
+                ("states_b16", csp.CSP_ASSEMBLE_STATES, 16, "fp32_conc", psi),
+                ("moments", csp.CSP_ASSEMBLE_MOMENTS, 0, "fp32_conc", psi),
+                ("complex128_states_b16", csp.CSP_ASSEMBLE_STATES, 16, "fp64_conc", psi64),
+                ("complex128_moments", csp.CSP_ASSEMBLE_MOMENTS, 0, "fp64_conc", psi64)):
+            prm = csp.make_params(64, mode=mode, assembly=asm, block_b=b, profile=True)
+            csp.csp_propagate(ctx, lat, p, prm)
             torch.cuda.synchronize()
-            _, rep = csp.csp_propagate(ctx, lat, psi, prm)
+            _, rep = csp.csp_propagate(ctx, lat, p, prm)
             torch.cuda.synchronize()
             us = 1000.0 * rep.ms_spmm / rep.spmm_launches
             gbs = rep.spmm_bytes / rep.ms_spmm / 1e6
@@ -615,7 +619,7 @@ def ell_steps(a):
                          rep.spmm_launches, "alg_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
             log("D_H=%d R=%d %s: %.1f us per step, %.0f GB/s algorithmic" % (D, R, name, us, gbs))
         out["cases"].append(res)
-        del psi
+        del psi, psi64
         lat.close()
         ctx.trim()
         torch.cuda.empty_cache()

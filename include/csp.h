@@ -237,17 +237,17 @@ csp_status csp_lattice_create(csp_context *ctx, const csp_lattice_desc *desc,
  * at least half of the slices of 128 rows, regrouped to be compact in the
  * matrix graph, name at most 2048 distinct columns that each serve four or
  * more entries, a second, windowed copy of the matrix is kept (rows per
- * slice, 16-bit window-local and 32-bit global columns, FP32 values: 10 B
- * per entry, rows padded to a multiple of 4 entries, besides the 16 of the
- * slice layout) and the complex64 recursion stages each slice's window of
- * phi_n in LDS; csp_lattice_get_info reports it.  Otherwise, in complex64 a
+ * slice, 16-bit window-local and 32-bit global columns, FP64 and FP32
+ * values: 18 B per entry, rows padded to a multiple of 4 entries, besides
+ * the 16 of the slice layout) and the recursion stages each slice's window
+ * of phi_n in LDS; csp_lattice_get_info reports it.  Otherwise, in complex64 a
  * call on it keeps, per group of Rg columns, two orbital-major copies of
  * floor(Rg/2) column pairs (32 floor(Rg/2) N bytes) in context memory
  * outside mem_cap_bytes, released by csp_context_trim.
  * csp_lattice_onsite and csp_lattice_neighbors return CSP_EUNSUPPORTED for
  * it.  Errors: CSP_EINVAL for N outside [1, 2^31), D outside [1, 4096], a
  * column index >= N, a non-finite value or an all-zero matrix; CSP_ENOMEM
- * when the device cannot hold the 16 D N bytes of the matrix (about 26 D N
+ * when the device cannot hold the 16 D N bytes of the matrix (about 34 D N
  * with the windowed copy). */
 csp_status csp_lattice_create_sparse(csp_context *ctx, int64_t N, int32_t D, const int32_t *col,
                                      const double *val, double margin, csp_lattice **out);

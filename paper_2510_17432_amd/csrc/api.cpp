@@ -110,6 +110,7 @@ struct csp_lattice {
   int32_t* ellw_rows = nullptr;
   uint16_t* ellw_loc = nullptr;
   int32_t* ellw_col = nullptr;
+  double* ellw_v64 = nullptr;
   float* ellw_v32 = nullptr;
   int64_t* ellw_off = nullptr;
   int32_t* ellw_idx = nullptr;
@@ -358,7 +359,7 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
     if (L->ell_v64) (void)hipFree(L->ell_v64);
     if (L->ell_v32) (void)hipFree(L->ell_v32);
     for (void* q : {(void*)L->ellw_rows, (void*)L->ellw_loc, (void*)L->ellw_col,
-                    (void*)L->ellw_v32, (void*)L->ellw_off,
+                    (void*)L->ellw_v64, (void*)L->ellw_v32, (void*)L->ellw_off,
                     (void*)L->ellw_idx})
       if (q) (void)hipFree(q);
     delete L;
@@ -405,6 +406,7 @@ extern "C" csp_status csp_lattice_create_sparse(csp_context* c, int64_t N, int32
       up((void**)&L->ellw_rows, w.rows.data(), sizeof(int32_t) * w.rows.size());
       up((void**)&L->ellw_loc, w.loc.data(), sizeof(uint16_t) * ne);
       up((void**)&L->ellw_col, w.col.data(), sizeof(int32_t) * ne);
+      up((void**)&L->ellw_v64, w.v64.data(), sizeof(double) * ne);
       up((void**)&L->ellw_v32, w.v32.data(), sizeof(float) * ne);
       up((void**)&L->ellw_off, w.off.data(), sizeof(int64_t) * w.off.size());
       up((void**)&L->ellw_idx, w.idx.data(), sizeof(int32_t) * w.idx.size());
@@ -441,7 +443,7 @@ extern "C" csp_status csp_lattice_destroy(csp_lattice* L) {
   if (L->ell_v32) (void)hipFree(L->ell_v32);
   if (L->pos) (void)hipFree(L->pos);
   for (void* q : {(void*)L->ellw_rows, (void*)L->ellw_loc, (void*)L->ellw_col,
-                  (void*)L->ellw_v32, (void*)L->ellw_off,
+                  (void*)L->ellw_v64, (void*)L->ellw_v32, (void*)L->ellw_off,
                   (void*)L->ellw_idx})
     if (q) (void)hipFree(q);
   delete L;
@@ -618,7 +620,7 @@ ChebPlan plan_cheb(std::vector<ChebInst>& insts, bool fp64, bool mom, int n_cu, 
     const int ct = sparse ? I.ell_ct : 0;
     const int64_t nw = sparse ? I.n_segs * ceil_div(I.Rg, ct) : 0;
     const bool honey = I.kind == CSP_HONEYCOMB, eps = I.eps != nullptr;
-    const bool win = sparse && I.ellw_rows != nullptr;   // set for complex64 only
+    const bool win = sparse && I.ellw_rows != nullptr;
     if (p.runs.empty() || p.runs.back().honey != honey || p.runs.back().eps != eps ||
         p.runs.back().sparse != sparse || p.runs.back().ct != ct || p.runs.back().win != win)
       p.runs.push_back({(int)k, 0, t0, 0, honey, eps, sparse, ct, w0, 0, win, 0});
@@ -662,15 +664,13 @@ ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
     I.ell_val = fp64 ? (const void*)L->ell_v64 : (const void*)L->ell_v32;
     I.ell_D = L->ell_D;
     I.ell_ct = ell_columns_per_wave(fp64, Rg);
-    // complex64 only: for complex128 the slice-layout kernel, whose 16-byte
-    // gathers already fill whole lanes, measured faster (3.96 against 5.63 ms
-    // per step at D_H = 121, 5 columns, on MI355X)
-    if (L->ellw_rows && !fp64) {
-      I.ell_ct = ellw_columns_per_group(fp64, Rg);
+    if (L->ellw_rows) {
+      const int64_t p97 = L->ellw_sorted[(L->ellw_sorted.size() * 97) / 100];
+      I.ell_ct = ellw_columns_per_group(fp64, Rg, p97);
       I.ellw_rows = L->ellw_rows;
       I.ellw_loc = L->ellw_loc;
       I.ellw_col = L->ellw_col;
-      I.ellw_val = L->ellw_v32;
+      I.ellw_val = fp64 ? (const void*)L->ellw_v64 : (const void*)L->ellw_v32;
       I.ellw_off = L->ellw_off;
       I.ellw_idx = L->ellw_idx;
       // LDS of a workgroup: its tile's columns (at most min(ct, Rg)) of the
@@ -680,7 +680,6 @@ ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
       // their LDS
       const int64_t ncs = std::min(I.ell_ct, Rg);
       const int64_t cap = kEllwLdsBytes / (ncs * (int64_t)(fp64 ? 16 : 8));
-      const int64_t p97 = L->ellw_sorted[(L->ellw_sorted.size() * 97) / 100];
       int64_t best = 0;
       for (int32_t W : L->ellw_sizes)
         if (W <= cap && W <= p97 && W > best) best = W;

@@ -186,7 +186,8 @@ hipError_t launch_cheb_ellw(bool fp64, bool mom, bool carry, int ct, int64_t lds
                             const ChebInst* d_inst, int n_inst, int64_t wg_lo, int64_t wg_hi,
                             const ChebStep& st, hipStream_t s);
 // columns per workgroup of the windowed kernel for a group of Rg columns
-int ellw_columns_per_group(bool fp64, int Rg);
+// whose slices stage windows of up to `window` positions
+int ellw_columns_per_group(bool fp64, int Rg, int64_t window);
 // LDS bytes a windowed workgroup may stage
 constexpr int64_t kEllwLdsBytes = 64 * 1024;
 
@@ -200,7 +201,8 @@ struct EllWindows {
   std::vector<int32_t> idx;      // windows, ascending per slice
   std::vector<uint16_t> loc;     // [n_slices][D4][128][4]
   std::vector<int32_t> col;      // [n_slices][D4][128][4]
-  std::vector<float> v32;        // [n_slices][D4][128][4]
+  std::vector<double> v64;       // [n_slices][D4][128][4]
+  std::vector<float> v32;        // same, FP32
 };
 bool build_ell_windows(int64_t N, int D, const int32_t* col, const double* val, EllWindows* w);
 // max_s sum_k |val_sk| (k in order, FP64): one maximum per block into partial

@@ -36,6 +36,7 @@ bool build_ell_windows(int64_t N, int D, const int32_t* col, const double* val,
   w->idx.clear();
   w->loc.assign(n, 0);
   w->col.assign(n, 0);
+  w->v64.assign(n, 0.0);
   w->v32.assign(n, 0.0f);
   w->max_window = 0;
 
@@ -120,6 +121,7 @@ bool build_ell_windows(int64_t N, int D, const int32_t* col, const double* val,
           // value 0)
           w->col[e] = j >= 0 ? j : r;
           w->loc[e] = j >= 0 && mark[j] <= 0xffff ? static_cast<uint16_t>(mark[j]) : 0;
+          w->v64[e] = v;
           w->v32[e] = static_cast<float>(v);
         }
       }

@@ -12,16 +12,17 @@
 // window's columns run consecutively), then thread t accumulates row t of
 // the slice over its D entries, reading the matrix once (16-bit
 // window-local columns and values in quads of four entries per load,
-// non-temporal: 6 B per entry in complex64 instead of the 8 B of the slice
-// layout) and gathering every phi_n value from LDS instead of the caches.
+// non-temporal: 6 B per entry in complex64 and 10 B in complex128, against
+// 8 and 12 B in the slice layout) and gathering every phi_n value from LDS
+// instead of the caches.
 // A slice whose window exceeds the LDS budget gathers from global memory
 // with the entries' global columns.  Rows keep their index in every vector:
 // thread t reads and writes row rows[t] of phi_n, phi_{n-1}, phi_{n+1},
 // psi0 and the carried state (scattered within the slice's ball of rows).
 // Moment epilogue and carried state as the other recursion kernels: one
 // record of 8 FP64 sums per (column, slice), the two waves of the
-// workgroup added in a fixed order.  complex64 only: for complex128 the
-// slice-layout kernel's 16-byte gathers measured faster.
+// workgroup added in a fixed order.
+#include <algorithm>
 #include <type_traits>
 
 #include "csp_internal.h"
@@ -351,11 +352,13 @@ __global__ __launch_bounds__(128) void k_cheb_ellw(const ChebInst* __restrict__ 
 }  // namespace ellw
 
 // Columns per workgroup (tile width CT): the group's columns in as few tiles
-// of at most 8 as possible, split evenly (10 columns: two tiles of 5; 25:
-// 7 + 6 + 6 + 6), so the matrix is read once per step per tile and every
-// tile holds CT or CT - 1 columns.
-int ellw_columns_per_group(bool fp64, int Rg) {
-  const int cap = fp64 ? 4 : 8;
+// as possible, split evenly (10 columns: two tiles of 5; 25: 7 + 6 + 6 + 6),
+// so the matrix is read once per step per tile and every tile holds CT or
+// CT - 1 columns.  A tile holds at most 8 columns, and at most as many as
+// fit the LDS budget with a window of `window` positions.
+int ellw_columns_per_group(bool fp64, int Rg, int64_t window) {
+  const int64_t fit = kEllwLdsBytes / (std::max<int64_t>(window, 1) * (fp64 ? 16 : 8));
+  const int cap = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(8, fit)));
   if (Rg < 1) return 1;
   const int tiles = (Rg + cap - 1) / cap;
   return (Rg + tiles - 1) / tiles;
@@ -388,11 +391,15 @@ hipError_t launch_cheb_ellw(bool fp64, bool mom, bool carry, int ct, int64_t lds
       default: CSP_ELLW(T, 8, M, CY); break; \
     }                              \
   } while (0)
-  // complex64 only (complex128 lattices run the slice-layout kernel)
-  if (fp64) return hipErrorInvalidValue;
-  if (carry) CSP_ELLW_CT(float, true, true);
-  else if (mom) CSP_ELLW_CT(float, true, false);
-  else CSP_ELLW_CT(float, false, false);
+  if (fp64) {
+    if (carry) CSP_ELLW_CT(double, true, true);
+    else if (mom) CSP_ELLW_CT(double, true, false);
+    else CSP_ELLW_CT(double, false, false);
+  } else {
+    if (carry) CSP_ELLW_CT(float, true, true);
+    else if (mom) CSP_ELLW_CT(float, true, false);
+    else CSP_ELLW_CT(float, false, false);
+  }
 #undef CSP_ELLW_CT
 #undef CSP_ELLW
   return hipGetLastError();
