@@ -2333,7 +2333,7 @@ extern "C" csp_status csp_ec_correlation(csp_context* c, const csp_lattice* L, i
   const bool fp64 = P.mode == CSP_FP64_CONC;
   const int nE = n_E;
   if (nE < 1 || nE > 128) return fail(CSP_EINVAL, "need 1 <= n_E <= 128");
-  const int e_tile = fp64 ? 16 : 32;
+  const int e_tile = fp64 ? ec64_tile(nE) : 32;
   const int ldp = (int)ceil_div(nE, e_tile) * e_tile;
   if (alpha != 0 && alpha != 1) return fail(CSP_EINVAL, "alpha must be 0 (x) or 1 (y)");
   if (R < 1) return fail(CSP_EINVAL, "R must be >= 1");

@@ -280,11 +280,14 @@ struct EcInst {
   int32_t wg0, n_wg;        // workgroups: Rg * n_slices
   int32_t q0, pad;          // first moment column of the group (col0 * nE)
 };
+// Energies per tile of the complex128 conductivity moments: 16, or 24 for more
+// than 16 energies (fewer tiles re-reading each chunk of orders).
+__host__ __device__ constexpr int ec64_tile(int nE) { return nE > 16 ? 24 : 16; }
 struct EcArgs {
   int32_t n_inst, n_lo, n_cnt, S;
   int32_t G;                // ring parts: position k in slot ring_slot(k, S, G)
   int32_t nE, K, total_wg;
-  int32_t ldp;              // energies per partial row: n_etiles x tile (32 FP32, 16 FP64)
+  int32_t ldp;              // energies per partial row: n_etiles x tile (32 FP32, ec64_tile FP64)
   double* mu;               // [Nmax + 1][ldmu] complex, column q = (col0 + c) nE + e
   int64_t ldmu;
 };

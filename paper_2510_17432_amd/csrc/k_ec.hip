@@ -390,26 +390,32 @@ __global__ __launch_bounds__(256) void k_ec_moments_f32(const EcInst* __restrict
 }
 
 // ------------------------------------------------------------------ moments, FP64
-// Workgroup per (instance, column, slice) and tile of 16 energies (grid y).
-// Per step of 32 orbitals the chunk's 128 orders and the 16 bras are staged
-// in LDS with coalesced loads (32 lanes read one 512-byte row); thread t
-// accumulates energies t % 8 and t % 8 + 8 against orders t / 8 + 32 p,
-// p = 0..3, with FMAs: six LDS reads per eight complex products (the kernel
-// is bound by LDS reads; one energy against eight orders took nine).
+// Workgroup per (instance, column, slice) and tile of up to 16 energies, or
+// 24 when there are more than 16 (the energies split evenly over the tiles).
+// Per step of 32 orbitals the chunk's 128 orders and the tile's bras are
+// staged in LDS with coalesced loads (32 lanes read one 512-byte row);
+// thread t accumulates energies t % 8 + 8 q (q < 2, or 3 with 24-energy
+// tiles) against orders t / 8 + 32 p, p = 0..3, with FMAs: six LDS reads per
+// eight complex products with two energies (the kernel is bound by LDS
+// reads; one energy against eight orders took nine).
 constexpr int kEc64Row = 33;         // complex values per LDS row (padded)
 
 template <int NE>
 __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict__ insts,
                                                         EcArgs a) {
+  constexpr int NQ = NE > 16 ? 3 : NE > 8 ? 2 : 1;  // energies per thread
+  constexpr int TILE = ec64_tile(NE);                 // energies a tile can hold
   __shared__ double2 sa[128 * kEc64Row];
-  __shared__ double2 sb[16 * kEc64Row];
+  __shared__ double2 sb[8 * NQ * kEc64Row];
   const int tid = threadIdx.x;
   // logical workgroup (slice, energy tile), the tiles of a slice adjacent
-  // (one XCD, the same orders at the same time: L2 hits after the first)
-  const int n_et = (a.nE + 15) / 16;
+  // (one XCD, the same orders at the same time: L2 hits after the first);
+  // the energies split evenly over the tiles (49: 17 + 16 + 16)
+  const int n_et = (a.nE + TILE - 1) / TILE;
+  const int tw = (a.nE + n_et - 1) / n_et;
   const int64_t lwg = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t wg = lwg / n_et;
-  const int e0 = 16 * static_cast<int>(lwg - wg * n_et);
+  const int e0 = tw * static_cast<int>(lwg - wg * n_et);
   int ii = 0;
   while (ii + 1 < a.n_inst && wg >= insts[ii + 1].wg0) ++ii;
   const EcInst& I = insts[ii];
@@ -431,25 +437,24 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
               (int64_t)ring_slot((a.n_lo + (aok[j] ? r : 0)) % a.S, a.S, a.G) * I.slot_stride +
               (int64_t)c * N;
   }
-  const double2* brow[2];
-  bool bok[2];
+  const double2* brow[NQ];
+  bool bok[NQ];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NQ; ++j) {
     const int e = e0 + 8 * j + rsub;
-    bok[j] = e < a.nE && 8 * j + rsub < NE;
+    bok[j] = e < a.nE && 8 * j + rsub < tw;
     brow[j] = static_cast<const double2*>(I.bra) + ((int64_t)(bok[j] ? e : 0) * I.Rg + c) * N;
   }
-  double2 ra[16], rb[2];
+  double2 ra[16], rb[NQ];
   auto fetch = [&](int64_t s) {
     const int64_t o = s + col;
     const bool in = o < s_end;
 #pragma unroll
     for (int j = 0; j < 16; ++j) ra[j] = (aok[j] && in) ? arow[j][o] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) rb[j] = (bok[j] && in) ? brow[j][o] : make_double2(0.0, 0.0);
+    for (int j = 0; j < NQ; ++j) rb[j] = (bok[j] && in) ? brow[j][o] : make_double2(0.0, 0.0);
   };
 
-  constexpr int NQ = NE > 8 ? 2 : 1;                // energies per thread
   const int eq = tid & 7, og = tid >> 3;           // energies eq + 8 q, orders og + 32 p
   double sr[NQ][4], si[NQ][4];
 #pragma unroll
@@ -462,7 +467,7 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
 #pragma unroll
     for (int j = 0; j < 16; ++j) sa[(8 * j + rsub) * kEc64Row + col] = ra[j];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) sb[(8 * j + rsub) * kEc64Row + col] = rb[j];
+    for (int j = 0; j < NQ; ++j) sb[(8 * j + rsub) * kEc64Row + col] = rb[j];
     __syncthreads();
     if (s + 32 < s_end) fetch(s + 32);
     if (eq < NE) {
@@ -486,7 +491,7 @@ __global__ __launch_bounds__(256) void k_ec_moments_f64(const EcInst* __restrict
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int e = eq + 8 * q;
-    if (e < NE && e0 + e < a.nE) {
+    if (e < tw && e0 + e < a.nE) {
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const int r = og + 32 * p;
@@ -520,13 +525,14 @@ __global__ void k_ec_mu_finish(const EcInst* __restrict__ insts, EcArgs a) {
 
 hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const EcArgs& a,
                              hipStream_t s) {
-  const int tile = fp64 ? 16 : 32;
+  const int tile = fp64 ? ec64_tile(a.nE) : 32;
   const int n_et = (int)ceil_div(a.nE, tile);
   if (a.n_cnt < 1 || a.n_cnt > a.K || a.K > 128 || a.nE < 1 || a.ldp != n_et * tile)
     return hipErrorInvalidValue;
   if (fp64) {
     int ne = 1;
     while (ne < std::min(a.nE, 16)) ne *= 2;
+    if (a.nE > 16) ne = 24;
 #define CSP_EC64(NE) \
   hipLaunchKernelGGL(k_ec_moments_f64<NE>, dim3(a.total_wg * n_et), dim3(256), 0, s, d_inst, a)
     switch (ne) {
@@ -534,7 +540,8 @@ hipError_t launch_ec_moments(bool fp64, const EcInst* d_inst, int n_inst, const 
       case 2: CSP_EC64(2); break;
       case 4: CSP_EC64(4); break;
       case 8: CSP_EC64(8); break;
-      default: CSP_EC64(16); break;
+      case 16: CSP_EC64(16); break;
+      default: CSP_EC64(24); break;
     }
 #undef CSP_EC64
   } else {

@@ -122,13 +122,17 @@ def test_ec_spectral_centre(csp, ctx):
 
 
 def test_ec_many_energies(csp, ctx):
-    # one and several energy tiles (32 per tile in complex64, 16 in complex128)
+    # one and several energy tiles (32 per tile in complex64; in complex128 16,
+    # or up to 24 with more than 16 energies)
     spec = dict(kind="honeycomb", Lx=12, Ly=10, t=-2.7, W=1.0, disorder_seed=8)
     g, c = pair(csp, ctx, spec)
     check(csp, ctx, g, c, 2, list(np.linspace(-7.0, 7.0, 32)), 10, 30, 1, "fp32_conc")
     check(csp, ctx, g, c, 2, list(np.linspace(-7.0, 7.0, 49)), 10, 30, 0, "fp32_conc")
     check(csp, ctx, g, c, 1, list(np.linspace(-7.0, 7.0, 16)), 10, 30, 0, "fp64_conc")
     check(csp, ctx, g, c, 1, list(np.linspace(-7.0, 7.0, 37)), 10, 30, 1, "fp64_conc")
+    # complex128 tiles of up to 24 energies: one of 17, three of 17 + 16 + 16
+    check(csp, ctx, g, c, 1, list(np.linspace(-7.0, 7.0, 17)), 10, 30, 0, "fp64_conc")
+    check(csp, ctx, g, c, 2, list(np.linspace(-7.0, 7.0, 49)), 10, 30, 1, "fp64_conc")
 
 
 @pytest.mark.parametrize("mode", ["fp64_conc", "fp32_conc"])
