@@ -122,8 +122,12 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
 #pragma unroll
       for (int v = 0; v < 16; ++v) { accR[jt][v] = 0.f; accI[jt][v] = 0.f; }
     float cr = 0.f, ci = 0.f;
-    // psi0 of the tile, value il in both half-waves (used after the orders)
+    // psi0 of the tile, value il in both half-waves (used after the orders),
+    // and the carried state of row il (half-wave 0, after the first chunk):
+    // both loaded with the orders, so the tile waits for memory once
     const float2 p0l = mv ? ldg2(psi0 + m) : make_float2(0.f, 0.f);
+    const float2 cold =
+        (h == 0 && mv && !a.first_chunk) ? ldg2(carry + m) : make_float2(0.f, 0.f);
 
     // Orders of the next 16-order step are in flight while the current one
     // is multiplied (its values are converted to bf16 first, so the loads
@@ -188,15 +192,8 @@ __global__ __launch_bounds__(kContractThreads) __attribute__((amdgpu_waves_per_e
     // Carried state: the two half-waves hold complementary orders of row il.
     cr += __shfl_xor(cr, 32);
     ci += __shfl_xor(ci, 32);
-    if (h == 0 && mv) {
-      float2 cv = make_float2(cr, ci);
-      if (!a.first_chunk) {
-        const float2 old = ldg2(carry + m);
-        cv.x += old.x;
-        cv.y += old.y;
-      }
-      stg2(carry + m, cv);
-    }
+    if (h == 0 && mv)
+      stg2(carry + m, a.first_chunk ? make_float2(cr, ci) : make_float2(cr + cold.x, ci + cold.y));
 
     // Correlation epilogue: conj(psi0[row]) * psi[row, time] summed over
     // the 16 rows 8(v/4) + 4h + v%4 of this lane; psi0 of row rho comes from
