@@ -11,8 +11,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsp.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["k_cheb_f32.hip", "k_cheb_f32m.hip", "k_cheb_f32mc.hip", "k_cheb_f64.hip",
-           "k_cheb_f64mc.hip", "k_setup.hip", "k_coeffs.hip",
+SOURCES = ["k_cheb_f32.hip", "k_cheb_f32m.hip", "k_cheb_f32mc.hip", "k_cheb_f32s.hip",
+           "k_cheb_f64.hip", "k_cheb_f64mc.hip", "k_cheb_f64s.hip", "k_setup.hip", "k_coeffs.hip",
            "k_cheb.hip", "k_cheb_ell.hip", "k_contract.hip", "k_moments.hip",
            "k_probe.hip", "k_qe.hip", "k_ec.hip", "k_cheb_ellw.hip", "ell_windows.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1587,7 +1587,9 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_MOMENTS);
   int vec_want = tune ? tune->spmm_vec : 0;
-  int kt_want = tune ? tune->spmm_steps : 4;
+  // default: 8 steps per launch for the complex64 self-product kernel
+  // (halving), 4 where psi0 or the carried state take registers
+  int kt_want = tune ? tune->spmm_steps : (halving && !fp64 ? 8 : 4);
   if (carry && !cheb_carry_supported(fp64, 2, kt_want)) kt_want = 4;
   if (carry) vec_want = 2;   // the carried-state kernels hold 2 values per lane
   const ChebPlan sp_plan = plan_cheb(sp, fp64, true, c->n_cu, vec_want, kt_want,
@@ -1683,7 +1685,6 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     const int bk = (int)std::min<int64_t>(b, Nt - t0);
     const int Nk = ntr[bk - 1];
     const int steps = halving ? (Nk + 1) / 2 : Nk;
-    const int h = Nk / 2;
     const std::vector<double>& arow = (bk == b) ? arow_b : arow_last;
     // per-block instance table: source and carry destination
     for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -1726,10 +1727,12 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
       }
       st.slot_out[st.nlev - 1] = new_cur;
       if (st.nlev >= 2) st.slot_out[st.nlev - 2] = new_prev;
-      st.dot_psi0 = (!halving || produced + 1 <= h || produced == 0) ? 1 : 0;
-      // The halving identity reads <phi_k|phi_k> and <phi_k|phi_k-1> only for
-      // 2k - 1 > h, i.e. k >= floor(h/2) + 1: launches below that skip them.
-      st.dot_self = (halving && produced + st.nlev >= h / 2 + 1) ? 1 : 0;
+      // With halving every moment above mu_1 comes from the self products
+      // <phi_k|phi_k> and <phi_k|phi_k-1> (Eq. cheby_prod): psi0 is read by
+      // the first launch only (mu_0, mu_1); the others run the kernel
+      // without psi0.
+      st.dot_psi0 = (!halving || produced == 0) ? 1 : 0;
+      st.dot_self = halving ? 1 : 0;
       st.mom_slot = launches;
       st.partial = d_part;
       if (carry) {
@@ -2670,6 +2673,8 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
     return fail(CSP_EINVAL, "bad assembly %d", P.assembly);
   const bool fp64 = P.mode != CSP_FP32_CONC;
   const bool mom = P.assembly == CSP_ASSEMBLE_MOMENTS;
+  // the moment form of one block (no final state) uses the halving identity
+  const bool halving_t = mom && P.mode != CSP_FP64_SEQ && (P.block_b <= 0 || P.block_b >= P.Nt);
   const size_t csz = fp64 ? sizeof(double2) : sizeof(float2);
   std::vector<InstIn> ins(n_inst);
   for (int i = 0; i < n_inst; ++i) {
@@ -2808,11 +2813,13 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
     st.slot_prev = 0;
     set_shadow(st, 1);   // a step inside a block, as the recursion runs it
     if (mom) {
-      // moment form: the two newest levels are kept
+      // moment form: the two newest levels are kept; one block (halving)
+      // runs the self products without psi0, time blocks the products
+      // with psi0
       st.slot_out[p.kt - 1] = 2;
       if (p.kt >= 2) st.slot_out[p.kt - 2] = 3;
-      st.dot_psi0 = 1;
-      st.dot_self = 1;
+      st.dot_psi0 = halving_t ? 0 : 1;
+      st.dot_self = halving_t ? 1 : 0;
     } else {
       for (int l = 1; l <= p.kt; ++l) st.slot_out[l - 1] = 1 + l;
     }

@@ -224,7 +224,7 @@ struct MomInst {
 hipError_t launch_cheb_mom_finish(const MomInst* d_mi, int n_inst, const double* partial,
                                   int64_t total_items, int kt, int n_slots, int n0, int max_row,
                                   hipStream_t s);
-// Moments of a block from the step sums (halving: doubling identity above h)
+// Moments of a block from the step sums (halving: every moment above mu_1 from the self products)
 // and correlations corr[(t0 + j) * ldc + col0 + r] = sum_n c_n(j tau) mu_n[r]
 // for j = 1..bk (table a as produced by launch_bessel, row j-1 for x = j tau).
 struct MomCorrInst {

@@ -15,6 +15,8 @@ CSP_CHEB_LAUNCHER(launch_cheb_f64)
 CSP_CHEB_LAUNCHER(launch_cheb_f64m)
 CSP_CHEB_LAUNCHER(launch_cheb_f32mc)
 CSP_CHEB_LAUNCHER(launch_cheb_f64mc)
+CSP_CHEB_LAUNCHER(launch_cheb_f32s)
+CSP_CHEB_LAUNCHER(launch_cheb_f64s)
 #undef CSP_CHEB_LAUNCHER
 
 bool cheb_shape_supported(bool fp64, int vec, int kt, bool mom) {
@@ -34,6 +36,8 @@ hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const C
   if (st.nlev < 1 || st.nlev > kt) return hipErrorInvalidValue;
   if (!cheb_shape_supported(fp64, vec, kt, mom)) return hipErrorInvalidValue;
   if (carry && (!mom || !cheb_carry_supported(fp64, vec, kt))) return hipErrorInvalidValue;
+  // only the self products (one block, bra = ket): the kernel without psi0
+  const bool self = mom && !carry && !st.dot_psi0 && st.dot_self;
   if (st.ow != 64 * vec - 2 * cheb_margin(vec, kt)) return hipErrorInvalidValue;
   for (const ChebRun& r : runs) {
     const ChebInst* di = d_inst + r.inst0;
@@ -46,13 +50,15 @@ hipError_t launch_cheb(bool fp64, int vec, int kt, bool mom, bool carry, const C
       e = launch_cheb_ell(fp64, mom, carry, r.ct, di, r.n_inst, r.wave0, r.wave0 + r.n_waves, st,
                           s);
     else if (fp64)
-      e = carry ? launch_cheb_f64mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
-          : mom ? launch_cheb_f64m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
-                : launch_cheb_f64(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
+      e = carry  ? launch_cheb_f64mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+          : self ? launch_cheb_f64s(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+          : mom  ? launch_cheb_f64m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+                 : launch_cheb_f64(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
     else
-      e = carry ? launch_cheb_f32mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
-          : mom ? launch_cheb_f32m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
-                : launch_cheb_f32(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
+      e = carry  ? launch_cheb_f32mc(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+          : self ? launch_cheb_f32s(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+          : mom  ? launch_cheb_f32m(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s)
+                 : launch_cheb_f32(vec, kt, r.honey, r.eps, di, r.n_inst, lo, hi, st, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -33,14 +33,18 @@
 // 2 nlev-row segment margins) and one write per level kept, instead of two
 // reads and one write per step.
 //
-// Moment variant (MOM, moment-based form of Sec. II.A): for every level and
-// owned value the epilogue accumulates <psi0|phi_{n+l}>, <psi0|phi_n> (first
-// level only), <phi_{n+l}|phi_{n+l}> and <phi_{n+l}|phi_{n+l-1}> (the halving
-// identity of Eq. cheby_prod): products over the V values of a lane in the
-// working precision, then FP64 sums over rows; each wave reduces with a
-// fixed butterfly and writes one record per level, so the sums do not depend
-// on the run.  With nlev = 1 it can also accumulate the carried state
-// s_{k+1} = sum_n c_n phi_n of a time block.
+// Moment variants (moment-based form of Sec. II.A).  MOM = kMomBra: for every
+// level and owned value the epilogue accumulates <psi0|phi_{n+l}>,
+// <psi0|phi_n> (first level only), <phi_{n+l}|phi_{n+l}> and
+// <phi_{n+l}|phi_{n+l-1}> (the products of Eq. cheby_prod), each kind when
+// its flag is set; it can also accumulate the carried state
+// s_{k+1} = sum_n c_n phi_n of a time block.  MOM = kMomSelf (one block with
+// bra = ket, Sec. III DOS-Concurrent-M): only |phi_{n+l}|^2 and
+// Re <phi_{n+l}|phi_{n+l-1}>, the two products that give every moment above
+// the first two; psi0 is not read and holds no registers.  Products over the
+// V values of a lane are summed in the working precision, then in FP64 over
+// rows; each wave reduces with a fixed butterfly and writes one record per
+// level, so the sums do not depend on the run.
 #pragma once
 
 #include <type_traits>
@@ -51,6 +55,11 @@
 
 namespace csp {
 namespace cheb {
+
+// moment epilogue of the recursion kernel (template argument MOM)
+constexpr int kMomNone = 0;   // state form: no inner products
+constexpr int kMomBra = 1;    // products with psi0 and the self products, by flags
+constexpr int kMomSelf = 2;   // self products only (bra = ket, one block)
 
 template <typename T> struct cx {
   T x, y;
@@ -223,10 +232,11 @@ template <int V, int KT> struct Shape {
 };
 
 // insts: the instances of this launch (consecutive items item_lo..item_hi-1).
-template <typename T, int V, int KT, bool HONEY, bool EPS, bool MOM, bool CARRY>
+template <typename T, int V, int KT, bool HONEY, bool EPS, int MOM, bool CARRY>
 __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts, int n_inst,
                                               int64_t item_lo, int64_t item_hi, ChebStep st) {
   static_assert(V % 2 == 0, "lanes hold whole (even, odd) orbital pairs");
+  static_assert(!CARRY || MOM == kMomBra, "the carried state comes with the bra moments");
   using C = cx<T>;
   using gT = CSP_GLOBAL T;
   constexpr int MG = Shape<V, KT>::MG;
@@ -324,25 +334,26 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
     for (int v = 0; v < V; ++v) er[k][v] = T(0);
 
-  // Moment sums, quantity q = 5 (l - 1) + j for level l: j = 0, 1
+  // Moment sums.  kMomBra: quantity q = 5 (l - 1) + j for level l: j = 0, 1
   // <psi0|out>, 2 |out|^2, 3, 4 <out|cur>; q = 5 KT + 0, 1: <psi0|cur> of
-  // the first level.  sq holds this lane's working-precision sums of the
-  // last rows; every kFlush rows each is summed over the wave and added in
-  // FP64 into accq of lane q.
+  // the first level.  kMomSelf: q = 2 (l - 1) + j: j = 0 |out|^2, 1
+  // Re <out|cur>.  sq holds this lane's working-precision sums of the last
+  // rows; every kFlush rows each is summed over the wave and added in FP64
+  // into accq of lane q.
   constexpr int kFlush = 16;
-  constexpr int NQ = MOM ? 5 * KT + 2 : 1;
+  constexpr int NQ = MOM == kMomBra ? 5 * KT + 2 : (MOM == kMomSelf ? 2 * KT : 1);
   T sq[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) sq[k] = T(0);
   double accq = 0.0;
   // psi0 rows r0 - k (moment epilogue)
-  C pq[MOM ? KT + 1 : 1][V];
+  C pq[MOM == kMomBra ? KT + 1 : 1][V];
 #pragma unroll
-  for (int k = 0; k < (MOM ? KT + 1 : 1); ++k)
+  for (int k = 0; k < (MOM == kMomBra ? KT + 1 : 1); ++k)
 #pragma unroll
     for (int v = 0; v < V; ++v) pq[k][v] = {T(0), T(0)};
-  const bool dots = MOM && (st.dot_psi0 || st.dot_self);
-  const bool want_psi0 = MOM && st.dot_psi0;
+  const bool dots = MOM == kMomSelf || (MOM == kMomBra && (st.dot_psi0 || st.dot_self));
+  const bool want_psi0 = MOM == kMomBra && st.dot_psi0;
   // carried state: partial sums of rows r0 - 1 - j (j < KT) in registers;
   // a row is read (carry_mode 2), completed and written once per launch
   const bool carry_on = CARRY && carry && st.carry_mode != 0;
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
         for (int v = 0; v < V; ++v) er[0][v] = neps[v];
       }
-      if constexpr (MOM) {
+      if constexpr (MOM == kMomBra) {
 #pragma unroll
         for (int k = KT; k >= 1; --k)
 #pragma unroll
@@ -535,7 +546,17 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
         }
         if (r >= y0 && r < y1) {
           if (outv[l - 1]) store_row(outv[l - 1], rw, o, true);
-          if constexpr (MOM) {
+          if constexpr (MOM == kMomSelf) {
+            const int q0 = 2 * (l - 1);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              const bool w = FAST ? true : own[v];
+              const C oo = w ? o[v] : C{T(0), T(0)};
+              sq[q0] += oo.x * oo.x + oo.y * oo.y;
+              sq[q0 + 1] += oo.x * c[v].x + oo.y * c[v].y;
+            }
+          }
+          if constexpr (MOM == kMomBra) {
             if (dots) {
               // values outside the owned positions take no part in the sums
               // (interior strips: whole lanes, masked when the sums are
@@ -599,7 +620,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
           }
         }
       }
-      if constexpr (MOM) {
+      if constexpr (MOM != kMomNone) {
         if (dots && (--flush_in == 0 || i + 1 == n_iter)) {
           flush_in = kFlush;
 #pragma unroll
@@ -617,18 +638,24 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   if (fast) run(std::true_type{});
   else run(std::false_type{});
 
-  if constexpr (MOM) {
+  if constexpr (MOM != kMomNone) {
     if (dots) {
       // one record of 8 doubles per level, [kind][re, im] with kinds
-      // <psi0|out>, <psi0|cur> (first level only), <out|out>, <out|cur>;
+      // <psi0|out>, <psi0|cur> (first level only), <out|out>, <out|cur>
+      // (kMomSelf: the real parts of the last two, zeros elsewhere);
       // lane m writes element m % 8 of level m / 8
       const int m = lane;
       const int l = m >> 3, slot = m & 7;
       int q = -1;
-      if (slot == 0 || slot == 1) q = 5 * l + slot;
-      else if (slot == 4) q = 5 * l + 2;
-      else if (slot == 6 || slot == 7) q = 5 * l + slot - 3;
-      else if ((slot == 2 || slot == 3) && l == 0) q = 5 * KT + slot - 2;
+      if constexpr (MOM == kMomSelf) {
+        if (slot == 4) q = 2 * l;
+        else if (slot == 6) q = 2 * l + 1;
+      } else {
+        if (slot == 0 || slot == 1) q = 5 * l + slot;
+        else if (slot == 4) q = 5 * l + 2;
+        else if (slot == 6 || slot == 7) q = 5 * l + slot - 3;
+        else if ((slot == 2 || slot == 3) && l == 0) q = 5 * KT + slot - 2;
+      }
       const double val = __shfl(accq, q < 0 ? 0 : q);
       if (l < nlev && l < KT) {
         double* out = st.partial + (((int64_t)st.mom_slot * KT + l) * st.total_items + item) * 8;

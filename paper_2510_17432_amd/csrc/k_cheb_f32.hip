@@ -9,14 +9,14 @@ hipError_t launch_cheb_f32(int vec, int kt, bool honey, bool eps, const ChebInst
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(float, 2, 1, false, false); break;
-    case 202: CSP_CHEB_LAUNCH(float, 2, 2, false, false); break;
-    case 204: CSP_CHEB_LAUNCH(float, 2, 4, false, false); break;
-    case 208: CSP_CHEB_LAUNCH(float, 2, 8, false, false); break;
-    case 401: CSP_CHEB_LAUNCH(float, 4, 1, false, false); break;
-    case 402: CSP_CHEB_LAUNCH(float, 4, 2, false, false); break;
-    case 404: CSP_CHEB_LAUNCH(float, 4, 4, false, false); break;
-    case 408: CSP_CHEB_LAUNCH(float, 4, 8, false, false); break;
+    case 201: CSP_CHEB_LAUNCH(float, 2, 1, cheb::kMomNone, false); break;
+    case 202: CSP_CHEB_LAUNCH(float, 2, 2, cheb::kMomNone, false); break;
+    case 204: CSP_CHEB_LAUNCH(float, 2, 4, cheb::kMomNone, false); break;
+    case 208: CSP_CHEB_LAUNCH(float, 2, 8, cheb::kMomNone, false); break;
+    case 401: CSP_CHEB_LAUNCH(float, 4, 1, cheb::kMomNone, false); break;
+    case 402: CSP_CHEB_LAUNCH(float, 4, 2, cheb::kMomNone, false); break;
+    case 404: CSP_CHEB_LAUNCH(float, 4, 4, cheb::kMomNone, false); break;
+    case 408: CSP_CHEB_LAUNCH(float, 4, 8, cheb::kMomNone, false); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -9,13 +9,13 @@ hipError_t launch_cheb_f32m(int vec, int kt, bool honey, bool eps, const ChebIns
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(float, 2, 1, true, false); break;
-    case 202: CSP_CHEB_LAUNCH(float, 2, 2, true, false); break;
-    case 204: CSP_CHEB_LAUNCH(float, 2, 4, true, false); break;
-    case 208: CSP_CHEB_LAUNCH(float, 2, 8, true, false); break;
-    case 401: CSP_CHEB_LAUNCH(float, 4, 1, true, false); break;
-    case 402: CSP_CHEB_LAUNCH(float, 4, 2, true, false); break;
-    case 404: CSP_CHEB_LAUNCH(float, 4, 4, true, false); break;
+    case 201: CSP_CHEB_LAUNCH(float, 2, 1, cheb::kMomBra, false); break;
+    case 202: CSP_CHEB_LAUNCH(float, 2, 2, cheb::kMomBra, false); break;
+    case 204: CSP_CHEB_LAUNCH(float, 2, 4, cheb::kMomBra, false); break;
+    case 208: CSP_CHEB_LAUNCH(float, 2, 8, cheb::kMomBra, false); break;
+    case 401: CSP_CHEB_LAUNCH(float, 4, 1, cheb::kMomBra, false); break;
+    case 402: CSP_CHEB_LAUNCH(float, 4, 2, cheb::kMomBra, false); break;
+    case 404: CSP_CHEB_LAUNCH(float, 4, 4, cheb::kMomBra, false); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

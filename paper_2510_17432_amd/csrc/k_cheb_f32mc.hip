@@ -9,10 +9,10 @@ hipError_t launch_cheb_f32mc(int vec, int kt, bool honey, bool eps, const ChebIn
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(float, 2, 1, true, true); break;
-    case 202: CSP_CHEB_LAUNCH(float, 2, 2, true, true); break;
-    case 204: CSP_CHEB_LAUNCH(float, 2, 4, true, true); break;
-    case 208: CSP_CHEB_LAUNCH(float, 2, 8, true, true); break;
+    case 201: CSP_CHEB_LAUNCH(float, 2, 1, cheb::kMomBra, true); break;
+    case 202: CSP_CHEB_LAUNCH(float, 2, 2, cheb::kMomBra, true); break;
+    case 204: CSP_CHEB_LAUNCH(float, 2, 4, cheb::kMomBra, true); break;
+    case 208: CSP_CHEB_LAUNCH(float, 2, 8, cheb::kMomBra, true); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

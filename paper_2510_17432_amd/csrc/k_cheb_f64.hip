@@ -9,9 +9,9 @@ hipError_t launch_cheb_f64(int vec, int kt, bool honey, bool eps, const ChebInst
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(double, 2, 1, false, false); break;
-    case 202: CSP_CHEB_LAUNCH(double, 2, 2, false, false); break;
-    case 204: CSP_CHEB_LAUNCH(double, 2, 4, false, false); break;
+    case 201: CSP_CHEB_LAUNCH(double, 2, 1, cheb::kMomNone, false); break;
+    case 202: CSP_CHEB_LAUNCH(double, 2, 2, cheb::kMomNone, false); break;
+    case 204: CSP_CHEB_LAUNCH(double, 2, 4, cheb::kMomNone, false); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -23,9 +23,9 @@ hipError_t launch_cheb_f64m(int vec, int kt, bool honey, bool eps, const ChebIns
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(double, 2, 1, true, false); break;
-    case 202: CSP_CHEB_LAUNCH(double, 2, 2, true, false); break;
-    case 204: CSP_CHEB_LAUNCH(double, 2, 4, true, false); break;
+    case 201: CSP_CHEB_LAUNCH(double, 2, 1, cheb::kMomBra, false); break;
+    case 202: CSP_CHEB_LAUNCH(double, 2, 2, cheb::kMomBra, false); break;
+    case 204: CSP_CHEB_LAUNCH(double, 2, 4, cheb::kMomBra, false); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

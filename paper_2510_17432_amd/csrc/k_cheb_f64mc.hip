@@ -9,9 +9,9 @@ hipError_t launch_cheb_f64mc(int vec, int kt, bool honey, bool eps, const ChebIn
   if (n <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(ceil_div(n, 4))), block(256);
   switch (vec * 100 + kt) {
-    case 201: CSP_CHEB_LAUNCH(double, 2, 1, true, true); break;
-    case 202: CSP_CHEB_LAUNCH(double, 2, 2, true, true); break;
-    case 204: CSP_CHEB_LAUNCH(double, 2, 4, true, true); break;
+    case 201: CSP_CHEB_LAUNCH(double, 2, 1, cheb::kMomBra, true); break;
+    case 202: CSP_CHEB_LAUNCH(double, 2, 2, cheb::kMomBra, true); break;
+    case 204: CSP_CHEB_LAUNCH(double, 2, 4, cheb::kMomBra, true); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

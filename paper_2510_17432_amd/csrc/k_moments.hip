@@ -1,8 +1,8 @@
 // Moment-based form (Sec. II.A, moment-based implementation; Sec. III
 // DOS-Concurrent-M): the per-order inner products (the recursion kernel's
 // moment records, summed per column by k_cheb_mom_finish) are turned into
-// the block moments mu_n = <psi0|T_n(H~) s_k> (directly, or above
-// h = floor(N/2) by the halving identity of Eq. cheby_prod), and contracted
+// the block moments mu_n = <psi0|T_n(H~) s_k> (directly, or with halving
+// every moment above mu_1 from the self products of Eq. cheby_prod), and contracted
 // with the expansion coefficients into correlations
 //   C(t_{kb+j}) = sum_{n=0}^{N(j tau)} c_n(j tau) mu_n,   c_n = (-i)^n a_n.
 // Everything here is FP64 and summed in a fixed order.
@@ -24,10 +24,9 @@ __global__ void k_mom_assemble(const MomCorrInst* __restrict__ mc, int Nk, int h
     return make_double2(p[0], p[1]);
   };
   double2 mu;
-  const int h = Nk / 2;
   if (n == 0) {
     mu = dot(1, 1);                       // <psi0|s_k>
-  } else if (!halving || n <= h) {
+  } else if (!halving || n == 1) {
     mu = dot(n, 0);
   } else if ((n & 1) == 0) {              // mu_2k = 2 <phi_k|phi_k> - mu_0
     const double2 a = dot(n / 2, 2), m0 = dot(1, 1);
