@@ -318,16 +318,24 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     outv[l] = st.slot_out[l] >= 0 ? base + 2 * (int64_t)st.slot_out[l] * I.slot_stride + coff
                                   : nullptr;
 
-  // ---- register rows: lo/mid/hi = the last three rows of levels 0..KT-1
-  C lo[KT][V], mid[KT][V], hi[KT][V];
+  // ---- register rows: rr[l][.] = the last three rows of level l.  With ROT
+  // (the self-product kernel, whose pace is set by its instruction count)
+  // the three slots rotate with the row index: before an iteration of phase
+  // P = i mod 3, slot P holds the oldest row, P + 1 the middle and P + 2 the
+  // newest; the iteration overwrites slot P with the new row, and the row
+  // loop is unrolled by three so every slot index is a constant (rotation by
+  // renaming, no register moves).  Without ROT every iteration moves the
+  // rows down one slot and writes the new row into slot 2.  At 8 steps per
+  // launch only the honeycomb lattice without on-site energies rotates:
+  // unrolled, the others take 186-214 VGPRs (2 waves per SIMD instead of 3).
+  constexpr bool ROT = MOM == kMomSelf && (KT <= 4 || (HONEY && !EPS));
+  C rr[KT][3][V];
 #pragma unroll
   for (int l = 0; l < KT; ++l)
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      lo[l][v] = {T(0), T(0)};
-      mid[l][v] = {T(0), T(0)};
-      hi[l][v] = {T(0), T(0)};
-    }
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int v = 0; v < V; ++v) rr[l][k][v] = {T(0), T(0)};
   T er[EPS ? KT + 1 : 1][V];                         // on-site energies of rows r0 - k
 #pragma unroll
   for (int k = 0; k < (EPS ? KT + 1 : 1); ++k)
@@ -368,7 +376,11 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   const T beta0 = static_cast<T>(I.beta0);
   const T oscale = static_cast<T>(I.onsite_scale);
   const bool vert = I.kind != CSP_CHAIN;
-  const int n_iter = (y1 - y0) + 2 * nlev;
+  // iterations: the segment's rows and nlev margin rows on each side; with
+  // ROT rounded up to a multiple of three (the extra iterations compute rows
+  // past the segment, which are neither stored nor summed, from loads of
+  // rows that are inside the lattice or absent and read as zero)
+  const int n_iter = ROT ? ((y1 - y0) + 2 * nlev + 2) / 3 * 3 : (y1 - y0) + 2 * nlev;
   const int rbase = y0 - nlev;                       // level-0 row of iteration 0
 
   // The row loop, compiled twice: FAST for strips inside the row (no wrap,
@@ -438,15 +450,32 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     if (carry_in) load_row(carry, rbase - nlev, ncar);
 
     int flush_in = kFlush;                           // rows left before the next flush
-#pragma unroll 1
-    for (int i = 0; i < n_iter; ++i) {
+    // one iteration: level 0 takes row r0 = rbase + i, level l computes row
+    // r0 - l; the phase selects the register slots.  STEADY iterations are
+    // those in which all KT levels run and compute rows of the segment
+    // (i in [2 KT, H + KT + 1) with nlev = KT): no level or row tests, and
+    // those rows are inside the lattice.
+    auto iter = [&](auto phase_tag, auto steady_tag, int i) {
+      constexpr int P = ROT ? decltype(phase_tag)::value : 2;
+      constexpr bool STEADY = decltype(steady_tag)::value;
+      // slots after this iteration's new rows: oldest, middle, newest
+      constexpr int SLO = (P + 1) % 3, SMI = (P + 2) % 3, SHI = P;
+      // without ROT a level moves its rows down one slot before it writes
+      // its new row
+      auto shift_down = [&](int l) {
+        if constexpr (!ROT) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            rr[l][0][v] = rr[l][1][v];
+            rr[l][1][v] = rr[l][2][v];
+          }
+        }
+      };
       const int r0 = rbase + i;
-      // level 0 takes row r0
+      shift_down(0);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        lo[0][v] = mid[0][v];
-        mid[0][v] = hi[0][v];
-        hi[0][v] = ncur[v];
+        rr[0][SHI][v] = ncur[v];
         pv[v] = nprev[v];
       }
       if constexpr (EPS) {
@@ -484,22 +513,28 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
         if (carry_in) load_row(carry, r0 + 1 - nlev, ncar);
       }
       // phi_n itself for the contraction (order 0 of a block)
-      if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, hi[0], true);
+      if (copyv && r0 >= y0 && r0 < y1) store_row(copyv, r0, rr[0][SHI], true);
 
 #pragma unroll
       for (int l = 1; l <= KT; ++l) {
-        if (l > nlev || i < 2 * l) break;
+        if constexpr (!STEADY) {
+          if (l > nlev || i < 2 * l) break;
+        }
         const int r = r0 - l;
-        bool rp;
-        const int rw = row_of(r, rp);
-        const T scale = (l == 1 && st.first) ? T(0.5) : T(1);
+        bool rp = true;
+        const int rw = STEADY ? r : row_of(r, rp);
+        // With ROT a row outside the lattice (rp false) gets zero
+        // coefficients: its phi_{n+l-1} and phi_{n+l-2} rows are zero, so o
+        // is zero without a branch.  The other kernels branch (measured
+        // faster there).
+        const T scale = (ROT && !rp) ? T(0) : ((l == 1 && st.first) ? T(0.5) : T(1));
         const T as = scale * alpha, bs = scale * beta0, os_ = scale * oscale;
         // level l-1 rows r - 1, r, r + 1 and level l-2 row r (phi_{n+l-2})
-        const C(&up)[V] = lo[l - 1];
-        const C(&c)[V] = mid[l - 1];
-        const C(&dn)[V] = hi[l - 1];
+        const C(&up)[V] = rr[l - 1][SLO];
+        const C(&c)[V] = rr[l - 1][SMI];
+        const C(&dn)[V] = rr[l - 1][SHI];
         C o[V];
-        if (rp) {
+        if (ROT || rp) {
           const T lx = shr1(c[V - 1].x), ly = shr1(c[V - 1].y);
           const T rx = shl1(c[0].x), ry = shl1(c[0].y);
 #pragma unroll
@@ -521,7 +556,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
                 ny += up[v].y + dn[v].y;
               }
             }
-            const C p = l == 1 ? pv[v] : lo[l - 2 >= 0 ? l - 2 : 0][v];
+            const C p = l == 1 ? pv[v] : rr[l - 2 >= 0 ? l - 2 : 0][SLO][v];
             T beta = bs;
             if constexpr (EPS) beta = bs + os_ * er[l][v];
             o[v].x = as * nx + (beta * c[v].x - p.x);
@@ -537,14 +572,11 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
           for (int v = 0; v < V; ++v) o[v] = {T(0), T(0)};
         }
         if (l < KT) {
+          shift_down(l);
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            lo[l][v] = mid[l][v];
-            mid[l][v] = hi[l][v];
-            hi[l][v] = o[v];
-          }
+          for (int v = 0; v < V; ++v) rr[l][SHI][v] = o[v];
         }
-        if (r >= y0 && r < y1) {
+        if (STEADY || (r >= y0 && r < y1)) {
           if (outv[l - 1]) store_row(outv[l - 1], rw, o, true);
           if constexpr (MOM == kMomSelf) {
             const int q0 = 2 * (l - 1);
@@ -552,8 +584,11 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
             for (int v = 0; v < V; ++v) {
               const bool w = FAST ? true : own[v];
               const C oo = w ? o[v] : C{T(0), T(0)};
-              sq[q0] += oo.x * oo.x + oo.y * oo.y;
-              sq[q0 + 1] += oo.x * c[v].x + oo.y * c[v].y;
+              // one accumulating FMA per product
+              sq[q0] += oo.x * oo.x;
+              sq[q0] += oo.y * oo.y;
+              sq[q0 + 1] += oo.x * c[v].x;
+              sq[q0 + 1] += oo.y * c[v].y;
             }
           }
           if constexpr (MOM == kMomBra) {
@@ -573,17 +608,24 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
 #pragma unroll
               for (int v = 0; v < V; ++v) {
                 if (want_psi0) {
-                  sq[q0] += q[v].x * oo[v].x + q[v].y * oo[v].y;
-                  sq[q0 + 1] += q[v].x * oo[v].y - q[v].y * oo[v].x;
+                  sq[q0] += q[v].x * oo[v].x;
+                  sq[q0] += q[v].y * oo[v].y;
+                  sq[q0 + 1] += q[v].x * oo[v].y;
+                  sq[q0 + 1] -= q[v].y * oo[v].x;
                   if (l == 1) {
-                    sq[5 * KT] += q[v].x * cc[v].x + q[v].y * cc[v].y;
-                    sq[5 * KT + 1] += q[v].x * cc[v].y - q[v].y * cc[v].x;
+                    sq[5 * KT] += q[v].x * cc[v].x;
+                    sq[5 * KT] += q[v].y * cc[v].y;
+                    sq[5 * KT + 1] += q[v].x * cc[v].y;
+                    sq[5 * KT + 1] -= q[v].y * cc[v].x;
                   }
                 }
                 if (st.dot_self) {
-                  sq[q0 + 2] += oo[v].x * oo[v].x + oo[v].y * oo[v].y;
-                  sq[q0 + 3] += oo[v].x * c[v].x + oo[v].y * c[v].y;
-                  sq[q0 + 4] += oo[v].x * c[v].y - oo[v].y * c[v].x;
+                  sq[q0 + 2] += oo[v].x * oo[v].x;
+                  sq[q0 + 2] += oo[v].y * oo[v].y;
+                  sq[q0 + 3] += oo[v].x * c[v].x;
+                  sq[q0 + 3] += oo[v].y * c[v].y;
+                  sq[q0 + 4] += oo[v].x * c[v].y;
+                  sq[q0 + 4] -= oo[v].y * c[v].x;
                 }
               }
             }
@@ -633,6 +675,41 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
           }
         }
       }
+    };
+    // iterations [i0, i1) (with ROT multiples of three)
+    auto iter_range = [&](auto steady_tag, int i0, int i1) {
+      if constexpr (ROT) {
+#pragma unroll 1
+        for (int i = i0; i < i1; i += 3) {
+          iter(std::integral_constant<int, 0>{}, steady_tag, i);
+          iter(std::integral_constant<int, 1>{}, steady_tag, i + 1);
+          iter(std::integral_constant<int, 2>{}, steady_tag, i + 2);
+        }
+      } else {
+#pragma unroll 1
+        for (int i = i0; i < i1; ++i) iter(std::integral_constant<int, 2>{}, steady_tag, i);
+      }
+    };
+    // steady iterations [ia, ib), rounded inwards to multiples of three
+    // with ROT; the others take the general form.  Only the ROT kernels
+    // have a steady form: in the others a second copy of the row loop costs
+    // registers (occupancy) that the shorter scalar path does not repay.
+    int ia = n_iter, ib = n_iter;
+    if (nlev == KT) {
+      ia = 2 * KT;
+      ib = (y1 - y0) + KT + 1;
+      if constexpr (ROT) {
+        ia = (ia + 2) / 3 * 3;
+        ib = ib / 3 * 3;
+      }
+      if (ib < ia) ib = ia;
+    }
+    if constexpr (ROT) {
+      iter_range(std::false_type{}, 0, ia);
+      iter_range(std::true_type{}, ia, ib);
+      iter_range(std::false_type{}, ib, n_iter);
+    } else {
+      iter_range(std::false_type{}, 0, n_iter);
     }
   };
   if (fast) run(std::true_type{});
