@@ -470,6 +470,7 @@ def graphene_leg(a, out):
         el = time.perf_counter() - t0
         res[name] = {"s": el, "recursion_steps": rep.amxsy, "value": N * R * rep.amxsy / el,
                      "recursion_us_per_launch": 1000.0 * rep.ms_spmm / rep.spmm_launches,
+                     "recursion_us_per_step": 1000.0 * rep.ms_spmm / rep.amxsy,
                      "recursion_alg_GBs": rep.spmm_bytes / rep.ms_spmm / 1e6,
                      "recursion_frac": rep.spmm_bytes / rep.ms_spmm / 1e6 / HBM_PEAK_GBS,
                      "steps_per_launch": rep.spmm_steps}

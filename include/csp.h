@@ -78,10 +78,12 @@ typedef enum {
      * C(t_j) = sum_n c_n(j tau) mu_n in FP64; four Chebyshev vectors per
      * column are kept (phi_n, phi_{n-1} and the two newest orders of a
      * recursion launch) besides psi0.  With one block (block_b = 0 or >= Nt) and no final
-     * state requested this is DOS-Concurrent-M of Sec. III: the moments
-     * above N/2 come from the halving identity of Eq. (cheby_prod),
-     * mu_2k = 2<phi_k|phi_k> - mu_0 and mu_2k+1 = 2<phi_k+1|phi_k> - mu_1,
-     * so only N/2 recursion steps run.  With several blocks the recursion
+     * state requested this is DOS-Concurrent-M of Sec. III with the halving
+     * identity of Eq. (cheby_prod): mu_0 and mu_1 are reduced against psi0,
+     * every other moment from mu_2k = 2<phi_k|phi_k> - mu_0 and
+     * mu_2k+1 = 2<phi_k+1|phi_k> - mu_1 (the paper takes mu_n up to N/2
+     * directly; the identity is the same), so only N/2 recursion steps run
+     * and psi0 is read once.  With several blocks the recursion
      * epilogue also accumulates the carried state.  Same correlations as
      * CSP_ASSEMBLE_STATES up to rounding. */
     CSP_ASSEMBLE_MOMENTS = 1
