@@ -655,6 +655,8 @@ ChebInst make_inst(const csp_lattice* L, int Rg, bool fp64) {
   I.Ly = L->g.Ly;
   I.opr = L->g.opr;
   I.N = L->g.N;
+  I.pitch = L->g.opr;   // unpadded rows (the propagation forms set their own)
+  I.cstride = L->g.N;
   I.alpha = 2.0 * (L->g.kind == CSP_SPARSE ? 1.0 : L->desc.t) / L->halfwidth;
   I.beta0 = -2.0 * L->H0 / L->halfwidth;
   I.onsite_scale = 2.0 / L->halfwidth;
@@ -806,7 +808,9 @@ struct InstIn {
 
 struct Group {
   int inst, col0, Rg;
-  int64_t M;
+  int64_t M;             // complex values of one Chebyshev slot of the group (Rg x cstride)
+  int64_t pitch = 0;     // values between rows (0: vectors of N values, unpadded)
+  int64_t cstride = 0;   // values between the group's columns
   // distance between Chebyshev slots: M rounded up to 64 values, so every
   // slot starts 512-byte aligned (16-byte vector loads in the contraction)
   int64_t stride() const { return (M + 63) / 64 * 64; }
@@ -816,6 +820,32 @@ struct Group {
   double* partial = nullptr;
   int n_wg = 1;
 };
+
+// Layout of the propagation forms' vectors: stencil lattices whose rows are
+// not a multiple of 16 values get rows padded to one, so every row starts
+// 128-byte aligned (measured on 16383^2 against 16384^2: 11 % longer
+// recursion launches unaligned); explicit matrices keep N values.
+void set_layout(Group& g, const csp_lattice* L) {
+  const int64_t opr = L->g.opr, Ly = L->g.Ly, N = L->g.N;
+  g.pitch = 0;
+  g.cstride = N;
+  if (L->g.kind != CSP_SPARSE && opr % 16 != 0) {
+    const int64_t pitch = (opr + 15) / 16 * 16;
+    if (Ly * pitch < ((int64_t)1 << 31)) {
+      g.pitch = pitch;
+      g.cstride = Ly * pitch;
+    }
+  }
+  g.M = g.cstride * g.Rg;
+}
+
+// The group's layout in a recursion instance.
+void apply_layout(ChebInst& I, const Group& g) {
+  if (g.pitch > 0) {
+    I.pitch = g.pitch;
+    I.cstride = g.cstride;
+  }
+}
 
 struct ChunkTab {
   int n_lo, n_cnt;
@@ -1111,7 +1141,8 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
 
   // ---------------------------------------------------------- groups & memory
   std::vector<Group> groups;
-  int64_t vec_elems = 0;   // complex values of one vector over all groups
+  int64_t vec_elems = 0;   // complex values of one vector over all groups (rows padded)
+  int64_t vec_alg = 0;     // the same without the padding (algorithmic bytes)
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
     for (int Rg : split_columns(ins[i].R, ins[i].lat->g.kind == CSP_SPARSE)) {
@@ -1119,9 +1150,10 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       g.inst = (int)i;
       g.col0 = col;
       g.Rg = Rg;
-      g.M = ins[i].lat->g.N * Rg;
+      set_layout(g, ins[i].lat);
       groups.push_back(g);
       vec_elems += g.M;
+      vec_alg += ins[i].lat->g.N * Rg;
       col += Rg;
     }
   }
@@ -1134,7 +1166,10 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
 
   // recursion launch shape (steps per launch kt)
   std::vector<ChebInst> sp;
-  for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+  for (auto& g : groups) {
+    sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+    apply_layout(sp.back(), g);
+  }
   const ChebPlan sp_plan = plan_cheb(sp, fp64, false, c->n_cu, tune ? tune->spmm_vec : 0,
                                      tune ? tune->spmm_steps : (fp64 ? 4 : 8),
                                      tune ? tune->spmm_seg_rows : 0);
@@ -1254,6 +1289,13 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     g.psi0g = cv.take(g.M * csz);
     g.carry = cv.take(g.M * csz);
     g.partial = (double*)cv.take((size_t)g.n_wg * b * 16);
+    // the contraction reads whole vectors: the row padding of the slots,
+    // which the recursion never writes, must hold zeros
+    if (g.pitch > 0) {
+      const csp_lattice* L = ins[g.inst].lat;
+      HIPCALL(launch_zero_pad(g.slots, S, g.stride(), g.Rg, g.cstride, L->g.Ly, L->g.opr, g.pitch,
+                              fp64, s));
+    }
   }
   double* d_sd = (double*)cv.take(sizeof(double) * n_sd * kMaxGroupCols);
   int* d_flag = (int*)cv.take(2 * sizeof(int));
@@ -1305,9 +1347,11 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     const InstIn& in = ins[g.inst];
     const int in_dtype = fp64 ? CSP_C128 : CSP_C64;
     const int64_t N = in.lat->g.N;
-    HIPCALL(launch_gather_cols(N, in.ld, g.col0, g.Rg, in_dtype, in.psi0, fp64, g.psi0g, s));
+    HIPCALL(launch_gather_cols(N, in.ld, g.col0, g.Rg, in_dtype, in.psi0, fp64, g.psi0g, s,
+                               in.lat->g.opr, g.pitch));
     HIPCALL(hipMemcpyAsync(g.carry, g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
-    HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, (int)n_sd, s));
+    // over the padded columns: the padding is zero
+    HIPCALL(launch_self_dot(g.cstride, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, (int)n_sd, s));
   }
 
   // ---------------------------------------------------------- blocks
@@ -1318,7 +1362,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
   double eps_bytes = 0;
   for (auto& g : groups)
     eps_bytes += static_bytes(ins[g.inst].lat, fp64);
-  const double vbytes = (double)vec_elems * csz;
+  const double vbytes = (double)vec_alg * csz;
 
   ContractArgs ca{};
   ca.n_inst = (int)groups.size();
@@ -1388,7 +1432,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     if (P.check_norm) {
       for (auto& g : groups) {
         const InstIn& in = ins[g.inst];
-        HIPCALL(launch_guard(in.lat->g.N, g.Rg, g.carry, fp64, in.corr, in.ld, g.col0, t0, bk,
+        HIPCALL(launch_guard(g.cstride, g.Rg, g.carry, fp64, in.corr, in.ld, g.col0, t0, bk,
                              P.norm_tol, (int)(t0 / b), from_dev ? d_blk : nullptr, d_flag, d_sd,
                              (int)n_sd, strm));
       }
@@ -1411,9 +1455,9 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
       const ChunkTab& ch = T.chunks[ci];
       ++n_con;
       con_bytes += vbytes * (ch.n_cnt + 2 + (ci == 0 ? 0 : 1));
-      con_flops += fp64 ? 8.0 * (double)vec_elems * ch.n_cnt * (bk + 1)
+      con_flops += fp64 ? 8.0 * (double)vec_alg * ch.n_cnt * (bk + 1)
                         : 2.0 * 6.0 * 32.0 * 32.0 * 16.0 * jtiles *
-                              (double)ceil_div(ch.n_cnt, 16) * (double)ceil_div(vec_elems, 32);
+                              (double)ceil_div(ch.n_cnt, 16) * (double)ceil_div(vec_alg, 32);
     }
   };
 
@@ -1470,7 +1514,7 @@ static csp_status propagate_impl(csp_context* c, const std::vector<InstIn>& ins,
     const InstIn& in = ins[g.inst];
     if (!in.final_out) continue;
     HIPCALL(launch_scatter_cols(in.lat->g.N, in.ld, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64,
-                                g.carry, fp64, in.final_out, s));
+                                g.carry, fp64, in.final_out, s, in.lat->g.opr, g.pitch));
   }
   HIPCALL(hipStreamSynchronize(s));
   if (P.check_norm) CHECK(guard_check(d_flag, s));
@@ -1567,7 +1611,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
 
   // Column groups (powers of two, <= 32 columns).
   std::vector<Group> groups;
-  int64_t vec_elems = 0;
+  int64_t vec_alg = 0;     // complex values of one vector over all groups (unpadded)
   int rmax = 1;
   for (size_t i = 0; i < ins.size(); ++i) {
     int col = ins[i].col_base;
@@ -1576,15 +1620,18 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
       g.inst = (int)i;
       g.col0 = col;
       g.Rg = Rg;
-      g.M = ins[i].lat->g.N * Rg;
+      set_layout(g, ins[i].lat);
       groups.push_back(g);
-      vec_elems += g.M;
+      vec_alg += ins[i].lat->g.N * Rg;
       rmax = std::max(rmax, Rg);
       col += Rg;
     }
   }
   std::vector<ChebInst> sp;
-  for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+  for (auto& g : groups) {
+    sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+    apply_layout(sp.back(), g);
+  }
   const csp_tuning* tune = find_tuning(c, ins, fp64, CSP_ASSEMBLE_MOMENTS);
   int vec_want = tune ? tune->spmm_vec : 0;
   // default: 8 steps per launch for the complex64 self-product kernel
@@ -1626,6 +1673,12 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     if (carry) {
       carry_a[gi] = cv.take(g.M * csz);
       carry_b[gi] = cv.take(g.M * csz);
+      // the recursion writes rows only; the norm guard reads whole vectors
+      if (g.pitch > 0) {
+        const csp_lattice* L = ins[g.inst].lat;
+        HIPCALL(launch_zero_pad(carry_b[gi], 1, 0, g.Rg, g.cstride, L->g.Ly, L->g.opr, g.pitch,
+                                fp64, s));
+      }
     }
     dots[gi] = (double*)cv.take((size_t)(steps_max + 1) * 4 * g.Rg * 16);
     mus[gi] = (double*)cv.take((size_t)(Nk_max + 1) * g.Rg * 16);
@@ -1645,8 +1698,8 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     const InstIn& in = ins[g.inst];
     const int64_t N = in.lat->g.N;
     HIPCALL(launch_gather_cols(N, in.ld, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, in.psi0, fp64,
-                               g.psi0g, s));
-    HIPCALL(launch_self_dot(N, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, 256, s));
+                               g.psi0g, s, in.lat->g.opr, g.pitch));
+    HIPCALL(launch_self_dot(g.cstride, g.Rg, g.psi0g, fp64, in.corr, g.col0, d_sd, 256, s));
     if (carry)
       HIPCALL(hipMemcpyAsync(carry_a[gi], g.psi0g, g.M * csz, hipMemcpyDeviceToDevice, s));
     ChebInst& I = sp[gi];
@@ -1677,7 +1730,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
   double eps_bytes = 0;
   for (auto& g : groups)
     eps_bytes += static_bytes(ins[g.inst].lat, fp64);
-  const double vbytes = (double)vec_elems * csz;
+  const double vbytes = (double)vec_alg * csz;
 
   const ChebStep st0 = step_args(sp_plan);
   int cur_carry = 0;   // carry_a holds s_k when 0
@@ -1780,7 +1833,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
         const Group& g = groups[gi];
         const InstIn& in = ins[g.inst];
         const void* cy = carry ? (cur_carry == 0 ? carry_b[gi] : carry_a[gi]) : nullptr;
-        HIPCALL(launch_guard(in.lat->g.N, g.Rg, cy, fp64, in.corr, in.ld, g.col0, t0, bk,
+        HIPCALL(launch_guard(g.cstride, g.Rg, cy, fp64, in.corr, in.ld, g.col0, t0, bk,
                              P.norm_tol, (int)(t0 / b), nullptr, d_flag, d_sd, 256, s));
       }
     }
@@ -1793,7 +1846,7 @@ static csp_status propagate_moments_impl(csp_context* c, const std::vector<InstI
     if (!in.final_out) continue;
     void* fin = cur_carry == 0 ? carry_a[gi] : carry_b[gi];
     HIPCALL(launch_scatter_cols(in.lat->g.N, in.ld, g.col0, g.Rg, fp64 ? CSP_C128 : CSP_C64, fin,
-                                fp64, in.final_out, s));
+                                fp64, in.final_out, s, in.lat->g.opr, g.pitch));
   }
   HIPCALL(hipStreamSynchronize(s));
   if (P.check_norm) CHECK(guard_check(d_flag, s));

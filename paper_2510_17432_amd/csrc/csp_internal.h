@@ -100,6 +100,10 @@ __host__ __device__ inline int64_t neighbour(const Geom& g, int64_t s, int k) {
 struct ChebInst {
   int32_t kind, px, py, Rg;
   int64_t Ly, opr, N;          // rows, values per row (Lx or 2 Lx), orbitals
+  // layout of the group's vectors: row r of a column starts at r * pitch
+  // (pitch >= opr; the positions opr..pitch-1 are padding, zero and never
+  // written by the recursion), column c at c * cstride
+  int64_t pitch, cstride;
   int64_t n_strips, n_segs;    // work items of one column: strips x row segments
   int64_t item0;               // first work item (wave) of this instance
   double alpha;                // 2 t / |H|
@@ -436,12 +440,22 @@ hipError_t launch_random_phase(int64_t N, int R, uint64_t seed, int dtype, void*
 hipError_t launch_ldos_sites(int64_t N, int n, uint64_t seed, int64_t* d_sites, hipStream_t s);
 hipError_t launch_site_states(int64_t N, int n, const int64_t* d_sites, int dtype, void* d_psi,
                               int ld, int col0, hipStream_t s);
-// Copy columns col0..col0+Rg-1 of an [N][ld] block (dtype) into a dense [N][Rg]
-// block of the path's precision (fp64 selects double2 output).
+// Copy columns col0..col0+Rg-1 of an [N][ld] block (dtype) into a dense
+// column-major group of the path's precision (fp64 selects double2 output).
+// With pitch > 0 the group's rows of opr values are pitch values apart and
+// its columns N / opr * pitch apart, the padding written as zero; pitch 0:
+// columns of N values.  launch_scatter_cols is the inverse.
 hipError_t launch_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype,
-                              const void* d_in, bool fp64, void* d_out, hipStream_t s);
+                              const void* d_in, bool fp64, void* d_out, hipStream_t s,
+                              int64_t opr = 0, int64_t pitch = 0);
 hipError_t launch_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtype,
-                               const void* d_in, bool fp64, void* d_out, hipStream_t s);
+                               const void* d_in, bool fp64, void* d_out, hipStream_t s,
+                               int64_t opr = 0, int64_t pitch = 0);
+// Zero the row padding (positions opr..pitch-1 of every row) of n_slots x Rg
+// vectors: vector c of slot k at base + k * slot_stride + c * cstride.
+hipError_t launch_zero_pad(void* d_base, int n_slots, int64_t slot_stride, int Rg,
+                           int64_t cstride, int64_t Ly, int64_t opr, int64_t pitch, bool fp64,
+                           hipStream_t s);
 // C_0: corr[col0 + r] = <psi0_r|psi0_r> for an [N][Rg] group, FP64 result.
 hipError_t launch_self_dot(int64_t N, int Rg, const void* d_psi, bool fp64, double* d_corr,
                            int col0, double* d_scratch, int n_scratch_wg, hipStream_t s);

@@ -4,10 +4,14 @@
 // applied as a stencil (no matrix in memory).  The first step of a time
 // block is phi_1 = H~ phi_0.
 //
-// Layout.  A column group is stored column-major, [Rg][N]: column c of the
-// group is one lattice vector of N values, rows of `opr` values in the
-// orbital order of the lattice, so the in-row stencil neighbours are at +-1
-// and the vertical ones one row up or down.
+// Layout.  A column group is stored column-major: column c of the group is
+// one lattice vector, cstride values from the previous one, rows of `opr`
+// values in the orbital order of the lattice and `pitch` values apart, so
+// the in-row stencil neighbours are at +-1 and the vertical ones one row up
+// or down.  The propagation forms pad rows whose length is not a multiple
+// of 16 values to one, so that rows start 128-byte aligned (unaligned rows
+// measured about a tenth slower); vectors the caller passes in are unpadded
+// (pitch = opr).
 //
 // Work decomposition.  One wave (64 lanes) owns a strip of a row segment of
 // one column and is independent of every other wave: no LDS, no barriers.
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
   const int y1 = (y0 + st.seg_rows < Ly) ? y0 + st.seg_rows : Ly;
   const int nlev = st.nlev;
   const int py = I.py;
-  const int64_t coff = 2 * col * I.N;                // column offset in T units
+  const int64_t coff = 2 * col * I.cstride;          // column offset in T units
 
   // ---- per-lane positions
   const int lq = V * lane;
@@ -298,8 +302,10 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
     present = static_cast<unsigned>(r) < static_cast<unsigned>(Ly);
     return r;
   };
-  // T offset of row rw (inside the lattice) in a column
-  auto row_off = [&](int rw) -> int64_t { return 2 * static_cast<int64_t>(rw * opr); };
+  // T offset of row rw (inside the lattice) in a column of the group's
+  // vectors (rows pitch values apart); the on-site energies are packed
+  const int64_t pitch = I.pitch;
+  auto row_off = [&](int rw) -> int64_t { return 2 * static_cast<int64_t>(rw) * pitch; };
 
   gT* base = (gT*)(I.base);
   const gT* curv = (st.slot_cur < 0 ? (const gT*)(I.src)
@@ -412,7 +418,7 @@ __global__ __launch_bounds__(256) void k_cheb(const ChebInst* __restrict__ insts
         for (int v = 0; v < V; ++v) d[v] = T(0);
         return;
       }
-      const gT* rowp = eps + row_off(rw) / 2;
+      const gT* rowp = eps + static_cast<int64_t>(rw) * opr;
       if constexpr (FAST) {
         ldr<V>(rowp + p0 + lq, d);
       } else {

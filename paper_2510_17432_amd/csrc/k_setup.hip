@@ -143,38 +143,52 @@ hipError_t launch_site_states(int64_t N, int n, const int64_t* d_sites, int dtyp
 // A column group is stored column-major, [Rg][N]: column c of the group is
 // values c*N .. c*N + N - 1 (one lattice vector).  Gather/scatter convert
 // from/to the caller's orbital-major [N][ld] blocks.
+// Element e of the group: column c, row r, position p (pitch and opr equal
+// to N when the group is not padded).
 __global__ void k_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype,
-                              const void* __restrict__ in, int fp64, void* __restrict__ out) {
+                              const void* __restrict__ in, int fp64, void* __restrict__ out,
+                              int64_t opr, int64_t pitch, int64_t Nc) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N * Rg) return;
-  const int64_t c = e / N;
-  const int64_t s = e - c * N;
-  const int64_t at = s * ld + col0 + c;
-  double x, y;
-  if (in_dtype == CSP_C128) {
-    const double2 v = static_cast<const double2*>(in)[at];
-    x = v.x; y = v.y;
-  } else {
-    const float2 v = static_cast<const float2*>(in)[at];
-    x = v.x; y = v.y;
+  if (e >= Nc * Rg) return;
+  const int64_t c = e / Nc;
+  const int64_t q = e - c * Nc;
+  const int64_t r = q / pitch;
+  const int64_t p = q - r * pitch;
+  double x = 0.0, y = 0.0;
+  if (p < opr) {
+    const int64_t at = (r * opr + p) * ld + col0 + c;
+    if (in_dtype == CSP_C128) {
+      const double2 v = static_cast<const double2*>(in)[at];
+      x = v.x; y = v.y;
+    } else {
+      const float2 v = static_cast<const float2*>(in)[at];
+      x = v.x; y = v.y;
+    }
   }
   if (fp64) static_cast<double2*>(out)[e] = make_double2(x, y);
   else static_cast<float2*>(out)[e] = make_float2(static_cast<float>(x), static_cast<float>(y));
 }
 
 hipError_t launch_gather_cols(int64_t N, int ld, int col0, int Rg, int in_dtype, const void* d_in,
-                              bool fp64, void* d_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)ceil_div(N * Rg, 256)), dim3(256), 0, s, N, ld,
-                     col0, Rg, in_dtype, d_in, fp64 ? 1 : 0, d_out);
+                              bool fp64, void* d_out, hipStream_t s, int64_t opr, int64_t pitch) {
+  if (pitch <= 0) opr = pitch = N;
+  if (opr <= 0 || pitch < opr || N % opr != 0) return hipErrorInvalidValue;
+  const int64_t Nc = N / opr * pitch;
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)ceil_div(Nc * Rg, 256)), dim3(256), 0, s, N,
+                     ld, col0, Rg, in_dtype, d_in, fp64 ? 1 : 0, d_out, opr, pitch, Nc);
   return hipGetLastError();
 }
 
 __global__ void k_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtype,
-                               const void* __restrict__ in, int fp64, void* __restrict__ out) {
+                               const void* __restrict__ in, int fp64, void* __restrict__ out,
+                               int64_t opr, int64_t pitch, int64_t Nc) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= N * Rg) return;
-  const int64_t c = e / N;
-  const int64_t s = e - c * N;
+  if (e >= Nc * Rg) return;
+  const int64_t c = e / Nc;
+  const int64_t q = e - c * Nc;
+  const int64_t r = q / pitch;
+  const int64_t p = q - r * pitch;
+  if (p >= opr) return;
   double x, y;
   if (fp64) {
     const double2 v = static_cast<const double2*>(in)[e];
@@ -183,15 +197,45 @@ __global__ void k_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtyp
     const float2 v = static_cast<const float2*>(in)[e];
     x = v.x; y = v.y;
   }
-  const int64_t at = s * ld + col0 + c;
+  const int64_t at = (r * opr + p) * ld + col0 + c;
   if (out_dtype == CSP_C128) static_cast<double2*>(out)[at] = make_double2(x, y);
   else static_cast<float2*>(out)[at] = make_float2(static_cast<float>(x), static_cast<float>(y));
 }
 
 hipError_t launch_scatter_cols(int64_t N, int ld, int col0, int Rg, int out_dtype, const void* d_in,
-                               bool fp64, void* d_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)ceil_div(N * Rg, 256)), dim3(256), 0, s, N,
-                     ld, col0, Rg, out_dtype, d_in, fp64 ? 1 : 0, d_out);
+                               bool fp64, void* d_out, hipStream_t s, int64_t opr, int64_t pitch) {
+  if (pitch <= 0) opr = pitch = N;
+  if (opr <= 0 || pitch < opr || N % opr != 0) return hipErrorInvalidValue;
+  const int64_t Nc = N / opr * pitch;
+  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)ceil_div(Nc * Rg, 256)), dim3(256), 0, s, N,
+                     ld, col0, Rg, out_dtype, d_in, fp64 ? 1 : 0, d_out, opr, pitch, Nc);
+  return hipGetLastError();
+}
+
+// One thread per padding value: vector k = slot * Rg + c, row r, position
+// opr + p.
+__global__ void k_zero_pad(void* __restrict__ base, int64_t n_pad, int Rg, int64_t slot_stride,
+                           int64_t cstride, int64_t Ly, int64_t opr, int64_t pitch, int fp64) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_pad) return;
+  const int64_t w = pitch - opr;
+  const int64_t per_vec = Ly * w;
+  const int64_t k = e / per_vec;
+  const int64_t q = e - k * per_vec;
+  const int64_t r = q / w;
+  const int64_t p = opr + (q - r * w);
+  const int64_t slot = k / Rg, c = k - slot * Rg;
+  const int64_t at = slot * slot_stride + c * cstride + r * pitch + p;
+  if (fp64) static_cast<double2*>(base)[at] = make_double2(0.0, 0.0);
+  else static_cast<float2*>(base)[at] = make_float2(0.f, 0.f);
+}
+
+hipError_t launch_zero_pad(void* d_base, int n_slots, int64_t slot_stride, int Rg, int64_t cstride,
+                           int64_t Ly, int64_t opr, int64_t pitch, bool fp64, hipStream_t s) {
+  if (pitch <= opr || n_slots <= 0) return hipSuccess;
+  const int64_t n_pad = (int64_t)n_slots * Rg * Ly * (pitch - opr);
+  hipLaunchKernelGGL(k_zero_pad, dim3((unsigned)ceil_div(n_pad, 256)), dim3(256), 0, s, d_base,
+                     n_pad, Rg, slot_stride, cstride, Ly, opr, pitch, fp64 ? 1 : 0);
   return hipGetLastError();
 }
 
