@@ -2749,7 +2749,7 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
       g.inst = (int)i;
       g.col0 = col;
       g.Rg = Rg;
-      g.M = ins[i].lat->g.N * Rg;
+      set_layout(g, ins[i].lat);
       groups.push_back(g);
       vec_elems += g.M;
       rmax = std::max(rmax, Rg);
@@ -2757,7 +2757,10 @@ extern "C" csp_status csp_autotune(csp_context* c, int32_t n_inst, const csp_lat
     }
   }
   std::vector<ChebInst> sp;
-  for (auto& g : groups) sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+  for (auto& g : groups) {
+    sp.push_back(make_inst(ins[g.inst].lat, g.Rg, fp64));
+    apply_layout(sp.back(), g);
+  }
 
   // recursion candidates (values per lane, steps per launch, rows per work
   // item) and the largest record buffer among them
