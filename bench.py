@@ -64,6 +64,7 @@ W5 = csp_inputs.SQUARE31623
 CHEB_SOURCES = ("k_cheb_body.h", "k_cheb_f32.hip")
 CONTRACT_SOURCES = ("k_contract.hip",)
 CHEB_COUNTERS = "k_cheb_square31623_cols4_counters.json"
+MOMENT_COUNTERS = "k_cheb_moments_graphene1024_cols68_counters.json"
 CONTRACT_COUNTERS = "k_contract_f32_square31623_cols4_mfma.json"
 
 
@@ -165,7 +166,7 @@ def summarize_pmc(kernel, out_json, csvs, commands, grid=None, note=None, alg_by
     matrix units.  The summary records the SHA-256 of the kernel's
     sources, so that a changed kernel voids it."""
     import csv
-    vals, copy, dur, names = {}, {}, [], set()
+    vals, copy, dur, dur_valu, names = {}, {}, [], [], set()
     for path in csvs:
         with open(path) as f:
             for r in csv.DictReader(f):
@@ -177,6 +178,9 @@ def summarize_pmc(kernel, out_json, csvs, commands, grid=None, note=None, alg_by
                     vals.setdefault(c, []).append(v)
                     if c == "SQ_INSTS_VALU_MFMA_MOPS_BF16":
                         dur.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+                    if c == "SQ_INSTS_VALU":
+                        dur_valu.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) *
+                                        1e-9)
     if not vals:
         raise SystemExit("no dispatch of %s in %s" % (kernel, csvs))
     mean = lambda x: sum(x) / len(x)  # noqa: E731
@@ -218,6 +222,20 @@ def summarize_pmc(kernel, out_json, csvs, commands, grid=None, note=None, alg_by
             # summed over the 1024 SIMDs; 2.4 GHz
             res["mfma_busy_frac"] = (mean(vals["SQ_VALU_MFMA_BUSY_CYCLES"]) /
                                      (N_CU * 4 * t * 2.4e9))
+    if "SQ_INSTS_VALU" in vals and "SQ_WAVES" in vals:
+        # instruction issue: a wave64 VALU instruction holds its SIMD for 4
+        # cycles, and each SIMD issues at most one SALU instruction per 4
+        # cycles; 1024 SIMDs at 2.4 GHz, over the dispatch's duration
+        t = mean(dur_valu)
+        waves = mean(vals["SQ_WAVES"])
+        slots = N_CU * 4 * t * 2.4e9 / 4.0
+        res["counter_run_launch_s"] = t
+        res["waves_per_launch"] = waves
+        res["valu_insts_per_wave"] = mean(vals["SQ_INSTS_VALU"]) / waves
+        res["valu_issue_frac"] = mean(vals["SQ_INSTS_VALU"]) / slots
+        if "SQ_INSTS_SALU" in vals:
+            res["salu_insts_per_wave"] = mean(vals["SQ_INSTS_SALU"]) / waves
+            res["salu_issue_frac"] = mean(vals["SQ_INSTS_SALU"]) / slots
     res["commands"] = ["cd /tmp && export TMPDIR=/tmp"] + list(commands)
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
@@ -476,6 +494,16 @@ def graphene_leg(a, out):
                      "steps_per_launch": rep.spmm_steps}
         if rep.contract_launches:
             res[name]["contraction_GBs"] = rep.contract_bytes / rep.ms_contract / 1e6
+        if name == "moments":
+            # the self-product kernel is bound by instruction issue, not by
+            # HBM: its issue shares from the committed counters (null when
+            # the kernel changed since they were taken)
+            mp = _profile(MOMENT_COUNTERS, CHEB_SOURCES)
+            res[name]["bound"] = "alu"
+            res[name]["issue"] = None if mp is None else {
+                k: mp.get(k) for k in ("valu_issue_frac", "salu_issue_frac",
+                                       "valu_insts_per_wave", "salu_insts_per_wave",
+                                       "hbm_bytes_per_launch", "ratio_hbm_to_algorithmic")}
         log("graphene %s: %.3f s, recursion %.0f GB/s" % (name, el,
                                                           res[name]["recursion_alg_GBs"]))
     ctx.trim()
